@@ -1,0 +1,127 @@
+"""Seeded synthetic density fields shaped like the paper's simulation densities.
+
+The paper's workloads are N-body densities on 256^3 domain grids (Sec. VI.E); its initial
+conditions are not available, so these generators stand in for them.  They hold none of
+the solver's arithmetic: they only draw random fields, so both the GPU library's tests
+and the CPU oracle's tests can use them.  All fields are float64, C order [i][j][k], with
+mean exactly 1 after normalisation (the code-unit mean density, Sec. III.A).
+
+Recipe (every config):
+  1. w ~ N(0,1) on N^3 from numpy PCG64(seed);
+  2. g^ = rfftn(w) |k|^(p/2) exp(-|k|^2 Rs^2 / 2), k in rad/cell, Rs = 2 cells, k=0 removed;
+  3. g = irfftn(g^), rescaled to std sigma;
+  4. rho = exp(g - sigma^2/2), plus structures drawn from PCG64(seed + 10^6), then
+     rho /= mean(rho).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def gaussian_field(N: int, sigma: float, p: float, seed: int, smooth_cells: float = 2.0) -> np.ndarray:
+    """Zero-mean Gaussian random field with power ~ k^p, Gaussian-smoothed, std sigma."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = rng.standard_normal((N, N, N))
+    wk = np.fft.rfftn(w)
+    kx = 2.0 * np.pi * np.fft.fftfreq(N)
+    kz = 2.0 * np.pi * np.fft.rfftfreq(N)
+    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
+    with np.errstate(divide="ignore"):
+        amp = np.where(k2 > 0, k2 ** (p / 4.0), 0.0)
+    wk *= amp * np.exp(-0.5 * k2 * smooth_cells ** 2)
+    g = np.fft.irfftn(wk, s=(N, N, N), axes=(0, 1, 2))
+    g -= g.mean()
+    s = g.std()
+    if s > 0:
+        g *= sigma / s
+    return g
+
+
+def lognormal(N: int, sigma: float, p: float, seed: int) -> np.ndarray:
+    """rho = exp(g - sigma^2/2), normalised to mean 1."""
+    g = gaussian_field(N, sigma, p, seed)
+    rho = np.exp(g - 0.5 * sigma * sigma)
+    return rho / rho.mean()
+
+
+def _periodic_box(N: int, centre, rmax: float):
+    """Index ranges (wrapped) and periodic distances of cells within a cube around centre."""
+    lo = [int(np.floor(c - rmax)) for c in centre]
+    hi = [int(np.ceil(c + rmax)) + 1 for c in centre]
+    axes = [np.arange(l, h) for l, h in zip(lo, hi)]
+    d = [(a + 0.5) - c for a, c in zip(axes, centre)]
+    r = np.sqrt(d[0][:, None, None] ** 2 + d[1][None, :, None] ** 2 + d[2][None, None, :] ** 2)
+    idx = np.ix_(*[a % N for a in axes])
+    return idx, r
+
+
+def add_tophats(rho: np.ndarray, count: int, seed: int, rmin=2.0, rmax=8.0, dmin=50.0, dmax=500.0):
+    """Adds count spheres of radius U[rmin,rmax] cells and amplitude U[dmin,dmax]."""
+    N = rho.shape[0]
+    rng = np.random.Generator(np.random.PCG64(seed + 10 ** 6))
+    for _ in range(count):
+        c = rng.uniform(0, N, size=3)
+        rad = rng.uniform(rmin, rmax)
+        amp = rng.uniform(dmin, dmax)
+        idx, r = _periodic_box(N, c, rad)
+        rho[idx] += np.where(r <= rad, amp, 0.0)
+    return rho
+
+
+def add_nfw_halos(rho: np.ndarray, count: int, seed: int, cmin=5.0, cmax=10.0, rvmin=4.0,
+                  rvmax=16.0, peak_min=1e2, peak_max=1e4):
+    """Adds count NFW-like profiles d(r) = ds / [x (1+x)^2], x = max(r, 0.5)/r_s, cut at r_vir,
+    with r_s = r_vir / c and the central value d(0.5) drawn log-uniform in [peak_min, peak_max]."""
+    N = rho.shape[0]
+    rng = np.random.Generator(np.random.PCG64(seed + 10 ** 6))
+    for _ in range(count):
+        ctr = rng.uniform(0, N, size=3)
+        conc = rng.uniform(cmin, cmax)
+        rvir = rng.uniform(rvmin, rvmax)
+        peak = np.exp(rng.uniform(np.log(peak_min), np.log(peak_max)))
+        rs = rvir / conc
+        x0 = 0.5 / rs
+        ds = peak * x0 * (1.0 + x0) ** 2
+        idx, r = _periodic_box(N, ctr, rvir)
+        x = np.maximum(r, 0.5) / rs
+        rho[idx] += np.where(r <= rvir, ds / (x * (1.0 + x) ** 2), 0.0)
+    return rho
+
+
+def normalise(rho: np.ndarray) -> np.ndarray:
+    return rho / rho.mean()
+
+
+# --- the five workloads --------------------------------------------------------------
+
+def small_box(N: int = 32, seed: int = 0) -> np.ndarray:
+    """32^3, B = 64 Mpc/h workload: lognormal, sigma = 1, P(k) ~ k^-2."""
+    return lognormal(N, 1.0, -2.0, seed)
+
+
+def tophat_box(N: int = 256, seed: int = 1, count: int = 200) -> np.ndarray:
+    """256^3, B = 256 Mpc/h workload: lognormal sigma = 2, P ~ k^-1.5, plus spherical top-hats
+    (radius 2-8 cells, amplitude 50-500)."""
+    rho = lognormal(N, 2.0, -1.5, seed)
+    return normalise(add_tophats(rho, count, seed))
+
+
+def halo_box(N: int = 512, seed: int = 2, count: int = 2000) -> np.ndarray:
+    """512^3, B = 512 Mpc/h workload: lognormal sigma = 3, P ~ k^-1.5, plus NFW-like halos
+    (concentration 5-10, r_vir 4-16 cells, central amplitude 1e2-1e4)."""
+    rho = lognormal(N, 3.0, -1.5, seed)
+    return normalise(add_nfw_halos(rho, count, seed))
+
+
+def batch_boxes(n64: int = 64, n128: int = 16):
+    """Independent periodic boxes: (N, B, |f_R0|, sigma, seed, rho) per box; |f_R0| log-uniform
+    in [1e-6, 1e-4], sigma uniform in [1, 3]; seeds 0.. for 64^3 and 100.. for 128^3."""
+    out = []
+    for N, B, cnt, s0 in ((64, 64.0, n64, 0), (128, 128.0, n128, 100)):
+        for b in range(cnt):
+            seed = s0 + b
+            rng = np.random.Generator(np.random.PCG64(seed + 2 * 10 ** 6))
+            fr0 = 10.0 ** rng.uniform(-6.0, -4.0)
+            sigma = rng.uniform(1.0, 3.0)
+            out.append((N, B, fr0, sigma, seed, lognormal(N, sigma, -1.5, seed)))
+    return out
