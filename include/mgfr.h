@@ -1,0 +1,130 @@
+/*
+ * mgfr.h -- C ABI of libmgfr.so, the MI355X (gfx950) multigrid solver of the nonlinear
+ * f(R) scalar-field equation of ECOSMOG (Li, Zhao, Teyssier & Koyama, arXiv:1110.1379).
+ *
+ * Problem (Sec. III.C, Sec. IV): given the code-unit density rho~ on a periodic N^3 grid
+ * (box side 1, h = 1/N) and the Hu-Sawicki model, find u with f~_R = -exp(u) such that at
+ * every cell
+ *
+ *   L_i(u) = c~^2/(2h^2) sum_nb (b_nb + b_i)(u_nb - u_i)          b = exp(u)
+ *          + (1/3) Om a^4 (n a^2 xi)^(1/(n+1)) exp(-u_i/(n+1))
+ *          - Om a (rho~_i - 1) - Om a^4 (a^-3 + 4 OL/Om)  = 0
+ *
+ * (eq. discrete_fR multiplied by c~^2, i.e. the scaling of eq. bc_modified_fR_op).  The
+ * solver runs FAS V-cycles (Sec. V.B.2) with a red-black Newton-Gauss-Seidel smoother
+ * (Sec. V.B.1) until the rms of L over the grid is <= tol.  Refinement patches (Sec. V,
+ * Sec. VI.B) are cube sub-grids whose boundary values come from the parent solution.
+ *
+ * Conventions for every entry point:
+ *   - Arrays of cells are C order [i][j][k] with k fastest; i is x.  Doubles unless noted.
+ *   - "device" pointers are HIP device memory of the context's device; "host" pointers are
+ *     ordinary host memory.  The caller owns every buffer passed in; the context owns its
+ *     internal scratch (multigrid hierarchy, reductions), which it keeps between calls.
+ *   - stream: a hipStream_t (NULL = the default stream).  Work is queued on it; calls that
+ *     return residual histories synchronise it before returning.
+ *   - Return value: MGFR_OK or a negative MGFR_E* code; mgfr_last_error() then holds a
+ *     message.  No C++ exception crosses this interface.  A context is not thread-safe.
+ */
+#ifndef MGFR_H
+#define MGFR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGFR_OK 0
+#define MGFR_EINVAL (-1)     /* invalid argument (sizes, pointers, options, patch layout)   */
+#define MGFR_ENONFINITE (-2) /* non-finite density or start field, or the iteration overflowed */
+#define MGFR_ENOTCONV (-3)   /* max_cycles reached; u and the history are still written     */
+#define MGFR_EDEVICE (-4)    /* HIP runtime error                                            */
+#define MGFR_ENOMEM (-5)     /* device allocation failed                                     */
+
+/* opts.precision */
+#define MGFR_FP64 0          /* every level and sweep in double precision                   */
+#define MGFR_MIXED 1         /* FP32 correction-form V-cycles inside an FP64 defect-correction loop */
+
+/* opts.flags */
+#define MGFR_SUBTRACT_MEAN 1 /* density contrast rho~ - mean(rho~) instead of rho~ - 1       */
+#define MGFR_WARM_START 2    /* start from the u passed in instead of the background u      */
+#define MGFR_PROFILE 4       /* time every finest-level smoother launch with HIP events      */
+
+/* Model (Sec. II, Sec. III.A): Om, OL (< 0 means 1 - Om), scale factor a, Hu-Sawicki n,
+ * |f_R0| (the present background f_R), box side B in Mpc/h. */
+typedef struct mgfr_params {
+    double omega_m, omega_l, a, n, fr0_abs, box_mpc_h;
+} mgfr_params;
+
+/* Solver options.  mgfr_default_opts() fills the defaults listed here. */
+typedef struct mgfr_opts {
+    double tol;           /* stop when rms(L) over the finest cells <= tol          [1e-8]   */
+    int pre, post;        /* Newton-Gauss-Seidel sweeps before/after the coarse step [2, 2] */
+    int coarsest_n;       /* side of the coarsest level, power of two >= 2          [4]      */
+    int coarsest_sweeps;  /* cap on the sweeps of the coarsest level                [400]    */
+    int max_cycles;       /* cap on V-cycles (mixed: on FP64 outer iterations)      [60]     */
+    int precision;        /* MGFR_FP64 or MGFR_MIXED                                [FP64]   */
+    int flags;            /* MGFR_SUBTRACT_MEAN | MGFR_WARM_START                   [0]      */
+    int inner_cycles;     /* mixed: FP32 V-cycles per FP64 outer iteration          [1]      */
+    double max_step;      /* > 0: bound |Newton step| per visit; 0: plain Newton    [1.0]    */
+    double coarsest_rtol; /* coarsest level sweeps until rms <= rtol x initial; 0: always
+                             coarsest_sweeps sweeps                                  [1e-3]   */
+} mgfr_opts;
+
+/* Counters of the last solve on a context (mgfr_get_stats). */
+typedef struct mgfr_stats {
+    int cycles;                /* V-cycles (FP64) or FP64 outer iterations (mixed)             */
+    int inner_cycles;          /* mixed: FP32 V-cycles in total; FP64: 0                       */
+    long long cell_updates;    /* Newton-Gauss-Seidel cell visits on all levels                */
+    long long finest_updates;  /* of which on the finest level                                 */
+    int sweep_launches;        /* MGFR_PROFILE: finest-level smoother kernel launches timed    */
+    double sweep_ms;           /* MGFR_PROFILE: their summed duration (HIP events, same stream) */
+    double sweep_bytes;        /* algorithmic bytes of those launches: 12 B (FP64) or 6 B (FP32)
+                                  per cell per colour, i.e. read u, read rho/f, write u once
+                                  per full sweep                                            */
+    double solve_ms;           /* host wall time of the last solve call                        */
+} mgfr_stats;
+
+typedef struct mgfr_ctx mgfr_ctx;
+
+/* Creates a context bound to HIP device `device`.  Returns MGFR_OK or MGFR_EDEVICE. */
+int mgfr_create(mgfr_ctx** ctx, int device);
+
+/* Frees the context and its device scratch (waits for its work to finish). */
+void mgfr_destroy(mgfr_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none).  Owned by ctx. */
+const char* mgfr_last_error(const mgfr_ctx* ctx);
+
+/* Copies the counters of the last solve on ctx into *out. */
+int mgfr_get_stats(const mgfr_ctx* ctx, mgfr_stats* out);
+
+/* Writes the defaults into *opts. */
+void mgfr_default_opts(mgfr_opts* opts);
+
+/* Derived constants of the model on an N^3 domain grid (Sec. II, III, VI.A.1), host only:
+ * out8 = {xi, c~, K = (n a^2 xi)^(1/(n+1)), A = (1/3) Om a^4 K,
+ *         Sbar = Om a^4 (a^-3 + 4 OL/Om), D = Om a, u_bar, C = c~^2 / (2 h^2), h = 1/N}. */
+int mgfr_constants(const mgfr_params* params, int N, double* out8);
+
+/* Residual of a given field (device): d_i = L_i(u) for every cell of the periodic N^3
+ * grid, the operator above with contrast rho~ - 1 (or rho~ - mean with
+ * MGFR_SUBTRACT_MEAN in flags).  rho, u, d: device, N^3.  Does not synchronise. */
+int mgfr_residual(mgfr_ctx* ctx, const double* rho, const double* u, int N,
+                  const mgfr_params* params, int flags, double* d, void* stream);
+
+/* The domain-grid solve (Sec. V.B, Sec. VI.A).
+ * rho      device, N^3: code-unit density (mean 1 in the paper's units; negative values
+ *          are allowed, non-finite ones are rejected with MGFR_ENONFINITE).
+ * N        power of two, N >= opts->coarsest_n.
+ * u        device, N^3: output; with MGFR_WARM_START also the starting field.
+ * res_hist host, max_cycles + 1 doubles (may be NULL): rms(L) before the first cycle and
+ *          after every cycle (mixed: after every FP64 outer iteration).
+ * n_hist   host (may be NULL): number of entries written to res_hist.
+ * Returns MGFR_OK when rms(L) <= tol, MGFR_ENOTCONV when max_cycles was reached first
+ * (u holds the last iterate).  Synchronises the stream. */
+int mg_fr_solve(mgfr_ctx* ctx, const double* rho, int N, const mgfr_params* params,
+                const mgfr_opts* opts, double* u, double* res_hist, int* n_hist, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGFR_H */

@@ -110,6 +110,8 @@ def lib():
         for f in ("orc_constants", "orc_operator", "orc_operator_at", "orc_solve", "orc_solve_patch",
                   "orc_patch_boundary", "orc_single_grid"):
             getattr(L, f).restype = ctypes.c_int
+        L.orc_last_cell_updates.argtypes = []
+        L.orc_last_cell_updates.restype = ctypes.c_longlong
         _lib = L
     return _lib
 
@@ -239,6 +241,11 @@ def solve_patches(u_domain, patches, rho_patches, model: Model, opts: Opts | Non
         ub, u0 = patch_boundary(pu, po, per, P["origin"], n)
         us[p], hs[p], sts[p] = solve_patch(rho_patches[p], h, ub, model, u0, opts)
     return us, hs, sts
+
+
+def last_cell_updates() -> int:
+    """Smoother cell visits of the last oracle solve (timing reports only)."""
+    return int(lib().orc_last_cell_updates())
 
 
 def single_grid(rho, model: Model, u0, nsweeps: int, subtract_mean: bool = False,

@@ -150,10 +150,16 @@ static double cell_op(const grid* g, const consts* c, const double* u, int i, in
     return L;
 }
 
+/* Cell visits of the smoother since the last solve started (reported for timing only). */
+static long long g_updates = 0;
+
+long long orc_last_cell_updates(void) { return g_updates; }
+
 /* Red-black Newton-Gauss-Seidel sweep: red (i+j+k even) first (Sec. V.B.1). */
 static void ngs_sweep(const grid* g, const consts* c, double* u, const double* f, double max_step)
 {
     int n = g->n;
+    g_updates += (long long)n * n * n;
     for (int colour = 0; colour < 2; ++colour)
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j)
@@ -361,6 +367,7 @@ static void free_levels(level* lv, int nlev)
 static int run_cycles(level* lv, int nlev, const consts* c, const orc_opts* o, double* hist,
                       int* nhist)
 {
+    g_updates = 0;
     long long ncell = (long long)lv[0].g.n * lv[0].g.n * lv[0].g.n;
     double rms = sqrt(residual(&lv[0].g, c, lv[0].u, NULL, NULL) / (double)ncell);
     int k = 0;

@@ -75,6 +75,9 @@ int orc_patch_boundary(const double* parent_u, int pn, const int* porigin, int p
 int orc_single_grid(const double* rho, int N, const orc_model* m, int subtract_mean, double max_step,
                     double* u, int nsweeps, double* hist);
 
+/* Smoother cell visits (all levels) of the last solve; for timing reports only. */
+long long orc_last_cell_updates(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,404 @@
+// Double-precision multigrid kernels for gfx950 (wave64).
+//
+// The equation is the f(R) field equation in the variable u, f~_R = -exp(u) (Sec. III.C),
+// discretised with the conservative 7-point flux of eq. discrete_fR (face b = arithmetic
+// mean of the two cell values), multiplied by c~^2 as in eq. bc_modified_fR_op.  Each
+// Newton-Gauss-Seidel visit of a cell replaces u_i by u_i - (L_i - f_i) / (dL_i/du_i)
+// (Sec. V.B.1, with the derivative of eq. bc_modified_fR_dop for a cell with no ghost).
+#include "mgfr_impl.h"
+
+namespace mgfr {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxPartials = 4096;
+
+struct OpVal {
+    double L, dL;
+};
+
+// L_i - f_i and dL_i/du_i from the cell value and its six neighbours.
+__device__ __forceinline__ OpVal cell_op(const Grid& g, double ui, const double (&un)[6], double f)
+{
+    const double bi = exp(ui);
+    double su = 0.0, sb = 0.0, sbu = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const double du = un[q] - ui;
+        const double bn = exp(un[q]);
+        su += du;
+        sb += bn;
+        sbu = fma(bn, du, sbu);
+    }
+    const double S = g.A * exp(-ui * g.inv_np1);
+    OpVal r;
+    // sum_nb (b_nb + b_i)(u_nb - u_i) = sum b_nb du + b_i sum du
+    r.L = g.C * fma(bi, su, sbu) + S - f;
+    // sum_nb [b_i (u_nb - u_i) - b_nb - b_i]
+    r.dL = g.C * (fma(bi, su, -sb) - 6.0 * bi) - S * g.inv_np1;
+    return r;
+}
+
+__device__ __forceinline__ double rhs(const Grid& g, const double* src, long long q)
+{
+    return fma(g.fscale, src[q] - g.sref, g.fshift);
+}
+
+__device__ __forceinline__ long long at(const Grid& g, int i, int j, int k)
+{
+    return ((((long long)i << g.lg) + j) << g.lg) + k;
+}
+
+__device__ __forceinline__ void load_nbrs(const Grid& g, const double* u, int i, int j, int k,
+                                          double (&un)[6])
+{
+    const int m = g.n - 1;
+    un[0] = u[at(g, (i - 1) & m, j, k)];
+    un[1] = u[at(g, (i + 1) & m, j, k)];
+    un[2] = u[at(g, i, (j - 1) & m, k)];
+    un[3] = u[at(g, i, (j + 1) & m, k)];
+    un[4] = u[at(g, i, j, (k - 1) & m)];
+    un[5] = u[at(g, i, j, (k + 1) & m)];
+}
+
+__device__ __forceinline__ double bounded(double step, double ms)
+{
+    // comparisons (not fmin/fmax) so that a NaN step stays NaN
+    if (ms > 0.0) {
+        if (step > ms) step = ms;
+        if (step < -ms) step = -ms;
+    }
+    return step;
+}
+
+// One colour of a sweep; one thread per cell of that colour.
+__global__ void __launch_bounds__(kBlock) k_ngs_colour(Grid g, double* __restrict__ u,
+                                                       const double* __restrict__ src, int colour)
+{
+    const long long half = 1LL << (3 * g.lg - 1);
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= half) return;
+    const int hk = g.n >> 1;
+    const int s = (int)(t & (hk - 1));
+    const long long row = t >> (g.lg - 1);
+    const int i = (int)(row >> g.lg), j = (int)(row & (g.n - 1));
+    const int k = 2 * s + ((i + j + colour) & 1);
+    const long long q = at(g, i, j, k);
+    double un[6];
+    load_nbrs(g, u, i, j, k, un);
+    const double ui = u[q];
+    const OpVal r = cell_op(g, ui, un, rhs(g, src, q));
+    u[q] = ui + bounded(-r.L / r.dL, g.max_step);
+}
+
+// One thread per coarse cell: residuals of its 8 children, restricted by the mean.
+__global__ void __launch_bounds__(kBlock) k_resid_restrict(Grid g, const double* __restrict__ u,
+                                                           const double* __restrict__ src,
+                                                           double* __restrict__ uc,
+                                                           double* __restrict__ uhat,
+                                                           double* __restrict__ fc)
+{
+    const int lgc = g.lg - 1, nc = g.n >> 1;
+    const long long tc = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (tc >= (1LL << (3 * lgc))) return;
+    const int I = (int)(tc >> (2 * lgc)), J = (int)((tc >> lgc) & (nc - 1)), K = (int)(tc & (nc - 1));
+    double su = 0.0, sd = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+                const long long q = at(g, i, j, k);
+                double un[6];
+                load_nbrs(g, u, i, j, k, un);
+                const double ui = u[q];
+                su += ui;
+                sd += cell_op(g, ui, un, rhs(g, src, q)).L;
+            }
+    uc[tc] = 0.125 * su;
+    uhat[tc] = 0.125 * su;
+    fc[tc] = 0.125 * sd;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fas_rhs(Grid g, const double* __restrict__ uhat,
+                                                    double* __restrict__ f)
+{
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= (1LL << (3 * g.lg))) return;
+    const int i = (int)(q >> (2 * g.lg)), j = (int)((q >> g.lg) & (g.n - 1)), k = (int)(q & (g.n - 1));
+    double un[6];
+    load_nbrs(g, uhat, i, j, k, un);
+    f[q] = cell_op(g, uhat[q], un, 0.0).L - f[q];
+}
+
+// One thread per fine cell; gc describes the coarse level.
+__global__ void __launch_bounds__(kBlock) k_prolong_correct(Grid gc, double* __restrict__ uf,
+                                                            const double* __restrict__ uc,
+                                                            const double* __restrict__ uhat)
+{
+    const int lg = gc.lg + 1, n = gc.n << 1, mc = gc.n - 1;
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= (1LL << (3 * lg))) return;
+    const int i = (int)(q >> (2 * lg)), j = (int)((q >> lg) & (n - 1)), k = (int)(q & (n - 1));
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int Ip = (I + ((i & 1) ? 1 : -1)) & mc;
+    const int Jp = (J + ((j & 1) ? 1 : -1)) & mc;
+    const int Kp = (K + ((k & 1) ? 1 : -1)) & mc;
+    auto e = [&](int a, int b, int c) {
+        const long long qc = at(gc, a, b, c);
+        return uc[qc] - uhat[qc];
+    };
+    const double p = (27.0 / 64.0) * e(I, J, K) +
+                     (9.0 / 64.0) * (e(Ip, J, K) + e(I, Jp, K) + e(I, J, Kp)) +
+                     (3.0 / 64.0) * (e(Ip, Jp, K) + e(Ip, J, Kp) + e(I, Jp, Kp)) +
+                     (1.0 / 64.0) * e(Ip, Jp, Kp);
+    uf[q] += p;
+}
+
+// Deterministic block reductions over kBlock threads (fixed tree order).
+// block_sum_max: a <- sum of a, b <- max of b (NaN propagates).  block_sum2: both summed.
+template <bool SecondIsMax>
+__device__ void block_reduce2(double& a, double& b, double* sh_a, double* sh_b)
+{
+    const int t = threadIdx.x;
+    sh_a[t] = a;
+    sh_b[t] = b;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            sh_a[t] += sh_a[t + w];
+            const double o = sh_b[t + w];
+            if (SecondIsMax) {
+                if (!(sh_b[t] >= o)) sh_b[t] = o;
+            } else {
+                sh_b[t] += o;
+            }
+        }
+        __syncthreads();
+    }
+    a = sh_a[0];
+    b = sh_b[0];
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kBlock) k_coarsest(Grid g, double* __restrict__ u,
+                                                     const double* __restrict__ src, int cap,
+                                                     double rtol, long long* __restrict__ sweeps_done)
+{
+    __shared__ double su[512];
+    __shared__ double sf[512];
+    __shared__ double rs[kBlock], rm[kBlock];
+    const int nc = 1 << (3 * g.lg);
+    for (int q = threadIdx.x; q < nc; q += kBlock) {
+        su[q] = u[q];
+        sf[q] = rhs(g, src, q);
+    }
+    __syncthreads();
+    const int m = g.n - 1;
+    auto nbrs = [&](int q, double (&un)[6]) {
+        const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
+        un[0] = su[(((i - 1) & m) << (2 * g.lg)) + (j << g.lg) + k];
+        un[1] = su[(((i + 1) & m) << (2 * g.lg)) + (j << g.lg) + k];
+        un[2] = su[(i << (2 * g.lg)) + (((j - 1) & m) << g.lg) + k];
+        un[3] = su[(i << (2 * g.lg)) + (((j + 1) & m) << g.lg) + k];
+        un[4] = su[(i << (2 * g.lg)) + (j << g.lg) + ((k - 1) & m)];
+        un[5] = su[(i << (2 * g.lg)) + (j << g.lg) + ((k + 1) & m)];
+        return (i + j + k) & 1;
+    };
+    auto rms = [&]() {
+        double s = 0.0, mx = 0.0;
+        for (int q = threadIdx.x; q < nc; q += kBlock) {
+            double un[6];
+            nbrs(q, un);
+            const double d = cell_op(g, su[q], un, sf[q]).L;
+            s += d * d;
+        }
+        block_reduce2<true>(s, mx, rs, rm);
+        return sqrt(s / nc);
+    };
+    const double r0 = rtol > 0.0 ? rms() : 0.0;
+    int sweep = 0;
+    for (; sweep < cap; ++sweep) {
+        if (rtol > 0.0 && rms() <= rtol * r0) break;
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int q = threadIdx.x; q < nc; q += kBlock) {
+                double un[6];
+                if (nbrs(q, un) != colour) continue;
+                const double ui = su[q];
+                const OpVal r = cell_op(g, ui, un, sf[q]);
+                su[q] = ui + bounded(-r.L / r.dL, g.max_step);
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = threadIdx.x; q < nc; q += kBlock) u[q] = su[q];
+    if (threadIdx.x == 0 && sweeps_done) sweeps_done[0] += sweep;
+}
+
+__global__ void __launch_bounds__(kBlock) k_residual_field(Grid g, const double* __restrict__ u,
+                                                           const double* __restrict__ src,
+                                                           double* __restrict__ d)
+{
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= (1LL << (3 * g.lg))) return;
+    const int i = (int)(q >> (2 * g.lg)), j = (int)((q >> g.lg) & (g.n - 1)), k = (int)(q & (g.n - 1));
+    double un[6];
+    load_nbrs(g, u, i, j, k, un);
+    d[q] = cell_op(g, u[q], un, rhs(g, src, q)).L;
+}
+
+__global__ void __launch_bounds__(kBlock) k_residual_partial(Grid g, const double* __restrict__ u,
+                                                             const double* __restrict__ src,
+                                                             double* __restrict__ partial)
+{
+    __shared__ double rs[kBlock], rm[kBlock];
+    const long long ncell = 1LL << (3 * g.lg);
+    double s = 0.0, mx = 0.0;
+    for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < ncell;
+         q += (long long)gridDim.x * kBlock) {
+        const int i = (int)(q >> (2 * g.lg)), j = (int)((q >> g.lg) & (g.n - 1)), k = (int)(q & (g.n - 1));
+        double un[6];
+        load_nbrs(g, u, i, j, k, un);
+        const double d = cell_op(g, u[q], un, rhs(g, src, q)).L;
+        s += d * d;
+        const double ad = fabs(d);
+        if (!(mx >= ad)) mx = ad;
+    }
+    block_reduce2<true>(s, mx, rs, rm);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = s;
+        partial[2 * blockIdx.x + 1] = mx;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sum_count_partial(const double* __restrict__ x,
+                                                              long long n,
+                                                              double* __restrict__ partial)
+{
+    __shared__ double rs[kBlock], rm[kBlock];
+    double s = 0.0, c = 0.0;
+    for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) {
+        const double v = x[q];
+        if (isfinite(v)) s += v;
+        else c += 1.0;
+    }
+    block_reduce2<false>(s, c, rs, rm);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = s;
+        partial[2 * blockIdx.x + 1] = c;
+    }
+}
+
+// One workgroup folds `nb` (sum, max-or-sum) pairs in a fixed order.
+__global__ void __launch_bounds__(kBlock) k_fold(const double* __restrict__ partial, int nb,
+                                                 int second_is_sum, double* __restrict__ out)
+{
+    __shared__ double rs[kBlock], rm[kBlock];
+    double s = 0.0, m = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        s += partial[2 * b];
+        const double o = partial[2 * b + 1];
+        if (second_is_sum) m += o;
+        else if (!(m >= o)) m = o;
+    }
+    if (second_is_sum) block_reduce2<false>(s, m, rs, rm);
+    else block_reduce2<true>(s, m, rs, rm);
+    if (threadIdx.x == 0) {
+        out[0] = s;
+        out[1] = m;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill(double* __restrict__ x, double v, long long n)
+{
+    for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock)
+        x[q] = v;
+}
+
+inline unsigned blocks_for(long long work)
+{
+    return (unsigned)((work + kBlock - 1) / kBlock);
+}
+
+inline unsigned reduction_blocks(long long work)
+{
+    long long b = (work + kBlock - 1) / kBlock;
+    return (unsigned)(b < kMaxPartials ? (b < 1 ? 1 : b) : kMaxPartials);
+}
+
+}  // namespace
+
+long long reduction_scratch() { return 2LL * kMaxPartials; }
+
+hipError_t ngs_sweep(const Grid& g, double* u, const double* src, hipStream_t s)
+{
+    const long long half = cells(g) / 2;
+    for (int colour = 0; colour < 2; ++colour) {
+        hipLaunchKernelGGL(k_ngs_colour, dim3(blocks_for(half)), dim3(kBlock), 0, s, g, u, src, colour);
+    }
+    return hipGetLastError();
+}
+
+hipError_t resid_restrict(const Grid& g, const double* u, const double* src, double* uc,
+                          double* uhat, double* fc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_resid_restrict, dim3(blocks_for(cells(g) / 8)), dim3(kBlock), 0, s, g, u, src,
+                       uc, uhat, fc);
+    return hipGetLastError();
+}
+
+hipError_t fas_rhs(const Grid& gc, const double* uhat, double* f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fas_rhs, dim3(blocks_for(cells(gc))), dim3(kBlock), 0, s, gc, uhat, f);
+    return hipGetLastError();
+}
+
+hipError_t prolong_correct(const Grid& gc, double* uf, const double* uc, const double* uhat,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prolong_correct, dim3(blocks_for(cells(gc) * 8)), dim3(kBlock), 0, s, gc, uf,
+                       uc, uhat);
+    return hipGetLastError();
+}
+
+hipError_t coarsest_solve(const Grid& g, double* u, const double* src, int cap, double rtol,
+                          long long* sweeps_done, hipStream_t s)
+{
+    if (g.n > 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_coarsest, dim3(1), dim3(kBlock), 0, s, g, u, src, cap, rtol, sweeps_done);
+    return hipGetLastError();
+}
+
+hipError_t residual_field(const Grid& g, const double* u, const double* src, double* d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_residual_field, dim3(blocks_for(cells(g))), dim3(kBlock), 0, s, g, u, src, d);
+    return hipGetLastError();
+}
+
+hipError_t residual_norm(const Grid& g, const double* u, const double* src, double* partial,
+                         double* out, hipStream_t s)
+{
+    const unsigned nb = reduction_blocks(cells(g));
+    hipLaunchKernelGGL(k_residual_partial, dim3(nb), dim3(kBlock), 0, s, g, u, src, partial);
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, partial, (int)nb, 0, out);
+    return hipGetLastError();
+}
+
+hipError_t sum_and_count_nonfinite(const double* x, long long n, double* partial, double* out,
+                                   hipStream_t s)
+{
+    const unsigned nb = reduction_blocks(n);
+    hipLaunchKernelGGL(k_sum_count_partial, dim3(nb), dim3(kBlock), 0, s, x, n, partial);
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, partial, (int)nb, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t fill(double* x, double v, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(reduction_blocks(n)), dim3(kBlock), 0, s, x, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace mgfr

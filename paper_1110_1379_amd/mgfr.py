@@ -1,0 +1,210 @@
+"""Python binding of libmgfr.so (include/mgfr.h): argument marshalling only.
+
+Every step of the solve runs in the HIP library; PyTorch supplies device memory and the
+stream.  The names follow the C ABI: mgfr_create, mg_fr_solve, mgfr_residual, ...  Loading
+fails loudly when the library has not been built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field, fields
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmgfr.so")
+
+MGFR_OK, MGFR_EINVAL, MGFR_ENONFINITE, MGFR_ENOTCONV, MGFR_EDEVICE, MGFR_ENOMEM = 0, -1, -2, -3, -4, -5
+MGFR_FP64, MGFR_MIXED = 0, 1
+MGFR_SUBTRACT_MEAN, MGFR_WARM_START, MGFR_PROFILE = 1, 2, 4
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENONFINITE", -3: "ENOTCONV", -4: "EDEVICE", -5: "ENOMEM"}
+
+
+class mgfr_params(ctypes.Structure):
+    _fields_ = [("omega_m", ctypes.c_double), ("omega_l", ctypes.c_double), ("a", ctypes.c_double),
+                ("n", ctypes.c_double), ("fr0_abs", ctypes.c_double), ("box_mpc_h", ctypes.c_double)]
+
+
+class mgfr_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("pre", ctypes.c_int), ("post", ctypes.c_int),
+                ("coarsest_n", ctypes.c_int), ("coarsest_sweeps", ctypes.c_int),
+                ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
+                ("inner_cycles", ctypes.c_int), ("max_step", ctypes.c_double),
+                ("coarsest_rtol", ctypes.c_double)]
+
+
+class mgfr_stats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("inner_cycles", ctypes.c_int),
+                ("cell_updates", ctypes.c_longlong), ("finest_updates", ctypes.c_longlong),
+                ("sweep_launches", ctypes.c_int), ("sweep_ms", ctypes.c_double),
+                ("sweep_bytes", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+@dataclass
+class Params:
+    """Hu-Sawicki f(R) model and box (mirrors mgfr_params)."""
+    omega_m: float = 0.24
+    omega_l: float = -1.0
+    a: float = 1.0
+    n: float = 1.0
+    fr0_abs: float = 1e-5
+    box_mpc_h: float = 64.0
+
+    def c(self) -> mgfr_params:
+        return mgfr_params(*[getattr(self, f.name) for f in fields(self)])
+
+
+_lib = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded libmgfr.so (raises LibraryMissing if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        P, O = ctypes.POINTER(mgfr_params), ctypes.POINTER(mgfr_opts)
+        sig = {
+            "mgfr_create": ([ctypes.POINTER(vp), ctypes.c_int], ctypes.c_int),
+            "mgfr_destroy": ([vp], None),
+            "mgfr_last_error": ([vp], ctypes.c_char_p),
+            "mgfr_default_opts": ([O], None),
+            "mgfr_get_stats": ([vp, ctypes.POINTER(mgfr_stats)], ctypes.c_int),
+            "mgfr_constants": ([P, ctypes.c_int, dp], ctypes.c_int),
+            "mgfr_residual": ([vp, vp, vp, ctypes.c_int, P, ctypes.c_int, vp, vp], ctypes.c_int),
+            "mg_fr_solve": ([vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ("mgfr_create", "mgfr_destroy", "mgfr_last_error", "mgfr_default_opts", "mgfr_constants",
+            "mgfr_residual", "mg_fr_solve", "mgfr_get_stats")
+
+
+def mgfr_default_opts(**overrides) -> mgfr_opts:
+    o = mgfr_opts()
+    lib().mgfr_default_opts(ctypes.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(f"mgfr_opts has no field {k}")
+        setattr(o, k, v)
+    return o
+
+
+CONST_NAMES = ("xi", "ctilde", "K", "A", "Sbar", "D", "ubar", "C")
+
+
+def mgfr_constants(params: Params, N: int) -> dict:
+    out = (ctypes.c_double * 8)()
+    st = lib().mgfr_constants(ctypes.byref(params.c()), N, out)
+    if st != MGFR_OK:
+        raise ValueError(f"mgfr_constants failed ({STATUS_NAMES.get(st, st)})")
+    return dict(zip(CONST_NAMES, list(out)))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class MgfrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Context:
+    """Owns an mgfr_ctx on one device (its multigrid scratch persists between calls)."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = ctypes.c_void_p()
+        st = lib().mgfr_create(ctypes.byref(h), device)
+        if st != MGFR_OK:
+            raise MgfrError(st, f"mgfr_create(device={device}) failed")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().mgfr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return lib().mgfr_last_error(self.handle).decode()
+
+
+def mgfr_get_stats(ctx: Context) -> dict:
+    s = mgfr_stats()
+    st = lib().mgfr_get_stats(ctx.handle, ctypes.byref(s))
+    if st != MGFR_OK:
+        raise MgfrError(st, "mgfr_get_stats failed")
+    return s.as_dict()
+
+
+def mgfr_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def mgfr_residual(ctx: Context, rho, u, params: Params, flags: int = 0, out=None, stream=None):
+    """d = L(u) on the periodic grid (device tensors, float64, N^3)."""
+    import torch
+    N = rho.shape[0]
+    if out is None:
+        out = torch.empty_like(u)
+    st = lib().mgfr_residual(ctx.handle, _ptr(rho), _ptr(u), N, ctypes.byref(params.c()), flags,
+                             _ptr(out), _stream(stream))
+    if st != MGFR_OK:
+        raise MgfrError(st, ctx.last_error())
+    return out
+
+
+def mg_fr_solve(ctx: Context, rho, params: Params, opts: mgfr_opts | None = None, u=None,
+                stream=None, raise_on_error: bool = True):
+    """Solves the domain grid.  rho, u: float64 device tensors of shape (N, N, N); u is
+    written in place (and read as the start field with MGFR_WARM_START).
+    Returns (u, residual history as a numpy array, status)."""
+    import torch
+    N = rho.shape[0]
+    if opts is None:
+        opts = mgfr_default_opts()
+    if u is None:
+        u = torch.empty_like(rho)
+    hist = np.zeros(opts.max_cycles + 1)
+    nh = ctypes.c_int(0)
+    st = lib().mg_fr_solve(ctx.handle, _ptr(rho), N, ctypes.byref(params.c()), ctypes.byref(opts), _ptr(u),
+                           hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(nh),
+                           _stream(stream))
+    if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
+        raise MgfrError(st, ctx.last_error())
+    return u, hist[:nh.value].copy(), st
