@@ -65,9 +65,22 @@ typedef struct mgfr_opts {
     int flags;            /* MGFR_SUBTRACT_MEAN | MGFR_WARM_START                   [0]      */
     int inner_cycles;     /* mixed: FP32 V-cycles per FP64 outer iteration          [1]      */
     double max_step;      /* > 0: bound |Newton step| per visit; 0: plain Newton    [1.0]    */
-    double coarsest_rtol; /* coarsest level sweeps until rms <= rtol x initial; 0: always
-                             coarsest_sweeps sweeps                                  [1e-3]   */
+    double coarsest_rtol; /* coarsest level sweeps until rms <= rtol x initial or down to
+                             its rounding floor; 0: always coarsest_sweeps            [1e-3]   */
 } mgfr_opts;
+
+/* One refinement patch: a cube of n^3 cells at refinement level `level` >= 1 (cell size
+ * 1 / (N0 2^level)), with `origin` its first cell in level-`level` cells of the whole box.
+ * `parent` is -1 for level 1 (the parent is the periodic N0^3 domain grid) and otherwise the
+ * index of the enclosing level-1 patch.  `offset` is the element offset of its n^3 block in
+ * the packed density and solution arrays. */
+typedef struct mgfr_patch {
+    int level;
+    int parent;
+    int origin[3];
+    int n;
+    long long offset;
+} mgfr_patch;
 
 /* Counters of the last solve on a context (mgfr_get_stats). */
 typedef struct mgfr_stats {
@@ -77,9 +90,10 @@ typedef struct mgfr_stats {
     long long finest_updates;  /* of which on the finest level                                 */
     int sweep_launches;        /* MGFR_PROFILE: finest-level smoother kernel launches timed    */
     double sweep_ms;           /* MGFR_PROFILE: their summed duration (HIP events, same stream) */
-    double sweep_bytes;        /* algorithmic bytes of those launches: 12 B (FP64) or 6 B (FP32)
-                                  per cell per colour, i.e. read u, read rho/f, write u once
-                                  per full sweep                                            */
+    double sweep_bytes;        /* algorithmic bytes of those launches: per cell and sweep
+                                  24 B in FP64 (read u, read rho, write u) and 16 B in the
+                                  single-precision correction sweep (read base, rhs and e,
+                                  write e)                                                  */
     double solve_ms;           /* host wall time of the last solve call                        */
 } mgfr_stats;
 
@@ -111,6 +125,15 @@ int mgfr_constants(const mgfr_params* params, int N, double* out8);
 int mgfr_residual(mgfr_ctx* ctx, const double* rho, const double* u, int N,
                   const mgfr_params* params, int flags, double* d, void* stream);
 
+/* Single-grid relaxation (Sec. VI.D.1's comparison; also the smoother on its own):
+ * nsweeps red-black Newton-Gauss-Seidel sweeps of the periodic N^3 grid, in place on u
+ * (device, N^3), with opts->max_step and opts->flags (MGFR_SUBTRACT_MEAN, MGFR_PROFILE).
+ * variant: 0 = the kernel the solver uses for this N, 1 = one kernel per colour (in place),
+ * 2 = the fused red-black sweep (N >= 64; out of place through context scratch).
+ * Does not synchronise unless MGFR_PROFILE is set. */
+int mgfr_smooth(mgfr_ctx* ctx, const double* rho, double* u, int N, const mgfr_params* params,
+                const mgfr_opts* opts, int nsweeps, int variant, void* stream);
+
 /* The domain-grid solve (Sec. V.B, Sec. VI.A).
  * rho      device, N^3: code-unit density (mean 1 in the paper's units; negative values
  *          are allowed, non-finite ones are rejected with MGFR_ENONFINITE).
@@ -123,6 +146,40 @@ int mgfr_residual(mgfr_ctx* ctx, const double* rho, const double* u, int N,
  * (u holds the last iterate).  Synchronises the stream. */
 int mg_fr_solve(mgfr_ctx* ctx, const double* rho, int N, const mgfr_params* params,
                 const mgfr_opts* opts, double* u, double* res_hist, int* n_hist, void* stream);
+
+/* Refinement patches, level by level (Sec. V, Sec. VI.B; the paper solves every refinement
+ * level with its own V-cycles after the coarser level, with boundary values from it).
+ * For each refinement level, in increasing order: every patch of that level gets its ghost
+ * values by trilinear (27/9/3/1) interpolation of its parent's solution (u_domain for level
+ * 1, the already solved parent patch otherwise), boundary values u_b = (u_g + u_i)/2 on its
+ * faces (eq. u_i-1jk with mask ratio -1) and the interpolated parent solution as initial
+ * guess; then all patches of the level run batched FAS V-cycles with the BC-modified
+ * operator (eq. bc_modified_fR_op) until each has rms(L) <= tol or max_cycles.
+ * u_domain    device, N0^3: the solved domain grid (read only).
+ * patches     host, npatch entries.  Rules (else MGFR_EINVAL): n a power of two in
+ *             [coarsest_n, 128]; origin even (aligned to parent cells) with the cube inside the
+ *             level's box; a level >= 2 patch lies inside its parent with a margin of at least
+ *             one parent cell on every side; patches of one level do not overlap; blocks
+ *             [offset, offset + n^3) do not overlap and lie in [0, packed_cells).
+ * rho_packed  device, packed_cells: the density of every patch cell (code units).
+ * u_packed    device, packed_cells: output.
+ * res_hist    host, npatch x (max_cycles + 1) (may be NULL); n_hist host, npatch (may be NULL).
+ * Double precision; MGFR_SUBTRACT_MEAN is rejected (the contrast is rho - 1).  Returns
+ * MGFR_ENOTCONV if any patch missed tol (all patches are still written).  Synchronises. */
+int mg_fr_solve_patches(mgfr_ctx* ctx, const double* u_domain, int N0, const mgfr_patch* patches,
+                        int npatch, const double* rho_packed, double* u_packed, long long packed_cells,
+                        const mgfr_params* params, const mgfr_opts* opts, double* res_hist,
+                        int* n_hist, void* stream);
+
+/* Independent periodic boxes solved together: box b has side N[b] (power of two in
+ * [coarsest_n, 1024]), density rho[b] and output u[b] (device arrays of N[b]^3, pointers
+ * given in host arrays), and its own model per_box[b] (box size, |f_R0|, ...).  Every box
+ * runs the domain-grid FAS V-cycles of mg_fr_solve (double precision) batched with the
+ * others until rms(L) <= tol or max_cycles.  res_hist host nbox x (max_cycles + 1), n_hist
+ * host nbox (both may be NULL).  Returns MGFR_ENOTCONV if any box missed tol.  Synchronises. */
+int mg_fr_solve_batch(mgfr_ctx* ctx, int nbox, const int* N, const double* const* rho,
+                      const mgfr_params* per_box, const mgfr_opts* opts, double* const* u,
+                      double* res_hist, int* n_hist, void* stream);
 
 #ifdef __cplusplus
 }

@@ -192,6 +192,33 @@ static double residual(const grid* g, const consts* c, const double* u, const do
     return s;
 }
 
+/* Size of the double-precision rounding noise of rms(L - f): per cell, one unit in the last
+   place of u times |dL/du| (u is only known to that granularity) plus one of the sum of the
+   magnitudes of the terms, C (b_nb + b_i)|u_nb - u_i| per face, the curvature term and |f|
+   (rms over the grid).  Sweeps cannot push the residual much below it. */
+static double rounding_floor(const grid* g, const consts* c, const double* u, const double* f)
+{
+    const double eps = 2.220446049250313e-16;
+    int n = g->n;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                double dL;
+                cell_op(g, c, u, i, j, k, &dL);
+                double ui = u[at(n, i, j, k)], bi = exp(ui), t = 0.0;
+                for (int q = 0; q < 6; ++q) {
+                    int ii = (i + DI[q] + n) % n, jj = (j + DJ[q] + n) % n, kk = (k + DK[q] + n) % n;
+                    double un = u[at(n, ii, jj, kk)];
+                    t += g->C * (exp(un) + bi) * fabs(un - ui);
+                }
+                t += c->A * exp(-ui / (c->n + 1.0)) + (f ? fabs(f[at(n, i, j, k)]) : 0.0);
+                double fl = eps * (fabs(dL) * fabs(ui) + t);
+                s += fl * fl;
+            }
+    return sqrt(s / ((double)n * n * n));
+}
+
 /* Restriction: each coarse cell gets the mean of its 8 children. */
 static void restrict_mean(int n, const double* fine, double* coarse)
 {
@@ -276,9 +303,11 @@ static void vcycle(level* lv, int m, int nlev, const consts* c, const orc_opts* 
         long long nc3 = (long long)F->g.n * F->g.n * F->g.n;
         double r0 = sqrt(residual(&F->g, c, F->u, F->f, NULL) / (double)nc3);
         for (int s = 0; s < o->coarsest_sweeps; ++s) {
-            if (o->coarsest_rtol > 0.0 &&
-                sqrt(residual(&F->g, c, F->u, F->f, NULL) / (double)nc3) <= o->coarsest_rtol * r0)
-                break;
+            if (o->coarsest_rtol > 0.0) {
+                /* stop once reduced by coarsest_rtol or down to the rounding floor */
+                double r = sqrt(residual(&F->g, c, F->u, F->f, NULL) / (double)nc3);
+                if (r <= o->coarsest_rtol * r0 || r <= rounding_floor(&F->g, c, F->u, F->f)) break;
+            }
             ngs_sweep(&F->g, c, F->u, F->f, o->max_step);
         }
         return;

@@ -33,8 +33,8 @@ typedef struct {
     int subtract_mean;    /* 1: density contrast rho - mean(rho); 0: rho - 1              */
     int warm_start;       /* 1: start from the u passed in; 0: from the background u     */
     double max_step;      /* > 0: bound |Newton step| per visit; 0: the plain Newton step */
-    double coarsest_rtol; /* coarsest level: stop once its rms residual <= rtol x initial;
-                             0: always coarsest_sweeps sweeps                            */
+    double coarsest_rtol; /* coarsest level: stop once its rms residual <= rtol x initial
+                             or reaches the rounding floor; 0: always coarsest_sweeps   */
 } orc_opts;
 
 /* Derived constants, in this order:

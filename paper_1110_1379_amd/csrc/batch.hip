@@ -1,0 +1,566 @@
+// Host driver of the batched solves: refinement patches level by level (Sec. V, Sec. VI.B)
+// and many independent periodic boxes.  Every unit of a batch runs the same FAS V-cycle
+// (Sec. V.B.2) with its own size, constants and hierarchy; each phase of the cycle is one
+// launch over all units that take part in it, through a table of (unit grid, block) pairs.
+// After every cycle the per-unit residual norms come back to the host, and units that have
+// converged are switched off for the remaining cycles.
+#include <algorithm>
+#include <cstring>
+
+#include "host_internal.h"
+
+using namespace mgfr_host;
+
+namespace {
+
+struct Unit {
+    int n = 0, nlev = 0;
+    bool periodic = false;
+    Model md{};
+    double h = 0.0;              // finest spacing
+    double* u = nullptr;         // caller's solution (finest)
+    const double* rho = nullptr; // caller's density (finest)
+    std::vector<mgfr::BGrid> g;  // descriptor of each multigrid level
+};
+
+// Host image of everything the kernels of one batch read from device memory: descriptor
+// arrays and workgroup tables, concatenated into one buffer.
+struct Meta {
+    std::vector<char> bytes;
+    template <class T>
+    size_t add(const std::vector<T>& v)
+    {
+        size_t off = (bytes.size() + 255) & ~size_t(255);
+        bytes.resize(off + v.size() * sizeof(T));
+        if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
+};
+
+struct Launch {
+    size_t grids = 0, blk = 0, other = 0;  // offsets into the device meta buffer
+    int nblk = 0, ngrid = 0;
+};
+
+struct Depth {
+    Launch half_f, coarse_f, coarse_c, fine_f, faces_c, crs;
+    bool deep = false, coarsest = false;
+};
+
+struct Plan {
+    std::vector<Depth> depth;
+    Launch cells0, setup;
+    size_t first = 0, count = 0;  // per-unit block ranges of cells0 (for the norm fold)
+    int nunit = 0;
+    long long nblk_cells0 = 0;
+};
+
+// Blocks of `work(g)` items for each grid; grids listed in order, so each grid's blocks are
+// contiguous.
+template <class W>
+Launch table(Meta& meta, const std::vector<mgfr::BGrid>& grids, W work, std::vector<int>* first = nullptr,
+             std::vector<int>* count = nullptr)
+{
+    const int B = mgfr::batch_block();
+    std::vector<int2> blk;
+    for (size_t i = 0; i < grids.size(); ++i) {
+        const long long w = work(grids[i]);
+        const int nb = (int)((w + B - 1) / B);
+        if (first) first->push_back((int)blk.size());
+        if (count) count->push_back(nb);
+        for (int b = 0; b < nb; ++b) blk.push_back(make_int2((int)i, b));
+    }
+    Launch L;
+    L.grids = meta.add(grids);
+    L.blk = meta.add(blk);
+    L.nblk = (int)blk.size();
+    L.ngrid = (int)grids.size();
+    return L;
+}
+
+long long cells3(const mgfr::BGrid& g) { return 1LL << (3 * g.lg); }
+
+struct Batch {
+    mgfr_ctx* c;
+    const mgfr_opts* o;
+    hipStream_t s;
+    std::vector<Unit>& units;
+    Plan plan;
+    char* dmeta = nullptr;
+    int* dactive = nullptr;
+    std::vector<int> active;
+    double* dpartial = nullptr;
+    double* dout = nullptr;
+    std::vector<double> hout;
+    std::vector<void*> owned;
+
+    ~Batch()
+    {
+        for (void* p : owned) (void)hipFree(p);
+    }
+
+    template <class T>
+    int alloc(T** p, size_t count)
+    {
+        if (count == 0) count = 1;
+        if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess)
+            return c->fail(MGFR_ENOMEM, "hipMalloc of %zu bytes for a batch failed", count * sizeof(T));
+        owned.push_back(*p);
+        return MGFR_OK;
+    }
+
+    mgfr::BTable tab(const Launch& L) const
+    {
+        mgfr::BTable t;
+        t.grids = (const mgfr::BGrid*)(dmeta + L.grids);
+        t.blk = (const int2*)(dmeta + L.blk);
+        t.active = dactive;
+        return t;
+    }
+    const mgfr::BGrid* grids(const Launch& L) const { return (const mgfr::BGrid*)(dmeta + L.grids); }
+
+    // Allocates each unit's coarse levels (and patch boundary faces), fills the descriptors
+    // and uploads the plan.
+    int prepare()
+    {
+        const int cn = o->coarsest_n;
+        // storage
+        size_t need = 0;
+        for (Unit& U : units) {
+            U.nlev = 0;
+            for (int n = U.n; n >= cn; n /= 2) ++U.nlev;
+            for (int m = 0; m < U.nlev; ++m) {
+                const size_t n = (size_t)(U.n >> m);
+                if (m > 0) need += 3 * n * n * n;
+                if (!U.periodic) need += 6 * n * n;
+            }
+        }
+        double* pool = nullptr;
+        MGFR_TRY(alloc(&pool, need));
+        size_t at = 0;
+        for (size_t ui = 0; ui < units.size(); ++ui) {
+            Unit& U = units[ui];
+            U.g.assign(U.nlev, mgfr::BGrid{});
+            for (int m = 0; m < U.nlev; ++m) {
+                mgfr::BGrid& G = U.g[m];
+                const int n = U.n >> m;
+                const double hm = U.h * (double)(1 << m);
+                G.n = n;
+                G.lg = ilog2(n);
+                G.periodic = U.periodic ? 1 : 0;
+                G.unit = (int)ui;
+                G.C = U.md.ct * U.md.ct / (2.0 * hm * hm);
+                G.A = U.md.A;
+                G.inv_np1 = U.md.inv_np1;
+                G.max_step = o->max_step;
+                G.u0 = U.md.ubar;
+                const size_t n3 = (size_t)n * n * n;
+                if (m == 0) {
+                    G.u = U.u;
+                    G.src = U.rho;
+                    G.fscale = U.md.D;
+                    G.sref = 1.0;
+                    G.fshift = U.md.Sbar;
+                } else {
+                    G.u = pool + at;
+                    G.uhat = pool + at + n3;
+                    G.f = pool + at + 2 * n3;
+                    G.src = G.f;
+                    G.fscale = 1.0;
+                    G.sref = 0.0;
+                    G.fshift = 0.0;
+                    at += 3 * n3;
+                }
+                if (!U.periodic) {
+                    G.ub = pool + at;
+                    at += 6 * (size_t)n * n;
+                }
+            }
+        }
+        // tables
+        Meta meta;
+        int maxlev = 0;
+        for (Unit& U : units) maxlev = std::max(maxlev, U.nlev);
+        plan.depth.assign(maxlev, Depth{});
+        for (int m = 0; m < maxlev; ++m) {
+            std::vector<mgfr::BGrid> f, cgr, crs;
+            for (Unit& U : units) {
+                if (U.nlev > m + 1) {
+                    f.push_back(U.g[m]);
+                    cgr.push_back(U.g[m + 1]);
+                } else if (U.nlev == m + 1) {
+                    crs.push_back(U.g[m]);
+                }
+            }
+            Depth& D = plan.depth[m];
+            D.deep = !f.empty();
+            D.coarsest = !crs.empty();
+            if (D.deep) {
+                D.half_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 2; });
+                D.fine_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g); });
+                D.coarse_c = table(meta, cgr, [](const mgfr::BGrid& g) { return cells3(g); });
+                // resid_restrict: table over the coarse cells, indexed by the fine grids
+                D.coarse_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 8; });
+                D.coarse_f.other = D.coarse_c.grids;  // coarse grids, same order
+                D.fine_f.other = D.coarse_c.grids;
+                std::vector<mgfr::BGrid> pf, pc;
+                for (size_t i = 0; i < f.size(); ++i)
+                    if (!f[i].periodic) {
+                        pf.push_back(f[i]);
+                        pc.push_back(cgr[i]);
+                    }
+                D.faces_c = table(meta, pc, [](const mgfr::BGrid& g) { return 6LL * g.n * g.n; });
+                D.faces_c.other = meta.add(pf);
+            }
+            if (D.coarsest) {
+                D.crs.grids = meta.add(crs);
+                D.crs.ngrid = (int)crs.size();
+            }
+        }
+        std::vector<mgfr::BGrid> g0;
+        for (Unit& U : units) g0.push_back(U.g[0]);
+        std::vector<int> first, count;
+        plan.cells0 = table(meta, g0, [](const mgfr::BGrid& g) { return cells3(g); }, &first, &count);
+        plan.first = meta.add(first);
+        plan.count = meta.add(count);
+        plan.nunit = (int)units.size();
+        plan.nblk_cells0 = plan.cells0.nblk;
+        setup_offset = meta.bytes.size();
+        meta_image = std::move(meta.bytes);
+        return MGFR_OK;
+    }
+
+    std::vector<char> meta_image;
+    size_t setup_offset = 0;
+
+    // Appends extra tables (patch set-up) before the upload.
+    template <class T>
+    size_t add_extra(const std::vector<T>& v)
+    {
+        Meta m;
+        m.bytes = std::move(meta_image);
+        const size_t off = m.add(v);
+        meta_image = std::move(m.bytes);
+        return off;
+    }
+
+    int upload()
+    {
+        MGFR_TRY(alloc(&dmeta, meta_image.size()));
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(dmeta, meta_image.data(), meta_image.size(), hipMemcpyHostToDevice, s),
+                           "hipMemcpyAsync"));
+        MGFR_TRY(alloc(&dactive, units.size()));
+        active.assign(units.size(), 1);
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(dactive, active.data(), sizeof(int) * active.size(),
+                                             hipMemcpyHostToDevice, s),
+                           "hipMemcpyAsync"));
+        MGFR_TRY(alloc(&dpartial, 2 * (size_t)std::max<long long>(plan.nblk_cells0, 1)));
+        MGFR_TRY(alloc(&dout, 2 * units.size()));
+        hout.assign(2 * units.size(), 0.0);
+        // the host image must stay alive until the copy has run
+        return hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
+
+    void count_sweep(int m)
+    {
+        for (size_t i = 0; i < units.size(); ++i)
+            if (active[i] && units[i].nlev > m + 1) {
+                const long long n3 = cells3(units[i].g[m]);
+                c->stats.cell_updates += n3;
+                if (m == 0) c->stats.finest_updates += n3;
+            }
+    }
+
+    int sweep(const Depth& D, int m)
+    {
+        count_sweep(m);
+        return hip_check(c, mgfr::batch_ngs(tab(D.half_f), D.half_f.nblk, s), "batch_ngs");
+    }
+
+    int vcycle(int m)
+    {
+        const Depth& D = plan.depth[m];
+        if (D.coarsest)
+            MGFR_TRY(hip_check(c, mgfr::batch_coarsest(grids(D.crs), D.crs.ngrid, dactive, o->coarsest_sweeps,
+                                                       o->coarsest_rtol, s),
+                               "batch_coarsest"));
+        if (!D.deep) return MGFR_OK;
+        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(D, m));
+        MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict(tab(D.coarse_f), D.coarse_f.nblk,
+                                                         (const mgfr::BGrid*)(dmeta + D.coarse_f.other), s),
+                           "batch_resid_restrict"));
+        MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs"));
+        MGFR_TRY(vcycle(m + 1));
+        MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_coarse_diff"));
+        MGFR_TRY(hip_check(c, mgfr::batch_prolong_add(tab(D.fine_f), D.fine_f.nblk,
+                                                      (const mgfr::BGrid*)(dmeta + D.fine_f.other), s),
+                           "batch_prolong_add"));
+        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep(D, m));
+        return MGFR_OK;
+    }
+
+    // Coarse-level patch boundary values, from the finest ones down.
+    int restrict_faces()
+    {
+        for (size_t m = 0; m < plan.depth.size(); ++m) {
+            const Depth& D = plan.depth[m];
+            if (!D.deep || D.faces_c.nblk == 0) continue;
+            MGFR_TRY(hip_check(c, mgfr::batch_restrict_faces(tab(D.faces_c), D.faces_c.nblk,
+                                                             (const mgfr::BGrid*)(dmeta + D.faces_c.other), s),
+                               "batch_restrict_faces"));
+        }
+        return MGFR_OK;
+    }
+
+    // Per-unit rms of the finest residual into rms[] (synchronises).
+    int norms(std::vector<double>& rms, std::vector<double>& mx)
+    {
+        MGFR_TRY(hip_check(c, mgfr::batch_norm(tab(plan.cells0), plan.cells0.nblk, dpartial,
+                                               (const int*)(dmeta + plan.first), (const int*)(dmeta + plan.count),
+                                               plan.nunit, dout, s),
+                           "batch_norm"));
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(hout.data(), dout, sizeof(double) * hout.size(), hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync"));
+        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+        for (size_t i = 0; i < units.size(); ++i) {
+            if (!active[i]) continue;
+            rms[i] = std::sqrt(hout[2 * i] / (double)cells3(units[i].g[0]));
+            mx[i] = hout[2 * i + 1];
+        }
+        return MGFR_OK;
+    }
+
+    int check_finite()
+    {
+        MGFR_TRY(hip_check(c, mgfr::batch_nonfinite(tab(plan.cells0), plan.cells0.nblk, dpartial, s), "batch_nonfinite"));
+        MGFR_TRY(hip_check(c, mgfr::batch_fold(dpartial, (const int*)(dmeta + plan.first),
+                                               (const int*)(dmeta + plan.count), plan.nunit, dout, s),
+                           "batch_fold"));
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(hout.data(), dout, sizeof(double) * hout.size(), hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync"));
+        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+        for (size_t i = 0; i < units.size(); ++i)
+            if (hout[2 * i] != 0.0)
+                return c->fail(MGFR_ENONFINITE, "unit %zu: %.0f non-finite density or start values", i, hout[2 * i]);
+        return MGFR_OK;
+    }
+
+    // V-cycles until every unit has rms <= tol or max_cycles; histories per unit.
+    int run(double* res_hist, int* n_hist, int* worst_status)
+    {
+        const int H = o->max_cycles + 1;
+        std::vector<double> rms(units.size(), 0.0), mx(units.size(), 0.0);
+        std::vector<int> k(units.size(), 0);
+        MGFR_TRY(norms(rms, mx));
+        for (size_t i = 0; i < units.size(); ++i) {
+            if (res_hist) res_hist[i * H] = rms[i];
+            if (!(std::isfinite(rms[i])) || rms[i] <= o->tol) active[i] = 0;
+        }
+        int cycles = 0;
+        for (;;) {
+            bool any = false;
+            for (size_t i = 0; i < units.size(); ++i) any = any || active[i];
+            if (!any || cycles >= o->max_cycles) break;
+            MGFR_TRY(hip_check(c, hipMemcpyAsync(dactive, active.data(), sizeof(int) * active.size(),
+                                                 hipMemcpyHostToDevice, s),
+                               "hipMemcpyAsync"));
+            MGFR_TRY(vcycle(0));
+            MGFR_TRY(norms(rms, mx));
+            ++cycles;
+            for (size_t i = 0; i < units.size(); ++i) {
+                if (!active[i]) continue;
+                ++k[i];
+                if (res_hist) res_hist[i * H + k[i]] = rms[i];
+                if (!std::isfinite(rms[i]) || rms[i] <= o->tol) active[i] = 0;
+            }
+        }
+        c->stats.cycles += cycles;
+        *worst_status = MGFR_OK;
+        for (size_t i = 0; i < units.size(); ++i) {
+            if (n_hist) n_hist[i] = k[i] + 1;
+            if (!std::isfinite(rms[i])) *worst_status = MGFR_ENONFINITE;
+            else if (rms[i] > o->tol && *worst_status == MGFR_OK) *worst_status = MGFR_ENOTCONV;
+        }
+        return MGFR_OK;
+    }
+};
+
+int check_batch_opts(mgfr_ctx* c, const mgfr_opts* o)
+{
+    MGFR_TRY(check_opts(c, o));
+    if (o->precision != MGFR_FP64) return c->fail(MGFR_EINVAL, "batched solves run in double precision");
+    if (o->flags & MGFR_SUBTRACT_MEAN) return c->fail(MGFR_EINVAL, "MGFR_SUBTRACT_MEAN is not available for batches");
+    return MGFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_fr_solve_patches(mgfr_ctx* c, const double* u_domain, int N0, const mgfr_patch* patches, int npatch,
+                        const double* rho_packed, double* u_packed, long long packed_cells,
+                        const mgfr_params* params, const mgfr_opts* o, double* res_hist, int* n_hist,
+                        void* stream)
+{
+    if (!c) return MGFR_EINVAL;
+    c->err.clear();
+    c->stats = mgfr_stats{};
+    const auto t0 = std::chrono::steady_clock::now();
+    MGFR_TRY(check_batch_opts(c, o));
+    Model md;
+    if (derive_model(params, &md) != MGFR_OK) return c->fail(MGFR_EINVAL, "invalid model parameters");
+    if (npatch < 0 || (npatch > 0 && (!patches || !u_domain || !rho_packed || !u_packed)))
+        return c->fail(MGFR_EINVAL, "invalid patch arguments");
+    if (!is_pow2(N0) || N0 < 2 || N0 > 2048) return c->fail(MGFR_EINVAL, "N0=%d must be a power of two", N0);
+    if (npatch == 0) return MGFR_OK;
+    // layout rules
+    int maxlevel = 0;
+    std::vector<std::pair<long long, long long>> ranges;
+    for (int p = 0; p < npatch; ++p) {
+        const mgfr_patch& P = patches[p];
+        if (P.level < 1 || P.level > 10 || !is_pow2(P.n) || P.n < o->coarsest_n || P.n > 128)
+            return c->fail(MGFR_EINVAL, "patch %d: level %d / n %d out of range", p, P.level, P.n);
+        const long long side = (long long)N0 << P.level;
+        for (int d = 0; d < 3; ++d) {
+            if (P.origin[d] & 1) return c->fail(MGFR_EINVAL, "patch %d: origin not aligned to parent cells", p);
+            if (P.origin[d] < 0 || P.origin[d] + P.n > side)
+                return c->fail(MGFR_EINVAL, "patch %d: outside the level-%d domain", p, P.level);
+        }
+        if (P.level == 1) {
+            if (P.parent != -1) return c->fail(MGFR_EINVAL, "patch %d: level-1 patches have parent -1", p);
+        } else {
+            if (P.parent < 0 || P.parent >= npatch || patches[P.parent].level != P.level - 1)
+                return c->fail(MGFR_EINVAL, "patch %d: parent must be a level-%d patch", p, P.level - 1);
+            const mgfr_patch& Q = patches[P.parent];
+            for (int d = 0; d < 3; ++d)
+                if (P.origin[d] / 2 - 1 < Q.origin[d] || (P.origin[d] + P.n) / 2 > Q.origin[d] + Q.n - 1)
+                    return c->fail(MGFR_EINVAL, "patch %d: needs a one-cell margin inside patch %d", p, P.parent);
+        }
+        const long long n3 = (long long)P.n * P.n * P.n;
+        if (P.offset < 0 || P.offset + n3 > packed_cells)
+            return c->fail(MGFR_EINVAL, "patch %d: offset outside the packed arrays", p);
+        ranges.emplace_back(P.offset, P.offset + n3);
+        maxlevel = std::max(maxlevel, P.level);
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t i = 1; i < ranges.size(); ++i)
+        if (ranges[i].first < ranges[i - 1].second) return c->fail(MGFR_EINVAL, "patch blocks overlap in the packed arrays");
+    for (int p = 0; p < npatch; ++p)
+        for (int q = p + 1; q < npatch; ++q) {
+            const mgfr_patch &A = patches[p], &B = patches[q];
+            if (A.level != B.level) continue;
+            bool sep = false;
+            for (int d = 0; d < 3; ++d)
+                sep = sep || A.origin[d] + A.n <= B.origin[d] || B.origin[d] + B.n <= A.origin[d];
+            if (!sep) return c->fail(MGFR_EINVAL, "patches %d and %d overlap", p, q);
+        }
+    MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+    hipStream_t s = (hipStream_t)stream;
+    int worst = MGFR_OK;
+    const int H = o->max_cycles + 1;
+    for (int lev = 1; lev <= maxlevel; ++lev) {
+        std::vector<int> ids;
+        for (int p = 0; p < npatch; ++p)
+            if (patches[p].level == lev) ids.push_back(p);
+        if (ids.empty()) continue;
+        std::vector<Unit> units(ids.size());
+        for (size_t i = 0; i < ids.size(); ++i) {
+            const mgfr_patch& P = patches[ids[i]];
+            Unit& U = units[i];
+            U.n = P.n;
+            U.periodic = false;
+            U.md = md;
+            U.h = 1.0 / ((double)N0 * (double)(1 << lev));
+            U.u = u_packed + P.offset;
+            U.rho = rho_packed + P.offset;
+        }
+        Batch b{c, o, s, units};
+        MGFR_TRY(b.prepare());
+        // boundary set-up: interior initial guess and boundary faces from the parent level
+        std::vector<mgfr::PatchParent> parents;
+        std::vector<mgfr::BGrid> g0;
+        for (size_t i = 0; i < ids.size(); ++i) {
+            const mgfr_patch& P = patches[ids[i]];
+            mgfr::PatchParent pp{};
+            if (P.parent < 0) {
+                pp.u = u_domain;
+                pp.n = N0;
+                pp.periodic = 1;
+            } else {
+                const mgfr_patch& Q = patches[P.parent];
+                pp.u = u_packed + Q.offset;
+                pp.n = Q.n;
+                pp.periodic = 0;
+                for (int d = 0; d < 3; ++d) pp.origin[d] = Q.origin[d];
+            }
+            pp.lg = ilog2(pp.n);
+            for (int d = 0; d < 3; ++d) pp.child[d] = P.origin[d];
+            parents.push_back(pp);
+            g0.push_back(units[i].g[0]);
+        }
+        Meta extra;
+        extra.bytes = std::move(b.meta_image);
+        Launch setup = table(extra, g0, [](const mgfr::BGrid& g) { return 7LL * g.n * g.n; });
+        const size_t parents_off = extra.add(parents);
+        b.meta_image = std::move(extra.bytes);
+        MGFR_TRY(b.upload());
+        MGFR_TRY(hip_check(c, mgfr::batch_setup(b.tab(setup), setup.nblk, (const mgfr::PatchParent*)(b.dmeta + parents_off), s),
+                           "batch_setup"));
+        MGFR_TRY(b.restrict_faces());
+        MGFR_TRY(b.check_finite());
+        std::vector<double> hist_level(ids.size() * H, 0.0);
+        std::vector<int> nh_level(ids.size(), 0);
+        int st = MGFR_OK;
+        MGFR_TRY(b.run(hist_level.data(), nh_level.data(), &st));
+        if (st == MGFR_ENONFINITE) worst = st;
+        else if (st == MGFR_ENOTCONV && worst == MGFR_OK) worst = st;
+        for (size_t i = 0; i < ids.size(); ++i) {
+            if (res_hist) std::memcpy(res_hist + (size_t)ids[i] * H, hist_level.data() + i * H, sizeof(double) * H);
+            if (n_hist) n_hist[ids[i]] = nh_level[i];
+        }
+    }
+    c->stats.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (worst == MGFR_ENONFINITE) return c->fail(worst, "a patch residual became non-finite");
+    if (worst == MGFR_ENOTCONV) return c->fail(worst, "some patches did not reach tol in max_cycles");
+    return MGFR_OK;
+}
+
+int mg_fr_solve_batch(mgfr_ctx* c, int nbox, const int* N, const double* const* rho, const mgfr_params* per_box,
+                      const mgfr_opts* o, double* const* u, double* res_hist, int* n_hist, void* stream)
+{
+    if (!c) return MGFR_EINVAL;
+    c->err.clear();
+    c->stats = mgfr_stats{};
+    const auto t0 = std::chrono::steady_clock::now();
+    MGFR_TRY(check_batch_opts(c, o));
+    if (nbox < 0 || (nbox > 0 && (!N || !rho || !per_box || !u))) return c->fail(MGFR_EINVAL, "invalid batch arguments");
+    if (nbox == 0) return MGFR_OK;
+    std::vector<Unit> units(nbox);
+    for (int b = 0; b < nbox; ++b) {
+        if (!is_pow2(N[b]) || N[b] < o->coarsest_n || N[b] > 1024 || !rho[b] || !u[b])
+            return c->fail(MGFR_EINVAL, "box %d: N=%d must be a power of two in [coarsest_n, 1024]", b, N[b]);
+        if (derive_model(&per_box[b], &units[b].md) != MGFR_OK)
+            return c->fail(MGFR_EINVAL, "box %d: invalid model parameters", b);
+        units[b].n = N[b];
+        units[b].periodic = true;
+        units[b].h = 1.0 / N[b];
+        units[b].u = u[b];
+        units[b].rho = rho[b];
+    }
+    MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+    hipStream_t s = (hipStream_t)stream;
+    Batch bt{c, o, s, units};
+    MGFR_TRY(bt.prepare());
+    MGFR_TRY(bt.upload());
+    if (!(o->flags & MGFR_WARM_START))
+        MGFR_TRY(hip_check(c, mgfr::batch_fill(bt.tab(bt.plan.cells0), bt.plan.cells0.nblk, s), "batch_fill"));
+    MGFR_TRY(bt.check_finite());
+    int st = MGFR_OK;
+    MGFR_TRY(bt.run(res_hist, n_hist, &st));
+    c->stats.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (st == MGFR_ENONFINITE) return c->fail(st, "a box residual became non-finite");
+    if (st == MGFR_ENOTCONV) return c->fail(st, "some boxes did not reach tol in max_cycles");
+    return MGFR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,251 @@
+// Host-side internals shared by the drivers of libmgfr.so: model constants, the context,
+// level storage and error handling.  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/mgfr.h"
+#include "mgfr_impl.h"
+
+namespace mgfr_host {
+
+// Derived model constants (Sec. II, Sec. III.A, Sec. VI.A.1).
+struct Model {
+    double xi, ct, K, A, Sbar, D, ubar, inv_np1;
+};
+
+inline int derive_model(const mgfr_params* p, Model* m)
+{
+    if (!p) return MGFR_EINVAL;
+    const double om = p->omega_m, a = p->a, n = p->n;
+    const double ol = p->omega_l < 0.0 ? 1.0 - om : p->omega_l;
+    if (!(om > 0.0) || !(a > 0.0) || !(n > 0.0) || !(p->fr0_abs > 0.0) || !(p->box_mpc_h > 0.0) ||
+        !(ol >= 0.0) || !std::isfinite(om + a + n + p->fr0_abs + p->box_mpc_h + ol))
+        return MGFR_EINVAL;
+    // present background: f_R0 = -n xi / [3 (1 + 4 OL/Om)]^(n+1)
+    m->xi = p->fr0_abs * std::pow(3.0 * (1.0 + 4.0 * ol / om), n + 1.0) / n;
+    // c~ = c / (B H0), c = 299792.458 km/s, H0 = 100 h km/s/Mpc
+    m->ct = 299792.458 / (100.0 * p->box_mpc_h);
+    const double q = std::pow(a, -3.0) + 4.0 * ol / om;
+    m->K = std::pow(n * a * a * m->xi, 1.0 / (n + 1.0));
+    m->A = om * std::pow(a, 4.0) * m->K / 3.0;
+    m->Sbar = om * std::pow(a, 4.0) * q;
+    m->D = om * a;
+    m->ubar = std::log(n * a * a * m->xi / std::pow(3.0 * q, n + 1.0));
+    m->inv_np1 = 1.0 / (n + 1.0);
+    return MGFR_OK;
+}
+
+inline int ilog2(int x)
+{
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+inline bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+struct Level {
+    mgfr::Grid g;
+    double* u = nullptr;     // level 0: the caller's u
+    double* alt = nullptr;   // second copy for out-of-place (fused) sweeps, n >= 64
+    double* uhat = nullptr;  // R u of the finer level (m >= 1); turned into u^H - R u^h
+    double* f = nullptr;     // FAS right-hand side (m >= 1)
+};
+
+// One level of the single-precision correction multigrid (mixed precision).
+struct Level32 {
+    mgfr::Grid g;
+    float* ub = nullptr;    // base u (level 0: u rounded; coarse: restricted)
+    float* e = nullptr;     // correction
+    float* ealt = nullptr;  // second copy for the fused sweep (n >= 64)
+    float* ehat = nullptr;  // R e of the finer level (m >= 1); turned into e^H - R e^h
+    float* f = nullptr;     // right-hand side (level 0: r = -d)
+};
+
+}  // namespace mgfr_host
+
+struct mgfr_ctx {
+    int device = 0;
+    std::string err;
+    // hierarchy for one finest size, kept between calls
+    int N = 0, coarsest = 0;
+    std::vector<mgfr_host::Level> lv;
+    int N32 = 0, coarsest32 = 0;
+    std::vector<mgfr_host::Level32> lv32;
+    double* partial = nullptr;  // reduction scratch
+    double* red = nullptr;      // device result of a reduction (2 doubles)
+    double* host_red = nullptr; // pinned copy of it
+    long long* counter = nullptr;  // device: coarsest-level sweeps of the current solve
+    mgfr_stats stats{};
+    // MGFR_PROFILE: event pairs around finest-level smoother launches
+    std::vector<hipEvent_t> ev;
+    int ev_used = 0;
+
+    int fail(int code, const char* fmt, ...)
+    {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+
+    void free_levels()
+    {
+        for (size_t m = 0; m < lv.size(); ++m) {
+            if (m > 0) {
+                (void)hipFree(lv[m].u);
+                (void)hipFree(lv[m].uhat);
+                (void)hipFree(lv[m].f);
+            }
+            (void)hipFree(lv[m].alt);
+        }
+        lv.clear();
+        N = 0;
+    }
+
+    void free_levels32()
+    {
+        for (mgfr_host::Level32& L : lv32) {
+            (void)hipFree(L.ub);
+            (void)hipFree(L.e);
+            (void)hipFree(L.ealt);
+            (void)hipFree(L.ehat);
+            (void)hipFree(L.f);
+        }
+        lv32.clear();
+        N32 = 0;
+    }
+};
+
+namespace mgfr_host {
+
+inline int hip_check(mgfr_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return MGFR_OK;
+    return c->fail(MGFR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define MGFR_TRY(expr)                       \
+    do {                                     \
+        int rc_ = (expr);                    \
+        if (rc_ != MGFR_OK) return rc_;      \
+    } while (0)
+
+inline int check_opts(mgfr_ctx* c, const mgfr_opts* o)
+{
+    if (!o) return c->fail(MGFR_EINVAL, "opts is NULL");
+    if (!(o->tol >= 0.0) || o->pre < 0 || o->post < 0 || o->max_cycles < 0 || o->coarsest_sweeps < 0 ||
+        !is_pow2(o->coarsest_n) || o->coarsest_n < 2 || o->coarsest_n > 8 || !(o->max_step >= 0.0) ||
+        !(o->coarsest_rtol >= 0.0) || (o->precision != MGFR_FP64 && o->precision != MGFR_MIXED) ||
+        o->inner_cycles < 1)
+        return c->fail(MGFR_EINVAL, "invalid options (tol=%g pre=%d post=%d coarsest_n=%d precision=%d)",
+                       o->tol, o->pre, o->post, o->coarsest_n, o->precision);
+    return MGFR_OK;
+}
+
+inline mgfr::Grid make_grid(const Model& md, int n, double h, double max_step)
+{
+    mgfr::Grid g;
+    g.n = n;
+    g.lg = ilog2(n);
+    g.C = md.ct * md.ct / (2.0 * h * h);
+    g.A = md.A;
+    g.inv_np1 = md.inv_np1;
+    g.max_step = max_step;
+    g.fscale = 1.0;
+    g.sref = 0.0;
+    g.fshift = 0.0;
+    return g;
+}
+
+inline int ensure_scratch(mgfr_ctx* c)
+{
+    if (!c->partial) {
+        if (hipMalloc(&c->partial, sizeof(double) * mgfr::reduction_scratch()) != hipSuccess)
+            return c->fail(MGFR_ENOMEM, "hipMalloc of reduction scratch failed");
+        if (hipMalloc(&c->red, sizeof(double) * 2) != hipSuccess)
+            return c->fail(MGFR_ENOMEM, "hipMalloc of reduction result failed");
+        if (hipHostMalloc(&c->host_red, sizeof(double) * 2, hipHostMallocDefault) != hipSuccess)
+            return c->fail(MGFR_ENOMEM, "hipHostMalloc failed");
+        if (hipMalloc(&c->counter, sizeof(long long)) != hipSuccess)
+            return c->fail(MGFR_ENOMEM, "hipMalloc of the sweep counter failed");
+    }
+    return MGFR_OK;
+}
+
+// Allocates levels N/2 ... coarsest (level 0 uses the caller's arrays).
+inline int ensure_levels(mgfr_ctx* c, int N, int coarsest)
+{
+    if (c->N == N && c->coarsest == coarsest) return MGFR_OK;
+    c->free_levels();
+    for (int n = N; n >= coarsest; n /= 2) {
+        Level L;
+        const size_t bytes = sizeof(double) * (size_t)n * n * n;
+        bool ok = true;
+        if (n < N)
+            ok = hipMalloc(&L.u, bytes) == hipSuccess && hipMalloc(&L.uhat, bytes) == hipSuccess &&
+                 hipMalloc(&L.f, bytes) == hipSuccess;
+        if (ok && n >= mgfr::fused_sweep_min_n()) ok = hipMalloc(&L.alt, bytes) == hipSuccess;
+        if (!ok) {
+            if (n < N) {
+                (void)hipFree(L.u);
+                (void)hipFree(L.uhat);
+                (void)hipFree(L.f);
+            }
+            (void)hipFree(L.alt);
+            c->free_levels();
+            return c->fail(MGFR_ENOMEM, "hipMalloc of the %d^3 level failed", n);
+        }
+        c->lv.push_back(L);
+    }
+    c->N = N;
+    c->coarsest = coarsest;
+    return MGFR_OK;
+}
+
+// Single-precision hierarchy N ... coarsest for the mixed solver.
+inline int ensure_levels32(mgfr_ctx* c, int N, int coarsest)
+{
+    if (c->N32 == N && c->coarsest32 == coarsest) return MGFR_OK;
+    c->free_levels32();
+    for (int n = N; n >= coarsest; n /= 2) {
+        Level32 L;
+        const size_t bytes = sizeof(float) * (size_t)n * n * n;
+        bool ok = hipMalloc(&L.ub, bytes) == hipSuccess && hipMalloc(&L.e, bytes) == hipSuccess &&
+                  hipMalloc(&L.f, bytes) == hipSuccess;
+        if (ok && n < N) ok = hipMalloc(&L.ehat, bytes) == hipSuccess;
+        if (ok && n >= mgfr::fused_sweep_min_n()) ok = hipMalloc(&L.ealt, bytes) == hipSuccess;
+        c->lv32.push_back(L);
+        if (!ok) {
+            c->free_levels32();
+            return c->fail(MGFR_ENOMEM, "hipMalloc of the single-precision %d^3 level failed", n);
+        }
+    }
+    c->N32 = N;
+    c->coarsest32 = coarsest;
+    return MGFR_OK;
+}
+
+// Copies a 2-double device reduction result to the host (synchronises the stream).
+inline int read_reduction(mgfr_ctx* c, hipStream_t s, double* out2)
+{
+    MGFR_TRY(hip_check(c, hipMemcpyAsync(c->host_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s),
+                       "hipMemcpyAsync"));
+    MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+    out2[0] = c->host_red[0];
+    out2[1] = c->host_red[1];
+    return MGFR_OK;
+}
+
+}  // namespace mgfr_host

@@ -1,0 +1,499 @@
+// Single-precision kernels of the defect-correction (mixed precision) solver.
+//
+// The outer double-precision loop holds u and its residual d = L(u) - f.  In between, a
+// single-precision FAS multigrid solves for the correction e of u in the form
+//   N_i(e) = L_i(ub + e) - L_i(ub) = r_i,   r = -d,   ub = u rounded to single precision,
+// written with every term proportional to e so that corrections far below the single-
+// precision spacing of u are still resolved:
+//   N_i(e) = C sum_nb [(M_nb + M_i)(ub_nb - ub_i) + (B_nb + B_i)(e_nb - e_i)]
+//          + S_i expm1(-e_i/(n+1))
+//   b = exp(ub),  M = b expm1(e),  B = b + M = b exp(e),  S_i = A exp(-ub_i/(n+1)),
+// i.e. the flux and curvature terms of eq. discrete_fR (times c~^2) differenced exactly.
+// The coarse levels of this inner multigrid use the restricted base R ub.  Smoother:
+// red-black Newton-Gauss-Seidel on N (Sec. V.B.1 applied to the correction equation).
+#include "mgfr_impl.h"
+
+namespace mgfr {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kTK = 64;
+
+struct Op32 {
+    float C, A, inv_np1, max_step;
+};
+
+__device__ __forceinline__ Op32 op32(const Grid& g)
+{
+    return Op32{(float)g.C, (float)g.A, (float)g.inv_np1, (float)g.max_step};
+}
+
+// expm1 in single precision: Taylor series to x^6 for |x| < 1/8 (truncation < 1e-10
+// relative), exp(x) - 1 above.
+__device__ __forceinline__ float em1f(float x)
+{
+    if (fabsf(x) < 0.125f)
+        return x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f + x * (1.0f / 720.0f))))));
+    return __expf(x) - 1.0f;
+}
+
+// Per-cell values a neighbour needs: base, correction, B = b e^e, M = b (e^e - 1).
+struct V32 {
+    float ub, e, B, M;
+};
+
+__device__ __forceinline__ V32 make_v(float ub, float e)
+{
+    V32 v;
+    v.ub = ub;
+    v.e = e;
+    const float b = __expf(ub);
+    v.M = b * em1f(e);
+    v.B = b + v.M;
+    return v;
+}
+
+struct Res32 {
+    float N, dN;
+};
+
+// N_i - f_i and dN_i/de_i.
+__device__ __forceinline__ Res32 corr_op(const Op32& o, const V32& c, const V32 (&nb)[6], float f)
+{
+    float t1 = 0.0f, t2 = 0.0f, sB = 0.0f, sd = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const float du = nb[q].ub - c.ub, de = nb[q].e - c.e;
+        t1 = fmaf(nb[q].M + c.M, du, t1);
+        t2 = fmaf(nb[q].B + c.B, de, t2);
+        sB += nb[q].B;
+        sd += du + de;
+    }
+    const float S = o.A * __expf(-c.ub * o.inv_np1);
+    const float x = em1f(-c.e * o.inv_np1);
+    Res32 r;
+    r.N = o.C * (t1 + t2) + S * x - f;
+    r.dN = o.C * (c.B * sd - sB - 6.0f * c.B) - S * o.inv_np1 * (1.0f + x);
+    return r;
+}
+
+__device__ __forceinline__ float bounded32(float step, float ms)
+{
+    if (ms > 0.0f) {
+        if (step > ms) step = ms;
+        if (step < -ms) step = -ms;
+    }
+    return step;
+}
+
+__device__ __forceinline__ long long at(int lg, int i, int j, int k)
+{
+    return ((((long long)i << lg) + j) << lg) + k;
+}
+
+__device__ __forceinline__ void nbr_index(int lg, int i, int j, int k, long long (&q)[6])
+{
+    const int m = (1 << lg) - 1;
+    q[0] = at(lg, (i - 1) & m, j, k);
+    q[1] = at(lg, (i + 1) & m, j, k);
+    q[2] = at(lg, i, (j - 1) & m, k);
+    q[3] = at(lg, i, (j + 1) & m, k);
+    q[4] = at(lg, i, j, (k - 1) & m);
+    q[5] = at(lg, i, j, (k + 1) & m);
+}
+
+// ---- per-colour sweep, in place (small levels) ------------------------------------------
+__global__ void __launch_bounds__(kBlock) k32_ngs_colour(Grid g, const float* __restrict__ ub, float* __restrict__ e,
+                                                         const float* __restrict__ f, int colour)
+{
+    const Op32 o = op32(g);
+    const long long half = 1LL << (3 * g.lg - 1);
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= half) return;
+    const int hk = g.n >> 1;
+    const int s = (int)(t & (hk - 1));
+    const long long row = t >> (g.lg - 1);
+    const int i = (int)(row >> g.lg), j = (int)(row & (g.n - 1));
+    const int k = 2 * s + ((i + j + colour) & 1);
+    const long long q = at(g.lg, i, j, k);
+    long long qn[6];
+    nbr_index(g.lg, i, j, k, qn);
+    V32 nb[6];
+#pragma unroll
+    for (int v = 0; v < 6; ++v) nb[v] = make_v(ub[qn[v]], e[qn[v]]);
+    const V32 c = make_v(ub[q], e[q]);
+    const Res32 r = corr_op(o, c, nb, f[q]);
+    e[q] = c.e + bounded32(-r.N / r.dN, o.max_step);
+}
+
+// ---- fused red-black sweep (n >= 64), same scheme as the double-precision one ----------
+template <int TJ, int NT, bool CORR>
+__global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict__ ub, const float* __restrict__ ein,
+                                                float* __restrict__ eout, const float* __restrict__ f,
+                                                FusedSweep32 a)
+{
+    constexpr int LJ = TJ + 4, LK = kTK + 4, NL = LJ * LK;
+    constexpr int NS = (NL + NT - 1) / NT;
+    __shared__ V32 lv[2][NL];
+    const Op32 o = op32(g);
+
+    const int nb = gridDim.x;
+    int lid = blockIdx.x;
+    if ((nb & 7) == 0) lid = (lid & 7) * (nb >> 3) + (lid >> 3);
+    const int tk = lid % a.ntk;
+    lid /= a.ntk;
+    const int tj = lid % a.ntj;
+    const int ci = lid / a.ntj;
+    const int i0 = ci * a.ti, j0 = tj * TJ, k0 = tk * kTK;
+    const int lg = g.lg, m = g.n - 1;
+
+    int col[NS], par[NS], fl[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int c = threadIdx.x + s * NT;
+        col[s] = 0;
+        par[s] = 0;
+        fl[s] = 0;
+        if (c < NL) {
+            const int jj = c / LK, kk = c - jj * LK;
+            const int gj = (j0 - 2 + jj) & m, gk = (k0 - 2 + kk) & m;
+            col[s] = (gj << lg) | gk;
+            par[s] = (gj + gk) & 1;
+            fl[s] = 1;
+            if (jj >= 1 && jj <= LJ - 2 && kk >= 1 && kk <= LK - 2) fl[s] |= 2;
+            if (jj >= 2 && jj <= LJ - 3 && kk >= 2 && kk <= LK - 3) fl[s] |= 4;
+        }
+    }
+    auto offset = [&](int p, int s) -> long long { return ((long long)(p & m) << (2 * lg)) + col[s]; };
+    auto load_e = [&](int p, int s) -> float {
+        float v = ein[offset(p, s)];
+        if (CORR) {
+            const int i = p & m, j = col[s] >> lg, k = col[s] & m;
+            const int lgc = lg - 1, mc = (1 << lgc) - 1;
+            const int I = i >> 1, J = j >> 1, K = k >> 1;
+            const int Ip = (I + ((i & 1) ? 1 : -1)) & mc, Jp = (J + ((j & 1) ? 1 : -1)) & mc,
+                      Kp = (K + ((k & 1) ? 1 : -1)) & mc;
+            auto E = [&](int x, int y, int z) { return a.ec[at(lgc, x, y, z)]; };
+            v += (27.0f / 64.0f) * E(I, J, K) + (9.0f / 64.0f) * (E(Ip, J, K) + E(I, Jp, K) + E(I, J, Kp)) +
+                 (3.0f / 64.0f) * (E(Ip, Jp, K) + E(Ip, J, Kp) + E(I, Jp, Kp)) + (1.0f / 64.0f) * E(Ip, Jp, Kp);
+        }
+        return v;
+    };
+    auto load_v = [&](int p, int s) -> V32 { return make_v(ub[offset(p, s)], load_e(p, s)); };
+
+    V32 vm2[NS], vm1[NS], v0[NS], vp1[NS];
+    float fm1[NS], f0[NS], fp1[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        vm2[s] = vm1[s] = v0[s] = vp1[s] = V32{0.f, 0.f, 0.f, 0.f};
+        fm1[s] = f0[s] = fp1[s] = 0.0f;
+        if (fl[s]) {
+            vm1[s] = load_v(i0 - 2, s);
+            v0[s] = load_v(i0 - 1, s);
+            vp1[s] = load_v(i0, s);
+            fm1[s] = f[offset(i0 - 2, s)];
+            f0[s] = f[offset(i0 - 1, s)];
+            fp1[s] = f[offset(i0, s)];
+        }
+    }
+    for (int p = i0 - 1; p <= i0 + a.ti; ++p) {
+        const bool more = p + 2 <= i0 + a.ti + 1;
+        float ub2[NS], e2[NS], f2[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            ub2[s] = e2[s] = f2[s] = 0.0f;
+            if (more && fl[s]) {
+                ub2[s] = ub[offset(p + 2, s)];
+                e2[s] = load_e(p + 2, s);
+                f2[s] = f[offset(p + 2, s)];
+            }
+        }
+        V32* LA = lv[p & 1];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (fl[s]) LA[threadIdx.x + s * NT] = v0[s];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int c = threadIdx.x + s * NT;
+            if ((fl[s] & 2) && ((p + par[s]) & 1) == 0) {
+                const V32 nbv[6] = {vm1[s], vp1[s], LA[c - LK], LA[c + LK], LA[c - 1], LA[c + 1]};
+                const Res32 r = corr_op(o, v0[s], nbv, f0[s]);
+                v0[s] = make_v(v0[s].ub, v0[s].e + bounded32(-r.N / r.dN, o.max_step));
+                LA[c] = v0[s];
+            }
+        }
+        if (p - 1 >= i0) {
+            const V32* LB = lv[(p - 1) & 1];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int c = threadIdx.x + s * NT;
+                if (fl[s] & 4) {
+                    if (((p - 1 + par[s]) & 1) == 1) {
+                        const V32 nbv[6] = {vm2[s], v0[s], LB[c - LK], LB[c + LK], LB[c - 1], LB[c + 1]};
+                        const Res32 r = corr_op(o, vm1[s], nbv, fm1[s]);
+                        vm1[s].e = vm1[s].e + bounded32(-r.N / r.dN, o.max_step);
+                    }
+                    eout[offset(p - 1, s)] = vm1[s].e;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            vm2[s] = vm1[s];
+            vm1[s] = v0[s];
+            fm1[s] = f0[s];
+            v0[s] = vp1[s];
+            f0[s] = fp1[s];
+            if (more && fl[s]) {
+                vp1[s] = make_v(ub2[s], e2[s]);
+                fp1[s] = f2[s];
+            }
+        }
+    }
+}
+
+// ---- residual + restriction, FAS right-hand side, transfers ----------------------------
+__global__ void __launch_bounds__(kBlock) k32_resid_restrict(Grid g, const float* __restrict__ ub,
+                                                             const float* __restrict__ e,
+                                                             const float* __restrict__ f,
+                                                             float* __restrict__ ec, float* __restrict__ ehat,
+                                                             float* __restrict__ fc)
+{
+    const Op32 o = op32(g);
+    const int lgc = g.lg - 1, nc = g.n >> 1;
+    const long long tc = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (tc >= (1LL << (3 * lgc))) return;
+    const int I = (int)(tc >> (2 * lgc)), J = (int)((tc >> lgc) & (nc - 1)), K = (int)(tc & (nc - 1));
+    float se = 0.0f, sd = 0.0f;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int z = 0; z < 2; ++z) {
+                const int i = 2 * I + x, j = 2 * J + y, k = 2 * K + z;
+                const long long q = at(g.lg, i, j, k);
+                long long qn[6];
+                nbr_index(g.lg, i, j, k, qn);
+                V32 nb[6];
+#pragma unroll
+                for (int v = 0; v < 6; ++v) nb[v] = make_v(ub[qn[v]], e[qn[v]]);
+                const V32 c = make_v(ub[q], e[q]);
+                se += c.e;
+                sd += corr_op(o, c, nb, f[q]).N;
+            }
+    ec[tc] = 0.125f * se;
+    ehat[tc] = 0.125f * se;
+    fc[tc] = 0.125f * sd;
+}
+
+__global__ void __launch_bounds__(kBlock) k32_fas_rhs(Grid g, const float* __restrict__ ub,
+                                                      const float* __restrict__ ehat, float* __restrict__ f)
+{
+    const Op32 o = op32(g);
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= (1LL << (3 * g.lg))) return;
+    const int i = (int)(q >> (2 * g.lg)), j = (int)((q >> g.lg) & (g.n - 1)), k = (int)(q & (g.n - 1));
+    long long qn[6];
+    nbr_index(g.lg, i, j, k, qn);
+    V32 nb[6];
+#pragma unroll
+    for (int v = 0; v < 6; ++v) nb[v] = make_v(ub[qn[v]], ehat[qn[v]]);
+    f[q] = corr_op(o, make_v(ub[q], ehat[q]), nb, 0.0f).N - f[q];
+}
+
+__global__ void __launch_bounds__(kBlock) k32_restrict_mean(int lgc, const float* __restrict__ fine,
+                                                            float* __restrict__ coarse)
+{
+    const long long tc = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (tc >= (1LL << (3 * lgc))) return;
+    const int nc = 1 << lgc, lg = lgc + 1;
+    const int I = (int)(tc >> (2 * lgc)), J = (int)((tc >> lgc) & (nc - 1)), K = (int)(tc & (nc - 1));
+    float s = 0.0f;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int z = 0; z < 2; ++z) s += fine[at(lg, 2 * I + x, 2 * J + y, 2 * K + z)];
+    coarse[tc] = 0.125f * s;
+}
+
+__global__ void __launch_bounds__(kBlock) k32_diff(const float* __restrict__ ec, float* __restrict__ e, long long n)
+{
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q < n) e[q] = ec[q] - e[q];
+}
+
+__global__ void __launch_bounds__(kBlock) k32_prolong_add(int lgc, float* __restrict__ ef, const float* __restrict__ d)
+{
+    const int lg = lgc + 1, n = 1 << lg, mc = (1 << lgc) - 1;
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= (1LL << (3 * lg))) return;
+    const int i = (int)(q >> (2 * lg)), j = (int)((q >> lg) & (n - 1)), k = (int)(q & (n - 1));
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int Ip = (I + ((i & 1) ? 1 : -1)) & mc, Jp = (J + ((j & 1) ? 1 : -1)) & mc, Kp = (K + ((k & 1) ? 1 : -1)) & mc;
+    auto E = [&](int x, int y, int z) { return d[at(lgc, x, y, z)]; };
+    ef[q] += (27.0f / 64.0f) * E(I, J, K) + (9.0f / 64.0f) * (E(Ip, J, K) + E(I, Jp, K) + E(I, J, Kp)) +
+             (3.0f / 64.0f) * (E(Ip, Jp, K) + E(Ip, J, Kp) + E(I, Jp, Kp)) + (1.0f / 64.0f) * E(Ip, Jp, Kp);
+}
+
+__global__ void __launch_bounds__(kBlock) k32_fill(float* __restrict__ x, float v, long long n)
+{
+    for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) x[q] = v;
+}
+
+// ---- coarsest level in one workgroup (n <= 8) ------------------------------------------
+__global__ void __launch_bounds__(kBlock) k32_coarsest(Grid g, const float* __restrict__ ub, float* __restrict__ e,
+                                                       const float* __restrict__ f, int cap, float rtol)
+{
+    __shared__ float sub[512], se[512], sf[512];
+    __shared__ float rs[kBlock], rf[kBlock];
+    const Op32 o = op32(g);
+    const int nc = 1 << (3 * g.lg);
+    for (int q = threadIdx.x; q < nc; q += kBlock) {
+        sub[q] = ub[q];
+        se[q] = e[q];
+        sf[q] = f[q];
+    }
+    __syncthreads();
+    auto cell = [&](int q, V32& c, V32 (&nb)[6]) {
+        const int i = q >> (2 * g.lg), j = (q >> g.lg) & (g.n - 1), k = q & (g.n - 1);
+        long long qn[6];
+        nbr_index(g.lg, i, j, k, qn);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) nb[v] = make_v(sub[qn[v]], se[qn[v]]);
+        c = make_v(sub[q], se[q]);
+        return (i + j + k) & 1;
+    };
+    // rms of N - f and its rounding floor (single precision: one unit in the last place of
+    // |dN||e| plus the summed magnitudes)
+    auto rms = [&](float& floor) {
+        float s = 0.0f, fl = 0.0f;
+        for (int q = threadIdx.x; q < nc; q += kBlock) {
+            V32 c, nb[6];
+            cell(q, c, nb);
+            const Res32 r = corr_op(o, c, nb, sf[q]);
+            s += r.N * r.N;
+            const float f1 = 1.1920929e-7f * (fabsf(r.dN) * fabsf(c.e) + fabsf(sf[q]));
+            fl += f1 * f1;
+        }
+        rs[threadIdx.x] = s;
+        rf[threadIdx.x] = fl;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                rs[threadIdx.x] += rs[threadIdx.x + w];
+                rf[threadIdx.x] += rf[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        const float tot = rs[0], tf = rf[0];
+        __syncthreads();
+        floor = sqrtf(tf / nc);
+        return sqrtf(tot / nc);
+    };
+    float fl0;
+    const float r0 = rtol > 0.0f ? rms(fl0) : 0.0f;
+    for (int sweep = 0; sweep < cap; ++sweep) {
+        if (rtol > 0.0f) {
+            float fl;
+            const float r = rms(fl);
+            if (r <= rtol * r0 || r <= fl) break;
+        }
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int q = threadIdx.x; q < nc; q += kBlock) {
+                V32 c, nb[6];
+                if (cell(q, c, nb) != colour) continue;
+                const Res32 r = corr_op(o, c, nb, sf[q]);
+                se[q] = c.e + bounded32(-r.N / r.dN, o.max_step);
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = threadIdx.x; q < nc; q += kBlock) e[q] = se[q];
+}
+
+inline unsigned blocks_for(long long work) { return (unsigned)((work + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t ngs_sweep32(const Grid& g, const float* ub, float* e, const float* f, hipStream_t s)
+{
+    const long long half = cells(g) / 2;
+    for (int colour = 0; colour < 2; ++colour)
+        hipLaunchKernelGGL(k32_ngs_colour, dim3(blocks_for(half)), dim3(kBlock), 0, s, g, ub, e, f, colour);
+    return hipGetLastError();
+}
+
+hipError_t ngs_sweep32_fused(const Grid& g, const float* ub, const float* ein, float* eout, const float* f,
+                             const float* ec, int ti, hipStream_t s)
+{
+    if (g.n < kTK || ein == eout || ti < 1 || ti > g.n || (g.n % ti) != 0) return hipErrorInvalidValue;
+    constexpr int TJ = 16, NT = 512;
+    FusedSweep32 a{};
+    a.ti = ti;
+    a.ec = ec;
+    a.ntj = g.n / TJ;
+    a.ntk = g.n / kTK;
+    const unsigned nb = (unsigned)((g.n / ti) * a.ntj * a.ntk);
+    if (ec)
+        hipLaunchKernelGGL((k32_fused<TJ, NT, true>), dim3(nb), dim3(NT), 0, s, g, ub, ein, eout, f, a);
+    else
+        hipLaunchKernelGGL((k32_fused<TJ, NT, false>), dim3(nb), dim3(NT), 0, s, g, ub, ein, eout, f, a);
+    return hipGetLastError();
+}
+
+hipError_t resid_restrict32(const Grid& g, const float* ub, const float* e, const float* f, float* ec,
+                            float* ehat, float* fc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k32_resid_restrict, dim3(blocks_for(cells(g) / 8)), dim3(kBlock), 0, s, g, ub, e, f, ec,
+                       ehat, fc);
+    return hipGetLastError();
+}
+
+hipError_t fas_rhs32(const Grid& gc, const float* ubc, const float* ehat, float* f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k32_fas_rhs, dim3(blocks_for(cells(gc))), dim3(kBlock), 0, s, gc, ubc, ehat, f);
+    return hipGetLastError();
+}
+
+hipError_t restrict_mean32(const Grid& gc, const float* fine, float* coarse, hipStream_t s)
+{
+    hipLaunchKernelGGL(k32_restrict_mean, dim3(blocks_for(cells(gc))), dim3(kBlock), 0, s, gc.lg, fine, coarse);
+    return hipGetLastError();
+}
+
+hipError_t coarse_difference32(const Grid& gc, const float* ec, float* ehat_to_d, hipStream_t s)
+{
+    const long long n = cells(gc);
+    hipLaunchKernelGGL(k32_diff, dim3(blocks_for(n)), dim3(kBlock), 0, s, ec, ehat_to_d, n);
+    return hipGetLastError();
+}
+
+hipError_t prolong_add32(const Grid& gc, float* ef, const float* d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k32_prolong_add, dim3(blocks_for(cells(gc) * 8)), dim3(kBlock), 0, s, gc.lg, ef, d);
+    return hipGetLastError();
+}
+
+hipError_t coarsest_solve32(const Grid& g, const float* ub, float* e, const float* f, int cap, double rtol,
+                            hipStream_t s)
+{
+    if (g.n > 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k32_coarsest, dim3(1), dim3(kBlock), 0, s, g, ub, e, f, cap, (float)rtol);
+    return hipGetLastError();
+}
+
+hipError_t fill32(float* x, float v, long long n, hipStream_t s)
+{
+    long long b = (n + kBlock - 1) / kBlock;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    hipLaunchKernelGGL(k32_fill, dim3((unsigned)b), dim3(kBlock), 0, s, x, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace mgfr

@@ -5,48 +5,22 @@
 // mean of the two cell values), multiplied by c~^2 as in eq. bc_modified_fR_op.  Each
 // Newton-Gauss-Seidel visit of a cell replaces u_i by u_i - (L_i - f_i) / (dL_i/du_i)
 // (Sec. V.B.1, with the derivative of eq. bc_modified_fR_dop for a cell with no ghost).
-#include "mgfr_impl.h"
+#include "device_fp64.h"
 
 namespace mgfr {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMaxPartials = 4096;
+constexpr int kMaxPartials = 8192;
 
-struct OpVal {
-    double L, dL;
-};
-
-// L_i - f_i and dL_i/du_i from the cell value and its six neighbours.
-__device__ __forceinline__ OpVal cell_op(const Grid& g, double ui, const double (&un)[6], double f)
-{
-    const double bi = exp(ui);
-    double su = 0.0, sb = 0.0, sbu = 0.0;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const double du = un[q] - ui;
-        const double bn = exp(un[q]);
-        su += du;
-        sb += bn;
-        sbu = fma(bn, du, sbu);
-    }
-    const double S = g.A * exp(-ui * g.inv_np1);
-    OpVal r;
-    // sum_nb (b_nb + b_i)(u_nb - u_i) = sum b_nb du + b_i sum du
-    r.L = g.C * fma(bi, su, sbu) + S - f;
-    // sum_nb [b_i (u_nb - u_i) - b_nb - b_i]
-    r.dL = g.C * (fma(bi, su, -sb) - 6.0 * bi) - S * g.inv_np1;
-    return r;
-}
+using dev::OpVal;
+using dev::at;
+using dev::bounded;
+using dev::cell_op;
 
 __device__ __forceinline__ double rhs(const Grid& g, const double* src, long long q)
 {
-    return fma(g.fscale, src[q] - g.sref, g.fshift);
-}
-
-__device__ __forceinline__ long long at(const Grid& g, int i, int j, int k)
-{
-    return ((((long long)i << g.lg) + j) << g.lg) + k;
+    return dev::rhs_value(g, src[q]);
 }
 
 __device__ __forceinline__ void load_nbrs(const Grid& g, const double* u, int i, int j, int k,
@@ -59,16 +33,6 @@ __device__ __forceinline__ void load_nbrs(const Grid& g, const double* u, int i,
     un[3] = u[at(g, i, (j + 1) & m, k)];
     un[4] = u[at(g, i, j, (k - 1) & m)];
     un[5] = u[at(g, i, j, (k + 1) & m)];
-}
-
-__device__ __forceinline__ double bounded(double step, double ms)
-{
-    // comparisons (not fmin/fmax) so that a NaN step stays NaN
-    if (ms > 0.0) {
-        if (step > ms) step = ms;
-        if (step < -ms) step = -ms;
-    }
-    return step;
 }
 
 // One colour of a sweep; one thread per cell of that colour.
@@ -133,10 +97,9 @@ __global__ void __launch_bounds__(kBlock) k_fas_rhs(Grid g, const double* __rest
     f[q] = cell_op(g, uhat[q], un, 0.0).L - f[q];
 }
 
-// One thread per fine cell; gc describes the coarse level.
-__global__ void __launch_bounds__(kBlock) k_prolong_correct(Grid gc, double* __restrict__ uf,
-                                                            const double* __restrict__ uc,
-                                                            const double* __restrict__ uhat)
+// uf += P(e): one thread per fine cell; gc describes the coarse level.
+__global__ void __launch_bounds__(kBlock) k_prolong_add(Grid gc, double* __restrict__ uf,
+                                                        const double* __restrict__ e)
 {
     const int lg = gc.lg + 1, n = gc.n << 1, mc = gc.n - 1;
     const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -146,14 +109,9 @@ __global__ void __launch_bounds__(kBlock) k_prolong_correct(Grid gc, double* __r
     const int Ip = (I + ((i & 1) ? 1 : -1)) & mc;
     const int Jp = (J + ((j & 1) ? 1 : -1)) & mc;
     const int Kp = (K + ((k & 1) ? 1 : -1)) & mc;
-    auto e = [&](int a, int b, int c) {
-        const long long qc = at(gc, a, b, c);
-        return uc[qc] - uhat[qc];
-    };
-    const double p = (27.0 / 64.0) * e(I, J, K) +
-                     (9.0 / 64.0) * (e(Ip, J, K) + e(I, Jp, K) + e(I, J, Kp)) +
-                     (3.0 / 64.0) * (e(Ip, Jp, K) + e(Ip, J, Kp) + e(I, Jp, Kp)) +
-                     (1.0 / 64.0) * e(Ip, Jp, Kp);
+    auto E = [&](int a, int b, int c) { return e[at(gc, a, b, c)]; };
+    const double p = (27.0 / 64.0) * E(I, J, K) + (9.0 / 64.0) * (E(Ip, J, K) + E(I, Jp, K) + E(I, J, Kp)) +
+                     (3.0 / 64.0) * (E(Ip, Jp, K) + E(Ip, J, Kp) + E(I, Jp, Kp)) + (1.0 / 64.0) * E(Ip, Jp, Kp);
     uf[q] += p;
 }
 
@@ -207,21 +165,39 @@ __global__ void __launch_bounds__(kBlock) k_coarsest(Grid g, double* __restrict_
         un[5] = su[(i << (2 * g.lg)) + (j << g.lg) + ((k + 1) & m)];
         return (i + j + k) & 1;
     };
-    auto rms = [&]() {
-        double s = 0.0, mx = 0.0;
+    // rms of L - f, and the rounding floor of that rms: per cell one unit in the last place
+    // of u times |dL/du| plus one of the summed magnitudes (C (b_nb + b_i)|u_nb - u_i| per
+    // face, the curvature term and |f|)
+    auto rms = [&](double& floor) {
+        double s = 0.0, fl = 0.0;
         for (int q = threadIdx.x; q < nc; q += kBlock) {
             double un[6];
             nbrs(q, un);
-            const double d = cell_op(g, su[q], un, sf[q]).L;
-            s += d * d;
+            const double ui = su[q];
+            const OpVal r = cell_op(g, ui, un, sf[q]);
+            s += r.L * r.L;
+            const double bi = exp(ui);
+            double t = 0.0;
+#pragma unroll
+            for (int v = 0; v < 6; ++v) t += g.C * (exp(un[v]) + bi) * fabs(un[v] - ui);
+            t += g.A * exp(-ui * g.inv_np1) + fabs(sf[q]);
+            const double f1 = 2.220446049250313e-16 * (fabs(r.dL) * fabs(ui) + t);
+            fl += f1 * f1;
         }
-        block_reduce2<true>(s, mx, rs, rm);
+        block_reduce2<false>(s, fl, rs, rm);
+        floor = sqrt(fl / nc);
         return sqrt(s / nc);
     };
-    const double r0 = rtol > 0.0 ? rms() : 0.0;
+    double floor0 = 0.0;
+    const double r0 = rtol > 0.0 ? rms(floor0) : 0.0;
     int sweep = 0;
     for (; sweep < cap; ++sweep) {
-        if (rtol > 0.0 && rms() <= rtol * r0) break;
+        if (rtol > 0.0) {
+            // stop once reduced by rtol or down to the rounding floor
+            double floor;
+            const double r = rms(floor);
+            if (r <= rtol * r0 || r <= floor) break;
+        }
         for (int colour = 0; colour < 2; ++colour) {
             for (int q = threadIdx.x; q < nc; q += kBlock) {
                 double un[6];
@@ -311,6 +287,38 @@ __global__ void __launch_bounds__(kBlock) k_fold(const double* __restrict__ part
     }
 }
 
+__global__ void __launch_bounds__(kBlock) k_add_correction(double* __restrict__ u, const float* __restrict__ e,
+                                                           long long n)
+{
+    for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock)
+        u[q] += (double)e[q];
+}
+
+__global__ void __launch_bounds__(kBlock) k_residual_cast(Grid g, const double* __restrict__ u,
+                                                          const double* __restrict__ src, float* __restrict__ r32,
+                                                          float* __restrict__ ub32, double* __restrict__ partial)
+{
+    __shared__ double rs[kBlock], rm[kBlock];
+    const long long ncell = 1LL << (3 * g.lg);
+    double s = 0.0, mx = 0.0;
+    for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < ncell; q += (long long)gridDim.x * kBlock) {
+        const int i = (int)(q >> (2 * g.lg)), j = (int)((q >> g.lg) & (g.n - 1)), k = (int)(q & (g.n - 1));
+        double un[6];
+        load_nbrs(g, u, i, j, k, un);
+        const double d = cell_op(g, u[q], un, rhs(g, src, q)).L;
+        r32[q] = (float)(-d);
+        ub32[q] = (float)u[q];
+        s += d * d;
+        const double ad = fabs(d);
+        if (!(mx >= ad)) mx = ad;
+    }
+    block_reduce2<true>(s, mx, rs, rm);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = s;
+        partial[2 * blockIdx.x + 1] = mx;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_fill(double* __restrict__ x, double v, long long n)
 {
     for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock)
@@ -355,11 +363,9 @@ hipError_t fas_rhs(const Grid& gc, const double* uhat, double* f, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t prolong_correct(const Grid& gc, double* uf, const double* uc, const double* uhat,
-                           hipStream_t s)
+hipError_t prolong_add(const Grid& gc, double* uf, const double* e, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prolong_correct, dim3(blocks_for(cells(gc) * 8)), dim3(kBlock), 0, s, gc, uf,
-                       uc, uhat);
+    hipLaunchKernelGGL(k_prolong_add, dim3(blocks_for(cells(gc) * 8)), dim3(kBlock), 0, s, gc, uf, e);
     return hipGetLastError();
 }
 
@@ -392,6 +398,27 @@ hipError_t sum_and_count_nonfinite(const double* x, long long n, double* partial
     const unsigned nb = reduction_blocks(n);
     hipLaunchKernelGGL(k_sum_count_partial, dim3(nb), dim3(kBlock), 0, s, x, n, partial);
     hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, partial, (int)nb, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t add_correction(double* u, const float* e, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_correction, dim3(reduction_blocks(n)), dim3(kBlock), 0, s, u, e, n);
+    return hipGetLastError();
+}
+
+hipError_t residual_cast(const Grid& g, const double* u, const double* src, float* r32, float* ub32,
+                         double* partial, double* out, hipStream_t s)
+{
+    const unsigned nb = reduction_blocks(cells(g));
+    hipLaunchKernelGGL(k_residual_cast, dim3(nb), dim3(kBlock), 0, s, g, u, src, r32, ub32, partial);
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, partial, (int)nb, 0, out);
+    return hipGetLastError();
+}
+
+hipError_t fold_partials(const double* partial, int nb, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, partial, nb, 0, out);
     return hipGetLastError();
 }
 

@@ -23,6 +23,77 @@ struct Grid {
 
 inline long long cells(const Grid& g) { return 1LL << (3 * g.lg); }
 
+// Launch geometry of the single-precision fused sweep (kernels_fp32.hip).
+struct FusedSweep32 {
+    int ti, ntj, ntk;
+    const float* ec;   // coarse correction to prolongate first, or null
+};
+
+// Outputs of the streaming residual (resid_fp64.hip); null pointers switch parts off.
+struct ResidStream {
+    int ti, ntj, ntk;              // planes per workgroup (even); tiles (set by the launcher)
+    double* partial;               // NORM: 2 doubles per workgroup (sum d^2, max |d|)
+    double *uc, *uhat, *fc;        // RESTRICT: coarse R u (twice) and R d
+    const float* e32;              // UPDATE: correction added to every loaded u ...
+    double* uout;                  // ... and the updated u of the tile written here
+    float *r32, *ub32;             // CAST: -d and u in single precision
+};
+
+// Launch geometry of the fused sweep (sweep_fp64.hip).
+struct FusedSweep {
+    int ti;            // planes per workgroup chunk
+    int ntj, ntk;      // tiles along j and k (set by the launcher)
+    const double* e;   // coarse correction e = u^H - R u^h to prolongate first, or null
+};
+
+// ---- batched units (batch_fp64.hip) ------------------------------------------------------
+// One multigrid level of one unit (a cube refinement patch or a periodic box).
+struct BGrid {
+    int n, lg;
+    int periodic;      // 1: periodic box; 0: patch with ghost faces from ub
+    int unit;          // index of the unit (for the active flags)
+    double C, A, inv_np1, max_step;
+    double fscale, sref, fshift;  // f = fscale (src - sref) + fshift
+    double u0;         // value that batch_fill writes
+    double* u;
+    double* uhat;      // coarse levels: R u of the finer level, then e = u - R u
+    double* f;         // coarse levels: FAS right-hand side
+    const double* src; // finest: the density; coarse: == f
+    double* ub;        // patch: boundary values [6][n][n]
+};
+
+// Workgroup table: blk[b] = (index into grids, block number within that grid).
+struct BTable {
+    const BGrid* grids;
+    const int2* blk;
+    const int* active;  // per-unit flags, or null (all active)
+};
+
+// Parent of a patch for the boundary set-up: the parent level's u (side n, periodic for the
+// domain grid), its origin in parent-level cells, and the child's origin in child cells.
+struct PatchParent {
+    const double* u;
+    int n, lg, periodic;
+    int origin[3];
+    int child[3];
+};
+
+int batch_block();
+hipError_t batch_ngs(const BTable& t, int nblk, hipStream_t s);
+hipError_t batch_resid_restrict(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
+hipError_t batch_fas_rhs(const BTable& t, int nblk, hipStream_t s);
+hipError_t batch_coarse_diff(const BTable& t, int nblk, hipStream_t s);
+hipError_t batch_prolong_add(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
+hipError_t batch_coarsest(const BGrid* grids, int ngrid, const int* active, int cap, double rtol, hipStream_t s);
+hipError_t batch_norm(const BTable& t, int nblk, double* partial, const int* first, const int* count, int ngrid,
+                      double* out, hipStream_t s);
+hipError_t batch_fold(const double* partial, const int* first, const int* count, int ngrid, double* out,
+                      hipStream_t s);
+hipError_t batch_setup(const BTable& t, int nblk, const PatchParent* parents, hipStream_t s);
+hipError_t batch_restrict_faces(const BTable& t, int nblk, const BGrid* fine, hipStream_t s);
+hipError_t batch_fill(const BTable& t, int nblk, hipStream_t s);
+hipError_t batch_nonfinite(const BTable& t, int nblk, double* partial, hipStream_t s);
+
 // ---- FP64 kernels (kernels_fp64.hip) -----------------------------------------------
 // All launchers queue work on `s` and return the hipError_t of the launch.
 
@@ -36,9 +107,8 @@ hipError_t resid_restrict(const Grid& g, const double* u, const double* src, dou
 // FAS right-hand side on a coarse level: f = L^H(uhat) - f (f holds R d on entry).
 hipError_t fas_rhs(const Grid& gc, const double* uhat, double* f, hipStream_t s);
 
-// uf += P(uc - uhat), cell-centred trilinear 27/9/3/1 over 64, periodic.
-hipError_t prolong_correct(const Grid& gc, double* uf, const double* uc, const double* uhat,
-                           hipStream_t s);
+// uf += P(e), cell-centred trilinear 27/9/3/1 over 64, periodic; gc is the coarse level.
+hipError_t prolong_add(const Grid& gc, double* uf, const double* e, hipStream_t s);
 
 // Coarsest level in one workgroup: sweeps until rms(L - f) <= rtol x initial or `cap`
 // sweeps (rtol = 0: exactly cap sweeps).  n <= 8.  Adds the sweeps done to *sweeps_done
@@ -60,6 +130,48 @@ hipError_t sum_and_count_nonfinite(const double* x, long long n, double* partial
                                    hipStream_t s);
 
 hipError_t fill(double* x, double v, long long n, hipStream_t s);
+
+// ---- fused sweep (sweep_fp64.hip) --------------------------------------------------
+// Smallest n the fused sweep supports, and its default planes per workgroup.
+int fused_sweep_min_n();
+int fused_sweep_planes(int n);
+
+// One red-black sweep from uin into uout (distinct arrays); with e != null, uin + P(e)
+// is swept (the coarse-grid correction fused into the sweep).
+hipError_t ngs_sweep_fused(const Grid& g, const double* uin, double* uout, const double* src,
+                           const double* e, int ti, hipStream_t s);
+
+// uhat_to_e <- uc - uhat_to_e on a coarse level.
+hipError_t coarse_difference(const Grid& gc, const double* uc, double* uhat_to_e, hipStream_t s);
+
+// ---- streaming residual (resid_fp64.hip), n >= 64 --------------------------------------
+int resid_stream_planes(int n);
+long long resid_stream_blocks(int n);
+hipError_t resid_stream(const Grid& g, const double* uin, const double* src, ResidStream a, hipStream_t s);
+
+// ---- small-grid helpers of the mixed loop (kernels_fp64.hip) ----------------------------
+// u += e (single-precision correction).
+hipError_t add_correction(double* u, const float* e, long long n, hipStream_t s);
+// r = -d, ub = u in single precision, and block partials of (sum d^2, max |d|) folded into
+// out[0..1].
+hipError_t residual_cast(const Grid& g, const double* u, const double* src, float* r32, float* ub32,
+                         double* partial, double* out, hipStream_t s);
+// out[0..1] from `nb` partial pairs (sum, max).
+hipError_t fold_partials(const double* partial, int nb, double* out, hipStream_t s);
+
+// ---- single-precision correction multigrid (kernels_fp32.hip) --------------------------
+hipError_t ngs_sweep32(const Grid& g, const float* ub, float* e, const float* f, hipStream_t s);
+hipError_t ngs_sweep32_fused(const Grid& g, const float* ub, const float* ein, float* eout, const float* f,
+                             const float* ec, int ti, hipStream_t s);
+hipError_t resid_restrict32(const Grid& g, const float* ub, const float* e, const float* f, float* ec,
+                            float* ehat, float* fc, hipStream_t s);
+hipError_t fas_rhs32(const Grid& gc, const float* ubc, const float* ehat, float* f, hipStream_t s);
+hipError_t restrict_mean32(const Grid& gc, const float* fine, float* coarse, hipStream_t s);
+hipError_t coarse_difference32(const Grid& gc, const float* ec, float* ehat_to_d, hipStream_t s);
+hipError_t prolong_add32(const Grid& gc, float* ef, const float* d, hipStream_t s);
+hipError_t coarsest_solve32(const Grid& g, const float* ub, float* e, const float* f, int cap, double rtol,
+                            hipStream_t s);
+hipError_t fill32(float* x, float v, long long n, hipStream_t s);
 
 // Number of doubles the partial-sum scratch of the reductions needs.
 long long reduction_scratch();

@@ -7,188 +7,16 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
 
-#include "../../include/mgfr.h"
-#include "mgfr_impl.h"
+#include "host_internal.h"
 
 namespace {
 
-// Derived model constants (Sec. II, Sec. III.A, Sec. VI.A.1).
-struct Model {
-    double xi, ct, K, A, Sbar, D, ubar, inv_np1;
-};
-
-int derive_model(const mgfr_params* p, Model* m)
-{
-    if (!p) return MGFR_EINVAL;
-    const double om = p->omega_m, a = p->a, n = p->n;
-    const double ol = p->omega_l < 0.0 ? 1.0 - om : p->omega_l;
-    if (!(om > 0.0) || !(a > 0.0) || !(n > 0.0) || !(p->fr0_abs > 0.0) || !(p->box_mpc_h > 0.0) ||
-        !(ol >= 0.0) || !std::isfinite(om + a + n + p->fr0_abs + p->box_mpc_h + ol))
-        return MGFR_EINVAL;
-    // present background: f_R0 = -n xi / [3 (1 + 4 OL/Om)]^(n+1)
-    m->xi = p->fr0_abs * std::pow(3.0 * (1.0 + 4.0 * ol / om), n + 1.0) / n;
-    // c~ = c / (B H0), c = 299792.458 km/s, H0 = 100 h km/s/Mpc
-    m->ct = 299792.458 / (100.0 * p->box_mpc_h);
-    const double q = std::pow(a, -3.0) + 4.0 * ol / om;
-    m->K = std::pow(n * a * a * m->xi, 1.0 / (n + 1.0));
-    m->A = om * std::pow(a, 4.0) * m->K / 3.0;
-    m->Sbar = om * std::pow(a, 4.0) * q;
-    m->D = om * a;
-    m->ubar = std::log(n * a * a * m->xi / std::pow(3.0 * q, n + 1.0));
-    m->inv_np1 = 1.0 / (n + 1.0);
-    return MGFR_OK;
-}
-
-int ilog2(int x)
-{
-    int l = 0;
-    while ((1 << l) < x) ++l;
-    return l;
-}
-
-bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
-
-struct Level {
-    mgfr::Grid g;
-    double* u = nullptr;     // level 0: the caller's u
-    double* uhat = nullptr;  // R u of the finer level (m >= 1)
-    double* f = nullptr;     // FAS right-hand side (m >= 1)
-};
-
-}  // namespace
-
-struct mgfr_ctx {
-    int device = 0;
-    std::string err;
-    // hierarchy for one finest size, kept between calls
-    int N = 0, coarsest = 0;
-    std::vector<Level> lv;
-    double* partial = nullptr;  // reduction scratch
-    double* red = nullptr;      // device result of a reduction (2 doubles)
-    double* host_red = nullptr; // pinned copy of it
-    long long* counter = nullptr;  // device: coarsest-level sweeps of the current solve
-    mgfr_stats stats{};
-    // MGFR_PROFILE: event pairs around finest-level smoother launches
-    std::vector<hipEvent_t> ev;
-    int ev_used = 0;
-
-    int fail(int code, const char* fmt, ...)
-    {
-        char buf[512];
-        va_list ap;
-        va_start(ap, fmt);
-        vsnprintf(buf, sizeof buf, fmt, ap);
-        va_end(ap);
-        err = buf;
-        return code;
-    }
-
-    void free_levels()
-    {
-        for (size_t m = 1; m < lv.size(); ++m) {
-            (void)hipFree(lv[m].u);
-            (void)hipFree(lv[m].uhat);
-            (void)hipFree(lv[m].f);
-        }
-        lv.clear();
-        N = 0;
-    }
-};
-
-namespace {
-
-int hip_check(mgfr_ctx* c, hipError_t e, const char* what)
-{
-    if (e == hipSuccess) return MGFR_OK;
-    return c->fail(MGFR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
-#define MGFR_TRY(expr)                       \
-    do {                                     \
-        int rc_ = (expr);                    \
-        if (rc_ != MGFR_OK) return rc_;      \
-    } while (0)
-
-int check_opts(mgfr_ctx* c, const mgfr_opts* o)
-{
-    if (!o) return c->fail(MGFR_EINVAL, "opts is NULL");
-    if (!(o->tol >= 0.0) || o->pre < 0 || o->post < 0 || o->max_cycles < 0 || o->coarsest_sweeps < 0 ||
-        !is_pow2(o->coarsest_n) || o->coarsest_n < 2 || o->coarsest_n > 8 || !(o->max_step >= 0.0) ||
-        !(o->coarsest_rtol >= 0.0) || (o->precision != MGFR_FP64 && o->precision != MGFR_MIXED) ||
-        o->inner_cycles < 1)
-        return c->fail(MGFR_EINVAL, "invalid options (tol=%g pre=%d post=%d coarsest_n=%d precision=%d)",
-                       o->tol, o->pre, o->post, o->coarsest_n, o->precision);
-    return MGFR_OK;
-}
-
-mgfr::Grid make_grid(const Model& md, int n, double h, double max_step)
-{
-    mgfr::Grid g;
-    g.n = n;
-    g.lg = ilog2(n);
-    g.C = md.ct * md.ct / (2.0 * h * h);
-    g.A = md.A;
-    g.inv_np1 = md.inv_np1;
-    g.max_step = max_step;
-    g.fscale = 1.0;
-    g.sref = 0.0;
-    g.fshift = 0.0;
-    return g;
-}
-
-int ensure_scratch(mgfr_ctx* c)
-{
-    if (!c->partial) {
-        if (hipMalloc(&c->partial, sizeof(double) * mgfr::reduction_scratch()) != hipSuccess)
-            return c->fail(MGFR_ENOMEM, "hipMalloc of reduction scratch failed");
-        if (hipMalloc(&c->red, sizeof(double) * 2) != hipSuccess)
-            return c->fail(MGFR_ENOMEM, "hipMalloc of reduction result failed");
-        if (hipHostMalloc(&c->host_red, sizeof(double) * 2, hipHostMallocDefault) != hipSuccess)
-            return c->fail(MGFR_ENOMEM, "hipHostMalloc failed");
-        if (hipMalloc(&c->counter, sizeof(long long)) != hipSuccess)
-            return c->fail(MGFR_ENOMEM, "hipMalloc of the sweep counter failed");
-    }
-    return MGFR_OK;
-}
-
-// Allocates levels N/2 ... coarsest (level 0 uses the caller's arrays).
-int ensure_levels(mgfr_ctx* c, int N, int coarsest)
-{
-    if (c->N == N && c->coarsest == coarsest) return MGFR_OK;
-    c->free_levels();
-    c->lv.emplace_back();
-    for (int n = N / 2; n >= coarsest; n /= 2) {
-        Level L;
-        const size_t bytes = sizeof(double) * (size_t)n * n * n;
-        if (hipMalloc(&L.u, bytes) != hipSuccess || hipMalloc(&L.uhat, bytes) != hipSuccess ||
-            hipMalloc(&L.f, bytes) != hipSuccess) {
-            (void)hipFree(L.u);
-            (void)hipFree(L.uhat);
-            (void)hipFree(L.f);
-            c->free_levels();
-            return c->fail(MGFR_ENOMEM, "hipMalloc of the %d^3 level failed", n);
-        }
-        c->lv.push_back(L);
-    }
-    c->N = N;
-    c->coarsest = coarsest;
-    return MGFR_OK;
-}
-
-// Copies a 2-double device reduction result to the host (synchronises the stream).
-int read_reduction(mgfr_ctx* c, hipStream_t s, double* out2)
-{
-    MGFR_TRY(hip_check(c, hipMemcpyAsync(c->host_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s),
-                       "hipMemcpyAsync"));
-    MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
-    out2[0] = c->host_red[0];
-    out2[1] = c->host_red[1];
-    return MGFR_OK;
-}
+using namespace mgfr_host;
 
 struct Cycle {
     mgfr_ctx* c;
@@ -196,27 +24,38 @@ struct Cycle {
     hipStream_t s;
     const double* finest_src = nullptr;
 
-    // One smoother sweep on level m; finest-level sweeps are timed under MGFR_PROFILE.
-    int sweep(size_t m, const double* src)
+    // One smoother sweep on level m, from *cur into the other buffer for the fused kernel
+    // (cur is updated) or in place; e != null fuses the coarse correction into it.
+    // Finest-level sweeps are timed under MGFR_PROFILE.
+    int sweep(size_t m, const double* src, double*& cur, const double* e)
     {
         Level& L = c->lv[m];
+        const bool fused = L.alt != nullptr && !o_simple;
         const bool timed = m == 0 && (o->flags & MGFR_PROFILE);
         if (timed) {
             if ((size_t)c->ev_used + 2 > c->ev.size()) {
                 for (int k = 0; k < 64; ++k) {
-                    hipEvent_t e;
-                    MGFR_TRY(hip_check(c, hipEventCreate(&e), "hipEventCreate"));
-                    c->ev.push_back(e);
+                    hipEvent_t ev;
+                    MGFR_TRY(hip_check(c, hipEventCreate(&ev), "hipEventCreate"));
+                    c->ev.push_back(ev);
                 }
             }
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used], s), "hipEventRecord"));
         }
-        MGFR_TRY(hip_check(c, mgfr::ngs_sweep(L.g, L.u, src, s), "ngs_sweep"));
+        if (fused) {
+            double* out = cur == L.u ? L.alt : L.u;
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep_fused(L.g, cur, out, src, e, mgfr::fused_sweep_planes(L.g.n), s),
+                               "ngs_sweep_fused"));
+            cur = out;
+        } else {
+            if (e) MGFR_TRY(hip_check(c, mgfr::prolong_add(c->lv[m + 1].g, cur, e, s), "prolong_add"));
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep(L.g, cur, src, s), "ngs_sweep"));
+        }
         if (timed) {
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
             c->ev_used += 2;
-            c->stats.sweep_launches += 2;
-            c->stats.sweep_bytes += 2.0 * 12.0 * (double)mgfr::cells(L.g);
+            c->stats.sweep_launches += fused ? 1 : 2;
+            c->stats.sweep_bytes += 24.0 * (double)mgfr::cells(L.g);
         }
         c->stats.cell_updates += mgfr::cells(L.g);
         if (m == 0) c->stats.finest_updates += mgfr::cells(L.g);
@@ -246,16 +85,125 @@ struct Cycle {
                                                      c->counter, s),
                              "coarsest_solve");
         }
-        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m, src));
+        double* cur = L.u;
+        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m, src, cur, nullptr));
         Level& H = c->lv[m + 1];
-        MGFR_TRY(hip_check(c, mgfr::resid_restrict(L.g, L.u, src, H.u, H.uhat, H.f, s), "resid_restrict"));
+        if (L.alt && !o_simple) {
+            mgfr::ResidStream a{};
+            a.ti = mgfr::resid_stream_planes(L.g.n);
+            a.uc = H.u;
+            a.uhat = H.uhat;
+            a.fc = H.f;
+            MGFR_TRY(hip_check(c, mgfr::resid_stream(L.g, cur, src, a, s), "resid_stream"));
+        } else {
+            MGFR_TRY(hip_check(c, mgfr::resid_restrict(L.g, cur, src, H.u, H.uhat, H.f, s), "resid_restrict"));
+        }
         MGFR_TRY(hip_check(c, mgfr::fas_rhs(H.g, H.uhat, H.f, s), "fas_rhs"));
         MGFR_TRY(vcycle(m + 1));
-        MGFR_TRY(hip_check(c, mgfr::prolong_correct(H.g, L.u, H.u, H.uhat, s), "prolong_correct"));
-        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep(m, src));
+        // e = u^H - R u^h (in H.uhat); u^h += P(e), inside the first post-smoothing sweep
+        MGFR_TRY(hip_check(c, mgfr::coarse_difference(H.g, H.u, H.uhat, s), "coarse_difference"));
+        if (o->post > 0) {
+            MGFR_TRY(sweep(m, src, cur, H.uhat));
+            for (int k = 1; k < o->post; ++k) MGFR_TRY(sweep(m, src, cur, nullptr));
+        } else {
+            MGFR_TRY(hip_check(c, mgfr::prolong_add(H.g, cur, H.uhat, s), "prolong_add"));
+        }
+        if (cur != L.u)
+            MGFR_TRY(hip_check(c, hipMemcpyAsync(L.u, cur, sizeof(double) * mgfr::cells(L.g), hipMemcpyDeviceToDevice, s),
+                               "hipMemcpyAsync"));
+        return MGFR_OK;
+    }
+
+    bool o_simple = false;
+};
+
+// V-cycle of the single-precision correction multigrid.
+struct Cycle32 {
+    mgfr_ctx* c;
+    const mgfr_opts* o;
+    hipStream_t s;
+
+    int sweep(size_t m, float*& cur, const float* ec)
+    {
+        Level32& L = c->lv32[m];
+        const bool timed = m == 0 && (o->flags & MGFR_PROFILE);
+        if (timed) {
+            if ((size_t)c->ev_used + 2 > c->ev.size()) {
+                for (int k = 0; k < 64; ++k) {
+                    hipEvent_t ev;
+                    MGFR_TRY(hip_check(c, hipEventCreate(&ev), "hipEventCreate"));
+                    c->ev.push_back(ev);
+                }
+            }
+            MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used], s), "hipEventRecord"));
+        }
+        if (L.ealt) {
+            float* out = cur == L.e ? L.ealt : L.e;
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep32_fused(L.g, L.ub, cur, out, L.f, ec,
+                                                          mgfr::fused_sweep_planes(L.g.n), s),
+                               "ngs_sweep32_fused"));
+            cur = out;
+        } else {
+            if (ec) MGFR_TRY(hip_check(c, mgfr::prolong_add32(c->lv32[m + 1].g, cur, ec, s), "prolong_add32"));
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep32(L.g, L.ub, cur, L.f, s), "ngs_sweep32"));
+        }
+        if (timed) {
+            MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
+            c->ev_used += 2;
+            c->stats.sweep_launches += L.ealt ? 1 : 2;
+            c->stats.sweep_bytes += 16.0 * (double)mgfr::cells(L.g);
+        }
+        c->stats.cell_updates += mgfr::cells(L.g);
+        if (m == 0) c->stats.finest_updates += mgfr::cells(L.g);
+        return MGFR_OK;
+    }
+
+    int vcycle(size_t m)
+    {
+        Level32& L = c->lv32[m];
+        if (m + 1 == c->lv32.size())
+            return hip_check(c, mgfr::coarsest_solve32(L.g, L.ub, L.e, L.f, o->coarsest_sweeps, o->coarsest_rtol, s),
+                             "coarsest_solve32");
+        float* cur = L.e;
+        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m, cur, nullptr));
+        Level32& H = c->lv32[m + 1];
+        MGFR_TRY(hip_check(c, mgfr::resid_restrict32(L.g, L.ub, cur, L.f, H.e, H.ehat, H.f, s), "resid_restrict32"));
+        MGFR_TRY(hip_check(c, mgfr::fas_rhs32(H.g, H.ub, H.ehat, H.f, s), "fas_rhs32"));
+        MGFR_TRY(vcycle(m + 1));
+        MGFR_TRY(hip_check(c, mgfr::coarse_difference32(H.g, H.e, H.ehat, s), "coarse_difference32"));
+        if (o->post > 0) {
+            MGFR_TRY(sweep(m, cur, H.ehat));
+            for (int k = 1; k < o->post; ++k) MGFR_TRY(sweep(m, cur, nullptr));
+        } else {
+            MGFR_TRY(hip_check(c, mgfr::prolong_add32(H.g, cur, H.ehat, s), "prolong_add32"));
+        }
+        if (cur != L.e)
+            MGFR_TRY(hip_check(c, hipMemcpyAsync(L.e, cur, sizeof(float) * mgfr::cells(L.g), hipMemcpyDeviceToDevice, s),
+                               "hipMemcpyAsync"));
         return MGFR_OK;
     }
 };
+
+// rms and max of the finest residual L(u) - f (synchronises).
+int finest_norm(mgfr_ctx* c, const mgfr::Grid& g, const double* u, const double* rho, hipStream_t s,
+                double* rms, double* mx)
+{
+    if (g.n >= mgfr::fused_sweep_min_n()) {
+        mgfr::ResidStream a{};
+        a.ti = mgfr::resid_stream_planes(g.n);
+        a.partial = c->partial;
+        MGFR_TRY(hip_check(c, mgfr::resid_stream(g, u, rho, a, s), "resid_stream"));
+        MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, (int)mgfr::resid_stream_blocks(g.n), c->red, s),
+                           "fold_partials"));
+    } else {
+        MGFR_TRY(hip_check(c, mgfr::residual_norm(g, u, rho, c->partial, c->red, s), "residual_norm"));
+    }
+    double r[2];
+    MGFR_TRY(read_reduction(c, s, r));
+    *rms = std::sqrt(r[0] / (double)mgfr::cells(g));
+    if (mx) *mx = r[1];
+    return MGFR_OK;
+}
 
 }  // namespace
 
@@ -280,6 +228,7 @@ void mgfr_destroy(mgfr_ctx* c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     c->free_levels();
+    c->free_levels32();
     (void)hipFree(c->partial);
     (void)hipFree(c->red);
     (void)hipFree(c->counter);
@@ -368,6 +317,38 @@ int mgfr_residual(mgfr_ctx* c, const double* rho, const double* u, int N, const 
     return hip_check(c, mgfr::residual_field(g, u, rho, d, s), "residual_field");
 }
 
+int mgfr_smooth(mgfr_ctx* c, const double* rho, double* u, int N, const mgfr_params* params,
+                const mgfr_opts* o, int nsweeps, int variant, void* stream)
+{
+    if (!c) return MGFR_EINVAL;
+    c->err.clear();
+    c->stats = mgfr_stats{};
+    MGFR_TRY(check_opts(c, o));
+    Model md;
+    if (derive_model(params, &md) != MGFR_OK) return c->fail(MGFR_EINVAL, "invalid model parameters");
+    if (!rho || !u || !is_pow2(N) || N < 2 || N > 2048 || nsweeps < 0 || variant < 0 || variant > 2)
+        return c->fail(MGFR_EINVAL, "invalid arguments");
+    if (variant == 2 && N < mgfr::fused_sweep_min_n())
+        return c->fail(MGFR_EINVAL, "the fused sweep needs N >= %d", mgfr::fused_sweep_min_n());
+    MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+    hipStream_t s = (hipStream_t)stream;
+    MGFR_TRY(ensure_scratch(c));
+    MGFR_TRY(ensure_levels(c, N, std::min(N, o->coarsest_n)));
+    Level& L0 = c->lv[0];
+    MGFR_TRY(finest_grid(c, md, rho, N, o->flags, o->max_step, s, &L0.g));
+    L0.u = u;
+    Cycle cyc{c, o, s};
+    cyc.finest_src = rho;
+    cyc.o_simple = variant == 1;
+    c->ev_used = 0;
+    double* cur = u;
+    for (int k = 0; k < nsweeps; ++k) MGFR_TRY(cyc.sweep(0, rho, cur, nullptr));
+    if (cur != u)
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(u, cur, sizeof(double) * mgfr::cells(L0.g), hipMemcpyDeviceToDevice, s),
+                           "hipMemcpyAsync"));
+    return cyc.harvest();
+}
+
 int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params, const mgfr_opts* o,
                 double* u, double* res_hist, int* n_hist, void* stream)
 {
@@ -382,7 +363,6 @@ int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params
     if (!rho || !u) return c->fail(MGFR_EINVAL, "rho or u is NULL");
     if (!is_pow2(N) || N < o->coarsest_n || N > 2048)
         return c->fail(MGFR_EINVAL, "N=%d must be a power of two in [coarsest_n, 2048]", N);
-    if (o->precision != MGFR_FP64) return c->fail(MGFR_EINVAL, "precision %d not available", o->precision);
     MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
     hipStream_t s = (hipStream_t)stream;
     MGFR_TRY(ensure_scratch(c));
@@ -410,22 +390,75 @@ int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params
     cyc.finest_src = rho;
     c->ev_used = 0;
     MGFR_TRY(hip_check(c, hipMemsetAsync(c->counter, 0, sizeof(long long), s), "hipMemsetAsync"));
-    auto norm = [&](double* rms) -> int {
-        MGFR_TRY(hip_check(c, mgfr::residual_norm(L0.g, u, rho, c->partial, c->red, s), "residual_norm"));
-        MGFR_TRY(read_reduction(c, s, r));
-        *rms = std::sqrt(r[0] / (double)ncell);
-        return MGFR_OK;
-    };
     double rms;
-    MGFR_TRY(norm(&rms));
     int k = 0;
-    if (res_hist) res_hist[0] = rms;
-    while (std::isfinite(rms) && rms > o->tol && k < o->max_cycles) {
-        MGFR_TRY(cyc.vcycle(0));
-        MGFR_TRY(norm(&rms));
-        MGFR_TRY(cyc.harvest());
-        ++k;
-        if (res_hist) res_hist[k] = rms;
+    if (o->precision == MGFR_FP64) {
+        MGFR_TRY(finest_norm(c, L0.g, u, rho, s, &rms, nullptr));
+        if (res_hist) res_hist[0] = rms;
+        while (std::isfinite(rms) && rms > o->tol && k < o->max_cycles) {
+            MGFR_TRY(cyc.vcycle(0));
+            MGFR_TRY(finest_norm(c, L0.g, u, rho, s, &rms, nullptr));
+            MGFR_TRY(cyc.harvest());
+            ++k;
+            if (res_hist) res_hist[k] = rms;
+        }
+    } else {
+        // Defect correction: d = L(u) - f in double precision; a single-precision FAS
+        // multigrid solves N(e) = -d for the correction; u += e; repeat.
+        MGFR_TRY(ensure_levels32(c, N, o->coarsest_n));
+        for (size_t m = 0; m < c->lv32.size(); ++m) c->lv32[m].g = c->lv[m].g;
+        Level32& I0 = c->lv32[0];
+        Cycle32 cyc32{c, o, s};
+        const bool stream = N >= mgfr::fused_sweep_min_n();
+        double* ucur = u;
+        // residual of ucur (+ e when `update`), cast to the single-precision right-hand side
+        auto outer_residual = [&](bool update) -> int {
+            if (stream) {
+                mgfr::ResidStream a{};
+                a.ti = mgfr::resid_stream_planes(N);
+                a.partial = c->partial;
+                a.r32 = I0.f;
+                a.ub32 = I0.ub;
+                double* next = ucur;
+                if (update) {
+                    next = ucur == u ? L0.alt : u;
+                    a.e32 = I0.e;
+                    a.uout = next;
+                }
+                MGFR_TRY(hip_check(c, mgfr::resid_stream(L0.g, ucur, rho, a, s), "resid_stream"));
+                MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, (int)mgfr::resid_stream_blocks(N), c->red, s),
+                                   "fold_partials"));
+                ucur = next;
+            } else {
+                if (update) MGFR_TRY(hip_check(c, mgfr::add_correction(ucur, I0.e, ncell, s), "add_correction"));
+                MGFR_TRY(hip_check(c, mgfr::residual_cast(L0.g, ucur, rho, I0.f, I0.ub, c->partial, c->red, s),
+                                   "residual_cast"));
+            }
+            double r2[2];
+            MGFR_TRY(read_reduction(c, s, r2));
+            rms = std::sqrt(r2[0] / (double)ncell);
+            return MGFR_OK;
+        };
+        MGFR_TRY(outer_residual(false));
+        if (res_hist) res_hist[0] = rms;
+        while (std::isfinite(rms) && rms > o->tol && k < o->max_cycles) {
+            for (size_t m = 1; m < c->lv32.size(); ++m)
+                MGFR_TRY(hip_check(c, mgfr::restrict_mean32(c->lv32[m].g, c->lv32[m - 1].ub, c->lv32[m].ub, s),
+                                   "restrict_mean32"));
+            MGFR_TRY(hip_check(c, mgfr::fill32(I0.e, 0.0f, ncell, s), "fill32"));
+            for (int ic = 0; ic < o->inner_cycles; ++ic) {
+                MGFR_TRY(cyc32.vcycle(0));
+                ++c->stats.inner_cycles;
+            }
+            MGFR_TRY(outer_residual(true));
+            MGFR_TRY(cyc.harvest());
+            ++k;
+            if (res_hist) res_hist[k] = rms;
+        }
+        if (ucur != u)
+            MGFR_TRY(hip_check(c, hipMemcpyAsync(u, ucur, sizeof(double) * ncell, hipMemcpyDeviceToDevice, s),
+                               "hipMemcpyAsync"));
+        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
     }
     if (n_hist) *n_hist = k + 1;
     {

@@ -34,6 +34,11 @@ class mgfr_opts(ctypes.Structure):
                 ("coarsest_rtol", ctypes.c_double)]
 
 
+class mgfr_patch(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int), ("parent", ctypes.c_int), ("origin", ctypes.c_int * 3),
+                ("n", ctypes.c_int), ("offset", ctypes.c_longlong)]
+
+
 class mgfr_stats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("inner_cycles", ctypes.c_int),
                 ("cell_updates", ctypes.c_longlong), ("finest_updates", ctypes.c_longlong),
@@ -83,6 +88,11 @@ def lib():
             "mgfr_constants": ([P, ctypes.c_int, dp], ctypes.c_int),
             "mgfr_residual": ([vp, vp, vp, ctypes.c_int, P, ctypes.c_int, vp, vp], ctypes.c_int),
             "mg_fr_solve": ([vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
+            "mgfr_smooth": ([vp, vp, vp, ctypes.c_int, P, O, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
+            "mg_fr_solve_patches": ([vp, vp, ctypes.c_int, ctypes.POINTER(mgfr_patch), ctypes.c_int, vp, vp,
+                                     ctypes.c_longlong, P, O, dp, ip, vp], ctypes.c_int),
+            "mg_fr_solve_batch": ([vp, ctypes.c_int, ip, ctypes.POINTER(vp), P, O, ctypes.POINTER(vp), dp, ip, vp],
+                                  ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -94,7 +104,8 @@ def lib():
 
 def exported_symbols():
     return ("mgfr_create", "mgfr_destroy", "mgfr_last_error", "mgfr_default_opts", "mgfr_constants",
-            "mgfr_residual", "mg_fr_solve", "mgfr_get_stats")
+            "mgfr_residual", "mg_fr_solve", "mgfr_get_stats", "mgfr_smooth", "mg_fr_solve_patches",
+            "mg_fr_solve_batch")
 
 
 def mgfr_default_opts(**overrides) -> mgfr_opts:
@@ -189,6 +200,20 @@ def mgfr_residual(ctx: Context, rho, u, params: Params, flags: int = 0, out=None
     return out
 
 
+def mgfr_smooth(ctx: Context, rho, u, params: Params, nsweeps: int, variant: int = 0,
+                opts: mgfr_opts | None = None, stream=None):
+    """nsweeps single-grid red-black Newton-Gauss-Seidel sweeps, in place on u.
+    variant 0: solver's choice, 1: per-colour kernels, 2: fused red-black kernel."""
+    N = rho.shape[0]
+    if opts is None:
+        opts = mgfr_default_opts()
+    st = lib().mgfr_smooth(ctx.handle, _ptr(rho), _ptr(u), N, ctypes.byref(params.c()), ctypes.byref(opts),
+                           nsweeps, variant, _stream(stream))
+    if st != MGFR_OK:
+        raise MgfrError(st, ctx.last_error())
+    return u
+
+
 def mg_fr_solve(ctx: Context, rho, params: Params, opts: mgfr_opts | None = None, u=None,
                 stream=None, raise_on_error: bool = True):
     """Solves the domain grid.  rho, u: float64 device tensors of shape (N, N, N); u is
@@ -208,3 +233,64 @@ def mg_fr_solve(ctx: Context, rho, params: Params, opts: mgfr_opts | None = None
     if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
         raise MgfrError(st, ctx.last_error())
     return u, hist[:nh.value].copy(), st
+
+
+def mg_fr_solve_patches(ctx: Context, u_domain, patches, rho_packed, params: Params,
+                        opts: mgfr_opts | None = None, u_packed=None, stream=None, raise_on_error: bool = True):
+    """Refinement patches, level by level.  patches: list of dicts {level, parent, origin, n,
+    offset}; rho_packed / u_packed: float64 device tensors holding every patch's n^3 block at
+    its offset; u_domain: the solved (N0, N0, N0) domain grid.
+    Returns (u_packed, per-patch residual histories, status)."""
+    import torch
+    if opts is None:
+        opts = mgfr_default_opts()
+    npatch = len(patches)
+    arr = (mgfr_patch * max(npatch, 1))()
+    for i, p in enumerate(patches):
+        arr[i].level = int(p["level"])
+        arr[i].parent = int(p["parent"])
+        for d in range(3):
+            arr[i].origin[d] = int(p["origin"][d])
+        arr[i].n = int(p["n"])
+        arr[i].offset = int(p["offset"])
+    if u_packed is None:
+        u_packed = torch.empty_like(rho_packed)
+    H = opts.max_cycles + 1
+    hist = np.zeros(max(npatch, 1) * H)
+    nh = np.zeros(max(npatch, 1), dtype=np.int32)
+    st = lib().mg_fr_solve_patches(ctx.handle, _ptr(u_domain), u_domain.shape[0], arr, npatch, _ptr(rho_packed),
+                                   _ptr(u_packed), rho_packed.numel(), ctypes.byref(params.c()),
+                                   ctypes.byref(opts), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   nh.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _stream(stream))
+    if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
+        raise MgfrError(st, ctx.last_error())
+    hists = [hist[i * H:i * H + nh[i]].copy() for i in range(npatch)]
+    return u_packed, hists, st
+
+
+def mg_fr_solve_batch(ctx: Context, rhos, params_list, opts: mgfr_opts | None = None, us=None, stream=None,
+                      raise_on_error: bool = True):
+    """Independent periodic boxes solved together.  rhos: list of (N, N, N) float64 device
+    tensors; params_list: one Params per box.  Returns (list of u, histories, status)."""
+    import torch
+    if opts is None:
+        opts = mgfr_default_opts()
+    nbox = len(rhos)
+    if us is None:
+        us = [torch.empty_like(r) for r in rhos]
+    Ns = (ctypes.c_int * max(nbox, 1))(*[int(r.shape[0]) for r in rhos])
+    rp = (ctypes.c_void_p * max(nbox, 1))(*[r.data_ptr() for r in rhos])
+    up = (ctypes.c_void_p * max(nbox, 1))(*[u.data_ptr() for u in us])
+    pp = (mgfr_params * max(nbox, 1))(*[p.c() for p in params_list])
+    for r, u in zip(rhos, us):
+        assert r.is_cuda and r.is_contiguous() and u.is_cuda and u.is_contiguous()
+    H = opts.max_cycles + 1
+    hist = np.zeros(max(nbox, 1) * H)
+    nh = np.zeros(max(nbox, 1), dtype=np.int32)
+    st = lib().mg_fr_solve_batch(ctx.handle, nbox, Ns, rp, pp, ctypes.byref(opts), up,
+                                 hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 nh.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _stream(stream))
+    if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
+        raise MgfrError(st, ctx.last_error())
+    hists = [hist[i * H:i * H + nh[i]].copy() for i in range(nbox)]
+    return us, hists, st

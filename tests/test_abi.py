@@ -48,14 +48,15 @@ def test_struct_layouts_match_the_header():
     import subprocess
     import tempfile
     from paper_1110_1379_amd import mgfr
-    src = ('#include "mgfr.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu\\n", '
-           'sizeof(mgfr_params), sizeof(mgfr_opts), sizeof(mgfr_stats));return 0;}\n')
+    src = ('#include "mgfr.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu %zu\\n", '
+           'sizeof(mgfr_params), sizeof(mgfr_opts), sizeof(mgfr_stats), sizeof(mgfr_patch));return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
         exe = os.path.join(d, "s")
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
-        a, b, c = map(int, subprocess.check_output([exe]).split())
+        a, b, c, d = map(int, subprocess.check_output([exe]).split())
     assert ctypes.sizeof(mgfr.mgfr_params) == a
     assert ctypes.sizeof(mgfr.mgfr_opts) == b
     assert ctypes.sizeof(mgfr.mgfr_stats) == c
+    assert ctypes.sizeof(mgfr.mgfr_patch) == d

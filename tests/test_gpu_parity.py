@@ -75,13 +75,40 @@ def test_operator_matches_oracle(mg, ctx, N):
     assert np.abs(d - L).max() <= 1e-13 * scale
 
 
+@pytest.mark.parametrize("N", [64, 128])
+def test_fused_sweep_is_bitwise_the_two_pass_sweep(mg, ctx, N):
+    """The fused red-black sweep (redundant ring of red updates per tile) gives exactly the
+    same bits as sweeping all red cells, then all black cells."""
+    say(f"[smooth] fused vs two-pass N={N}")
+    p, m = both(float(N), 1e-5)
+    rho = inputs.lognormal(N, 2.0, -1.5, seed=11)
+    u0 = O.constants(m, N)["ubar"] + 0.2 * np.random.default_rng(1).standard_normal((N, N, N))
+    a = mg.mgfr_smooth(ctx, dev(rho), dev(u0), p, nsweeps=3, variant=1).cpu().numpy()
+    b = mg.mgfr_smooth(ctx, dev(rho), dev(u0), p, nsweeps=3, variant=2).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("N,variant", [(16, 1), (64, 1), (64, 2)])
+def test_smoother_matches_oracle_single_grid(mg, ctx, N, variant):
+    """Three single-grid Newton-Gauss-Seidel sweeps against the oracle's, cell by cell."""
+    say(f"[smooth] vs oracle N={N} variant={variant}")
+    p, m = both(64.0, 1e-5)
+    rho = inputs.lognormal(N, 1.5, -2.0, seed=12)
+    u0 = O.constants(m, N)["ubar"] + 0.2 * np.random.default_rng(2).standard_normal((N, N, N))
+    g = mg.mgfr_smooth(ctx, dev(rho), dev(u0), p, nsweeps=3, variant=variant).cpu().numpy()
+    ref, _ = O.single_grid(rho, m, u0, 3, max_step=1.0)
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 SOLVE_CASES = [
     # (name, N, box, fr0, density maker, tol)
     ("lognormal-32-F5", 32, 64.0, 1e-5, lambda N: inputs.small_box(N, 0), 1e-12),
     ("lognormal-16-F5", 16, 32.0, 1e-5, lambda N: inputs.small_box(N, 3), 1e-12),
-    ("lognormal-8-F4", 8, 16.0, 1e-4, lambda N: inputs.lognormal(N, 1.0, -2.0, 5), 1e-12),
+    # c~^2 b / h^2 ~ 220 here: the double-precision floor of the residual is ~1e-12
+    ("lognormal-8-F4", 8, 16.0, 1e-4, lambda N: inputs.lognormal(N, 1.0, -2.0, 5), 1e-11),
     ("tophat-64-F5", 64, 64.0, 1e-5, lambda N: inputs.tophat_box(N, 1, count=3), 1e-11),
     ("halo-64-F6", 64, 64.0, 1e-6, lambda N: inputs.halo_box(N, 2, count=4), 1e-11),
+    ("lognormal-128-F5", 128, 128.0, 1e-5, lambda N: inputs.lognormal(N, 1.5, -1.5, 6), 1e-11),
 ]
 
 
@@ -100,6 +127,32 @@ def test_fp64_solve_matches_oracle(mg, ctx, name, N, box, fr0, make, tol):
     # six digits above the double-precision noise of the residual (~1e-13 .. 1e-12 here)
     assert len(hist) == len(h_ref)
     np.testing.assert_allclose(hist, h_ref, rtol=1e-6, atol=100 * tol)
+
+
+MIXED_CASES = [
+    ("lognormal-32-F5", 32, 64.0, 1e-5, lambda N: inputs.small_box(N, 0)),
+    ("halo-64-F6", 64, 64.0, 1e-6, lambda N: inputs.halo_box(N, 2, count=4)),
+    ("tophat-128-F5", 128, 128.0, 1e-5, lambda N: inputs.tophat_box(N, 1, count=25)),
+]
+
+
+@pytest.mark.parametrize("inner", [1, 2])
+@pytest.mark.parametrize("name,N,box,fr0,make", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_mixed_solve_matches_fp64_oracle(mg, ctx, name, N, box, fr0, make, inner):
+    """Single-precision correction V-cycles inside the double-precision defect-correction loop
+    reach rms(L) <= 1e-8 with max|u - u*|/max|u*| <= 1e-6 against the oracle at 1e-12."""
+    say(f"[mixed] {name} inner={inner}")
+    p, m = both(box, fr0)
+    rho = make(N)
+    o = mg.mgfr_default_opts(tol=1e-8, precision=mg.MGFR_MIXED, inner_cycles=inner)
+    u_d, hist, st = mg.mg_fr_solve(ctx, dev(rho), p, o)
+    assert st == mg.MGFR_OK, (ctx.last_error(), hist)
+    assert hist[-1] <= 1e-8
+    u_ref, _, st_ref = O.solve(rho, m, O.Opts(tol=1e-12 if N < 128 else 1e-11))
+    assert st_ref == 0
+    assert rel_err(u_d.cpu().numpy(), u_ref) <= 1e-6
+    # the outer residual falls at every step
+    assert np.all(np.diff(hist) < 0), hist
 
 
 def test_uniform_density_gives_background(mg, ctx):
@@ -169,17 +222,19 @@ def _sampled_residual(u, rho, m, nsample, seed):
     return O.operator_at(u, m, 1.0 / N, idx, rho=rho)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name,N,box,fr0", [("tophat-256-F5", 256, 256.0, 1e-5),
                                            ("halo-512-F6", 512, 512.0, 1e-6)])
-def test_full_size_solution_satisfies_oracle_operator(mg, ctx, name, N, box, fr0):
+def test_full_size_solution_satisfies_oracle_operator(mg, ctx, name, N, box, fr0, precision):
     """At the benchmark sizes the oracle's operator, evaluated on the GPU solution at sampled
     cells, is consistent with the reported rms residual <= 1e-8 (the residual is a property
     of the solution alone, so this holds whatever path produced it)."""
     say(f"[full] {name}: generating input")
     rho = inputs.tophat_box(N) if N == 256 else inputs.halo_box(N)
     p, m = both(box, fr0)
-    say(f"[full] {name}: solving")
-    u_d, hist, st = mg.mg_fr_solve(ctx, dev(rho), p, mg.mgfr_default_opts(tol=1e-8, max_cycles=100))
+    say(f"[full] {name} {precision}: solving")
+    prec = mg.MGFR_MIXED if precision == "mixed" else mg.MGFR_FP64
+    u_d, hist, st = mg.mg_fr_solve(ctx, dev(rho), p, mg.mgfr_default_opts(tol=1e-8, max_cycles=100, precision=prec))
     assert st == mg.MGFR_OK, (ctx.last_error(), hist)
     u = u_d.cpu().numpy()
     say(f"[full] {name}: cycles={len(hist) - 1} final={hist[-1]:.3e}; oracle check")
