@@ -1,14 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the f(R) multigrid solve on one MI355X.
 
-One step = one complete solve of the 512^3 periodic domain grid (box 512 Mpc/h, |f_R0| =
-1e-6, lognormal sigma = 3 density plus 2000 NFW-like halos) from the background field to an
-rms residual <= 1e-8, with the density already resident in HBM.  Printed: ONE JSON line
-with time-to-tolerance (ms_per_step), cell-updates/s over all multigrid levels (value), the
-smoother's roofline position (HIP-event timing of the finest-level smoother launches in the
-timed steps), and the CPU oracle timed on a bounded sample of the same workload.
+Default workload (halo512): one step = one complete solve of the 512^3 periodic domain
+grid (box 512 Mpc/h, |f_R0| = 1e-6, lognormal sigma = 3 density plus 2000 NFW-like halos)
+from the background field to an rms residual <= 1e-8, with the density already resident in
+HBM.  Both solvers are timed, FP64 and mixed (FP32 correction V-cycles inside an FP64
+defect-correction loop); the headline `value` is the mixed solver's cell-updates/s and
+ms_per_step its time-to-tolerance, the FP64 solver is reported under "fp64".  Printed: ONE
+JSON line, with the smoother's roofline position (HIP events around the finest-level
+smoother launches of the timed solves, on the solve's stream) and the CPU oracle timed on a
+bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--precision fp64|mixed] [--workload halo512]
+Other workloads: --workload tophat256 | small32 (same line, other grid), amr (domain grid
+plus refinement patches over 3 levels), batch (64 boxes of 64^3 + 16 of 128^3).
 """
 from __future__ import annotations
 
@@ -23,13 +27,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "f(R) MG time-to-residual 1e-8 & cell-updates/s, 512^3, FP64 vs mixed"
 
 WORKLOADS = {
-    # name: (N, box Mpc/h, |f_R0|, generator, oracle sample (N, count))
+    # name: (N, box Mpc/h, |f_R0|, generator, oracle sample (N, structures))
     "halo512": (512, 512.0, 1e-6, "halo_box", (128, 31)),
     "tophat256": (256, 256.0, 1e-5, "tophat_box", (128, 25)),
     "small32": (32, 64.0, 1e-5, "small_box", (32, 0)),
 }
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def make_density(name, N):
@@ -61,9 +70,172 @@ def cpu_baseline(name, tol):
     ups = oracle.last_cell_updates()
     return {"value": ups / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{Ns}^3 box of {box_s:g} Mpc/h (same cell size and density recipe, "
-                      f"{count} structures), solved to rms {tol:g}: {len(hist) - 1} V-cycles, "
+                      f"{count} structures), FP64, solved to rms {tol:g}: {len(hist) - 1} V-cycles, "
                       f"{dt:.1f} s, status {st}",
             "time_to_tol_s": dt}
+
+
+def time_domain(mgfr, ctx, rho_d, params, prec, tol, steps, warmup, profile=True):
+    import torch
+    u_d = torch.empty_like(rho_d)
+    flags = mgfr.MGFR_PROFILE if profile else 0
+    opts = mgfr.mgfr_default_opts(tol=tol, precision=prec, max_cycles=100, flags=flags)
+    stream = torch.cuda.current_stream()
+    for w in range(warmup):
+        _, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, opts, u=u_d, stream=stream)
+        log(f"warmup {w} prec={prec}: status {st}, {len(hist) - 1} cycles, final {hist[-1]:.3e}")
+    stats, hists = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, opts, u=u_d, stream=stream)
+        if st != mgfr.MGFR_OK:
+            raise SystemExit(f"solve failed: {mgfr.STATUS_NAMES.get(st, st)} {ctx.last_error()}")
+        stats.append(mgfr.mgfr_get_stats(ctx))
+        hists.append(hist)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    updates = sum(s["cell_updates"] for s in stats) / steps
+    finest = sum(s["finest_updates"] for s in stats) / steps
+    sweep_ms = sum(s["sweep_ms"] for s in stats)
+    sweep_bytes = sum(s["sweep_bytes"] for s in stats)
+    launches = sum(s["sweep_launches"] for s in stats)
+    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
+    res = {"ms_per_step": ms, "value": updates / (ms * 1e-3), "cycles": stats[-1]["cycles"],
+           "inner_cycles": stats[-1]["inner_cycles"], "final_residual": float(hists[-1][-1]),
+           "finest_cell_updates_per_s": finest / (ms * 1e-3),
+           "smoother": {"achieved_GBs": achieved, "launches": launches,
+                        "avg_launch_ms": sweep_ms / launches if launches else None,
+                        "bytes_per_cell_sweep": 24 if prec == mgfr.MGFR_FP64 else 16}}
+    log(f"prec={prec}: {ms:.2f} ms/solve, {res['cycles']} cycles, smoother "
+        f"{achieved and round(achieved)} GB/s over {launches} launches")
+    return res, u_d
+
+
+def bench_domain(args):
+    import torch
+    from paper_1110_1379_amd import mgfr
+    N, box, fr0, _, _ = WORKLOADS[args.workload]
+    log(f"generating {args.workload} density ({N}^3)")
+    rho_d = torch.from_numpy(make_density(args.workload, N)).to("cuda:0")
+    params = mgfr.Params(box_mpc_h=box, fr0_abs=fr0)
+    ctx = mgfr.Context(0)
+    runs = {}
+    precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    for p in precs:
+        code = mgfr.MGFR_MIXED if p == "mixed" else mgfr.MGFR_FP64
+        runs[p], _ = time_domain(mgfr, ctx, rho_d, params, code, args.tol, args.steps, args.warmup)
+    head = runs["mixed"] if "mixed" in runs else runs["fp64"]
+    headp = "mixed" if "mixed" in runs else "fp64"
+    sm = head["smoother"]
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if headp == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {N}^3 periodic, box {box:g} Mpc/h, |f_R0|={fr0:g}, n=1, "
+                               f"Om=0.24, a=1; solve from the background to rms residual {args.tol:g}",
+                   "N": N, "tol": args.tol, "precision": headp, "pre_post": [2, 2], "coarsest": 4},
+        "time_to_tol_ms": head["ms_per_step"],
+        "cycles": head["cycles"],
+        "final_residual": head["final_residual"],
+        "roofline": {
+            "bound": "hbm", "achieved": sm["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (sm["achieved_GBs"] / HBM_PEAK_GBS) if sm["achieved_GBs"] else None, "traffic": None,
+            "kernel": ("single-precision correction smoother k32_fused" if headp == "mixed"
+                       else "double-precision smoother k_ngs_fused") + " (finest level)",
+            "bytes_per_cell": sm["bytes_per_cell_sweep"], "launches": sm["launches"],
+            "avg_launch_ms": sm["avg_launch_ms"],
+        },
+    }
+    for p, r in runs.items():
+        out[p] = r
+    if "fp64" in runs and "mixed" in runs:
+        out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.tol)
+    return out
+
+
+def bench_amr(args):
+    """Domain grid (256^3, FP64) plus its refinement patches, all levels; one step = the
+    patch solve of every refinement level (domain solution given)."""
+    import numpy as np
+    import torch
+    from paper_1110_1379_amd import inputs, mgfr
+    N0, box, fr0 = 256, 256.0, 1e-5
+    log("generating the AMR workload")
+    rho0, patches, rho_packed = inputs.amr_workload(N0)
+    cells = int(sum(p["n"] ** 3 for p in patches))
+    log(f"{len(patches)} patches, {cells} patch cells")
+    ctx = mgfr.Context(0)
+    params = mgfr.Params(box_mpc_h=box, fr0_abs=fr0)
+    rho_d = torch.from_numpy(rho0).to("cuda:0")
+    ud, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100))
+    assert st == mgfr.MGFR_OK, ctx.last_error()
+    rp = torch.from_numpy(rho_packed).to("cuda:0")
+    up = torch.empty_like(rp)
+    opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100)
+    for _ in range(args.warmup):
+        mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, opts, u_packed=up)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, hists, st = mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, opts, u_packed=up)
+        if st != mgfr.MGFR_OK:
+            raise SystemExit(f"patch solve failed: {ctx.last_error()}")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    s = mgfr.mgfr_get_stats(ctx)
+    return {"metric": "f(R) MG patch solve time-to-residual & cell-updates/s (AMR refinements)",
+            "value": s["cell_updates"] / (ms * 1e-3), "unit": "cell-updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"amr: {N0}^3 domain (lognormal sigma 2), {len(patches)} cube patches "
+                                   f"8^3-64^3 over {max(p['level'] for p in patches)} levels "
+                                   f"(contrast > 50/200/1000), {cells} patch cells, tol {args.tol:g}"},
+            "max_cycles_per_patch": int(max(len(h) for h in hists) - 1)}
+
+
+def bench_batch(args):
+    """64 boxes of 64^3 plus 16 of 128^3 with their own |f_R0| and sigma, solved together."""
+    import torch
+    from paper_1110_1379_amd import inputs, mgfr
+    log("generating the boxes")
+    boxes = inputs.batch_boxes()
+    rhos = [torch.from_numpy(b[5]).to("cuda:0") for b in boxes]
+    params = [mgfr.Params(box_mpc_h=b[1], fr0_abs=b[2]) for b in boxes]
+    us = [torch.empty_like(r) for r in rhos]
+    ctx = mgfr.Context(0)
+    opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100)
+    for _ in range(args.warmup):
+        mgfr.mg_fr_solve_batch(ctx, rhos, params, opts, us=us)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, hists, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, opts, us=us)
+        if st != mgfr.MGFR_OK:
+            raise SystemExit(f"batch solve failed: {ctx.last_error()}")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    s = mgfr.mgfr_get_stats(ctx)
+    return {"metric": "f(R) MG batch of independent boxes: boxes/s at residual 1e-8",
+            "value": len(boxes) / (ms * 1e-3), "unit": "boxes/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "batch: 64 x 64^3 (B=64) + 16 x 128^3 (B=128), |f_R0| log-uniform "
+                                   f"[1e-6,1e-4], lognormal sigma U[1,3], tol {args.tol:g}"},
+            "cell_updates_per_s": s["cell_updates"] / (ms * 1e-3),
+            "max_cycles_per_box": int(max(len(h) for h in hists) - 1)}
 
 
 def main():
@@ -71,89 +243,32 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="halo512", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--workload", default="halo512", choices=sorted(WORKLOADS) + ["amr", "batch"])
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each": a.numel() * 8, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs the "
               f"solver on a single MI355X).", file=sys.stderr)
         sys.exit(2)
-
-    import torch
-    from paper_1110_1379_amd import mgfr
-
-    N, box, fr0, _, _ = WORKLOADS[args.workload]
-    print(f"[bench] generating {args.workload} density ({N}^3)", file=sys.stderr, flush=True)
-    rho = make_density(args.workload, N)
-    rho_d = torch.from_numpy(rho).to("cuda:0")
-    del rho
-    u_d = torch.empty_like(rho_d)
-    params = mgfr.Params(box_mpc_h=box, fr0_abs=fr0)
-    prec = mgfr.MGFR_MIXED if args.precision == "mixed" else mgfr.MGFR_FP64
-    opts = mgfr.mgfr_default_opts(tol=args.tol, precision=prec, max_cycles=100, flags=mgfr.MGFR_PROFILE)
-    ctx = mgfr.Context(0)
-    stream = torch.cuda.current_stream()
-
-    for w in range(args.warmup):
-        _, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, opts, u=u_d, stream=stream)
-        print(f"[bench] warmup {w}: status {st}, {len(hist) - 1} cycles, final {hist[-1]:.3e}",
-              file=sys.stderr, flush=True)
-
-    stats = []
-    hists = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        _, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, opts, u=u_d, stream=stream)
-        if st != mgfr.MGFR_OK:
-            raise SystemExit(f"solve failed: {mgfr.STATUS_NAMES.get(st, st)} {ctx.last_error()}")
-        stats.append(mgfr.mgfr_get_stats(ctx))
-        hists.append(hist)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    updates = sum(s["cell_updates"] for s in stats) / args.steps
-    finest = sum(s["finest_updates"] for s in stats) / args.steps
-    sweep_ms = sum(s["sweep_ms"] for s in stats)
-    sweep_bytes = sum(s["sweep_bytes"] for s in stats)
-    launches = sum(s["sweep_launches"] for s in stats)
-    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
-    print(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/solve, {stats[-1]['cycles']} cycles, "
-          f"smoother {achieved and round(achieved)} GB/s over {launches} launches", file=sys.stderr, flush=True)
-
-    out = {
-        "metric": "f(R) MG time-to-residual 1e-8 & cell-updates/s, 512^3, FP64 vs mixed",
-        "value": updates / (ms_per_step * 1e-3),
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == mgfr.MGFR_FP64 else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {N}^3 periodic, box {box:g} Mpc/h, |f_R0|={fr0:g}, n=1, "
-                               f"Om=0.24, a=1; solve from the background to rms residual {args.tol:g}",
-                   "N": N, "tol": args.tol, "precision": args.precision,
-                   "pre_post": [opts.pre, opts.post], "coarsest": opts.coarsest_n},
-        "time_to_tol_ms": ms_per_step,
-        "cycles": stats[-1]["cycles"],
-        "final_residual": float(hists[-1][-1]),
-        "finest_cell_updates_per_s": finest / (ms_per_step * 1e-3),
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-            "kernel": "finest-level Newton-Gauss-Seidel smoother",
-            "launches": launches, "avg_launch_ms": sweep_ms / launches if launches else None,
-        },
-    }
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.tol)
+    if args.workload == "amr":
+        out = bench_amr(args)
+    elif args.workload == "batch":
+        out = bench_batch(args)
+    else:
+        out = bench_domain(args)
     print(json.dumps(out))
 
 

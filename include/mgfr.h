@@ -67,6 +67,8 @@ typedef struct mgfr_opts {
     double max_step;      /* > 0: bound |Newton step| per visit; 0: plain Newton    [1.0]    */
     double coarsest_rtol; /* coarsest level sweeps until rms <= rtol x initial or down to
                              its rounding floor; 0: always coarsest_sweeps            [1e-3]   */
+    int planes;           /* planes per workgroup of the finest-level fused sweeps (N >= 64):
+                             0 = automatic, else a power of two <= N                 [0]      */
 } mgfr_opts;
 
 /* One refinement patch: a cube of n^3 cells at refinement level `level` >= 1 (cell size
@@ -110,6 +112,17 @@ const char* mgfr_last_error(const mgfr_ctx* ctx);
 
 /* Copies the counters of the last solve on ctx into *out. */
 int mgfr_get_stats(const mgfr_ctx* ctx, mgfr_stats* out);
+
+/* Autotuner: times complete solves of this problem (rho, N, params as for mg_fr_solve,
+ * starting from the background) over candidate settings of the tunable options -- sweeps
+ * before/after the coarse step, planes per workgroup of the fused sweep, and for
+ * MGFR_MIXED the single-precision V-cycles per outer iteration -- and writes the fastest
+ * (by host wall time, best of two solves each) into *best (other fields copied from *base).
+ * u_scratch: device, N^3, overwritten.  best_ms (host, may be NULL) gets its solve time.
+ * Candidates that do not converge within base->max_cycles are skipped.  Synchronises. */
+int mgfr_autotune(mgfr_ctx* ctx, const double* rho, int N, const mgfr_params* params,
+                  const mgfr_opts* base, double* u_scratch, mgfr_opts* best, double* best_ms,
+                  void* stream);
 
 /* Writes the defaults into *opts. */
 void mgfr_default_opts(mgfr_opts* opts);

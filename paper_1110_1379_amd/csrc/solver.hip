@@ -18,6 +18,13 @@ namespace {
 
 using namespace mgfr_host;
 
+// Planes per workgroup of a fused sweep: the option on the finest level, else automatic.
+int planes_for(const mgfr_opts* o, size_t m, int n)
+{
+    if (m == 0 && o->planes > 0 && o->planes <= n) return o->planes;
+    return mgfr::fused_sweep_planes(n);
+}
+
 struct Cycle {
     mgfr_ctx* c;
     const mgfr_opts* o;
@@ -44,7 +51,7 @@ struct Cycle {
         }
         if (fused) {
             double* out = cur == L.u ? L.alt : L.u;
-            MGFR_TRY(hip_check(c, mgfr::ngs_sweep_fused(L.g, cur, out, src, e, mgfr::fused_sweep_planes(L.g.n), s),
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep_fused(L.g, cur, out, src, e, planes_for(o, m, L.g.n), s),
                                "ngs_sweep_fused"));
             cur = out;
         } else {
@@ -139,8 +146,7 @@ struct Cycle32 {
         }
         if (L.ealt) {
             float* out = cur == L.e ? L.ealt : L.e;
-            MGFR_TRY(hip_check(c, mgfr::ngs_sweep32_fused(L.g, L.ub, cur, out, L.f, ec,
-                                                          mgfr::fused_sweep_planes(L.g.n), s),
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep32_fused(L.g, L.ub, cur, out, L.f, ec, planes_for(o, m, L.g.n), s),
                                "ngs_sweep32_fused"));
             cur = out;
         } else {
@@ -260,6 +266,7 @@ void mgfr_default_opts(mgfr_opts* o)
     o->inner_cycles = 1;
     o->max_step = 1.0;
     o->coarsest_rtol = 1e-3;
+    o->planes = 0;
 }
 
 int mgfr_constants(const mgfr_params* params, int N, double* out8)
@@ -474,6 +481,74 @@ int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params
     }
     if (!std::isfinite(rms)) return c->fail(MGFR_ENONFINITE, "residual became non-finite after %d cycles", k);
     if (rms > o->tol) return c->fail(MGFR_ENOTCONV, "rms residual %.3e > tol %.3e after %d cycles", rms, o->tol, k);
+    return MGFR_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int mgfr_autotune(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params, const mgfr_opts* base,
+                  double* u_scratch, mgfr_opts* best, double* best_ms, void* stream)
+{
+    if (!c) return MGFR_EINVAL;
+    if (!base || !best || !u_scratch) return c->fail(MGFR_EINVAL, "invalid autotune arguments");
+    MGFR_TRY(check_opts(c, base));
+    const int H = base->max_cycles + 1;
+    std::vector<double> hist(H);
+    double best_t = -1.0;
+    mgfr_opts cur_best = *base;
+    auto trial = [&](const mgfr_opts& o, double* t) -> int {
+        double tmin = -1.0;
+        for (int rep = 0; rep < 2; ++rep) {
+            int nh = 0;
+            mgfr_opts oo = o;
+            oo.flags &= ~(MGFR_WARM_START | MGFR_PROFILE);
+            const int st = mg_fr_solve(c, rho, N, params, &oo, u_scratch, hist.data(), &nh, stream);
+            if (st == MGFR_ENOTCONV || st == MGFR_ENONFINITE) {
+                *t = -1.0;
+                return MGFR_OK;
+            }
+            if (st != MGFR_OK) return st;
+            if (tmin < 0.0 || c->stats.solve_ms < tmin) tmin = c->stats.solve_ms;
+        }
+        *t = tmin;
+        return MGFR_OK;
+    };
+    auto consider = [&](const mgfr_opts& o) -> int {
+        double t;
+        MGFR_TRY(trial(o, &t));
+        if (t > 0.0 && (best_t < 0.0 || t < best_t)) {
+            best_t = t;
+            cur_best = o;
+        }
+        return MGFR_OK;
+    };
+    // stage 1: sweeps before / after the coarse step (and inner cycles for mixed)
+    const int sweeps[][2] = {{1, 1}, {2, 1}, {1, 2}, {2, 2}, {3, 3}};
+    const int inners[] = {1, 2};
+    for (const auto& pp : sweeps)
+        for (int ic : inners) {
+            if (ic > 1 && base->precision != MGFR_MIXED) continue;
+            mgfr_opts o = *base;
+            o.pre = pp[0];
+            o.post = pp[1];
+            o.inner_cycles = ic;
+            MGFR_TRY(consider(o));
+        }
+    // stage 2: planes per workgroup of the finest-level fused sweep
+    if (N >= mgfr::fused_sweep_min_n()) {
+        const mgfr_opts stage1 = cur_best;
+        for (int planes = 8; planes <= 128 && planes <= N; planes *= 2) {
+            mgfr_opts o = stage1;
+            o.planes = planes;
+            MGFR_TRY(consider(o));
+        }
+    }
+    if (best_t < 0.0) return c->fail(MGFR_ENOTCONV, "no candidate setting converged");
+    *best = cur_best;
+    if (best_ms) *best_ms = best_t;
+    c->err.clear();
     return MGFR_OK;
 }
 

@@ -125,3 +125,102 @@ def batch_boxes(n64: int = 64, n128: int = 16):
             sigma = rng.uniform(1.0, 3.0)
             out.append((N, B, fr0, sigma, seed, lognormal(N, sigma, -1.5, seed)))
     return out
+
+
+def _interp_periodic(g: np.ndarray, level: int, origin, n: int) -> np.ndarray:
+    """Trilinear interpolation of the cell-centred domain field g (N0^3, periodic) at the
+    centres of an n^3 block of level-`level` cells starting at `origin` (level cells)."""
+    N0 = g.shape[0]
+    f = 2 ** level
+    axes = []
+    for d in range(3):
+        x = (origin[d] + np.arange(n) + 0.5) / f - 0.5      # in domain cell units
+        i0 = np.floor(x).astype(np.int64)
+        w = x - i0
+        axes.append((i0 % N0, (i0 + 1) % N0, w))
+    out = np.zeros((n, n, n))
+    for a in (0, 1):
+        ia, wa = axes[0][a], (1 - axes[0][2]) if a == 0 else axes[0][2]
+        for b in (0, 1):
+            ib, wb = axes[1][b], (1 - axes[1][2]) if b == 0 else axes[1][2]
+            for c in (0, 1):
+                ic, wc = axes[2][c], (1 - axes[2][2]) if c == 0 else axes[2][2]
+                out += (wa[:, None, None] * wb[None, :, None] * wc[None, None, :]) * g[np.ix_(ia, ib, ic)]
+    return out
+
+
+def amr_workload(N0: int = 256, seed: int = 1, sigma: float = 2.0, p: float = -1.5,
+                 thresholds=(50.0, 200.0, 1000.0), sizes=(32, 16, 8, 4), max_patches: int = 2000,
+                 min_fraction: float = 0.02):
+    """Domain density plus refinement patches over len(thresholds) levels.
+
+    Level l refines the cells of level l-1 whose contrast exceeds thresholds[l-1]: greedy,
+    densest flagged cell first, with the largest cube of `sizes` (in parent cells; the patch
+    has twice as many cells per side) that keeps `min_fraction` of flagged cells, stays inside
+    its parent with a one-parent-cell margin and does not overlap a patch of its level.  The
+    density on every level is exp(g - sigma^2/2) normalised as on the domain grid, with g the
+    domain Gaussian field interpolated to the level's cell centres.
+
+    Returns (rho_domain, patches, rho_packed): patches is a list of dicts {level, parent,
+    origin, n, offset}, rho_packed the concatenated patch densities."""
+    g = gaussian_field(N0, sigma, p, seed)
+    rho0 = np.exp(g - 0.5 * sigma * sigma)
+    norm = rho0.mean()
+    rho0 /= norm
+    patches, blocks = [], []
+    offset = 0
+    # parents of level 1: the domain (periodic)
+    parents = [dict(level=0, origin=(0, 0, 0), n=N0, rho=rho0, index=-1)]
+    for lev, thr in enumerate(thresholds, start=1):
+        children = []
+        for par in parents:
+            if len(patches) >= max_patches:
+                break
+            prho = par["rho"]
+            n_p = par["n"]
+            flags = prho - 1.0 > thr
+            if not flags.any():
+                continue
+            occupied = np.zeros_like(flags)
+            covered = np.zeros_like(flags)
+            cand = np.argwhere(flags)
+            order = np.argsort(-prho[flags], kind="stable")
+            for ci in order:
+                if len(patches) >= max_patches:
+                    break
+                c = cand[ci]
+                if covered[tuple(c)]:
+                    continue
+                placed = False
+                for s in sizes:
+                    if lev == 1:
+                        lo, hi = 0, n_p - s           # the domain is periodic: no margin needed
+                    else:
+                        lo, hi = 1, n_p - 1 - s       # one parent cell of margin
+                    if hi < lo:
+                        continue
+                    o = np.clip(c - s // 2, lo, hi)
+                    sl = tuple(slice(int(o[d]), int(o[d]) + s) for d in range(3))
+                    if occupied[sl].any():
+                        continue
+                    if flags[sl].mean() < min_fraction and s != sizes[-1]:
+                        continue
+                    occupied[sl] = True
+                    covered[sl] = True
+                    n = 2 * s
+                    origin = tuple(int(2 * (par["origin"][d] + o[d])) for d in range(3))
+                    rho = np.exp(_interp_periodic(g, lev, origin, n) - 0.5 * sigma * sigma) / norm
+                    rec = dict(level=lev, parent=par["index"], origin=origin, n=n, offset=offset)
+                    patches.append(rec)
+                    blocks.append(rho.ravel())
+                    offset += n ** 3
+                    children.append(dict(level=lev, origin=origin, n=n, rho=rho, index=len(patches) - 1))
+                    placed = True
+                    break
+                if not placed:
+                    covered[tuple(c)] = True
+        parents = children
+        if not parents:
+            break
+    rho_packed = np.concatenate(blocks) if blocks else np.zeros(0)
+    return rho0, patches, rho_packed

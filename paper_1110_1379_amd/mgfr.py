@@ -31,7 +31,7 @@ class mgfr_opts(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int), ("coarsest_sweeps", ctypes.c_int),
                 ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
                 ("inner_cycles", ctypes.c_int), ("max_step", ctypes.c_double),
-                ("coarsest_rtol", ctypes.c_double)]
+                ("coarsest_rtol", ctypes.c_double), ("planes", ctypes.c_int)]
 
 
 class mgfr_patch(ctypes.Structure):
@@ -93,6 +93,7 @@ def lib():
                                      ctypes.c_longlong, P, O, dp, ip, vp], ctypes.c_int),
             "mg_fr_solve_batch": ([vp, ctypes.c_int, ip, ctypes.POINTER(vp), P, O, ctypes.POINTER(vp), dp, ip, vp],
                                   ctypes.c_int),
+            "mgfr_autotune": ([vp, vp, ctypes.c_int, P, O, vp, O, dp, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -105,7 +106,7 @@ def lib():
 def exported_symbols():
     return ("mgfr_create", "mgfr_destroy", "mgfr_last_error", "mgfr_default_opts", "mgfr_constants",
             "mgfr_residual", "mg_fr_solve", "mgfr_get_stats", "mgfr_smooth", "mg_fr_solve_patches",
-            "mg_fr_solve_batch")
+            "mg_fr_solve_batch", "mgfr_autotune")
 
 
 def mgfr_default_opts(**overrides) -> mgfr_opts:
@@ -294,3 +295,46 @@ def mg_fr_solve_batch(ctx: Context, rhos, params_list, opts: mgfr_opts | None = 
         raise MgfrError(st, ctx.last_error())
     hists = [hist[i * H:i * H + nh[i]].copy() for i in range(nbox)]
     return us, hists, st
+
+
+TUNED_FIELDS = ("pre", "post", "inner_cycles", "planes")
+
+
+def mgfr_autotune(ctx: Context, rho, params: Params, base: mgfr_opts | None = None, u_scratch=None,
+                  stream=None, cache_path: str | None = None, key: str | None = None):
+    """Times candidate settings (sweeps, planes per workgroup, inner cycles) on this problem and
+    returns (best opts, best solve ms).  With cache_path, results are kept in a JSON file under
+    `key` (default: N and precision) and reused without timing."""
+    import json
+    import torch
+    if base is None:
+        base = mgfr_default_opts()
+    N = rho.shape[0]
+    key = key or f"N={N},precision={base.precision}"
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            o = mgfr_opts()
+            ctypes.memmove(ctypes.byref(o), ctypes.byref(base), ctypes.sizeof(o))
+            for k in TUNED_FIELDS:
+                setattr(o, k, cache[key][k])
+            return o, cache[key]["ms"]
+    if u_scratch is None:
+        u_scratch = torch.empty_like(rho)
+    best = mgfr_opts()
+    ms = ctypes.c_double(0.0)
+    st = lib().mgfr_autotune(ctx.handle, _ptr(rho), N, ctypes.byref(params.c()), ctypes.byref(base),
+                             _ptr(u_scratch), ctypes.byref(best), ctypes.byref(ms), _stream(stream))
+    if st != MGFR_OK:
+        raise MgfrError(st, ctx.last_error())
+    if cache_path:
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        cache[key] = {k: getattr(best, k) for k in TUNED_FIELDS}
+        cache[key]["ms"] = ms.value
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return best, ms.value
