@@ -150,7 +150,7 @@ int mgfr_smooth(mgfr_ctx* ctx, const double* rho, double* u, int N, const mgfr_p
 /* The domain-grid solve (Sec. V.B, Sec. VI.A).
  * rho      device, N^3: code-unit density (mean 1 in the paper's units; negative values
  *          are allowed, non-finite ones are rejected with MGFR_ENONFINITE).
- * N        power of two, N >= opts->coarsest_n.
+ * N        power of two, opts->coarsest_n <= N <= 1024.
  * u        device, N^3: output; with MGFR_WARM_START also the starting field.
  * res_hist host, max_cycles + 1 doubles (may be NULL): rms(L) before the first cycle and
  *          after every cycle (mixed: after every FP64 outer iteration).

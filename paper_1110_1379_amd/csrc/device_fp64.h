@@ -12,6 +12,22 @@ struct OpVal {
     double L, dL;
 };
 
+// Curvature term S = A exp(-u/(n+1)).  For n = 1 it is A / sqrt(b) with b = exp(u) already
+// at hand: the hardware reciprocal square root refined by two Newton steps (each doubles
+// the correct bits), instead of a second double-precision exponential.
+__device__ __forceinline__ double curvature(const Grid& g, double ui, double bi)
+{
+    if (g.half_power) {
+        double y = __builtin_amdgcn_rsq(bi);
+        double e = fma(-bi * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+        e = fma(-bi * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+        return g.A * y;
+    }
+    return g.A * exp(-ui * g.inv_np1);
+}
+
 // L_i - f_i and dL_i/du_i from the cell value, its six neighbours and their b = exp(u).
 __device__ __forceinline__ OpVal cell_op_b(const Grid& g, double ui, double bi, const double (&un)[6],
                                            const double (&bn)[6], double f)
@@ -24,7 +40,7 @@ __device__ __forceinline__ OpVal cell_op_b(const Grid& g, double ui, double bi, 
         sb += bn[q];
         sbu = fma(bn[q], du, sbu);
     }
-    const double S = g.A * exp(-ui * g.inv_np1);
+    const double S = curvature(g, ui, bi);
     OpVal r;
     // sum_nb (b_nb + b_i)(u_nb - u_i) = sum b_nb du + b_i sum du
     r.L = g.C * fma(bi, su, sbu) + S - f;

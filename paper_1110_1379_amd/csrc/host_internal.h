@@ -162,6 +162,7 @@ inline mgfr::Grid make_grid(const Model& md, int n, double h, double max_step)
     g.C = md.ct * md.ct / (2.0 * h * h);
     g.A = md.A;
     g.inv_np1 = md.inv_np1;
+    g.half_power = md.inv_np1 == 0.5 ? 1 : 0;
     g.max_step = max_step;
     g.fscale = 1.0;
     g.sref = 0.0;

@@ -127,14 +127,15 @@ __global__ void __launch_bounds__(kBlock) k32_ngs_colour(Grid g, const float* __
 }
 
 // ---- fused red-black sweep (n >= 64), same scheme as the double-precision one ----------
-template <int TJ, int NT, bool CORR>
+// (three LDS plane buffers, one barrier per plane, red ring recomputed per tile)
+template <int TJ, int NT>
 __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict__ ub, const float* __restrict__ ein,
                                                 float* __restrict__ eout, const float* __restrict__ f,
                                                 FusedSweep32 a)
 {
     constexpr int LJ = TJ + 4, LK = kTK + 4, NL = LJ * LK;
     constexpr int NS = (NL + NT - 1) / NT;
-    __shared__ V32 lv[2][NL];
+    __shared__ V32 lv[3][NL];
     const Op32 o = op32(g);
 
     const int nb = gridDim.x;
@@ -146,8 +147,10 @@ __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict_
     const int ci = lid / a.ntj;
     const int i0 = ci * a.ti, j0 = tj * TJ, k0 = tk * kTK;
     const int lg = g.lg, m = g.n - 1;
+    const int last = i0 + a.ti + 1;
 
-    int col[NS], par[NS], fl[NS];
+    unsigned col[NS];
+    int par[NS], fl[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int c = threadIdx.x + s * NT;
@@ -157,63 +160,54 @@ __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict_
         if (c < NL) {
             const int jj = c / LK, kk = c - jj * LK;
             const int gj = (j0 - 2 + jj) & m, gk = (k0 - 2 + kk) & m;
-            col[s] = (gj << lg) | gk;
+            col[s] = (unsigned)((gj << lg) | gk);
             par[s] = (gj + gk) & 1;
             fl[s] = 1;
             if (jj >= 1 && jj <= LJ - 2 && kk >= 1 && kk <= LK - 2) fl[s] |= 2;
             if (jj >= 2 && jj <= LJ - 3 && kk >= 2 && kk <= LK - 3) fl[s] |= 4;
         }
     }
-    auto offset = [&](int p, int s) -> long long { return ((long long)(p & m) << (2 * lg)) + col[s]; };
-    auto load_e = [&](int p, int s) -> float {
-        float v = ein[offset(p, s)];
-        if (CORR) {
-            const int i = p & m, j = col[s] >> lg, k = col[s] & m;
-            const int lgc = lg - 1, mc = (1 << lgc) - 1;
-            const int I = i >> 1, J = j >> 1, K = k >> 1;
-            const int Ip = (I + ((i & 1) ? 1 : -1)) & mc, Jp = (J + ((j & 1) ? 1 : -1)) & mc,
-                      Kp = (K + ((k & 1) ? 1 : -1)) & mc;
-            auto E = [&](int x, int y, int z) { return a.ec[at(lgc, x, y, z)]; };
-            v += (27.0f / 64.0f) * E(I, J, K) + (9.0f / 64.0f) * (E(Ip, J, K) + E(I, Jp, K) + E(I, J, Kp)) +
-                 (3.0f / 64.0f) * (E(Ip, Jp, K) + E(Ip, J, Kp) + E(I, Jp, Kp)) + (1.0f / 64.0f) * E(Ip, Jp, Kp);
-        }
-        return v;
-    };
-    auto load_v = [&](int p, int s) -> V32 { return make_v(ub[offset(p, s)], load_e(p, s)); };
+    // element offsets fit in 32 bits (n <= 1024)
+    auto offset = [&](int p, int s) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + col[s]; };
+    auto buf = [&](int p) { return (p - i0 + 3) % 3; };
 
+    // planes p-2 .. p+1 as cell values, plane p+2 as raw loads in flight
     V32 vm2[NS], vm1[NS], v0[NS], vp1[NS];
     float fm1[NS], f0[NS], fp1[NS];
+    float ub2[NS], e2[NS], f2[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         vm2[s] = vm1[s] = v0[s] = vp1[s] = V32{0.f, 0.f, 0.f, 0.f};
         fm1[s] = f0[s] = fp1[s] = 0.0f;
+        ub2[s] = e2[s] = f2[s] = 0.0f;
         if (fl[s]) {
-            vm1[s] = load_v(i0 - 2, s);
-            v0[s] = load_v(i0 - 1, s);
-            vp1[s] = load_v(i0, s);
+            vm1[s] = make_v(ub[offset(i0 - 2, s)], ein[offset(i0 - 2, s)]);
+            v0[s] = make_v(ub[offset(i0 - 1, s)], ein[offset(i0 - 1, s)]);
+            vp1[s] = make_v(ub[offset(i0, s)], ein[offset(i0, s)]);
             fm1[s] = f[offset(i0 - 2, s)];
             f0[s] = f[offset(i0 - 1, s)];
             fp1[s] = f[offset(i0, s)];
+            ub2[s] = ub[offset(i0 + 1, s)];
+            e2[s] = ein[offset(i0 + 1, s)];
+            f2[s] = f[offset(i0 + 1, s)];
+            lv[buf(i0 - 1)][threadIdx.x + s * NT] = v0[s];
         }
     }
+    __syncthreads();
     for (int p = i0 - 1; p <= i0 + a.ti; ++p) {
-        const bool more = p + 2 <= i0 + a.ti + 1;
-        float ub2[NS], e2[NS], f2[NS];
+        // loads of plane p+3, two steps ahead of their use
+        const bool more3 = p + 3 <= last;
+        float ub3[NS], e3[NS], f3[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            ub2[s] = e2[s] = f2[s] = 0.0f;
-            if (more && fl[s]) {
-                ub2[s] = ub[offset(p + 2, s)];
-                e2[s] = load_e(p + 2, s);
-                f2[s] = f[offset(p + 2, s)];
+            ub3[s] = e3[s] = f3[s] = 0.0f;
+            if (more3 && fl[s]) {
+                ub3[s] = ub[offset(p + 3, s)];
+                e3[s] = ein[offset(p + 3, s)];
+                f3[s] = f[offset(p + 3, s)];
             }
         }
-        V32* LA = lv[p & 1];
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-            if (fl[s]) LA[threadIdx.x + s * NT] = v0[s];
-        __syncthreads();
+        V32* LA = lv[buf(p)];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int c = threadIdx.x + s * NT;
@@ -225,7 +219,7 @@ __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict_
             }
         }
         if (p - 1 >= i0) {
-            const V32* LB = lv[(p - 1) & 1];
+            const V32* LB = lv[buf(p - 1)];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const int c = threadIdx.x + s * NT;
@@ -239,18 +233,147 @@ __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict_
                 }
             }
         }
+        V32* LC = lv[buf(p + 1)];
+        const bool more2 = p + 2 <= last;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
+            if (fl[s]) LC[threadIdx.x + s * NT] = vp1[s];
             vm2[s] = vm1[s];
             vm1[s] = v0[s];
             fm1[s] = f0[s];
             v0[s] = vp1[s];
             f0[s] = fp1[s];
-            if (more && fl[s]) {
+            if (more2 && fl[s]) {
                 vp1[s] = make_v(ub2[s], e2[s]);
                 fp1[s] = f2[s];
             }
+            ub2[s] = ub3[s];
+            e2[s] = e3[s];
+            f2[s] = f3[s];
         }
+        __syncthreads();
+    }
+}
+
+// ---- streaming residual + restriction (n >= 64) ----------------------------------------
+// Per plane the tile's cell values (ub, e, B, M) plus a one-cell in-plane halo sit in LDS and
+// the i-neighbours in registers, so every cell's exponentials are evaluated once; the
+// residual N(e) - f of plane pairs is summed over 2x2x2 children into the coarse level.
+template <int TJ, int NT>
+__global__ void __launch_bounds__(NT) k32_resid_stream(Grid g, const float* __restrict__ ub, const float* __restrict__ e,
+                                                       const float* __restrict__ f, float* __restrict__ ec,
+                                                       float* __restrict__ ehat, float* __restrict__ fc, int ti,
+                                                       int ntj, int ntk)
+{
+    constexpr int LJ = TJ + 2, LK = kTK + 2, NL = LJ * LK;
+    constexpr int NS = (NL + NT - 1) / NT;
+    __shared__ V32 lv[2][NL];
+    __shared__ float re[TJ * kTK], rd[TJ * kTK];
+    const Op32 o = op32(g);
+    const int nb = gridDim.x;
+    int lid = blockIdx.x;
+    if ((nb & 7) == 0) lid = (lid & 7) * (nb >> 3) + (lid >> 3);
+    const int tk = lid % ntk;
+    lid /= ntk;
+    const int tj = lid % ntj;
+    const int ci = lid / ntj;
+    const int i0 = ci * ti, j0 = tj * TJ, k0 = tk * kTK;
+    const int lg = g.lg, m = g.n - 1;
+    const int last = i0 + ti;  // last plane read
+    unsigned col[NS];
+    int fl[NS], li[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int c = threadIdx.x + s * NT;
+        col[s] = 0;
+        fl[s] = li[s] = 0;
+        if (c < NL) {
+            const int jj = c / LK, kk = c - jj * LK;
+            col[s] = (unsigned)((((j0 - 1 + jj) & m) << lg) | ((k0 - 1 + kk) & m));
+            fl[s] = 1;
+            if (jj >= 1 && jj <= TJ && kk >= 1 && kk <= kTK) {
+                fl[s] |= 2;
+                li[s] = (jj - 1) * kTK + (kk - 1);
+            }
+        }
+    }
+    // element offsets fit in 32 bits (n <= 1024)
+    auto offset = [&](int p, int s) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + col[s]; };
+    // planes p-1, p, p+1 expanded in registers; raw (ub, e) of plane p+2 and f of plane p+1 in flight
+    V32 vm1[NS], v0[NS], vp1[NS];
+    float u2[NS], e2[NS], f0[NS], eprev[NS], dprev[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        vm1[s] = v0[s] = vp1[s] = V32{0.f, 0.f, 0.f, 0.f};
+        u2[s] = e2[s] = f0[s] = eprev[s] = dprev[s] = 0.0f;
+        if (fl[s] & 2) f0[s] = f[offset(i0, s)];
+        if (fl[s]) {
+            vm1[s] = make_v(ub[offset(i0 - 1, s)], e[offset(i0 - 1, s)]);
+            v0[s] = make_v(ub[offset(i0, s)], e[offset(i0, s)]);
+            vp1[s] = make_v(ub[offset(i0 + 1, s)], e[offset(i0 + 1, s)]);
+            u2[s] = ub[offset(i0 + 2, s)];
+            e2[s] = e[offset(i0 + 2, s)];
+            lv[0][threadIdx.x + s * NT] = v0[s];
+        }
+    }
+    __syncthreads();
+    for (int p = i0; p < i0 + ti; ++p) {
+        const bool more3 = p + 3 <= last, moref = p + 1 < last;
+        float u3[NS], e3[NS], f1[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            u3[s] = e3[s] = f1[s] = 0.0f;
+            if (fl[s] && more3) {
+                u3[s] = ub[offset(p + 3, s)];
+                e3[s] = e[offset(p + 3, s)];
+            }
+            if ((fl[s] & 2) && moref) f1[s] = f[offset(p + 1, s)];
+        }
+        const V32* LV = lv[(p - i0) & 1];
+        const bool second = (p - i0) & 1;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int c = threadIdx.x + s * NT;
+            if (fl[s] & 2) {
+                const V32 nbv[6] = {vm1[s], vp1[s], LV[c - LK], LV[c + LK], LV[c - 1], LV[c + 1]};
+                const float d = corr_op(o, v0[s], nbv, f0[s]).N;
+                if (second) {
+                    re[li[s]] = eprev[s] + v0[s].e;
+                    rd[li[s]] = dprev[s] + d;
+                } else {
+                    eprev[s] = v0[s].e;
+                    dprev[s] = d;
+                }
+            }
+        }
+        if (second) {
+            __syncthreads();
+            const int lgc = lg - 1;
+            for (int t = threadIdx.x; t < (TJ / 2) * (kTK / 2); t += NT) {
+                const int cj = t / (kTK / 2), ck = t - cj * (kTK / 2);
+                const int q = (2 * cj) * kTK + 2 * ck;
+                const float se = re[q] + re[q + 1] + re[q + kTK] + re[q + kTK + 1];
+                const float sd = rd[q] + rd[q + 1] + rd[q + kTK] + rd[q + kTK + 1];
+                const long long qc = at(lgc, (p & m) >> 1, (j0 >> 1) + cj, (k0 >> 1) + ck);
+                ec[qc] = 0.125f * se;
+                ehat[qc] = 0.125f * se;
+                fc[qc] = 0.125f * sd;
+            }
+        }
+        // stage plane p+1 into the other buffer and shift the registers
+        V32* NV = lv[(p + 1 - i0) & 1];
+        const bool more2 = p + 2 <= last;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (fl[s]) NV[threadIdx.x + s * NT] = vp1[s];
+            vm1[s] = v0[s];
+            v0[s] = vp1[s];
+            if (more2 && fl[s]) vp1[s] = make_v(u2[s], e2[s]);
+            u2[s] = u3[s];
+            e2[s] = e3[s];
+            f0[s] = f1[s];
+        }
+        __syncthreads();
     }
 }
 
@@ -319,25 +442,6 @@ __global__ void __launch_bounds__(kBlock) k32_restrict_mean(int lgc, const float
 #pragma unroll
             for (int z = 0; z < 2; ++z) s += fine[at(lg, 2 * I + x, 2 * J + y, 2 * K + z)];
     coarse[tc] = 0.125f * s;
-}
-
-__global__ void __launch_bounds__(kBlock) k32_diff(const float* __restrict__ ec, float* __restrict__ e, long long n)
-{
-    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (q < n) e[q] = ec[q] - e[q];
-}
-
-__global__ void __launch_bounds__(kBlock) k32_prolong_add(int lgc, float* __restrict__ ef, const float* __restrict__ d)
-{
-    const int lg = lgc + 1, n = 1 << lg, mc = (1 << lgc) - 1;
-    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= (1LL << (3 * lg))) return;
-    const int i = (int)(q >> (2 * lg)), j = (int)((q >> lg) & (n - 1)), k = (int)(q & (n - 1));
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const int Ip = (I + ((i & 1) ? 1 : -1)) & mc, Jp = (J + ((j & 1) ? 1 : -1)) & mc, Kp = (K + ((k & 1) ? 1 : -1)) & mc;
-    auto E = [&](int x, int y, int z) { return d[at(lgc, x, y, z)]; };
-    ef[q] += (27.0f / 64.0f) * E(I, J, K) + (9.0f / 64.0f) * (E(Ip, J, K) + E(I, Jp, K) + E(I, J, Kp)) +
-             (3.0f / 64.0f) * (E(Ip, Jp, K) + E(Ip, J, Kp) + E(I, Jp, Kp)) + (1.0f / 64.0f) * E(Ip, Jp, Kp);
 }
 
 __global__ void __launch_bounds__(kBlock) k32_fill(float* __restrict__ x, float v, long long n)
@@ -429,26 +533,32 @@ hipError_t ngs_sweep32(const Grid& g, const float* ub, float* e, const float* f,
 }
 
 hipError_t ngs_sweep32_fused(const Grid& g, const float* ub, const float* ein, float* eout, const float* f,
-                             const float* ec, int ti, hipStream_t s)
+                             int ti, hipStream_t s)
 {
-    if (g.n < kTK || ein == eout || ti < 1 || ti > g.n || (g.n % ti) != 0) return hipErrorInvalidValue;
+    if (g.n < kTK || g.n > 1024 || ein == eout || ti < 1 || ti > g.n || (g.n % ti) != 0) return hipErrorInvalidValue;
     constexpr int TJ = 16, NT = 512;
     FusedSweep32 a{};
     a.ti = ti;
-    a.ec = ec;
     a.ntj = g.n / TJ;
     a.ntk = g.n / kTK;
     const unsigned nb = (unsigned)((g.n / ti) * a.ntj * a.ntk);
-    if (ec)
-        hipLaunchKernelGGL((k32_fused<TJ, NT, true>), dim3(nb), dim3(NT), 0, s, g, ub, ein, eout, f, a);
-    else
-        hipLaunchKernelGGL((k32_fused<TJ, NT, false>), dim3(nb), dim3(NT), 0, s, g, ub, ein, eout, f, a);
+    hipLaunchKernelGGL((k32_fused<TJ, NT>), dim3(nb), dim3(NT), 0, s, g, ub, ein, eout, f, a);
     return hipGetLastError();
 }
 
 hipError_t resid_restrict32(const Grid& g, const float* ub, const float* e, const float* f, float* ec,
                             float* ehat, float* fc, hipStream_t s)
 {
+    if (g.n >= kTK) {
+        constexpr int TJ = 8, NT = 256;
+        const int ntj = g.n / TJ, ntk = g.n / kTK;
+        int ti = 8;
+        while (ti < g.n && (long long)ntj * ntk * (g.n / ti) > 8192) ti *= 2;
+        const unsigned nb = (unsigned)((g.n / ti) * ntj * ntk);
+        hipLaunchKernelGGL((k32_resid_stream<TJ, NT>), dim3(nb), dim3(NT), 0, s, g, ub, e, f, ec, ehat, fc, ti, ntj,
+                           ntk);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k32_resid_restrict, dim3(blocks_for(cells(g) / 8)), dim3(kBlock), 0, s, g, ub, e, f, ec,
                        ehat, fc);
     return hipGetLastError();
@@ -463,19 +573,6 @@ hipError_t fas_rhs32(const Grid& gc, const float* ubc, const float* ehat, float*
 hipError_t restrict_mean32(const Grid& gc, const float* fine, float* coarse, hipStream_t s)
 {
     hipLaunchKernelGGL(k32_restrict_mean, dim3(blocks_for(cells(gc))), dim3(kBlock), 0, s, gc.lg, fine, coarse);
-    return hipGetLastError();
-}
-
-hipError_t coarse_difference32(const Grid& gc, const float* ec, float* ehat_to_d, hipStream_t s)
-{
-    const long long n = cells(gc);
-    hipLaunchKernelGGL(k32_diff, dim3(blocks_for(n)), dim3(kBlock), 0, s, ec, ehat_to_d, n);
-    return hipGetLastError();
-}
-
-hipError_t prolong_add32(const Grid& gc, float* ef, const float* d, hipStream_t s)
-{
-    hipLaunchKernelGGL(k32_prolong_add, dim3(blocks_for(cells(gc) * 8)), dim3(kBlock), 0, s, gc.lg, ef, d);
     return hipGetLastError();
 }
 

@@ -97,24 +97,6 @@ __global__ void __launch_bounds__(kBlock) k_fas_rhs(Grid g, const double* __rest
     f[q] = cell_op(g, uhat[q], un, 0.0).L - f[q];
 }
 
-// uf += P(e): one thread per fine cell; gc describes the coarse level.
-__global__ void __launch_bounds__(kBlock) k_prolong_add(Grid gc, double* __restrict__ uf,
-                                                        const double* __restrict__ e)
-{
-    const int lg = gc.lg + 1, n = gc.n << 1, mc = gc.n - 1;
-    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= (1LL << (3 * lg))) return;
-    const int i = (int)(q >> (2 * lg)), j = (int)((q >> lg) & (n - 1)), k = (int)(q & (n - 1));
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const int Ip = (I + ((i & 1) ? 1 : -1)) & mc;
-    const int Jp = (J + ((j & 1) ? 1 : -1)) & mc;
-    const int Kp = (K + ((k & 1) ? 1 : -1)) & mc;
-    auto E = [&](int a, int b, int c) { return e[at(gc, a, b, c)]; };
-    const double p = (27.0 / 64.0) * E(I, J, K) + (9.0 / 64.0) * (E(Ip, J, K) + E(I, Jp, K) + E(I, J, Kp)) +
-                     (3.0 / 64.0) * (E(Ip, Jp, K) + E(Ip, J, Kp) + E(I, Jp, Kp)) + (1.0 / 64.0) * E(Ip, Jp, Kp);
-    uf[q] += p;
-}
-
 // Deterministic block reductions over kBlock threads (fixed tree order).
 // block_sum_max: a <- sum of a, b <- max of b (NaN propagates).  block_sum2: both summed.
 template <bool SecondIsMax>
@@ -360,12 +342,6 @@ hipError_t resid_restrict(const Grid& g, const double* u, const double* src, dou
 hipError_t fas_rhs(const Grid& gc, const double* uhat, double* f, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fas_rhs, dim3(blocks_for(cells(gc))), dim3(kBlock), 0, s, gc, uhat, f);
-    return hipGetLastError();
-}
-
-hipError_t prolong_add(const Grid& gc, double* uf, const double* e, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_prolong_add, dim3(blocks_for(cells(gc) * 8)), dim3(kBlock), 0, s, gc, uf, e);
     return hipGetLastError();
 }
 

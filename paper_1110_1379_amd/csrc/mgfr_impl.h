@@ -17,6 +17,7 @@ struct Grid {
     double C;         // c~^2 / (2 h^2)
     double A;         // (1/3) Om a^4 (n a^2 xi)^(1/(n+1))
     double inv_np1;   // 1 / (n_HS + 1)
+    int half_power;   // 1 when n_HS = 1: exp(-u/2) is taken as 1/sqrt(exp(u))
     double max_step;  // > 0: bound on |Newton step|
     double fscale, sref, fshift;
 };
@@ -26,7 +27,6 @@ inline long long cells(const Grid& g) { return 1LL << (3 * g.lg); }
 // Launch geometry of the single-precision fused sweep (kernels_fp32.hip).
 struct FusedSweep32 {
     int ti, ntj, ntk;
-    const float* ec;   // coarse correction to prolongate first, or null
 };
 
 // Outputs of the streaming residual (resid_fp64.hip); null pointers switch parts off.
@@ -43,7 +43,6 @@ struct ResidStream {
 struct FusedSweep {
     int ti;            // planes per workgroup chunk
     int ntj, ntk;      // tiles along j and k (set by the launcher)
-    const double* e;   // coarse correction e = u^H - R u^h to prolongate first, or null
 };
 
 // ---- batched units (batch_fp64.hip) ------------------------------------------------------
@@ -107,8 +106,10 @@ hipError_t resid_restrict(const Grid& g, const double* u, const double* src, dou
 // FAS right-hand side on a coarse level: f = L^H(uhat) - f (f holds R d on entry).
 hipError_t fas_rhs(const Grid& gc, const double* uhat, double* f, hipStream_t s);
 
-// uf += P(e), cell-centred trilinear 27/9/3/1 over 64, periodic; gc is the coarse level.
-hipError_t prolong_add(const Grid& gc, double* uf, const double* e, hipStream_t s);
+// Coarse-grid correction uf += P(uc - uhat), cell-centred trilinear 27/9/3/1 over 64,
+// periodic; gc is the coarse level, 2 <= gc.n <= 512 (prolong.hip).
+hipError_t prolong_correct(const Grid& gc, double* uf, const double* uc, const double* uhat, hipStream_t s);
+hipError_t prolong_correct32(const Grid& gc, float* ef, const float* ec, const float* ehat, hipStream_t s);
 
 // Coarsest level in one workgroup: sweeps until rms(L - f) <= rtol x initial or `cap`
 // sweeps (rtol = 0: exactly cap sweeps).  n <= 8.  Adds the sweeps done to *sweeps_done
@@ -136,13 +137,9 @@ hipError_t fill(double* x, double v, long long n, hipStream_t s);
 int fused_sweep_min_n();
 int fused_sweep_planes(int n);
 
-// One red-black sweep from uin into uout (distinct arrays); with e != null, uin + P(e)
-// is swept (the coarse-grid correction fused into the sweep).
-hipError_t ngs_sweep_fused(const Grid& g, const double* uin, double* uout, const double* src,
-                           const double* e, int ti, hipStream_t s);
-
-// uhat_to_e <- uc - uhat_to_e on a coarse level.
-hipError_t coarse_difference(const Grid& gc, const double* uc, double* uhat_to_e, hipStream_t s);
+// One red-black sweep from uin into uout (distinct arrays).
+hipError_t ngs_sweep_fused(const Grid& g, const double* uin, double* uout, const double* src, int ti,
+                           hipStream_t s);
 
 // ---- streaming residual (resid_fp64.hip), n >= 64 --------------------------------------
 int resid_stream_planes(int n);
@@ -162,13 +159,11 @@ hipError_t fold_partials(const double* partial, int nb, double* out, hipStream_t
 // ---- single-precision correction multigrid (kernels_fp32.hip) --------------------------
 hipError_t ngs_sweep32(const Grid& g, const float* ub, float* e, const float* f, hipStream_t s);
 hipError_t ngs_sweep32_fused(const Grid& g, const float* ub, const float* ein, float* eout, const float* f,
-                             const float* ec, int ti, hipStream_t s);
+                             int ti, hipStream_t s);
 hipError_t resid_restrict32(const Grid& g, const float* ub, const float* e, const float* f, float* ec,
                             float* ehat, float* fc, hipStream_t s);
 hipError_t fas_rhs32(const Grid& gc, const float* ubc, const float* ehat, float* f, hipStream_t s);
 hipError_t restrict_mean32(const Grid& gc, const float* fine, float* coarse, hipStream_t s);
-hipError_t coarse_difference32(const Grid& gc, const float* ec, float* ehat_to_d, hipStream_t s);
-hipError_t prolong_add32(const Grid& gc, float* ef, const float* d, hipStream_t s);
 hipError_t coarsest_solve32(const Grid& g, const float* ub, float* e, const float* f, int cap, double rtol,
                             hipStream_t s);
 hipError_t fill32(float* x, float v, long long n, hipStream_t s);

@@ -23,8 +23,8 @@ __global__ void __launch_bounds__(NT) k_resid_stream(Grid g, const double* __res
 {
     constexpr int LJ = TJ + 2, LK = kTK + 2, NL = LJ * LK;
     constexpr int NS = (NL + NT - 1) / NT;
-    __shared__ double lu[NL];
-    __shared__ double lb[NL];
+    __shared__ double lu[2][NL];
+    __shared__ double lb[2][NL];
     __shared__ double ru[RESTRICT ? TJ * kTK : 1];
     __shared__ double rd[RESTRICT ? TJ * kTK : 1];
     __shared__ double red_s[NT], red_m[NT];
@@ -38,8 +38,10 @@ __global__ void __launch_bounds__(NT) k_resid_stream(Grid g, const double* __res
     const int ci = lid / a.ntj;
     const int i0 = ci * a.ti, j0 = tj * TJ, k0 = tk * kTK;
     const int lg = g.lg, m = g.n - 1;
+    const int last = i0 + a.ti;  // last plane read
 
-    int col[NS], fl[NS], li[NS];
+    unsigned col[NS];
+    int fl[NS], li[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int c = threadIdx.x + s * NT;
@@ -48,7 +50,7 @@ __global__ void __launch_bounds__(NT) k_resid_stream(Grid g, const double* __res
         li[s] = 0;
         if (c < NL) {
             const int jj = c / LK, kk = c - jj * LK;
-            col[s] = (((j0 - 1 + jj) & m) << lg) | ((k0 - 1 + kk) & m);
+            col[s] = (unsigned)((((j0 - 1 + jj) & m) << lg) | ((k0 - 1 + kk) & m));
             fl[s] = 1;
             if (jj >= 1 && jj <= TJ && kk >= 1 && kk <= kTK) {
                 fl[s] |= 2;
@@ -56,57 +58,68 @@ __global__ void __launch_bounds__(NT) k_resid_stream(Grid g, const double* __res
             }
         }
     }
-    auto offset = [&](int p, int s) -> long long { return ((long long)(p & m) << (2 * lg)) + col[s]; };
+    // element offsets fit in 32 bits (n <= 1024)
+    auto offset = [&](int p, int s) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + col[s]; };
     auto load_u = [&](int p, int s) -> double {
         double v = uin[offset(p, s)];
         if (UPDATE) v += (double)a.e32[offset(p, s)];
         return v;
     };
+    // the correction of a prefetched plane is kept apart and added when the plane is used,
+    // so that issuing the loads does not wait for them
+    auto load_e = [&](int p, int s) -> float { return UPDATE ? a.e32[offset(p, s)] : 0.0f; };
 
-    double um1[NS], u0[NS], up1[NS], bm1[NS], b0[NS], bp1[NS];
-    double uprev[NS], dprev[NS];
+    // u of planes p-1, p, p+1 in registers while planes p+2 and p+3 (and f of p+1) are in flight
+    double um1[NS], u0[NS], up1[NS], bm1[NS], b0[NS], bp1[NS], un2[NS];
+    float en2[NS];
+    double uprev[NS], dprev[NS], f0[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        um1[s] = u0[s] = up1[s] = bm1[s] = b0[s] = bp1[s] = 0.0;
+        um1[s] = u0[s] = up1[s] = bm1[s] = b0[s] = bp1[s] = un2[s] = f0[s] = 0.0;
+        en2[s] = 0.0f;
         uprev[s] = dprev[s] = 0.0;
+        if (fl[s] & 2) f0[s] = src[offset(i0, s)];
         if (fl[s]) {
             um1[s] = load_u(i0 - 1, s);
             u0[s] = load_u(i0, s);
+            up1[s] = load_u(i0 + 1, s);
+            un2[s] = uin[offset(i0 + 2, s)];
+            en2[s] = load_e(i0 + 2, s);
             bm1[s] = exp(um1[s]);
             b0[s] = exp(u0[s]);
+            bp1[s] = exp(up1[s]);
+            lu[0][threadIdx.x + s * NT] = u0[s];
+            lb[0][threadIdx.x + s * NT] = b0[s];
         }
     }
+    __syncthreads();
     double acc = 0.0, mx = 0.0;
     for (int p = i0; p < i0 + a.ti; ++p) {
-        double f0[NS];
+        const bool more3 = p + 3 <= last, moref = p + 1 < last;
+        double un3[NS], f1[NS];
+        float en3[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            f0[s] = 0.0;
-            if (fl[s]) {
-                up1[s] = load_u(p + 1, s);
-                if (fl[s] & 2) f0[s] = dev::rhs_value(g, src[offset(p, s)]);
+            un3[s] = 0.0;
+            en3[s] = 0.0f;
+            f1[s] = 0.0;
+            if (fl[s] && more3) {
+                un3[s] = uin[offset(p + 3, s)];
+                en3[s] = load_e(p + 3, s);
             }
+            if ((fl[s] & 2) && moref) f1[s] = src[offset(p + 1, s)];
         }
-        __syncthreads();  // previous plane fully consumed
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int c = threadIdx.x + s * NT;
-            if (fl[s]) {
-                lu[c] = u0[s];
-                lb[c] = b0[s];
-                bp1[s] = exp(up1[s]);
-            }
-        }
-        __syncthreads();
+        const double* LU = lu[(p - i0) & 1];
+        const double* LB = lb[(p - i0) & 1];
         const bool second = RESTRICT && ((p - i0) & 1);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int c = threadIdx.x + s * NT;
             if (fl[s] & 2) {
-                const double un[6] = {um1[s], up1[s], lu[c - LK], lu[c + LK], lu[c - 1], lu[c + 1]};
-                const double bn[6] = {bm1[s], bp1[s], lb[c - LK], lb[c + LK], lb[c - 1], lb[c + 1]};
-                const double d = dev::cell_op_b(g, u0[s], b0[s], un, bn, f0[s]).L;
-                const long long q = offset(p, s);
+                const double un[6] = {um1[s], up1[s], LU[c - LK], LU[c + LK], LU[c - 1], LU[c + 1]};
+                const double bn[6] = {bm1[s], bp1[s], LB[c - LK], LB[c + LK], LB[c - 1], LB[c + 1]};
+                const double d = dev::cell_op_b(g, u0[s], b0[s], un, bn, dev::rhs_value(g, f0[s])).L;
+                const unsigned q = offset(p, s);
                 if (NORM) {
                     acc += d * d;
                     const double ad = fabs(d);
@@ -142,16 +155,31 @@ __global__ void __launch_bounds__(NT) k_resid_stream(Grid g, const double* __res
                 a.fc[qc] = 0.125 * sd;
             }
         }
+        // stage plane p+1 into the other buffer and shift the registers
+        double* NU = lu[(p + 1 - i0) & 1];
+        double* NB = lb[(p + 1 - i0) & 1];
+        const bool more2 = p + 2 <= last;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
+            if (fl[s]) {
+                NU[threadIdx.x + s * NT] = up1[s];
+                NB[threadIdx.x + s * NT] = bp1[s];
+            }
             um1[s] = u0[s];
             bm1[s] = b0[s];
             u0[s] = up1[s];
             b0[s] = bp1[s];
+            if (more2 && fl[s]) {
+                up1[s] = UPDATE ? un2[s] + (double)en2[s] : un2[s];
+                bp1[s] = exp(up1[s]);
+            }
+            un2[s] = un3[s];
+            en2[s] = en3[s];
+            f0[s] = f1[s];
         }
+        __syncthreads();
     }
     if (NORM) {
-        __syncthreads();
         const int t = threadIdx.x;
         red_s[t] = acc;
         red_m[t] = mx;
@@ -199,7 +227,7 @@ long long resid_stream_blocks(int n) { return (long long)(n / resid_stream_plane
 
 hipError_t resid_stream(const Grid& g, const double* uin, const double* src, ResidStream a, hipStream_t s)
 {
-    if (g.n < kTK || a.ti < 2 || (a.ti & 1) || g.n % a.ti) return hipErrorInvalidValue;
+    if (g.n < kTK || g.n > 1024 || a.ti < 2 || (a.ti & 1) || g.n % a.ti) return hipErrorInvalidValue;
     const bool norm = a.partial != nullptr, restr = a.uc != nullptr, upd = a.e32 != nullptr,
                cast = a.r32 != nullptr;
     if (upd && (a.uout == nullptr || a.uout == uin)) return hipErrorInvalidValue;

@@ -32,9 +32,8 @@ struct Cycle {
     const double* finest_src = nullptr;
 
     // One smoother sweep on level m, from *cur into the other buffer for the fused kernel
-    // (cur is updated) or in place; e != null fuses the coarse correction into it.
-    // Finest-level sweeps are timed under MGFR_PROFILE.
-    int sweep(size_t m, const double* src, double*& cur, const double* e)
+    // (cur is updated) or in place.  Finest-level sweeps are timed under MGFR_PROFILE.
+    int sweep(size_t m, const double* src, double*& cur)
     {
         Level& L = c->lv[m];
         const bool fused = L.alt != nullptr && !o_simple;
@@ -51,11 +50,10 @@ struct Cycle {
         }
         if (fused) {
             double* out = cur == L.u ? L.alt : L.u;
-            MGFR_TRY(hip_check(c, mgfr::ngs_sweep_fused(L.g, cur, out, src, e, planes_for(o, m, L.g.n), s),
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep_fused(L.g, cur, out, src, planes_for(o, m, L.g.n), s),
                                "ngs_sweep_fused"));
             cur = out;
         } else {
-            if (e) MGFR_TRY(hip_check(c, mgfr::prolong_add(c->lv[m + 1].g, cur, e, s), "prolong_add"));
             MGFR_TRY(hip_check(c, mgfr::ngs_sweep(L.g, cur, src, s), "ngs_sweep"));
         }
         if (timed) {
@@ -93,7 +91,7 @@ struct Cycle {
                              "coarsest_solve");
         }
         double* cur = L.u;
-        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m, src, cur, nullptr));
+        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m, src, cur));
         Level& H = c->lv[m + 1];
         if (L.alt && !o_simple) {
             mgfr::ResidStream a{};
@@ -107,14 +105,9 @@ struct Cycle {
         }
         MGFR_TRY(hip_check(c, mgfr::fas_rhs(H.g, H.uhat, H.f, s), "fas_rhs"));
         MGFR_TRY(vcycle(m + 1));
-        // e = u^H - R u^h (in H.uhat); u^h += P(e), inside the first post-smoothing sweep
-        MGFR_TRY(hip_check(c, mgfr::coarse_difference(H.g, H.u, H.uhat, s), "coarse_difference"));
-        if (o->post > 0) {
-            MGFR_TRY(sweep(m, src, cur, H.uhat));
-            for (int k = 1; k < o->post; ++k) MGFR_TRY(sweep(m, src, cur, nullptr));
-        } else {
-            MGFR_TRY(hip_check(c, mgfr::prolong_add(H.g, cur, H.uhat, s), "prolong_add"));
-        }
+        // u^h += P(u^H - R u^h)
+        MGFR_TRY(hip_check(c, mgfr::prolong_correct(H.g, cur, H.u, H.uhat, s), "prolong_correct"));
+        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep(m, src, cur));
         if (cur != L.u)
             MGFR_TRY(hip_check(c, hipMemcpyAsync(L.u, cur, sizeof(double) * mgfr::cells(L.g), hipMemcpyDeviceToDevice, s),
                                "hipMemcpyAsync"));
@@ -130,7 +123,7 @@ struct Cycle32 {
     const mgfr_opts* o;
     hipStream_t s;
 
-    int sweep(size_t m, float*& cur, const float* ec)
+    int sweep(size_t m, float*& cur)
     {
         Level32& L = c->lv32[m];
         const bool timed = m == 0 && (o->flags & MGFR_PROFILE);
@@ -146,11 +139,10 @@ struct Cycle32 {
         }
         if (L.ealt) {
             float* out = cur == L.e ? L.ealt : L.e;
-            MGFR_TRY(hip_check(c, mgfr::ngs_sweep32_fused(L.g, L.ub, cur, out, L.f, ec, planes_for(o, m, L.g.n), s),
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep32_fused(L.g, L.ub, cur, out, L.f, planes_for(o, m, L.g.n), s),
                                "ngs_sweep32_fused"));
             cur = out;
         } else {
-            if (ec) MGFR_TRY(hip_check(c, mgfr::prolong_add32(c->lv32[m + 1].g, cur, ec, s), "prolong_add32"));
             MGFR_TRY(hip_check(c, mgfr::ngs_sweep32(L.g, L.ub, cur, L.f, s), "ngs_sweep32"));
         }
         if (timed) {
@@ -171,18 +163,14 @@ struct Cycle32 {
             return hip_check(c, mgfr::coarsest_solve32(L.g, L.ub, L.e, L.f, o->coarsest_sweeps, o->coarsest_rtol, s),
                              "coarsest_solve32");
         float* cur = L.e;
-        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m, cur, nullptr));
+        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m, cur));
         Level32& H = c->lv32[m + 1];
         MGFR_TRY(hip_check(c, mgfr::resid_restrict32(L.g, L.ub, cur, L.f, H.e, H.ehat, H.f, s), "resid_restrict32"));
         MGFR_TRY(hip_check(c, mgfr::fas_rhs32(H.g, H.ub, H.ehat, H.f, s), "fas_rhs32"));
         MGFR_TRY(vcycle(m + 1));
-        MGFR_TRY(hip_check(c, mgfr::coarse_difference32(H.g, H.e, H.ehat, s), "coarse_difference32"));
-        if (o->post > 0) {
-            MGFR_TRY(sweep(m, cur, H.ehat));
-            for (int k = 1; k < o->post; ++k) MGFR_TRY(sweep(m, cur, nullptr));
-        } else {
-            MGFR_TRY(hip_check(c, mgfr::prolong_add32(H.g, cur, H.ehat, s), "prolong_add32"));
-        }
+        // e^h += P(e^H - R e^h)
+        MGFR_TRY(hip_check(c, mgfr::prolong_correct32(H.g, cur, H.e, H.ehat, s), "prolong_correct32"));
+        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep(m, cur));
         if (cur != L.e)
             MGFR_TRY(hip_check(c, hipMemcpyAsync(L.e, cur, sizeof(float) * mgfr::cells(L.g), hipMemcpyDeviceToDevice, s),
                                "hipMemcpyAsync"));
@@ -333,7 +321,7 @@ int mgfr_smooth(mgfr_ctx* c, const double* rho, double* u, int N, const mgfr_par
     MGFR_TRY(check_opts(c, o));
     Model md;
     if (derive_model(params, &md) != MGFR_OK) return c->fail(MGFR_EINVAL, "invalid model parameters");
-    if (!rho || !u || !is_pow2(N) || N < 2 || N > 2048 || nsweeps < 0 || variant < 0 || variant > 2)
+    if (!rho || !u || !is_pow2(N) || N < 2 || N > 1024 || nsweeps < 0 || variant < 0 || variant > 2)
         return c->fail(MGFR_EINVAL, "invalid arguments");
     if (variant == 2 && N < mgfr::fused_sweep_min_n())
         return c->fail(MGFR_EINVAL, "the fused sweep needs N >= %d", mgfr::fused_sweep_min_n());
@@ -349,7 +337,7 @@ int mgfr_smooth(mgfr_ctx* c, const double* rho, double* u, int N, const mgfr_par
     cyc.o_simple = variant == 1;
     c->ev_used = 0;
     double* cur = u;
-    for (int k = 0; k < nsweeps; ++k) MGFR_TRY(cyc.sweep(0, rho, cur, nullptr));
+    for (int k = 0; k < nsweeps; ++k) MGFR_TRY(cyc.sweep(0, rho, cur));
     if (cur != u)
         MGFR_TRY(hip_check(c, hipMemcpyAsync(u, cur, sizeof(double) * mgfr::cells(L0.g), hipMemcpyDeviceToDevice, s),
                            "hipMemcpyAsync"));
@@ -368,8 +356,8 @@ int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params
     Model md;
     if (derive_model(params, &md) != MGFR_OK) return c->fail(MGFR_EINVAL, "invalid model parameters");
     if (!rho || !u) return c->fail(MGFR_EINVAL, "rho or u is NULL");
-    if (!is_pow2(N) || N < o->coarsest_n || N > 2048)
-        return c->fail(MGFR_EINVAL, "N=%d must be a power of two in [coarsest_n, 2048]", N);
+    if (!is_pow2(N) || N < o->coarsest_n || N > 1024)
+        return c->fail(MGFR_EINVAL, "N=%d must be a power of two in [coarsest_n, 1024]", N);
     MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
     hipStream_t s = (hipStream_t)stream;
     MGFR_TRY(ensure_scratch(c));
