@@ -120,11 +120,11 @@ def bench_domain(args):
     rho_d = torch.from_numpy(make_density(args.workload, N)).to("cuda:0")
     params = mgfr.Params(box_mpc_h=box, fr0_abs=fr0)
     ctx = mgfr.Context(0)
-    runs = {}
+    runs, fields = {}, {}
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     for p in precs:
         code = mgfr.MGFR_MIXED if p == "mixed" else mgfr.MGFR_FP64
-        runs[p], _ = time_domain(mgfr, ctx, rho_d, params, code, args.tol, args.steps, args.warmup)
+        runs[p], fields[p] = time_domain(mgfr, ctx, rho_d, params, code, args.tol, args.steps, args.warmup)
     head = runs["mixed"] if "mixed" in runs else runs["fp64"]
     headp = "mixed" if "mixed" in runs else "fp64"
     sm = head["smoother"]
@@ -160,6 +160,14 @@ def bench_domain(args):
         out[p] = r
     if "fp64" in runs and "mixed" in runs:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
+        # both solves stop at the same residual; their fields differ by the error the mixed
+        # solver adds (measured here, outside the timed region)
+        d = (fields["mixed"] - fields["fp64"]).abs()
+        ref = fields["fp64"].abs().max().item()
+        out["field_error_mixed_vs_fp64"] = {
+            "max_abs": d.max().item(), "rms_abs": d.square().mean().sqrt().item(),
+            "max_rel": d.max().item() / ref if ref > 0 else None}
+        del d
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.tol)

@@ -13,6 +13,8 @@
 // red-black Newton-Gauss-Seidel on N (Sec. V.B.1 applied to the correction equation).
 #include "mgfr_impl.h"
 
+#include <type_traits>
+
 namespace mgfr {
 namespace {
 
@@ -29,12 +31,13 @@ __device__ __forceinline__ Op32 op32(const Grid& g)
 }
 
 // expm1 in single precision: Taylor series to x^6 for |x| < 1/8 (truncation < 1e-10
-// relative), exp(x) - 1 above.
+// relative), exp(x) - 1 above.  Corrections are small once the outer loop has started to
+// converge, so the exponential is a branch that whole wavefronts skip.
 __device__ __forceinline__ float em1f(float x)
 {
-    if (fabsf(x) < 0.125f)
-        return x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f + x * (1.0f / 720.0f))))));
-    return __expf(x) - 1.0f;
+    float r = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f + x * (1.0f / 720.0f))))));
+    if (__builtin_expect(!(fabsf(x) < 0.125f), 0)) r = __expf(x) - 1.0f;
+    return r;
 }
 
 // Per-cell values a neighbour needs: base, correction, B = b e^e, M = b (e^e - 1).
@@ -57,28 +60,33 @@ struct Res32 {
     float N, dN;
 };
 
-// N_i - f_i and dN_i/de_i.
+// N_i - f_i and dN_i/de_i.  The flux sum (M_nb + M_i) du + (B_nb + B_i) de is split into
+// the neighbour parts and M_i sum(du) + B_i sum(de).
 __device__ __forceinline__ Res32 corr_op(const Op32& o, const V32& c, const V32 (&nb)[6], float f)
 {
-    float t1 = 0.0f, t2 = 0.0f, sB = 0.0f, sd = 0.0f;
+    float t1 = 0.0f, t2 = 0.0f, su = 0.0f, se = 0.0f, sB = 0.0f;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         const float du = nb[q].ub - c.ub, de = nb[q].e - c.e;
-        t1 = fmaf(nb[q].M + c.M, du, t1);
-        t2 = fmaf(nb[q].B + c.B, de, t2);
+        t1 = fmaf(nb[q].M, du, t1);
+        t2 = fmaf(nb[q].B, de, t2);
+        su += du;
+        se += de;
         sB += nb[q].B;
-        sd += du + de;
     }
     const float S = o.A * __expf(-c.ub * o.inv_np1);
     const float x = em1f(-c.e * o.inv_np1);
     Res32 r;
-    r.N = o.C * (t1 + t2) + S * x - f;
-    r.dN = o.C * (c.B * sd - sB - 6.0f * c.B) - S * o.inv_np1 * (1.0f + x);
+    r.N = o.C * (fmaf(c.M, su, t1) + fmaf(c.B, se, t2)) + S * x - f;
+    r.dN = o.C * (c.B * (su + se) - sB - 6.0f * c.B) - S * o.inv_np1 * (1.0f + x);
     return r;
 }
 
-__device__ __forceinline__ float bounded32(float step, float ms)
+// Newton step -N/dN through the hardware reciprocal (about 1 ulp), bounded to [-ms, ms]
+// when ms > 0; a NaN step stays NaN.
+__device__ __forceinline__ float newton32(const Res32& r, float ms)
 {
+    float step = -r.N * __builtin_amdgcn_rcpf(r.dN);
     if (ms > 0.0f) {
         if (step > ms) step = ms;
         if (step < -ms) step = -ms;
@@ -123,21 +131,31 @@ __global__ void __launch_bounds__(kBlock) k32_ngs_colour(Grid g, const float* __
     for (int v = 0; v < 6; ++v) nb[v] = make_v(ub[qn[v]], e[qn[v]]);
     const V32 c = make_v(ub[q], e[q]);
     const Res32 r = corr_op(o, c, nb, f[q]);
-    e[q] = c.e + bounded32(-r.N / r.dN, o.max_step);
+    e[q] = c.e + newton32(r, o.max_step);
 }
 
 // ---- fused red-black sweep (n >= 64), same scheme as the double-precision one ----------
-// (three LDS plane buffers, one barrier per plane, red ring recomputed per tile)
+// Three LDS plane buffers, one barrier per plane, the red ring recomputed per tile.  A thread
+// owns a pair of k-adjacent columns: at every plane step exactly one column of each pair
+// holds the cells to update (red on plane p, black on plane p-1), and the two swap at the
+// next step, so with the step loop unrolled by two every lane updates a cell at every step.
+struct Col32 {
+    V32 v[4];                 // plane q in v[(q - i0 + 3) & 3]: planes p-2 .. p+1 at step p
+    float f[4];               // right-hand side, same slots (planes p-1 .. p+1 used)
+    float rub[2], re[2], rf[2];  // raw loads of planes p+2 and p+3, plane q in [(q - i0) & 1]
+    unsigned col;             // (j,k) offset within a plane
+    int c, fl;                // LDS cell; 1 loaded, 2 red range (tile + ring), 4 tile
+};
+
 template <int TJ, int NT>
 __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict__ ub, const float* __restrict__ ein,
                                                 float* __restrict__ eout, const float* __restrict__ f,
                                                 FusedSweep32 a)
 {
-    constexpr int LJ = TJ + 4, LK = kTK + 4, NL = LJ * LK;
-    constexpr int NS = (NL + NT - 1) / NT;
+    constexpr int LJ = TJ + 4, LK = kTK + 4, NL = LJ * LK, NP = NL / 2;
+    static_assert(NP <= NT, "one column pair per thread");
     __shared__ V32 lv[3][NL];
     const Op32 o = op32(g);
-
     const int nb = gridDim.x;
     int lid = blockIdx.x;
     if ((nb & 7) == 0) lid = (lid & 7) * (nb >> 3) + (lid >> 3);
@@ -147,111 +165,114 @@ __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict_
     const int ci = lid / a.ntj;
     const int i0 = ci * a.ti, j0 = tj * TJ, k0 = tk * kTK;
     const int lg = g.lg, m = g.n - 1;
-    const int last = i0 + a.ti + 1;
+    const int last = i0 + a.ti + 1;  // last plane read
 
-    unsigned col[NS];
-    int par[NS], fl[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int c = threadIdx.x + s * NT;
-        col[s] = 0;
-        par[s] = 0;
-        fl[s] = 0;
-        if (c < NL) {
-            const int jj = c / LK, kk = c - jj * LK;
-            const int gj = (j0 - 2 + jj) & m, gk = (k0 - 2 + kk) & m;
-            col[s] = (unsigned)((gj << lg) | gk);
-            par[s] = (gj + gk) & 1;
-            fl[s] = 1;
-            if (jj >= 1 && jj <= LJ - 2 && kk >= 1 && kk <= LK - 2) fl[s] |= 2;
-            if (jj >= 2 && jj <= LJ - 3 && kk >= 2 && kk <= LK - 3) fl[s] |= 4;
-        }
+    // X: the column of the pair whose cell on plane i0-1 is red; Y: the other one
+    Col32 X{}, Y{};
+    const int pc = threadIdx.x;
+    if (pc < NP) {
+        const int jj = pc / (LK / 2), kk0 = 2 * (pc - jj * (LK / 2));
+        const int gj = (j0 - 2 + jj) & m, gk0 = (k0 - 2 + kk0) & m;
+        const int sx = (i0 - 1 + gj + gk0) & 1;
+        auto setup = [&](Col32& q, int d) {
+            const int kk = kk0 + d;
+            q.col = (unsigned)((gj << lg) | (gk0 + d));
+            q.c = jj * LK + kk;
+            q.fl = 1;
+            if (jj >= 1 && jj <= LJ - 2 && kk >= 1 && kk <= LK - 2) q.fl |= 2;
+            if (jj >= 2 && jj <= LJ - 3 && kk >= 2 && kk <= LK - 3) q.fl |= 4;
+        };
+        setup(X, sx);
+        setup(Y, 1 - sx);
     }
     // element offsets fit in 32 bits (n <= 1024)
-    auto offset = [&](int p, int s) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + col[s]; };
+    auto offset = [&](int p, const Col32& q) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + q.col; };
     auto buf = [&](int p) { return (p - i0 + 3) % 3; };
-
-    // planes p-2 .. p+1 as cell values, plane p+2 as raw loads in flight
-    V32 vm2[NS], vm1[NS], v0[NS], vp1[NS];
-    float fm1[NS], f0[NS], fp1[NS];
-    float ub2[NS], e2[NS], f2[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        vm2[s] = vm1[s] = v0[s] = vp1[s] = V32{0.f, 0.f, 0.f, 0.f};
-        fm1[s] = f0[s] = fp1[s] = 0.0f;
-        ub2[s] = e2[s] = f2[s] = 0.0f;
-        if (fl[s]) {
-            vm1[s] = make_v(ub[offset(i0 - 2, s)], ein[offset(i0 - 2, s)]);
-            v0[s] = make_v(ub[offset(i0 - 1, s)], ein[offset(i0 - 1, s)]);
-            vp1[s] = make_v(ub[offset(i0, s)], ein[offset(i0, s)]);
-            fm1[s] = f[offset(i0 - 2, s)];
-            f0[s] = f[offset(i0 - 1, s)];
-            fp1[s] = f[offset(i0, s)];
-            ub2[s] = ub[offset(i0 + 1, s)];
-            e2[s] = ein[offset(i0 + 1, s)];
-            f2[s] = f[offset(i0 + 1, s)];
-            lv[buf(i0 - 1)][threadIdx.x + s * NT] = v0[s];
-        }
-    }
+    auto prologue = [&](Col32& q) {
+        if (!q.fl) return;
+        // planes i0-2, i0-1, i0 in slots 1, 2, 3; plane i0+1 raw in slot 1
+        q.v[1] = make_v(ub[offset(i0 - 2, q)], ein[offset(i0 - 2, q)]);
+        q.v[2] = make_v(ub[offset(i0 - 1, q)], ein[offset(i0 - 1, q)]);
+        q.v[3] = make_v(ub[offset(i0, q)], ein[offset(i0, q)]);
+        q.f[1] = f[offset(i0 - 2, q)];
+        q.f[2] = f[offset(i0 - 1, q)];
+        q.f[3] = f[offset(i0, q)];
+        q.rub[1] = ub[offset(i0 + 1, q)];
+        q.re[1] = ein[offset(i0 + 1, q)];
+        q.rf[1] = f[offset(i0 + 1, q)];
+        lv[buf(i0 - 1)][q.c] = q.v[2];
+    };
+    prologue(X);
+    prologue(Y);
     __syncthreads();
-    for (int p = i0 - 1; p <= i0 + a.ti; ++p) {
-        // loads of plane p+3, two steps ahead of their use
-        const bool more3 = p + 3 <= last;
-        float ub3[NS], e3[NS], f3[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            ub3[s] = e3[s] = f3[s] = 0.0f;
-            if (more3 && fl[s]) {
-                ub3[s] = ub[offset(p + 3, s)];
-                e3[s] = ein[offset(p + 3, s)];
-                f3[s] = f[offset(p + 3, s)];
+
+    // One plane step, R = (p - i0 + 1) mod 4 fixed at compile time so that the register
+    // planes rotate by renaming.  A holds the red cell of plane p and the black cell of
+    // plane p-1.
+    auto step = [&](auto Rc, int p, Col32& A, Col32& B) {
+        constexpr int R = decltype(Rc)::value;
+        constexpr int M2 = R, M1 = (R + 1) & 3, P0 = (R + 2) & 3, P1 = (R + 3) & 3;
+        constexpr int N2 = (R + 1) & 1, N3 = R & 1;  // raw slots of planes p+2, p+3
+        if (p + 3 <= last) {
+            if (A.fl) {
+                A.rub[N3] = ub[offset(p + 3, A)];
+                A.re[N3] = ein[offset(p + 3, A)];
+                A.rf[N3] = f[offset(p + 3, A)];
+            }
+            if (B.fl) {
+                B.rub[N3] = ub[offset(p + 3, B)];
+                B.re[N3] = ein[offset(p + 3, B)];
+                B.rf[N3] = f[offset(p + 3, B)];
             }
         }
         V32* LA = lv[buf(p)];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int c = threadIdx.x + s * NT;
-            if ((fl[s] & 2) && ((p + par[s]) & 1) == 0) {
-                const V32 nbv[6] = {vm1[s], vp1[s], LA[c - LK], LA[c + LK], LA[c - 1], LA[c + 1]};
-                const Res32 r = corr_op(o, v0[s], nbv, f0[s]);
-                v0[s] = make_v(v0[s].ub, v0[s].e + bounded32(-r.N / r.dN, o.max_step));
-                LA[c] = v0[s];
-            }
+        if (A.fl & 2) {
+            const int c = A.c;
+            const V32 nbv[6] = {A.v[M1], A.v[P1], LA[c - LK], LA[c + LK], LA[c - 1], LA[c + 1]};
+            const Res32 r = corr_op(o, A.v[P0], nbv, A.f[P0]);
+            A.v[P0] = make_v(A.v[P0].ub, A.v[P0].e + newton32(r, o.max_step));
+            LA[c] = A.v[P0];
         }
         if (p - 1 >= i0) {
-            const V32* LB = lv[buf(p - 1)];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int c = threadIdx.x + s * NT;
-                if (fl[s] & 4) {
-                    if (((p - 1 + par[s]) & 1) == 1) {
-                        const V32 nbv[6] = {vm2[s], v0[s], LB[c - LK], LB[c + LK], LB[c - 1], LB[c + 1]};
-                        const Res32 r = corr_op(o, vm1[s], nbv, fm1[s]);
-                        vm1[s].e = vm1[s].e + bounded32(-r.N / r.dN, o.max_step);
-                    }
-                    eout[offset(p - 1, s)] = vm1[s].e;
-                }
+            if (A.fl & 4) {
+                const V32* LB = lv[buf(p - 1)];
+                const int c = A.c;
+                const V32 nbv[6] = {A.v[M2], A.v[P0], LB[c - LK], LB[c + LK], LB[c - 1], LB[c + 1]};
+                const Res32 r = corr_op(o, A.v[M1], nbv, A.f[M1]);
+                A.v[M1].e = A.v[M1].e + newton32(r, o.max_step);
+                eout[offset(p - 1, A)] = A.v[M1].e;
             }
+            if (B.fl & 4) eout[offset(p - 1, B)] = B.v[M1].e;
         }
         V32* LC = lv[buf(p + 1)];
         const bool more2 = p + 2 <= last;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (fl[s]) LC[threadIdx.x + s * NT] = vp1[s];
-            vm2[s] = vm1[s];
-            vm1[s] = v0[s];
-            fm1[s] = f0[s];
-            v0[s] = vp1[s];
-            f0[s] = fp1[s];
-            if (more2 && fl[s]) {
-                vp1[s] = make_v(ub2[s], e2[s]);
-                fp1[s] = f2[s];
+        auto advance = [&](Col32& q) {
+            if (q.fl) {
+                LC[q.c] = q.v[P1];
+                if (more2) {  // plane p+2 takes the slot of plane p-2
+                    q.v[M2] = make_v(q.rub[N2], q.re[N2]);
+                    q.f[M2] = q.rf[N2];
+                }
             }
-            ub2[s] = ub3[s];
-            e2[s] = e3[s];
-            f2[s] = f3[s];
-        }
+        };
+        advance(A);
+        advance(B);
         __syncthreads();
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    // a.ti + 2 steps (a.ti a multiple of 4): two, then groups of four so that the register
+    // planes and the column roles are back in place at the end of every iteration.  X holds
+    // the red cells of planes i0-1, i0+1, ...
+    step(I0{}, i0 - 1, X, Y);
+    step(I1{}, i0, Y, X);
+    for (int p = i0 + 1; p <= i0 + a.ti; p += 4) {
+        step(I2{}, p, X, Y);
+        step(I3{}, p + 1, Y, X);
+        step(I0{}, p + 2, X, Y);
+        step(I1{}, p + 3, Y, X);
     }
 }
 
@@ -512,7 +533,7 @@ __global__ void __launch_bounds__(kBlock) k32_coarsest(Grid g, const float* __re
                 V32 c, nb[6];
                 if (cell(q, c, nb) != colour) continue;
                 const Res32 r = corr_op(o, c, nb, sf[q]);
-                se[q] = c.e + bounded32(-r.N / r.dN, o.max_step);
+                se[q] = c.e + newton32(r, o.max_step);
             }
             __syncthreads();
         }
@@ -535,8 +556,9 @@ hipError_t ngs_sweep32(const Grid& g, const float* ub, float* e, const float* f,
 hipError_t ngs_sweep32_fused(const Grid& g, const float* ub, const float* ein, float* eout, const float* f,
                              int ti, hipStream_t s)
 {
-    if (g.n < kTK || g.n > 1024 || ein == eout || ti < 1 || ti > g.n || (g.n % ti) != 0) return hipErrorInvalidValue;
-    constexpr int TJ = 16, NT = 512;
+    if (g.n < kTK || g.n > 1024 || ein == eout || ti < 4 || (ti & 3) || ti > g.n || (g.n % ti) != 0)
+        return hipErrorInvalidValue;
+    constexpr int TJ = 8, NT = 448;  // 408 column pairs per 12 x 68 tile
     FusedSweep32 a{};
     a.ti = ti;
     a.ntj = g.n / TJ;

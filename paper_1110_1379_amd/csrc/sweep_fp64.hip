@@ -15,6 +15,8 @@
 // same array) so that halo reads always see the values from before the sweep.
 #include "device_fp64.h"
 
+#include <type_traits>
+
 namespace mgfr {
 namespace {
 
@@ -22,13 +24,23 @@ using dev::OpVal;
 
 constexpr int kTK = 64;  // tile width along k (contiguous)
 
+// State of one column of a thread's pair.  Plane q of u and b = exp(u) sits in slot
+// (q - i0 + 3) & 3 (planes p-2 .. p+1 at step p), its right-hand side in the same slot
+// (planes p-1 .. p+1 used), and the raw loads of planes p+2 and p+3 in slot (q - i0) & 1.
+struct Col64 {
+    double u[4], b[4], f[4];
+    double ru[2], rf[2];
+    unsigned col;  // (j,k) offset within a plane
+    int c, fl;     // LDS cell; 1 loaded, 2 red range (tile + ring), 4 tile
+};
+
 template <int TJ, int NT>
 __global__ void __launch_bounds__(NT) k_ngs_fused(Grid g, const double* __restrict__ uin,
                                                   double* __restrict__ uout,
                                                   const double* __restrict__ src, FusedSweep a)
 {
-    constexpr int LJ = TJ + 4, LK = kTK + 4, NL = LJ * LK;
-    constexpr int NS = (NL + NT - 1) / NT;
+    constexpr int LJ = TJ + 4, LK = kTK + 4, NL = LJ * LK, NP = NL / 2;
+    static_assert(NP <= NT, "one column pair per thread");
     // three plane buffers: plane p (red update), plane p-1 (black update), plane p+1 (staged)
     __shared__ double lu[3][NL];
     __shared__ double lb[3][NL];
@@ -46,140 +58,131 @@ __global__ void __launch_bounds__(NT) k_ngs_fused(Grid g, const double* __restri
     const int lg = g.lg, m = g.n - 1;
     const int last = i0 + a.ti + 1;  // last plane read
 
-    unsigned col[NS];
-    int par[NS], fl[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int c = threadIdx.x + s * NT;
-        col[s] = 0;
-        par[s] = 0;
-        fl[s] = 0;
-        if (c < NL) {
-            const int jj = c / LK, kk = c - jj * LK;
-            const int gj = (j0 - 2 + jj) & m, gk = (k0 - 2 + kk) & m;
-            col[s] = (unsigned)((gj << lg) | gk);
-            par[s] = (gj + gk) & 1;
-            fl[s] = 1;
-            if (jj >= 1 && jj <= LJ - 2 && kk >= 1 && kk <= LK - 2) fl[s] |= 2;  // red ring + tile
-            if (jj >= 2 && jj <= LJ - 3 && kk >= 2 && kk <= LK - 3) fl[s] |= 4;  // tile
-        }
+    // A thread owns the k-adjacent columns (kk0, kk0+1) of one tile row.  At step p the
+    // column whose cell on plane p is red does both updates of the step (red on plane p,
+    // black on plane p-1, the same column); the other column's cells there are black on p
+    // and red on p-1, so it has nothing to do until the next step.  X is the column with
+    // the red cell on plane i0-1, Y the other; as the roles alternate, every lane updates
+    // at every step.
+    Col64 X{}, Y{};
+    const int pc = threadIdx.x;
+    if (pc < NP) {
+        const int jj = pc / (LK / 2), kk0 = 2 * (pc - jj * (LK / 2));
+        const int gj = (j0 - 2 + jj) & m, gk0 = (k0 - 2 + kk0) & m;
+        const int sx = (i0 - 1 + gj + gk0) & 1;
+        auto setup = [&](Col64& q, int d) {
+            const int kk = kk0 + d;
+            q.col = (unsigned)((gj << lg) | (gk0 + d));
+            q.c = jj * LK + kk;
+            q.fl = 1;
+            if (jj >= 1 && jj <= LJ - 2 && kk >= 1 && kk <= LK - 2) q.fl |= 2;
+            if (jj >= 2 && jj <= LJ - 3 && kk >= 2 && kk <= LK - 3) q.fl |= 4;
+        };
+        setup(X, sx);
+        setup(Y, 1 - sx);
     }
 
     // element offsets fit in 32 bits (n <= 1024)
-    auto offset = [&](int p, int s) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + col[s]; };
-    auto load_u = [&](int p, int s) -> double { return uin[offset(p, s)]; };
+    auto offset = [&](int p, const Col64& q) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + q.col; };
     auto buf = [&](int p) { return (p - i0 + 3) % 3; };
-
-    // registers of plane p-2, p-1, p, p+1 for each column slot, and the raw loads of planes
-    // p+2 and p+3 in flight
-    double um2[NS], um1[NS], u0[NS], up1[NS];
-    double bm2[NS], bm1[NS], b0[NS], bp1[NS];
-    double fm1[NS], f0[NS], fp1[NS];
-    double un2[NS], fn2[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        um2[s] = bm2[s] = 0.0;
-        um1[s] = bm1[s] = u0[s] = b0[s] = up1[s] = bp1[s] = 0.0;
-        fm1[s] = f0[s] = fp1[s] = 0.0;
-        un2[s] = fn2[s] = 0.0;
-        if (fl[s]) {
-            um1[s] = load_u(i0 - 2, s);
-            u0[s] = load_u(i0 - 1, s);
-            up1[s] = load_u(i0, s);
-            un2[s] = load_u(i0 + 1, s);
-            fm1[s] = dev::rhs_value(g, src[offset(i0 - 2, s)]);
-            f0[s] = dev::rhs_value(g, src[offset(i0 - 1, s)]);
-            fp1[s] = dev::rhs_value(g, src[offset(i0, s)]);
-            fn2[s] = src[offset(i0 + 1, s)];  // raw: transformed when it becomes plane p+1
-            bm1[s] = exp(um1[s]);
-            b0[s] = exp(u0[s]);
-            bp1[s] = exp(up1[s]);
-            const int c = threadIdx.x + s * NT;
-            lu[buf(i0 - 1)][c] = u0[s];
-            lb[buf(i0 - 1)][c] = b0[s];
+    auto prologue = [&](Col64& q) {
+        if (!q.fl) return;
+        // planes i0-2, i0-1, i0 in slots 1, 2, 3; plane i0+1 raw in slot 1
+        for (int t = 1; t < 4; ++t) {
+            q.u[t] = uin[offset(i0 - 3 + t, q)];
+            q.f[t] = dev::rhs_value(g, src[offset(i0 - 3 + t, q)]);
         }
-    }
+        q.ru[1] = uin[offset(i0 + 1, q)];
+        q.rf[1] = src[offset(i0 + 1, q)];  // raw: transformed when it becomes plane p+1
+        for (int t = 1; t < 4; ++t) q.b[t] = exp(q.u[t]);
+        lu[buf(i0 - 1)][q.c] = q.u[2];
+        lb[buf(i0 - 1)][q.c] = q.b[2];
+    };
+    prologue(X);
+    prologue(Y);
     __syncthreads();
 
     const double ms = g.max_step;
-    for (int p = i0 - 1; p <= i0 + a.ti; ++p) {
+    // One plane step, R = (p - i0 + 1) mod 4 fixed at compile time so that the register
+    // planes rotate by renaming.  A holds the red cell of plane p and the black cell of
+    // plane p-1.
+    auto step = [&](auto Rc, int p, Col64& A, Col64& B) {
+        constexpr int R = decltype(Rc)::value;
+        constexpr int M2 = R, M1 = (R + 1) & 3, P0 = (R + 2) & 3, P1 = (R + 3) & 3;
+        constexpr int N2 = (R + 1) & 1, N3 = R & 1;  // raw slots of planes p+2, p+3
         // issue the loads of plane p+3 two steps ahead of their use
-        const bool more3 = p + 3 <= last;
-        double un3[NS], fn3[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            un3[s] = 0.0;
-            fn3[s] = 0.0;
-            if (more3 && fl[s]) {
-                un3[s] = load_u(p + 3, s);
-                fn3[s] = src[offset(p + 3, s)];
+        if (p + 3 <= last) {
+            if (A.fl) {
+                A.ru[N3] = uin[offset(p + 3, A)];
+                A.rf[N3] = src[offset(p + 3, A)];
+            }
+            if (B.fl) {
+                B.ru[N3] = uin[offset(p + 3, B)];
+                B.rf[N3] = src[offset(p + 3, B)];
             }
         }
+        // red cell of plane p (tile + ring); its black neighbours are all old
         double* LA = lu[buf(p)];
         double* BA = lb[buf(p)];
-        // red cells of plane p (tile + ring); their black neighbours are all old
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int c = threadIdx.x + s * NT;
-            if ((fl[s] & 2) && ((p + par[s]) & 1) == 0) {
-                const double un[6] = {um1[s], up1[s], LA[c - LK], LA[c + LK], LA[c - 1], LA[c + 1]};
-                const double bn[6] = {bm1[s], bp1[s], BA[c - LK], BA[c + LK], BA[c - 1], BA[c + 1]};
-                const OpVal r = dev::cell_op_b(g, u0[s], b0[s], un, bn, f0[s]);
-                const double v = u0[s] + dev::bounded(-r.L / r.dL, ms);
-                const double bv = exp(v);
-                u0[s] = v;
-                b0[s] = bv;
-                LA[c] = v;
-                BA[c] = bv;
-            }
+        if (A.fl & 2) {
+            const int c = A.c;
+            const double un[6] = {A.u[M1], A.u[P1], LA[c - LK], LA[c + LK], LA[c - 1], LA[c + 1]};
+            const double bn[6] = {A.b[M1], A.b[P1], BA[c - LK], BA[c + LK], BA[c - 1], BA[c + 1]};
+            const OpVal r = dev::cell_op_b(g, A.u[P0], A.b[P0], un, bn, A.f[P0]);
+            const double v = A.u[P0] + dev::bounded(-r.L / r.dL, ms);
+            const double bv = exp(v);
+            A.u[P0] = v;
+            A.b[P0] = bv;
+            LA[c] = v;
+            BA[c] = bv;
         }
-        // black cells of plane p-1 (tile); their red neighbours are all new, then plane p-1
-        // is final
+        // black cell of plane p-1 (tile); its red neighbours are all new.  Plane p-1 is then
+        // final in both columns.
         if (p - 1 >= i0) {
-            const double* LB = lu[buf(p - 1)];
-            const double* BB = lb[buf(p - 1)];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int c = threadIdx.x + s * NT;
-                if (fl[s] & 4) {
-                    if (((p - 1 + par[s]) & 1) == 1) {
-                        const double un[6] = {um2[s], u0[s], LB[c - LK], LB[c + LK], LB[c - 1], LB[c + 1]};
-                        const double bn[6] = {bm2[s], b0[s], BB[c - LK], BB[c + LK], BB[c - 1], BB[c + 1]};
-                        const OpVal r = dev::cell_op_b(g, um1[s], bm1[s], un, bn, fm1[s]);
-                        um1[s] = um1[s] + dev::bounded(-r.L / r.dL, ms);
-                    }
-                    uout[offset(p - 1, s)] = um1[s];
-                }
+            if (A.fl & 4) {
+                const double* LB = lu[buf(p - 1)];
+                const double* BB = lb[buf(p - 1)];
+                const int c = A.c;
+                const double un[6] = {A.u[M2], A.u[P0], LB[c - LK], LB[c + LK], LB[c - 1], LB[c + 1]};
+                const double bn[6] = {A.b[M2], A.b[P0], BB[c - LK], BB[c + LK], BB[c - 1], BB[c + 1]};
+                const OpVal r = dev::cell_op_b(g, A.u[M1], A.b[M1], un, bn, A.f[M1]);
+                A.u[M1] = A.u[M1] + dev::bounded(-r.L / r.dL, ms);
+                uout[offset(p - 1, A)] = A.u[M1];
             }
+            if (B.fl & 4) uout[offset(p - 1, B)] = B.u[M1];
         }
-        // stage plane p+1 for the next step, then shift the register planes
+        // stage plane p+1 for the next step; plane p+2 takes the slot of plane p-2
         double* LC = lu[buf(p + 1)];
         double* BC = lb[buf(p + 1)];
         const bool more2 = p + 2 <= last;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int c = threadIdx.x + s * NT;
-            if (fl[s]) {
-                LC[c] = up1[s];
-                BC[c] = bp1[s];
+        auto advance = [&](Col64& q) {
+            if (q.fl) {
+                LC[q.c] = q.u[P1];
+                BC[q.c] = q.b[P1];
+                if (more2) {
+                    q.u[M2] = q.ru[N2];
+                    q.b[M2] = exp(q.ru[N2]);
+                    q.f[M2] = dev::rhs_value(g, q.rf[N2]);
+                }
             }
-            um2[s] = um1[s];
-            bm2[s] = bm1[s];
-            um1[s] = u0[s];
-            bm1[s] = b0[s];
-            fm1[s] = f0[s];
-            u0[s] = up1[s];
-            b0[s] = bp1[s];
-            f0[s] = fp1[s];
-            if (more2 && fl[s]) {
-                up1[s] = un2[s];
-                bp1[s] = exp(un2[s]);
-                fp1[s] = dev::rhs_value(g, fn2[s]);
-            }
-            un2[s] = un3[s];
-            fn2[s] = fn3[s];
-        }
+        };
+        advance(A);
+        advance(B);
         __syncthreads();
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    // a.ti + 2 steps (a.ti a multiple of 4): two, then groups of four so that the register
+    // planes and the column roles are back in place at the end of every iteration
+    step(I0{}, i0 - 1, X, Y);
+    step(I1{}, i0, Y, X);
+    for (int p = i0 + 1; p <= i0 + a.ti; p += 4) {
+        step(I2{}, p, X, Y);
+        step(I3{}, p + 1, Y, X);
+        step(I0{}, p + 2, X, Y);
+        step(I1{}, p + 3, Y, X);
     }
 }
 
@@ -212,10 +215,11 @@ int fused_sweep_planes(int n)
 hipError_t ngs_sweep_fused(const Grid& g, const double* uin, double* uout, const double* src, int ti,
                            hipStream_t s)
 {
-    if (g.n < kTK || g.n > 1024 || uin == uout || ti < 1 || ti > g.n || (g.n % ti) != 0) return hipErrorInvalidValue;
+    if (g.n < kTK || g.n > 1024 || uin == uout || ti < 4 || (ti & 3) || ti > g.n || (g.n % ti) != 0)
+        return hipErrorInvalidValue;
     FusedSweep a{};
     a.ti = ti;
-    return launch<16, 1024>(g, uin, uout, src, a, s);
+    return launch<16, 704>(g, uin, uout, src, a, s);  // 680 column pairs per 20 x 68 tile
 }
 
 }  // namespace mgfr
