@@ -29,6 +29,34 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "f(R) MG time-to-residual 1e-8 & cell-updates/s, 512^3, FP64 vs mixed"
 
+# HBM bytes per finest-level (512^3) launch of the dominant kernels, from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE runs scaled by a plain copy (profiles/halo512_traffic.md), with the SHA-256
+# of the sources those kernels were built from: when any of them differs the figure no longer
+# describes the kernel that runs and `traffic` is reported as null.
+MEASURED_TRAFFIC = {
+    "mixed": {"bytes": 2.540e9, "sources": {
+        "kernels_fp32.hip": "9875fee927415282cbaed15ab75138ba8ef914e879cbf3ea2718cf36cbbed74d",
+        "mgfr_impl.h": "aa7831585137f0c5228a1dec003e766a5565fc8bc0798311f427b0d459a201f3"}},
+    "fp64": {"bytes": 3.500e9, "sources": {
+        "sweep_fp64.hip": "8626f8c275f300f245261a3ce754af32586572b601a374203ca3eeb1fd8c8850",
+        "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
+        "mgfr_impl.h": "aa7831585137f0c5228a1dec003e766a5565fc8bc0798311f427b0d459a201f3"}},
+}
+
+
+def measured_traffic(prec, N):
+    """Bytes per finest launch if the counters describe the kernel built from these sources."""
+    import hashlib
+    entry = MEASURED_TRAFFIC.get(prec)
+    if entry is None or N != 512:
+        return None
+    csrc = os.path.join(ROOT, "paper_1110_1379_amd", "csrc")
+    for name, digest in entry["sources"].items():
+        with open(os.path.join(csrc, name), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
+                return None
+    return entry["bytes"]
+
 WORKLOADS = {
     # name: (N, box Mpc/h, |f_R0|, generator, oracle sample (N, structures))
     "halo512": (512, 512.0, 1e-6, "halo_box", (128, 31)),
@@ -149,14 +177,17 @@ def bench_domain(args):
         "final_residual": head["final_residual"],
         "roofline": {
             "bound": "hbm", "achieved": sm["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (sm["achieved_GBs"] / HBM_PEAK_GBS) if sm["achieved_GBs"] else None, "traffic": None,
+            "frac": (sm["achieved_GBs"] / HBM_PEAK_GBS) if sm["achieved_GBs"] else None,
+            "traffic": measured_traffic(headp, N),
             "kernel": ("single-precision correction smoother k32_fused" if headp == "mixed"
                        else "double-precision smoother k_ngs_fused") + " (finest level)",
             "bytes_per_cell": sm["bytes_per_cell_sweep"], "launches": sm["launches"],
             "avg_launch_ms": sm["avg_launch_ms"],
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
     }
     for p, r in runs.items():
+        r["smoother"]["traffic"] = measured_traffic(p, N)
         out[p] = r
     if "fp64" in runs and "mixed" in runs:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
