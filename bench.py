@@ -205,10 +205,33 @@ def bench_domain(args):
     return out
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1000.0 / steps, out
+
+
+def _precisions(mgfr, args):
+    names = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    return [(n, mgfr.MGFR_MIXED if n == "mixed" else mgfr.MGFR_FP64) for n in names]
+
+
+def _field_error(a, b):
+    d = (a - b).abs()
+    ref = b.abs().max().item()
+    return {"max_abs": d.max().item(), "rms_abs": d.square().mean().sqrt().item(),
+            "max_rel": d.max().item() / ref if ref > 0 else None}
+
+
 def bench_amr(args):
     """Domain grid (256^3, FP64) plus its refinement patches, all levels; one step = the
-    patch solve of every refinement level (domain solution given)."""
-    import numpy as np
+    patch solve of every refinement level (domain solution given), FP64 and mixed."""
     import torch
     from paper_1110_1379_amd import inputs, mgfr
     N0, box, fr0 = 256, 256.0, 1e-5
@@ -222,59 +245,84 @@ def bench_amr(args):
     ud, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100))
     assert st == mgfr.MGFR_OK, ctx.last_error()
     rp = torch.from_numpy(rho_packed).to("cuda:0")
-    up = torch.empty_like(rp)
-    opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100)
-    for _ in range(args.warmup):
-        mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, opts, u_packed=up)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, hists, st = mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, opts, u_packed=up)
-        if st != mgfr.MGFR_OK:
-            raise SystemExit(f"patch solve failed: {ctx.last_error()}")
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
-    s = mgfr.mgfr_get_stats(ctx)
-    return {"metric": "f(R) MG patch solve time-to-residual & cell-updates/s (AMR refinements)",
-            "value": s["cell_updates"] / (ms * 1e-3), "unit": "cell-updates/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"amr: {N0}^3 domain (lognormal sigma 2), {len(patches)} cube patches "
-                                   f"8^3-64^3 over {max(p['level'] for p in patches)} levels "
-                                   f"(contrast > 50/200/1000), {cells} patch cells, tol {args.tol:g}"},
-            "max_cycles_per_patch": int(max(len(h) for h in hists) - 1)}
+    runs, fields = {}, {}
+    for name, code in _precisions(mgfr, args):
+        opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code)
+        up = torch.empty_like(rp)
+
+        def solve():
+            _, hists, st = mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, opts, u_packed=up)
+            if st != mgfr.MGFR_OK:
+                raise SystemExit(f"patch solve failed: {ctx.last_error()}")
+            return hists
+        ms, hists = _timed(solve, args.steps, args.warmup)
+        s = mgfr.mgfr_get_stats(ctx)
+        runs[name] = {"ms_per_step": ms, "value": s["cell_updates"] / (ms * 1e-3),
+                      "max_cycles_per_patch": int(max(len(h) for h in hists) - 1),
+                      "max_final_residual": float(max(h[-1] for h in hists))}
+        fields[name] = up
+        log(f"amr {name}: {ms:.2f} ms, {runs[name]['max_cycles_per_patch']} cycles max")
+    headp = "mixed" if "mixed" in runs else "fp64"
+    head = runs[headp]
+    out = {"metric": "f(R) MG patch solve time-to-residual & cell-updates/s (AMR refinements)",
+           "value": head["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if headp == "fp64" else "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": f"amr: {N0}^3 domain (lognormal sigma 2), {len(patches)} cube patches "
+                                  f"8^3-64^3 over {max(p['level'] for p in patches)} levels "
+                                  f"(contrast > 50/200/1000), {cells} patch cells, tol {args.tol:g}",
+                      "precision": headp}}
+    out.update(runs)
+    if len(runs) == 2:
+        out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
+        out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])
+    return out
 
 
 def bench_batch(args):
-    """64 boxes of 64^3 plus 16 of 128^3 with their own |f_R0| and sigma, solved together."""
+    """64 boxes of 64^3 plus 16 of 128^3 with their own |f_R0| and sigma, solved together,
+    FP64 and mixed."""
     import torch
     from paper_1110_1379_amd import inputs, mgfr
     log("generating the boxes")
     boxes = inputs.batch_boxes()
     rhos = [torch.from_numpy(b[5]).to("cuda:0") for b in boxes]
     params = [mgfr.Params(box_mpc_h=b[1], fr0_abs=b[2]) for b in boxes]
-    us = [torch.empty_like(r) for r in rhos]
     ctx = mgfr.Context(0)
-    opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100)
-    for _ in range(args.warmup):
-        mgfr.mg_fr_solve_batch(ctx, rhos, params, opts, us=us)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, hists, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, opts, us=us)
-        if st != mgfr.MGFR_OK:
-            raise SystemExit(f"batch solve failed: {ctx.last_error()}")
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
-    s = mgfr.mgfr_get_stats(ctx)
-    return {"metric": "f(R) MG batch of independent boxes: boxes/s at residual 1e-8",
-            "value": len(boxes) / (ms * 1e-3), "unit": "boxes/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "batch: 64 x 64^3 (B=64) + 16 x 128^3 (B=128), |f_R0| log-uniform "
-                                   f"[1e-6,1e-4], lognormal sigma U[1,3], tol {args.tol:g}"},
-            "cell_updates_per_s": s["cell_updates"] / (ms * 1e-3),
-            "max_cycles_per_box": int(max(len(h) for h in hists) - 1)}
+    runs, fields = {}, {}
+    for name, code in _precisions(mgfr, args):
+        opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code)
+        us = [torch.empty_like(r) for r in rhos]
+
+        def solve():
+            _, hists, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, opts, us=us)
+            if st != mgfr.MGFR_OK:
+                raise SystemExit(f"batch solve failed: {ctx.last_error()}")
+            return hists
+        ms, hists = _timed(solve, args.steps, args.warmup)
+        s = mgfr.mgfr_get_stats(ctx)
+        runs[name] = {"ms_per_step": ms, "value": len(boxes) / (ms * 1e-3),
+                      "cell_updates_per_s": s["cell_updates"] / (ms * 1e-3),
+                      "max_cycles_per_box": int(max(len(h) for h in hists) - 1),
+                      "max_final_residual": float(max(h[-1] for h in hists))}
+        fields[name] = torch.cat([u.reshape(-1) for u in us])
+        log(f"batch {name}: {ms:.2f} ms, {runs[name]['max_cycles_per_box']} cycles max")
+    headp = "mixed" if "mixed" in runs else "fp64"
+    head = runs[headp]
+    out = {"metric": "f(R) MG batch of independent boxes: boxes/s at residual 1e-8",
+           "value": head["value"], "unit": "boxes/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if headp == "fp64" else "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": "batch: 64 x 64^3 (B=64) + 16 x 128^3 (B=128), |f_R0| log-uniform "
+                                  f"[1e-6,1e-4], lognormal sigma U[1,3], tol {args.tol:g}",
+                      "precision": headp}}
+    out.update(runs)
+    if len(runs) == 2:
+        out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
+        out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])
+    return out
 
 
 def main():

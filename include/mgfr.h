@@ -47,6 +47,8 @@ extern "C" {
 #define MGFR_SUBTRACT_MEAN 1 /* density contrast rho~ - mean(rho~) instead of rho~ - 1       */
 #define MGFR_WARM_START 2    /* start from the u passed in instead of the background u      */
 #define MGFR_PROFILE 4       /* time every finest-level smoother launch with HIP events      */
+#define MGFR_GRAPH 8         /* batched solves: capture one cycle's launches in a HIP graph
+                                on first use and replay it for every later cycle of the call */
 
 /* Model (Sec. II, Sec. III.A): Om, OL (< 0 means 1 - Om), scale factor a, Hu-Sawicki n,
  * |f_R0| (the present background f_R), box side B in Mpc/h. */
@@ -177,8 +179,12 @@ int mg_fr_solve(mgfr_ctx* ctx, const double* rho, int N, const mgfr_params* para
  * rho_packed  device, packed_cells: the density of every patch cell (code units).
  * u_packed    device, packed_cells: output.
  * res_hist    host, npatch x (max_cycles + 1) (may be NULL); n_hist host, npatch (may be NULL).
- * Double precision; MGFR_SUBTRACT_MEAN is rejected (the contrast is rho - 1).  Returns
- * MGFR_ENOTCONV if any patch missed tol (all patches are still written).  Synchronises. */
+ * opts->precision: MGFR_FP64 runs the V-cycles in double precision; MGFR_MIXED runs, per
+ * cycle, opts->inner_cycles single-precision correction V-cycles (ghost faces in correction
+ * form) followed by u += e and the double-precision residual, as in mg_fr_solve.  Histories
+ * hold the double-precision rms per cycle.  MGFR_SUBTRACT_MEAN is rejected (the contrast is
+ * rho - 1).  Returns MGFR_ENOTCONV if any patch missed tol (all patches are still written).
+ * Synchronises. */
 int mg_fr_solve_patches(mgfr_ctx* ctx, const double* u_domain, int N0, const mgfr_patch* patches,
                         int npatch, const double* rho_packed, double* u_packed, long long packed_cells,
                         const mgfr_params* params, const mgfr_opts* opts, double* res_hist,
@@ -187,9 +193,12 @@ int mg_fr_solve_patches(mgfr_ctx* ctx, const double* u_domain, int N0, const mgf
 /* Independent periodic boxes solved together: box b has side N[b] (power of two in
  * [coarsest_n, 1024]), density rho[b] and output u[b] (device arrays of N[b]^3, pointers
  * given in host arrays), and its own model per_box[b] (box size, |f_R0|, ...).  Every box
- * runs the domain-grid FAS V-cycles of mg_fr_solve (double precision) batched with the
- * others until rms(L) <= tol or max_cycles.  res_hist host nbox x (max_cycles + 1), n_hist
- * host nbox (both may be NULL).  Returns MGFR_ENOTCONV if any box missed tol.  Synchronises. */
+ * runs the domain-grid FAS V-cycles of mg_fr_solve batched with the others until
+ * rms(L) <= tol or max_cycles, in double precision or (MGFR_MIXED) as single-precision
+ * correction V-cycles inside the double-precision defect-correction loop.  MGFR_WARM_START
+ * keeps the given u as the start; MGFR_SUBTRACT_MEAN is rejected.  res_hist host
+ * nbox x (max_cycles + 1), n_hist host nbox (both may be NULL).  Returns MGFR_ENOTCONV if
+ * any box missed tol.  Synchronises. */
 int mg_fr_solve_batch(mgfr_ctx* ctx, int nbox, const int* N, const double* const* rho,
                       const mgfr_params* per_box, const mgfr_opts* opts, double* const* u,
                       double* res_hist, int* n_hist, void* stream);

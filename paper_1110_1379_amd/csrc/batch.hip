@@ -96,6 +96,10 @@ struct Batch {
 
     ~Batch()
     {
+        if (gexec || cap_stream) (void)hipStreamSynchronize(s);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void* p : owned) (void)hipFree(p);
     }
 
@@ -138,6 +142,20 @@ struct Batch {
         double* pool = nullptr;
         MGFR_TRY(alloc(&pool, need));
         size_t at = 0;
+        // mixed precision: single-precision base, correction, right-hand side (every level)
+        // and coarse difference (coarse levels)
+        const bool mixed = o->precision == MGFR_MIXED;
+        float* pool32 = nullptr;
+        size_t at32 = 0;
+        if (mixed) {
+            size_t need32 = 0;
+            for (Unit& U : units)
+                for (int m = 0; m < U.nlev; ++m) {
+                    const size_t n = (size_t)(U.n >> m);
+                    need32 += (m > 0 ? 4 : 3) * n * n * n;
+                }
+            MGFR_TRY(alloc(&pool32, need32));
+        }
         for (size_t ui = 0; ui < units.size(); ++ui) {
             Unit& U = units[ui];
             U.g.assign(U.nlev, mgfr::BGrid{});
@@ -174,6 +192,16 @@ struct Batch {
                 if (!U.periodic) {
                     G.ub = pool + at;
                     at += 6 * (size_t)n * n;
+                }
+                if (mixed) {
+                    G.ub32 = pool32 + at32;
+                    G.e32 = pool32 + at32 + n3;
+                    G.f32 = pool32 + at32 + 2 * n3;
+                    at32 += 3 * n3;
+                    if (m > 0) {
+                        G.eh32 = pool32 + at32;
+                        at32 += n3;
+                    }
                 }
             }
         }
@@ -261,19 +289,22 @@ struct Batch {
         return hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize");
     }
 
-    void count_sweep(int m)
+    // Cell updates of one V-cycle of the active units (pre + post sweeps on every level
+    // above the coarsest), added to the statistics per cycle run.
+    void count_vcycle(int times)
     {
-        for (size_t i = 0; i < units.size(); ++i)
-            if (active[i] && units[i].nlev > m + 1) {
-                const long long n3 = cells3(units[i].g[m]);
+        for (size_t i = 0; i < units.size(); ++i) {
+            if (!active[i]) continue;
+            for (int m = 0; m + 1 < units[i].nlev; ++m) {
+                const long long n3 = cells3(units[i].g[m]) * (o->pre + o->post) * times;
                 c->stats.cell_updates += n3;
                 if (m == 0) c->stats.finest_updates += n3;
             }
+        }
     }
 
-    int sweep(const Depth& D, int m)
+    int sweep(const Depth& D)
     {
-        count_sweep(m);
         return hip_check(c, mgfr::batch_ngs(tab(D.half_f), D.half_f.nblk, s), "batch_ngs");
     }
 
@@ -285,7 +316,7 @@ struct Batch {
                                                        o->coarsest_rtol, s),
                                "batch_coarsest"));
         if (!D.deep) return MGFR_OK;
-        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(D, m));
+        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(D));
         MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict(tab(D.coarse_f), D.coarse_f.nblk,
                                                          (const mgfr::BGrid*)(dmeta + D.coarse_f.other), s),
                            "batch_resid_restrict"));
@@ -295,7 +326,68 @@ struct Batch {
         MGFR_TRY(hip_check(c, mgfr::batch_prolong_add(tab(D.fine_f), D.fine_f.nblk,
                                                       (const mgfr::BGrid*)(dmeta + D.fine_f.other), s),
                            "batch_prolong_add"));
-        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep(D, m));
+        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep(D));
+        return MGFR_OK;
+    }
+
+    // ---- mixed precision: single-precision correction V-cycle, double-precision outer loop
+    int sweep32(const Depth& D)
+    {
+        return hip_check(c, mgfr::batch_ngs32(tab(D.half_f), D.half_f.nblk, s), "batch_ngs32");
+    }
+
+    int vcycle32(int m)
+    {
+        const Depth& D = plan.depth[m];
+        if (D.coarsest)
+            MGFR_TRY(hip_check(c, mgfr::batch_coarsest32(grids(D.crs), D.crs.ngrid, dactive, o->coarsest_sweeps,
+                                                         o->coarsest_rtol, s),
+                               "batch_coarsest32"));
+        if (!D.deep) return MGFR_OK;
+        const mgfr::BGrid* coarse = (const mgfr::BGrid*)(dmeta + D.coarse_f.other);
+        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep32(D));
+        MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict32(tab(D.coarse_f), D.coarse_f.nblk, coarse, s),
+                           "batch_resid_restrict32"));
+        MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs32(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs32"));
+        MGFR_TRY(vcycle32(m + 1));
+        MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff32(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_coarse_diff32"));
+        MGFR_TRY(hip_check(c, mgfr::batch_prolong_add32(tab(D.fine_f), D.fine_f.nblk,
+                                                        (const mgfr::BGrid*)(dmeta + D.fine_f.other), s),
+                           "batch_prolong_add32"));
+        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep32(D));
+        return MGFR_OK;
+    }
+
+    // Base of every coarse level: R ub, from the finest down.
+    int restrict_base32()
+    {
+        for (size_t m = 0; m < plan.depth.size(); ++m) {
+            const Depth& D = plan.depth[m];
+            if (!D.deep) continue;
+            MGFR_TRY(hip_check(c, mgfr::batch_restrict_base32(tab(D.coarse_f), D.coarse_f.nblk,
+                                                              (const mgfr::BGrid*)(dmeta + D.coarse_f.other), s),
+                               "batch_restrict_base32"));
+        }
+        return MGFR_OK;
+    }
+
+    // Per-unit rms of the finest double-precision residual (synchronises); also writes the
+    // single-precision right-hand side r = -d, base ub = u and e = 0 of the next inner solve.
+    int norms_cast(std::vector<double>& rms, std::vector<double>& mx)
+    {
+        MGFR_TRY(hip_check(c, mgfr::batch_resid_cast(tab(plan.cells0), plan.cells0.nblk, dpartial, s),
+                           "batch_resid_cast"));
+        MGFR_TRY(hip_check(c, mgfr::batch_fold(dpartial, (const int*)(dmeta + plan.first),
+                                               (const int*)(dmeta + plan.count), plan.nunit, dout, s),
+                           "batch_fold"));
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(hout.data(), dout, sizeof(double) * hout.size(), hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync"));
+        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+        for (size_t i = 0; i < units.size(); ++i) {
+            if (!active[i]) continue;
+            rms[i] = std::sqrt(hout[2 * i] / (double)cells3(units[i].g[0]));
+            mx[i] = hout[2 * i + 1];
+        }
         return MGFR_OK;
     }
 
@@ -345,13 +437,55 @@ struct Batch {
         return MGFR_OK;
     }
 
-    // V-cycles until every unit has rms <= tol or max_cycles; histories per unit.
+    // The launches of one cycle: a double-precision V-cycle, or (mixed) the coarse bases,
+    // inner_cycles single-precision V-cycles on the correction and u += e.  Every launch
+    // reads the active flags from device memory, so the same sequence serves every cycle.
+    int cycle_body()
+    {
+        if (o->precision != MGFR_MIXED) return vcycle(0);
+        MGFR_TRY(restrict_base32());
+        for (int it = 0; it < o->inner_cycles; ++it) MGFR_TRY(vcycle32(0));
+        return hip_check(c, mgfr::batch_add_correction(tab(plan.cells0), plan.cells0.nblk, s), "batch_add_correction");
+    }
+
+    // With MGFR_GRAPH, the body is captured once on a private stream and the graph is
+    // launched on the caller's stream for every cycle.
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+
+    int cycle()
+    {
+        if (!(o->flags & MGFR_GRAPH)) return cycle_body();
+        if (!gexec) {
+            MGFR_TRY(hip_check(c, hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking), "hipStreamCreate"));
+            hipStream_t caller = s;
+            s = cap_stream;
+            MGFR_TRY(hip_check(c, hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal),
+                               "hipStreamBeginCapture"));
+            const int st = cycle_body();
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(cap_stream, &g);
+            s = caller;
+            graph = g;
+            MGFR_TRY(st);
+            MGFR_TRY(hip_check(c, e, "hipStreamEndCapture"));
+            MGFR_TRY(hip_check(c, hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate"));
+        }
+        return hip_check(c, hipGraphLaunch(gexec, s), "hipGraphLaunch");
+    }
+
+    // Cycles until every unit has rms <= tol or max_cycles; histories per unit.  Double
+    // precision: one V-cycle per cycle.  Mixed: one outer iteration per cycle (inner_cycles
+    // single-precision V-cycles on the correction, then u += e and the double-precision
+    // residual).
     int run(double* res_hist, int* n_hist, int* worst_status)
     {
+        const bool mixed = o->precision == MGFR_MIXED;
         const int H = o->max_cycles + 1;
         std::vector<double> rms(units.size(), 0.0), mx(units.size(), 0.0);
         std::vector<int> k(units.size(), 0);
-        MGFR_TRY(norms(rms, mx));
+        MGFR_TRY(mixed ? norms_cast(rms, mx) : norms(rms, mx));
         for (size_t i = 0; i < units.size(); ++i) {
             if (res_hist) res_hist[i * H] = rms[i];
             if (!(std::isfinite(rms[i])) || rms[i] <= o->tol) active[i] = 0;
@@ -364,8 +498,14 @@ struct Batch {
             MGFR_TRY(hip_check(c, hipMemcpyAsync(dactive, active.data(), sizeof(int) * active.size(),
                                                  hipMemcpyHostToDevice, s),
                                "hipMemcpyAsync"));
-            MGFR_TRY(vcycle(0));
-            MGFR_TRY(norms(rms, mx));
+            MGFR_TRY(cycle());
+            count_vcycle(mixed ? o->inner_cycles : 1);
+            if (mixed) {
+                MGFR_TRY(norms_cast(rms, mx));
+                c->stats.inner_cycles += o->inner_cycles;
+            } else {
+                MGFR_TRY(norms(rms, mx));
+            }
             ++cycles;
             for (size_t i = 0; i < units.size(); ++i) {
                 if (!active[i]) continue;
@@ -388,7 +528,6 @@ struct Batch {
 int check_batch_opts(mgfr_ctx* c, const mgfr_opts* o)
 {
     MGFR_TRY(check_opts(c, o));
-    if (o->precision != MGFR_FP64) return c->fail(MGFR_EINVAL, "batched solves run in double precision");
     if (o->flags & MGFR_SUBTRACT_MEAN) return c->fail(MGFR_EINVAL, "MGFR_SUBTRACT_MEAN is not available for batches");
     return MGFR_OK;
 }

@@ -386,6 +386,52 @@ __global__ void __launch_bounds__(kB) kb_nonfinite(BTable t, double* __restrict_
     }
 }
 
+// ---- outer double-precision loop of the mixed solves --------------------------------------
+// d = L(u) - f on finest grids: r = -d and ub = u in single precision, e = 0, and block
+// partials of (sum d^2, max |d|) as kb_norm.
+__global__ void __launch_bounds__(kB) kb_resid_cast(BTable t, double* __restrict__ partial)
+{
+    __shared__ double ra[kB], rb[kB];
+    const int2 e = t.blk[blockIdx.x];
+    const BGrid g = t.grids[e.x];
+    double s = 0.0, mx = 0.0;
+    const long long q = (long long)e.y * kB + threadIdx.x;
+    if (live(t, g) && q < (1LL << (3 * g.lg))) {
+        const int i = (int)(q >> (2 * g.lg)), j = (int)((q >> g.lg) & (g.n - 1)), k = (int)(q & (g.n - 1));
+        const double d = bcell(g, g.u, i, j, k, brhs(g, q)).L;
+        g.f32[q] = (float)(-d);
+        g.ub32[q] = (float)g.u[q];
+        g.e32[q] = 0.0f;
+        s = d * d;
+        mx = fabs(d);
+    }
+    ra[threadIdx.x] = s;
+    rb[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = kB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            ra[threadIdx.x] += ra[threadIdx.x + w];
+            const double o = rb[threadIdx.x + w];
+            if (!(rb[threadIdx.x] >= o)) rb[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = ra[0];
+        partial[2 * blockIdx.x + 1] = rb[0];
+    }
+}
+
+// u += e on finest grids
+__global__ void __launch_bounds__(kB) kb_add_correction(BTable t)
+{
+    const int2 e = t.blk[blockIdx.x];
+    const BGrid g = t.grids[e.x];
+    if (!live(t, g)) return;
+    const long long q = (long long)e.y * kB + threadIdx.x;
+    if (q < (1LL << (3 * g.lg))) g.u[q] += (double)g.e32[q];
+}
+
 }  // namespace
 
 int batch_block() { return kB; }
@@ -451,6 +497,17 @@ hipError_t batch_fill(const BTable& t, int nblk, hipStream_t s)
 hipError_t batch_nonfinite(const BTable& t, int nblk, double* partial, hipStream_t s)
 {
     hipLaunchKernelGGL(kb_nonfinite, dim3(nblk), dim3(kB), 0, s, t, partial);
+    return hipGetLastError();
+}
+
+hipError_t batch_resid_cast(const BTable& t, int nblk, double* partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_resid_cast, dim3(nblk), dim3(kB), 0, s, t, partial);
+    return hipGetLastError();
+}
+hipError_t batch_add_correction(const BTable& t, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_add_correction, dim3(nblk), dim3(kB), 0, s, t);
     return hipGetLastError();
 }
 

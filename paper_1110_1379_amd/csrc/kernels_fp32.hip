@@ -1,98 +1,27 @@
-// Single-precision kernels of the defect-correction (mixed precision) solver.
+// Single-precision kernels of the defect-correction (mixed precision) domain solver.
 //
 // The outer double-precision loop holds u and its residual d = L(u) - f.  In between, a
-// single-precision FAS multigrid solves for the correction e of u in the form
-//   N_i(e) = L_i(ub + e) - L_i(ub) = r_i,   r = -d,   ub = u rounded to single precision,
-// written with every term proportional to e so that corrections far below the single-
-// precision spacing of u are still resolved:
-//   N_i(e) = C sum_nb [(M_nb + M_i)(ub_nb - ub_i) + (B_nb + B_i)(e_nb - e_i)]
-//          + S_i expm1(-e_i/(n+1))
-//   b = exp(ub),  M = b expm1(e),  B = b + M = b exp(e),  S_i = A exp(-ub_i/(n+1)),
-// i.e. the flux and curvature terms of eq. discrete_fR (times c~^2) differenced exactly.
+// single-precision FAS multigrid solves N(e) = r for the correction e of u, in the
+// correction form of device_fp32.h (r = -d, base ub = u rounded to single precision).
 // The coarse levels of this inner multigrid use the restricted base R ub.  Smoother:
 // red-black Newton-Gauss-Seidel on N (Sec. V.B.1 applied to the correction equation).
-#include "mgfr_impl.h"
+#include "device_fp32.h"
 
 #include <type_traits>
 
 namespace mgfr {
 namespace {
 
+using dev32::em1f;
+using dev32::make_v;
+using dev32::newton32;
+using dev32::Op32;
+using dev32::op32;
+using dev32::Res32;
+using dev32::V32;
+
 constexpr int kBlock = 256;
 constexpr int kTK = 64;
-
-struct Op32 {
-    float C, A, inv_np1, max_step;
-};
-
-__device__ __forceinline__ Op32 op32(const Grid& g)
-{
-    return Op32{(float)g.C, (float)g.A, (float)g.inv_np1, (float)g.max_step};
-}
-
-// expm1 in single precision: Taylor series to x^6 for |x| < 1/8 (truncation < 1e-10
-// relative), exp(x) - 1 above.  Corrections are small once the outer loop has started to
-// converge, so the exponential is a branch that whole wavefronts skip.
-__device__ __forceinline__ float em1f(float x)
-{
-    float r = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f + x * (1.0f / 720.0f))))));
-    if (__builtin_expect(!(fabsf(x) < 0.125f), 0)) r = __expf(x) - 1.0f;
-    return r;
-}
-
-// Per-cell values a neighbour needs: base, correction, B = b e^e, M = b (e^e - 1).
-struct V32 {
-    float ub, e, B, M;
-};
-
-__device__ __forceinline__ V32 make_v(float ub, float e)
-{
-    V32 v;
-    v.ub = ub;
-    v.e = e;
-    const float b = __expf(ub);
-    v.M = b * em1f(e);
-    v.B = b + v.M;
-    return v;
-}
-
-struct Res32 {
-    float N, dN;
-};
-
-// N_i - f_i and dN_i/de_i.  The flux sum (M_nb + M_i) du + (B_nb + B_i) de is split into
-// the neighbour parts and M_i sum(du) + B_i sum(de).
-__device__ __forceinline__ Res32 corr_op(const Op32& o, const V32& c, const V32 (&nb)[6], float f)
-{
-    float t1 = 0.0f, t2 = 0.0f, su = 0.0f, se = 0.0f, sB = 0.0f;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const float du = nb[q].ub - c.ub, de = nb[q].e - c.e;
-        t1 = fmaf(nb[q].M, du, t1);
-        t2 = fmaf(nb[q].B, de, t2);
-        su += du;
-        se += de;
-        sB += nb[q].B;
-    }
-    const float S = o.A * __expf(-c.ub * o.inv_np1);
-    const float x = em1f(-c.e * o.inv_np1);
-    Res32 r;
-    r.N = o.C * (fmaf(c.M, su, t1) + fmaf(c.B, se, t2)) + S * x - f;
-    r.dN = o.C * (c.B * (su + se) - sB - 6.0f * c.B) - S * o.inv_np1 * (1.0f + x);
-    return r;
-}
-
-// Newton step -N/dN through the hardware reciprocal (about 1 ulp), bounded to [-ms, ms]
-// when ms > 0; a NaN step stays NaN.
-__device__ __forceinline__ float newton32(const Res32& r, float ms)
-{
-    float step = -r.N * __builtin_amdgcn_rcpf(r.dN);
-    if (ms > 0.0f) {
-        if (step > ms) step = ms;
-        if (step < -ms) step = -ms;
-    }
-    return step;
-}
 
 __device__ __forceinline__ long long at(int lg, int i, int j, int k)
 {
@@ -130,7 +59,7 @@ __global__ void __launch_bounds__(kBlock) k32_ngs_colour(Grid g, const float* __
 #pragma unroll
     for (int v = 0; v < 6; ++v) nb[v] = make_v(ub[qn[v]], e[qn[v]]);
     const V32 c = make_v(ub[q], e[q]);
-    const Res32 r = corr_op(o, c, nb, f[q]);
+    const Res32 r = dev32::corr_op(o, c, nb, f[q]);
     e[q] = c.e + newton32(r, o.max_step);
 }
 
@@ -229,7 +158,7 @@ __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict_
         if (A.fl & 2) {
             const int c = A.c;
             const V32 nbv[6] = {A.v[M1], A.v[P1], LA[c - LK], LA[c + LK], LA[c - 1], LA[c + 1]};
-            const Res32 r = corr_op(o, A.v[P0], nbv, A.f[P0]);
+            const Res32 r = dev32::corr_op(o, A.v[P0], nbv, A.f[P0]);
             A.v[P0] = make_v(A.v[P0].ub, A.v[P0].e + newton32(r, o.max_step));
             LA[c] = A.v[P0];
         }
@@ -238,7 +167,7 @@ __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict_
                 const V32* LB = lv[buf(p - 1)];
                 const int c = A.c;
                 const V32 nbv[6] = {A.v[M2], A.v[P0], LB[c - LK], LB[c + LK], LB[c - 1], LB[c + 1]};
-                const Res32 r = corr_op(o, A.v[M1], nbv, A.f[M1]);
+                const Res32 r = dev32::corr_op(o, A.v[M1], nbv, A.f[M1]);
                 A.v[M1].e = A.v[M1].e + newton32(r, o.max_step);
                 eout[offset(p - 1, A)] = A.v[M1].e;
             }
@@ -357,7 +286,7 @@ __global__ void __launch_bounds__(NT) k32_resid_stream(Grid g, const float* __re
             const int c = threadIdx.x + s * NT;
             if (fl[s] & 2) {
                 const V32 nbv[6] = {vm1[s], vp1[s], LV[c - LK], LV[c + LK], LV[c - 1], LV[c + 1]};
-                const float d = corr_op(o, v0[s], nbv, f0[s]).N;
+                const float d = dev32::corr_op(o, v0[s], nbv, f0[s]).N;
                 if (second) {
                     re[li[s]] = eprev[s] + v0[s].e;
                     rd[li[s]] = dprev[s] + d;
@@ -426,7 +355,7 @@ __global__ void __launch_bounds__(kBlock) k32_resid_restrict(Grid g, const float
                 for (int v = 0; v < 6; ++v) nb[v] = make_v(ub[qn[v]], e[qn[v]]);
                 const V32 c = make_v(ub[q], e[q]);
                 se += c.e;
-                sd += corr_op(o, c, nb, f[q]).N;
+                sd += dev32::corr_op(o, c, nb, f[q]).N;
             }
     ec[tc] = 0.125f * se;
     ehat[tc] = 0.125f * se;
@@ -445,7 +374,7 @@ __global__ void __launch_bounds__(kBlock) k32_fas_rhs(Grid g, const float* __res
     V32 nb[6];
 #pragma unroll
     for (int v = 0; v < 6; ++v) nb[v] = make_v(ub[qn[v]], ehat[qn[v]]);
-    f[q] = corr_op(o, make_v(ub[q], ehat[q]), nb, 0.0f).N - f[q];
+    f[q] = dev32::corr_op(o, make_v(ub[q], ehat[q]), nb, 0.0f).N - f[q];
 }
 
 __global__ void __launch_bounds__(kBlock) k32_restrict_mean(int lgc, const float* __restrict__ fine,
@@ -500,7 +429,7 @@ __global__ void __launch_bounds__(kBlock) k32_coarsest(Grid g, const float* __re
         for (int q = threadIdx.x; q < nc; q += kBlock) {
             V32 c, nb[6];
             cell(q, c, nb);
-            const Res32 r = corr_op(o, c, nb, sf[q]);
+            const Res32 r = dev32::corr_op(o, c, nb, sf[q]);
             s += r.N * r.N;
             const float f1 = 1.1920929e-7f * (fabsf(r.dN) * fabsf(c.e) + fabsf(sf[q]));
             fl += f1 * f1;
@@ -532,7 +461,7 @@ __global__ void __launch_bounds__(kBlock) k32_coarsest(Grid g, const float* __re
             for (int q = threadIdx.x; q < nc; q += kBlock) {
                 V32 c, nb[6];
                 if (cell(q, c, nb) != colour) continue;
-                const Res32 r = corr_op(o, c, nb, sf[q]);
+                const Res32 r = dev32::corr_op(o, c, nb, sf[q]);
                 se[q] = c.e + newton32(r, o.max_step);
             }
             __syncthreads();

@@ -59,6 +59,11 @@ struct BGrid {
     double* f;         // coarse levels: FAS right-hand side
     const double* src; // finest: the density; coarse: == f
     double* ub;        // patch: boundary values [6][n][n]
+    // single-precision correction levels of a mixed solve (null in double precision)
+    float* ub32;       // base: finest = u rounded, coarse = R ub
+    float* e32;        // correction e
+    float* eh32;       // coarse: R e of the finer level, then e - R e
+    float* f32;        // finest: r = -d; coarse: the FAS right-hand side
 };
 
 // Workgroup table: blk[b] = (index into grids, block number within that grid).
@@ -92,6 +97,22 @@ hipError_t batch_setup(const BTable& t, int nblk, const PatchParent* parents, hi
 hipError_t batch_restrict_faces(const BTable& t, int nblk, const BGrid* fine, hipStream_t s);
 hipError_t batch_fill(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_nonfinite(const BTable& t, int nblk, double* partial, hipStream_t s);
+
+// ---- batched mixed-precision solves (batch_fp32.hip; the double-precision parts in
+// batch_fp64.hip) ------------------------------------------------------------------------------
+// Finest grids (double precision): d = L(u) - f with ghost faces; r = -d, ub = u in single
+// precision, e = 0; block partials of (sum d^2, max |d|) as batch_norm.
+hipError_t batch_resid_cast(const BTable& t, int nblk, double* partial, hipStream_t s);
+// Finest grids: u += e.
+hipError_t batch_add_correction(const BTable& t, int nblk, hipStream_t s);
+// Coarse base R ub (table over the coarse cells, indexed by the fine grids).
+hipError_t batch_restrict_base32(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
+hipError_t batch_ngs32(const BTable& t, int nblk, hipStream_t s);
+hipError_t batch_resid_restrict32(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
+hipError_t batch_fas_rhs32(const BTable& t, int nblk, hipStream_t s);
+hipError_t batch_coarse_diff32(const BTable& t, int nblk, hipStream_t s);
+hipError_t batch_prolong_add32(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
+hipError_t batch_coarsest32(const BGrid* grids, int ngrid, const int* active, int cap, double rtol, hipStream_t s);
 
 // ---- FP64 kernels (kernels_fp64.hip) -----------------------------------------------
 // All launchers queue work on `s` and return the hipError_t of the launch.

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmgfr.so")
 
 MGFR_OK, MGFR_EINVAL, MGFR_ENONFINITE, MGFR_ENOTCONV, MGFR_EDEVICE, MGFR_ENOMEM = 0, -1, -2, -3, -4, -5
 MGFR_FP64, MGFR_MIXED = 0, 1
-MGFR_SUBTRACT_MEAN, MGFR_WARM_START, MGFR_PROFILE = 1, 2, 4
+MGFR_SUBTRACT_MEAN, MGFR_WARM_START, MGFR_PROFILE, MGFR_GRAPH = 1, 2, 4, 8
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENONFINITE", -3: "ENOTCONV", -4: "EDEVICE", -5: "ENOMEM"}
 
 
