@@ -247,7 +247,8 @@ def bench_amr(args):
     rp = torch.from_numpy(rho_packed).to("cuda:0")
     runs, fields = {}, {}
     for name, code in _precisions(mgfr, args):
-        opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code)
+        opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code,
+                                      flags=0 if args.no_graph else mgfr.MGFR_GRAPH)
         up = torch.empty_like(rp)
 
         def solve():
@@ -272,7 +273,7 @@ def bench_amr(args):
            "config": {"workload": f"amr: {N0}^3 domain (lognormal sigma 2), {len(patches)} cube patches "
                                   f"8^3-64^3 over {max(p['level'] for p in patches)} levels "
                                   f"(contrast > 50/200/1000), {cells} patch cells, tol {args.tol:g}",
-                      "precision": headp}}
+                      "precision": headp, "graph": not args.no_graph}}
     out.update(runs)
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
@@ -292,7 +293,8 @@ def bench_batch(args):
     ctx = mgfr.Context(0)
     runs, fields = {}, {}
     for name, code in _precisions(mgfr, args):
-        opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code)
+        opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code,
+                                      flags=0 if args.no_graph else mgfr.MGFR_GRAPH)
         us = [torch.empty_like(r) for r in rhos]
 
         def solve():
@@ -317,7 +319,7 @@ def bench_batch(args):
            "data": "synthetic",
            "config": {"workload": "batch: 64 x 64^3 (B=64) + 16 x 128^3 (B=128), |f_R0| log-uniform "
                                   f"[1e-6,1e-4], lognormal sigma U[1,3], tol {args.tol:g}",
-                      "precision": headp}}
+                      "precision": headp, "graph": not args.no_graph}}
     out.update(runs)
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
@@ -334,6 +336,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="amr/batch: launch every cycle eagerly instead of replaying a HIP graph")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy three times (calibrates HBM counters)")
     args = ap.parse_args()

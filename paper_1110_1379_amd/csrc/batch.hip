@@ -91,25 +91,35 @@ struct Batch {
     std::vector<int> active;
     double* dpartial = nullptr;
     double* dout = nullptr;
-    std::vector<double> hout;
-    std::vector<void*> owned;
+    double* hout = nullptr;  // pinned: per-unit (sum d^2, max |d|) read back every cycle
+    int* hact = nullptr;     // pinned: per-unit active flags uploaded every cycle
+    std::vector<std::pair<void*, size_t>> owned;
 
+    // Device blocks go back to the context for the next batched solve once this one's work
+    // has finished.
     ~Batch()
     {
-        if (gexec || cap_stream) (void)hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
-        for (void* p : owned) (void)hipFree(p);
+        for (auto& b : owned) c->spare.push_back(b);
     }
 
     template <class T>
     int alloc(T** p, size_t count)
     {
         if (count == 0) count = 1;
-        if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess)
-            return c->fail(MGFR_ENOMEM, "hipMalloc of %zu bytes for a batch failed", count * sizeof(T));
-        owned.push_back(*p);
+        const size_t bytes = count * sizeof(T);
+        void* q = c->take_spare(bytes);
+        if (!q && hipMalloc(&q, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            c->free_spare();  // give cached blocks back and try once more
+            if (hipMalloc(&q, bytes) != hipSuccess)
+                return c->fail(MGFR_ENOMEM, "hipMalloc of %zu bytes for a batch failed", bytes);
+        }
+        *p = (T*)q;
+        owned.emplace_back(q, bytes);
         return MGFR_OK;
     }
 
@@ -274,23 +284,37 @@ struct Batch {
 
     int upload()
     {
+        // pinned staging: [per-unit (sum, max) | per-unit flags | descriptor image]
+        const size_t nu = units.size();
+        const size_t meta_at = (sizeof(double) * 2 * nu + sizeof(int) * nu + 255) & ~size_t(255);
+        MGFR_TRY(ensure_pinned(c, meta_at + meta_image.size()));
+        hout = (double*)c->pin;
+        hact = (int*)(hout + 2 * nu);
+        char* hmeta = (char*)c->pin + meta_at;
+        std::memcpy(hmeta, meta_image.data(), meta_image.size());
         MGFR_TRY(alloc(&dmeta, meta_image.size()));
-        MGFR_TRY(hip_check(c, hipMemcpyAsync(dmeta, meta_image.data(), meta_image.size(), hipMemcpyHostToDevice, s),
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(dmeta, hmeta, meta_image.size(), hipMemcpyHostToDevice, s),
                            "hipMemcpyAsync"));
-        MGFR_TRY(alloc(&dactive, units.size()));
-        active.assign(units.size(), 1);
-        MGFR_TRY(hip_check(c, hipMemcpyAsync(dactive, active.data(), sizeof(int) * active.size(),
-                                             hipMemcpyHostToDevice, s),
-                           "hipMemcpyAsync"));
+        MGFR_TRY(alloc(&dactive, nu));
+        active.assign(nu, 1);
+        MGFR_TRY(upload_active());
         MGFR_TRY(alloc(&dpartial, 2 * (size_t)std::max<long long>(plan.nblk_cells0, 1)));
-        MGFR_TRY(alloc(&dout, 2 * units.size()));
-        hout.assign(2 * units.size(), 0.0);
-        // the host image must stay alive until the copy has run
+        MGFR_TRY(alloc(&dout, 2 * nu));
+        // the staging area must stay unchanged until the copies have run
         return hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize");
     }
 
     // Cell updates of one V-cycle of the active units (pre + post sweeps on every level
     // above the coarsest), added to the statistics per cycle run.
+    // Copies the host active flags to the device (through pinned memory, so the copy is a
+    // direct transfer; the staging area is next rewritten after a later synchronisation).
+    int upload_active()
+    {
+        std::copy(active.begin(), active.end(), hact);
+        return hip_check(c, hipMemcpyAsync(dactive, hact, sizeof(int) * active.size(), hipMemcpyHostToDevice, s),
+                         "hipMemcpyAsync");
+    }
+
     void count_vcycle(int times)
     {
         for (size_t i = 0; i < units.size(); ++i) {
@@ -312,7 +336,7 @@ struct Batch {
     {
         const Depth& D = plan.depth[m];
         if (D.coarsest)
-            MGFR_TRY(hip_check(c, mgfr::batch_coarsest(grids(D.crs), D.crs.ngrid, dactive, o->coarsest_sweeps,
+            MGFR_TRY(hip_check(c, mgfr::batch_coarsest(grids(D.crs), D.crs.ngrid, o->coarsest_n, dactive, o->coarsest_sweeps,
                                                        o->coarsest_rtol, s),
                                "batch_coarsest"));
         if (!D.deep) return MGFR_OK;
@@ -340,7 +364,7 @@ struct Batch {
     {
         const Depth& D = plan.depth[m];
         if (D.coarsest)
-            MGFR_TRY(hip_check(c, mgfr::batch_coarsest32(grids(D.crs), D.crs.ngrid, dactive, o->coarsest_sweeps,
+            MGFR_TRY(hip_check(c, mgfr::batch_coarsest32(grids(D.crs), D.crs.ngrid, o->coarsest_n, dactive, o->coarsest_sweeps,
                                                          o->coarsest_rtol, s),
                                "batch_coarsest32"));
         if (!D.deep) return MGFR_OK;
@@ -380,7 +404,7 @@ struct Batch {
         MGFR_TRY(hip_check(c, mgfr::batch_fold(dpartial, (const int*)(dmeta + plan.first),
                                                (const int*)(dmeta + plan.count), plan.nunit, dout, s),
                            "batch_fold"));
-        MGFR_TRY(hip_check(c, hipMemcpyAsync(hout.data(), dout, sizeof(double) * hout.size(), hipMemcpyDeviceToHost, s),
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(hout, dout, sizeof(double) * 2 * units.size(), hipMemcpyDeviceToHost, s),
                            "hipMemcpyAsync"));
         MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
         for (size_t i = 0; i < units.size(); ++i) {
@@ -411,7 +435,7 @@ struct Batch {
                                                (const int*)(dmeta + plan.first), (const int*)(dmeta + plan.count),
                                                plan.nunit, dout, s),
                            "batch_norm"));
-        MGFR_TRY(hip_check(c, hipMemcpyAsync(hout.data(), dout, sizeof(double) * hout.size(), hipMemcpyDeviceToHost, s),
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(hout, dout, sizeof(double) * 2 * units.size(), hipMemcpyDeviceToHost, s),
                            "hipMemcpyAsync"));
         MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
         for (size_t i = 0; i < units.size(); ++i) {
@@ -428,7 +452,7 @@ struct Batch {
         MGFR_TRY(hip_check(c, mgfr::batch_fold(dpartial, (const int*)(dmeta + plan.first),
                                                (const int*)(dmeta + plan.count), plan.nunit, dout, s),
                            "batch_fold"));
-        MGFR_TRY(hip_check(c, hipMemcpyAsync(hout.data(), dout, sizeof(double) * hout.size(), hipMemcpyDeviceToHost, s),
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(hout, dout, sizeof(double) * 2 * units.size(), hipMemcpyDeviceToHost, s),
                            "hipMemcpyAsync"));
         MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
         for (size_t i = 0; i < units.size(); ++i)
@@ -495,9 +519,7 @@ struct Batch {
             bool any = false;
             for (size_t i = 0; i < units.size(); ++i) any = any || active[i];
             if (!any || cycles >= o->max_cycles) break;
-            MGFR_TRY(hip_check(c, hipMemcpyAsync(dactive, active.data(), sizeof(int) * active.size(),
-                                                 hipMemcpyHostToDevice, s),
-                               "hipMemcpyAsync"));
+            MGFR_TRY(upload_active());
             MGFR_TRY(cycle());
             count_vcycle(mixed ? o->inner_cycles : 1);
             if (mixed) {

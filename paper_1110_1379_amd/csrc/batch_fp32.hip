@@ -194,35 +194,91 @@ __global__ void __launch_bounds__(kB) kb32_prolong_add(BTable t, const BGrid* __
 }
 
 // ---- coarsest level: one workgroup per grid (n <= 8) --------------------------------------
-__global__ void __launch_bounds__(kB) kb32_coarsest(const BGrid* __restrict__ grids, const int* __restrict__ active,
+// Everything that depends only on the base stays in LDS for the whole solve: ub, b = exp(ub),
+// the curvature coefficient S, and per ghost face ub_g - ub_i and b_g; per sweep only the
+// correction-dependent parts (M, B) of the updated cells are recomputed.  The arithmetic is
+// that of bcell32, in the same order.
+template <int NT>
+__global__ void __launch_bounds__(NT) kb32_coarsest(const BGrid* __restrict__ grids, const int* __restrict__ active,
                                                    int cap, float rtol)
 {
-    __shared__ float sub[512], se[512], sf[512];
-    __shared__ float ra[kB], rb[kB];
+    __shared__ float sub[512], sb[512], se[512], sB[512], sM[512], sf[512], sS[512];
+    __shared__ float gdu[6][512], gbb[6][512];
+    __shared__ float ra[NT], rb[NT];
     const BGrid g = grids[blockIdx.x];
     if (active && !active[g.unit]) return;
     const Op32 o = op32(g);
-    const int nc = 1 << (3 * g.lg);
-    for (int q = threadIdx.x; q < nc; q += kB) {
-        sub[q] = g.ub32[q];
-        se[q] = g.e32[q];
+    const int nc = 1 << (3 * g.lg), m = g.n - 1;
+    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+    auto ghost = [&](int q, int f) {
+        const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
+        const int ii = i + di[f], jj = j + dj[f], kk = k + dk[f];
+        return !g.periodic && (ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m);
+    };
+    for (int q = threadIdx.x; q < nc; q += NT) {
+        const V32 v = make_v(g.ub32[q], g.e32[q]);
+        sub[q] = v.ub;
+        sb[q] = __expf(v.ub);
+        se[q] = v.e;
+        sB[q] = v.B;
+        sM[q] = v.M;
         sf[q] = g.f32[q];
+        sS[q] = o.A * __expf(-v.ub * o.inv_np1);
+        const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
+        for (int f = 0; f < 6; ++f) {
+            gdu[f][q] = 0.0f;
+            gbb[f][q] = 0.0f;
+            if (ghost(q, f)) {
+                const float ubg = (1.0f - kR) * face_ub32(g, f, i, j, k) + kR * v.ub;
+                gdu[f][q] = ubg - v.ub;
+                gbb[f][q] = __expf(ubg);
+            }
+        }
     }
     __syncthreads();
+    auto cell = [&](int q, float& dN) -> float {
+        const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
+        const float cub = sub[q], ce = se[q], cB = sB[q], cM = sM[q];
+        float t1 = 0.0f, t2 = 0.0f, su = 0.0f, sE = 0.0f, sBn = 0.0f, nreg = 0.0f, lgh = 0.0f, dgh = 0.0f;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (ghost(q, f)) {
+                const float eg = kR * ce;
+                const float bg = gbb[f][q];
+                const float Mg = bg * em1f(eg), Bg = bg + Mg;
+                const float du = gdu[f][q], de = eg - ce;
+                lgh += (Mg + cM) * du + (Bg + cB) * de;
+                dgh += (kR * Bg + cB) * (du + de) + (Bg + cB) * (kR - 1.0f);
+            } else {
+                const int qn = (((i + di[f]) & m) << (2 * g.lg)) + (((j + dj[f]) & m) << g.lg) + ((k + dk[f]) & m);
+                const float du = sub[qn] - cub, de = se[qn] - ce;
+                t1 = fmaf(sM[qn], du, t1);
+                t2 = fmaf(sB[qn], de, t2);
+                su += du;
+                sE += de;
+                sBn += sB[qn];
+                nreg += 1.0f;
+            }
+        }
+        const float S = sS[q];
+        const float x = em1f(-ce * o.inv_np1);
+        dN = o.C * (cB * (su + sE) - sBn - nreg * cB + dgh) - S * o.inv_np1 * (1.0f + x);
+        return o.C * (fmaf(cM, su, t1) + fmaf(cB, sE, t2) + lgh) + S * x - sf[q];
+    };
     // rms of N - f and its single-precision rounding floor (|dN||e| + |f|)
     auto rms = [&](float& floor) {
         float s = 0.0f, fl = 0.0f;
-        for (int q = threadIdx.x; q < nc; q += kB) {
-            const int i = q >> (2 * g.lg), j = (q >> g.lg) & (g.n - 1), k = q & (g.n - 1);
-            const Res32 r = bcell32(g, o, sub, se, i, j, k, sf[q]);
-            s += r.N * r.N;
-            const float f1 = 1.1920929e-7f * (fabsf(r.dN) * fabsf(se[q]) + fabsf(sf[q]));
+        for (int q = threadIdx.x; q < nc; q += NT) {
+            float dN;
+            const float N = cell(q, dN);
+            s += N * N;
+            const float f1 = 1.1920929e-7f * (fabsf(dN) * fabsf(se[q]) + fabsf(sf[q]));
             fl += f1 * f1;
         }
         ra[threadIdx.x] = s;
         rb[threadIdx.x] = fl;
         __syncthreads();
-        for (int w = kB / 2; w > 0; w >>= 1) {
+        for (int w = NT / 2; w > 0; w >>= 1) {
             if (threadIdx.x < w) {
                 ra[threadIdx.x] += ra[threadIdx.x + w];
                 rb[threadIdx.x] += rb[threadIdx.x + w];
@@ -243,16 +299,21 @@ __global__ void __launch_bounds__(kB) kb32_coarsest(const BGrid* __restrict__ gr
             if (r <= rtol * r0 || r <= fl) break;
         }
         for (int colour = 0; colour < 2; ++colour) {
-            for (int q = threadIdx.x; q < nc; q += kB) {
-                const int i = q >> (2 * g.lg), j = (q >> g.lg) & (g.n - 1), k = q & (g.n - 1);
+            for (int q = threadIdx.x; q < nc; q += NT) {
+                const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
                 if (((i + j + k) & 1) != colour) continue;
-                const Res32 r = bcell32(g, o, sub, se, i, j, k, sf[q]);
-                se[q] = se[q] + newton32(r, o.max_step);
+                Res32 r;
+                r.N = cell(q, r.dN);
+                const float e = se[q] + newton32(r, o.max_step);
+                const float M = sb[q] * em1f(e);
+                se[q] = e;
+                sM[q] = M;
+                sB[q] = sb[q] + M;
             }
             __syncthreads();
         }
     }
-    for (int q = threadIdx.x; q < nc; q += kB) g.e32[q] = se[q];
+    for (int q = threadIdx.x; q < nc; q += NT) g.e32[q] = se[q];
 }
 
 }  // namespace
@@ -287,9 +348,14 @@ hipError_t batch_prolong_add32(const BTable& t, int nblk, const BGrid* coarse, h
     hipLaunchKernelGGL(kb32_prolong_add, dim3(nblk), dim3(kB), 0, s, t, coarse);
     return hipGetLastError();
 }
-hipError_t batch_coarsest32(const BGrid* grids, int ngrid, const int* active, int cap, double rtol, hipStream_t s)
+hipError_t batch_coarsest32(const BGrid* grids, int ngrid, int n, const int* active, int cap, double rtol,
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL(kb32_coarsest, dim3(ngrid), dim3(kB), 0, s, grids, active, cap, (float)rtol);
+    // one wavefront per grid when it fits (barriers and reductions stay within the wave)
+    if (n <= 4)
+        hipLaunchKernelGGL((kb32_coarsest<64>), dim3(ngrid), dim3(64), 0, s, grids, active, cap, (float)rtol);
+    else
+        hipLaunchKernelGGL((kb32_coarsest<kB>), dim3(ngrid), dim3(kB), 0, s, grids, active, cap, (float)rtol);
     return hipGetLastError();
 }
 

@@ -163,24 +163,60 @@ __global__ void __launch_bounds__(kB) kb_prolong_add(BTable t, const BGrid* __re
 }
 
 // ---- coarsest level: one workgroup per grid (n <= 8) --------------------------------------
-__global__ void __launch_bounds__(kB) kb_coarsest(const BGrid* __restrict__ grids, const int* __restrict__ active,
+// b = exp(u) and the curvature term S of every cell stay in LDS and are refreshed when the
+// cell is updated, so a visit evaluates exponentials only for its ghost faces.  The
+// arithmetic is that of bcell, in the same order.
+template <int NT>
+__global__ void __launch_bounds__(NT) kb_coarsest(const BGrid* __restrict__ grids, const int* __restrict__ active,
                                                  int cap, double rtol)
 {
-    __shared__ double su[512], sf[512];
-    __shared__ double ra[kB], rb[kB];
+    __shared__ double su[512], sb[512], sS[512], sf[512];
+    __shared__ double ra[NT], rb[NT];
     const BGrid g = grids[blockIdx.x];
     if (active && !active[g.unit]) return;
-    const int nc = 1 << (3 * g.lg);
-    for (int q = threadIdx.x; q < nc; q += kB) {
+    const int nc = 1 << (3 * g.lg), m = g.n - 1;
+    for (int q = threadIdx.x; q < nc; q += NT) {
         su[q] = g.u[q];
+        sb[q] = exp(su[q]);
+        sS[q] = g.A * exp(-su[q] * g.inv_np1);
         sf[q] = brhs(g, q);
     }
     __syncthreads();
+    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+    auto cell = [&](int q) -> OpVal {
+        const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
+        const double ui = su[q], bi = sb[q];
+        double s_u = 0.0, s_b = 0.0, sbu = 0.0, lg_ = 0.0, dlg = 0.0;
+        int nreg = 0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int ii = i + di[f], jj = j + dj[f], kk = k + dk[f];
+            const bool out = ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m;
+            if (out && !g.periodic) {
+                const double ug = (1.0 - kR) * face_ub(g, f, i, j, k) + kR * ui;
+                const double bg = exp(ug);
+                lg_ += (bg + bi) * (ug - ui);
+                dlg += (kR * bg + bi) * (ug - ui) + (bg + bi) * (kR - 1.0);
+            } else {
+                const int qn = ((ii & m) << (2 * g.lg)) + ((jj & m) << g.lg) + (kk & m);
+                const double bn = sb[qn], du = su[qn] - ui;
+                s_u += du;
+                s_b += bn;
+                sbu = fma(bn, du, sbu);
+                ++nreg;
+            }
+        }
+        const double S = sS[q];
+        OpVal r;
+        r.L = g.C * (fma(bi, s_u, sbu) + lg_) + S - sf[q];
+        r.dL = g.C * (fma(bi, s_u, -s_b) - nreg * bi + dlg) - S * g.inv_np1;
+        return r;
+    };
     auto reduce = [&](double a, double b, double& ta, double& tb) {
         ra[threadIdx.x] = a;
         rb[threadIdx.x] = b;
         __syncthreads();
-        for (int w = kB / 2; w > 0; w >>= 1) {
+        for (int w = NT / 2; w > 0; w >>= 1) {
             if (threadIdx.x < w) {
                 ra[threadIdx.x] += ra[threadIdx.x + w];
                 rb[threadIdx.x] += rb[threadIdx.x + w];
@@ -194,11 +230,10 @@ __global__ void __launch_bounds__(kB) kb_coarsest(const BGrid* __restrict__ grid
     // rms of L - f and its rounding floor (one unit in the last place of |dL||u| + |f| + S)
     auto rms = [&](double& floor) {
         double s = 0.0, fl = 0.0;
-        for (int q = threadIdx.x; q < nc; q += kB) {
-            const int i = q >> (2 * g.lg), j = (q >> g.lg) & (g.n - 1), k = q & (g.n - 1);
-            const OpVal r = bcell(g, su, i, j, k, sf[q]);
+        for (int q = threadIdx.x; q < nc; q += NT) {
+            const OpVal r = cell(q);
             s += r.L * r.L;
-            const double f1 = 2.220446049250313e-16 * (fabs(r.dL) * fabs(su[q]) + fabs(sf[q]) + g.A * exp(-su[q] * g.inv_np1));
+            const double f1 = 2.220446049250313e-16 * (fabs(r.dL) * fabs(su[q]) + fabs(sf[q]) + sS[q]);
             fl += f1 * f1;
         }
         double ts, tf;
@@ -215,16 +250,19 @@ __global__ void __launch_bounds__(kB) kb_coarsest(const BGrid* __restrict__ grid
             if (r <= rtol * r0 || r <= fl) break;
         }
         for (int colour = 0; colour < 2; ++colour) {
-            for (int q = threadIdx.x; q < nc; q += kB) {
-                const int i = q >> (2 * g.lg), j = (q >> g.lg) & (g.n - 1), k = q & (g.n - 1);
+            for (int q = threadIdx.x; q < nc; q += NT) {
+                const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
                 if (((i + j + k) & 1) != colour) continue;
-                const OpVal r = bcell(g, su, i, j, k, sf[q]);
-                su[q] = su[q] + dev::bounded(-r.L / r.dL, g.max_step);
+                const OpVal r = cell(q);
+                const double u = su[q] + dev::bounded(-r.L / r.dL, g.max_step);
+                su[q] = u;
+                sb[q] = exp(u);
+                sS[q] = g.A * exp(-u * g.inv_np1);
             }
             __syncthreads();
         }
     }
-    for (int q = threadIdx.x; q < nc; q += kB) g.u[q] = su[q];
+    for (int q = threadIdx.x; q < nc; q += NT) g.u[q] = su[q];
 }
 
 // ---- per-grid residual norms -------------------------------------------------------------
@@ -461,9 +499,14 @@ hipError_t batch_prolong_add(const BTable& t, int nblk, const BGrid* coarse, hip
     hipLaunchKernelGGL(kb_prolong_add, dim3(nblk), dim3(kB), 0, s, t, coarse);
     return hipGetLastError();
 }
-hipError_t batch_coarsest(const BGrid* grids, int ngrid, const int* active, int cap, double rtol, hipStream_t s)
+hipError_t batch_coarsest(const BGrid* grids, int ngrid, int n, const int* active, int cap, double rtol,
+                          hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_coarsest, dim3(ngrid), dim3(kB), 0, s, grids, active, cap, rtol);
+    // one wavefront per grid when it fits (barriers and reductions stay within the wave)
+    if (n <= 4)
+        hipLaunchKernelGGL((kb_coarsest<64>), dim3(ngrid), dim3(64), 0, s, grids, active, cap, rtol);
+    else
+        hipLaunchKernelGGL((kb_coarsest<kB>), dim3(ngrid), dim3(kB), 0, s, grids, active, cap, rtol);
     return hipGetLastError();
 }
 hipError_t batch_norm(const BTable& t, int nblk, double* partial, const int* first, const int* count, int ngrid,

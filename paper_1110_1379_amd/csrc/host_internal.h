@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mgfr.h"
@@ -83,6 +84,26 @@ struct mgfr_ctx {
     double* partial = nullptr;  // reduction scratch
     double* red = nullptr;      // device result of a reduction (2 doubles)
     double* host_red = nullptr; // pinned copy of it
+    void* pin = nullptr;        // pinned host staging of the batched solves' per-cycle copies
+    size_t pin_bytes = 0;
+    // device blocks of finished batched solves, reused by later ones (smallest that fits)
+    std::vector<std::pair<void*, size_t>> spare;
+
+    void* take_spare(size_t bytes)
+    {
+        size_t best = spare.size();
+        for (size_t i = 0; i < spare.size(); ++i)
+            if (spare[i].second >= bytes && (best == spare.size() || spare[i].second < spare[best].second)) best = i;
+        if (best == spare.size()) return nullptr;
+        void* p = spare[best].first;
+        spare.erase(spare.begin() + (long)best);
+        return p;
+    }
+    void free_spare()
+    {
+        for (auto& b : spare) (void)hipFree(b.first);
+        spare.clear();
+    }
     long long* counter = nullptr;  // device: coarsest-level sweeps of the current solve
     mgfr_stats stats{};
     // MGFR_PROFILE: event pairs around finest-level smoother launches
@@ -182,6 +203,22 @@ inline int ensure_scratch(mgfr_ctx* c)
         if (hipMalloc(&c->counter, sizeof(long long)) != hipSuccess)
             return c->fail(MGFR_ENOMEM, "hipMalloc of the sweep counter failed");
     }
+    return MGFR_OK;
+}
+
+// Pinned host buffer of at least `bytes` (kept in the context; contents not preserved).
+inline int ensure_pinned(mgfr_ctx* c, size_t bytes)
+{
+    if (c->pin_bytes >= bytes) return MGFR_OK;
+    if (c->pin) {
+        (void)hipDeviceSynchronize();
+        (void)hipHostFree(c->pin);
+        c->pin = nullptr;
+        c->pin_bytes = 0;
+    }
+    if (hipHostMalloc(&c->pin, bytes, hipHostMallocDefault) != hipSuccess)
+        return c->fail(MGFR_ENOMEM, "hipHostMalloc of %zu bytes failed", bytes);
+    c->pin_bytes = bytes;
     return MGFR_OK;
 }
 

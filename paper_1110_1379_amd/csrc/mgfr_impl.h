@@ -88,7 +88,9 @@ hipError_t batch_resid_restrict(const BTable& t, int nblk, const BGrid* coarse, 
 hipError_t batch_fas_rhs(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_coarse_diff(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_prolong_add(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
-hipError_t batch_coarsest(const BGrid* grids, int ngrid, const int* active, int cap, double rtol, hipStream_t s);
+// n: side of every grid in the list (the coarsest side, <= 8)
+hipError_t batch_coarsest(const BGrid* grids, int ngrid, int n, const int* active, int cap, double rtol,
+                          hipStream_t s);
 hipError_t batch_norm(const BTable& t, int nblk, double* partial, const int* first, const int* count, int ngrid,
                       double* out, hipStream_t s);
 hipError_t batch_fold(const double* partial, const int* first, const int* count, int ngrid, double* out,
@@ -112,7 +114,8 @@ hipError_t batch_resid_restrict32(const BTable& t, int nblk, const BGrid* coarse
 hipError_t batch_fas_rhs32(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_coarse_diff32(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_prolong_add32(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
-hipError_t batch_coarsest32(const BGrid* grids, int ngrid, const int* active, int cap, double rtol, hipStream_t s);
+hipError_t batch_coarsest32(const BGrid* grids, int ngrid, int n, const int* active, int cap, double rtol,
+                            hipStream_t s);
 
 // ---- FP64 kernels (kernels_fp64.hip) -----------------------------------------------
 // All launchers queue work on `s` and return the hipError_t of the launch.

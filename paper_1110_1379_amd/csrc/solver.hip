@@ -228,6 +228,8 @@ void mgfr_destroy(mgfr_ctx* c)
     (void)hipFree(c->counter);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->host_red) (void)hipHostFree(c->host_red);
+    if (c->pin) (void)hipHostFree(c->pin);
+    c->free_spare();
     delete c;
 }
 
