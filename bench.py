@@ -34,13 +34,14 @@ METRIC = "f(R) MG time-to-residual 1e-8 & cell-updates/s, 512^3, FP64 vs mixed"
 # of the sources those kernels were built from: when any of them differs the figure no longer
 # describes the kernel that runs and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "mixed": {"bytes": 2.540e9, "sources": {
-        "kernels_fp32.hip": "9875fee927415282cbaed15ab75138ba8ef914e879cbf3ea2718cf36cbbed74d",
-        "mgfr_impl.h": "aa7831585137f0c5228a1dec003e766a5565fc8bc0798311f427b0d459a201f3"}},
-    "fp64": {"bytes": 3.500e9, "sources": {
+    "mixed": {"bytes": 2.620e9, "sources": {
+        "kernels_fp32.hip": "d94c636fbf7cea404db182a5e9c93cb71f343adcb6c84d301b00ab6941af2905",
+        "device_fp32.h": "8e0b1788cfffc170c22c27c14ed38910f5eb958ebe543a31c498e8e0de7d38e0",
+        "mgfr_impl.h": "a3d1a03a5bc35087868460c1d6192e94158c44008ddf3555d1ce0d3445871012"}},
+    "fp64": {"bytes": 3.428e9, "sources": {
         "sweep_fp64.hip": "8626f8c275f300f245261a3ce754af32586572b601a374203ca3eeb1fd8c8850",
         "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
-        "mgfr_impl.h": "aa7831585137f0c5228a1dec003e766a5565fc8bc0798311f427b0d459a201f3"}},
+        "mgfr_impl.h": "a3d1a03a5bc35087868460c1d6192e94158c44008ddf3555d1ce0d3445871012"}},
 }
 
 
@@ -103,11 +104,22 @@ def cpu_baseline(name, tol):
             "time_to_tol_s": dt}
 
 
-def time_domain(mgfr, ctx, rho_d, params, prec, tol, steps, warmup, profile=True):
+def time_domain(mgfr, ctx, rho_d, params, prec, tol, steps, warmup, profile=True, autotune=True,
+                tune_cache=None):
     import torch
     u_d = torch.empty_like(rho_d)
     flags = mgfr.MGFR_PROFILE if profile else 0
     opts = mgfr.mgfr_default_opts(tol=tol, precision=prec, max_cycles=100, flags=flags)
+    tuned = None
+    if autotune:
+        # untimed: the library's autotuner times sweep counts, inner cycles and planes per
+        # workgroup on this very problem and the fastest setting is used below
+        best, tms = mgfr.mgfr_autotune(ctx, rho_d, params, base=opts, u_scratch=u_d, cache_path=tune_cache)
+        for k in mgfr.TUNED_FIELDS:
+            setattr(opts, k, getattr(best, k))
+        tuned = {k: getattr(best, k) for k in mgfr.TUNED_FIELDS}
+        tuned["autotune_best_ms"] = tms
+        log(f"autotuned prec={prec}: {tuned}")
     stream = torch.cuda.current_stream()
     for w in range(warmup):
         _, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, opts, u=u_d, stream=stream)
@@ -130,6 +142,7 @@ def time_domain(mgfr, ctx, rho_d, params, prec, tol, steps, warmup, profile=True
     launches = sum(s["sweep_launches"] for s in stats)
     achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
     res = {"ms_per_step": ms, "value": updates / (ms * 1e-3), "cycles": stats[-1]["cycles"],
+           "settings": tuned or {k: getattr(opts, k) for k in mgfr.TUNED_FIELDS},
            "inner_cycles": stats[-1]["inner_cycles"], "final_residual": float(hists[-1][-1]),
            "finest_cell_updates_per_s": finest / (ms * 1e-3),
            "smoother": {"achieved_GBs": achieved, "launches": launches,
@@ -152,7 +165,8 @@ def bench_domain(args):
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     for p in precs:
         code = mgfr.MGFR_MIXED if p == "mixed" else mgfr.MGFR_FP64
-        runs[p], fields[p] = time_domain(mgfr, ctx, rho_d, params, code, args.tol, args.steps, args.warmup)
+        runs[p], fields[p] = time_domain(mgfr, ctx, rho_d, params, code, args.tol, args.steps, args.warmup,
+                                         autotune=not args.no_autotune, tune_cache=args.tune_cache)
     head = runs["mixed"] if "mixed" in runs else runs["fp64"]
     headp = "mixed" if "mixed" in runs else "fp64"
     sm = head["smoother"]
@@ -171,7 +185,9 @@ def bench_domain(args):
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {N}^3 periodic, box {box:g} Mpc/h, |f_R0|={fr0:g}, n=1, "
                                f"Om=0.24, a=1; solve from the background to rms residual {args.tol:g}",
-                   "N": N, "tol": args.tol, "precision": headp, "pre_post": [2, 2], "coarsest": 4},
+                   "N": N, "tol": args.tol, "precision": headp,
+                   "pre_post": [head["settings"]["pre"], head["settings"]["post"]], "coarsest": 4,
+                   "autotuned": not args.no_autotune},
         "time_to_tol_ms": head["ms_per_step"],
         "cycles": head["cycles"],
         "final_residual": head["final_residual"],
@@ -336,6 +352,11 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="domain workloads: time the default options instead of autotuned ones")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of autotuned settings: reused when it holds this problem, else "
+                         "written after tuning (so that profiled runs time the same settings)")
     ap.add_argument("--no-graph", action="store_true",
                     help="amr/batch: launch every cycle eagerly instead of replaying a HIP graph")
     ap.add_argument("--copy-probe", action="store_true",
