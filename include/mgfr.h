@@ -203,6 +203,27 @@ int mg_fr_solve_batch(mgfr_ctx* ctx, int nbox, const int* N, const double* const
                       const mgfr_params* per_box, const mgfr_opts* opts, double* const* u,
                       double* res_hist, int* n_hist, void* stream);
 
+/* The modified Poisson equation (eq. discrete_poisson; Sec. II, Sec. III.B): the Newtonian
+ * potential phi of the density and of delta R of the scalaron f~_R = -exp(u), on the periodic
+ * N^3 grid (box side 1, h = 1/N):
+ *   (1/h^2) [sum of the 6 neighbours of phi - 6 phi] = S - mean(S),
+ *   S = 2 Om a (rho~ - 1) - (1/6) Om a^4 [(n a^2 xi)^(1/(n+1)) exp(-u/(n+1)) - 3 (a^-3 + 4 OL/Om)].
+ * The periodic system fixes phi up to a constant and needs a source of zero mean: the mean of
+ * S is removed and phi is returned with zero mean.  Linear multigrid V-cycles (Sec. V.A.3):
+ * red-black Gauss-Seidel (opts->pre / post sweeps), the residual restricted by 8-child means,
+ * the coarse correction prolongated 27/9/3/1, the coarsest level (opts->coarsest_n) relaxed
+ * as in mg_fr_solve; until rms(residual) <= opts->tol x rms(S - mean S) (a relative
+ * criterion: the equation is linear) or opts->max_cycles.
+ * rho, u   device, N^3 (read): the density and the scalaron, e.g. the solution of mg_fr_solve.
+ * phi      device, N^3: output (with MGFR_WARM_START in opts->flags, also the start).
+ * N        power of two in [2 coarsest_n, 1024].  opts->precision must be MGFR_FP64.
+ * res_hist host, max_cycles + 1 (may be NULL): rms residual before each cycle and at the end;
+ * n_hist   host (may be NULL): entries written.
+ * Returns MGFR_ENONFINITE for a non-finite source, MGFR_ENOTCONV if tol was not reached (phi
+ * still written).  Synchronises. */
+int mg_poisson_solve(mgfr_ctx* ctx, const double* rho, const double* u, int N, const mgfr_params* params,
+                     const mgfr_opts* opts, double* phi, double* res_hist, int* n_hist, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

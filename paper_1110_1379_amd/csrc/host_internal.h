@@ -86,6 +86,25 @@ struct mgfr_ctx {
     double* host_red = nullptr; // pinned copy of it
     void* pin = nullptr;        // pinned host staging of the batched solves' per-cycle copies
     size_t pin_bytes = 0;
+    // modified Poisson solve: levels (finest x is the caller's phi), source and scratch
+    struct PLevel {
+        mgfr::PGrid g{};
+        double* x = nullptr;    // coarse levels: the correction
+        double* b = nullptr;    // finest: the source S; coarse: the restricted residual
+        double* alt = nullptr;  // n >= 64: second buffer of the out-of-place fused sweep
+    };
+    int PN = 0, Pcoarsest = 0;
+    std::vector<PLevel> plv;
+    void free_poisson()
+    {
+        for (size_t m = 0; m < plv.size(); ++m) {
+            if (m > 0) (void)hipFree(plv[m].x);
+            (void)hipFree(plv[m].b);
+            (void)hipFree(plv[m].alt);
+        }
+        plv.clear();
+        PN = 0;
+    }
     // device blocks of finished batched solves, reused by later ones (smallest that fits)
     std::vector<std::pair<void*, size_t>> spare;
 

@@ -45,6 +45,42 @@ struct FusedSweep {
     int ntj, ntk;      // tiles along j and k (set by the launcher)
 };
 
+// ---- modified Poisson solve (poisson_kernels.hip) -----------------------------------------
+// One periodic level of the linear solve: side n = 2^lg, h^2 and 1/h^2 (h = 1/n on the box).
+struct PGrid {
+    int n, lg;
+    double hh, inv_hh;
+};
+
+// Constants of the source S = 2 D (rho~ - 1) - (A exp(-u inv_np1) - Sbar) / 2.
+struct PoissonSource {
+    double D, A, inv_np1, Sbar;
+};
+
+// Number of block partials the grid-stride reductions below write for n elements.
+int poisson_partials(long long n);
+// S at every cell, and block partials (sum S, max |S|) for fold_partials.
+hipError_t poisson_source(const PoissonSource& c, long long n3, const double* rho, const double* u, double* S,
+                          double* partial, hipStream_t s);
+// Block partials (sum r^2, max |r|) of r = b - bmean - lap x (x null: r = b - bmean).
+hipError_t poisson_resid_norm(const PGrid& g, const double* x, const double* b, double bmean, double* partial,
+                              hipStream_t s);
+// One red-black Gauss-Seidel sweep in place (one launch per colour).
+hipError_t poisson_ngs(const PGrid& g, double* x, const double* b, double bmean, hipStream_t s);
+// One red-black sweep from xin into xout (distinct arrays), n >= poisson_fused_min_n().
+int poisson_fused_min_n();
+hipError_t poisson_ngs_fused(const PGrid& g, const double* xin, double* xout, const double* b, double bmean, int ti,
+                             hipStream_t s);
+// bc = R (b - bmean - lap x) on the level below.
+hipError_t poisson_resid_restrict(const PGrid& g, const double* x, const double* b, double bmean, double* bc,
+                                  hipStream_t s);
+// Coarsest level (n <= 8) in one workgroup: x relaxed against b - bmean until rms <= rtol x
+// initial (or its rounding floor, or cap sweeps).
+hipError_t poisson_coarsest(const PGrid& g, double* x, const double* b, double bmean, int cap, double rtol,
+                            hipStream_t s);
+// x += v.
+hipError_t poisson_add(double* x, double v, long long n, hipStream_t s);
+
 // ---- batched units (batch_fp64.hip) ------------------------------------------------------
 // One multigrid level of one unit (a cube refinement patch or a periodic box).
 struct BGrid {
@@ -134,6 +170,8 @@ hipError_t fas_rhs(const Grid& gc, const double* uhat, double* f, hipStream_t s)
 // periodic; gc is the coarse level, 2 <= gc.n <= 512 (prolong.hip).
 hipError_t prolong_correct(const Grid& gc, double* uf, const double* uc, const double* uhat, hipStream_t s);
 hipError_t prolong_correct32(const Grid& gc, float* ef, const float* ec, const float* ehat, hipStream_t s);
+// uf += P(ec), the correction itself on the coarse level (linear correction scheme).
+hipError_t prolong_add_direct(const Grid& gc, double* uf, const double* ec, hipStream_t s);
 
 // Coarsest level in one workgroup: sweeps until rms(L - f) <= rtol x initial or `cap`
 // sweeps (rtol = 0: exactly cap sweeps).  n <= 8.  Adds the sweeps done to *sweeps_done

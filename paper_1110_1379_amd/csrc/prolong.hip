@@ -6,7 +6,8 @@
 // thread owns one fine column (j,k) and a chunk of fine planes: it forms the in-plane
 // interpolant once per coarse plane and reuses it for the two fine planes that need it, so
 // a fine cell costs one load and one store of u plus a share of the coarse reads.  The
-// difference e = u^H - R u^h is formed on the fly from the two coarse arrays.
+// difference e = u^H - R u^h is formed on the fly from the two coarse arrays (FAS); the
+// linear correction scheme passes the correction itself (no second array).
 #include "mgfr_impl.h"
 
 namespace mgfr {
@@ -14,7 +15,7 @@ namespace {
 
 constexpr int kPT = 256;  // threads (fine columns) per workgroup
 
-template <typename T, int PI>
+template <typename T, int PI, bool DIFF>
 __global__ void __launch_bounds__(kPT) k_prolong_stream(int lgc, T* __restrict__ uf, const T* __restrict__ uc,
                                                         const T* __restrict__ uhat, int ncolblk)
 {
@@ -44,7 +45,7 @@ __global__ void __launch_bounds__(kPT) k_prolong_stream(int lgc, T* __restrict__
 #pragma unroll
     for (int t = 0; t < PI / 2 + 2; ++t) {
         const unsigned base = (unsigned)((ib + t) & mc) << (2 * lgc);
-        auto E = [&](unsigned c) -> T { return uc[base + c] - uhat[base + c]; };
+        auto E = [&](unsigned c) -> T { return DIFF ? uc[base + c] - uhat[base + c] : uc[base + c]; };
         ep[t] = T(9.0 / 16.0) * E(c00) + T(3.0 / 16.0) * (E(c10) + E(c01)) + T(1.0 / 16.0) * E(c11);
     }
 #pragma unroll
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(kPT) k_prolong_stream(int lgc, T* __restrict__
     }
 }
 
-template <typename T>
+template <typename T, bool DIFF>
 hipError_t launch(const Grid& gc, T* uf, const T* uc, const T* uhat, hipStream_t s)
 {
     const int n = gc.n * 2;
@@ -65,9 +66,9 @@ hipError_t launch(const Grid& gc, T* uf, const T* uc, const T* uhat, hipStream_t
     const int ncolblk = (n * n + kPT - 1) / kPT;
     if (n >= 8) {
         const unsigned nb = (unsigned)(ncolblk * (n / 8));
-        hipLaunchKernelGGL((k_prolong_stream<T, 8>), dim3(nb), dim3(kPT), 0, s, gc.lg, uf, uc, uhat, ncolblk);
+        hipLaunchKernelGGL((k_prolong_stream<T, 8, DIFF>), dim3(nb), dim3(kPT), 0, s, gc.lg, uf, uc, uhat, ncolblk);
     } else {
-        hipLaunchKernelGGL((k_prolong_stream<T, 4>), dim3((unsigned)ncolblk), dim3(kPT), 0, s, gc.lg, uf, uc, uhat,
+        hipLaunchKernelGGL((k_prolong_stream<T, 4, DIFF>), dim3((unsigned)ncolblk), dim3(kPT), 0, s, gc.lg, uf, uc, uhat,
                            ncolblk);
     }
     return hipGetLastError();
@@ -77,12 +78,17 @@ hipError_t launch(const Grid& gc, T* uf, const T* uc, const T* uhat, hipStream_t
 
 hipError_t prolong_correct(const Grid& gc, double* uf, const double* uc, const double* uhat, hipStream_t s)
 {
-    return launch<double>(gc, uf, uc, uhat, s);
+    return launch<double, true>(gc, uf, uc, uhat, s);
 }
 
 hipError_t prolong_correct32(const Grid& gc, float* ef, const float* ec, const float* ehat, hipStream_t s)
 {
-    return launch<float>(gc, ef, ec, ehat, s);
+    return launch<float, true>(gc, ef, ec, ehat, s);
+}
+
+hipError_t prolong_add_direct(const Grid& gc, double* uf, const double* ec, hipStream_t s)
+{
+    return launch<double, false>(gc, uf, ec, nullptr, s);
 }
 
 }  // namespace mgfr

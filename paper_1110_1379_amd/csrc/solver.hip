@@ -230,6 +230,7 @@ void mgfr_destroy(mgfr_ctx* c)
     if (c->host_red) (void)hipHostFree(c->host_red);
     if (c->pin) (void)hipHostFree(c->pin);
     c->free_spare();
+    c->free_poisson();
     delete c;
 }
 

@@ -94,6 +94,7 @@ def lib():
             "mg_fr_solve_batch": ([vp, ctypes.c_int, ip, ctypes.POINTER(vp), P, O, ctypes.POINTER(vp), dp, ip, vp],
                                   ctypes.c_int),
             "mgfr_autotune": ([vp, vp, ctypes.c_int, P, O, vp, O, dp, vp], ctypes.c_int),
+            "mg_poisson_solve": ([vp, vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -106,7 +107,7 @@ def lib():
 def exported_symbols():
     return ("mgfr_create", "mgfr_destroy", "mgfr_last_error", "mgfr_default_opts", "mgfr_constants",
             "mgfr_residual", "mg_fr_solve", "mgfr_get_stats", "mgfr_smooth", "mg_fr_solve_patches",
-            "mg_fr_solve_batch", "mgfr_autotune")
+            "mg_fr_solve_batch", "mgfr_autotune", "mg_poisson_solve")
 
 
 def mgfr_default_opts(**overrides) -> mgfr_opts:
@@ -234,6 +235,27 @@ def mg_fr_solve(ctx: Context, rho, params: Params, opts: mgfr_opts | None = None
     if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
         raise MgfrError(st, ctx.last_error())
     return u, hist[:nh.value].copy(), st
+
+
+def mg_poisson_solve(ctx: Context, rho, u, params: Params, opts: mgfr_opts | None = None, phi=None,
+                     stream=None, raise_on_error: bool = True):
+    """The modified Poisson equation for the potential phi, given the density rho and the
+    scalaron u (float64 device tensors of shape (N, N, N)); opts.tol is relative to the rms of
+    the source.  Returns (phi, residual history as a numpy array, status)."""
+    import torch
+    N = rho.shape[0]
+    if opts is None:
+        opts = mgfr_default_opts()
+    if phi is None:
+        phi = torch.empty_like(rho)
+    hist = np.zeros(opts.max_cycles + 1)
+    nh = ctypes.c_int(0)
+    st = lib().mg_poisson_solve(ctx.handle, _ptr(rho), _ptr(u), N, ctypes.byref(params.c()), ctypes.byref(opts),
+                                _ptr(phi), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(nh),
+                                _stream(stream))
+    if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
+        raise MgfrError(st, ctx.last_error())
+    return phi, hist[:nh.value].copy(), st
 
 
 def mg_fr_solve_patches(ctx: Context, u_domain, patches, rho_packed, params: Params,
