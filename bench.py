@@ -42,6 +42,9 @@ MEASURED_TRAFFIC = {
         "sweep_fp64.hip": "8626f8c275f300f245261a3ce754af32586572b601a374203ca3eeb1fd8c8850",
         "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
         "mgfr_impl.h": "a3d1a03a5bc35087868460c1d6192e94158c44008ddf3555d1ce0d3445871012"}},
+    "poisson": {"bytes": 4.066e9, "sources": {
+        "poisson_kernels.hip": "9f8450a69b89060ccd64b388e3d917e830632923c46e8af95fe879c5e20f908d",
+        "mgfr_impl.h": "54f0112e8a32b398f1f64c43ab2b45410fbc2a4cc1a5e938fb4612e8f5bde746"}},
 }
 
 
@@ -221,6 +224,61 @@ def bench_domain(args):
     return out
 
 
+def bench_poisson(args):
+    """Modified Poisson solve (the potential of the density and of delta R) on the 512^3 halo
+    workload, with u from an untimed mixed f(R) solve of the same density; one step = one
+    Poisson solve from zero to rms residual <= tol x rms(source)."""
+    import torch
+    from paper_1110_1379_amd import mgfr
+    N, box, fr0 = 512, 512.0, 1e-6
+    log("generating halo512 density")
+    rho_h = make_density("halo512", N)
+    rho_d = torch.from_numpy(rho_h).to("cuda:0")
+    params = mgfr.Params(box_mpc_h=box, fr0_abs=fr0)
+    ctx = mgfr.Context(0)
+    u_d, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, mgfr.mgfr_default_opts(
+        tol=1e-8, precision=mgfr.MGFR_MIXED, inner_cycles=2, max_cycles=100))
+    assert st == mgfr.MGFR_OK, ctx.last_error()
+    phi = torch.empty_like(rho_d)
+    opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, flags=mgfr.MGFR_PROFILE)
+
+    def solve():
+        _, h, st = mgfr.mg_poisson_solve(ctx, rho_d, u_d, params, opts, phi=phi)
+        if st != mgfr.MGFR_OK:
+            raise SystemExit(f"Poisson solve failed: {ctx.last_error()}")
+        return h, mgfr.mgfr_get_stats(ctx)
+    ms, (h, s) = _timed(solve, args.steps, args.warmup)
+    achieved = s["sweep_bytes"] / (s["sweep_ms"] * 1e-3) / 1e9 if s["sweep_ms"] > 0 else None
+    out = {"metric": "modified Poisson solve (phi of rho and delta R(u)), 512^3: cells/s at relative residual 1e-8",
+           "value": N ** 3 / (ms * 1e-3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"poisson512: {N}^3 periodic, box {box:g} Mpc/h, |f_R0|={fr0:g}; u from the "
+                                  f"f(R) solve; linear V-cycles 2+2 to rms residual {args.tol:g} x rms(source)"},
+           "cycles": int(len(h) - 1), "cell_updates_per_s": s["cell_updates"] / (ms * 1e-3),
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                        "traffic": measured_traffic("poisson", N),
+                        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                        "kernel": "linear fused red-black sweep kp_fused (finest level)", "bytes_per_cell": 24,
+                        "launches": s["sweep_launches"],
+                        "avg_launch_ms": s["sweep_ms"] / s["sweep_launches"] if s["sweep_launches"] else None}}
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import poisson as P
+        from paper_1110_1379_amd import inputs
+        log("timing the CPU oracle on the same density (synthetic u)")
+        model = oracle.Model(box_mpc_h=box, fr0_abs=fr0)
+        u = oracle.constants(model, N)["ubar"] + inputs.gaussian_field(N, 1.0, -2.0, 11)
+        t0 = time.perf_counter()
+        P.solve(P.source(rho_h, u, model))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": N ** 3 / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole {N}^3 density with a seeded synthetic scalaron: exact periodic "
+                                         f"solve by FFT in numpy (float64), {dt:.1f} s"}
+    return out
+
+
 def _timed(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -348,7 +406,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="halo512", choices=sorted(WORKLOADS) + ["amr", "batch"])
+    ap.add_argument("--workload", default="halo512", choices=sorted(WORKLOADS) + ["amr", "batch", "poisson512"])
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -379,6 +437,8 @@ def main():
         out = bench_amr(args)
     elif args.workload == "batch":
         out = bench_batch(args)
+    elif args.workload == "poisson512":
+        out = bench_poisson(args)
     else:
         out = bench_domain(args)
     print(json.dumps(out))

@@ -62,9 +62,10 @@ int poisson_partials(long long n);
 // S at every cell, and block partials (sum S, max |S|) for fold_partials.
 hipError_t poisson_source(const PoissonSource& c, long long n3, const double* rho, const double* u, double* S,
                           double* partial, hipStream_t s);
-// Block partials (sum r^2, max |r|) of r = b - bmean - lap x (x null: r = b - bmean).
+// Block partials (sum r^2, max |r|) of r = b - bmean - lap x (x null: r = b - bmean); their
+// number (at most 8192) in *nparts.
 hipError_t poisson_resid_norm(const PGrid& g, const double* x, const double* b, double bmean, double* partial,
-                              hipStream_t s);
+                              int* nparts, hipStream_t s);
 // One red-black Gauss-Seidel sweep in place (one launch per colour).
 hipError_t poisson_ngs(const PGrid& g, double* x, const double* b, double bmean, hipStream_t s);
 // One red-black sweep from xin into xout (distinct arrays), n >= poisson_fused_min_n().

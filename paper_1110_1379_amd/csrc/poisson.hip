@@ -61,13 +61,31 @@ struct PCycle {
     int sweep(size_t m, double*& cur, double bm)
     {
         mgfr_ctx::PLevel& L = c->plv[m];
+        // MGFR_PROFILE: HIP events around every finest-level sweep, on the solve's stream
+        const bool timed = m == 0 && (o->flags & MGFR_PROFILE);
+        if (timed) {
+            if ((size_t)c->ev_used + 2 > c->ev.size()) {
+                for (int k = 0; k < 64; ++k) {
+                    hipEvent_t ev;
+                    MGFR_TRY(hip_check(c, hipEventCreate(&ev), "hipEventCreate"));
+                    c->ev.push_back(ev);
+                }
+            }
+            MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used], s), "hipEventRecord"));
+        }
         if (L.alt) {
             double* out = cur == L.alt ? (m == 0 ? finest_x : L.x) : L.alt;
-            const int ti = m == 0 && o->planes > 0 && o->planes <= L.g.n ? o->planes : std::min(L.g.n, 64);
+            const int ti = m == 0 && o->planes > 0 && o->planes <= L.g.n ? o->planes : mgfr::fused_sweep_planes(L.g.n);
             MGFR_TRY(hip_check(c, mgfr::poisson_ngs_fused(L.g, cur, out, L.b, bm, ti, s), "poisson_ngs_fused"));
             cur = out;
         } else {
             MGFR_TRY(hip_check(c, mgfr::poisson_ngs(L.g, cur, L.b, bm, s), "poisson_ngs"));
+        }
+        if (timed) {
+            MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
+            c->ev_used += 2;
+            c->stats.sweep_launches += L.alt ? 1 : 2;
+            c->stats.sweep_bytes += 24.0 * (double)(1LL << (3 * L.g.lg));  // read x, b; write x
         }
         c->stats.cell_updates += 1LL << (3 * L.g.lg);
         if (m == 0) c->stats.finest_updates += 1LL << (3 * L.g.lg);
@@ -99,13 +117,29 @@ struct PCycle {
         return MGFR_OK;
     }
 
+    // Sums the timed intervals recorded so far (synchronises) and releases the events.
+    int harvest()
+    {
+        if (c->ev_used == 0) return MGFR_OK;
+        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+        for (int k = 0; k < c->ev_used; k += 2) {
+            float ms = 0.0f;
+            MGFR_TRY(hip_check(c, hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]), "hipEventElapsedTime"));
+            c->stats.sweep_ms += ms;
+        }
+        c->ev_used = 0;
+        return MGFR_OK;
+    }
+
     // rms and max of b - bmean - lap x on the finest level (x null: of b - bmean); synchronises
     int norm(const double* x, double* rms, double* mx)
     {
         mgfr_ctx::PLevel& L = c->plv[0];
         const long long n3 = 1LL << (3 * L.g.lg);
-        MGFR_TRY(hip_check(c, mgfr::poisson_resid_norm(L.g, x, L.b, mean0, c->partial, s), "poisson_resid_norm"));
-        MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, mgfr::poisson_partials(n3), c->red, s), "fold_partials"));
+        int nparts = 0;
+        MGFR_TRY(hip_check(c, mgfr::poisson_resid_norm(L.g, x, L.b, mean0, c->partial, &nparts, s),
+                           "poisson_resid_norm"));
+        MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, nparts, c->red, s), "fold_partials"));
         double out[2];
         MGFR_TRY(read_reduction(c, s, out));
         *rms = std::sqrt(out[0] / (double)n3);
@@ -136,6 +170,7 @@ int mg_poisson_solve(mgfr_ctx* c, const double* rho, const double* u, int N, con
     hipStream_t s = (hipStream_t)stream;
     MGFR_TRY(ensure_scratch(c));
     MGFR_TRY(ensure_poisson(c, N, o->coarsest_n));
+    c->ev_used = 0;
     const long long n3 = (long long)N * N * N;
     mgfr_ctx::PLevel& L0 = c->plv[0];
 
@@ -168,6 +203,7 @@ int mg_poisson_solve(mgfr_ctx* c, const double* rho, const double* u, int N, con
             break;
         }
         MGFR_TRY(cyc.vcycle(0));
+        MGFR_TRY(cyc.harvest());
         ++k;
         MGFR_TRY(cyc.norm(phi, &rms, &mx));
         if (res_hist) res_hist[k] = rms;

@@ -253,6 +253,137 @@ __global__ void __launch_bounds__(kB) kp_resid_restrict(PGrid g, const double* _
     bc[tc] = 0.125 * s;
 }
 
+// ---- streaming residual (n >= 64): norm partials or restriction ----------------------------
+// r = b - bmean - lap x.  A workgroup owns a TJ x 64 tile of columns and a chunk of ti planes
+// (ti even): x of the tile plus a one-cell in-plane halo is staged in LDS per plane (two
+// buffers, one barrier per plane), the i-neighbours stay in registers, and the loads run two
+// planes ahead.  NORM: per-workgroup (sum r^2, max |r|); RESTRICT: 8-child means into bc.
+template <int TJ, int NT, bool RESTRICT>
+__global__ void __launch_bounds__(NT) kp_resid_stream(PGrid g, const double* __restrict__ x,
+                                                      const double* __restrict__ b, double bmean, int ti, int ntj,
+                                                      int ntk, double* __restrict__ out)
+{
+    constexpr int LJ = TJ + 2, LK = kTK + 2, NL = LJ * LK;
+    constexpr int NS = (NL + NT - 1) / NT;
+    __shared__ double lx[2][NL];
+    __shared__ double rr[RESTRICT ? TJ * kTK : 1];
+    __shared__ double red_s[NT], red_m[NT];
+    const int nb = gridDim.x;
+    int lid = blockIdx.x;
+    if ((nb & 7) == 0) lid = (lid & 7) * (nb >> 3) + (lid >> 3);
+    const int tk = lid % ntk;
+    lid /= ntk;
+    const int tj = lid % ntj;
+    const int ci = lid / ntj;
+    const int i0 = ci * ti, j0 = tj * TJ, k0 = tk * kTK;
+    const int lg = g.lg, m = g.n - 1;
+    const int last = i0 + ti;  // last plane read
+    unsigned col[NS];
+    int fl[NS], li[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int c = threadIdx.x + s * NT;
+        col[s] = 0;
+        fl[s] = li[s] = 0;
+        if (c < NL) {
+            const int jj = c / LK, kk = c - jj * LK;
+            col[s] = (unsigned)((((j0 - 1 + jj) & m) << lg) | ((k0 - 1 + kk) & m));
+            fl[s] = 1;
+            if (jj >= 1 && jj <= TJ && kk >= 1 && kk <= kTK) {
+                fl[s] |= 2;
+                li[s] = (jj - 1) * kTK + (kk - 1);
+            }
+        }
+    }
+    auto offset = [&](int p, int s) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + col[s]; };
+    // x of planes p-1, p, p+1 and b of plane p in registers; x of p+2 (and b of p+1) in flight
+    double xm1[NS], x0[NS], xp1[NS], xn2[NS], b0[NS], prev[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        xm1[s] = x0[s] = xp1[s] = xn2[s] = b0[s] = prev[s] = 0.0;
+        if (fl[s] & 2) b0[s] = b[offset(i0, s)];
+        if (fl[s]) {
+            xm1[s] = x[offset(i0 - 1, s)];
+            x0[s] = x[offset(i0, s)];
+            xp1[s] = x[offset(i0 + 1, s)];
+            xn2[s] = x[offset(i0 + 2, s)];
+            lx[0][threadIdx.x + s * NT] = x0[s];
+        }
+    }
+    __syncthreads();
+    double acc = 0.0, mx = 0.0;
+    for (int p = i0; p < i0 + ti; ++p) {
+        const bool more3 = p + 3 <= last, moreb = p + 1 < last;
+        double xn3[NS], b1[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            xn3[s] = b1[s] = 0.0;
+            if (fl[s] && more3) xn3[s] = x[offset(p + 3, s)];
+            if ((fl[s] & 2) && moreb) b1[s] = b[offset(p + 1, s)];
+        }
+        const double* LX = lx[(p - i0) & 1];
+        const bool second = RESTRICT && ((p - i0) & 1);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int c = threadIdx.x + s * NT;
+            if (fl[s] & 2) {
+                const double lap =
+                    (xm1[s] + xp1[s] + LX[c - LK] + LX[c + LK] + LX[c - 1] + LX[c + 1] - 6.0 * x0[s]) * g.inv_hh;
+                const double r = b0[s] - bmean - lap;
+                if (!RESTRICT) {
+                    acc += r * r;
+                    const double ar = fabs(r);
+                    if (!(mx >= ar)) mx = ar;
+                } else if (second) {
+                    rr[li[s]] = prev[s] + r;
+                } else {
+                    prev[s] = r;
+                }
+            }
+        }
+        if (second) {
+            __syncthreads();
+            const int lgc = lg - 1;
+            for (int t = threadIdx.x; t < (TJ / 2) * (kTK / 2); t += NT) {
+                const int cj = t / (kTK / 2), ck = t - cj * (kTK / 2);
+                const int q = (2 * cj) * kTK + 2 * ck;
+                const double sr = rr[q] + rr[q + 1] + rr[q + kTK] + rr[q + kTK + 1];
+                out[at3(lgc, (p & m) >> 1, (j0 >> 1) + cj, (k0 >> 1) + ck)] = 0.125 * sr;
+            }
+        }
+        double* NX = lx[(p + 1 - i0) & 1];
+        const bool more2 = p + 2 <= last;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (fl[s]) NX[threadIdx.x + s * NT] = xp1[s];
+            xm1[s] = x0[s];
+            x0[s] = xp1[s];
+            if (more2) xp1[s] = xn2[s];
+            xn2[s] = xn3[s];
+            b0[s] = b1[s];
+        }
+        __syncthreads();
+    }
+    if (!RESTRICT) {
+        const int t = threadIdx.x;
+        red_s[t] = acc;
+        red_m[t] = mx;
+        __syncthreads();
+        for (int w = NT / 2; w > 0; w >>= 1) {
+            if (t < w) {
+                red_s[t] += red_s[t + w];
+                const double o = red_m[t + w];
+                if (!(red_m[t] >= o)) red_m[t] = o;
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            out[2 * blockIdx.x] = red_s[0];
+            out[2 * blockIdx.x + 1] = red_m[0];
+        }
+    }
+}
+
 // ---- coarsest level in one workgroup (n <= 8) --------------------------------------------
 // Gauss-Seidel until rms(residual) <= rtol x initial, or down to its rounding floor, or cap
 // sweeps.  The periodic Laplacian has the constant null mode; the restricted residual has
@@ -340,10 +471,32 @@ hipError_t poisson_source(const PoissonSource& c, long long n3, const double* rh
     return hipGetLastError();
 }
 
-hipError_t poisson_resid_norm(const PGrid& g, const double* x, const double* b, double bmean, double* partial,
-                              hipStream_t s)
+// Streaming residual launch geometry: TJ x 64 tiles, ti planes per workgroup (even, dividing
+// n), few enough workgroups for the partial-sum scratch.
+constexpr int kRTJ = 8, kRNT = 256;
+
+int resid_planes(int n)
 {
-    hipLaunchKernelGGL(kp_resid_norm, dim3(grid_for(1LL << (3 * g.lg))), dim3(kB), 0, s, g, x, b, bmean, partial);
+    const long long tiles = (long long)(n / kRTJ) * (n / kTK);
+    int ti = 8;
+    while (ti < n && tiles * (n / ti) > 8192) ti *= 2;
+    return ti;
+}
+
+hipError_t poisson_resid_norm(const PGrid& g, const double* x, const double* b, double bmean, double* partial,
+                              int* nparts, hipStream_t s)
+{
+    if (x && g.n >= kTK && g.n <= 1024) {
+        const int ti = resid_planes(g.n), ntj = g.n / kRTJ, ntk = g.n / kTK;
+        const unsigned nb = (unsigned)((g.n / ti) * ntj * ntk);
+        *nparts = (int)nb;
+        hipLaunchKernelGGL((kp_resid_stream<kRTJ, kRNT, false>), dim3(nb), dim3(kRNT), 0, s, g, x, b, bmean, ti, ntj,
+                           ntk, partial);
+        return hipGetLastError();
+    }
+    const unsigned nb = grid_for(1LL << (3 * g.lg));
+    *nparts = (int)nb;
+    hipLaunchKernelGGL(kp_resid_norm, dim3(nb), dim3(kB), 0, s, g, x, b, bmean, partial);
     return hipGetLastError();
 }
 
@@ -356,7 +509,8 @@ hipError_t poisson_ngs(const PGrid& g, double* x, const double* b, double bmean,
     return hipGetLastError();
 }
 
-int poisson_fused_min_n() { return kTK; }
+// below 256 a level has too few tiles to fill the chip; the per-colour sweep is used there
+int poisson_fused_min_n() { return 4 * kTK; }
 
 hipError_t poisson_ngs_fused(const PGrid& g, const double* xin, double* xout, const double* b, double bmean, int ti,
                              hipStream_t s)
@@ -372,6 +526,13 @@ hipError_t poisson_ngs_fused(const PGrid& g, const double* xin, double* xout, co
 hipError_t poisson_resid_restrict(const PGrid& g, const double* x, const double* b, double bmean, double* bc,
                                   hipStream_t s)
 {
+    if (g.n >= kTK && g.n <= 1024) {
+        const int ti = resid_planes(g.n), ntj = g.n / kRTJ, ntk = g.n / kTK;
+        const unsigned nb = (unsigned)((g.n / ti) * ntj * ntk);
+        hipLaunchKernelGGL((kp_resid_stream<kRTJ, kRNT, true>), dim3(nb), dim3(kRNT), 0, s, g, x, b, bmean, ti, ntj,
+                           ntk, bc);
+        return hipGetLastError();
+    }
     const long long ncell = 1LL << (3 * (g.lg - 1));
     hipLaunchKernelGGL(kp_resid_restrict, dim3((unsigned)((ncell + kB - 1) / kB)), dim3(kB), 0, s, g, x, b, bmean, bc);
     return hipGetLastError();

@@ -5,10 +5,11 @@ The scalaron u that sources delta R is never taken from the GPU path: it is the 
 own f(R) solution (small grids) or a seeded synthetic field u_bar + g with g a smooth
 Gaussian field of unit scale (larger grids; the Poisson equation is linear in phi for any
 given u).  Bar: max|phi - phi*| / max|phi*| <= 1e-10 against the exact periodic solution,
-with the GPU solve taken to a relative residual of 1e-12 (1e-11 at 128^3, above the
-double-precision floor of the 7-point residual there).  At 512^3, in the configuration
-bench.py times, the stencil residual of the GPU potential is checked at sampled cells with
-the oracle's source.
+with the GPU solve taken to a relative residual of 1e-12 (1e-11 at 128^3, 1e-10 at 256^3:
+above the double-precision floor of the 7-point residual, which grows as N^2).  256^3 is the
+smallest level where the fused streaming sweep runs, so it is compared element by element.
+At 512^3, in the configuration bench.py times, the stencil residual of the GPU potential is
+checked at sampled cells with the oracle's source.
 """
 import sys
 
@@ -58,6 +59,7 @@ CASES = [
     ("oracle-u-32", 32, 64.0, 1e-5, lambda N: inputs.small_box(N, 0), "oracle"),
     ("synthetic-u-64", 64, 64.0, 1e-6, lambda N: inputs.halo_box(N, 2, count=4), "synthetic"),
     ("synthetic-u-128", 128, 128.0, 1e-5, lambda N: inputs.tophat_box(N, 1, count=25), "synthetic"),
+    ("synthetic-u-256", 256, 256.0, 1e-5, lambda N: inputs.tophat_box(N, 1, count=200), "synthetic"),
 ]
 
 
@@ -73,7 +75,7 @@ def test_poisson_matches_oracle(mg, ctx, name, N, box, fr0, make, usrc):
     else:
         u = synthetic_u(model, N, seed=N)
     ref = P.solve(P.source(rho, u, model))
-    tol = 1e-12 if N <= 64 else 1e-11
+    tol = 1e-12 if N <= 64 else 1e-11 if N <= 128 else 1e-10
     phi, hist, st = mg.mg_poisson_solve(ctx, dev(rho), dev(u), params, mg.mgfr_default_opts(tol=tol, max_cycles=60))
     assert st == mg.MGFR_OK, (ctx.last_error(), hist)
     g = phi.cpu().numpy()
