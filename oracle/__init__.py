@@ -173,6 +173,25 @@ def operator_at(u, model: Model, h: float, idx, rho=None, rho_ref: float = 1.0, 
     return out
 
 
+def restrict_mean(v):
+    """8-child mean onto the level with half the cells per side."""
+    v = _f64(v)
+    n = v.shape[0] // 2
+    return v.reshape(n, 2, n, 2, n, 2).mean(axis=(1, 3, 5))
+
+
+def tau(u, rho, model: Model, h: float | None = None, rho_ref: float = 1.0):
+    """Truncation-error estimate of Sec. V.B (the FAS relation): tau^h = L^H(R u) - R L^h(u) on
+    the periodic grid, each operator with its own level's density (R rho on the coarse level)
+    and cell size (H = 2h).  Written out from the definition with the oracle's operator."""
+    u = _f64(u)
+    n = u.shape[0]
+    h = 1.0 / n if h is None else h
+    LH, _ = operator(restrict_mean(u), model, 2.0 * h, rho=restrict_mean(rho), rho_ref=rho_ref)
+    Lh, _ = operator(u, model, h, rho=rho, rho_ref=rho_ref)
+    return LH - restrict_mean(Lh)
+
+
 def solve(rho, model: Model, opts: Opts | None = None, u0=None):
     """Periodic domain-grid solve.  Returns (u, residual history, status)."""
     opts = opts or Opts()
