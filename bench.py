@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -153,7 +154,39 @@ def time_domain(mgfr, ctx, rho_d, params, prec, tol, steps, warmup, profile=True
                         "bytes_per_cell_sweep": 24 if prec == mgfr.MGFR_FP64 else 16}}
     log(f"prec={prec}: {ms:.2f} ms/solve, {res['cycles']} cycles, smoother "
         f"{achieved and round(achieved)} GB/s over {launches} launches")
-    return res, u_d
+    return res, u_d, opts
+
+
+def stop_rule_comparison(mgfr, ctx, rho_d, params, opts, u_ref, steps=3):
+    """The solve of the timed configuration stopped by the truncation-error rule of Sec. V.B
+    with MLAPM's constants, rms(d) <= max(1e-6, 0.03 rms(tau)), against the field of the timed
+    solve (absolute tolerance): cycles, time and the difference in u and in f_R = -e^u.  Also
+    the cost of one standalone tau estimate.  Outside the timed region of the main metric."""
+    import ctypes
+    import torch
+    o = mgfr.mgfr_opts()
+    ctypes.memmove(ctypes.byref(o), ctypes.byref(opts), ctypes.sizeof(o))
+    o.tol, o.tau_alpha, o.flags = 1e-6, 0.03, 0
+    u_d = torch.empty_like(rho_d)
+    stream = torch.cuda.current_stream()
+
+    def solve():
+        _, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, o, u=u_d, stream=stream)
+        if st != mgfr.MGFR_OK:
+            raise SystemExit(f"tau-rule solve failed: {mgfr.STATUS_NAMES.get(st, st)} {ctx.last_error()}")
+        return hist
+
+    ms, hist = _timed(solve, steps, 1)
+    stats = mgfr.mgfr_get_stats(ctx)
+    du = (u_d - u_ref).abs().max().item()
+    tau_ms, (_, trms) = _timed(lambda: mgfr.mgfr_tau(ctx, rho_d, u_ref, params, stream=stream), steps, 1)
+    out = {"rule": "rms(d) <= max(1e-6, 0.03 rms(tau))", "ms_per_solve": ms, "cycles": len(hist) - 1,
+           "final_residual": float(hist[-1]), "tau_rms_at_stop": stats["tau_rms"],
+           "max_abs_du_vs_timed_solve": du, "max_rel_dfR_vs_timed_solve": math.expm1(du),
+           "tau_rms_of_timed_solution": trms, "tau_estimate_ms": tau_ms}
+    log(f"tau rule: {ms:.2f} ms, {out['cycles']} cycles, max |du| {du:.3e}, tau estimate {tau_ms:.3f} ms")
+    del u_d
+    return out
 
 
 def bench_domain(args):
@@ -164,11 +197,11 @@ def bench_domain(args):
     rho_d = torch.from_numpy(make_density(args.workload, N)).to("cuda:0")
     params = mgfr.Params(box_mpc_h=box, fr0_abs=fr0)
     ctx = mgfr.Context(0)
-    runs, fields = {}, {}
+    runs, fields, used = {}, {}, {}
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     for p in precs:
         code = mgfr.MGFR_MIXED if p == "mixed" else mgfr.MGFR_FP64
-        runs[p], fields[p] = time_domain(mgfr, ctx, rho_d, params, code, args.tol, args.steps, args.warmup,
+        runs[p], fields[p], used[p] = time_domain(mgfr, ctx, rho_d, params, code, args.tol, args.steps, args.warmup,
                                          autotune=not args.no_autotune, tune_cache=args.tune_cache)
     head = runs["mixed"] if "mixed" in runs else runs["fp64"]
     headp = "mixed" if "mixed" in runs else "fp64"
@@ -218,6 +251,7 @@ def bench_domain(args):
             "max_abs": d.max().item(), "rms_abs": d.square().mean().sqrt().item(),
             "max_rel": d.max().item() / ref if ref > 0 else None}
         del d
+    out["stop_rule_comparison"] = stop_rule_comparison(mgfr, ctx, rho_d, params, used[headp], fields[headp])
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.tol)

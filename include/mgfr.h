@@ -70,7 +70,11 @@ typedef struct mgfr_opts {
     double coarsest_rtol; /* coarsest level sweeps until rms <= rtol x initial or down to
                              its rounding floor; 0: always coarsest_sweeps            [1e-3]   */
     int planes;           /* planes per workgroup of the finest-level fused sweeps (N >= 64):
-                             0 = automatic, else a power of two <= N                 [0]      */
+                             0 = automatic, else a power of two in [4, N]            [0]      */
+    double tau_alpha;     /* > 0: also stop once rms(L) <= tau_alpha x rms(tau), tau the
+                             truncation-error estimate of the current field (Sec. V.B;
+                             the stop test is rms(L) <= max(tol, tau_alpha rms(tau)));
+                             domain solves only                                    [0]      */
 } mgfr_opts;
 
 /* One refinement patch: a cube of n^3 cells at refinement level `level` >= 1 (cell size
@@ -99,6 +103,7 @@ typedef struct mgfr_stats {
                                   single-precision correction sweep (read base, rhs and e,
                                   write e)                                                  */
     double solve_ms;           /* host wall time of the last solve call                        */
+    double tau_rms;            /* tau_alpha > 0: rms of tau at the last stop test; else 0    */
 } mgfr_stats;
 
 typedef struct mgfr_ctx mgfr_ctx;
@@ -202,6 +207,16 @@ int mg_fr_solve_patches(mgfr_ctx* ctx, const double* u_domain, int N0, const mgf
 int mg_fr_solve_batch(mgfr_ctx* ctx, int nbox, const int* N, const double* const* rho,
                       const mgfr_params* per_box, const mgfr_opts* opts, double* const* u,
                       double* res_hist, int* n_hist, void* stream);
+
+/* Truncation-error estimate (Sec. V.B): tau = L^H(R u) - R L^h(u) on the level with N/2 cells
+ * per side, R the 8-child mean, each operator with its own level's density (R rho~) and
+ * spacing, on the periodic N^3 grid; the density and background terms cancel, so tau is the
+ * FAS coarse right-hand side L^H(R u) - R d minus the restricted source.  rho, u: device N^3
+ * (read); flags: MGFR_SUBTRACT_MEAN as in mgfr_residual.  tau: device (N/2)^3 (written; may
+ * be NULL); rms: host (may be NULL), rms of tau.  N a power of two in [4, 1024].
+ * Synchronises. */
+int mgfr_tau(mgfr_ctx* ctx, const double* rho, const double* u, int N, const mgfr_params* params, int flags,
+             double* tau, double* rms, void* stream);
 
 /* The modified Poisson equation (eq. discrete_poisson; Sec. II, Sec. III.B): the Newtonian
  * potential phi of the density and of delta R of the scalaron f~_R = -exp(u), on the periodic

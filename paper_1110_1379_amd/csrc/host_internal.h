@@ -188,7 +188,8 @@ inline int check_opts(mgfr_ctx* c, const mgfr_opts* o)
     if (!(o->tol >= 0.0) || o->pre < 0 || o->post < 0 || o->max_cycles < 0 || o->coarsest_sweeps < 0 ||
         !is_pow2(o->coarsest_n) || o->coarsest_n < 2 || o->coarsest_n > 8 || !(o->max_step >= 0.0) ||
         !(o->coarsest_rtol >= 0.0) || (o->precision != MGFR_FP64 && o->precision != MGFR_MIXED) ||
-        o->inner_cycles < 1 || o->planes < 0 || (o->planes > 0 && !is_pow2(o->planes)))
+        o->inner_cycles < 1 || o->planes < 0 || (o->planes > 0 && (!is_pow2(o->planes) || o->planes < 4)) ||
+        !(o->tau_alpha >= 0.0))
         return c->fail(MGFR_EINVAL, "invalid options (tol=%g pre=%d post=%d coarsest_n=%d precision=%d)",
                        o->tol, o->pre, o->post, o->coarsest_n, o->precision);
     return MGFR_OK;

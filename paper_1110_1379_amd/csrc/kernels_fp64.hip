@@ -97,6 +97,45 @@ __global__ void __launch_bounds__(kBlock) k_fas_rhs(Grid g, const double* __rest
     f[q] = cell_op(g, uhat[q], un, 0.0).L - f[q];
 }
 
+// tau = fH - R f_src on the coarse level (fH = L^H(R u) - R d, the FAS right-hand side), with
+// f_src = fscale (rho - sref) + fshift of the fine grid g; block partials (sum tau^2, max |tau|).
+__global__ void __launch_bounds__(kBlock) k_tau_finish(Grid g, const double* __restrict__ rho,
+                                                       const double* __restrict__ fH, double* __restrict__ tau,
+                                                       double* __restrict__ partial)
+{
+    __shared__ double rs[kBlock], rm[kBlock];
+    const int lgc = g.lg - 1, nc = g.n >> 1;
+    const long long ncell = 1LL << (3 * lgc);
+    double s = 0.0, mx = 0.0;
+    for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < ncell; q += (long long)gridDim.x * kBlock) {
+        const int I = (int)(q >> (2 * lgc)), J = (int)((q >> lgc) & (nc - 1)), K = (int)(q & (nc - 1));
+        double sf = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int z = 0; z < 2; ++z) sf += dev::rhs_value(g, rho[at(g, 2 * I + a, 2 * J + b, 2 * K + z)]);
+        const double t = fH[q] - 0.125 * sf;
+        if (tau) tau[q] = t;
+        s += t * t;
+        const double at_ = fabs(t);
+        if (!(mx >= at_)) mx = at_;
+    }
+    rs[threadIdx.x] = s;
+    rm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            rs[threadIdx.x] += rs[threadIdx.x + w];
+            const double o = rm[threadIdx.x + w];
+            if (!(rm[threadIdx.x] >= o)) rm[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = rs[0];
+        partial[2 * blockIdx.x + 1] = rm[0];
+    }
+}
+
 // Deterministic block reductions over kBlock threads (fixed tree order).
 // block_sum_max: a <- sum of a, b <- max of b (NaN propagates).  block_sum2: both summed.
 template <bool SecondIsMax>
@@ -402,6 +441,14 @@ hipError_t fill(double* x, double v, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill, dim3(reduction_blocks(n)), dim3(kBlock), 0, s, x, v, n);
     return hipGetLastError();
+}
+
+int tau_finish(const Grid& g, const double* rho, const double* fH, double* tau, double* partial, hipStream_t s)
+{
+    const long long ncell = 1LL << (3 * (g.lg - 1));
+    const unsigned nb = reduction_blocks(ncell);
+    hipLaunchKernelGGL(k_tau_finish, dim3(nb), dim3(kBlock), 0, s, g, rho, fH, tau, partial);
+    return hipGetLastError() == hipSuccess ? (int)nb : -1;
 }
 
 }  // namespace mgfr

@@ -219,6 +219,11 @@ hipError_t residual_cast(const Grid& g, const double* u, const double* src, floa
 // out[0..1] from `nb` partial pairs (sum, max).
 hipError_t fold_partials(const double* partial, int nb, double* out, hipStream_t s);
 
+// tau = fH - R f_src on the level below the fine grid g (fH = L^H(R u) - R d there), written
+// to tau if not null; block partials (sum tau^2, max |tau|).  Returns their number, or -1 if
+// the launch failed.
+int tau_finish(const Grid& g, const double* rho, const double* fH, double* tau, double* partial, hipStream_t s);
+
 // ---- single-precision correction multigrid (kernels_fp32.hip) --------------------------
 hipError_t ngs_sweep32(const Grid& g, const float* ub, float* e, const float* f, hipStream_t s);
 hipError_t ngs_sweep32_fused(const Grid& g, const float* ub, const float* ein, float* eout, const float* f,

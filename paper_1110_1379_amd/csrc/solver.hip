@@ -258,6 +258,7 @@ void mgfr_default_opts(mgfr_opts* o)
     o->max_step = 1.0;
     o->coarsest_rtol = 1e-3;
     o->planes = 0;
+    o->tau_alpha = 0.0;
 }
 
 int mgfr_constants(const mgfr_params* params, int N, double* out8)
@@ -296,9 +297,79 @@ int finest_grid(mgfr_ctx* c, const Model& md, const double* rho, int N, int flag
     return MGFR_OK;
 }
 
+// rms of the truncation-error estimate tau = L^H(R u) - R L^h(u) (Sec. V.B) of the finest
+// field u, through the coarse level's scratch: R u and R d by the restriction pass, the FAS
+// right-hand side fH = L^H(R u) - R d, then tau = fH - R f_src (synchronises).  tau_out: the
+// tau field (may be null).
+int tau_rms(mgfr_ctx* c, const mgfr::Grid& g0, const double* u, const double* rho, hipStream_t s, double* rms,
+            double* tau_out)
+{
+    if (c->lv.size() < 2) {
+        *rms = 0.0;
+        return MGFR_OK;
+    }
+    Level& H = c->lv[1];
+    if (g0.n >= mgfr::fused_sweep_min_n()) {
+        mgfr::ResidStream a{};
+        a.ti = mgfr::resid_stream_planes(g0.n);
+        a.uc = H.u;
+        a.uhat = H.uhat;
+        a.fc = H.f;
+        MGFR_TRY(hip_check(c, mgfr::resid_stream(g0, u, rho, a, s), "resid_stream"));
+    } else {
+        MGFR_TRY(hip_check(c, mgfr::resid_restrict(g0, u, rho, H.u, H.uhat, H.f, s), "resid_restrict"));
+    }
+    MGFR_TRY(hip_check(c, mgfr::fas_rhs(H.g, H.uhat, H.f, s), "fas_rhs"));
+    const int nb = mgfr::tau_finish(g0, rho, H.f, tau_out, c->partial, s);
+    if (nb < 0) return hip_check(c, hipGetLastError(), "tau_finish");
+    MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, nb, c->red, s), "fold_partials"));
+    double r[2];
+    MGFR_TRY(read_reduction(c, s, r));
+    *rms = std::sqrt(r[0] / (double)mgfr::cells(H.g));
+    return MGFR_OK;
+}
+
+// Stop test of the domain solves: rms(L) <= tol, or <= tau_alpha x rms(tau) when tau_alpha > 0.
+int converged(mgfr_ctx* c, const mgfr_opts* o, const mgfr::Grid& g0, const double* u, const double* rho,
+              hipStream_t s, double rms, bool* done)
+{
+    *done = !(rms > o->tol);
+    if (*done || !(o->tau_alpha > 0.0) || !std::isfinite(rms)) return MGFR_OK;
+    double t;
+    MGFR_TRY(tau_rms(c, g0, u, rho, s, &t, nullptr));
+    c->stats.tau_rms = t;
+    *done = rms <= o->tau_alpha * t;
+    return MGFR_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int mgfr_tau(mgfr_ctx* c, const double* rho, const double* u, int N, const mgfr_params* params, int flags,
+             double* tau, double* rms, void* stream)
+{
+    if (!c) return MGFR_EINVAL;
+    c->err.clear();
+    Model md;
+    if (!rho || !u || !is_pow2(N) || N < 4 || N > 1024) return c->fail(MGFR_EINVAL, "invalid arguments");
+    if (derive_model(params, &md) != MGFR_OK) return c->fail(MGFR_EINVAL, "invalid model parameters");
+    MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+    MGFR_TRY(ensure_scratch(c));
+    hipStream_t s = (hipStream_t)stream;
+    const int coarsest = c->coarsest >= 2 && c->coarsest <= N / 2 ? c->coarsest : 2;
+    MGFR_TRY(ensure_levels(c, N, coarsest));
+    Level& L0 = c->lv[0];
+    MGFR_TRY(finest_grid(c, md, rho, N, flags, 0.0, s, &L0.g));
+    for (size_t m = 1; m < c->lv.size(); ++m) {
+        const int n = N >> m;
+        c->lv[m].g = make_grid(md, n, 1.0 / n, 0.0);
+    }
+    double r;
+    MGFR_TRY(tau_rms(c, L0.g, u, rho, s, &r, tau));
+    if (rms) *rms = r;
+    return MGFR_OK;
+}
 
 int mgfr_residual(mgfr_ctx* c, const double* rho, const double* u, int N, const mgfr_params* params,
                   int flags, double* d, void* stream)
@@ -390,15 +461,18 @@ int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params
     MGFR_TRY(hip_check(c, hipMemsetAsync(c->counter, 0, sizeof(long long), s), "hipMemsetAsync"));
     double rms;
     int k = 0;
+    bool stop = false;  // the stop test passed
     if (o->precision == MGFR_FP64) {
         MGFR_TRY(finest_norm(c, L0.g, u, rho, s, &rms, nullptr));
         if (res_hist) res_hist[0] = rms;
-        while (std::isfinite(rms) && rms > o->tol && k < o->max_cycles) {
+        MGFR_TRY(converged(c, o, L0.g, u, rho, s, rms, &stop));
+        while (std::isfinite(rms) && !stop && k < o->max_cycles) {
             MGFR_TRY(cyc.vcycle(0));
             MGFR_TRY(finest_norm(c, L0.g, u, rho, s, &rms, nullptr));
             MGFR_TRY(cyc.harvest());
             ++k;
             if (res_hist) res_hist[k] = rms;
+            MGFR_TRY(converged(c, o, L0.g, u, rho, s, rms, &stop));
         }
     } else {
         // Defect correction: d = L(u) - f in double precision; a single-precision FAS
@@ -439,7 +513,8 @@ int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params
         };
         MGFR_TRY(outer_residual(false));
         if (res_hist) res_hist[0] = rms;
-        while (std::isfinite(rms) && rms > o->tol && k < o->max_cycles) {
+        MGFR_TRY(converged(c, o, L0.g, ucur, rho, s, rms, &stop));
+        while (std::isfinite(rms) && !stop && k < o->max_cycles) {
             for (size_t m = 1; m < c->lv32.size(); ++m)
                 MGFR_TRY(hip_check(c, mgfr::restrict_mean32(c->lv32[m].g, c->lv32[m - 1].ub, c->lv32[m].ub, s),
                                    "restrict_mean32"));
@@ -452,6 +527,7 @@ int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params
             MGFR_TRY(cyc.harvest());
             ++k;
             if (res_hist) res_hist[k] = rms;
+            MGFR_TRY(converged(c, o, L0.g, ucur, rho, s, rms, &stop));
         }
         if (ucur != u)
             MGFR_TRY(hip_check(c, hipMemcpyAsync(u, ucur, sizeof(double) * ncell, hipMemcpyDeviceToDevice, s),
@@ -471,7 +547,7 @@ int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (!std::isfinite(rms)) return c->fail(MGFR_ENONFINITE, "residual became non-finite after %d cycles", k);
-    if (rms > o->tol) return c->fail(MGFR_ENOTCONV, "rms residual %.3e > tol %.3e after %d cycles", rms, o->tol, k);
+    if (!stop) return c->fail(MGFR_ENOTCONV, "rms residual %.3e > tol %.3e after %d cycles", rms, o->tol, k);
     return MGFR_OK;
 }
 

@@ -31,7 +31,7 @@ class mgfr_opts(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int), ("coarsest_sweeps", ctypes.c_int),
                 ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
                 ("inner_cycles", ctypes.c_int), ("max_step", ctypes.c_double),
-                ("coarsest_rtol", ctypes.c_double), ("planes", ctypes.c_int)]
+                ("coarsest_rtol", ctypes.c_double), ("planes", ctypes.c_int), ("tau_alpha", ctypes.c_double)]
 
 
 class mgfr_patch(ctypes.Structure):
@@ -43,7 +43,7 @@ class mgfr_stats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("inner_cycles", ctypes.c_int),
                 ("cell_updates", ctypes.c_longlong), ("finest_updates", ctypes.c_longlong),
                 ("sweep_launches", ctypes.c_int), ("sweep_ms", ctypes.c_double),
-                ("sweep_bytes", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+                ("sweep_bytes", ctypes.c_double), ("solve_ms", ctypes.c_double), ("tau_rms", ctypes.c_double)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -95,6 +95,7 @@ def lib():
                                   ctypes.c_int),
             "mgfr_autotune": ([vp, vp, ctypes.c_int, P, O, vp, O, dp, vp], ctypes.c_int),
             "mg_poisson_solve": ([vp, vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
+            "mgfr_tau": ([vp, vp, vp, ctypes.c_int, P, ctypes.c_int, vp, dp, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -107,7 +108,7 @@ def lib():
 def exported_symbols():
     return ("mgfr_create", "mgfr_destroy", "mgfr_last_error", "mgfr_default_opts", "mgfr_constants",
             "mgfr_residual", "mg_fr_solve", "mgfr_get_stats", "mgfr_smooth", "mg_fr_solve_patches",
-            "mg_fr_solve_batch", "mgfr_autotune", "mg_poisson_solve")
+            "mg_fr_solve_batch", "mgfr_autotune", "mg_poisson_solve", "mgfr_tau")
 
 
 def mgfr_default_opts(**overrides) -> mgfr_opts:
@@ -235,6 +236,20 @@ def mg_fr_solve(ctx: Context, rho, params: Params, opts: mgfr_opts | None = None
     if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
         raise MgfrError(st, ctx.last_error())
     return u, hist[:nh.value].copy(), st
+
+
+def mgfr_tau(ctx: Context, rho, u, params: Params, flags: int = 0, stream=None):
+    """Truncation-error estimate tau = L^H(R u) - R L^h(u) of the field u (float64 device
+    tensors of shape (N, N, N)).  Returns (tau on the (N/2)^3 level, rms of tau)."""
+    import torch
+    N = rho.shape[0]
+    tau = torch.empty((N // 2,) * 3, dtype=torch.float64, device=rho.device)
+    r = ctypes.c_double(0.0)
+    st = lib().mgfr_tau(ctx.handle, _ptr(rho), _ptr(u), N, ctypes.byref(params.c()), flags, _ptr(tau),
+                        ctypes.byref(r), _stream(stream))
+    if st != MGFR_OK:
+        raise MgfrError(st, ctx.last_error())
+    return tau, r.value
 
 
 def mg_poisson_solve(ctx: Context, rho, u, params: Params, opts: mgfr_opts | None = None, phi=None,
