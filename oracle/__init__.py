@@ -107,8 +107,12 @@ def lib():
         L.orc_patch_boundary.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, ip, ctypes.c_int, dp, dp]
         L.orc_single_grid.argtypes = [dp, ctypes.c_int, ctypes.POINTER(_Model), ctypes.c_int,
                                       ctypes.c_double, dp, ctypes.c_int, dp]
+        L.orc_solve_masked.argtypes = [dp, dp, ctypes.c_int, ctypes.POINTER(_Model), ctypes.POINTER(_Opts),
+                                       dp, dp, ip]
+        L.orc_masked_operator.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_double,
+                                          ctypes.POINTER(_Model), dp, dp]
         for f in ("orc_constants", "orc_operator", "orc_operator_at", "orc_solve", "orc_solve_patch",
-                  "orc_patch_boundary", "orc_single_grid"):
+                  "orc_patch_boundary", "orc_single_grid", "orc_solve_masked", "orc_masked_operator"):
             getattr(L, f).restype = ctypes.c_int
         L.orc_last_cell_updates.argtypes = []
         L.orc_last_cell_updates.restype = ctypes.c_longlong
@@ -278,3 +282,33 @@ def single_grid(rho, model: Model, u0, nsweeps: int, subtract_mean: bool = False
     if st != 0:
         raise ValueError(f"orc_single_grid failed ({st})")
     return u, hist
+
+
+def solve_masked(rho, mask, model: Model, u0, opts: Opts | None = None):
+    """A refinement level with the mask scheme (Sec. V): periodic N^3 grid of the level's
+    resolution, mask in [-1, 1] (active where > 0), u0 = initial guess in active cells and the
+    fixed values from the coarser level elsewhere.  Returns (u, residual history, status)."""
+    opts = opts or Opts()
+    rho = _f64(rho)
+    mask = _f64(mask)
+    u = _f64(u0).copy()
+    N = rho.shape[0]
+    hist = np.zeros(opts.max_cycles + 1)
+    nh = ctypes.c_int(0)
+    st = lib().orc_solve_masked(_dp(rho), _dp(mask), N, ctypes.byref(model.c()), ctypes.byref(opts.c()),
+                                _dp(u), _dp(hist), ctypes.byref(nh))
+    return u, hist[:nh.value].copy(), st
+
+
+def masked_operator(u, w, mask, model: Model, rho=None, rho_ref: float = 1.0):
+    """(L, dL/du) of the masked operator at active cells (zero elsewhere), fixed values w."""
+    u, w, mask = _f64(u), _f64(w), _f64(mask)
+    rho = None if rho is None else _f64(rho)
+    n = u.shape[0]
+    L = np.zeros_like(u)
+    dL = np.zeros_like(u)
+    st = lib().orc_masked_operator(n, _dp(u), _dp(w), _dp(mask), _dp(rho), rho_ref, ctypes.byref(model.c()),
+                                   _dp(L), _dp(dL))
+    if st != 0:
+        raise ValueError(f"orc_masked_operator failed ({st})")
+    return L, dL

@@ -578,3 +578,268 @@ int orc_single_grid(const double* rho, int N, const orc_model* m, int subtract_m
     }
     return 0;
 }
+
+/* ----------------------------------------------------------------------------------- */
+/* A refinement level with the mask scheme (Sec. V, Sec. V.A.1-2, Sec. V.B.1-2).         */
+/*                                                                                       */
+/* The level is held as the periodic N^3 grid of its resolution.  mask[q] > 0 marks an   */
+/* active cell (relaxed); mask <= 0 a cell outside the refinement, whose value is fixed.  */
+/* Readings (listed in the design notes of the repo):                                   */
+/*   - w = the field on entry, kept for the whole solve: in masked cells the values      */
+/*     interpolated from the coarser level, in active cells the initial guess;           */
+/*   - boundary value between active i and masked nb, where the linearly interpolated    */
+/*     mask vanishes: u_b = (m_i w_nb - m_nb w_i) / (m_i - m_nb) (eq. phi_b, fixed);     */
+/*   - ghost u_nb = (1 - r) u_b + r u_i, r = m_nb / m_i, and b_nb = exp(u_nb)            */
+/*     (eq. u_i-1jk; b is not interpolated);                                             */
+/*   - coarse levels: mask and w are the 8-child means of the finer level's;             */
+/*   - R d: mean of the 8 children with d = 0 in masked children, into active coarse     */
+/*     cells only; R u: mean of all 8 children (masked ones at their fixed value), into  */
+/*     active coarse cells only; masked coarse cells hold their w;                       */
+/*   - P: the coarse correction u^H - R u is zero in masked coarse cells (no             */
+/*     renormalisation of the weights) and is added to active fine cells only;           */
+/*   - the stop test is the rms of d over the active cells of the level.                 */
+
+typedef struct {
+    int n;
+    double h, C;
+    const double* mask;
+    const double* w;
+    const double* rho; /* finest level only */
+    double rho_ref;
+} mgrid;
+
+/* L_i and dL_i/du_i at an active cell (eq. bc_modified_fR_op, eq. bc_modified_fR_dop
+   with the ghost of each masked neighbour substituted). */
+static double masked_op(const mgrid* g, const consts* c, const double* u, int i, int j, int k,
+                        double* dop)
+{
+    int n = g->n;
+    long long q = at(n, i, j, k);
+    double mi = g->mask[q];
+    double ui = u[q], bi = exp(ui);
+    double L = 0.0, dL = 0.0;
+    for (int f = 0; f < 6; ++f) {
+        int ii = (i + DI[f] + n) % n, jj = (j + DJ[f] + n) % n, kk = (k + DK[f] + n) % n;
+        long long p = at(n, ii, jj, kk);
+        double mn = g->mask[p];
+        if (mn > 0.0) {
+            double un = u[p], bn = exp(un);
+            L += g->C * (bn + bi) * (un - ui);
+            dL += g->C * (bi * (un - ui) - bn - bi);
+        } else {
+            double r = mn / mi;
+            double ubv = (mi * g->w[p] - mn * g->w[q]) / (mi - mn);
+            double ug = (1.0 - r) * ubv + r * ui;
+            double bg = exp(ug);
+            L += g->C * (bg + bi) * (ug - ui);
+            dL += g->C * ((r * bg + bi) * (ug - ui) + (bg + bi) * (r - 1.0));
+        }
+    }
+    double S = c->A * exp(-ui / (c->n + 1.0));
+    L += S;
+    dL -= S / (c->n + 1.0);
+    if (g->rho) L -= c->D * (g->rho[q] - g->rho_ref) + c->Sbar;
+    if (dop) *dop = dL;
+    return L;
+}
+
+static void masked_sweep(const mgrid* g, const consts* c, double* u, const double* f, double max_step)
+{
+    int n = g->n;
+    for (int colour = 0; colour < 2; ++colour)
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int k = 0; k < n; ++k) {
+                    if (((i + j + k) & 1) != colour) continue;
+                    long long q = at(n, i, j, k);
+                    if (!(g->mask[q] > 0.0)) continue;
+                    ++g_updates;
+                    double d;
+                    double L = masked_op(g, c, u, i, j, k, &d);
+                    if (f) L -= f[q];
+                    double step = -L / d;
+                    if (max_step > 0.0) step = fmax(-max_step, fmin(max_step, step));
+                    u[q] += step;
+                }
+}
+
+/* d = L(u) - f at active cells, 0 elsewhere; returns the sum of d^2 and the number of
+   active cells in *nact. */
+static double masked_residual(const mgrid* g, const consts* c, const double* u, const double* f,
+                              double* d, long long* nact)
+{
+    int n = g->n;
+    double s = 0.0;
+    long long na = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                long long q = at(n, i, j, k);
+                double v = 0.0;
+                if (g->mask[q] > 0.0) {
+                    v = masked_op(g, c, u, i, j, k, NULL);
+                    if (f) v -= f[q];
+                    ++na;
+                }
+                if (d) d[q] = v;
+                s += v * v;
+            }
+    if (nact) *nact = na;
+    return s;
+}
+
+typedef struct {
+    mgrid g;
+    double *u, *f, *uhat, *d;
+    double *mbuf, *wbuf; /* owned mask and w (coarse levels; w on level 0 too) */
+} mlevel;
+
+static double masked_rms(const mlevel* L, const consts* c, const double* f)
+{
+    long long na = 0;
+    double s = masked_residual(&L->g, c, L->u, f, NULL, &na);
+    return na > 0 ? sqrt(s / (double)na) : 0.0;
+}
+
+static void masked_vcycle(mlevel* lv, int m, int nlev, const consts* c, const orc_opts* o)
+{
+    mlevel* F = &lv[m];
+    if (m == nlev - 1) {
+        double r0 = masked_rms(F, c, F->f);
+        for (int s = 0; s < o->coarsest_sweeps; ++s) {
+            if (o->coarsest_rtol > 0.0 && masked_rms(F, c, F->f) <= o->coarsest_rtol * r0) break;
+            masked_sweep(&F->g, c, F->u, F->f, o->max_step);
+        }
+        return;
+    }
+    for (int s = 0; s < o->pre; ++s) masked_sweep(&F->g, c, F->u, F->f, o->max_step);
+    masked_residual(&F->g, c, F->u, F->f, F->d, NULL);
+    mlevel* H = &lv[m + 1];
+    int nc = H->g.n;
+    long long ncell = (long long)nc * nc * nc;
+    double* Ru = (double*)calloc((size_t)ncell, sizeof(double));
+    double* Rd = (double*)calloc((size_t)ncell, sizeof(double));
+    restrict_mean(F->g.n, F->u, Ru);
+    restrict_mean(F->g.n, F->d, Rd); /* d is zero in masked fine cells */
+    for (long long q = 0; q < ncell; ++q) {
+        if (H->g.mask[q] > 0.0) {
+            H->uhat[q] = Ru[q];
+            H->u[q] = Ru[q];
+        } else {
+            H->uhat[q] = H->g.w[q];
+            H->u[q] = H->g.w[q];
+        }
+    }
+    /* FAS coarse equation at active coarse cells: L^H(u^H) = L^H(R u^h) - R d^h */
+    for (int I = 0; I < nc; ++I)
+        for (int J = 0; J < nc; ++J)
+            for (int K = 0; K < nc; ++K) {
+                long long q = at(nc, I, J, K);
+                H->f[q] = H->g.mask[q] > 0.0 ? masked_op(&H->g, c, H->uhat, I, J, K, NULL) - Rd[q] : 0.0;
+            }
+    free(Ru);
+    free(Rd);
+    masked_vcycle(lv, m + 1, nlev, c, o);
+    /* u^h += P(u^H - R u^h) at active fine cells; zero correction from masked coarse cells */
+    for (long long q = 0; q < ncell; ++q) H->d[q] = H->g.mask[q] > 0.0 ? H->u[q] - H->uhat[q] : 0.0;
+    int n = F->g.n;
+    double* corr = (double*)calloc((size_t)n * n * n, sizeof(double));
+    prolong_add(nc, H->d, 1, corr);
+    for (long long q = 0; q < (long long)n * n * n; ++q)
+        if (F->g.mask[q] > 0.0) F->u[q] += corr[q];
+    free(corr);
+    for (int s = 0; s < o->post; ++s) masked_sweep(&F->g, c, F->u, F->f, o->max_step);
+}
+
+static void free_mlevels(mlevel* lv, int nlev)
+{
+    for (int m = 0; m < nlev; ++m) {
+        if (m > 0) {
+            free(lv[m].u);
+            free(lv[m].f);
+            free(lv[m].uhat);
+        }
+        free(lv[m].d);
+        free(lv[m].mbuf);
+        free(lv[m].wbuf);
+    }
+}
+
+int orc_solve_masked(const double* rho, const double* mask, int N, const orc_model* m, const orc_opts* o,
+                     double* u, double* hist, int* nhist)
+{
+    consts c;
+    if (derive(m, &c) != 0 || check_opts(o) != 0 || !rho || !mask || !u || !is_pow2(N) || N < 2)
+        return ORC_EINVAL;
+    long long ncell = (long long)N * N * N;
+    double mean = 0.0;
+    for (long long q = 0; q < ncell; ++q) {
+        if (!isfinite(rho[q]) || !isfinite(u[q])) return ORC_ENONFINITE;
+        if (!(mask[q] >= -1.0 && mask[q] <= 1.0)) return ORC_EINVAL;
+        mean += rho[q];
+    }
+    mean /= (double)ncell;
+    mlevel lv[32];
+    memset(lv, 0, sizeof(lv));
+    int nlev = 0;
+    for (int nm = N; nlev < 30; nm /= 2) {
+        mlevel* L = &lv[nlev];
+        long long nc = (long long)nm * nm * nm;
+        double hm = 1.0 / nm;
+        L->g.n = nm;
+        L->g.h = hm;
+        L->g.C = c.ct * c.ct / (2.0 * hm * hm);
+        L->g.rho = nlev == 0 ? rho : NULL;
+        L->g.rho_ref = o->subtract_mean ? mean : 1.0;
+        L->wbuf = (double*)calloc((size_t)nc, sizeof(double));
+        if (nlev == 0) {
+            memcpy(L->wbuf, u, (size_t)nc * sizeof(double));
+            L->g.mask = mask;
+        } else {
+            L->mbuf = (double*)calloc((size_t)nc, sizeof(double));
+            restrict_mean(2 * nm, lv[nlev - 1].g.mask, L->mbuf);
+            restrict_mean(2 * nm, lv[nlev - 1].g.w, L->wbuf);
+            L->g.mask = L->mbuf;
+        }
+        L->g.w = L->wbuf;
+        L->u = nlev == 0 ? u : (double*)calloc((size_t)nc, sizeof(double));
+        L->f = nlev == 0 ? NULL : (double*)calloc((size_t)nc, sizeof(double));
+        L->uhat = nlev == 0 ? NULL : (double*)calloc((size_t)nc, sizeof(double));
+        L->d = (double*)calloc((size_t)nc, sizeof(double));
+        ++nlev;
+        if (nm <= o->coarsest_n || nm % 2) break;
+    }
+    g_updates = 0;
+    double rms = masked_rms(&lv[0], &c, NULL);
+    int k = 0;
+    if (hist) hist[0] = rms;
+    while (isfinite(rms) && rms > o->tol && k < o->max_cycles) {
+        masked_vcycle(lv, 0, nlev, &c, o);
+        rms = masked_rms(&lv[0], &c, NULL);
+        ++k;
+        if (hist) hist[k] = rms;
+    }
+    if (nhist) *nhist = k + 1;
+    free_mlevels(lv, nlev);
+    if (!isfinite(rms)) return ORC_ENONFINITE;
+    return rms <= o->tol ? 0 : ORC_ENOTCONV;
+}
+
+int orc_masked_operator(int n, const double* u, const double* w, const double* mask, const double* rho,
+                        double rho_ref, const orc_model* m, double* L, double* dL)
+{
+    consts c;
+    if (derive(m, &c) != 0 || n < 1 || !u || !w || !mask) return ORC_EINVAL;
+    double h = 1.0 / n;
+    mgrid g = {n, h, c.ct * c.ct / (2.0 * h * h), mask, w, rho, rho_ref};
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                long long q = at(n, i, j, k);
+                double d = 0.0, v = 0.0;
+                if (mask[q] > 0.0) v = masked_op(&g, &c, u, i, j, k, &d);
+                if (L) L[q] = v;
+                if (dL) dL[q] = d;
+            }
+    return 0;
+}

@@ -75,6 +75,20 @@ int orc_patch_boundary(const double* parent_u, int pn, const int* porigin, int p
 int orc_single_grid(const double* rho, int N, const orc_model* m, int subtract_mean, double max_step,
                     double* u, int nsweeps, double* hist);
 
+/* A refinement level with the mask scheme (Sec. V): the periodic N^3 grid of the level's
+ * resolution (h = 1/N); mask[q] in [-1, 1], active (relaxed) where > 0; on entry u holds the
+ * initial guess in active cells and the fixed values interpolated from the coarser level in
+ * the others, and both are kept as w for the boundary values.  FAS V-cycles over coarse
+ * levels with 8-child-mean masks until the rms residual over the active cells <= tol.
+ * Only active cells of u change. */
+int orc_solve_masked(const double* rho, const double* mask, int N, const orc_model* m, const orc_opts* o,
+                     double* u, double* hist, int* nhist);
+
+/* L and dL/du of the masked operator at active cells (0 elsewhere), with fixed values w;
+ * rho == NULL: no density and background terms (coarse levels); h = 1/n. */
+int orc_masked_operator(int n, const double* u, const double* w, const double* mask, const double* rho,
+                        double rho_ref, const orc_model* m, double* L, double* dL);
+
 /* Smoother cell visits (all levels) of the last solve; for timing reports only. */
 long long orc_last_cell_updates(void);
 

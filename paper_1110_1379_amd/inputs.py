@@ -224,3 +224,37 @@ def amr_workload(N0: int = 256, seed: int = 1, sigma: float = 2.0, p: float = -1
             break
     rho_packed = np.concatenate(blocks) if blocks else np.zeros(0)
     return rho0, patches, rho_packed
+
+
+# --- refinement masks of an adaptive level ----------------------------------------------
+
+def oct_mask(rho: np.ndarray, threshold: float, expand: int = 1) -> np.ndarray:
+    """Mask of a refinement level held on the periodic N^3 grid of its resolution, built the
+    way an oct-based AMR code refines: the 2^3-cell oct under a coarser cell is created when
+    that cell's mean density exceeds `threshold`, then the set of octs is grown by `expand`
+    octs in every direction (26-neighbourhood, periodic), a buffer around refined regions.
+    Returns +1 in the cells of refined octs and -1 elsewhere (float64, C order)."""
+    N = rho.shape[0]
+    n = N // 2
+    od = rho.reshape(n, 2, n, 2, n, 2).mean(axis=(1, 3, 5))
+    refined = od > threshold
+    for _ in range(expand):
+        grown = refined.copy()
+        for di in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                for dk in (-1, 0, 1):
+                    grown |= np.roll(refined, (di, dj, dk), axis=(0, 1, 2))
+        refined = grown
+    m = np.where(refined, 1.0, -1.0)
+    return np.repeat(np.repeat(np.repeat(m, 2, 0), 2, 1), 2, 2)
+
+
+def masked_level(N: int = 512, seed: int = 2, count: int = 2000, fraction: float = 0.25):
+    """Masked-level workload: the halo density on N^3 and the oct mask refining the densest
+    `fraction` of octs (before the one-oct buffer).  Returns (rho, mask)."""
+    rho = halo_box(N, seed, count)
+    n = N // 2
+    od = rho.reshape(n, 2, n, 2, n, 2).mean(axis=(1, 3, 5))
+    thr = float(np.quantile(od, 1.0 - fraction))
+    del od
+    return rho, oct_mask(rho, thr, expand=1)

@@ -80,3 +80,24 @@ def test_batch_boxes_parameters():
     for N, B, fr0, sigma, seed, rho in boxes:
         assert 1e-6 <= fr0 <= 1e-4 and 1.0 <= sigma <= 3.0 and B == float(N)
         assert abs(rho.mean() - 1.0) < 1e-12
+
+
+def test_oct_mask_is_oct_aligned_and_buffered():
+    rho = inputs.small_box(32, 4)
+    od = rho.reshape(16, 2, 16, 2, 16, 2).mean(axis=(1, 3, 5))
+    thr = float(np.quantile(od, 0.95))
+    m0 = inputs.oct_mask(rho, thr, expand=0)
+    m1 = inputs.oct_mask(rho, thr, expand=1)
+    for m in (m0, m1):
+        assert set(np.unique(m)) <= {-1.0, 1.0}
+        blocks = m.reshape(16, 2, 16, 2, 16, 2)
+        assert np.all(blocks.min(axis=(1, 3, 5)) == blocks.max(axis=(1, 3, 5)))
+    # without the buffer exactly the octs above the threshold; the buffer only adds cells,
+    # and every added oct touches a refined one
+    assert np.array_equal(m0[::2, ::2, ::2] > 0, od > thr)
+    assert np.all(m1[m0 > 0] > 0) and (m1 > 0).sum() > (m0 > 0).sum()
+    o0, o1 = m0[::2, ::2, ::2] > 0, m1[::2, ::2, ::2] > 0
+    near = np.zeros_like(o0)
+    for s in np.ndindex(3, 3, 3):
+        near |= np.roll(o0, tuple(x - 1 for x in s), axis=(0, 1, 2))
+    assert np.array_equal(o1, near)

@@ -1,5 +1,5 @@
 """Planted mistakes in the oracle (CPU only): each mutant of mgfr_oracle.c must fail at
-least one pin in test_oracle_pins.py, so a plausible slip anywhere in the oracle (a dropped
+least one pin in test_oracle_pins.py or test_masked_oracle.py, so a plausible slip anywhere in the oracle (a dropped
 term, a wrong sign, a wrong weight or exponent) cannot pass unnoticed."""
 import os
 import subprocess
@@ -48,7 +48,31 @@ MUTANTS = {
     "ghost Jacobian without r": (
         "dL += g->C * ((g->r * bg + bi) * (ug - ui) + (bg + bi) * (g->r - 1.0));",
         "dL += g->C * ((bg + bi) * (ug - ui) + (bg + bi) * (g->r - 1.0));"),
+    # the refinement level with the mask scheme
+    "masked boundary value = fixed neighbour value": (
+        "double ubv = (mi * g->w[p] - mn * g->w[q]) / (mi - mn);",
+        "double ubv = g->w[p];"),
+    "masked ghost without r u_i": (
+        "double r = mn / mi;",
+        "double r = 0.0 * mn / mi;"),
+    "masked ghost Jacobian without r": (
+        "dL += g->C * ((r * bg + bi) * (ug - ui) + (bg + bi) * (r - 1.0));",
+        "dL += g->C * ((bg + bi) * (ug - ui) + (bg + bi) * (r - 1.0));"),
+    "masked cells relaxed too": (
+        "if (!(g->mask[q] > 0.0)) continue;\n                    ++g_updates;",
+        "if (!(g->mask[q] > -2.0)) continue;\n                    ++g_updates;"),
+    "correction prolongated into masked cells": (
+        "if (F->g.mask[q] > 0.0) F->u[q] += corr[q];",
+        "F->u[q] += corr[q];"),
+    "masked FAS right-hand side sign": (
+        "masked_op(&H->g, c, H->uhat, I, J, K, NULL) - Rd[q]",
+        "masked_op(&H->g, c, H->uhat, I, J, K, NULL) + Rd[q]"),
+    "masked prolongation without the coarse correction": (
+        "H->d[q] = H->g.mask[q] > 0.0 ? H->u[q] - H->uhat[q] : 0.0;",
+        "H->d[q] = 0.0;"),
 }
+
+PIN_FILES = ("test_oracle_pins.py", "test_masked_oracle.py")
 
 
 def _run(name, old, new, tmpdir):
@@ -58,11 +82,11 @@ def _run(name, old, new, tmpdir):
     c = os.path.join(tmpdir, tag + ".c")
     so = os.path.join(tmpdir, tag + ".so")
     with open(c, "w") as f:
-        f.write(src.replace(old, new))
+        f.write(src.replace(old, new, 1))
     subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-I", os.path.join(ROOT, "oracle"), c, "-o", so, "-lm"])
     env = dict(os.environ, MGFR_ORACLE_LIB=so)
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider"] +
+                       [os.path.join(ROOT, "tests", f) for f in PIN_FILES],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 
