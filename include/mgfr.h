@@ -239,6 +239,32 @@ int mgfr_tau(mgfr_ctx* ctx, const double* rho, const double* u, int N, const mgf
 int mg_poisson_solve(mgfr_ctx* ctx, const double* rho, const double* u, int N, const mgfr_params* params,
                      const mgfr_opts* opts, double* phi, double* res_hist, int* n_hist, void* stream);
 
+/* A refinement level of irregular shape solved with the mask scheme (Sec. V; eq. phi_b,
+ * eq. u_i-1jk, eq. bc_modified_fR_op, eq. bc_modified_fR_dop; restriction and prolongation
+ * rules of Sec. V.A.2, V.A.3, V.B.2).  The level is held as the periodic N^3 grid of its
+ * resolution (h = 1/N).  A cell with mask > 0 is active and is solved for; a cell with
+ * mask <= 0 keeps the value u holds on entry (the coarser level's solution interpolated
+ * there).  A masked neighbour of an active cell i enters the operator through the boundary
+ * value u_b = (m_i w_nb - m_nb w_i) / (m_i - m_nb), w = u on entry, fixed where the linearly
+ * interpolated mask vanishes, and the ghost u_g = (1 - r) u_b + r u_i, r = m_nb / m_i, with
+ * b_g = exp(u_g).  Coarse multigrid levels carry the 8-child means of the masks (fractional
+ * values) and of w; the residual is restricted from active children into active coarse cells,
+ * R u from all 8 children, and the coarse correction is prolongated (27/9/3/1) from active
+ * coarse cells into active fine cells only.  FAS V-cycles until the rms residual over the
+ * active finest cells <= opts->tol, or opts->max_cycles.
+ * rho      device, N^3 (read): density rho~ (contrast rho - 1, or rho - mean with
+ *          MGFR_SUBTRACT_MEAN in opts->flags).
+ * mask     device, N^3 float in [-1, 1] (read); +1 / -1 on an adaptive level.
+ * u        device, N^3, read and written: on entry the initial guess in active cells and the
+ *          fixed values elsewhere (always read: MGFR_WARM_START is implied); on return the
+ *          active cells hold the solution and the others are bit-for-bit unchanged.
+ * N        power of two in [coarsest_n, 1024].  opts->precision must be MGFR_FP64 and
+ *          opts->tau_alpha 0.  res_hist, n_hist: as mg_fr_solve (rms over active cells).
+ * Returns MGFR_EINVAL for a mask outside [-1, 1], MGFR_ENONFINITE for non-finite rho or u,
+ * MGFR_ENOTCONV if tol was not reached (u still written).  Synchronises. */
+int mg_fr_solve_masked(mgfr_ctx* ctx, const double* rho, const float* mask, int N, const mgfr_params* params,
+                       const mgfr_opts* opts, double* u, double* res_hist, int* n_hist, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -105,6 +105,33 @@ struct mgfr_ctx {
         plv.clear();
         PN = 0;
     }
+    // refinement level with the mask scheme: levels (level 0 u and mask are the caller's)
+    struct MLevel {
+        mgfr::Grid g{};
+        const float* mask = nullptr;  // level 0: the caller's; coarse: owned (mbuf)
+        float* mbuf = nullptr;
+        double* w = nullptr;          // fixed values (level 0: u on entry)
+        double* u = nullptr;          // coarse levels
+        double* uhat = nullptr;       // coarse: R u of the finer level
+        double* f = nullptr;          // coarse: FAS right-hand side
+        long long active = 0;         // number of active cells
+    };
+    int MN = 0, Mcoarsest = 0;
+    std::vector<MLevel> mlv;
+    void free_masked()
+    {
+        for (size_t m = 0; m < mlv.size(); ++m) {
+            (void)hipFree(mlv[m].mbuf);
+            (void)hipFree(mlv[m].w);
+            if (m > 0) {
+                (void)hipFree(mlv[m].u);
+                (void)hipFree(mlv[m].uhat);
+                (void)hipFree(mlv[m].f);
+            }
+        }
+        mlv.clear();
+        MN = 0;
+    }
     // device blocks of finished batched solves, reused by later ones (smallest that fits)
     std::vector<std::pair<void*, size_t>> spare;
 

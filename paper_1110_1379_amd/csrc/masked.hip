@@ -1,0 +1,403 @@
+// Kernels of a refinement level solved with the mask scheme (Sec. V), double precision.
+//
+// The level is the periodic N^3 grid of its resolution.  A cell with mask > 0 is active and
+// relaxed; a cell with mask <= 0 keeps a fixed value w (the coarser level's solution
+// interpolated there).  A masked neighbour nb of an active cell i enters the operator as
+// the ghost value u_g = (1 - r) u_b + r u_i, r = m_nb / m_i (eq. u_i-1jk), with the boundary
+// value u_b = (m_i w_nb - m_nb w_i) / (m_i - m_nb) fixed where the linearly interpolated mask
+// vanishes (eq. phi_b), and b_g = exp(u_g) (b is not interpolated): eq. bc_modified_fR_op
+// and eq. bc_modified_fR_dop.  Coarse levels carry the 8-child means of the masks and of w.
+// The residual is restricted from active children (masked ones count zero) into active coarse
+// cells, R u from all 8 children; the coarse correction is zero in masked coarse cells and
+// is prolongated into active fine cells only (Sec. V.A.2, V.A.3, V.B.2).
+#include "device_fp64.h"
+
+namespace mgfr {
+namespace {
+
+constexpr int kB = 256;
+constexpr int kMaxParts = 8192;
+
+using dev::OpVal;
+using dev::at;
+using dev::bounded;
+
+// L_i - f and dL_i/du_i at active cell (i,j,k) of value ui, mask mi.
+__device__ __forceinline__ OpVal masked_op(const Grid& g, const float* __restrict__ mask,
+                                           const double* __restrict__ w, const double* __restrict__ u,
+                                           int i, int j, int k, double ui, double mi, double f)
+{
+    const int m = g.n - 1;
+    const long long qn[6] = {at(g, (i - 1) & m, j, k), at(g, (i + 1) & m, j, k), at(g, i, (j - 1) & m, k),
+                             at(g, i, (j + 1) & m, k), at(g, i, j, (k - 1) & m), at(g, i, j, (k + 1) & m)};
+    const double bi = exp(ui);
+    double L = 0.0, dL = 0.0, wi = 0.0;
+    bool have_wi = false;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) {
+        const double mn = mask[qn[v]];
+        if (mn > 0.0) {
+            const double un = u[qn[v]], bn = exp(un), du = un - ui;
+            L = fma(bn + bi, du, L);
+            dL += bi * du - bn - bi;
+        } else {
+            if (!have_wi) {
+                wi = w[at(g, i, j, k)];
+                have_wi = true;
+            }
+            const double r = mn / mi;
+            const double ubv = (mi * w[qn[v]] - mn * wi) / (mi - mn);
+            const double ug = (1.0 - r) * ubv + r * ui;
+            const double bg = exp(ug), du = ug - ui;
+            L = fma(bg + bi, du, L);
+            // chain rule: du_g/du_i = r, db_g/du_i = r b_g
+            dL += (r * bg + bi) * du + (bg + bi) * (r - 1.0);
+        }
+    }
+    const double S = dev::curvature(g, ui, bi);
+    OpVal o;
+    o.L = fma(g.C, L, S) - f;
+    o.dL = fma(g.C, dL, -S * g.inv_np1);
+    return o;
+}
+
+__device__ __forceinline__ void cell_of(const Grid& g, long long q, int& i, int& j, int& k)
+{
+    i = (int)(q >> (2 * g.lg));
+    j = (int)((q >> g.lg) & (g.n - 1));
+    k = (int)(q & (g.n - 1));
+}
+
+// Block reduction over kB threads in a fixed order: a summed, b maxed (NaN propagates).
+__device__ __forceinline__ void block_sum_max(double& a, double& b, double* sa, double* sb)
+{
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = kB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sa[threadIdx.x] += sa[threadIdx.x + s];
+            const double o = sb[threadIdx.x + s];
+            if (!(sb[threadIdx.x] >= o)) sb[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    a = sa[0];
+    b = sb[0];
+    __syncthreads();
+}
+
+// Block reduction over kB threads in a fixed order: a and b both summed.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sa, double* sb)
+{
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = kB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sa[threadIdx.x] += sa[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    a = sa[0];
+    b = sb[0];
+    __syncthreads();
+}
+
+// One colour of a red-black Newton-Gauss-Seidel sweep; one thread per cell of the colour,
+// masked cells untouched.
+__global__ void __launch_bounds__(kB) km_ngs_colour(Grid g, const float* __restrict__ mask,
+                                                    const double* __restrict__ w, double* __restrict__ u,
+                                                    const double* __restrict__ src, int colour)
+{
+    const long long half = 1LL << (3 * g.lg - 1);
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    if (t >= half) return;
+    const int hk = g.n >> 1;
+    const int s = (int)(t & (hk - 1));
+    const long long row = t >> (g.lg - 1);
+    const int i = (int)(row >> g.lg), j = (int)(row & (g.n - 1));
+    const int k = 2 * s + ((i + j + colour) & 1);
+    const long long q = at(g, i, j, k);
+    const double mi = mask[q];
+    if (!(mi > 0.0)) return;
+    const double ui = u[q];
+    const OpVal r = masked_op(g, mask, w, u, i, j, k, ui, mi, dev::rhs_value(g, src[q]));
+    u[q] = ui + bounded(-r.L / r.dL, g.max_step);
+}
+
+// One thread per coarse cell: R u of all 8 children and R d of the active ones into active
+// coarse cells; masked coarse cells take their fixed value and a zero right-hand side.
+__global__ void __launch_bounds__(kB) km_resid_restrict(Grid g, const float* __restrict__ mask,
+                                                        const double* __restrict__ w, const double* __restrict__ u,
+                                                        const double* __restrict__ src,
+                                                        const float* __restrict__ maskc,
+                                                        const double* __restrict__ wc, double* __restrict__ uc,
+                                                        double* __restrict__ uhat, double* __restrict__ fc)
+{
+    const int lgc = g.lg - 1, nc = g.n >> 1;
+    const long long tc = (long long)blockIdx.x * kB + threadIdx.x;
+    if (tc >= (1LL << (3 * lgc))) return;
+    if (!(maskc[tc] > 0.0f)) {
+        uc[tc] = wc[tc];
+        uhat[tc] = wc[tc];
+        fc[tc] = 0.0;
+        return;
+    }
+    const int I = (int)(tc >> (2 * lgc)), J = (int)((tc >> lgc) & (nc - 1)), K = (int)(tc & (nc - 1));
+    double su = 0.0, sd = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+                const long long q = at(g, i, j, k);
+                const double ui = u[q], mi = mask[q];
+                su += ui;
+                if (mi > 0.0) sd += masked_op(g, mask, w, u, i, j, k, ui, mi, dev::rhs_value(g, src[q])).L;
+            }
+    uc[tc] = 0.125 * su;
+    uhat[tc] = 0.125 * su;
+    fc[tc] = 0.125 * sd;
+}
+
+// FAS right-hand side at active coarse cells: f = L^H(R u) - R d.
+__global__ void __launch_bounds__(kB) km_fas_rhs(Grid g, const float* __restrict__ mask,
+                                                 const double* __restrict__ w, const double* __restrict__ uhat,
+                                                 double* __restrict__ f)
+{
+    const long long q = (long long)blockIdx.x * kB + threadIdx.x;
+    if (q >= (1LL << (3 * g.lg))) return;
+    const double mi = mask[q];
+    if (!(mi > 0.0)) return;
+    int i, j, k;
+    cell_of(g, q, i, j, k);
+    f[q] = masked_op(g, mask, w, uhat, i, j, k, uhat[q], mi, 0.0).L - f[q];
+}
+
+// u^h += P(u^H - R u^h) at active fine cells, weights 27/9/3/1 over 64, periodic; masked
+// coarse cells contribute no correction.
+__global__ void __launch_bounds__(kB) km_prolong(int lgc, const float* __restrict__ maskc,
+                                                 const double* __restrict__ uc, const double* __restrict__ uhat,
+                                                 const float* __restrict__ maskf, double* __restrict__ uf)
+{
+    const int lg = lgc + 1, n = 1 << lg, mc = (1 << lgc) - 1;
+    const long long q = (long long)blockIdx.x * kB + threadIdx.x;
+    if (q >= (1LL << (3 * lg))) return;
+    if (!(maskf[q] > 0.0f)) return;
+    const int i = (int)(q >> (2 * lg)), j = (int)((q >> lg) & (n - 1)), k = (int)(q & (n - 1));
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int In = (I + ((i & 1) ? 1 : -1)) & mc, Jn = (J + ((j & 1) ? 1 : -1)) & mc,
+              Kn = (K + ((k & 1) ? 1 : -1)) & mc;
+    auto e = [&](int a, int b, int c) -> double {
+        const long long p = ((((long long)a << lgc) + b) << lgc) + c;
+        return maskc[p] > 0.0f ? uc[p] - uhat[p] : 0.0;
+    };
+    const double p = 27.0 / 64.0 * e(I, J, K) + 9.0 / 64.0 * (e(In, J, K) + e(I, Jn, K) + e(I, J, Kn)) +
+                     3.0 / 64.0 * (e(In, Jn, K) + e(In, J, Kn) + e(I, Jn, Kn)) + 1.0 / 64.0 * e(In, Jn, Kn);
+    uf[q] += p;
+}
+
+// Block partials (sum d^2, max |d|) over the active cells.
+__global__ void __launch_bounds__(kB) km_norm(Grid g, const float* __restrict__ mask,
+                                              const double* __restrict__ w, const double* __restrict__ u,
+                                              const double* __restrict__ src, double* __restrict__ partial)
+{
+    __shared__ double sa[kB], sb[kB];
+    const long long n3 = 1LL << (3 * g.lg);
+    double s = 0.0, mx = 0.0;
+    for (long long q = (long long)blockIdx.x * kB + threadIdx.x; q < n3; q += (long long)gridDim.x * kB) {
+        const double mi = mask[q];
+        if (!(mi > 0.0)) continue;
+        int i, j, k;
+        cell_of(g, q, i, j, k);
+        const double d = masked_op(g, mask, w, u, i, j, k, u[q], mi, dev::rhs_value(g, src[q])).L;
+        s += d * d;
+        const double a = fabs(d);
+        if (!(mx >= a)) mx = a;
+    }
+    block_sum_max(s, mx, sa, sb);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = s;
+        partial[2 * blockIdx.x + 1] = mx;
+    }
+}
+
+// Block partials (number of active cells, max |mask|; NaN propagates).
+__global__ void __launch_bounds__(kB) km_count(const float* __restrict__ mask, long long n,
+                                               double* __restrict__ partial)
+{
+    __shared__ double sa[kB], sb[kB];
+    double s = 0.0, mx = 0.0;
+    for (long long q = (long long)blockIdx.x * kB + threadIdx.x; q < n; q += (long long)gridDim.x * kB) {
+        const float m = mask[q];
+        if (m > 0.0f) s += 1.0;
+        const double a = fabs((double)m);
+        if (!(mx >= a)) mx = a;
+    }
+    block_sum_max(s, mx, sa, sb);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = s;
+        partial[2 * blockIdx.x + 1] = mx;
+    }
+}
+
+// Coarse mask and fixed values: 8-child means.
+__global__ void __launch_bounds__(kB) km_restrict_setup(int lgc, const float* __restrict__ maskf,
+                                                        const double* __restrict__ wf, float* __restrict__ maskc,
+                                                        double* __restrict__ wc)
+{
+    const int lg = lgc + 1, nc = 1 << lgc;
+    const long long tc = (long long)blockIdx.x * kB + threadIdx.x;
+    if (tc >= (1LL << (3 * lgc))) return;
+    const int I = (int)(tc >> (2 * lgc)), J = (int)((tc >> lgc) & (nc - 1)), K = (int)(tc & (nc - 1));
+    double sm = 0.0, sw = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const long long q = ((((long long)(2 * I + a) << lg) + 2 * J + b) << lg) + 2 * K + c;
+                sm += maskf[q];
+                sw += wf[q];
+            }
+    maskc[tc] = (float)(0.125 * sm);
+    wc[tc] = 0.125 * sw;
+}
+
+// Coarsest level (n <= 8) in one workgroup, through LDS: relax the active cells until the rms
+// residual over them is <= rtol x its initial value, or cap sweeps.
+__global__ void __launch_bounds__(kB) km_coarsest(Grid g, const float* __restrict__ mask,
+                                                  const double* __restrict__ w, double* __restrict__ u,
+                                                  const double* __restrict__ f, int cap, double rtol,
+                                                  long long* __restrict__ sweeps_done)
+{
+    __shared__ double su[512], sw[512], sf[512];
+    __shared__ float sm[512];
+    __shared__ double sa[kB], sb[kB];
+    const int nc = 1 << (3 * g.lg);
+    for (int q = threadIdx.x; q < nc; q += kB) {
+        su[q] = u[q];
+        sw[q] = w[q];
+        sf[q] = dev::rhs_value(g, f[q]);
+        sm[q] = mask[q];
+    }
+    __syncthreads();
+    auto rms = [&]() {
+        double s = 0.0, cnt = 0.0;
+        for (int q = threadIdx.x; q < nc; q += kB) {
+            const double mi = sm[q];
+            if (!(mi > 0.0)) continue;
+            int i, j, k;
+            cell_of(g, q, i, j, k);
+            const double d = masked_op(g, sm, sw, su, i, j, k, su[q], mi, sf[q]).L;
+            s += d * d;
+            cnt += 1.0;
+        }
+        block_sum2(s, cnt, sa, sb);
+        return cnt > 0.0 ? sqrt(s / cnt) : 0.0;
+    };
+    const double r0 = rtol > 0.0 ? rms() : 0.0;
+    int sweep = 0;
+    for (; sweep < cap; ++sweep) {
+        if (rtol > 0.0 && rms() <= rtol * r0) break;
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int q = threadIdx.x; q < nc; q += kB) {
+                const double mi = sm[q];
+                int i, j, k;
+                cell_of(g, q, i, j, k);
+                if (((i + j + k) & 1) != colour || !(mi > 0.0)) continue;
+                const double ui = su[q];
+                const OpVal r = masked_op(g, sm, sw, su, i, j, k, ui, mi, sf[q]);
+                su[q] = ui + bounded(-r.L / r.dL, g.max_step);
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = threadIdx.x; q < nc; q += kB) u[q] = su[q];
+    if (threadIdx.x == 0 && sweeps_done) sweeps_done[0] += sweep;
+}
+
+inline unsigned blocks(long long work) { return (unsigned)((work + kB - 1) / kB); }
+
+inline unsigned rblocks(long long work)
+{
+    const long long b = (work + kB - 1) / kB;
+    return (unsigned)(b < kMaxParts ? (b < 1 ? 1 : b) : kMaxParts);
+}
+
+}  // namespace
+
+hipError_t masked_count(const float* mask, long long n, double* partial, int* nparts, hipStream_t s)
+{
+    const unsigned nb = rblocks(n);
+    hipLaunchKernelGGL(km_count, dim3(nb), dim3(kB), 0, s, mask, n, partial);
+    *nparts = (int)nb;
+    return hipGetLastError();
+}
+
+hipError_t masked_restrict_setup(const Grid& gc, const float* maskf, const double* wf, float* maskc, double* wc,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(km_restrict_setup, dim3(blocks(cells(gc))), dim3(kB), 0, s, gc.lg, maskf, wf, maskc, wc);
+    return hipGetLastError();
+}
+
+hipError_t masked_ngs(const Grid& g, const float* mask, const double* w, double* u, const double* src, hipStream_t s)
+{
+    if (g.n < 2) return hipErrorInvalidValue;
+    const long long half = cells(g) / 2;
+    for (int colour = 0; colour < 2; ++colour) {
+        hipLaunchKernelGGL(km_ngs_colour, dim3(blocks(half)), dim3(kB), 0, s, g, mask, w, u, src, colour);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t masked_resid_restrict(const Grid& g, const float* mask, const double* w, const double* u,
+                                 const double* src, const float* maskc, const double* wc, double* uc, double* uhat,
+                                 double* fc, hipStream_t s)
+{
+    if (g.n < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(km_resid_restrict, dim3(blocks(cells(g) / 8)), dim3(kB), 0, s, g, mask, w, u, src, maskc, wc,
+                       uc, uhat, fc);
+    return hipGetLastError();
+}
+
+hipError_t masked_fas_rhs(const Grid& gc, const float* maskc, const double* wc, const double* uhat, double* f,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(km_fas_rhs, dim3(blocks(cells(gc))), dim3(kB), 0, s, gc, maskc, wc, uhat, f);
+    return hipGetLastError();
+}
+
+hipError_t masked_prolong(const Grid& gc, const float* maskc, const double* uc, const double* uhat,
+                          const float* maskf, double* uf, hipStream_t s)
+{
+    hipLaunchKernelGGL(km_prolong, dim3(blocks(8 * cells(gc))), dim3(kB), 0, s, gc.lg, maskc, uc, uhat, maskf, uf);
+    return hipGetLastError();
+}
+
+hipError_t masked_norm(const Grid& g, const float* mask, const double* w, const double* u, const double* src,
+                       double* partial, int* nparts, hipStream_t s)
+{
+    const unsigned nb = rblocks(cells(g));
+    hipLaunchKernelGGL(km_norm, dim3(nb), dim3(kB), 0, s, g, mask, w, u, src, partial);
+    *nparts = (int)nb;
+    return hipGetLastError();
+}
+
+hipError_t masked_coarsest(const Grid& g, const float* mask, const double* w, double* u, const double* f, int cap,
+                           double rtol, long long* sweeps, hipStream_t s)
+{
+    if (cells(g) > 512) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(km_coarsest, dim3(1), dim3(kB), 0, s, g, mask, w, u, f, cap, rtol, sweeps);
+    return hipGetLastError();
+}
+
+}  // namespace mgfr

@@ -82,6 +82,34 @@ hipError_t poisson_coarsest(const PGrid& g, double* x, const double* b, double b
 // x += v.
 hipError_t poisson_add(double* x, double v, long long n, hipStream_t s);
 
+// ---- refinement level with the mask scheme (masked.hip) ------------------------------------
+// Active cells: mask > 0; w: fixed values (masked cells) and initial values (active cells).
+// Block partials (number of active cells, max |mask|) of n masks; their number in *nparts.
+hipError_t masked_count(const float* mask, long long n, double* partial, int* nparts, hipStream_t s);
+// Coarse mask and w of level gc: 8-child means of the finer level's.
+hipError_t masked_restrict_setup(const Grid& gc, const float* maskf, const double* wf, float* maskc, double* wc,
+                                 hipStream_t s);
+// One red-black Newton-Gauss-Seidel sweep of the active cells (one launch per colour).
+hipError_t masked_ngs(const Grid& g, const float* mask, const double* w, double* u, const double* src, hipStream_t s);
+// Into the level below: uc = uhat = R u and fc = R d at active coarse cells (w, w and 0 at
+// masked ones).
+hipError_t masked_resid_restrict(const Grid& g, const float* mask, const double* w, const double* u,
+                                 const double* src, const float* maskc, const double* wc, double* uc, double* uhat,
+                                 double* fc, hipStream_t s);
+// f = L^H(uhat) - f at active cells of the coarse level gc.
+hipError_t masked_fas_rhs(const Grid& gc, const float* maskc, const double* wc, const double* uhat, double* f,
+                          hipStream_t s);
+// uf += P(uc - uhat) at active fine cells; zero correction from masked coarse cells.
+hipError_t masked_prolong(const Grid& gc, const float* maskc, const double* uc, const double* uhat,
+                          const float* maskf, double* uf, hipStream_t s);
+// Block partials (sum d^2, max |d|) over active cells; their number in *nparts.
+hipError_t masked_norm(const Grid& g, const float* mask, const double* w, const double* u, const double* src,
+                       double* partial, int* nparts, hipStream_t s);
+// Coarsest level (n <= 8), one workgroup: sweeps until rms <= rtol x initial or cap;
+// the sweep count is added to *sweeps.
+hipError_t masked_coarsest(const Grid& g, const float* mask, const double* w, double* u, const double* f, int cap,
+                           double rtol, long long* sweeps, hipStream_t s);
+
 // ---- batched units (batch_fp64.hip) ------------------------------------------------------
 // One multigrid level of one unit (a cube refinement patch or a periodic box).
 struct BGrid {

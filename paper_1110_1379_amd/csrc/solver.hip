@@ -231,6 +231,7 @@ void mgfr_destroy(mgfr_ctx* c)
     if (c->pin) (void)hipHostFree(c->pin);
     c->free_spare();
     c->free_poisson();
+    c->free_masked();
     delete c;
 }
 

@@ -96,6 +96,7 @@ def lib():
             "mgfr_autotune": ([vp, vp, ctypes.c_int, P, O, vp, O, dp, vp], ctypes.c_int),
             "mg_poisson_solve": ([vp, vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
             "mgfr_tau": ([vp, vp, vp, ctypes.c_int, P, ctypes.c_int, vp, dp, vp], ctypes.c_int),
+            "mg_fr_solve_masked": ([vp, vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -108,7 +109,8 @@ def lib():
 def exported_symbols():
     return ("mgfr_create", "mgfr_destroy", "mgfr_last_error", "mgfr_default_opts", "mgfr_constants",
             "mgfr_residual", "mg_fr_solve", "mgfr_get_stats", "mgfr_smooth", "mg_fr_solve_patches",
-            "mg_fr_solve_batch", "mgfr_autotune", "mg_poisson_solve", "mgfr_tau")
+            "mg_fr_solve_batch", "mgfr_autotune", "mg_poisson_solve", "mgfr_tau",
+            "mg_fr_solve_masked")
 
 
 def mgfr_default_opts(**overrides) -> mgfr_opts:
@@ -250,6 +252,30 @@ def mgfr_tau(ctx: Context, rho, u, params: Params, flags: int = 0, stream=None):
     if st != MGFR_OK:
         raise MgfrError(st, ctx.last_error())
     return tau, r.value
+
+
+def mg_fr_solve_masked(ctx: Context, rho, mask, u, params: Params, opts: mgfr_opts | None = None, stream=None,
+                       raise_on_error: bool = True):
+    """Refinement level with the mask scheme.  rho, u: float64 device tensors (N, N, N); mask:
+    float32 device tensor (N, N, N) in [-1, 1], active where > 0; u holds the initial guess in
+    active cells and the fixed values elsewhere and is solved in place.
+    Returns (u, residual history over the active cells, status)."""
+    import torch
+    if rho.dtype != torch.float64 or u.dtype != torch.float64 or mask.dtype != torch.float32:
+        raise TypeError("rho and u must be float64 and mask float32")
+    N = rho.shape[0]
+    if tuple(rho.shape) != (N,) * 3 or tuple(mask.shape) != (N,) * 3 or tuple(u.shape) != (N,) * 3:
+        raise ValueError("rho, mask and u must all have shape (N, N, N)")
+    if opts is None:
+        opts = mgfr_default_opts()
+    hist = np.zeros(opts.max_cycles + 1)
+    nh = ctypes.c_int(0)
+    st = lib().mg_fr_solve_masked(ctx.handle, _ptr(rho), _ptr(mask), N, ctypes.byref(params.c()), ctypes.byref(opts),
+                                  _ptr(u), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(nh),
+                                  _stream(stream))
+    if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
+        raise MgfrError(st, ctx.last_error())
+    return u, hist[:nh.value].copy(), st
 
 
 def mg_poisson_solve(ctx: Context, rho, u, params: Params, opts: mgfr_opts | None = None, phi=None,
