@@ -251,7 +251,8 @@ def bench_domain(args):
             "max_abs": d.max().item(), "rms_abs": d.square().mean().sqrt().item(),
             "max_rel": d.max().item() / ref if ref > 0 else None}
         del d
-    out["stop_rule_comparison"] = stop_rule_comparison(mgfr, ctx, rho_d, params, used[headp], fields[headp])
+    if not args.no_stop_rule:
+        out["stop_rule_comparison"] = stop_rule_comparison(mgfr, ctx, rho_d, params, used[headp], fields[headp])
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.tol)
@@ -310,6 +311,87 @@ def bench_poisson(args):
         out["cpu_baseline"] = {"value": N ** 3 / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
                                "sample": f"the whole {N}^3 density with a seeded synthetic scalaron: exact periodic "
                                          f"solve by FFT in numpy (float64), {dt:.1f} s"}
+    return out
+
+
+def _prolong_periodic(uc):
+    """Cell-centred trilinear interpolation (weights 27/9/3/1 over 64, periodic) of a coarse
+    field to twice the resolution; input preparation only (the fixed values of a refinement
+    level come from the coarser level's solution)."""
+    import torch
+    f = uc
+    for d in range(3):
+        even = 0.75 * f + 0.25 * torch.roll(f, 1, dims=d)
+        odd = 0.75 * f + 0.25 * torch.roll(f, -1, dims=d)
+        f = torch.stack([even, odd], dim=d + 1).flatten(d, d + 1)
+    return f.contiguous()
+
+
+def bench_masked(args):
+    """A 512^3 refinement level of irregular shape solved with the mask scheme: the halo
+    density, the oct mask of the densest quarter of octs plus a one-oct buffer, fixed values
+    interpolated from a 256^3 solve of the restricted density (untimed set-up).  One step =
+    one masked solve from those values to rms residual tol over the active cells."""
+    import torch
+    from paper_1110_1379_amd import inputs, mgfr
+    N, box, fr0 = 512, 512.0, 1e-6
+    log("generating the masked 512^3 level")
+    rho_h, mask_h = inputs.masked_level(N)
+    act = int((mask_h > 0).sum())
+    rho_d = torch.from_numpy(rho_h).to("cuda:0")
+    mask_d = torch.from_numpy(mask_h).to("cuda:0", dtype=torch.float32)
+    del mask_h
+    params = mgfr.Params(box_mpc_h=box, fr0_abs=fr0)
+    ctx = mgfr.Context(0)
+    rho_c = rho_d.reshape(N // 2, 2, N // 2, 2, N // 2, 2).mean(dim=(1, 3, 5)).contiguous()
+    uc, _, st = mgfr.mg_fr_solve(ctx, rho_c, params, mgfr.mgfr_default_opts(tol=1e-8, precision=mgfr.MGFR_MIXED,
+                                                                              inner_cycles=2, max_cycles=100))
+    assert st == mgfr.MGFR_OK, ctx.last_error()
+    u0 = _prolong_periodic(uc)
+    del uc, rho_c
+    u_d = torch.empty_like(u0)
+    opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, flags=mgfr.MGFR_PROFILE)
+
+    def solve():
+        u_d.copy_(u0)
+        _, h, st = mgfr.mg_fr_solve_masked(ctx, rho_d, mask_d, u_d, params, opts)
+        if st != mgfr.MGFR_OK:
+            raise SystemExit(f"masked solve failed: {ctx.last_error()}")
+        return h, mgfr.mgfr_get_stats(ctx)
+    ms, (h, s) = _timed(solve, args.steps, args.warmup)
+    achieved = s["sweep_bytes"] / (s["sweep_ms"] * 1e-3) / 1e9 if s["sweep_ms"] > 0 else None
+    sweeps = s["sweep_launches"] // 2
+    out = {"metric": "masked refinement level (mask scheme), 512^3: active cell-updates/s at rms residual 1e-8",
+           "value": s["cell_updates"] / (ms * 1e-3), "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"masked512: {N}^3 level, box {box:g} Mpc/h, |f_R0|={fr0:g}, halo density; "
+                                  f"oct mask of the densest 25% of octs plus a one-oct buffer ({act / N ** 3:.3f} "
+                                  f"active); fixed values from a 256^3 solve; FAS V-cycles 2+2 to rms {args.tol:g}",
+                      "active_cells": act},
+           "cycles": int(len(h) - 1), "final_residual": float(h[-1]),
+           "time_includes": "the 1 GiB device copy that resets u before each solve",
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                        "kernel": "masked red-black sweep km_ngs_colour, both colours (finest level)",
+                        "bytes_per_sweep": "4 N^3 (mask) + 24 per active cell (u read and write, density)",
+                        "sweeps": sweeps, "avg_sweep_ms": s["sweep_ms"] / sweeps if sweeps else None}}
+    if not args.no_cpu_baseline:
+        import oracle
+        Ns = 128
+        log(f"timing the CPU oracle on a {Ns}^3 masked level")
+        rs, ms_h = inputs.masked_level(Ns, count=31)
+        model = oracle.Model(box_mpc_h=box * Ns / N, fr0_abs=fr0)
+        us = oracle.constants(model, Ns)["ubar"] + 0.5 * inputs.gaussian_field(Ns, 1.0, -2.0, 44)
+        t0 = time.perf_counter()
+        _, hs, sts = oracle.solve_masked(rs, ms_h, model, us, oracle.Opts(tol=args.tol))
+        dt = time.perf_counter() - t0
+        ups = oracle.last_cell_updates()
+        out["cpu_baseline"] = {"value": ups / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{Ns}^3 masked level of {box * Ns / N:g} Mpc/h (same cell size and "
+                                         f"recipe, 31 halos, {(ms_h > 0).mean():.3f} active), fixed values u_bar + "
+                                         f"a smooth field, to rms {args.tol:g}: {len(hs) - 1} V-cycles, {dt:.1f} s, "
+                                         f"status {sts}"}
     return out
 
 
@@ -440,7 +522,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="halo512", choices=sorted(WORKLOADS) + ["amr", "batch", "poisson512"])
+    ap.add_argument("--workload", default="halo512", choices=sorted(WORKLOADS) + ["amr", "batch", "poisson512", "masked512"])
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -451,6 +533,8 @@ def main():
                          "written after tuning (so that profiled runs time the same settings)")
     ap.add_argument("--no-graph", action="store_true",
                     help="amr/batch: launch every cycle eagerly instead of replaying a HIP graph")
+    ap.add_argument("--no-stop-rule", action="store_true",
+                    help="domain workloads: skip the truncation-error stop-rule comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy three times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -473,6 +557,8 @@ def main():
         out = bench_batch(args)
     elif args.workload == "poisson512":
         out = bench_poisson(args)
+    elif args.workload == "masked512":
+        out = bench_masked(args)
     else:
         out = bench_domain(args)
     print(json.dumps(out))

@@ -701,13 +701,57 @@ static double masked_rms(const mlevel* L, const consts* c, const double* f)
     return na > 0 ? sqrt(s / (double)na) : 0.0;
 }
 
+/* Rounding noise of the rms residual over the active cells, as rounding_floor() for the
+   periodic grid: per active cell one unit in the last place of u times |dL/du| plus one of
+   the summed magnitudes of the terms (C (b_nb + b_i)|u_nb - u_i| per face, the ghost's for a
+   masked neighbour, the curvature term and |f|). */
+static double masked_floor(const mlevel* L, const consts* c, const double* f)
+{
+    const double eps = 2.220446049250313e-16;
+    const mgrid* g = &L->g;
+    int n = g->n;
+    double s = 0.0;
+    long long na = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                long long q = at(n, i, j, k);
+                double mi = g->mask[q];
+                if (!(mi > 0.0)) continue;
+                double dL;
+                masked_op(g, c, L->u, i, j, k, &dL);
+                double ui = L->u[q], bi = exp(ui), t = 0.0;
+                for (int e = 0; e < 6; ++e) {
+                    long long p = at(n, (i + DI[e] + n) % n, (j + DJ[e] + n) % n, (k + DK[e] + n) % n);
+                    double mn = g->mask[p], un;
+                    if (mn > 0.0) {
+                        un = L->u[p];
+                    } else {
+                        double r = mn / mi;
+                        un = (1.0 - r) * ((mi * g->w[p] - mn * g->w[q]) / (mi - mn)) + r * ui;
+                    }
+                    t += g->C * (exp(un) + bi) * fabs(un - ui);
+                }
+                t += c->A * exp(-ui / (c->n + 1.0)) + (f ? fabs(f[q]) : 0.0);
+                double fl = eps * (fabs(dL) * fabs(ui) + t);
+                s += fl * fl;
+                ++na;
+            }
+    return na > 0 ? sqrt(s / (double)na) : 0.0;
+}
+
 static void masked_vcycle(mlevel* lv, int m, int nlev, const consts* c, const orc_opts* o)
 {
     mlevel* F = &lv[m];
     if (m == nlev - 1) {
+        /* coarsest level: sweep until its residual has dropped by coarsest_rtol or reached
+           the rounding floor (with coarsest_rtol = 0, exactly coarsest_sweeps times) */
         double r0 = masked_rms(F, c, F->f);
         for (int s = 0; s < o->coarsest_sweeps; ++s) {
-            if (o->coarsest_rtol > 0.0 && masked_rms(F, c, F->f) <= o->coarsest_rtol * r0) break;
+            if (o->coarsest_rtol > 0.0) {
+                double r = masked_rms(F, c, F->f);
+                if (r <= o->coarsest_rtol * r0 || r <= masked_floor(F, c, F->f)) break;
+            }
             masked_sweep(&F->g, c, F->u, F->f, o->max_step);
         }
         return;

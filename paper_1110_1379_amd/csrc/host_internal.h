@@ -118,8 +118,11 @@ struct mgfr_ctx {
     };
     int MN = 0, Mcoarsest = 0;
     std::vector<MLevel> mlv;
+    double* mpart = nullptr;  // block partials of the finest-level norm
     void free_masked()
     {
+        (void)hipFree(mpart);
+        mpart = nullptr;
         for (size_t m = 0; m < mlv.size(); ++m) {
             (void)hipFree(mlv[m].mbuf);
             (void)hipFree(mlv[m].w);

@@ -61,6 +61,30 @@ __device__ __forceinline__ OpVal masked_op(const Grid& g, const float* __restric
     return o;
 }
 
+// Summed magnitudes of the terms of L_i - f at an active cell: C (b_nb + b_i)|u_nb - u_i| per
+// face (the ghost's for a masked neighbour), the curvature term and |f|.
+__device__ double masked_mag(const Grid& g, const float* mask, const double* w, const double* u, int i, int j, int k,
+                             double ui, double mi, double f)
+{
+    const int m = g.n - 1;
+    const long long qn[6] = {at(g, (i - 1) & m, j, k), at(g, (i + 1) & m, j, k), at(g, i, (j - 1) & m, k),
+                             at(g, i, (j + 1) & m, k), at(g, i, j, (k - 1) & m), at(g, i, j, (k + 1) & m)};
+    const double bi = exp(ui), wi = w[at(g, i, j, k)];
+    double t = 0.0;
+    for (int v = 0; v < 6; ++v) {
+        const double mn = mask[qn[v]];
+        double un;
+        if (mn > 0.0) {
+            un = u[qn[v]];
+        } else {
+            const double r = mn / mi;
+            un = (1.0 - r) * ((mi * w[qn[v]] - mn * wi) / (mi - mn)) + r * ui;
+        }
+        t += g.C * (exp(un) + bi) * fabs(un - ui);
+    }
+    return t + g.A * exp(-ui * g.inv_np1) + fabs(f);
+}
+
 __device__ __forceinline__ void cell_of(const Grid& g, long long q, int& i, int& j, int& k)
 {
     i = (int)(q >> (2 * g.lg));
@@ -201,23 +225,35 @@ __global__ void __launch_bounds__(kB) km_prolong(int lgc, const float* __restric
     uf[q] += p;
 }
 
-// Block partials (sum d^2, max |d|) over the active cells.
+// Block partials (sum d^2, max |d|) over the active cells.  A thread takes one 2x2x2 block of
+// cells, the eight cells unrolled so that their loads overlap; one partial pair per workgroup.
 __global__ void __launch_bounds__(kB) km_norm(Grid g, const float* __restrict__ mask,
                                               const double* __restrict__ w, const double* __restrict__ u,
                                               const double* __restrict__ src, double* __restrict__ partial)
 {
     __shared__ double sa[kB], sb[kB];
-    const long long n3 = 1LL << (3 * g.lg);
+    const int lgc = g.lg - 1, nc = g.n >> 1;
+    const long long nblk = 1LL << (3 * lgc);
     double s = 0.0, mx = 0.0;
-    for (long long q = (long long)blockIdx.x * kB + threadIdx.x; q < n3; q += (long long)gridDim.x * kB) {
-        const double mi = mask[q];
-        if (!(mi > 0.0)) continue;
-        int i, j, k;
-        cell_of(g, q, i, j, k);
-        const double d = masked_op(g, mask, w, u, i, j, k, u[q], mi, dev::rhs_value(g, src[q])).L;
-        s += d * d;
-        const double a = fabs(d);
-        if (!(mx >= a)) mx = a;
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    if (t < nblk) {
+        const int I = (int)(t >> (2 * lgc)), J = (int)((t >> lgc) & (nc - 1)), K = (int)(t & (nc - 1));
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int z = 0; z < 2; ++z) {
+                    const int i = 2 * I + x, j = 2 * J + y, k = 2 * K + z;
+                    const long long q = at(g, i, j, k);
+                    const double mi = mask[q];
+                    if (mi > 0.0) {
+                        const double d = masked_op(g, mask, w, u, i, j, k, u[q], mi, dev::rhs_value(g, src[q])).L;
+                        s += d * d;
+                        const double a = fabs(d);
+                        if (!(mx >= a)) mx = a;
+                    }
+                }
     }
     block_sum_max(s, mx, sa, sb);
     if (threadIdx.x == 0) {
@@ -270,7 +306,7 @@ __global__ void __launch_bounds__(kB) km_restrict_setup(int lgc, const float* __
 }
 
 // Coarsest level (n <= 8) in one workgroup, through LDS: relax the active cells until the rms
-// residual over them is <= rtol x its initial value, or cap sweeps.
+// residual over them is <= rtol x its initial value or its rounding floor, or cap sweeps.
 __global__ void __launch_bounds__(kB) km_coarsest(Grid g, const float* __restrict__ mask,
                                                   const double* __restrict__ w, double* __restrict__ u,
                                                   const double* __restrict__ f, int cap, double rtol,
@@ -287,24 +323,45 @@ __global__ void __launch_bounds__(kB) km_coarsest(Grid g, const float* __restric
         sm[q] = mask[q];
     }
     __syncthreads();
-    auto rms = [&]() {
-        double s = 0.0, cnt = 0.0;
+    // rms residual over the active cells, and its rounding floor: per cell one unit in the
+    // last place of u times |dL/du| plus one of the summed magnitudes of the terms
+    __shared__ double sc[kB];
+    auto rms = [&](double& floor) {
+        double s = 0.0, fl = 0.0, cnt = 0.0;
         for (int q = threadIdx.x; q < nc; q += kB) {
             const double mi = sm[q];
             if (!(mi > 0.0)) continue;
             int i, j, k;
             cell_of(g, q, i, j, k);
-            const double d = masked_op(g, sm, sw, su, i, j, k, su[q], mi, sf[q]).L;
-            s += d * d;
+            const OpVal r = masked_op(g, sm, sw, su, i, j, k, su[q], mi, sf[q]);
+            s += r.L * r.L;
+            const double f1 = 2.220446049250313e-16 *
+                              (fabs(r.dL) * fabs(su[q]) + masked_mag(g, sm, sw, su, i, j, k, su[q], mi, sf[q]));
+            fl += f1 * f1;
             cnt += 1.0;
         }
-        block_sum2(s, cnt, sa, sb);
+        block_sum2(s, fl, sa, sb);
+        sc[threadIdx.x] = cnt;
+        __syncthreads();
+        for (int w2 = kB / 2; w2 > 0; w2 >>= 1) {
+            if (threadIdx.x < w2) sc[threadIdx.x] += sc[threadIdx.x + w2];
+            __syncthreads();
+        }
+        cnt = sc[0];
+        __syncthreads();
+        floor = cnt > 0.0 ? sqrt(fl / cnt) : 0.0;
         return cnt > 0.0 ? sqrt(s / cnt) : 0.0;
     };
-    const double r0 = rtol > 0.0 ? rms() : 0.0;
+    double floor0 = 0.0;
+    const double r0 = rtol > 0.0 ? rms(floor0) : 0.0;
     int sweep = 0;
     for (; sweep < cap; ++sweep) {
-        if (rtol > 0.0 && rms() <= rtol * r0) break;
+        if (rtol > 0.0) {
+            // stop once reduced by rtol or down to the rounding floor
+            double floor;
+            const double r = rms(floor);
+            if (r <= rtol * r0 || r <= floor) break;
+        }
         for (int colour = 0; colour < 2; ++colour) {
             for (int q = threadIdx.x; q < nc; q += kB) {
                 const double mi = sm[q];
@@ -383,10 +440,13 @@ hipError_t masked_prolong(const Grid& gc, const float* maskc, const double* uc, 
     return hipGetLastError();
 }
 
+long long masked_norm_partials(const Grid& g) { return (long long)blocks(cells(g) / 8); }
+
 hipError_t masked_norm(const Grid& g, const float* mask, const double* w, const double* u, const double* src,
                        double* partial, int* nparts, hipStream_t s)
 {
-    const unsigned nb = rblocks(cells(g));
+    if (g.n < 2) return hipErrorInvalidValue;
+    const unsigned nb = blocks(cells(g) / 8);
     hipLaunchKernelGGL(km_norm, dim3(nb), dim3(kB), 0, s, g, mask, w, u, src, partial);
     *nparts = (int)nb;
     return hipGetLastError();

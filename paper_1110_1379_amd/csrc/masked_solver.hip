@@ -29,6 +29,13 @@ int ensure_masked(mgfr_ctx* c, int N, int coarsest)
             return c->fail(MGFR_ENOMEM, "hipMalloc of the masked %d^3 level failed", n);
         }
     }
+    mgfr::Grid gN{};
+    gN.n = N;
+    gN.lg = ilog2(N);
+    if (hipMalloc(&c->mpart, sizeof(double) * 2 * (size_t)mgfr::masked_norm_partials(gN)) != hipSuccess) {
+        c->free_masked();
+        return c->fail(MGFR_ENOMEM, "hipMalloc of the norm partials failed");
+    }
     c->MN = N;
     c->Mcoarsest = coarsest;
     return MGFR_OK;
@@ -106,8 +113,8 @@ struct MCycle {
     {
         mgfr_ctx::MLevel& L = c->mlv[0];
         int nparts = 0;
-        MGFR_TRY(hip_check(c, mgfr::masked_norm(L.g, L.mask, L.w, L.u, rho, c->partial, &nparts, s), "masked_norm"));
-        MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, nparts, c->red, s), "fold_partials"));
+        MGFR_TRY(hip_check(c, mgfr::masked_norm(L.g, L.mask, L.w, L.u, rho, c->mpart, &nparts, s), "masked_norm"));
+        MGFR_TRY(hip_check(c, mgfr::fold_partials(c->mpart, nparts, c->red, s), "fold_partials"));
         double r[2];
         MGFR_TRY(read_reduction(c, s, r));
         *rms = L.active > 0 ? std::sqrt(r[0] / (double)L.active) : 0.0;

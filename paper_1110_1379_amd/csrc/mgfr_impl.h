@@ -102,10 +102,13 @@ hipError_t masked_fas_rhs(const Grid& gc, const float* maskc, const double* wc, 
 // uf += P(uc - uhat) at active fine cells; zero correction from masked coarse cells.
 hipError_t masked_prolong(const Grid& gc, const float* maskc, const double* uc, const double* uhat,
                           const float* maskf, double* uf, hipStream_t s);
-// Block partials (sum d^2, max |d|) over active cells; their number in *nparts.
+// Block partials (sum d^2, max |d|) over active cells, one pair per 2048 cells (partial holds
+// masked_norm_partials(n) pairs); their number in *nparts.
+long long masked_norm_partials(const Grid& g);
 hipError_t masked_norm(const Grid& g, const float* mask, const double* w, const double* u, const double* src,
                        double* partial, int* nparts, hipStream_t s);
-// Coarsest level (n <= 8), one workgroup: sweeps until rms <= rtol x initial or cap;
+// Coarsest level (n <= 8), one workgroup: sweeps until rms <= rtol x initial, or the rounding
+// floor, or cap;
 // the sweep count is added to *sweeps.
 hipError_t masked_coarsest(const Grid& g, const float* mask, const double* w, double* u, const double* f, int cap,
                            double rtol, long long* sweeps, hipStream_t s);
