@@ -258,3 +258,39 @@ def masked_level(N: int = 512, seed: int = 2, count: int = 2000, fraction: float
     thr = float(np.quantile(od, 1.0 - fraction))
     del od
     return rho, oct_mask(rho, thr, expand=1)
+
+
+# --- particles --------------------------------------------------------------------------
+
+def particles(Ng: int, seed: int = 3, disp_cells: float = 2.0, clump_fraction: float = 0.3,
+              clump_every: int = 2000) -> np.ndarray:
+    """Ng^3 particle positions in the unit box, shaped like an evolved N-body set: a lattice of
+    cell centres displaced along the gradient of a smooth Gaussian potential (the Zel'dovich
+    recipe of N-body initial conditions; rms displacement `disp_cells` lattice cells per axis),
+    then a fraction `clump_fraction` of the particles moved into compact Gaussian clumps (one
+    clump per `clump_every` particles, radii 0.5-3 cells) to give the dense knots that halos
+    make.  Returns float64 (Ng^3, 3) in [0, 1), lattice (C) order."""
+    rng = np.random.Generator(np.random.PCG64(seed + 3 * 10 ** 6))
+    n = Ng ** 3
+    phi = gaussian_field(Ng, 1.0, -3.0, seed)
+    pk = np.fft.rfftn(phi)
+    del phi
+    kx = 2.0 * np.pi * np.fft.fftfreq(Ng)
+    kz = 2.0 * np.pi * np.fft.rfftfreq(Ng)
+    pos = np.empty((n, 3))
+    q = (np.arange(Ng) + 0.5) / Ng
+    for ax in range(3):
+        k = (kx[:, None, None], kx[None, :, None], kz[None, None, :])[ax]
+        psi = np.fft.irfftn(-1j * k * pk, s=(Ng,) * 3, axes=(0, 1, 2))
+        psi *= disp_cells / (psi.std() * Ng)
+        lat = np.broadcast_to(q.reshape([-1 if a == ax else 1 for a in range(3)]), (Ng,) * 3)
+        pos[:, ax] = (lat + psi).reshape(-1)
+        del psi
+    del pk
+    nc = max(1, n // clump_every)
+    centres = rng.random((nc, 3))
+    radii = rng.uniform(0.5, 3.0, nc) / Ng
+    moved = rng.random(n) < clump_fraction
+    which = rng.integers(0, nc, int(moved.sum()))
+    pos[moved] = centres[which] + radii[which, None] * rng.standard_normal((len(which), 3))
+    return np.mod(pos, 1.0)
