@@ -395,6 +395,89 @@ def bench_masked(args):
     return out
 
 
+def bench_tsc(args):
+    """TSC density assignment of 512^3 clustered particles on the 512^3 grid and the TSC force
+    interpolation of the potential back to them (Sec. VI.C); the potential comes from an
+    untimed f(R) solve (mixed) and modified Poisson solve of the deposited density.  One step =
+    one assignment + one interpolation."""
+    import torch
+    from paper_1110_1379_amd import inputs, mgfr
+    N = Ng = 512
+    box, fr0 = 512.0, 1e-6
+    log("generating 512^3 particles")
+    pos_h = inputs.particles(Ng, seed=3)
+    npart = len(pos_h)
+    pos = torch.from_numpy(pos_h).to("cuda:0")
+    params = mgfr.Params(box_mpc_h=box, fr0_abs=fr0)
+    ctx = mgfr.Context(0)
+    mass = N ** 3 / npart
+    rho = mgfr.mgfr_tsc_density(ctx, pos, N, mass)
+    u, _, st = mgfr.mg_fr_solve(ctx, rho, params, mgfr.mgfr_default_opts(tol=1e-8, precision=mgfr.MGFR_MIXED,
+                                                                            inner_cycles=2, max_cycles=100))
+    assert st == mgfr.MGFR_OK, ctx.last_error()
+    phi, _, st = mgfr.mg_poisson_solve(ctx, rho, u, params, mgfr.mgfr_default_opts(tol=1e-8, max_cycles=100))
+    assert st == mgfr.MGFR_OK, ctx.last_error()
+    del u
+    acc = torch.empty_like(pos)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    dep_ms, frc_ms = [], []
+
+    def step():
+        ev[0].record(stream)
+        mgfr.mgfr_tsc_density(ctx, pos, N, mass, rho=rho, stream=stream)
+        ev[1].record(stream)
+        mgfr.mgfr_tsc_force(ctx, phi, pos, acc=acc, stream=stream)
+        ev[2].record(stream)
+        return None
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        dep_ms.append(ev[0].elapsed_time(ev[1]))
+        frc_ms.append(ev[1].elapsed_time(ev[2]))
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    d_ms, f_ms = sum(dep_ms) / len(dep_ms), sum(frc_ms) / len(frc_ms)
+    # algorithmic bytes: assignment reads the positions and clears and fills the grid;
+    # interpolation reads the positions and the potential and writes the accelerations
+    dep_bytes = 24.0 * npart + 16.0 * N ** 3
+    frc_bytes = 48.0 * npart + 8.0 * N ** 3
+    out = {"metric": "TSC density assignment + force interpolation, 512^3 particles on 512^3: particles/s",
+           "value": npart / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"tsc512: {npart} particles (Zel'dovich-displaced lattice, 30% in compact clumps) "
+                                  f"on the {N}^3 grid of a {box:g} Mpc/h box; potential from the f(R) and modified "
+                                  f"Poisson solves of their density",
+                      "particles": npart, "N": N},
+           "time_includes": "the coordinate checks of both calls (one reduction and one synchronisation each)",
+           "assignment_ms": d_ms, "interpolation_ms": f_ms,
+           "roofline": {"bound": "hbm", "achieved": dep_bytes / (d_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": dep_bytes / (d_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "k_tsc_deposit (27 hardware FP64 atomics per particle) with its clear and check",
+                        "bytes": "24 per particle + 16 per cell",
+                        "interpolation": {"achieved": frc_bytes / (f_ms * 1e-3) / 1e9,
+                                          "frac": frc_bytes / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                          "bytes": "48 per particle + 8 per cell"}}}
+    if not args.no_cpu_baseline:
+        import oracle.tsc as T
+        ns = 128
+        log(f"timing the CPU oracle on {ns}^3 particles")
+        ps = inputs.particles(ns, seed=3)
+        t0 = time.perf_counter()
+        r = T.deposit(ps, ns, 1.0)
+        T.force(r, ps)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": len(ps) / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{ns}^3 particles of the same recipe on the {ns}^3 grid, numpy "
+                                         f"assignment + interpolation (the density as potential), {dt:.1f} s"}
+    return out
+
+
 def _timed(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -522,7 +605,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="halo512", choices=sorted(WORKLOADS) + ["amr", "batch", "poisson512", "masked512"])
+    ap.add_argument("--workload", default="halo512", choices=sorted(WORKLOADS) + ["amr", "batch", "poisson512", "masked512", "tsc512"])
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -559,6 +642,8 @@ def main():
         out = bench_poisson(args)
     elif args.workload == "masked512":
         out = bench_masked(args)
+    elif args.workload == "tsc512":
+        out = bench_tsc(args)
     else:
         out = bench_domain(args)
     print(json.dumps(out))

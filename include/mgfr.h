@@ -265,6 +265,28 @@ int mg_poisson_solve(mgfr_ctx* ctx, const double* rho, const double* u, int N, c
 int mg_fr_solve_masked(mgfr_ctx* ctx, const double* rho, const float* mask, int N, const mgfr_params* params,
                        const mgfr_opts* opts, double* u, double* res_hist, int* n_hist, void* stream);
 
+/* Triangle-shaped-cloud density assignment (Sec. VI.C): the density of np particles on the
+ * periodic N^3 grid of the unit box.  A particle at x (box units; taken modulo 1) with
+ * s = x N, nearest cell floor(s) and offset d = s - floor(s) - 1/2 gives the cells floor(s)-1,
+ * floor(s), floor(s)+1 the weights (1/2 - d)^2/2, 3/4 - d^2, (1/2 + d)^2/2 per axis, times
+ * mass, the product over the three axes (mass N^3 / np gives mean density 1, the code-unit
+ * normalisation of rho~).
+ * pos   device, np x 3 doubles (x, y, z per particle), read; finite.
+ * rho   device, N^3 doubles, written (cleared first).
+ * N     power of two in [4, 1024].  The atomic additions make the summation order vary from
+ * call to call (results agree to rounding).  Returns MGFR_ENONFINITE for a non-finite
+ * coordinate (rho untouched).  Synchronises once (the coordinate check). */
+int mgfr_tsc_density(mgfr_ctx* ctx, const double* pos, long long np, int N, double mass, double* rho, void* stream);
+
+/* TSC force interpolation (Sec. VI.C): the acceleration -grad phi at np particles, the cell
+ * values -(phi[i+1] - phi[i-1]) N / 2 per axis (central differences, periodic) weighted with
+ * the same 27 TSC weights as mgfr_tsc_density, which makes the pair momentum conserving.
+ * phi   device, N^3 doubles (e.g. from mg_poisson_solve), read.
+ * pos   device, np x 3 doubles, read; acc: device, np x 3 doubles, written.
+ * Returns MGFR_ENONFINITE for a non-finite coordinate.  Synchronises once. */
+int mgfr_tsc_force(mgfr_ctx* ctx, const double* phi, int N, const double* pos, long long np, double* acc,
+                   void* stream);
+
 #ifdef __cplusplus
 }
 #endif

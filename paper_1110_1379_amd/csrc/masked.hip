@@ -202,27 +202,14 @@ __global__ void __launch_bounds__(kB) km_fas_rhs(Grid g, const float* __restrict
     f[q] = masked_op(g, mask, w, uhat, i, j, k, uhat[q], mi, 0.0).L - f[q];
 }
 
-// u^h += P(u^H - R u^h) at active fine cells, weights 27/9/3/1 over 64, periodic; masked
-// coarse cells contribute no correction.
-__global__ void __launch_bounds__(kB) km_prolong(int lgc, const float* __restrict__ maskc,
-                                                 const double* __restrict__ uc, const double* __restrict__ uhat,
-                                                 const float* __restrict__ maskf, double* __restrict__ uf)
+// Coarse correction u^H - R u^h at active coarse cells, zero at masked ones (no correction
+// comes from a cell that is not a valid multigrid cell), written over uhat.
+__global__ void __launch_bounds__(kB) km_coarse_diff(long long n, const float* __restrict__ maskc,
+                                                     const double* __restrict__ uc, double* __restrict__ uhat)
 {
-    const int lg = lgc + 1, n = 1 << lg, mc = (1 << lgc) - 1;
     const long long q = (long long)blockIdx.x * kB + threadIdx.x;
-    if (q >= (1LL << (3 * lg))) return;
-    if (!(maskf[q] > 0.0f)) return;
-    const int i = (int)(q >> (2 * lg)), j = (int)((q >> lg) & (n - 1)), k = (int)(q & (n - 1));
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const int In = (I + ((i & 1) ? 1 : -1)) & mc, Jn = (J + ((j & 1) ? 1 : -1)) & mc,
-              Kn = (K + ((k & 1) ? 1 : -1)) & mc;
-    auto e = [&](int a, int b, int c) -> double {
-        const long long p = ((((long long)a << lgc) + b) << lgc) + c;
-        return maskc[p] > 0.0f ? uc[p] - uhat[p] : 0.0;
-    };
-    const double p = 27.0 / 64.0 * e(I, J, K) + 9.0 / 64.0 * (e(In, J, K) + e(I, Jn, K) + e(I, J, Kn)) +
-                     3.0 / 64.0 * (e(In, Jn, K) + e(In, J, Kn) + e(I, Jn, Kn)) + 1.0 / 64.0 * e(In, Jn, Kn);
-    uf[q] += p;
+    if (q >= n) return;
+    uhat[q] = maskc[q] > 0.0f ? uc[q] - uhat[q] : 0.0;
 }
 
 // Block partials (sum d^2, max |d|) over the active cells.  A thread takes one 2x2x2 block of
@@ -433,11 +420,14 @@ hipError_t masked_fas_rhs(const Grid& gc, const float* maskc, const double* wc, 
     return hipGetLastError();
 }
 
-hipError_t masked_prolong(const Grid& gc, const float* maskc, const double* uc, const double* uhat,
-                          const float* maskf, double* uf, hipStream_t s)
+hipError_t masked_prolong(const Grid& gc, const float* maskc, const double* uc, double* uhat, const float* maskf,
+                          double* uf, hipStream_t s)
 {
-    hipLaunchKernelGGL(km_prolong, dim3(blocks(8 * cells(gc))), dim3(kB), 0, s, gc.lg, maskc, uc, uhat, maskf, uf);
-    return hipGetLastError();
+    // the correction, then the streaming 27/9/3/1 prolongation into the active fine cells
+    hipLaunchKernelGGL(km_coarse_diff, dim3(blocks(cells(gc))), dim3(kB), 0, s, cells(gc), maskc, uc, uhat);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return prolong_add_masked(gc, uf, uhat, maskf, s);
 }
 
 long long masked_norm_partials(const Grid& g) { return (long long)blocks(cells(g) / 8); }

@@ -99,9 +99,10 @@ hipError_t masked_resid_restrict(const Grid& g, const float* mask, const double*
 // f = L^H(uhat) - f at active cells of the coarse level gc.
 hipError_t masked_fas_rhs(const Grid& gc, const float* maskc, const double* wc, const double* uhat, double* f,
                           hipStream_t s);
-// uf += P(uc - uhat) at active fine cells; zero correction from masked coarse cells.
-hipError_t masked_prolong(const Grid& gc, const float* maskc, const double* uc, const double* uhat,
-                          const float* maskf, double* uf, hipStream_t s);
+// uf += P(uc - uhat) at active fine cells; zero correction from masked coarse cells.  uhat is
+// overwritten with the coarse correction.
+hipError_t masked_prolong(const Grid& gc, const float* maskc, const double* uc, double* uhat, const float* maskf,
+                          double* uf, hipStream_t s);
 // Block partials (sum d^2, max |d|) over active cells, one pair per 2048 cells (partial holds
 // masked_norm_partials(n) pairs); their number in *nparts.
 long long masked_norm_partials(const Grid& g);
@@ -204,6 +205,8 @@ hipError_t prolong_correct(const Grid& gc, double* uf, const double* uc, const d
 hipError_t prolong_correct32(const Grid& gc, float* ef, const float* ec, const float* ehat, hipStream_t s);
 // uf += P(ec), the correction itself on the coarse level (linear correction scheme).
 hipError_t prolong_add_direct(const Grid& gc, double* uf, const double* ec, hipStream_t s);
+// uf += P ec at the fine cells whose mask is positive (the others unchanged).
+hipError_t prolong_add_masked(const Grid& gc, double* uf, const double* ec, const float* maskf, hipStream_t s);
 
 // Coarsest level in one workgroup: sweeps until rms(L - f) <= rtol x initial or `cap`
 // sweeps (rtol = 0: exactly cap sweeps).  n <= 8.  Adds the sweeps done to *sweeps_done

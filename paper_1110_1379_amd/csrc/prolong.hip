@@ -15,9 +15,12 @@ namespace {
 
 constexpr int kPT = 256;  // threads (fine columns) per workgroup
 
+// DIFF: the correction is uc - uhat (else uc itself).  maskf (may be null): add only where
+// the fine mask is positive (the active cells of a masked level).
 template <typename T, int PI, bool DIFF>
 __global__ void __launch_bounds__(kPT) k_prolong_stream(int lgc, T* __restrict__ uf, const T* __restrict__ uc,
-                                                        const T* __restrict__ uhat, int ncolblk)
+                                                        const T* __restrict__ uhat, const float* __restrict__ maskf,
+                                                        int ncolblk)
 {
     const int lg = lgc + 1, n = 1 << lg, mc = (1 << lgc) - 1;
     const int nb = gridDim.x;
@@ -54,22 +57,25 @@ __global__ void __launch_bounds__(kPT) k_prolong_stream(int lgc, T* __restrict__
         const int lo = ((i - 1) >> 1) - ib;
         // odd i: the nearer coarse plane is the lower one
         const T wlo = (i & 1) ? T(0.75) : T(0.25);
-        uf[((unsigned)i << (2 * lg)) + col] = v[t] + (wlo * ep[lo] + (T(1) - wlo) * ep[lo + 1]);
+        const unsigned q = ((unsigned)i << (2 * lg)) + col;
+        if (maskf && !(maskf[q] > 0.0f)) continue;
+        uf[q] = v[t] + (wlo * ep[lo] + (T(1) - wlo) * ep[lo + 1]);
     }
 }
 
 template <typename T, bool DIFF>
-hipError_t launch(const Grid& gc, T* uf, const T* uc, const T* uhat, hipStream_t s)
+hipError_t launch(const Grid& gc, T* uf, const T* uc, const T* uhat, hipStream_t s, const float* maskf = nullptr)
 {
     const int n = gc.n * 2;
     if (gc.n < 2 || n > 1024) return hipErrorInvalidValue;
     const int ncolblk = (n * n + kPT - 1) / kPT;
     if (n >= 8) {
         const unsigned nb = (unsigned)(ncolblk * (n / 8));
-        hipLaunchKernelGGL((k_prolong_stream<T, 8, DIFF>), dim3(nb), dim3(kPT), 0, s, gc.lg, uf, uc, uhat, ncolblk);
+        hipLaunchKernelGGL((k_prolong_stream<T, 8, DIFF>), dim3(nb), dim3(kPT), 0, s, gc.lg, uf, uc, uhat, maskf,
+                           ncolblk);
     } else {
         hipLaunchKernelGGL((k_prolong_stream<T, 4, DIFF>), dim3((unsigned)ncolblk), dim3(kPT), 0, s, gc.lg, uf, uc, uhat,
-                           ncolblk);
+                           maskf, ncolblk);
     }
     return hipGetLastError();
 }
@@ -89,6 +95,11 @@ hipError_t prolong_correct32(const Grid& gc, float* ef, const float* ec, const f
 hipError_t prolong_add_direct(const Grid& gc, double* uf, const double* ec, hipStream_t s)
 {
     return launch<double, false>(gc, uf, ec, nullptr, s);
+}
+
+hipError_t prolong_add_masked(const Grid& gc, double* uf, const double* ec, const float* maskf, hipStream_t s)
+{
+    return launch<double, false>(gc, uf, ec, nullptr, s, maskf);
 }
 
 }  // namespace mgfr

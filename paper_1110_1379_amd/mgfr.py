@@ -97,6 +97,8 @@ def lib():
             "mg_poisson_solve": ([vp, vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
             "mgfr_tau": ([vp, vp, vp, ctypes.c_int, P, ctypes.c_int, vp, dp, vp], ctypes.c_int),
             "mg_fr_solve_masked": ([vp, vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
+            "mgfr_tsc_density": ([vp, vp, ctypes.c_longlong, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int),
+            "mgfr_tsc_force": ([vp, vp, ctypes.c_int, vp, ctypes.c_longlong, vp, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -110,7 +112,7 @@ def exported_symbols():
     return ("mgfr_create", "mgfr_destroy", "mgfr_last_error", "mgfr_default_opts", "mgfr_constants",
             "mgfr_residual", "mg_fr_solve", "mgfr_get_stats", "mgfr_smooth", "mg_fr_solve_patches",
             "mg_fr_solve_batch", "mgfr_autotune", "mg_poisson_solve", "mgfr_tau",
-            "mg_fr_solve_masked")
+            "mg_fr_solve_masked", "mgfr_tsc_density", "mgfr_tsc_force")
 
 
 def mgfr_default_opts(**overrides) -> mgfr_opts:
@@ -276,6 +278,33 @@ def mg_fr_solve_masked(ctx: Context, rho, mask, u, params: Params, opts: mgfr_op
     if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
         raise MgfrError(st, ctx.last_error())
     return u, hist[:nh.value].copy(), st
+
+
+def mgfr_tsc_density(ctx: Context, pos, N: int, mass: float, rho=None, stream=None):
+    """TSC density of particles pos (float64 device tensor (np, 3), box units) on the N^3 grid."""
+    import torch
+    if pos.dtype != torch.float64 or pos.dim() != 2 or pos.shape[1] != 3:
+        raise TypeError("pos must be a float64 (np, 3) tensor")
+    if rho is None:
+        rho = torch.empty((N,) * 3, dtype=torch.float64, device=pos.device)
+    st = lib().mgfr_tsc_density(ctx.handle, _ptr(pos), pos.shape[0], N, float(mass), _ptr(rho), _stream(stream))
+    if st != MGFR_OK:
+        raise MgfrError(st, ctx.last_error())
+    return rho
+
+
+def mgfr_tsc_force(ctx: Context, phi, pos, acc=None, stream=None):
+    """-grad phi interpolated to the particles with the TSC weights: float64 (np, 3)."""
+    import torch
+    if pos.dtype != torch.float64 or pos.dim() != 2 or pos.shape[1] != 3 or phi.dtype != torch.float64:
+        raise TypeError("phi must be float64 and pos a float64 (np, 3) tensor")
+    if acc is None:
+        acc = torch.empty_like(pos)
+    st = lib().mgfr_tsc_force(ctx.handle, _ptr(phi), phi.shape[0], _ptr(pos), pos.shape[0], _ptr(acc),
+                              _stream(stream))
+    if st != MGFR_OK:
+        raise MgfrError(st, ctx.last_error())
+    return acc
 
 
 def mg_poisson_solve(ctx: Context, rho, u, params: Params, opts: mgfr_opts | None = None, phi=None,
