@@ -32,20 +32,21 @@ METRIC = "f(R) MG time-to-residual 1e-8 & cell-updates/s, 512^3, FP64 vs mixed"
 
 # HBM bytes per finest-level (512^3) launch of the dominant kernels, from rocprofv3 FETCH_SIZE
 # and WRITE_SIZE runs scaled by a plain copy (profiles/halo512_traffic.md), with the SHA-256
-# of the sources those kernels were built from: when any of them differs the figure no longer
-# describes the kernel that runs and `traffic` is reported as null.
+# of the sources those kernels are compiled from (the kernel file, its device header and the
+# by-value kernel types): when any of them differs the figure no longer describes the kernel
+# that runs and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "mixed": {"bytes": 2.620e9, "sources": {
+    "mixed": {"bytes": 2.782e9, "sources": {
         "kernels_fp32.hip": "d94c636fbf7cea404db182a5e9c93cb71f343adcb6c84d301b00ab6941af2905",
         "device_fp32.h": "8e0b1788cfffc170c22c27c14ed38910f5eb958ebe543a31c498e8e0de7d38e0",
-        "mgfr_impl.h": "a3d1a03a5bc35087868460c1d6192e94158c44008ddf3555d1ce0d3445871012"}},
+        "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
     "fp64": {"bytes": 3.428e9, "sources": {
         "sweep_fp64.hip": "8626f8c275f300f245261a3ce754af32586572b601a374203ca3eeb1fd8c8850",
         "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
-        "mgfr_impl.h": "a3d1a03a5bc35087868460c1d6192e94158c44008ddf3555d1ce0d3445871012"}},
-    "poisson": {"bytes": 4.066e9, "sources": {
+        "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
+    "poisson": {"bytes": 4.020e9, "sources": {
         "poisson_kernels.hip": "9f8450a69b89060ccd64b388e3d917e830632923c46e8af95fe879c5e20f908d",
-        "mgfr_impl.h": "54f0112e8a32b398f1f64c43ab2b45410fbc2a4cc1a5e938fb4612e8f5bde746"}},
+        "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
 }
 
 
