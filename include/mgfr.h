@@ -271,11 +271,14 @@ int mg_fr_solve_masked(mgfr_ctx* ctx, const double* rho, const float* mask, int 
  * floor(s), floor(s)+1 the weights (1/2 - d)^2/2, 3/4 - d^2, (1/2 + d)^2/2 per axis, times
  * mass, the product over the three axes (mass N^3 / np gives mean density 1, the code-unit
  * normalisation of rho~).
- * pos   device, np x 3 doubles (x, y, z per particle), read; finite.
- * rho   device, N^3 doubles, written (cleared first).
- * N     power of two in [4, 1024].  The atomic additions make the summation order vary from
- * call to call (results agree to rounding).  Returns MGFR_ENONFINITE for a non-finite
- * coordinate (rho untouched).  Synchronises once (the coordinate check). */
+ * The particles are sorted by nearest cell on the device and every cell sums the
+ * contributions of the particles in its 27 neighbouring cells in a fixed order: the result is
+ * the same bits on every call (no atomics).
+ * pos   device, np x 3 doubles (x, y, z per particle), read; finite; np < 2^31.
+ * rho   device, N^3 doubles, written.
+ * N     power of two in [4, 1024].  Scratch (about 40 B per particle + 4 B per cell) is kept
+ * in the context.  Returns MGFR_ENONFINITE for a non-finite coordinate (rho untouched).
+ * Synchronises once (the coordinate check). */
 int mgfr_tsc_density(mgfr_ctx* ctx, const double* pos, long long np, int N, double mass, double* rho, void* stream);
 
 /* TSC force interpolation (Sec. VI.C): the acceleration -grad phi at np particles, the cell

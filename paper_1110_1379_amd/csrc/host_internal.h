@@ -135,6 +135,9 @@ struct mgfr_ctx {
         mlv.clear();
         MN = 0;
     }
+    // TSC assignment scratch (keys, indices, sorted positions, cell table, sort storage)
+    void* tsc = nullptr;
+    size_t tsc_bytes = 0;
     // device blocks of finished batched solves, reused by later ones (smallest that fits)
     std::vector<std::pair<void*, size_t>> spare;
 

@@ -232,6 +232,7 @@ void mgfr_destroy(mgfr_ctx* c)
     c->free_spare();
     c->free_poisson();
     c->free_masked();
+    (void)hipFree(c->tsc);
     delete c;
 }
 

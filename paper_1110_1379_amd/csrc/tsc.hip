@@ -4,12 +4,22 @@
 // Box units, periodic: cell i of the N^3 grid covers [i/N, (i+1)/N).  A particle at x has
 // s = x N (modulo N), nearest cell floor(s) and offset d = s - floor(s) - 1/2; the cells
 // floor(s) - 1, floor(s), floor(s) + 1 get the weights (1/2 - d)^2 / 2, 3/4 - d^2,
-// (1/2 + d)^2 / 2 per axis, their product in 3-D.  Assignment adds mass x weight to the 27
-// cells (hardware double-precision atomics in L2; the order of the additions is not fixed,
-// so the density is exact up to the rounding of a sum in some order).  Interpolation applies
-// the same weights to the cell accelerations -grad phi, taken by central differences, so the
-// pair conserves momentum.  Contraction into fused multiply-adds is switched off in the
-// weight and interpolation arithmetic, so every product and sum rounds as written.
+// (1/2 + d)^2 / 2 per axis, their product in 3-D.  Interpolation applies the same weights to
+// the cell accelerations -grad phi, taken by central differences, so the pair conserves
+// momentum.  Contraction into fused multiply-adds is switched off in the weight, product and
+// sum arithmetic, so every operation rounds as written.
+//
+// Assignment is a gather, not a scatter: the particles are sorted by the key of their nearest
+// cell (radix sort), a table gives each cell's range in that order, and one thread per cell
+// sums the contributions of the particles whose nearest cell is one of its 27 neighbours (in
+// a fixed order, so the density is the same bits on every call).  Along k the three
+// neighbouring cells of a row are consecutive keys, so a cell reads nine contiguous particle
+// ranges.  No atomics: in the clumps a scatter would put many lanes of a wavefront on the
+// same few addresses.
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
 #include "host_internal.h"
 
 using namespace mgfr_host;
@@ -24,11 +34,11 @@ constexpr int kB = 256;
 // Nearest cell index and the three weights per axis of the particle at p[0..2].
 __device__ __forceinline__ void tsc_weights(const double* __restrict__ p, int N, int (&c)[3], double (&w)[3][3])
 {
-    const double Nd = (double)N;
+    const double Nd = (double)N, inv = 1.0 / Nd;  // N is a power of two: s * inv is s / N exactly
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         double s = p[ax] * Nd;
-        s = s - Nd * floor(s / Nd);
+        s = s - Nd * floor(s * inv);
         if (s >= Nd) s -= Nd;
         const double fl = floor(s);
         const double d = s - fl - 0.5;
@@ -40,27 +50,102 @@ __device__ __forceinline__ void tsc_weights(const double* __restrict__ p, int N,
     }
 }
 
-__global__ void __launch_bounds__(kB) k_tsc_deposit(const double* __restrict__ pos, long long np, int N, int lg,
-                                                    double mass, double* __restrict__ rho)
+// Key (flat index of the nearest cell) and identity index of every particle.
+__global__ void __launch_bounds__(kB) k_tsc_keys(const double* __restrict__ pos, long long np, int N, int lg,
+                                                 unsigned* __restrict__ key, unsigned* __restrict__ idx)
 {
     const long long p = (long long)blockIdx.x * kB + threadIdx.x;
     if (p >= np) return;
     int c[3];
     double w[3][3];
     tsc_weights(pos + 3 * p, N, c, w);
-    const int m = N - 1;
+    key[p] = ((unsigned)c[0] << (2 * lg)) | ((unsigned)c[1] << lg) | (unsigned)c[2];
+    idx[p] = (unsigned)p;
+}
+
+// Offsets d (x, y, z) of the particles from their nearest cell centre, in key order: the
+// weights of a particle follow from d alone, and its nearest cell from its key.
+__global__ void __launch_bounds__(kB) k_tsc_gather(const double* __restrict__ pos, const unsigned* __restrict__ idx,
+                                                   long long np, int N, double* __restrict__ dsorted)
+{
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    if (t >= np) return;
+    const long long p = idx[t];
+    const double Nd = (double)N, inv = 1.0 / Nd;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const long long ia = (long long)((c[0] + a - 1) & m) << (2 * lg);
-        const double ma = mass * w[0][a];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const long long jb = ia + ((long long)((c[1] + b - 1) & m) << lg);
-            const double mab = ma * w[1][b];
-#pragma unroll
-            for (int z = 0; z < 3; ++z) unsafeAtomicAdd(rho + jb + ((c[2] + z - 1) & m), mab * w[2][z]);
-        }
+    for (int ax = 0; ax < 3; ++ax) {
+        double s = pos[3 * p + ax] * Nd;
+        s = s - Nd * floor(s * inv);
+        if (s >= Nd) s -= Nd;
+        dsorted[3 * t + ax] = s - floor(s) - 0.5;
     }
+}
+
+// The TSC weight of offset o in {0, 1, 2} (cells -1, 0, +1 from the nearest) at offset d.
+__device__ __forceinline__ double tsc_w(double d, int o)
+{
+    if (o == 1) return 0.75 - d * d;
+    const double t = o == 0 ? 0.5 - d : 0.5 + d;
+    return 0.5 * (t * t);
+}
+
+// start[c] = first position in key order of a particle with key >= c, for c = 0 .. ncell
+// (start[ncell] = np): the particles of cell c are start[c] .. start[c+1] - 1.
+__global__ void __launch_bounds__(kB) k_tsc_cell_start(const unsigned* __restrict__ key, long long np,
+                                                       long long ncell, unsigned* __restrict__ start)
+{
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    if (t >= np) return;
+    const long long k = key[t];
+    const long long prev = t > 0 ? (long long)key[t - 1] : -1;
+    for (long long c = prev + 1; c <= k; ++c) start[c] = (unsigned)t;
+    if (t == np - 1)
+        for (long long c = k + 1; c <= ncell; ++c) start[c] = (unsigned)np;
+}
+
+__global__ void __launch_bounds__(kB) k_tsc_fill_start(unsigned* __restrict__ start, long long n)
+{
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    if (t < n) start[t] = 0u;
+}
+
+// Density of cell (i,j,k): the sum over the particles whose nearest cell is (i+a, j+b, k+c),
+// a, b, c in {-1, 0, 1}, of mass x their weight for offset (-a, -b, -c).
+__global__ void __launch_bounds__(kB) k_tsc_density(const double* __restrict__ dsorted, const unsigned* __restrict__ key,
+                                                    const unsigned* __restrict__ start, int N, int lg, double mass,
+                                                    double* __restrict__ rho)
+{
+    const long long q = (long long)blockIdx.x * kB + threadIdx.x;
+    if (q >= (1LL << (3 * lg))) return;
+    const int m = N - 1;
+    const int i = (int)(q >> (2 * lg)), j = (int)((q >> lg) & m), k = (int)(q & m);
+    double sum = 0.0;
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b) {
+            const unsigned row = ((unsigned)((i + a) & m) << (2 * lg)) | ((unsigned)((j + b) & m) << lg);
+            // the row's cells k-1, k, k+1: one range unless the row wraps
+            unsigned r0[3], r1[3];
+            int nr;
+            if (k >= 1 && k <= N - 2) {
+                r0[0] = start[row + k - 1];
+                r1[0] = start[row + k + 2];
+                nr = 1;
+            } else {
+                for (int c = 0; c < 3; ++c) {
+                    const unsigned cell = row + (unsigned)((k + c - 1) & m);
+                    r0[c] = start[cell];
+                    r1[c] = start[cell + 1];
+                }
+                nr = 3;
+            }
+            for (int r = 0; r < nr; ++r)
+                for (unsigned t = r0[r]; t < r1[r]; ++t) {
+                    const int oz = (k - (int)(key[t] & (unsigned)m) + 1) & m;  // 0, 1, 2 for offsets -1, 0, +1
+                    const double* d = dsorted + 3 * (long long)t;
+                    sum = sum + mass * tsc_w(d[0], 1 - a) * tsc_w(d[1], 1 - b) * tsc_w(d[2], oz);
+                }
+        }
+    rho[q] = sum;
 }
 
 // acc = sum over the 27 cells of weight x (-grad phi), -grad phi by central differences.
@@ -75,7 +160,14 @@ __global__ void __launch_bounds__(kB) k_tsc_force(const double* __restrict__ phi
     tsc_weights(pos + 3 * p, N, c, w);
     const int m = N - 1;
     const double half = (double)N / 2.0;
-    auto at = [&](int i, int j, int k) { return phi[((((long long)(i & m) << lg) + (j & m)) << lg) + (k & m)]; };
+    // offsets of the planes c0-2 .. c0+2, rows c1-2 .. c1+2 and columns c2-2 .. c2+2
+    unsigned pi[5], rj[5], ck[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        pi[t] = (unsigned)((c[0] + t - 2) & m) << (2 * lg);
+        rj[t] = (unsigned)((c[1] + t - 2) & m) << lg;
+        ck[t] = (unsigned)((c[2] + t - 2) & m);
+    }
     double fx = 0.0, fy = 0.0, fz = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -83,11 +175,11 @@ __global__ void __launch_bounds__(kB) k_tsc_force(const double* __restrict__ phi
         for (int b = 0; b < 3; ++b)
 #pragma unroll
             for (int z = 0; z < 3; ++z) {
-                const int i = c[0] + a - 1, j = c[1] + b - 1, k = c[2] + z - 1;
+                // cell (c0 + a - 1, c1 + b - 1, c2 + z - 1) is index a+1, b+1, z+1 of the 5-wide ranges
                 const double wt = w[0][a] * w[1][b] * w[2][z];
-                const double gx = -(at(i + 1, j, k) - at(i - 1, j, k)) * half;
-                const double gy = -(at(i, j + 1, k) - at(i, j - 1, k)) * half;
-                const double gz = -(at(i, j, k + 1) - at(i, j, k - 1)) * half;
+                const double gx = -(phi[pi[a + 2] + rj[b + 1] + ck[z + 1]] - phi[pi[a] + rj[b + 1] + ck[z + 1]]) * half;
+                const double gy = -(phi[pi[a + 1] + rj[b + 2] + ck[z + 1]] - phi[pi[a + 1] + rj[b] + ck[z + 1]]) * half;
+                const double gz = -(phi[pi[a + 1] + rj[b + 1] + ck[z + 2]] - phi[pi[a + 1] + rj[b + 1] + ck[z]]) * half;
                 fx = fx + wt * gx;
                 fy = fy + wt * gy;
                 fz = fz + wt * gz;
@@ -131,17 +223,57 @@ int mgfr_tsc_density(mgfr_ctx* c, const double* pos, long long np, int N, double
     if (!c) return MGFR_EINVAL;
     c->err.clear();
     MGFR_TRY(mgfr::check_args(c, pos, np, N));
+    if (np >= (1LL << 31)) return c->fail(MGFR_EINVAL, "assignment takes at most 2^31 - 1 particles (%lld)", np);
     if (!rho) return c->fail(MGFR_EINVAL, "rho is NULL");
     if (!std::isfinite(mass)) return c->fail(MGFR_EINVAL, "mass must be finite");
     MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
     hipStream_t s = (hipStream_t)stream;
     MGFR_TRY(mgfr::check_positions(c, pos, np, s));
-    MGFR_TRY(hip_check(c, mgfr::fill(rho, 0.0, (long long)N * N * N, s), "fill"));
-    if (np > 0) {
-        hipLaunchKernelGGL(mgfr::k_tsc_deposit, dim3(mgfr::blocks(np)), dim3(mgfr::kB), 0, s, pos, np, N, ilog2(N), mass,
-                           rho);
-        MGFR_TRY(hip_check(c, hipGetLastError(), "k_tsc_deposit"));
+    const int lg = ilog2(N);
+    const long long ncell = (long long)N * N * N;
+    // scratch: keys and indices (twice, for the sort), positions in key order, cell starts,
+    // sort temporary storage -- one block kept in the context
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t tmp_bytes = 0;
+    if (np > 0)
+        MGFR_TRY(hip_check(c, rocprim::radix_sort_pairs(nullptr, tmp_bytes, (unsigned*)nullptr, (unsigned*)nullptr,
+                                                        (unsigned*)nullptr, (unsigned*)nullptr, (size_t)np, 0, 3 * lg, s),
+                           "radix_sort_pairs (size query)"));
+    const size_t ub = al(sizeof(unsigned) * (size_t)np);
+    const size_t need = 4 * ub + al(sizeof(double) * 3 * (size_t)np) + al(sizeof(unsigned) * (size_t)(ncell + 1)) +
+                        al(tmp_bytes);
+    if (c->tsc_bytes < need) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(c->tsc);
+        c->tsc = nullptr;
+        c->tsc_bytes = 0;
+        if (hipMalloc(&c->tsc, need) != hipSuccess) return c->fail(MGFR_ENOMEM, "hipMalloc of %zu bytes failed", need);
+        c->tsc_bytes = need;
     }
+    char* b = (char*)c->tsc;
+    unsigned* key = (unsigned*)b;
+    unsigned* key2 = (unsigned*)(b + ub);
+    unsigned* idx = (unsigned*)(b + 2 * ub);
+    unsigned* idx2 = (unsigned*)(b + 3 * ub);
+    double* sorted = (double*)(b + 4 * ub);
+    unsigned* start = (unsigned*)(b + 4 * ub + al(sizeof(double) * 3 * (size_t)np));
+    void* tmp = b + 4 * ub + al(sizeof(double) * 3 * (size_t)np) + al(sizeof(unsigned) * (size_t)(ncell + 1));
+    if (np > 0) {
+        hipLaunchKernelGGL(mgfr::k_tsc_keys, dim3(mgfr::blocks(np)), dim3(mgfr::kB), 0, s, pos, np, N, lg, key, idx);
+        MGFR_TRY(hip_check(c, hipGetLastError(), "k_tsc_keys"));
+        MGFR_TRY(hip_check(c, rocprim::radix_sort_pairs(tmp, tmp_bytes, key, key2, idx, idx2, (size_t)np, 0, 3 * lg, s),
+                           "radix_sort_pairs"));
+        hipLaunchKernelGGL(mgfr::k_tsc_gather, dim3(mgfr::blocks(np)), dim3(mgfr::kB), 0, s, pos, idx2, np, N, sorted);
+        MGFR_TRY(hip_check(c, hipGetLastError(), "k_tsc_gather"));
+        hipLaunchKernelGGL(mgfr::k_tsc_cell_start, dim3(mgfr::blocks(np)), dim3(mgfr::kB), 0, s, key2, np, ncell, start);
+        MGFR_TRY(hip_check(c, hipGetLastError(), "k_tsc_cell_start"));
+    } else {
+        hipLaunchKernelGGL(mgfr::k_tsc_fill_start, dim3(mgfr::blocks(ncell + 1)), dim3(mgfr::kB), 0, s, start, ncell + 1);
+        MGFR_TRY(hip_check(c, hipGetLastError(), "k_tsc_fill_start"));
+    }
+    hipLaunchKernelGGL(mgfr::k_tsc_density, dim3(mgfr::blocks(ncell)), dim3(mgfr::kB), 0, s, sorted, key2, start, N, lg,
+                       mass, rho);
+    MGFR_TRY(hip_check(c, hipGetLastError(), "k_tsc_density"));
     return MGFR_OK;
 }
 

@@ -3,10 +3,10 @@ mgfr_tsc_force) with the oracle (oracle/tsc.py), on an MI355X.
 
 Particles come from the seeded clustered generator (inputs.particles); potentials from the
 oracle's periodic Poisson solve of the oracle's own density, or a seeded smooth field.  The
-density is a sum of atomic additions in no fixed order, so it is compared to a bar of 1e-12
-of its maximum; the force evaluates the same products and sums in the same order as the
-oracle (no contraction), so it is compared to 1e-13 of the largest term and reported when
-bit-identical.  At 512^3 particles on the 512^3 grid (the configuration bench.py times) the
+density sums each cell's contributions in an order of its own (particles sorted by cell), so
+it is compared to a bar of 1e-12 of its maximum and checked to repeat bit for bit; the force
+evaluates the same products and sums in the same order as the oracle (no contraction), so it
+is compared to 1e-13 of the largest term and reported when bit-identical.  At 512^3 particles on the 512^3 grid (the configuration bench.py times) the
 density is checked at sampled cells against the brute-force sum over the particles near
 them, the total mass exactly, and the force at sampled particles.
 """
@@ -56,6 +56,8 @@ def test_density_and_force_match_oracle(mg, ctx, Ng, N):
     ref = tsc.deposit(pos, N, m)
     pd = dev(pos)
     rho = mg.mgfr_tsc_density(ctx, pd, N, m).cpu().numpy()
+    # a fixed summation order: the same bits on a second call
+    assert np.array_equal(rho, mg.mgfr_tsc_density(ctx, pd, N, m).cpu().numpy())
     err = np.abs(rho - ref).max()
     assert err <= 1e-12 * ref.max(), err
     assert abs(rho.sum() - len(pos) * m) <= 1e-12 * len(pos) * m
