@@ -138,12 +138,28 @@ __global__ void __launch_bounds__(kB) k_tsc_density(const double* __restrict__ d
                 }
                 nr = 3;
             }
-            for (int r = 0; r < nr; ++r)
-                for (unsigned t = r0[r]; t < r1[r]; ++t) {
-                    const int oz = (k - (int)(key[t] & (unsigned)m) + 1) & m;  // 0, 1, 2 for offsets -1, 0, +1
-                    const double* d = dsorted + 3 * (long long)t;
-                    sum = sum + mass * tsc_w(d[0], 1 - a) * tsc_w(d[1], 1 - b) * tsc_w(d[2], oz);
+            auto term = [&](unsigned kk, double dx, double dy, double dz) {
+                const int oz = (k - (int)(kk & (unsigned)m) + 1) & m;  // 0, 1, 2 for offsets -1, 0, +1
+                return mass * tsc_w(dx, 1 - a) * tsc_w(dy, 1 - b) * tsc_w(dz, oz);
+            };
+            for (int r = 0; r < nr; ++r) {
+                unsigned t = r0[r];
+                // four particles' loads in flight at a time; the sum still runs in order
+                for (; t + 4 <= r1[r]; t += 4) {
+                    unsigned kk[4];
+                    double dd[12];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) kk[u] = key[t + u];
+#pragma unroll
+                    for (int u = 0; u < 12; ++u) dd[u] = dsorted[3 * (long long)t + u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) sum = sum + term(kk[u], dd[3 * u], dd[3 * u + 1], dd[3 * u + 2]);
                 }
+                for (; t < r1[r]; ++t) {
+                    const double* d = dsorted + 3 * (long long)t;
+                    sum = sum + term(key[t], d[0], d[1], d[2]);
+                }
+            }
         }
     rho[q] = sum;
 }
