@@ -31,6 +31,15 @@ constexpr int kB = 256;
 
 #pragma clang fp contract(off)
 
+// Workgroup index remapped so that each of the 8 XCDs (which take workgroups round robin)
+// runs one contiguous eighth of the grid: neighbouring cells and particles then share an L2.
+__device__ __forceinline__ long long xcd_block()
+{
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    if (nb & 7) return b;
+    return (long long)(b & 7) * (nb >> 3) + (b >> 3);
+}
+
 // Nearest cell index and the three weights per axis of the particle at p[0..2].
 __device__ __forceinline__ void tsc_weights(const double* __restrict__ p, int N, int (&c)[3], double (&w)[3][3])
 {
@@ -115,7 +124,7 @@ __global__ void __launch_bounds__(kB) k_tsc_density(const double* __restrict__ d
                                                     const unsigned* __restrict__ start, int N, int lg, double mass,
                                                     double* __restrict__ rho)
 {
-    const long long q = (long long)blockIdx.x * kB + threadIdx.x;
+    const long long q = xcd_block() * kB + threadIdx.x;
     if (q >= (1LL << (3 * lg))) return;
     const int m = N - 1;
     const int i = (int)(q >> (2 * lg)), j = (int)((q >> lg) & m), k = (int)(q & m);
@@ -169,7 +178,7 @@ __global__ void __launch_bounds__(kB) k_tsc_force(const double* __restrict__ phi
                                                   const double* __restrict__ pos, long long np,
                                                   double* __restrict__ acc)
 {
-    const long long p = (long long)blockIdx.x * kB + threadIdx.x;
+    const long long p = xcd_block() * kB + threadIdx.x;
     if (p >= np) return;
     int c[3];
     double w[3][3];
