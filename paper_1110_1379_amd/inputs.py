@@ -282,7 +282,9 @@ def particles(Ng: int, seed: int = 3, disp_cells: float = 2.0, clump_fraction: f
     for ax in range(3):
         k = (kx[:, None, None], kx[None, :, None], kz[None, None, :])[ax]
         psi = np.fft.irfftn(-1j * k * pk, s=(Ng,) * 3, axes=(0, 1, 2))
-        psi *= disp_cells / (psi.std() * Ng)
+        sd = psi.std()
+        if sd > 0:  # a 2^3 lattice has no resolved gradient
+            psi *= disp_cells / (sd * Ng)
         lat = np.broadcast_to(q.reshape([-1 if a == ax else 1 for a in range(3)]), (Ng,) * 3)
         pos[:, ax] = (lat + psi).reshape(-1)
         del psi

@@ -138,6 +138,38 @@ def test_cycle_settings(mg, ctx):
     assert np.abs(ug - ug2).max() <= 1e-9
 
 
+def test_subtract_mean_and_single_level(mg, ctx):
+    """MGFR_SUBTRACT_MEAN (contrast about the mean density) against the oracle's
+    subtract_mean, and a level that is its own coarsest level (8^3, coarsest_n 8: the whole
+    solve runs in the one-workgroup kernel with the density as source)."""
+    say("[masked] subtract mean, single level")
+    import torch
+    rho, mask, u0, box, fr0 = oct_case(32, 7, 0.15)
+    rho = rho * 1.7  # mean 1.7: the two density references differ
+    m = O.Model(box_mpc_h=box, fr0_abs=fr0)
+    p = mg.Params(box_mpc_h=box, fr0_abs=fr0)
+    ur, hr, sr = O.solve_masked(rho, mask, m, u0, O.Opts(tol=1e-11, subtract_mean=True))
+    assert sr == 0
+    ud, hg, sg = mg.mg_fr_solve_masked(ctx, dev(rho), dev(mask, torch.float32), dev(u0), p,
+                                       mg.mgfr_default_opts(tol=1e-11, flags=mg.MGFR_SUBTRACT_MEAN))
+    assert sg == mg.MGFR_OK, ctx.last_error()
+    check(ur, hr, ud.cpu().numpy(), hg, mask, u0)
+    N = 8
+    rho8 = inputs.small_box(N, 2)
+    mask8 = np.where(np.random.default_rng(3).random((N, N, N)) < 0.5, 1.0, -1.0)
+    m8 = O.Model(box_mpc_h=16.0, fr0_abs=1e-5)
+    u8 = O.constants(m8, N)["ubar"] + 0.3 * inputs.gaussian_field(N, 1.0, -2.0, seed=5)
+    kw = dict(tol=1e-11, coarsest_n=8, coarsest_sweeps=400, max_cycles=40)
+    ur8, hr8, sr8 = O.solve_masked(rho8, mask8, m8, u8, O.Opts(**kw))
+    assert sr8 == 0, hr8
+    ud8, hg8, sg8 = mg.mg_fr_solve_masked(ctx, dev(rho8), dev(mask8, torch.float32), dev(u8),
+                                          mg.Params(box_mpc_h=16.0, fr0_abs=1e-5), mg.mgfr_default_opts(**kw))
+    assert sg8 == mg.MGFR_OK, ctx.last_error()
+    g8 = ud8.cpu().numpy()
+    assert np.array_equal(g8[mask8 <= 0], u8[mask8 <= 0])
+    assert np.abs(g8 - ur8).max() <= 1e-9
+
+
 def test_masked_errors(mg, ctx):
     say("[masked] errors")
     import torch

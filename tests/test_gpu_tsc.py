@@ -48,7 +48,7 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
 
 
-@pytest.mark.parametrize("Ng,N", [(16, 32), (32, 32), (64, 64), (64, 128)])
+@pytest.mark.parametrize("Ng,N", [(2, 4), (16, 32), (32, 32), (64, 64), (64, 128)])
 def test_density_and_force_match_oracle(mg, ctx, Ng, N):
     say(f"[tsc] {Ng}^3 particles on {N}^3")
     pos = inputs.particles(Ng, seed=Ng + N)
