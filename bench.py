@@ -44,6 +44,11 @@ MEASURED_TRAFFIC = {
         "sweep_fp64.hip": "8626f8c275f300f245261a3ce754af32586572b601a374203ca3eeb1fd8c8850",
         "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
         "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
+    # per sweep (both colour launches of the masked per-colour kernel)
+    "masked": {"bytes": 14.380e9, "sources": {
+        "masked.hip": "a817c4e9e94d53f0f705367b678670a6db06150245dd2edbe41fc098446a8bf3",
+        "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
+        "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
     "poisson": {"bytes": 4.020e9, "sources": {
         "poisson_kernels.hip": "9f8450a69b89060ccd64b388e3d917e830632923c46e8af95fe879c5e20f908d",
         "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
@@ -373,7 +378,9 @@ def bench_masked(args):
            "cycles": int(len(h) - 1), "final_residual": float(h[-1]),
            "time_includes": "the 1 GiB device copy that resets u before each solve",
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                        "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                        "traffic": measured_traffic("masked", N),
+                        "traffic_unit": "HBM bytes per sweep (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                         "kernel": "masked red-black sweep km_ngs_colour, both colours (finest level)",
                         "bytes_per_sweep": "4 N^3 (mask) + 24 per active cell (u read and write, density)",
                         "sweeps": sweeps, "avg_sweep_ms": s["sweep_ms"] / sweeps if sweeps else None}}
