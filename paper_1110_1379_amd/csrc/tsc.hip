@@ -119,58 +119,84 @@ __global__ void __launch_bounds__(kB) k_tsc_fill_start(unsigned* __restrict__ st
 }
 
 // Density of cell (i,j,k): the sum over the particles whose nearest cell is (i+a, j+b, k+c),
-// a, b, c in {-1, 0, 1}, of mass x their weight for offset (-a, -b, -c).
+// a, b, c in {-1, 0, 1}, of mass x their weight for offset (-a, -b, -c), neighbour rows in
+// the order (a, b) and within a row in key order.  A workgroup owns a segment of kB cells of
+// one row (the whole row when N < kB).  For each of the 9 neighbour rows it stages the
+// particles of the cells its segment touches (key and offsets, kCH at a time) in LDS, and
+// every thread sums its cell's share from there: each particle comes from L2 once per
+// workgroup instead of once per cell that needs it.  The wrapped cells of a row (k = -1 and
+// k = N) form ranges of their own, taken before and after the row's main range, so each
+// cell adds its particles in the order k-1, k, k+1.
+constexpr int kCH = 512;
+
 __global__ void __launch_bounds__(kB) k_tsc_density(const double* __restrict__ dsorted, const unsigned* __restrict__ key,
                                                     const unsigned* __restrict__ start, int N, int lg, double mass,
                                                     double* __restrict__ rho)
 {
-    const long long q = xcd_block() * kB + threadIdx.x;
-    if (q >= (1LL << (3 * lg))) return;
+    __shared__ unsigned sk[kCH];
+    __shared__ double sx[kCH], sy[kCH], sz[kCH];
     const int m = N - 1;
-    const int i = (int)(q >> (2 * lg)), j = (int)((q >> lg) & m), k = (int)(q & m);
+    const int S = N < kB ? N : kB;               // cells per segment
+    const int nseg = N / S;                      // segments per row
+    const long long wg = xcd_block();
+    const long long rowid = wg / nseg;           // (i, j)
+    const int k0 = (int)(wg % nseg) * S;
+    const int i = (int)(rowid >> lg), j = (int)(rowid & m);
+    const int tid = threadIdx.x;
+    const bool live = tid < S;
+    const int k = k0 + tid;
     double sum = 0.0;
-    for (int a = -1; a <= 1; ++a)
-        for (int b = -1; b <= 1; ++b) {
-            const unsigned row = ((unsigned)((i + a) & m) << (2 * lg)) | ((unsigned)((j + b) & m) << lg);
-            // the row's cells k-1, k, k+1: one range unless the row wraps
-            unsigned r0[3], r1[3];
-            int nr;
-            if (k >= 1 && k <= N - 2) {
-                r0[0] = start[row + k - 1];
-                r1[0] = start[row + k + 2];
-                nr = 1;
+    for (int ab = 0; ab < 9; ++ab) {
+        const int a = ab / 3 - 1, b = ab % 3 - 1;
+        const unsigned row = ((unsigned)((i + a) & m) << (2 * lg)) | ((unsigned)((j + b) & m) << lg);
+        // segments of particles: the wrapped cell N-1 (if k0 = 0), the cells
+        // max(k0-1, 0) .. min(k0+S, N-1), the wrapped cell 0 (if k0 + S = N)
+        for (int sg = 0; sg < 3; ++sg) {
+            unsigned g0, g1, t0 = 0, t1 = 0;
+            if (sg == 0) {
+                if (k0 != 0) continue;
+                g0 = start[row + N - 1];
+                g1 = start[row + N];
+                if (k == 0) {
+                    t0 = g0;
+                    t1 = g1;
+                }
+            } else if (sg == 1) {
+                g0 = start[row + (k0 > 0 ? k0 - 1 : 0)];
+                g1 = start[row + (k0 + S < N ? k0 + S + 1 : N)];
+                if (live) {
+                    t0 = start[row + (k > 0 ? k - 1 : 0)];
+                    t1 = start[row + (k + 2 < N ? k + 2 : N)];
+                }
             } else {
-                for (int c = 0; c < 3; ++c) {
-                    const unsigned cell = row + (unsigned)((k + c - 1) & m);
-                    r0[c] = start[cell];
-                    r1[c] = start[cell + 1];
+                if (k0 + S != N) continue;
+                g0 = start[row];
+                g1 = start[row + 1];
+                if (k == N - 1) {
+                    t0 = g0;
+                    t1 = g1;
                 }
-                nr = 3;
             }
-            auto term = [&](unsigned kk, double dx, double dy, double dz) {
-                const int oz = (k - (int)(kk & (unsigned)m) + 1) & m;  // 0, 1, 2 for offsets -1, 0, +1
-                return mass * tsc_w(dx, 1 - a) * tsc_w(dy, 1 - b) * tsc_w(dz, oz);
-            };
-            for (int r = 0; r < nr; ++r) {
-                unsigned t = r0[r];
-                // four particles' loads in flight at a time; the sum still runs in order
-                for (; t + 4 <= r1[r]; t += 4) {
-                    unsigned kk[4];
-                    double dd[12];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) kk[u] = key[t + u];
-#pragma unroll
-                    for (int u = 0; u < 12; ++u) dd[u] = dsorted[3 * (long long)t + u];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) sum = sum + term(kk[u], dd[3 * u], dd[3 * u + 1], dd[3 * u + 2]);
+            for (unsigned c0 = g0; c0 < g1; c0 += kCH) {
+                const unsigned c1 = c0 + kCH < g1 ? c0 + kCH : g1;
+                __syncthreads();
+                for (unsigned t = c0 + tid; t < c1; t += kB) {
+                    sk[t - c0] = key[t];
+                    sx[t - c0] = dsorted[3 * (long long)t];
+                    sy[t - c0] = dsorted[3 * (long long)t + 1];
+                    sz[t - c0] = dsorted[3 * (long long)t + 2];
                 }
-                for (; t < r1[r]; ++t) {
-                    const double* d = dsorted + 3 * (long long)t;
-                    sum = sum + term(key[t], d[0], d[1], d[2]);
+                __syncthreads();
+                const unsigned lo = t0 > c0 ? t0 : c0, hi = t1 < c1 ? t1 : c1;
+                for (unsigned t = lo; t < hi; ++t) {
+                    const unsigned l = t - c0;
+                    const int oz = (k - (int)(sk[l] & (unsigned)m) + 1) & m;  // 0, 1, 2 for offsets -1, 0, +1
+                    sum = sum + mass * tsc_w(sx[l], 1 - a) * tsc_w(sy[l], 1 - b) * tsc_w(sz[l], oz);
                 }
             }
         }
-    rho[q] = sum;
+    }
+    if (live) rho[((long long)rowid << lg) + k] = sum;
 }
 
 // acc = sum over the 27 cells of weight x (-grad phi), -grad phi by central differences.
@@ -296,8 +322,9 @@ int mgfr_tsc_density(mgfr_ctx* c, const double* pos, long long np, int N, double
         hipLaunchKernelGGL(mgfr::k_tsc_fill_start, dim3(mgfr::blocks(ncell + 1)), dim3(mgfr::kB), 0, s, start, ncell + 1);
         MGFR_TRY(hip_check(c, hipGetLastError(), "k_tsc_fill_start"));
     }
-    hipLaunchKernelGGL(mgfr::k_tsc_density, dim3(mgfr::blocks(ncell)), dim3(mgfr::kB), 0, s, sorted, key2, start, N, lg,
-                       mass, rho);
+    const long long segs = (long long)N * N * (N < mgfr::kB ? 1 : N / mgfr::kB);
+    hipLaunchKernelGGL(mgfr::k_tsc_density, dim3((unsigned)segs), dim3(mgfr::kB), 0, s, sorted, key2, start, N, lg, mass,
+                       rho);
     MGFR_TRY(hip_check(c, hipGetLastError(), "k_tsc_density"));
     return MGFR_OK;
 }
