@@ -472,8 +472,11 @@ def bench_tsc(args):
            "assignment_ms": d_ms, "interpolation_ms": f_ms,
            "roofline": {"bound": "hbm", "achieved": dep_bytes / (d_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": dep_bytes / (d_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "k_tsc_deposit (27 hardware FP64 atomics per particle) with its clear and check",
+                        "kernel": "one TSC assignment call: coordinate check, keys, radix sort, gather of offsets, "
+                                  "cell table, cell sums (k_tsc_density, about 3/4 of the call)",
                         "bytes": "24 per particle + 16 per cell",
+                        "traffic_note": "per-kernel FETCH/WRITE bytes of the call are listed in the TSC profile "
+                                        "summary; the sort's are not counted, so no total is given",
                         "interpolation": {"achieved": frc_bytes / (f_ms * 1e-3) / 1e9,
                                           "frac": frc_bytes / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                           "bytes": "48 per particle + 8 per cell"}}}
