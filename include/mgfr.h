@@ -74,7 +74,8 @@ typedef struct mgfr_opts {
     double tau_alpha;     /* > 0: also stop once rms(L) <= tau_alpha x rms(tau), tau the
                              truncation-error estimate of the current field (Sec. V.B;
                              the stop test is rms(L) <= max(tol, tau_alpha rms(tau)));
-                             domain solves only                                    [0]      */
+                             mg_fr_solve only: the batched and masked solves reject it
+                             with MGFR_EINVAL                                      [0]      */
 } mgfr_opts;
 
 /* One refinement patch: a cube of n^3 cells at refinement level `level` >= 1 (cell size
@@ -162,8 +163,9 @@ int mgfr_smooth(mgfr_ctx* ctx, const double* rho, double* u, int N, const mgfr_p
  * res_hist host, max_cycles + 1 doubles (may be NULL): rms(L) before the first cycle and
  *          after every cycle (mixed: after every FP64 outer iteration).
  * n_hist   host (may be NULL): number of entries written to res_hist.
- * Returns MGFR_OK when rms(L) <= tol, MGFR_ENOTCONV when max_cycles was reached first
- * (u holds the last iterate).  Synchronises the stream. */
+ * Returns MGFR_OK when rms(L) <= tol (or, with opts->tau_alpha > 0, when rms(L) <=
+ * tau_alpha x rms(tau), rms(tau) then reported in the stats), MGFR_ENOTCONV when max_cycles
+ * was reached first (u holds the last iterate).  Synchronises the stream. */
 int mg_fr_solve(mgfr_ctx* ctx, const double* rho, int N, const mgfr_params* params,
                 const mgfr_opts* opts, double* u, double* res_hist, int* n_hist, void* stream);
 

@@ -551,6 +551,7 @@ int check_batch_opts(mgfr_ctx* c, const mgfr_opts* o)
 {
     MGFR_TRY(check_opts(c, o));
     if (o->flags & MGFR_SUBTRACT_MEAN) return c->fail(MGFR_EINVAL, "MGFR_SUBTRACT_MEAN is not available for batches");
+    if (o->tau_alpha > 0.0) return c->fail(MGFR_EINVAL, "tau_alpha is not available for batches");
     return MGFR_OK;
 }
 

@@ -90,6 +90,10 @@ def test_patch_layout_errors(mg, ctx):
     # no patches: nothing to do
     _, _, st = mg.mg_fr_solve_patches(ctx, ud, [], rho, params, raise_on_error=False)
     assert st == mg.MGFR_OK
+    # the truncation-error stop rule belongs to the domain solve
+    _, _, st = mg.mg_fr_solve_patches(ctx, ud, [good], rho, params, mg.mgfr_default_opts(tau_alpha=0.3),
+                                      raise_on_error=False)
+    assert st == mg.MGFR_EINVAL
 
 
 def test_batch_of_boxes_matches_oracle(mg, ctx):
