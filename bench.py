@@ -568,6 +568,22 @@ def bench_amr(args):
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
         out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])
+    if not args.no_cpu_baseline:
+        import oracle
+        Ns = 128
+        log(f"timing the CPU oracle on the patches of a {Ns}^3 domain of the same recipe")
+        r0, ps, rps = inputs.amr_workload(Ns)
+        m = oracle.Model(box_mpc_h=box * Ns / N0, fr0_abs=fr0)
+        u0, _, st0 = oracle.solve(r0, m, oracle.Opts(tol=args.tol))  # the parent solution, untimed
+        rl = [rps[p["offset"]:p["offset"] + p["n"] ** 3].reshape((p["n"],) * 3) for p in ps]
+        t0 = time.perf_counter()
+        _, _, sts = oracle.solve_patches(u0, ps, rl, m, oracle.Opts(tol=args.tol))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": oracle.last_patch_updates / dt, "unit": "cell-updates/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the {len(ps)} patches ({sum(p['n'] ** 3 for p in ps)} cells) of a {Ns}^3 "
+                                         f"domain of the same recipe and cell size, FP64, one after another to rms "
+                                         f"{args.tol:g}: {dt:.1f} s, statuses {sorted(set(sts))}"}
     return out
 
 
@@ -614,6 +630,26 @@ def bench_batch(args):
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
         out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = [b for b in boxes if b[0] == 64][:4] + [b for b in boxes if b[0] == 128][:1]
+        log("timing the CPU oracle on four 64^3 boxes and one 128^3 box")
+        ups, tsum, per = 0, 0.0, {64: [], 128: []}
+        for N, B, fr0, _, _, rho in sample:
+            t0 = time.perf_counter()
+            oracle.solve(rho, oracle.Model(box_mpc_h=B, fr0_abs=fr0), oracle.Opts(tol=args.tol))
+            dt = time.perf_counter() - t0
+            tsum += dt
+            ups += oracle.last_cell_updates()
+            per[N].append(dt)
+        t64, t128 = sum(per[64]) / len(per[64]), sum(per[128]) / len(per[128])
+        n64 = sum(1 for b in boxes if b[0] == 64)
+        n128 = len(boxes) - n64
+        out["cpu_baseline"] = {"value": len(boxes) / (n64 * t64 + n128 * t128), "unit": "boxes/s", "cores": 1,
+                               "kind": "oracle", "cell_updates_per_s": ups / tsum,
+                               "sample": f"four 64^3 boxes ({t64:.2f} s each on average) and one 128^3 box "
+                                         f"({t128:.1f} s), FP64, to rms {args.tol:g}; boxes/s of the batch's mix "
+                                         f"({n64} + {n128}) from those per-box times"}
     return out
 
 
