@@ -512,6 +512,23 @@ def _precisions(mgfr, args):
     return [(n, mgfr.MGFR_MIXED if n == "mixed" else mgfr.MGFR_FP64) for n in names]
 
 
+def _batched_roofline(s, prec_name):
+    """Roofline object of the batched smoother from the statistics of a solve run eagerly with
+    MGFR_PROFILE: HIP events around every sweep of the finest level of every unit (the two
+    colour launches of kb_ngs / kb32_ngs), algorithmic bytes of the active units swept."""
+    launches = s["sweep_launches"]
+    achieved = s["sweep_bytes"] / (s["sweep_ms"] * 1e-3) / 1e9 if s["sweep_ms"] > 0 else None
+    fp64 = prec_name == "fp64"
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+            "kernel": ("kb_ngs" if fp64 else "kb32_ngs") + " (red-black Newton-Gauss-Seidel, one launch per "
+                      "colour over the finest level of every unit)",
+            "bytes_per_cell": 24 if fp64 else 16, "launches": launches,
+            "avg_launch_ms": s["sweep_ms"] / launches if launches else None,
+            "timing": "one more solve of the same problem after the timed steps, launched eagerly (no graph) "
+                      "with HIP events around every finest-level sweep on the solve's stream"}
+
+
 def _field_error(a, b):
     d = (a - b).abs()
     ref = b.abs().max().item()
@@ -535,7 +552,7 @@ def bench_amr(args):
     ud, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100))
     assert st == mgfr.MGFR_OK, ctx.last_error()
     rp = torch.from_numpy(rho_packed).to("cuda:0")
-    runs, fields = {}, {}
+    runs, fields, profiled = {}, {}, {}
     for name, code in _precisions(mgfr, args):
         opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code,
                                       flags=0 if args.no_graph else mgfr.MGFR_GRAPH)
@@ -548,6 +565,13 @@ def bench_amr(args):
             return hists
         ms, hists = _timed(solve, args.steps, args.warmup)
         s = mgfr.mgfr_get_stats(ctx)
+
+        def solve_profiled(code=code):
+            po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=mgfr.MGFR_PROFILE)
+            _, _, st = mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, po, u_packed=torch.empty_like(rp))
+            assert st == mgfr.MGFR_OK, ctx.last_error()
+            return mgfr.mgfr_get_stats(ctx)
+        profiled[name] = solve_profiled
         runs[name] = {"ms_per_step": ms, "value": s["cell_updates"] / (ms * 1e-3),
                       "max_cycles_per_patch": int(max(len(h) for h in hists) - 1),
                       "max_final_residual": float(max(h[-1] for h in hists))}
@@ -565,6 +589,7 @@ def bench_amr(args):
                                   f"(contrast > 50/200/1000), {cells} patch cells, tol {args.tol:g}",
                       "precision": headp, "graph": not args.no_graph}}
     out.update(runs)
+    out["roofline"] = _batched_roofline(profiled[headp](), headp)
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
         out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])
@@ -597,7 +622,7 @@ def bench_batch(args):
     rhos = [torch.from_numpy(b[5]).to("cuda:0") for b in boxes]
     params = [mgfr.Params(box_mpc_h=b[1], fr0_abs=b[2]) for b in boxes]
     ctx = mgfr.Context(0)
-    runs, fields = {}, {}
+    runs, fields, profiled = {}, {}, {}
     for name, code in _precisions(mgfr, args):
         opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code,
                                       flags=0 if args.no_graph else mgfr.MGFR_GRAPH)
@@ -610,6 +635,13 @@ def bench_batch(args):
             return hists
         ms, hists = _timed(solve, args.steps, args.warmup)
         s = mgfr.mgfr_get_stats(ctx)
+
+        def solve_profiled(code=code):
+            po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=mgfr.MGFR_PROFILE)
+            _, _, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, po, us=[torch.empty_like(r) for r in rhos])
+            assert st == mgfr.MGFR_OK, ctx.last_error()
+            return mgfr.mgfr_get_stats(ctx)
+        profiled[name] = solve_profiled
         runs[name] = {"ms_per_step": ms, "value": len(boxes) / (ms * 1e-3),
                       "cell_updates_per_s": s["cell_updates"] / (ms * 1e-3),
                       "max_cycles_per_box": int(max(len(h) for h in hists) - 1),
@@ -627,6 +659,7 @@ def bench_batch(args):
                                   f"[1e-6,1e-4], lognormal sigma U[1,3], tol {args.tol:g}",
                       "precision": headp, "graph": not args.no_graph}}
     out.update(runs)
+    out["roofline"] = _batched_roofline(profiled[headp](), headp)
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
         out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])

@@ -46,7 +46,9 @@ extern "C" {
 /* opts.flags */
 #define MGFR_SUBTRACT_MEAN 1 /* density contrast rho~ - mean(rho~) instead of rho~ - 1       */
 #define MGFR_WARM_START 2    /* start from the u passed in instead of the background u      */
-#define MGFR_PROFILE 4       /* time every finest-level smoother launch with HIP events      */
+#define MGFR_PROFILE 4       /* time every finest-level smoother launch with HIP events
+                                (batched solves: every sweep of the finest level of every
+                                unit, both colour launches, when MGFR_GRAPH is not set)      */
 #define MGFR_GRAPH 8         /* batched solves: capture one cycle's launches in a HIP graph
                                 on first use and replay it for every later cycle of the call */
 

@@ -304,8 +304,6 @@ struct Batch {
         return hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize");
     }
 
-    // Cell updates of one V-cycle of the active units (pre + post sweeps on every level
-    // above the coarsest), added to the statistics per cycle run.
     // Copies the host active flags to the device (through pinned memory, so the copy is a
     // direct transfer; the staging area is next rewritten after a later synchronisation).
     int upload_active()
@@ -315,6 +313,8 @@ struct Batch {
                          "hipMemcpyAsync");
     }
 
+    // Cell updates of one V-cycle of the active units (pre + post sweeps on every level
+    // above the coarsest), added to the statistics per cycle run.
     void count_vcycle(int times)
     {
         for (size_t i = 0; i < units.size(); ++i) {
@@ -327,9 +327,50 @@ struct Batch {
         }
     }
 
-    int sweep(const Depth& D)
+    // MGFR_PROFILE, eager cycles only: HIP events around every sweep of the finest depth (the
+    // finest level of every unit), with the algorithmic bytes of its active units.
+    long long act0 = 0;  // cells of the finest levels of the active units, this cycle
+    bool profiled(int m) const { return m == 0 && (o->flags & MGFR_PROFILE) && !(o->flags & MGFR_GRAPH); }
+    int ev_begin(int m)
     {
-        return hip_check(c, mgfr::batch_ngs(tab(D.half_f), D.half_f.nblk, s), "batch_ngs");
+        if (!profiled(m)) return MGFR_OK;
+        if ((size_t)c->ev_used + 2 > c->ev.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t ev;
+                MGFR_TRY(hip_check(c, hipEventCreate(&ev), "hipEventCreate"));
+                c->ev.push_back(ev);
+            }
+        }
+        return hip_check(c, hipEventRecord(c->ev[c->ev_used], s), "hipEventRecord");
+    }
+    int ev_end(int m, double bytes_per_cell)
+    {
+        if (!profiled(m)) return MGFR_OK;
+        MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
+        c->ev_used += 2;
+        c->stats.sweep_launches += 2;  // one launch per colour
+        c->stats.sweep_bytes += bytes_per_cell * (double)act0;
+        return MGFR_OK;
+    }
+    // Sums the timed intervals (the stream has been synchronised) and releases the events.
+    int harvest()
+    {
+        for (int k = 0; k < c->ev_used; k += 2) {
+            float ms = 0.0f;
+            MGFR_TRY(hip_check(c, hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]), "hipEventElapsedTime"));
+            c->stats.sweep_ms += ms;
+        }
+        c->ev_used = 0;
+        return MGFR_OK;
+    }
+
+    // read u and rho, write u
+    int sweep(int m)
+    {
+        const Depth& D = plan.depth[m];
+        MGFR_TRY(ev_begin(m));
+        MGFR_TRY(hip_check(c, mgfr::batch_ngs(tab(D.half_f), D.half_f.nblk, s), "batch_ngs"));
+        return ev_end(m, 24.0);
     }
 
     int vcycle(int m)
@@ -340,7 +381,7 @@ struct Batch {
                                                        o->coarsest_rtol, s),
                                "batch_coarsest"));
         if (!D.deep) return MGFR_OK;
-        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(D));
+        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m));
         MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict(tab(D.coarse_f), D.coarse_f.nblk,
                                                          (const mgfr::BGrid*)(dmeta + D.coarse_f.other), s),
                            "batch_resid_restrict"));
@@ -350,14 +391,18 @@ struct Batch {
         MGFR_TRY(hip_check(c, mgfr::batch_prolong_add(tab(D.fine_f), D.fine_f.nblk,
                                                       (const mgfr::BGrid*)(dmeta + D.fine_f.other), s),
                            "batch_prolong_add"));
-        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep(D));
+        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep(m));
         return MGFR_OK;
     }
 
     // ---- mixed precision: single-precision correction V-cycle, double-precision outer loop
-    int sweep32(const Depth& D)
+    // read ub, e and the right-hand side, write e
+    int sweep32(int m)
     {
-        return hip_check(c, mgfr::batch_ngs32(tab(D.half_f), D.half_f.nblk, s), "batch_ngs32");
+        const Depth& D = plan.depth[m];
+        MGFR_TRY(ev_begin(m));
+        MGFR_TRY(hip_check(c, mgfr::batch_ngs32(tab(D.half_f), D.half_f.nblk, s), "batch_ngs32"));
+        return ev_end(m, 16.0);
     }
 
     int vcycle32(int m)
@@ -369,7 +414,7 @@ struct Batch {
                                "batch_coarsest32"));
         if (!D.deep) return MGFR_OK;
         const mgfr::BGrid* coarse = (const mgfr::BGrid*)(dmeta + D.coarse_f.other);
-        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep32(D));
+        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep32(m));
         MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict32(tab(D.coarse_f), D.coarse_f.nblk, coarse, s),
                            "batch_resid_restrict32"));
         MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs32(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs32"));
@@ -378,7 +423,7 @@ struct Batch {
         MGFR_TRY(hip_check(c, mgfr::batch_prolong_add32(tab(D.fine_f), D.fine_f.nblk,
                                                         (const mgfr::BGrid*)(dmeta + D.fine_f.other), s),
                            "batch_prolong_add32"));
-        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep32(D));
+        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep32(m));
         return MGFR_OK;
     }
 
@@ -520,6 +565,9 @@ struct Batch {
             for (size_t i = 0; i < units.size(); ++i) any = any || active[i];
             if (!any || cycles >= o->max_cycles) break;
             MGFR_TRY(upload_active());
+            act0 = 0;
+            for (size_t i = 0; i < units.size(); ++i)
+                if (active[i] && units[i].nlev > 1) act0 += cells3(units[i].g[0]);  // swept at depth 0
             MGFR_TRY(cycle());
             count_vcycle(mixed ? o->inner_cycles : 1);
             if (mixed) {
@@ -528,6 +576,7 @@ struct Batch {
             } else {
                 MGFR_TRY(norms(rms, mx));
             }
+            MGFR_TRY(harvest());  // the norms synchronised the stream
             ++cycles;
             for (size_t i = 0; i < units.size(); ++i) {
                 if (!active[i]) continue;

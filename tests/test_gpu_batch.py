@@ -186,16 +186,19 @@ def test_graph_replays_match_eager(mg, ctx, precision):
     rhos = [dev(s[3]) for s in specs]
     params = [mg.Params(box_mpc_h=s[1], fr0_abs=s[2]) for s in specs]
     out = {}
-    for flags in (0, mg.MGFR_GRAPH):
+    for flags in (0, mg.MGFR_GRAPH, mg.MGFR_PROFILE):
         opts = mg.mgfr_default_opts(tol=tol, precision=prec, flags=flags)
         us, hists, st = mg.mg_fr_solve_batch(ctx, rhos, params, opts)
         assert st == mg.MGFR_OK, ctx.last_error()
         out[flags] = ([u.cpu().numpy() for u in us], [np.asarray(h) for h in hists])
+        if flags == mg.MGFR_PROFILE:
+            check_profile(mg, ctx, opts)
     assert max(len(h) for h in out[0][1]) >= 4          # several replays
-    for a, b in zip(out[0][0], out[mg.MGFR_GRAPH][0]):
-        assert np.array_equal(a, b)
-    for a, b in zip(out[0][1], out[mg.MGFR_GRAPH][1]):
-        assert np.array_equal(a, b)
+    for f in (mg.MGFR_GRAPH, mg.MGFR_PROFILE):
+        for a, b in zip(out[0][0], out[f][0]):
+            assert np.array_equal(a, b)
+        for a, b in zip(out[0][1], out[f][1]):
+            assert np.array_equal(a, b)
     # patches (ghost faces, units of several depths) under a graph
     N0 = 32
     rho0, patches, rho_packed = inputs.amr_workload(N0, seed=3, thresholds=(3.0, 8.0), sizes=(8, 4))
@@ -203,11 +206,28 @@ def test_graph_replays_match_eager(mg, ctx, precision):
     ud, _, st = mg.mg_fr_solve(ctx, dev(rho0), p, mg.mgfr_default_opts(tol=1e-12))
     assert st == mg.MGFR_OK
     res = {}
-    for flags in (0, mg.MGFR_GRAPH):
+    for flags in (0, mg.MGFR_GRAPH, mg.MGFR_PROFILE):
         opts = mg.mgfr_default_opts(tol=tol, precision=prec, flags=flags)
         up, hists, st = mg.mg_fr_solve_patches(ctx, ud, patches, dev(rho_packed), p, opts)
         assert st == mg.MGFR_OK, ctx.last_error()
         res[flags] = (up.cpu().numpy(), [np.asarray(h) for h in hists])
-    assert np.array_equal(res[0][0], res[mg.MGFR_GRAPH][0])
-    for a, b in zip(res[0][1], res[mg.MGFR_GRAPH][1]):
-        assert np.array_equal(a, b)
+        if flags == mg.MGFR_PROFILE:
+            check_profile(mg, ctx, opts)
+    for f in (mg.MGFR_GRAPH, mg.MGFR_PROFILE):
+        assert np.array_equal(res[0][0], res[f][0])
+        for a, b in zip(res[0][1], res[f][1]):
+            assert np.array_equal(a, b)
+
+
+def check_profile(mg, ctx, opts):
+    """MGFR_PROFILE on a batched solve: both colour launches of every finest-level sweep are
+    timed (every V-cycle of a run whose units have more than one level), and the bytes
+    credited are 24 (FP64) or 16 (single-precision correction) per finest-level cell update of
+    the active units."""
+    s = mg.mgfr_get_stats(ctx)
+    mixed = opts.precision == mg.MGFR_MIXED
+    vcycles = s["inner_cycles"] if mixed else s["cycles"]
+    per = 2 * (opts.pre + opts.post)
+    assert 0 < s["sweep_launches"] <= per * vcycles and s["sweep_launches"] % per == 0, s
+    assert s["sweep_ms"] > 0.0
+    assert s["sweep_bytes"] == (16 if mixed else 24) * s["finest_updates"], s
