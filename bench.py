@@ -36,9 +36,9 @@ METRIC = "f(R) MG time-to-residual 1e-8 & cell-updates/s, 512^3, FP64 vs mixed"
 # by-value kernel types): when any of them differs the figure no longer describes the kernel
 # that runs and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "mixed": {"bytes": 2.782e9, "sources": {
-        "kernels_fp32.hip": "d94c636fbf7cea404db182a5e9c93cb71f343adcb6c84d301b00ab6941af2905",
-        "device_fp32.h": "8e0b1788cfffc170c22c27c14ed38910f5eb958ebe543a31c498e8e0de7d38e0",
+    "mixed": {"bytes": 2.699e9, "sources": {
+        "kernels_fp32.hip": "9f678b380311577e8d67d9cbe38a8decc8747afb0ab3ff0d6f549fddbfa525fe",
+        "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
         "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
     "fp64": {"bytes": 3.428e9, "sources": {
         "sweep_fp64.hip": "8626f8c275f300f245261a3ce754af32586572b601a374203ca3eeb1fd8c8850",

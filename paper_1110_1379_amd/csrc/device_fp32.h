@@ -29,12 +29,13 @@ __device__ __forceinline__ Op32 op32(const BGrid& g)
     return Op32{(float)g.C, (float)g.A, (float)g.inv_np1, (float)g.max_step};
 }
 
-// expm1 in single precision: Taylor series to x^6 for |x| < 1/8 (truncation < 1e-10
-// relative), exp(x) - 1 above.  Corrections are small once the outer loop has started to
-// converge, so the exponential is a branch that whole wavefronts skip.
+// expm1 in single precision: Taylor series to x^5 for |x| < 1/8 (the first omitted term,
+// x^6/720, is below 4.3e-8 of x: under half the single-precision spacing), exp(x) - 1
+// above.  Corrections are small once the outer loop has started to converge, so the
+// exponential is a branch that whole wavefronts skip.
 __device__ __forceinline__ float em1f(float x)
 {
-    float r = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f + x * (1.0f / 720.0f))))));
+    float r = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f)))));
     if (__builtin_expect(!(fabsf(x) < 0.125f), 0)) r = __expf(x) - 1.0f;
     return r;
 }
@@ -53,6 +54,19 @@ __device__ __forceinline__ V32 make_v(float ub, float e)
     v.M = b * em1f(e);
     v.B = b + v.M;
     return v;
+}
+
+// The same values after the correction changed to e: b = B - M recovers exp(ub) without a
+// second exponential (to the rounding of B).
+__device__ __forceinline__ V32 remake_v(const V32& v, float e)
+{
+    V32 r;
+    r.ub = v.ub;
+    r.e = e;
+    const float b = v.B - v.M;
+    r.M = b * em1f(e);
+    r.B = b + r.M;
+    return r;
 }
 
 struct Res32 {

@@ -76,12 +76,12 @@ struct Col32 {
     int c, fl;                // LDS cell; 1 loaded, 2 red range (tile + ring), 4 tile
 };
 
-template <int TJ, int NT>
+template <int TJ, int TK, int NT>
 __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict__ ub, const float* __restrict__ ein,
                                                 float* __restrict__ eout, const float* __restrict__ f,
                                                 FusedSweep32 a)
 {
-    constexpr int LJ = TJ + 4, LK = kTK + 4, NL = LJ * LK, NP = NL / 2;
+    constexpr int LJ = TJ + 4, LK = TK + 4, NL = LJ * LK, NP = NL / 2;
     static_assert(NP <= NT, "one column pair per thread");
     __shared__ V32 lv[3][NL];
     const Op32 o = op32(g);
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict_
     lid /= a.ntk;
     const int tj = lid % a.ntj;
     const int ci = lid / a.ntj;
-    const int i0 = ci * a.ti, j0 = tj * TJ, k0 = tk * kTK;
+    const int i0 = ci * a.ti, j0 = tj * TJ, k0 = tk * TK;
     const int lg = g.lg, m = g.n - 1;
     const int last = i0 + a.ti + 1;  // last plane read
 
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict_
             const int c = A.c;
             const V32 nbv[6] = {A.v[M1], A.v[P1], LA[c - LK], LA[c + LK], LA[c - 1], LA[c + 1]};
             const Res32 r = dev32::corr_op(o, A.v[P0], nbv, A.f[P0]);
-            A.v[P0] = make_v(A.v[P0].ub, A.v[P0].e + newton32(r, o.max_step));
+            A.v[P0] = dev32::remake_v(A.v[P0], A.v[P0].e + newton32(r, o.max_step));
             LA[c] = A.v[P0];
         }
         if (p - 1 >= i0) {
@@ -487,13 +487,17 @@ hipError_t ngs_sweep32_fused(const Grid& g, const float* ub, const float* ein, f
 {
     if (g.n < kTK || g.n > 1024 || ein == eout || ti < 4 || (ti & 3) || ti > g.n || (g.n % ti) != 0)
         return hipErrorInvalidValue;
-    constexpr int TJ = 8, NT = 448;  // 408 column pairs per 12 x 68 tile
+    // 216 column pairs per 12 x 36 tile.  With 90 VGPRs a SIMD holds 5 wavefronts, so five
+    // 4-wavefront workgroups share a CU: narrower tiles re-read more halo than 8 x 64 tiles
+    // of 7 wavefronts, but the extra resident waves hide more of the per-plane barrier and
+    // load latency (0.90 against 0.95 ms per 512^3 sweep).
+    constexpr int TJ = 8, TK = 32, NT = 256;
     FusedSweep32 a{};
     a.ti = ti;
     a.ntj = g.n / TJ;
-    a.ntk = g.n / kTK;
+    a.ntk = g.n / TK;
     const unsigned nb = (unsigned)((g.n / ti) * a.ntj * a.ntk);
-    hipLaunchKernelGGL((k32_fused<TJ, NT>), dim3(nb), dim3(NT), 0, s, g, ub, ein, eout, f, a);
+    hipLaunchKernelGGL((k32_fused<TJ, TK, NT>), dim3(nb), dim3(NT), 0, s, g, ub, ein, eout, f, a);
     return hipGetLastError();
 }
 
