@@ -246,15 +246,22 @@ inline mgfr::Grid make_grid(const Model& md, int n, double h, double max_step)
 
 inline int ensure_scratch(mgfr_ctx* c)
 {
-    if (!c->partial) {
-        if (hipMalloc(&c->partial, sizeof(double) * mgfr::reduction_scratch()) != hipSuccess)
-            return c->fail(MGFR_ENOMEM, "hipMalloc of reduction scratch failed");
-        if (hipMalloc(&c->red, sizeof(double) * 2) != hipSuccess)
-            return c->fail(MGFR_ENOMEM, "hipMalloc of reduction result failed");
-        if (hipHostMalloc(&c->host_red, sizeof(double) * 2, hipHostMallocDefault) != hipSuccess)
-            return c->fail(MGFR_ENOMEM, "hipHostMalloc failed");
-        if (hipMalloc(&c->counter, sizeof(long long)) != hipSuccess)
-            return c->fail(MGFR_ENOMEM, "hipMalloc of the sweep counter failed");
+    // each buffer on its own, so that a call after a failed one completes the set
+    if (!c->partial && hipMalloc(&c->partial, sizeof(double) * mgfr::reduction_scratch()) != hipSuccess) {
+        c->partial = nullptr;
+        return c->fail(MGFR_ENOMEM, "hipMalloc of reduction scratch failed");
+    }
+    if (!c->red && hipMalloc(&c->red, sizeof(double) * 2) != hipSuccess) {
+        c->red = nullptr;
+        return c->fail(MGFR_ENOMEM, "hipMalloc of reduction result failed");
+    }
+    if (!c->host_red && hipHostMalloc(&c->host_red, sizeof(double) * 2, hipHostMallocDefault) != hipSuccess) {
+        c->host_red = nullptr;
+        return c->fail(MGFR_ENOMEM, "hipHostMalloc failed");
+    }
+    if (!c->counter && hipMalloc(&c->counter, sizeof(long long)) != hipSuccess) {
+        c->counter = nullptr;
+        return c->fail(MGFR_ENOMEM, "hipMalloc of the sweep counter failed");
     }
     return MGFR_OK;
 }
