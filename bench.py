@@ -555,7 +555,7 @@ def bench_amr(args):
     runs, fields, profiled = {}, {}, {}
     for name, code in _precisions(mgfr, args):
         opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code,
-                                      flags=0 if args.no_graph else mgfr.MGFR_GRAPH)
+                                      flags=mgfr.MGFR_GRAPH if args.graph else 0)
         up = torch.empty_like(rp)
 
         def solve():
@@ -587,7 +587,7 @@ def bench_amr(args):
            "config": {"workload": f"amr: {N0}^3 domain (lognormal sigma 2), {len(patches)} cube patches "
                                   f"8^3-64^3 over {max(p['level'] for p in patches)} levels "
                                   f"(contrast > 50/200/1000), {cells} patch cells, tol {args.tol:g}",
-                      "precision": headp, "graph": not args.no_graph}}
+                      "precision": headp, "graph": bool(args.graph)}}
     out.update(runs)
     out["roofline"] = _batched_roofline(profiled[headp](), headp)
     if len(runs) == 2:
@@ -625,7 +625,7 @@ def bench_batch(args):
     runs, fields, profiled = {}, {}, {}
     for name, code in _precisions(mgfr, args):
         opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code,
-                                      flags=0 if args.no_graph else mgfr.MGFR_GRAPH)
+                                      flags=mgfr.MGFR_GRAPH if args.graph else 0)
         us = [torch.empty_like(r) for r in rhos]
 
         def solve():
@@ -657,7 +657,7 @@ def bench_batch(args):
            "data": "synthetic",
            "config": {"workload": "batch: 64 x 64^3 (B=64) + 16 x 128^3 (B=128), |f_R0| log-uniform "
                                   f"[1e-6,1e-4], lognormal sigma U[1,3], tol {args.tol:g}",
-                      "precision": headp, "graph": not args.no_graph}}
+                      "precision": headp, "graph": bool(args.graph)}}
     out.update(runs)
     out["roofline"] = _batched_roofline(profiled[headp](), headp)
     if len(runs) == 2:
@@ -700,8 +700,10 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of autotuned settings: reused when it holds this problem, else "
                          "written after tuning (so that profiled runs time the same settings)")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="amr/batch: launch every cycle eagerly instead of replaying a HIP graph")
+    ap.add_argument("--graph", action="store_true",
+                    help="amr/batch: capture one cycle's launches in a HIP graph and replay it (the default "
+                         "launches every cycle eagerly, which measured as fast or faster)")
+    ap.add_argument("--no-graph", action="store_true", help="amr/batch: eager launches (the default)")
     ap.add_argument("--no-stop-rule", action="store_true",
                     help="domain workloads: skip the truncation-error stop-rule comparison")
     ap.add_argument("--copy-probe", action="store_true",
