@@ -12,7 +12,9 @@ smoother launches of the timed solves, on the solve's stream) and the CPU oracle
 bounded sample of the same workload.
 
 Other workloads: --workload tophat256 | small32 (same line, other grid), amr (domain grid
-plus refinement patches over 3 levels), batch (64 boxes of 64^3 + 16 of 128^3).
+plus refinement patches over 3 levels), batch (64 boxes of 64^3 + 16 of 128^3), poisson512
+(the modified Poisson solve of the same 512^3 density), masked512 (a 512^3 refinement level
+of oct-mask shape), tsc512 (TSC assignment and force interpolation of 512^3 particles).
 """
 from __future__ import annotations
 

@@ -1,0 +1,52 @@
+"""Host logic of bench.py that runs without a GPU: the one-GPU guard, the source-hash guard
+on the measured HBM traffic, and the roofline arithmetic of the batched smoother."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
+    # the committed figures describe the committed sources
+    for prec in ("mixed", "fp64", "masked", "poisson"):
+        assert bench.measured_traffic(prec, 512) == bench.MEASURED_TRAFFIC[prec]["bytes"]
+        assert bench.measured_traffic(prec, 256) is None
+    assert bench.measured_traffic("tsc", 512) is None
+    # a changed source voids the figure of every kernel built from it, and only those
+    csrc = tmp_path / "paper_1110_1379_amd" / "csrc"
+    shutil.copytree(os.path.join(ROOT, "paper_1110_1379_amd", "csrc"), csrc)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("mixed", 512) is not None
+    with open(csrc / "device_fp32.h", "a") as fh:
+        fh.write("\n// edited\n")
+    assert bench.measured_traffic("mixed", 512) is None
+    assert bench.measured_traffic("fp64", 512) is not None
+    with open(csrc / "kernel_types.h", "a") as fh:
+        fh.write("\n// edited\n")
+    assert all(bench.measured_traffic(p, 512) is None for p in ("fp64", "masked", "poisson"))
+
+
+@pytest.mark.parametrize("prec,bpc", [("fp64", 24), ("mixed", 16)])
+def test_batched_roofline(prec, bpc):
+    s = {"sweep_launches": 8, "sweep_ms": 2.0, "sweep_bytes": 4.0e9}
+    r = bench._batched_roofline(s, prec)
+    assert r["achieved"] == pytest.approx(2000.0)  # 4 GB in 2 ms
+    assert r["frac"] == pytest.approx(2000.0 / bench.HBM_PEAK_GBS)
+    assert r["avg_launch_ms"] == pytest.approx(0.25)
+    assert r["bytes_per_cell"] == bpc and r["bound"] == "hbm" and r["traffic"] is None
+    empty = bench._batched_roofline({"sweep_launches": 0, "sweep_ms": 0.0, "sweep_bytes": 0.0}, prec)
+    assert empty["achieved"] is None and empty["frac"] is None and empty["avg_launch_ms"] is None
