@@ -475,7 +475,7 @@ def bench_tsc(args):
            "roofline": {"bound": "hbm", "achieved": dep_bytes / (d_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": dep_bytes / (d_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                         "kernel": "one TSC assignment call: coordinate check, keys, radix sort, gather of offsets, "
-                                  "cell table, cell sums (k_tsc_density, about 3/4 of the call)",
+                                  "cell table, cell sums (k_tsc_density, about 2/3 of the call)",
                         "bytes": "24 per particle + 16 per cell",
                         "traffic_note": "per-kernel FETCH/WRITE bytes of the call are listed in the TSC profile "
                                         "summary; the sort's are not counted, so no total is given",

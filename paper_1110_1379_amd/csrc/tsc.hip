@@ -10,12 +10,11 @@
 // sum arithmetic, so every operation rounds as written.
 //
 // Assignment is a gather, not a scatter: the particles are sorted by the key of their nearest
-// cell (radix sort), a table gives each cell's range in that order, and one thread per cell
-// sums the contributions of the particles whose nearest cell is one of its 27 neighbours (in
-// a fixed order, so the density is the same bits on every call).  Along k the three
-// neighbouring cells of a row are consecutive keys, so a cell reads nine contiguous particle
-// ranges.  No atomics: in the clumps a scatter would put many lanes of a wavefront on the
-// same few addresses.
+// cell (radix sort), a table gives each cell's range in that order, and every cell sums the
+// contributions of the particles whose nearest cell is one of its 27 neighbours, through
+// per-cell moments of each neighbour row (k_tsc_density), in a fixed order, so the density
+// is the same bits on every call.  No atomics: in the clumps a scatter would put many lanes
+// of a wavefront on the same few addresses.
 #include <cstring>
 
 #include <rocprim/rocprim.hpp>
@@ -119,22 +118,27 @@ __global__ void __launch_bounds__(kB) k_tsc_fill_start(unsigned* __restrict__ st
 }
 
 // Density of cell (i,j,k): the sum over the particles whose nearest cell is (i+a, j+b, k+c),
-// a, b, c in {-1, 0, 1}, of mass x their weight for offset (-a, -b, -c), neighbour rows in
-// the order (a, b) and within a row in key order.  A workgroup owns a segment of kB cells of
-// one row (the whole row when N < kB).  For each of the 9 neighbour rows it stages the
-// particles of the cells its segment touches (key and offsets, kCH at a time) in LDS, and
-// every thread sums its cell's share from there: each particle comes from L2 once per
-// workgroup instead of once per cell that needs it.  The wrapped cells of a row (k = -1 and
-// k = N) form ranges of their own, taken before and after the row's main range, so each
-// cell adds its particles in the order k-1, k, k+1.
+// a, b, c in {-1, 0, 1}, of mass x their weight for offset (-a, -b, -c).  A workgroup owns a
+// segment of S = min(N, kB) cells of one row.  For each of the 9 neighbour rows (a, b) in
+// turn:
+//  - the particles of the source cells k0-1 .. k0+S of that row are staged in LDS, kCH at a
+//    time, in up to three key ranges: the wrapped cell N-1 (when k0 = 0), the cells
+//    max(k0-1, 0) .. min(k0+S, N-1), the wrapped cell 0 (when k0 + S = N);
+//  - one thread per source cell sums, over the cell's particles in key order, mass x w_x(-a)
+//    x w_y(-b) x w_z(o) for the three z offsets o at once (three moments, kept in LDS);
+//  - every cell adds the moments of its source cells k-1, k, k+1 for the offsets that reach
+//    it.
+// Each particle's weights are evaluated once per neighbour row rather than once per target
+// cell, and a dense cell's particles are walked by one lane rather than three.  The order of
+// every sum is fixed, so the density is the same bits on every call.
 constexpr int kCH = 512;
 
-__global__ void __launch_bounds__(kB) k_tsc_density(const double* __restrict__ dsorted, const unsigned* __restrict__ key,
+__global__ void __launch_bounds__(kB) k_tsc_density(const double* __restrict__ dsorted,
                                                     const unsigned* __restrict__ start, int N, int lg, double mass,
                                                     double* __restrict__ rho)
 {
-    __shared__ unsigned sk[kCH];
     __shared__ double sx[kCH], sy[kCH], sz[kCH];
+    __shared__ double mom[3][kB + 2];            // moments of source cell k0-1+sc for z offsets 0, 1, 2
     const int m = N - 1;
     const int S = N < kB ? N : kB;               // cells per segment
     const int nseg = N / S;                      // segments per row
@@ -144,59 +148,86 @@ __global__ void __launch_bounds__(kB) k_tsc_density(const double* __restrict__ d
     const int i = (int)(rowid >> lg), j = (int)(rowid & m);
     const int tid = threadIdx.x;
     const bool live = tid < S;
-    const int k = k0 + tid;
     double sum = 0.0;
     for (int ab = 0; ab < 9; ++ab) {
         const int a = ab / 3 - 1, b = ab % 3 - 1;
         const unsigned row = ((unsigned)((i + a) & m) << (2 * lg)) | ((unsigned)((j + b) & m) << lg);
-        // segments of particles: the wrapped cell N-1 (if k0 = 0), the cells
-        // max(k0-1, 0) .. min(k0+S, N-1), the wrapped cell 0 (if k0 + S = N)
+        // the source cells of this thread (slots tid and tid + kB): particle range and the
+        // key range (0, 1, 2 as above; -1 none) that holds it
+        unsigned lo[2], hi[2];
+        int rg[2];
+        double mm[2][3];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int sc = tid + q * kB;
+            lo[q] = hi[q] = 0;
+            rg[q] = -1;
+            if (sc < S + 2) {
+                const unsigned key = row | (unsigned)((k0 - 1 + sc) & m);
+                lo[q] = start[key];
+                hi[q] = start[key + 1];
+                rg[q] = (sc == 0 && k0 == 0) ? 0 : (sc == S + 1 && k0 + S == N) ? 2 : 1;
+            }
+            mm[q][0] = mm[q][1] = mm[q][2] = 0.0;
+        }
         for (int sg = 0; sg < 3; ++sg) {
-            unsigned g0, g1, t0 = 0, t1 = 0;
+            unsigned g0, g1;
             if (sg == 0) {
                 if (k0 != 0) continue;
                 g0 = start[row + N - 1];
                 g1 = start[row + N];
-                if (k == 0) {
-                    t0 = g0;
-                    t1 = g1;
-                }
             } else if (sg == 1) {
                 g0 = start[row + (k0 > 0 ? k0 - 1 : 0)];
                 g1 = start[row + (k0 + S < N ? k0 + S + 1 : N)];
-                if (live) {
-                    t0 = start[row + (k > 0 ? k - 1 : 0)];
-                    t1 = start[row + (k + 2 < N ? k + 2 : N)];
-                }
             } else {
                 if (k0 + S != N) continue;
                 g0 = start[row];
                 g1 = start[row + 1];
-                if (k == N - 1) {
-                    t0 = g0;
-                    t1 = g1;
-                }
             }
             for (unsigned c0 = g0; c0 < g1; c0 += kCH) {
                 const unsigned c1 = c0 + kCH < g1 ? c0 + kCH : g1;
                 __syncthreads();
                 for (unsigned t = c0 + tid; t < c1; t += kB) {
-                    sk[t - c0] = key[t];
                     sx[t - c0] = dsorted[3 * (long long)t];
                     sy[t - c0] = dsorted[3 * (long long)t + 1];
                     sz[t - c0] = dsorted[3 * (long long)t + 2];
                 }
                 __syncthreads();
-                const unsigned lo = t0 > c0 ? t0 : c0, hi = t1 < c1 ? t1 : c1;
-                for (unsigned t = lo; t < hi; ++t) {
-                    const unsigned l = t - c0;
-                    const int oz = (k - (int)(sk[l] & (unsigned)m) + 1) & m;  // 0, 1, 2 for offsets -1, 0, +1
-                    sum = sum + mass * tsc_w(sx[l], 1 - a) * tsc_w(sy[l], 1 - b) * tsc_w(sz[l], oz);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    if (rg[q] != sg) continue;
+                    const unsigned t0 = lo[q] > c0 ? lo[q] : c0, t1 = hi[q] < c1 ? hi[q] : c1;
+                    for (unsigned t = t0; t < t1; ++t) {
+                        const unsigned l = t - c0;
+                        const double wxy = mass * tsc_w(sx[l], 1 - a) * tsc_w(sy[l], 1 - b);
+                        const double dz = sz[l];
+                        mm[q][0] = mm[q][0] + wxy * tsc_w(dz, 0);
+                        mm[q][1] = mm[q][1] + wxy * tsc_w(dz, 1);
+                        mm[q][2] = mm[q][2] + wxy * tsc_w(dz, 2);
+                    }
                 }
             }
         }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int sc = tid + q * kB;
+            if (sc < S + 2) {
+                mom[0][sc] = mm[q][0];
+                mom[1][sc] = mm[q][1];
+                mom[2][sc] = mm[q][2];
+            }
+        }
+        __syncthreads();
+        // source cells k-1, k, k+1 are slots tid, tid+1, tid+2; they reach cell k with the
+        // z weights of offsets +1, 0, -1 (o = 2, 1, 0)
+        if (live) {
+            sum = sum + mom[2][tid];
+            sum = sum + mom[1][tid + 1];
+            sum = sum + mom[0][tid + 2];
+        }
+        __syncthreads();  // the next row rewrites mom (it may stage nothing before that)
     }
-    if (live) rho[((long long)rowid << lg) + k] = sum;
+    if (live) rho[((long long)rowid << lg) + k0 + tid] = sum;
 }
 
 // acc = sum over the 27 cells of weight x (-grad phi), -grad phi by central differences.
@@ -323,8 +354,7 @@ int mgfr_tsc_density(mgfr_ctx* c, const double* pos, long long np, int N, double
         MGFR_TRY(hip_check(c, hipGetLastError(), "k_tsc_fill_start"));
     }
     const long long segs = (long long)N * N * (N < mgfr::kB ? 1 : N / mgfr::kB);
-    hipLaunchKernelGGL(mgfr::k_tsc_density, dim3((unsigned)segs), dim3(mgfr::kB), 0, s, sorted, key2, start, N, lg, mass,
-                       rho);
+    hipLaunchKernelGGL(mgfr::k_tsc_density, dim3((unsigned)segs), dim3(mgfr::kB), 0, s, sorted, start, N, lg, mass, rho);
     MGFR_TRY(hip_check(c, hipGetLastError(), "k_tsc_density"));
     return MGFR_OK;
 }
