@@ -121,15 +121,18 @@ __global__ void __launch_bounds__(kB) k_tsc_fill_start(unsigned* __restrict__ st
 // a, b, c in {-1, 0, 1}, of mass x their weight for offset (-a, -b, -c).  A workgroup owns a
 // segment of S = min(N, kB) cells of one row.  For each of the 9 neighbour rows (a, b) in
 // turn:
-//  - the particles of the source cells k0-1 .. k0+S of that row are staged in LDS, kCH at a
-//    time, in up to three key ranges: the wrapped cell N-1 (when k0 = 0), the cells
-//    max(k0-1, 0) .. min(k0+S, N-1), the wrapped cell 0 (when k0 + S = N);
-//  - one thread per source cell sums, over the cell's particles in key order, mass x w_x(-a)
-//    x w_y(-b) x w_z(o) for the three z offsets o at once (three moments, kept in LDS);
+//  - the particles of the source cells k0-1 .. k0+S of that row are taken kCH at a time, in
+//    up to three key ranges: the wrapped cell N-1 (when k0 = 0), the cells
+//    max(k0-1, 0) .. min(k0+S, N-1), the wrapped cell 0 (when k0 + S = N); every thread
+//    evaluates mass x w_x(-a) x w_y(-b) x w_z(o) for the three z offsets o of its particles
+//    of the chunk into LDS, so that the weights cost the same in every lane;
+//  - one thread per source cell sums those terms over the cell's particles in key order
+//    (three moments, kept in LDS);
 //  - every cell adds the moments of its source cells k-1, k, k+1 for the offsets that reach
 //    it.
 // Each particle's weights are evaluated once per neighbour row rather than once per target
-// cell, and a dense cell's particles are walked by one lane rather than three.  The order of
+// cell, and the serial walk over a dense cell's particles is one lane's three additions per
+// particle.  The order of
 // every sum is fixed, so the density is the same bits on every call.
 constexpr int kCH = 512;
 
@@ -137,7 +140,7 @@ __global__ void __launch_bounds__(kB) k_tsc_density(const double* __restrict__ d
                                                     const unsigned* __restrict__ start, int N, int lg, double mass,
                                                     double* __restrict__ rho)
 {
-    __shared__ double sx[kCH], sy[kCH], sz[kCH];
+    __shared__ double cw[3][kCH];                // per particle of the chunk: its three terms
     __shared__ double mom[3][kB + 2];            // moments of source cell k0-1+sc for z offsets 0, 1, 2
     const int m = N - 1;
     const int S = N < kB ? N : kB;               // cells per segment
@@ -188,9 +191,12 @@ __global__ void __launch_bounds__(kB) k_tsc_density(const double* __restrict__ d
                 const unsigned c1 = c0 + kCH < g1 ? c0 + kCH : g1;
                 __syncthreads();
                 for (unsigned t = c0 + tid; t < c1; t += kB) {
-                    sx[t - c0] = dsorted[3 * (long long)t];
-                    sy[t - c0] = dsorted[3 * (long long)t + 1];
-                    sz[t - c0] = dsorted[3 * (long long)t + 2];
+                    const double* d = dsorted + 3 * (long long)t;
+                    const double wxy = mass * tsc_w(d[0], 1 - a) * tsc_w(d[1], 1 - b);
+                    const double dz = d[2];
+                    cw[0][t - c0] = wxy * tsc_w(dz, 0);
+                    cw[1][t - c0] = wxy * tsc_w(dz, 1);
+                    cw[2][t - c0] = wxy * tsc_w(dz, 2);
                 }
                 __syncthreads();
 #pragma unroll
@@ -199,11 +205,9 @@ __global__ void __launch_bounds__(kB) k_tsc_density(const double* __restrict__ d
                     const unsigned t0 = lo[q] > c0 ? lo[q] : c0, t1 = hi[q] < c1 ? hi[q] : c1;
                     for (unsigned t = t0; t < t1; ++t) {
                         const unsigned l = t - c0;
-                        const double wxy = mass * tsc_w(sx[l], 1 - a) * tsc_w(sy[l], 1 - b);
-                        const double dz = sz[l];
-                        mm[q][0] = mm[q][0] + wxy * tsc_w(dz, 0);
-                        mm[q][1] = mm[q][1] + wxy * tsc_w(dz, 1);
-                        mm[q][2] = mm[q][2] + wxy * tsc_w(dz, 2);
+                        mm[q][0] = mm[q][0] + cw[0][l];
+                        mm[q][1] = mm[q][1] + cw[1][l];
+                        mm[q][2] = mm[q][2] + cw[2][l];
                     }
                 }
             }
