@@ -141,3 +141,31 @@ def test_poisson_full_size_stencil_residual(mg, ctx):
     say(f"  cycles {len(hist) - 1}, sampled rms residual {rms:.3e}, source rms {rms_src:.3e}")
     assert rms <= 2e-8 * rms_src
     assert abs(g.mean()) <= 1e-12 * np.abs(g).max()
+
+
+def test_poisson_maximum_size_sine_mode(mg, ctx):
+    """N = 1024, the largest grid the library takes: an x-only density 1 + eps sin(2 pi x)
+    with the scalaron at its background value, so that the source is 2 Om a eps sin(2 pi x)
+    (delta R vanishes at the background).  A single Fourier mode is an eigenvector of the
+    periodic 7-point Laplacian, so the exact discrete potential is the source divided by the
+    eigenvalue (2 cos(2 pi / N) - 2) N^2, in every cell."""
+    import torch
+    N, box, fr0, eps = 1024, 256.0, 1e-5, 0.3
+    params = mg.Params(box_mpc_h=box, fr0_abs=fr0)
+    model = O.Model(box_mpc_h=box, fr0_abs=fr0)
+    x = (np.arange(N) + 0.5) / N
+    s1 = np.sin(2.0 * np.pi * x)
+    lam = (2.0 * np.cos(2.0 * np.pi / N) - 2.0) * N * N
+    phi1 = 2.0 * model.omega_m * model.a * eps * s1 / lam
+    ubar = O.constants(model, N)["ubar"]
+    rho = dev(1.0 + eps * s1)[:, None, None].expand(N, N, N).contiguous()
+    u = torch.full_like(rho, ubar)
+    say(f"[poisson] max size N={N}")
+    phi, hist, st = mg.mg_poisson_solve(ctx, rho, u, params, mg.mgfr_default_opts(tol=1e-9, max_cycles=60))
+    assert st == mg.MGFR_OK, (ctx.last_error(), hist)
+    del rho, u
+    err = (phi - dev(phi1)[:, None, None]).abs().max().item() / np.abs(phi1).max()
+    say(f"  cycles {len(hist) - 1}, final {hist[-1]:.2e}, max rel err {err:.2e}")
+    assert err <= 1e-8
+    del phi
+    torch.cuda.empty_cache()
