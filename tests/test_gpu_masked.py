@@ -217,3 +217,30 @@ def test_masked_full_size(mg, ctx):
     say(f"  active {act.mean():.3f}, cycles {len(hg) - 1}, rms {hg[-1]:.3e}, oracle rms {rms:.3e}")
     assert rms <= 1e-8 * 1.001
     assert abs(rms - hg[-1]) <= 1e-3 * hg[-1]
+
+
+def test_masked_maximum_size_all_active_sine(mg, ctx):
+    """N = 1024, the largest grid the library takes, every cell active: the mask scheme
+    reduces to the domain equations, so the x-only sine density of Sec. VI.A.3 must give the
+    brute-force 1-D Newton solution of the discrete equations (paper_refs.newton_1d)."""
+    import paper_refs as P
+    import torch
+    N, box, fr0 = 1024, 256.0, 1e-5
+    m = O.Model(box_mpc_h=box, fr0_abs=fr0)
+    x = (np.arange(N) + 0.5) / N
+    rho1 = 1.0 + P.sine_density(m, x)
+    say("[masked] max size: 1-D Newton reference")
+    u1 = P.newton_1d(m, rho1, 1.0 / N, P.sine_u(m, x))
+    rho = dev(rho1)[:, None, None].expand(N, N, N).contiguous()
+    ones = torch.ones((N, N, N), dtype=torch.float32, device="cuda:0")
+    u0 = torch.full_like(rho, O.constants(m, N)["ubar"])
+    say("[masked] max size: solving")
+    ud, hg, st = mg.mg_fr_solve_masked(ctx, rho, ones, u0, mg.Params(box_mpc_h=box, fr0_abs=fr0),
+                                       mg.mgfr_default_opts(tol=1e-11, max_cycles=100))
+    assert st == mg.MGFR_OK, (ctx.last_error(), hg)
+    del rho, ones
+    err = (ud - dev(u1)[:, None, None]).abs().max().item()
+    say(f"  cycles {len(hg) - 1}, final {hg[-1]:.2e}, max|u - u_1d| {err:.2e}")
+    assert err <= 1e-10
+    del ud, u0
+    torch.cuda.empty_cache()
