@@ -71,11 +71,12 @@ def test_density_and_force_match_oracle(mg, ctx, Ng, N):
     assert ferr <= 1e-13 * scale
 
 
-def test_density_rows_of_several_segments(mg, ctx):
-    """N = 512: each row is split over two workgroups, so the wrapped source cells at both
-    row ends and the segment seams are exercised; every cell is compared to the oracle."""
-    say("[tsc] 64^3 particles on 512^3")
-    N = 512
+@pytest.mark.parametrize("N", [512, 1024])
+def test_density_rows_of_several_segments(mg, ctx, N):
+    """N = 512 and 1024 (the largest grid): each row is split over two or four workgroups, so
+    the wrapped source cells at both row ends, the segment seams and segments with neither
+    end are exercised; every cell is compared to the oracle."""
+    say(f"[tsc] 64^3 particles on {N}^3")
     pos = inputs.particles(64, seed=17)
     m = N ** 3 / len(pos)
     ref = tsc.deposit(pos, N, m)
