@@ -51,8 +51,8 @@ MEASURED_TRAFFIC = {
         "masked.hip": "a817c4e9e94d53f0f705367b678670a6db06150245dd2edbe41fc098446a8bf3",
         "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
         "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
-    "poisson": {"bytes": 4.020e9, "sources": {
-        "poisson_kernels.hip": "9f8450a69b89060ccd64b388e3d917e830632923c46e8af95fe879c5e20f908d",
+    "poisson": {"bytes": 3.631e9, "sources": {
+        "poisson_kernels.hip": "8ef270f9a78d0ee210179a3dab0de7499c9764aa3bab3ed9d665d4bd122c4738",
         "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
 }
 
@@ -303,7 +303,10 @@ def bench_poisson(args):
                         "frac": achieved / HBM_PEAK_GBS if achieved else None,
                         "traffic": measured_traffic("poisson", N),
                         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                        "kernel": "linear fused red-black sweep kp_fused (finest level)", "bytes_per_cell": 24,
+                        "kernel": "linear fused red-black sweeps kp_fused2 (finest level; two sweeps per launch, "
+                                  "temporally blocked)",
+                        "bytes_per_cell": 24, "sweeps_per_launch": 2,
+                        "bytes_note": "24 B per cell per launch: x and S read once and x written once for both sweeps",
                         "launches": s["sweep_launches"],
                         "avg_launch_ms": s["sweep_ms"] / s["sweep_launches"] if s["sweep_launches"] else None}}
     if not args.no_cpu_baseline:

@@ -243,6 +243,18 @@ int mgfr_tau(mgfr_ctx* ctx, const double* rho, const double* u, int N, const mgf
 int mg_poisson_solve(mgfr_ctx* ctx, const double* rho, const double* u, int N, const mgfr_params* params,
                      const mgfr_opts* opts, double* phi, double* res_hist, int* n_hist, void* stream);
 
+/* Single-grid red-black Gauss-Seidel sweeps of the modified Poisson equation (Sec. V.A.3),
+ * the smoother of mg_poisson_solve on its own: nsweeps sweeps of phi in place against the
+ * source of rho and u (its mean removed), with no coarse levels.
+ * variant 0: per-colour kernels (any N); 1: the one-sweep fused kernel; 2: the two-sweep
+ * temporally blocked kernel (nsweeps even).  Variants 1 and 2 need N >= 256 and give the same
+ * bits; variant 0 sums each cell's neighbours in another order.
+ * rho, u device, N^3 (read); phi device, N^3 (read and written).  N power of two in
+ * [4, 1024].  Returns MGFR_EINVAL for other N, variants or an odd nsweeps with variant 2,
+ * MGFR_ENONFINITE for a non-finite source.  Synchronises. */
+int mg_poisson_smooth(mgfr_ctx* ctx, const double* rho, const double* u, int N, const mgfr_params* params,
+                      int nsweeps, int variant, double* phi, void* stream);
+
 /* A refinement level of irregular shape solved with the mask scheme (Sec. V; eq. phi_b,
  * eq. u_i-1jk, eq. bc_modified_fR_op, eq. bc_modified_fR_dop; restriction and prolongation
  * rules of Sec. V.A.2, V.A.3, V.B.2).  The level is held as the periodic N^3 grid of its

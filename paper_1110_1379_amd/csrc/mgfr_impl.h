@@ -24,6 +24,11 @@ hipError_t poisson_ngs(const PGrid& g, double* x, const double* b, double bmean,
 int poisson_fused_min_n();
 hipError_t poisson_ngs_fused(const PGrid& g, const double* xin, double* xout, const double* b, double bmean, int ti,
                              hipStream_t s);
+// Two red-black sweeps from xin into xout in one pass (the same bits as two one-sweep calls),
+// and its planes per workgroup when the options leave them automatic.
+int poisson_fused2_planes(int n);
+hipError_t poisson_ngs_fused2(const PGrid& g, const double* xin, double* xout, const double* b, double bmean, int ti,
+                              hipStream_t s);
 // bc = R (b - bmean - lap x) on the level below.
 hipError_t poisson_resid_restrict(const PGrid& g, const double* x, const double* b, double bmean, double* bc,
                                   hipStream_t s);

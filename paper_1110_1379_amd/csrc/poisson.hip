@@ -58,7 +58,18 @@ struct PCycle {
     hipStream_t s;
     double mean0;  // mean of the finest source
 
-    int sweep(size_t m, double*& cur, double bm)
+    // `count` sweeps: one launch, or on levels with the fused kernels as many two-sweep
+    // passes as fit and one single sweep for an odd remainder
+    int sweeps(size_t m, double*& cur, double bm, int count)
+    {
+        int k = 0;
+        if (c->plv[m].alt)
+            for (; k + 2 <= count; k += 2) MGFR_TRY(sweep(m, cur, bm, 2));
+        for (; k < count; ++k) MGFR_TRY(sweep(m, cur, bm, 1));
+        return MGFR_OK;
+    }
+
+    int sweep(size_t m, double*& cur, double bm, int passes)
     {
         mgfr_ctx::PLevel& L = c->plv[m];
         // MGFR_PROFILE: HIP events around every finest-level sweep, on the solve's stream
@@ -75,8 +86,14 @@ struct PCycle {
         }
         if (L.alt) {
             double* out = cur == L.alt ? (m == 0 ? finest_x : L.x) : L.alt;
-            const int ti = m == 0 && o->planes > 0 && o->planes <= L.g.n ? o->planes : mgfr::fused_sweep_planes(L.g.n);
-            MGFR_TRY(hip_check(c, mgfr::poisson_ngs_fused(L.g, cur, out, L.b, bm, ti, s), "poisson_ngs_fused"));
+            const bool opt = m == 0 && o->planes > 0 && o->planes <= L.g.n;
+            if (passes == 2) {
+                const int ti = opt ? o->planes : mgfr::poisson_fused2_planes(L.g.n);
+                MGFR_TRY(hip_check(c, mgfr::poisson_ngs_fused2(L.g, cur, out, L.b, bm, ti, s), "poisson_ngs_fused2"));
+            } else {
+                const int ti = opt ? o->planes : mgfr::fused_sweep_planes(L.g.n);
+                MGFR_TRY(hip_check(c, mgfr::poisson_ngs_fused(L.g, cur, out, L.b, bm, ti, s), "poisson_ngs_fused"));
+            }
             cur = out;
         } else {
             MGFR_TRY(hip_check(c, mgfr::poisson_ngs(L.g, cur, L.b, bm, s), "poisson_ngs"));
@@ -85,10 +102,11 @@ struct PCycle {
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
             c->ev_used += 2;
             c->stats.sweep_launches += L.alt ? 1 : 2;
-            c->stats.sweep_bytes += 24.0 * (double)(1LL << (3 * L.g.lg));  // read x, b; write x
+            // read x, b; write x: once per launch, also for a two-sweep pass
+            c->stats.sweep_bytes += 24.0 * (double)(1LL << (3 * L.g.lg));
         }
-        c->stats.cell_updates += 1LL << (3 * L.g.lg);
-        if (m == 0) c->stats.finest_updates += 1LL << (3 * L.g.lg);
+        c->stats.cell_updates += passes * (1LL << (3 * L.g.lg));
+        if (m == 0) c->stats.finest_updates += passes * (1LL << (3 * L.g.lg));
         return MGFR_OK;
     }
 
@@ -104,12 +122,12 @@ struct PCycle {
                              "poisson_coarsest");
         mgfr_ctx::PLevel& H = c->plv[m + 1];
         double* cur = x;
-        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m, cur, bm));
+        MGFR_TRY(sweeps(m, cur, bm, o->pre));
         MGFR_TRY(hip_check(c, mgfr::poisson_resid_restrict(L.g, cur, L.b, bm, H.b, s), "poisson_resid_restrict"));
         MGFR_TRY(hip_check(c, mgfr::fill(H.x, 0.0, 1LL << (3 * H.g.lg), s), "fill"));
         MGFR_TRY(vcycle(m + 1));
         MGFR_TRY(hip_check(c, mgfr::prolong_add_direct(coarse_grid(H.g), cur, H.x, s), "prolong_add_direct"));
-        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep(m, cur, bm));
+        MGFR_TRY(sweeps(m, cur, bm, o->post));
         if (cur != x)
             MGFR_TRY(hip_check(c, hipMemcpyAsync(x, cur, sizeof(double) * ((size_t)1 << (3 * L.g.lg)),
                                                  hipMemcpyDeviceToDevice, s),
@@ -220,6 +238,52 @@ int mg_poisson_solve(mgfr_ctx* c, const double* rho, const double* u, int N, con
     if (status == MGFR_ENONFINITE) return c->fail(status, "the Poisson residual became non-finite");
     if (status == MGFR_ENOTCONV) return c->fail(status, "rms residual %.3e above tol x source rms after %d cycles", rms, k);
     return MGFR_OK;
+}
+
+int mg_poisson_smooth(mgfr_ctx* c, const double* rho, const double* u, int N, const mgfr_params* params,
+                      int nsweeps, int variant, double* phi, void* stream)
+{
+    if (!c) return MGFR_EINVAL;
+    c->err.clear();
+    if (!rho || !u || !phi) return c->fail(MGFR_EINVAL, "null rho, u or phi");
+    if (!is_pow2(N) || N < 4 || N > 1024) return c->fail(MGFR_EINVAL, "N=%d must be a power of two in [4, 1024]", N);
+    if (nsweeps < 0 || variant < 0 || variant > 2 || (variant == 2 && (nsweeps & 1)))
+        return c->fail(MGFR_EINVAL, "invalid sweep count or variant");
+    if (variant > 0 && N < mgfr::poisson_fused_min_n())
+        return c->fail(MGFR_EINVAL, "the fused sweeps need N >= %d", mgfr::poisson_fused_min_n());
+    Model md;
+    if (derive_model(params, &md) != MGFR_OK) return c->fail(MGFR_EINVAL, "invalid model parameters");
+    MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+    hipStream_t s = (hipStream_t)stream;
+    MGFR_TRY(ensure_scratch(c));
+    MGFR_TRY(ensure_poisson(c, N, N));  // the finest level alone: its source and second buffer
+    const long long n3 = (long long)N * N * N;
+    mgfr_ctx::PLevel& L0 = c->plv[0];
+    mgfr::PoissonSource src{md.D, md.A, md.inv_np1, md.Sbar};
+    MGFR_TRY(hip_check(c, mgfr::poisson_source(src, n3, rho, u, L0.b, c->partial, s), "poisson_source"));
+    MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, mgfr::poisson_partials(n3), c->red, s), "fold_partials"));
+    double sm[2];
+    MGFR_TRY(read_reduction(c, s, sm));
+    if (!std::isfinite(sm[0]) || !std::isfinite(sm[1]))
+        return c->fail(MGFR_ENONFINITE, "the source is not finite (non-finite rho or u)");
+    const double mean = sm[0] / (double)n3;
+    double* cur = phi;
+    for (int k = 0; k < nsweeps; k += variant == 2 ? 2 : 1) {
+        double* out = cur == phi ? L0.alt : phi;
+        if (variant == 0)
+            MGFR_TRY(hip_check(c, mgfr::poisson_ngs(L0.g, cur, L0.b, mean, s), "poisson_ngs"));
+        else if (variant == 1)
+            MGFR_TRY(hip_check(c, mgfr::poisson_ngs_fused(L0.g, cur, out, L0.b, mean, mgfr::fused_sweep_planes(N), s),
+                               "poisson_ngs_fused"));
+        else
+            MGFR_TRY(hip_check(c, mgfr::poisson_ngs_fused2(L0.g, cur, out, L0.b, mean, mgfr::poisson_fused2_planes(N), s),
+                               "poisson_ngs_fused2"));
+        if (variant > 0) cur = out;
+    }
+    if (cur != phi)
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(phi, cur, sizeof(double) * (size_t)n3, hipMemcpyDeviceToDevice, s),
+                           "hipMemcpyAsync"));
+    return hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
 }  // extern "C"

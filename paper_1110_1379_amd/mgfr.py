@@ -96,6 +96,7 @@ def lib():
             "mgfr_autotune": ([vp, vp, ctypes.c_int, P, O, vp, O, dp, vp], ctypes.c_int),
             "mg_poisson_solve": ([vp, vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
             "mgfr_tau": ([vp, vp, vp, ctypes.c_int, P, ctypes.c_int, vp, dp, vp], ctypes.c_int),
+            "mg_poisson_smooth": ([vp, vp, vp, ctypes.c_int, P, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
             "mg_fr_solve_masked": ([vp, vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
             "mgfr_tsc_density": ([vp, vp, ctypes.c_longlong, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int),
             "mgfr_tsc_force": ([vp, vp, ctypes.c_int, vp, ctypes.c_longlong, vp, vp], ctypes.c_int),
@@ -111,7 +112,7 @@ def lib():
 def exported_symbols():
     return ("mgfr_create", "mgfr_destroy", "mgfr_last_error", "mgfr_default_opts", "mgfr_constants",
             "mgfr_residual", "mg_fr_solve", "mgfr_get_stats", "mgfr_smooth", "mg_fr_solve_patches",
-            "mg_fr_solve_batch", "mgfr_autotune", "mg_poisson_solve", "mgfr_tau",
+            "mg_fr_solve_batch", "mgfr_autotune", "mg_poisson_solve", "mg_poisson_smooth", "mgfr_tau",
             "mg_fr_solve_masked", "mgfr_tsc_density", "mgfr_tsc_force")
 
 
@@ -305,6 +306,18 @@ def mgfr_tsc_force(ctx: Context, phi, pos, acc=None, stream=None):
     if st != MGFR_OK:
         raise MgfrError(st, ctx.last_error())
     return acc
+
+
+def mg_poisson_smooth(ctx: Context, rho, u, phi, params: Params, nsweeps: int, variant: int = 0, stream=None):
+    """nsweeps single-grid red-black sweeps of the modified Poisson equation, in place on phi
+    (float64 device tensors of shape (N, N, N)).  variant 0: per-colour kernels, 1: one-sweep
+    fused kernel, 2: two-sweep fused kernel (nsweeps even; N >= 256 for 1 and 2)."""
+    N = rho.shape[0]
+    st = lib().mg_poisson_smooth(ctx.handle, _ptr(rho), _ptr(u), N, ctypes.byref(params.c()), nsweeps, variant,
+                                 _ptr(phi), _stream(stream))
+    if st != MGFR_OK:
+        raise MgfrError(st, ctx.last_error())
+    return phi
 
 
 def mg_poisson_solve(ctx: Context, rho, u, params: Params, opts: mgfr_opts | None = None, phi=None,
