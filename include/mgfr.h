@@ -101,11 +101,12 @@ typedef struct mgfr_stats {
     long long finest_updates;  /* of which on the finest level                                 */
     int sweep_launches;        /* MGFR_PROFILE: finest-level smoother kernel launches timed    */
     double sweep_ms;           /* MGFR_PROFILE: their summed duration (HIP events, same stream) */
-    double sweep_bytes;        /* algorithmic bytes of those launches: per cell and launch
-                                  24 B in FP64 (read u, read rho, write u; the two-sweep
-                                  pass of mg_poisson_solve moves them once for both sweeps)
-                                  and 16 B in the single-precision correction sweep (read
-                                  base, rhs and e, write e)                                 */
+    double sweep_bytes;        /* algorithmic bytes of those launches: per cell 24 B in FP64
+                                  (read u, read rho, write u) and 16 B in the single-
+                                  precision correction sweep (read base, rhs and e, write e),
+                                  counted once per fused launch (also for the two-sweep pass
+                                  of mg_poisson_solve, which moves them once for both
+                                  sweeps) or per pair of colour launches                    */
     double solve_ms;           /* host wall time of the last solve call                        */
     double tau_rms;            /* tau_alpha > 0: rms of tau at the last stop test; else 0    */
 } mgfr_stats;
