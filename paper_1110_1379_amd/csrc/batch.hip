@@ -111,7 +111,8 @@ struct Batch {
     {
         if (count == 0) count = 1;
         const size_t bytes = count * sizeof(T);
-        void* q = c->take_spare(bytes);
+        size_t size = bytes;  // a reused block keeps its full size for later reuse
+        void* q = c->take_spare(bytes, &size);
         if (!q && hipMalloc(&q, bytes) != hipSuccess) {
             (void)hipGetLastError();
             c->free_spare();  // give cached blocks back and try once more
@@ -119,7 +120,7 @@ struct Batch {
                 return c->fail(MGFR_ENOMEM, "hipMalloc of %zu bytes for a batch failed", bytes);
         }
         *p = (T*)q;
-        owned.emplace_back(q, bytes);
+        owned.emplace_back(q, size);
         return MGFR_OK;
     }
 

@@ -141,13 +141,15 @@ struct mgfr_ctx {
     // device blocks of finished batched solves, reused by later ones (smallest that fits)
     std::vector<std::pair<void*, size_t>> spare;
 
-    void* take_spare(size_t bytes)
+    // the smallest kept block of at least `bytes`, or null; *size gets its full size
+    void* take_spare(size_t bytes, size_t* size)
     {
         size_t best = spare.size();
         for (size_t i = 0; i < spare.size(); ++i)
             if (spare[i].second >= bytes && (best == spare.size() || spare[i].second < spare[best].second)) best = i;
         if (best == spare.size()) return nullptr;
         void* p = spare[best].first;
+        *size = spare[best].second;
         spare.erase(spare.begin() + (long)best);
         return p;
     }
