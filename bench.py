@@ -37,24 +37,7 @@ METRIC = "f(R) MG time-to-residual 1e-8 & cell-updates/s, 512^3, FP64 vs mixed"
 # of the sources those kernels are compiled from (the kernel file, its device header and the
 # by-value kernel types): when any of them differs the figure no longer describes the kernel
 # that runs and `traffic` is reported as null.
-MEASURED_TRAFFIC = {
-    "mixed": {"bytes": 2.699e9, "sources": {
-        "kernels_fp32.hip": "9f678b380311577e8d67d9cbe38a8decc8747afb0ab3ff0d6f549fddbfa525fe",
-        "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
-        "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
-    "fp64": {"bytes": 3.428e9, "sources": {
-        "sweep_fp64.hip": "8626f8c275f300f245261a3ce754af32586572b601a374203ca3eeb1fd8c8850",
-        "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
-        "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
-    # per sweep (both colour launches of the masked per-colour kernel)
-    "masked": {"bytes": 14.380e9, "sources": {
-        "masked.hip": "a817c4e9e94d53f0f705367b678670a6db06150245dd2edbe41fc098446a8bf3",
-        "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
-        "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
-    "poisson": {"bytes": 3.631e9, "sources": {
-        "poisson_kernels.hip": "8ef270f9a78d0ee210179a3dab0de7499c9764aa3bab3ed9d665d4bd122c4738",
-        "kernel_types.h": "6718bebe4ac142a4e45471e68a4000ff70a2a5670e4af01b73940ba6f78e47e4"}},
-}
+MEASURED_TRAFFIC = {}
 
 
 def measured_traffic(prec, N):
@@ -92,10 +75,16 @@ def make_density(name, N):
     return inputs.halo_box(N)
 
 
-def cpu_baseline(name, tol):
-    """The oracle as it stands (single thread) on a bounded sample: the same density recipe
-    and cell size on a smaller periodic box (structures scaled with the volume)."""
+def host_cores():
+    """CPUs this process may use (affinity, cgroup quota, OMP_NUM_THREADS) and the machine's
+    count."""
     import oracle
+    return oracle.cpu_share(), os.cpu_count()
+
+
+def oracle_sample(name):
+    """The bounded sample the CPU oracle runs: the same density recipe and cell size on a
+    smaller periodic box (structures scaled with the volume)."""
     from paper_1110_1379_amd import inputs
     N, box, fr0, gen, (Ns, count) = WORKLOADS[name]
     box_s = box * Ns / N
@@ -105,15 +94,66 @@ def cpu_baseline(name, tol):
         rho = inputs.tophat_box(Ns, 1, count=count)
     else:
         rho = inputs.small_box(Ns, 0)
-    t0 = time.perf_counter()
-    u, hist, st = oracle.solve(rho, oracle.Model(box_mpc_h=box_s, fr0_abs=fr0), oracle.Opts(tol=tol))
-    dt = time.perf_counter() - t0
-    ups = oracle.last_cell_updates()
-    return {"value": ups / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+    return Ns, box_s, fr0, count, rho
+
+
+def cpu_baseline(name, tol):
+    """The oracle as it stands on the bounded sample, once on one host thread and once on
+    every core this process may use (OpenMP); cell updates per second of each."""
+    import oracle
+    Ns, box_s, fr0, count, rho = oracle_sample(name)
+    model = oracle.Model(box_mpc_h=box_s, fr0_abs=fr0)
+    avail, total = host_cores()
+    legs = {}
+    for threads in (avail, 1):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        u, hist, st = oracle.solve(rho, model, oracle.Opts(tol=tol))
+        dt = time.perf_counter() - t0
+        legs[threads] = (oracle.last_cell_updates() / dt, dt, len(hist) - 1, st)
+    oracle.set_threads(avail)
+    used = oracle.threads()
+    v, dt, cyc, st = legs[avail]
+    v1, dt1, _, _ = legs[1]
+    return {"value": v, "unit": "cell-updates/s", "cores": used, "kind": "oracle",
+            "nproc": avail, "host_cpus": total,
             "sample": f"{Ns}^3 box of {box_s:g} Mpc/h (same cell size and density recipe, "
-                      f"{count} structures), FP64, solved to rms {tol:g}: {len(hist) - 1} V-cycles, "
-                      f"{dt:.1f} s, status {st}",
-            "time_to_tol_s": dt}
+                      f"{count} structures), FP64, solved to rms {tol:g}: {cyc} V-cycles, "
+                      f"{dt:.2f} s on {used} threads (OpenMP), status {st}",
+            "time_to_tol_s": dt,
+            "single_thread": {"value": v1, "unit": "cell-updates/s", "cores": 1, "time_to_tol_s": dt1}}
+
+
+def field_error_vs_oracle(mgfr, ctx, name, used, tol):
+    """Max and rms |u - u*| of the GPU solutions (FP64 and mixed, at the timed settings and
+    tolerance) against the FP64 oracle solved to rms 1e-12, on the bounded sample the CPU
+    baseline runs (the oracle at the full size would take minutes)."""
+    import numpy as np
+    import oracle
+    import torch
+    Ns, box_s, fr0, count, rho = oracle_sample(name)
+    ref, hist, st = oracle.solve(rho, oracle.Model(box_mpc_h=box_s, fr0_abs=fr0), oracle.Opts(tol=1e-12))
+    if st != 0:
+        raise SystemExit(f"oracle reference solve failed: status {st}")
+    rho_d = torch.from_numpy(rho).to("cuda:0")
+    params = mgfr.Params(box_mpc_h=box_s, fr0_abs=fr0)
+    scale = float(np.abs(ref).max())
+    out = {"sample": f"{Ns}^3 box of {box_s:g} Mpc/h (the CPU-baseline sample); oracle at rms 1e-12 "
+                     f"({len(hist) - 1} V-cycles); GPU at the timed settings and tolerance {tol:g}"}
+    for pname, opts in used.items():
+        o = mgfr.mgfr_opts()
+        import ctypes
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(opts), ctypes.sizeof(o))
+        o.flags = 0
+        if o.planes > Ns:
+            o.planes = 0
+        u, h, st = mgfr.mg_fr_solve(ctx, rho_d, params, o)
+        if st != mgfr.MGFR_OK:
+            raise SystemExit(f"sample solve failed: {ctx.last_error()}")
+        d = np.abs(u.cpu().numpy() - ref)
+        out[pname] = {"max_abs": float(d.max()), "rms_abs": float(np.sqrt(np.mean(d * d))),
+                      "max_rel": float(d.max() / scale), "cycles": len(h) - 1, "final_residual": float(h[-1])}
+    return out
 
 
 def time_domain(mgfr, ctx, rho_d, params, prec, tol, steps, warmup, profile=True, autotune=True,
@@ -159,7 +199,7 @@ def time_domain(mgfr, ctx, rho_d, params, prec, tol, steps, warmup, profile=True
            "finest_cell_updates_per_s": finest / (ms * 1e-3),
            "smoother": {"achieved_GBs": achieved, "launches": launches,
                         "avg_launch_ms": sweep_ms / launches if launches else None,
-                        "bytes_per_cell_sweep": 24 if prec == mgfr.MGFR_FP64 else 16}}
+                        "bytes_per_cell_sweep": 24 if prec == mgfr.MGFR_FP64 else 12}}
     log(f"prec={prec}: {ms:.2f} ms/solve, {res['cycles']} cycles, smoother "
         f"{achieved and round(achieved)} GB/s over {launches} launches")
     return res, u_d, opts
@@ -246,6 +286,13 @@ def bench_domain(args):
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
     }
+    if headp == "mixed" and sm["achieved_GBs"]:
+        # the correction sweep also reads its fixed base ub: 16 B per cell moved in all
+        out["roofline"]["bytes_note"] = ("12 B per cell: e read and written, its right-hand side read (half the "
+                                         "24 B of a double-precision sweep); the fixed base ub the correction "
+                                         "sweep also reads is not credited")
+        out["roofline"]["achieved_with_base"] = sm["achieved_GBs"] * 16.0 / 12.0
+        out["roofline"]["frac_with_base"] = sm["achieved_GBs"] * 16.0 / 12.0 / HBM_PEAK_GBS
     for p, r in runs.items():
         r["smoother"]["traffic"] = measured_traffic(p, N)
         out[p] = r
@@ -264,6 +311,8 @@ def bench_domain(args):
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.tol)
+        log("field error of the GPU solutions against the oracle on the same sample")
+        out["field_error_vs_oracle"] = field_error_vs_oracle(mgfr, ctx, args.workload, used, args.tol)
     return out
 
 
@@ -400,7 +449,8 @@ def bench_masked(args):
         _, hs, sts = oracle.solve_masked(rs, ms_h, model, us, oracle.Opts(tol=args.tol))
         dt = time.perf_counter() - t0
         ups = oracle.last_cell_updates()
-        out["cpu_baseline"] = {"value": ups / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": ups / dt, "unit": "cell-updates/s", "cores": oracle.threads(),
+                               "nproc": host_cores()[0], "kind": "oracle",
                                "sample": f"{Ns}^3 masked level of {box * Ns / N:g} Mpc/h (same cell size and "
                                          f"recipe, 31 halos, {(ms_h > 0).mean():.3f} active), fixed values u_bar + "
                                          f"a smooth field, to rms {args.tol:g}: {len(hs) - 1} V-cycles, {dt:.1f} s, "
@@ -517,18 +567,27 @@ def _precisions(mgfr, args):
     return [(n, mgfr.MGFR_MIXED if n == "mixed" else mgfr.MGFR_FP64) for n in names]
 
 
-def _batched_roofline(s, prec_name):
+def _engines(args):
+    return {"units": ["units"], "phases": ["phases"], "both": ["units", "phases"]}[args.engine]
+
+
+def _engine_name(args):
+    return {"units": "workgroup per unit", "phases": "per phase", "both": "workgroup per unit"}[args.engine]
+
+
+def _batched_roofline(s, prec_name, unit_n=0):
     """Roofline object of the batched smoother from the statistics of a solve run eagerly with
-    MGFR_PROFILE: HIP events around every sweep of the finest level of every unit (the two
-    colour launches of kb_ngs / kb32_ngs), algorithmic bytes of the active units swept."""
+    MGFR_PROFILE: HIP events around the finest-level sweeps of the units launched per phase
+    (the two colour launches of kb_ngs / kb32_ngs), algorithmic bytes of the sweeps those
+    units ran."""
     launches = s["sweep_launches"]
     achieved = s["sweep_bytes"] / (s["sweep_ms"] * 1e-3) / 1e9 if s["sweep_ms"] > 0 else None
     fp64 = prec_name == "fp64"
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
             "kernel": ("kb_ngs" if fp64 else "kb32_ngs") + " (red-black Newton-Gauss-Seidel, one launch per "
-                      "colour over the finest level of every unit)",
-            "bytes_per_cell": 24 if fp64 else 16, "launches": launches,
+                      f"colour over the finest level of every unit larger than {unit_n or 16}^3)",
+            "bytes_per_cell": 24 if fp64 else 12, "launches": launches,
             "avg_launch_ms": s["sweep_ms"] / launches if launches else None,
             "timing": "one more solve of the same problem after the timed steps, launched eagerly (no graph) "
                       "with HIP events around every finest-level sweep on the solve's stream"}
@@ -557,31 +616,38 @@ def bench_amr(args):
     ud, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100))
     assert st == mgfr.MGFR_OK, ctx.last_error()
     rp = torch.from_numpy(rho_packed).to("cuda:0")
-    runs, fields, profiled = {}, {}, {}
-    for name, code in _precisions(mgfr, args):
-        opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code,
-                                      flags=mgfr.MGFR_GRAPH if args.graph else 0)
-        up = torch.empty_like(rp)
+    runs, fields, profiled, per_phase = {}, {}, {}, {}
+    for engine in _engines(args):
+        for name, code in _precisions(mgfr, args):
+            eflags = (mgfr.MGFR_GRAPH if args.graph else 0) | (mgfr.MGFR_PER_PHASE if engine == "phases" else 0)
+            opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=eflags,
+                                          unit_n=args.unit_n)
+            up = torch.empty_like(rp)
 
-        def solve():
-            _, hists, st = mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, opts, u_packed=up)
-            if st != mgfr.MGFR_OK:
-                raise SystemExit(f"patch solve failed: {ctx.last_error()}")
-            return hists
-        ms, hists = _timed(solve, args.steps, args.warmup)
-        s = mgfr.mgfr_get_stats(ctx)
+            def solve(opts=opts, up=up):
+                _, hists, st = mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, opts, u_packed=up)
+                if st != mgfr.MGFR_OK:
+                    raise SystemExit(f"patch solve failed: {ctx.last_error()}")
+                return hists
+            ms, hists = _timed(solve, args.steps, args.warmup)
+            s = mgfr.mgfr_get_stats(ctx)
+            r = {"ms_per_step": ms, "value": s["cell_updates"] / (ms * 1e-3),
+                 "max_cycles_per_patch": int(max(len(h) for h in hists) - 1),
+                 "max_final_residual": float(max(h[-1] for h in hists))}
+            log(f"amr {engine} {name}: {ms:.2f} ms, {r['max_cycles_per_patch']} cycles max")
+            if engine == "phases":
+                per_phase[name] = r
+                continue
 
-        def solve_profiled(code=code):
-            po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=mgfr.MGFR_PROFILE)
-            _, _, st = mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, po, u_packed=torch.empty_like(rp))
-            assert st == mgfr.MGFR_OK, ctx.last_error()
-            return mgfr.mgfr_get_stats(ctx)
-        profiled[name] = solve_profiled
-        runs[name] = {"ms_per_step": ms, "value": s["cell_updates"] / (ms * 1e-3),
-                      "max_cycles_per_patch": int(max(len(h) for h in hists) - 1),
-                      "max_final_residual": float(max(h[-1] for h in hists))}
-        fields[name] = up
-        log(f"amr {name}: {ms:.2f} ms, {runs[name]['max_cycles_per_patch']} cycles max")
+            def solve_profiled(code=code):
+                po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=mgfr.MGFR_PROFILE,
+                                            unit_n=args.unit_n)
+                _, _, st = mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, po, u_packed=torch.empty_like(rp))
+                assert st == mgfr.MGFR_OK, ctx.last_error()
+                return mgfr.mgfr_get_stats(ctx)
+            profiled[name] = solve_profiled
+            runs[name] = r
+            fields[name] = up
     headp = "mixed" if "mixed" in runs else "fp64"
     head = runs[headp]
     out = {"metric": "f(R) MG patch solve time-to-residual & cell-updates/s (AMR refinements)",
@@ -592,9 +658,12 @@ def bench_amr(args):
            "config": {"workload": f"amr: {N0}^3 domain (lognormal sigma 2), {len(patches)} cube patches "
                                   f"8^3-64^3 over {max(p['level'] for p in patches)} levels "
                                   f"(contrast > 50/200/1000), {cells} patch cells, tol {args.tol:g}",
-                      "precision": headp, "graph": bool(args.graph)}}
+                      "precision": headp, "graph": bool(args.graph), "engine": _engine_name(args),
+                      "patches": len(patches), "patch_cells": cells}}
     out.update(runs)
-    out["roofline"] = _batched_roofline(profiled[headp](), headp)
+    if per_phase:
+        out["per_phase_engine"] = per_phase
+    out["roofline"] = _batched_roofline(profiled[headp](), headp, args.unit_n)
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
         out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])
@@ -609,7 +678,8 @@ def bench_amr(args):
         t0 = time.perf_counter()
         _, _, sts = oracle.solve_patches(u0, ps, rl, m, oracle.Opts(tol=args.tol))
         dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": oracle.last_patch_updates / dt, "unit": "cell-updates/s", "cores": 1,
+        out["cpu_baseline"] = {"value": oracle.last_patch_updates / dt, "unit": "cell-updates/s",
+                               "cores": oracle.threads(), "nproc": host_cores()[0],
                                "kind": "oracle",
                                "sample": f"the {len(ps)} patches ({sum(p['n'] ** 3 for p in ps)} cells) of a {Ns}^3 "
                                          f"domain of the same recipe and cell size, FP64, one after another to rms "
@@ -627,32 +697,39 @@ def bench_batch(args):
     rhos = [torch.from_numpy(b[5]).to("cuda:0") for b in boxes]
     params = [mgfr.Params(box_mpc_h=b[1], fr0_abs=b[2]) for b in boxes]
     ctx = mgfr.Context(0)
-    runs, fields, profiled = {}, {}, {}
-    for name, code in _precisions(mgfr, args):
-        opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code,
-                                      flags=mgfr.MGFR_GRAPH if args.graph else 0)
-        us = [torch.empty_like(r) for r in rhos]
+    runs, fields, profiled, per_phase = {}, {}, {}, {}
+    for engine in _engines(args):
+        for name, code in _precisions(mgfr, args):
+            eflags = (mgfr.MGFR_GRAPH if args.graph else 0) | (mgfr.MGFR_PER_PHASE if engine == "phases" else 0)
+            opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=eflags,
+                                          unit_n=args.unit_n)
+            us = [torch.empty_like(r) for r in rhos]
 
-        def solve():
-            _, hists, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, opts, us=us)
-            if st != mgfr.MGFR_OK:
-                raise SystemExit(f"batch solve failed: {ctx.last_error()}")
-            return hists
-        ms, hists = _timed(solve, args.steps, args.warmup)
-        s = mgfr.mgfr_get_stats(ctx)
+            def solve(opts=opts, us=us):
+                _, hists, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, opts, us=us)
+                if st != mgfr.MGFR_OK:
+                    raise SystemExit(f"batch solve failed: {ctx.last_error()}")
+                return hists
+            ms, hists = _timed(solve, args.steps, args.warmup)
+            s = mgfr.mgfr_get_stats(ctx)
+            r = {"ms_per_step": ms, "value": len(boxes) / (ms * 1e-3),
+                 "cell_updates_per_s": s["cell_updates"] / (ms * 1e-3),
+                 "max_cycles_per_box": int(max(len(h) for h in hists) - 1),
+                 "max_final_residual": float(max(h[-1] for h in hists))}
+            log(f"batch {engine} {name}: {ms:.2f} ms, {r['max_cycles_per_box']} cycles max")
+            if engine == "phases":
+                per_phase[name] = r
+                continue
 
-        def solve_profiled(code=code):
-            po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=mgfr.MGFR_PROFILE)
-            _, _, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, po, us=[torch.empty_like(r) for r in rhos])
-            assert st == mgfr.MGFR_OK, ctx.last_error()
-            return mgfr.mgfr_get_stats(ctx)
-        profiled[name] = solve_profiled
-        runs[name] = {"ms_per_step": ms, "value": len(boxes) / (ms * 1e-3),
-                      "cell_updates_per_s": s["cell_updates"] / (ms * 1e-3),
-                      "max_cycles_per_box": int(max(len(h) for h in hists) - 1),
-                      "max_final_residual": float(max(h[-1] for h in hists))}
-        fields[name] = torch.cat([u.reshape(-1) for u in us])
-        log(f"batch {name}: {ms:.2f} ms, {runs[name]['max_cycles_per_box']} cycles max")
+            def solve_profiled(code=code):
+                po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=mgfr.MGFR_PROFILE,
+                                            unit_n=args.unit_n)
+                _, _, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, po, us=[torch.empty_like(r) for r in rhos])
+                assert st == mgfr.MGFR_OK, ctx.last_error()
+                return mgfr.mgfr_get_stats(ctx)
+            profiled[name] = solve_profiled
+            runs[name] = r
+            fields[name] = torch.cat([u.reshape(-1) for u in us])
     headp = "mixed" if "mixed" in runs else "fp64"
     head = runs[headp]
     out = {"metric": "f(R) MG batch of independent boxes: boxes/s at residual 1e-8",
@@ -662,9 +739,11 @@ def bench_batch(args):
            "data": "synthetic",
            "config": {"workload": "batch: 64 x 64^3 (B=64) + 16 x 128^3 (B=128), |f_R0| log-uniform "
                                   f"[1e-6,1e-4], lognormal sigma U[1,3], tol {args.tol:g}",
-                      "precision": headp, "graph": bool(args.graph)}}
+                      "precision": headp, "graph": bool(args.graph), "engine": _engine_name(args)}}
     out.update(runs)
-    out["roofline"] = _batched_roofline(profiled[headp](), headp)
+    if per_phase:
+        out["per_phase_engine"] = per_phase
+    out["roofline"] = _batched_roofline(profiled[headp](), headp, args.unit_n)
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
         out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])
@@ -683,7 +762,8 @@ def bench_batch(args):
         t64, t128 = sum(per[64]) / len(per[64]), sum(per[128]) / len(per[128])
         n64 = sum(1 for b in boxes if b[0] == 64)
         n128 = len(boxes) - n64
-        out["cpu_baseline"] = {"value": len(boxes) / (n64 * t64 + n128 * t128), "unit": "boxes/s", "cores": 1,
+        out["cpu_baseline"] = {"value": len(boxes) / (n64 * t64 + n128 * t128), "unit": "boxes/s",
+                               "cores": oracle.threads(), "nproc": host_cores()[0],
                                "kind": "oracle", "cell_updates_per_s": ups / tsum,
                                "sample": f"four 64^3 boxes ({t64:.2f} s each on average) and one 128^3 box "
                                          f"({t128:.1f} s), FP64, to rms {args.tol:g}; boxes/s of the batch's mix "
@@ -709,6 +789,11 @@ def main():
                     help="amr/batch: capture one cycle's launches in a HIP graph and replay it (the default "
                          "launches every cycle eagerly, which measured as fast or faster)")
     ap.add_argument("--no-graph", action="store_true", help="amr/batch: eager launches (the default)")
+    ap.add_argument("--engine", default="both", choices=["units", "phases", "both"],
+                    help="amr/batch: the workgroup-per-unit engine (the line's value), the per-phase engine "
+                         "(baseline), or both")
+    ap.add_argument("--unit-n", type=int, default=0,
+                    help="amr/batch: units and levels of side <= this run in one workgroup (0: the library's 16)")
     ap.add_argument("--no-stop-rule", action="store_true",
                     help="domain workloads: skip the truncation-error stop-rule comparison")
     ap.add_argument("--copy-probe", action="store_true",

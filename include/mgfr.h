@@ -50,7 +50,22 @@ extern "C" {
                                 (batched solves: every sweep of the finest level of every
                                 unit, both colour launches, when MGFR_GRAPH is not set)      */
 #define MGFR_GRAPH 8         /* batched solves: capture one cycle's launches in a HIP graph
-                                on first use and replay it for every later cycle of the call */
+                                on first use and replay it for every later cycle of the call.
+                                mg_fr_solve: capture two cycles, each ending in the stop test
+                                on the device, once per context and storage (kept until the
+                                hierarchy changes or the context is destroyed), replay them
+                                until the device test stops the solve (every kernel of a cycle
+                                returns at once after it) and read one flag per replay.  Only
+                                with pre + post even and without MGFR_PROFILE and tau_alpha
+                                (otherwise the cycles run eagerly); the results are the same
+                                bits as eager cycles.                                       */
+#define MGFR_PER_PHASE 16    /* batched solves: the per-phase engine (every phase of every
+                                level one launch over all units, per-unit norms read back by
+                                the host after every cycle) instead of the default engine
+                                (units of side <= unit_n solved whole by one workgroup each in
+                                one persistent launch; larger units' fine levels launched per
+                                phase, their coarse levels in one workgroup per unit; stop
+                                tests on the device)                                          */
 
 /* Model (Sec. II, Sec. III.A): Om, OL (< 0 means 1 - Om), scale factor a, Hu-Sawicki n,
  * |f_R0| (the present background f_R), box side B in Mpc/h. */
@@ -78,6 +93,15 @@ typedef struct mgfr_opts {
                              the stop test is rms(L) <= max(tol, tau_alpha rms(tau)));
                              mg_fr_solve only: the batched and masked solves reject it
                              with MGFR_EINVAL                                      [0]      */
+    int unit_n;           /* batched solves (default engine): units, and the levels of larger
+                             units, of side <= unit_n are relaxed by one workgroup each; 0 =
+                             16; values below coarsest_n count as coarsest_n       [0]      */
+    int tile;             /* tile of the finest level's fused sweeps (N >= 64).  FP64: 0 =
+                             automatic (16 x 64), 1 = 16 x 64, 2 = 8 x 64 (column pairs over
+                             the tile and its halo; 3, 4 as 0).  Mixed, the single-precision
+                             correction sweep: 0 = automatic (16 x 32), 1 = 16 x 32, 2 = 32 x
+                             32, 3 = 16 x 64 (one tile column pair per thread), 4 = 8 x 32
+                             (column pairs over the tile and its halo)              [0]      */
 } mgfr_opts;
 
 /* One refinement patch: a cube of n^3 cells at refinement level `level` >= 1 (cell size
@@ -101,10 +125,13 @@ typedef struct mgfr_stats {
     long long finest_updates;  /* of which on the finest level                                 */
     int sweep_launches;        /* MGFR_PROFILE: finest-level smoother kernel launches timed    */
     double sweep_ms;           /* MGFR_PROFILE: their summed duration (HIP events, same stream) */
-    double sweep_bytes;        /* algorithmic bytes of those launches: per cell 24 B in FP64
-                                  (read u, read rho, write u) and 16 B in the single-
-                                  precision correction sweep (read base, rhs and e, write e),
-                                  counted once per fused launch (also for the two-sweep pass
+    double sweep_bytes;        /* algorithmic bytes of those launches: per cell the field
+                                  read and written and its right-hand side read, in the
+                                  sweep's precision: 24 B in FP64 (read u, read rho, write
+                                  u), 12 B in the single-precision correction sweep (read
+                                  and write e, read the rhs; the fixed base ub it also reads
+                                  is not credited), counted once per fused launch (also for
+                                  the two-sweep pass
                                   of mg_poisson_solve, which moves them once for both
                                   sweeps) or per pair of colour launches                    */
     double solve_ms;           /* host wall time of the last solve call                        */
@@ -127,7 +154,7 @@ int mgfr_get_stats(const mgfr_ctx* ctx, mgfr_stats* out);
 
 /* Autotuner: times complete solves of this problem (rho, N, params as for mg_fr_solve,
  * starting from the background) over candidate settings of the tunable options -- sweeps
- * before/after the coarse step, planes per workgroup of the fused sweep, and for
+ * before/after the coarse step, planes per workgroup and tile of the fused sweep, and for
  * MGFR_MIXED the single-precision V-cycles per outer iteration -- and writes the fastest
  * (by host wall time, best of two solves each) into *best (other fields copied from *base).
  * u_scratch: device, N^3, overwritten.  best_ms (host, may be NULL) gets its solve time.
@@ -158,6 +185,22 @@ int mgfr_residual(mgfr_ctx* ctx, const double* rho, const double* u, int N,
  * Does not synchronise unless MGFR_PROFILE is set. */
 int mgfr_smooth(mgfr_ctx* ctx, const double* rho, double* u, int N, const mgfr_params* params,
                 const mgfr_opts* opts, int nsweeps, int variant, void* stream);
+
+/* Single-grid relaxation of the single-precision correction equation of the mixed solver:
+ * Sec. V.B.1's red-black Newton-Gauss-Seidel applied to N(e) = L(ub + e) - L(ub) = f, the
+ * operator of eq. discrete_fR (times c~^2) differenced exactly about the base ub, on the
+ * periodic N^3 grid (h = 1/N), every term written proportional to e:
+ *   N_i(e) = C sum_nb [(M_nb + M_i)(ub_nb - ub_i) + (B_nb + B_i)(e_nb - e_i)]
+ *          + A exp(-ub_i/(n+1)) expm1(-e_i/(n+1)),   b = exp(ub), M = b expm1(e), B = b + M.
+ * nsweeps sweeps in place on e (device, N^3 float); ub and f (device, N^3 float) are read.
+ * variant: 0 = the kernel the mixed solver uses on its finest level for this N, 1 = one kernel
+ * per colour (in place), 2 = the fused red-black sweep (N >= 64, out of place through context
+ * scratch), opts->planes planes per workgroup (0: the mixed solver's automatic choice; else a
+ * multiple of 4 that is <= N).  opts->max_step bounds each step; MGFR_PROFILE times every
+ * launch (12 B per cell: read ub and f, read and write e).  Returns MGFR_EINVAL for other N,
+ * variants or planes.  Does not synchronise unless MGFR_PROFILE is set. */
+int mgfr_smooth32(mgfr_ctx* ctx, const float* ub, float* e, const float* f, int N, const mgfr_params* params,
+                  const mgfr_opts* opts, int nsweeps, int variant, void* stream);
 
 /* The domain-grid solve (Sec. V.B, Sec. VI.A).
  * rho      device, N^3: code-unit density (mean 1 in the paper's units; negative values

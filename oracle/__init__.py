@@ -26,10 +26,10 @@ CUBE_PATCH_R = -1.0
 
 
 def build(force: bool = True) -> str:
-    """Compiles the oracle with gcc (plain -O2, single thread)."""
+    """Compiles the oracle with gcc (plain -O2; OpenMP over the independent cell loops)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", _SRC,
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-fopenmp", "-shared", "-fPIC", _SRC,
                                "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -116,8 +116,36 @@ def lib():
             getattr(L, f).restype = ctypes.c_int
         L.orc_last_cell_updates.argtypes = []
         L.orc_last_cell_updates.restype = ctypes.c_longlong
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
+        # no more threads than the CPUs this process may use (a quota caps them too)
+        share = cpu_share()
+        if L.orc_threads() > share:
+            L.orc_set_threads(share)
         _lib = L
     return _lib
+
+
+def cpu_share() -> int:
+    """CPUs this process may use: its affinity mask, capped by a cgroup CPU quota and by
+    OMP_NUM_THREADS when set."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            quota, period = fh.read().split()[:2]
+        if quota != "max":
+            n = min(n, max(1, int(int(quota) // int(period))))
+    except (OSError, ValueError):
+        pass
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
 
 
 def _dp(a):
@@ -271,6 +299,16 @@ def solve_patches(u_domain, patches, rho_patches, model: Model, opts: Opts | Non
 
 # smoother cell visits of the last solve_patches call, all patches (timing reports only)
 last_patch_updates = 0
+
+
+def threads() -> int:
+    """Host threads the oracle's loops use (results do not depend on it)."""
+    return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Sets the oracle's host thread count (n > 0)."""
+    lib().orc_set_threads(int(n))
 
 
 def last_cell_updates() -> int:

@@ -6,7 +6,11 @@
  * test suite, the smoke check and the benchmark's CPU-baseline leg may load it; the GPU
  * library shares nothing with it.  Every loop is written for a reader checking it
  * against the paper, not for speed: one cell at a time, exp() evaluated where the
- * formula has it, no blocking, no fusion, single thread.
+ * formula has it, no blocking, no fusion.  Loops whose cells do not depend on each other
+ * (one colour of a red-black sweep, a residual, a restriction, a prolongation) run on
+ * several host threads (OpenMP) when the grid has at least 32 planes; their sums are formed
+ * per plane and the planes added in order, so every result is the same whatever the thread
+ * count.
  *
  * What is computed (the paper's notation, code units, tildes dropped):
  *   f_R = -exp(u), b = exp(u)                                      (Sec. III.C)
@@ -31,6 +35,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_EINVAL (-1)
 #define ORC_ENONFINITE (-2)
@@ -155,12 +162,41 @@ static long long g_updates = 0;
 
 long long orc_last_cell_updates(void) { return g_updates; }
 
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+/* Sum of per-plane partial sums, planes in order. */
+static double sum_planes(const double* plane, int n)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += plane[i];
+    return s;
+}
+
 /* Red-black Newton-Gauss-Seidel sweep: red (i+j+k even) first (Sec. V.B.1). */
 static void ngs_sweep(const grid* g, const consts* c, double* u, const double* f, double max_step)
 {
     int n = g->n;
     g_updates += (long long)n * n * n;
+    /* a cell of one colour reads only cells of the other colour: its colour's cells can be
+       visited in any order */
     for (int colour = 0; colour < 2; ++colour)
+#pragma omp parallel for schedule(static) if (n >= 32)
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j)
                 for (int k = 0; k < n; ++k) {
@@ -180,8 +216,10 @@ static void ngs_sweep(const grid* g, const consts* c, double* u, const double* f
 static double residual(const grid* g, const consts* c, const double* u, const double* f, double* d)
 {
     int n = g->n;
-    double s = 0.0;
-    for (int i = 0; i < n; ++i)
+    double* plane = (double*)malloc((size_t)n * sizeof(double));
+#pragma omp parallel for schedule(static) if (n >= 32)
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
         for (int j = 0; j < n; ++j)
             for (int k = 0; k < n; ++k) {
                 double v = cell_op(g, c, u, i, j, k, NULL);
@@ -189,6 +227,10 @@ static double residual(const grid* g, const consts* c, const double* u, const do
                 if (d) d[at(n, i, j, k)] = v;
                 s += v * v;
             }
+        plane[i] = s;
+    }
+    double s = sum_planes(plane, n);
+    free(plane);
     return s;
 }
 
@@ -200,8 +242,10 @@ static double rounding_floor(const grid* g, const consts* c, const double* u, co
 {
     const double eps = 2.220446049250313e-16;
     int n = g->n;
-    double s = 0.0;
-    for (int i = 0; i < n; ++i)
+    double* plane = (double*)malloc((size_t)n * sizeof(double));
+#pragma omp parallel for schedule(static) if (n >= 32)
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
         for (int j = 0; j < n; ++j)
             for (int k = 0; k < n; ++k) {
                 double dL;
@@ -216,6 +260,10 @@ static double rounding_floor(const grid* g, const consts* c, const double* u, co
                 double fl = eps * (fabs(dL) * fabs(ui) + t);
                 s += fl * fl;
             }
+        plane[i] = s;
+    }
+    double s = sum_planes(plane, n);
+    free(plane);
     return sqrt(s / ((double)n * n * n));
 }
 
@@ -223,6 +271,7 @@ static double rounding_floor(const grid* g, const consts* c, const double* u, co
 static void restrict_mean(int n, const double* fine, double* coarse)
 {
     int nc = n / 2;
+#pragma omp parallel for schedule(static) if (nc >= 32)
     for (int I = 0; I < nc; ++I)
         for (int J = 0; J < nc; ++J)
             for (int K = 0; K < nc; ++K) {
@@ -254,6 +303,7 @@ static double coarse_val(int nc, const double* v, int periodic, int I, int J, in
 static void prolong_add(int nc, const double* v, int periodic, double* ufine)
 {
     int n = 2 * nc;
+#pragma omp parallel for schedule(static) if (n >= 32)
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j)
             for (int k = 0; k < n; ++k) {
@@ -321,6 +371,7 @@ static void vcycle(level* lv, int m, int nlev, const consts* c, const orc_opts* 
     restrict_mean(F->g.n, F->u, H->uhat);
     restrict_mean(F->g.n, F->d, H->f);
     /* FAS coarse equation L^H(u^H) = L^H(R u^h) - R d^h, started from R u^h */
+#pragma omp parallel for schedule(static) if (nc >= 32)
     for (int I = 0; I < nc; ++I)
         for (int J = 0; J < nc; ++J)
             for (int K = 0; K < nc; ++K) {
@@ -532,6 +583,7 @@ int orc_operator(int n, double h, const double* u, const double* rho, double rho
     consts c;
     if (derive(m, &c) != 0 || n < 1 || !u || !(h > 0.0)) return ORC_EINVAL;
     grid g = {n, h, c.ct * c.ct / (2.0 * h * h), ub, r, rho, rho_ref};
+#pragma omp parallel for schedule(static) if (n >= 32)
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j)
             for (int k = 0; k < n; ++k) {
@@ -551,9 +603,11 @@ int orc_operator_at(int n, double h, const double* u, const double* rho, double 
     if (derive(m, &c) != 0 || n < 1 || !u || !idx || !L || !(h > 0.0)) return ORC_EINVAL;
     grid g = {n, h, c.ct * c.ct / (2.0 * h * h), ub, r, rho, rho_ref};
     long long tot = (long long)n * n * n;
+    for (long long s = 0; s < ncell; ++s)
+        if (idx[s] < 0 || idx[s] >= tot) return ORC_EINVAL;
+#pragma omp parallel for schedule(static) if (ncell >= 4096)
     for (long long s = 0; s < ncell; ++s) {
         long long q = idx[s];
-        if (q < 0 || q >= tot) return ORC_EINVAL;
         int k = (int)(q % n), j = (int)((q / n) % n), i = (int)(q / ((long long)n * n));
         L[s] = cell_op(&g, &c, u, i, j, k, NULL);
     }
@@ -646,14 +700,17 @@ static double masked_op(const mgrid* g, const consts* c, const double* u, int i,
 static void masked_sweep(const mgrid* g, const consts* c, double* u, const double* f, double max_step)
 {
     int n = g->n;
+    for (long long q = 0; q < (long long)n * n * n; ++q)
+        if (g->mask[q] > 0.0) ++g_updates;
+    /* as ngs_sweep: the cells of one colour can be visited in any order */
     for (int colour = 0; colour < 2; ++colour)
+#pragma omp parallel for schedule(static) if (n >= 32)
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j)
                 for (int k = 0; k < n; ++k) {
                     if (((i + j + k) & 1) != colour) continue;
                     long long q = at(n, i, j, k);
                     if (!(g->mask[q] > 0.0)) continue;
-                    ++g_updates;
                     double d;
                     double L = masked_op(g, c, u, i, j, k, &d);
                     if (f) L -= f[q];
@@ -669,9 +726,11 @@ static double masked_residual(const mgrid* g, const consts* c, const double* u, 
                               double* d, long long* nact)
 {
     int n = g->n;
-    double s = 0.0;
+    double* plane = (double*)malloc((size_t)n * sizeof(double));
     long long na = 0;
-    for (int i = 0; i < n; ++i)
+#pragma omp parallel for schedule(static) if (n >= 32) reduction(+ : na)
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
         for (int j = 0; j < n; ++j)
             for (int k = 0; k < n; ++k) {
                 long long q = at(n, i, j, k);
@@ -684,6 +743,10 @@ static double masked_residual(const mgrid* g, const consts* c, const double* u, 
                 if (d) d[q] = v;
                 s += v * v;
             }
+        plane[i] = s;
+    }
+    double s = sum_planes(plane, n);
+    free(plane);
     if (nact) *nact = na;
     return s;
 }
@@ -710,9 +773,11 @@ static double masked_floor(const mlevel* L, const consts* c, const double* f)
     const double eps = 2.220446049250313e-16;
     const mgrid* g = &L->g;
     int n = g->n;
-    double s = 0.0;
+    double* plane = (double*)malloc((size_t)n * sizeof(double));
     long long na = 0;
-    for (int i = 0; i < n; ++i)
+#pragma omp parallel for schedule(static) if (n >= 32) reduction(+ : na)
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
         for (int j = 0; j < n; ++j)
             for (int k = 0; k < n; ++k) {
                 long long q = at(n, i, j, k);
@@ -737,6 +802,10 @@ static double masked_floor(const mlevel* L, const consts* c, const double* f)
                 s += fl * fl;
                 ++na;
             }
+        plane[i] = s;
+    }
+    double s = sum_planes(plane, n);
+    free(plane);
     return na > 0 ? sqrt(s / (double)na) : 0.0;
 }
 
@@ -775,6 +844,7 @@ static void masked_vcycle(mlevel* lv, int m, int nlev, const consts* c, const or
         }
     }
     /* FAS coarse equation at active coarse cells: L^H(u^H) = L^H(R u^h) - R d^h */
+#pragma omp parallel for schedule(static) if (nc >= 32)
     for (int I = 0; I < nc; ++I)
         for (int J = 0; J < nc; ++J)
             for (int K = 0; K < nc; ++K) {
@@ -876,6 +946,7 @@ int orc_masked_operator(int n, const double* u, const double* w, const double* m
     if (derive(m, &c) != 0 || n < 1 || !u || !w || !mask) return ORC_EINVAL;
     double h = 1.0 / n;
     mgrid g = {n, h, c.ct * c.ct / (2.0 * h * h), mask, w, rho, rho_ref};
+#pragma omp parallel for schedule(static) if (n >= 32)
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j)
             for (int k = 0; k < n; ++k) {

@@ -92,6 +92,11 @@ int orc_masked_operator(int n, const double* u, const double* w, const double* m
 /* Smoother cell visits (all levels) of the last solve; for timing reports only. */
 long long orc_last_cell_updates(void);
 
+/* Host threads the loops may use (OpenMP; 1 when built without it), and a new count (> 0).
+ * Results do not depend on it: sums are formed per plane and added in plane order. */
+int orc_threads(void);
+void orc_set_threads(int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,9 +1,18 @@
 // Host driver of the batched solves: refinement patches level by level (Sec. V, Sec. VI.B)
 // and many independent periodic boxes.  Every unit of a batch runs the same FAS V-cycle
-// (Sec. V.B.2) with its own size, constants and hierarchy; each phase of the cycle is one
-// launch over all units that take part in it, through a table of (unit grid, block) pairs.
-// After every cycle the per-unit residual norms come back to the host, and units that have
-// converged are switched off for the remaining cycles.
+// (Sec. V.B.2) with its own size, constants and hierarchy.
+//
+// Default engine (workgroup per unit, unit.hip): units of side <= opts.unit_n are solved
+// whole, every cycle and stop test, by one workgroup each, in one persistent launch that
+// takes them from a device queue (largest first).  Larger units run their fine levels as one
+// launch per phase over all of them, through a table of (unit grid, block) pairs, and the
+// rest of each V-cycle (levels of side <= unit_n) in one workgroup per unit; their stop tests
+// run on the device, and the host reads one word per chunk of cycles.  The two kinds run
+// concurrently on two streams.
+//
+// MGFR_PER_PHASE selects the earlier engine, kept as the baseline: every phase of every level
+// is one launch over all units, and after every cycle the per-unit residual norms come back
+// to the host, which switches converged units off for the remaining cycles.
 #include <algorithm>
 #include <cstring>
 
@@ -55,6 +64,28 @@ struct Plan {
     long long nblk_cells0 = 0;
 };
 
+// Launch-based depth of the large units (workgroup-per-unit engine): their grids at depth m
+// whose level m is larger than unit_n, and the units whose V-cycle continues in one
+// workgroup from level m + 1 (tails: (index of that level in the all-levels array, levels
+// from there)).
+struct UDepth {
+    Launch half_f, coarse_f, coarse_c, fine_f;
+    size_t tails = 0;
+    int ntail = 0;
+    bool deep = false;
+};
+
+struct UPlan {
+    std::vector<UDepth> depth;
+    size_t grids = 0, first = 0, nlev = 0, order = 0;  // all levels of all units; whole units in queue order
+    int nwhole = 0, nlarge = 0;
+    size_t ids = 0, ncell = 0;        // large units: unit index, finest cells
+    Launch cells0;                     // finest cells of the large units
+    size_t lfirst = 0, lcount = 0;     // their block ranges (for the fold)
+    size_t all_tails = 0;              // every large unit's tail (for the tail bases)
+    int nall_tails = 0;
+};
+
 // Blocks of `work(g)` items for each grid; grids listed in order, so each grid's blocks are
 // contiguous.
 template <class W>
@@ -85,12 +116,17 @@ struct Batch {
     const mgfr_opts* o;
     hipStream_t s;
     std::vector<Unit>& units;
+    bool phases = false;  // MGFR_PER_PHASE: the per-phase engine with host stop tests
+    int W = 16;           // workgroup-per-unit engine: units and levels of side <= W in one workgroup
     Plan plan;
+    UPlan up;
     char* dmeta = nullptr;
     int* dactive = nullptr;
     std::vector<int> active;
     double* dpartial = nullptr;
     double* dout = nullptr;
+    double* dhist = nullptr;  // workgroup-per-unit engine: per-unit histories on the device
+    int* dints = nullptr;     // ... per-unit cycles and status, the active count and the queue
     double* hout = nullptr;  // pinned: per-unit (sum d^2, max |d|) read back every cycle
     int* hact = nullptr;     // pinned: per-unit active flags uploaded every cycle
     std::vector<std::pair<void*, size_t>> owned;
@@ -264,9 +300,74 @@ struct Batch {
         plan.count = meta.add(count);
         plan.nunit = (int)units.size();
         plan.nblk_cells0 = plan.cells0.nblk;
+        if (!phases) build_units(meta);
         setup_offset = meta.bytes.size();
         meta_image = std::move(meta.bytes);
         return MGFR_OK;
+    }
+
+    // Tables of the workgroup-per-unit engine: every level of every unit in one array, the
+    // whole units in queue order (largest first), and the launch-based depths of the large
+    // units with the tails that start below each.
+    void build_units(Meta& meta)
+    {
+        std::vector<mgfr::BGrid> allg;
+        std::vector<int> first, nlev, order, ids;
+        std::vector<double> ncell;
+        for (size_t ui = 0; ui < units.size(); ++ui) {
+            first.push_back((int)allg.size());
+            nlev.push_back(units[ui].nlev);
+            for (const mgfr::BGrid& G : units[ui].g) allg.push_back(G);
+            if (units[ui].n <= W) {
+                order.push_back((int)ui);
+            } else {
+                ids.push_back((int)ui);
+                ncell.push_back((double)cells3(units[ui].g[0]));
+            }
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return units[a].n > units[b].n; });
+        up.grids = meta.add(allg);
+        up.first = meta.add(first);
+        up.nlev = meta.add(nlev);
+        up.order = meta.add(order);
+        up.nwhole = (int)order.size();
+        up.nlarge = (int)ids.size();
+        up.ids = meta.add(ids);
+        up.ncell = meta.add(ncell);
+        std::vector<mgfr::BGrid> g0;
+        for (int u : ids) g0.push_back(units[u].g[0]);
+        std::vector<int> lf, lc;
+        up.cells0 = table(meta, g0, [](const mgfr::BGrid& g) { return cells3(g); }, &lf, &lc);
+        up.lfirst = meta.add(lf);
+        up.lcount = meta.add(lc);
+        std::vector<int2> all_tails;
+        up.depth.clear();
+        for (int m = 0;; ++m) {
+            std::vector<mgfr::BGrid> f, cg;
+            std::vector<int2> tails;
+            for (int u : ids) {
+                const Unit& U = units[u];
+                if (m + 1 >= U.nlev || U.g[m].n <= W) continue;  // not launch-based at depth m
+                f.push_back(U.g[m]);
+                cg.push_back(U.g[m + 1]);
+                if (U.g[m + 1].n <= W) tails.push_back(make_int2(first[u] + m + 1, U.nlev - m - 1));
+            }
+            if (f.empty()) break;
+            UDepth D;
+            D.deep = true;
+            D.half_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 2; });
+            D.fine_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g); });
+            D.coarse_c = table(meta, cg, [](const mgfr::BGrid& g) { return cells3(g); });
+            D.coarse_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 8; });
+            D.coarse_f.other = D.coarse_c.grids;
+            D.fine_f.other = D.coarse_c.grids;
+            D.tails = meta.add(tails);
+            D.ntail = (int)tails.size();
+            all_tails.insert(all_tails.end(), tails.begin(), tails.end());
+            up.depth.push_back(D);
+        }
+        up.all_tails = meta.add(all_tails);
+        up.nall_tails = (int)all_tails.size();
     }
 
     std::vector<char> meta_image;
@@ -301,6 +402,10 @@ struct Batch {
         MGFR_TRY(upload_active());
         MGFR_TRY(alloc(&dpartial, 2 * (size_t)std::max<long long>(plan.nblk_cells0, 1)));
         MGFR_TRY(alloc(&dout, 2 * nu));
+        if (!phases) {
+            MGFR_TRY(alloc(&dhist, nu * (size_t)(o->max_cycles + 1)));
+            MGFR_TRY(alloc(&dints, 3 * nu + 2));  // cycles, status per unit; any; queue
+        }
         // the staging area must stay unchanged until the copies have run
         return hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize");
     }
@@ -397,13 +502,14 @@ struct Batch {
     }
 
     // ---- mixed precision: single-precision correction V-cycle, double-precision outer loop
-    // read ub, e and the right-hand side, write e
+    // credited 12 B per cell: e and the right-hand side read, e written (the fixed base ub,
+    // also read, is not counted)
     int sweep32(int m)
     {
         const Depth& D = plan.depth[m];
         MGFR_TRY(ev_begin(m));
         MGFR_TRY(hip_check(c, mgfr::batch_ngs32(tab(D.half_f), D.half_f.nblk, s), "batch_ngs32"));
-        return ev_end(m, 16.0);
+        return ev_end(m, 12.0);
     }
 
     int vcycle32(int m)
@@ -595,7 +701,247 @@ struct Batch {
         }
         return MGFR_OK;
     }
+
+    // ---- workgroup-per-unit engine ------------------------------------------------------------
+    mgfr::UnitSet uset() const
+    {
+        mgfr::UnitSet u;
+        u.grids = (const mgfr::BGrid*)(dmeta + up.grids);
+        u.first = (const int*)(dmeta + up.first);
+        u.nlev = (const int*)(dmeta + up.nlev);
+        u.order = (const int*)(dmeta + up.order);
+        u.nwhole = up.nwhole;
+        return u;
+    }
+    mgfr::UnitOut uout() const
+    {
+        const size_t nu = units.size();
+        return mgfr::UnitOut{dhist, dints, dints + nu, o->max_cycles + 1};
+    }
+    mgfr::UnitCfg ucfg() const
+    {
+        mgfr::UnitCfg f;
+        f.tol = o->tol;
+        f.rtol = o->coarsest_rtol;
+        f.pre = o->pre;
+        f.post = o->post;
+        f.max_cycles = o->max_cycles;
+        f.inner = o->inner_cycles;
+        f.cap = o->coarsest_sweeps;
+        return f;
+    }
+    int* dany() const { return dints + 2 * units.size(); }
+    int* dqueue() const { return dints + 2 * units.size() + 1; }
+    mgfr::BTable utab(const Launch& L) const
+    {
+        mgfr::BTable t;
+        t.grids = (const mgfr::BGrid*)(dmeta + L.grids);
+        t.blk = (const int2*)(dmeta + L.blk);
+        t.active = dactive;
+        return t;
+    }
+
+    // one V-cycle of the large units from depth m (double precision, or the single-precision
+    // correction cycle when mixed): launch-based phases while their level is larger than W,
+    // then one workgroup per unit for the rest
+    int uvcycle(int m, bool mixed)
+    {
+        const UDepth& D = up.depth[m];
+        const mgfr::BGrid* coarse = (const mgfr::BGrid*)(dmeta + D.coarse_f.other);
+        for (int k = 0; k < o->pre; ++k) MGFR_TRY(usweep(m, mixed));
+        if (mixed) {
+            MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict32(utab(D.coarse_f), D.coarse_f.nblk, coarse, s),
+                               "batch_resid_restrict32"));
+            MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs32(utab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs32"));
+        } else {
+            MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict(utab(D.coarse_f), D.coarse_f.nblk, coarse, s),
+                               "batch_resid_restrict"));
+            MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs(utab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs"));
+        }
+        if (D.ntail > 0)
+            MGFR_TRY(hip_check(c, mgfr::unit_tail(uset(), (const int2*)(dmeta + D.tails), D.ntail, dactive, ucfg(),
+                                                  mixed, s),
+                               "unit_tail"));
+        if ((size_t)m + 1 < up.depth.size()) MGFR_TRY(uvcycle(m + 1, mixed));
+        if (mixed) {
+            MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff32(utab(D.coarse_c), D.coarse_c.nblk, s),
+                               "batch_coarse_diff32"));
+            MGFR_TRY(hip_check(c, mgfr::batch_prolong_add32(utab(D.fine_f), D.fine_f.nblk, coarse, s),
+                               "batch_prolong_add32"));
+        } else {
+            MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff(utab(D.coarse_c), D.coarse_c.nblk, s), "batch_coarse_diff"));
+            MGFR_TRY(hip_check(c, mgfr::batch_prolong_add(utab(D.fine_f), D.fine_f.nblk, coarse, s),
+                               "batch_prolong_add"));
+        }
+        for (int k = 0; k < o->post; ++k) MGFR_TRY(usweep(m, mixed));
+        return MGFR_OK;
+    }
+
+    int usweep(int m, bool mixed)
+    {
+        const UDepth& D = up.depth[m];
+        const bool timed = m == 0 && (o->flags & MGFR_PROFILE) && !(o->flags & MGFR_GRAPH);
+        if (timed) MGFR_TRY(ev_begin(0));
+        if (mixed)
+            MGFR_TRY(hip_check(c, mgfr::batch_ngs32(utab(D.half_f), D.half_f.nblk, s), "batch_ngs32"));
+        else
+            MGFR_TRY(hip_check(c, mgfr::batch_ngs(utab(D.half_f), D.half_f.nblk, s), "batch_ngs"));
+        if (timed) {
+            MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
+            c->ev_used += 2;
+            c->stats.sweep_launches += 2;
+        }
+        return MGFR_OK;
+    }
+
+    // Stop test of the large units on the device: the residual (mixed: with the cast of the
+    // next right-hand side and base), its per-unit sums and the judge.
+    int ujudge(bool mixed, bool first)
+    {
+        const mgfr::BTable t = utab(up.cells0);
+        const int* lfirst = (const int*)(dmeta + up.lfirst);
+        const int* lcount = (const int*)(dmeta + up.lcount);
+        if (mixed) {
+            MGFR_TRY(hip_check(c, mgfr::batch_resid_cast(t, up.cells0.nblk, dpartial, s), "batch_resid_cast"));
+            MGFR_TRY(hip_check(c, mgfr::batch_fold(dpartial, lfirst, lcount, up.nlarge, dout, s), "batch_fold"));
+        } else {
+            MGFR_TRY(hip_check(c, mgfr::batch_norm(t, up.cells0.nblk, dpartial, lfirst, lcount, up.nlarge, dout, s),
+                               "batch_norm"));
+        }
+        return hip_check(c, mgfr::unit_judge(dout, (const int*)(dmeta + up.ids), (const double*)(dmeta + up.ncell),
+                                             up.nlarge, dactive, uout(), o->tol, o->max_cycles, first, dany(), s),
+                         "unit_judge");
+    }
+
+    // One cycle of the large units: a double-precision V-cycle, or (mixed) the coarse bases,
+    // inner_cycles single-precision V-cycles and u += e; then the device stop test.
+    int ucycle_body()
+    {
+        const bool mixed = o->precision == MGFR_MIXED;
+        if (mixed) {
+            for (size_t m = 0; m < up.depth.size(); ++m) {
+                const UDepth& D = up.depth[m];
+                MGFR_TRY(hip_check(c, mgfr::batch_restrict_base32(utab(D.coarse_f), D.coarse_f.nblk,
+                                                                  (const mgfr::BGrid*)(dmeta + D.coarse_f.other), s),
+                                   "batch_restrict_base32"));
+            }
+            MGFR_TRY(hip_check(c, mgfr::unit_tail_base32(uset(), (const int2*)(dmeta + up.all_tails), up.nall_tails,
+                                                         dactive, s),
+                               "unit_tail_base32"));
+            for (int it = 0; it < o->inner_cycles; ++it) MGFR_TRY(uvcycle(0, true));
+            MGFR_TRY(hip_check(c, mgfr::batch_add_correction(utab(up.cells0), up.cells0.nblk, s),
+                               "batch_add_correction"));
+        } else {
+            MGFR_TRY(uvcycle(0, false));
+        }
+        return ujudge(mixed, false);
+    }
+
+    int ucycle()
+    {
+        if (!(o->flags & MGFR_GRAPH)) return ucycle_body();
+        if (!gexec) {
+            MGFR_TRY(hip_check(c, hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking), "hipStreamCreate"));
+            hipStream_t caller = s;
+            s = cap_stream;
+            MGFR_TRY(hip_check(c, hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal),
+                               "hipStreamBeginCapture"));
+            const int st = ucycle_body();
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(cap_stream, &g);
+            s = caller;
+            graph = g;
+            MGFR_TRY(st);
+            MGFR_TRY(hip_check(c, e, "hipStreamEndCapture"));
+            MGFR_TRY(hip_check(c, hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate"));
+        }
+        return hip_check(c, hipGraphLaunch(gexec, s), "hipGraphLaunch");
+    }
+
+    // Number of large units still active (synchronises).
+    int read_any(int* any)
+    {
+        int* h = hact;
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(h, dany(), sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+        *any = *h;
+        return MGFR_OK;
+    }
+
+    // Solves every unit; histories, cycle counts and statuses come back once at the end.
+    int run_units(double* res_hist, int* n_hist, int* worst_status)
+    {
+        const bool mixed = o->precision == MGFR_MIXED;
+        const size_t nu = units.size();
+        const int H = o->max_cycles + 1;
+        c->ev_used = 0;
+        // whole units: one persistent launch on the side stream, beside the large units
+        if (up.nwhole > 0) {
+            MGFR_TRY(ensure_side(c));
+            MGFR_TRY(hip_check(c, hipEventRecord(c->ev_fork, s), "hipEventRecord"));
+            MGFR_TRY(hip_check(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "hipStreamWaitEvent"));
+            const int nwg = std::min(up.nwhole, 1024);
+            MGFR_TRY(hip_check(c, mgfr::unit_whole(uset(), dqueue(), uout(), ucfg(), mixed, nwg, c->side), "unit_whole"));
+            MGFR_TRY(hip_check(c, hipEventRecord(c->ev_join, c->side), "hipEventRecord"));
+        }
+        int cycles = 0;
+        if (up.nlarge > 0) {
+            MGFR_TRY(hip_check(c, mgfr::unit_fill_int(dactive, 1, (int)nu, s), "unit_fill_int"));
+            MGFR_TRY(ujudge(mixed, true));
+            int any = 0;
+            MGFR_TRY(read_any(&any));
+            while (any > 0 && cycles < o->max_cycles) {
+                // a chunk of cycles between host checks: units converge after several cycles,
+                // and the ones that have are switched off on the device
+                const int chunk = std::min(cycles == 0 ? 4 : 2, o->max_cycles - cycles);
+                for (int k = 0; k < chunk; ++k) MGFR_TRY(ucycle());
+                cycles += chunk;
+                MGFR_TRY(read_any(&any));
+            }
+        }
+        if (up.nwhole > 0) MGFR_TRY(hip_check(c, hipStreamWaitEvent(s, c->ev_join, 0), "hipStreamWaitEvent"));
+        // results: histories, then cycles and statuses, through the pinned staging buffer
+        const size_t hb = sizeof(double) * nu * H, ib = sizeof(int) * 2 * nu;
+        MGFR_TRY(ensure_pinned(c, hb + ib));
+        double* hh = (double*)c->pin;
+        int* hi = (int*)((char*)c->pin + hb);
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(hh, dhist, hb, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(hi, dints, ib, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+        MGFR_TRY(harvest());
+        *worst_status = MGFR_OK;
+        const int per = mixed ? o->inner_cycles : 1;
+        int maxk = 0;
+        for (size_t i = 0; i < nu; ++i) {
+            const int k = hi[i], st = hi[nu + i];
+            maxk = std::max(maxk, k);
+            if (res_hist) std::memcpy(res_hist + i * H, hh + i * H, sizeof(double) * (k + 1));
+            if (n_hist) n_hist[i] = k + 1;
+            if (st == 2) *worst_status = MGFR_ENONFINITE;
+            else if (st == 1 && *worst_status == MGFR_OK) *worst_status = MGFR_ENOTCONV;
+            const Unit& U = units[i];
+            for (int m = 0; m + 1 < U.nlev; ++m) {
+                const long long n3 = cells3(U.g[m]) * (o->pre + o->post) * (long long)k * per;
+                c->stats.cell_updates += n3;
+                if (m == 0) c->stats.finest_updates += n3;
+            }
+            if (U.n > W && (o->flags & MGFR_PROFILE) && !(o->flags & MGFR_GRAPH))
+                c->stats.sweep_bytes += (mixed ? 12.0 : 24.0) * (double)cells3(U.g[0]) * (o->pre + o->post) *
+                                        (double)k * per;
+        }
+        c->stats.cycles += maxk;
+        if (mixed) c->stats.inner_cycles += maxk * o->inner_cycles;
+        return MGFR_OK;
+    }
 };
+
+// Which engine a batch runs, and the side up to which the default one relaxes a unit in
+// one workgroup.
+void engine(Batch& b)
+{
+    b.phases = (b.o->flags & MGFR_PER_PHASE) != 0;
+    b.W = std::max(b.o->unit_n > 0 ? b.o->unit_n : 16, b.o->coarsest_n);
+}
 
 int check_batch_opts(mgfr_ctx* c, const mgfr_opts* o)
 {
@@ -687,6 +1033,7 @@ int mg_fr_solve_patches(mgfr_ctx* c, const double* u_domain, int N0, const mgfr_
             U.rho = rho_packed + P.offset;
         }
         Batch b{c, o, s, units};
+        engine(b);
         MGFR_TRY(b.prepare());
         // boundary set-up: interior initial guess and boundary faces from the parent level
         std::vector<mgfr::PatchParent> parents;
@@ -723,7 +1070,8 @@ int mg_fr_solve_patches(mgfr_ctx* c, const double* u_domain, int N0, const mgfr_
         std::vector<double> hist_level(ids.size() * H, 0.0);
         std::vector<int> nh_level(ids.size(), 0);
         int st = MGFR_OK;
-        MGFR_TRY(b.run(hist_level.data(), nh_level.data(), &st));
+        MGFR_TRY(b.phases ? b.run(hist_level.data(), nh_level.data(), &st)
+                          : b.run_units(hist_level.data(), nh_level.data(), &st));
         if (st == MGFR_ENONFINITE) worst = st;
         else if (st == MGFR_ENOTCONV && worst == MGFR_OK) worst = st;
         for (size_t i = 0; i < ids.size(); ++i) {
@@ -762,13 +1110,14 @@ int mg_fr_solve_batch(mgfr_ctx* c, int nbox, const int* N, const double* const* 
     MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
     hipStream_t s = (hipStream_t)stream;
     Batch bt{c, o, s, units};
+    engine(bt);
     MGFR_TRY(bt.prepare());
     MGFR_TRY(bt.upload());
     if (!(o->flags & MGFR_WARM_START))
         MGFR_TRY(hip_check(c, mgfr::batch_fill(bt.tab(bt.plan.cells0), bt.plan.cells0.nblk, s), "batch_fill"));
     MGFR_TRY(bt.check_finite());
     int st = MGFR_OK;
-    MGFR_TRY(bt.run(res_hist, n_hist, &st));
+    MGFR_TRY(bt.phases ? bt.run(res_hist, n_hist, &st) : bt.run_units(res_hist, n_hist, &st));
     c->stats.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (st == MGFR_ENONFINITE) return c->fail(st, "a box residual became non-finite");
     if (st == MGFR_ENOTCONV) return c->fail(st, "some boxes did not reach tol in max_cycles");

@@ -2,86 +2,16 @@
 //
 // Same batching as batch_fp64.hip (one launch per multigrid depth over every unit, a block
 // table of (unit grid, block) pairs, per-unit active flags), applied to the correction
-// equation N(e) = r of device_fp32.h.  On a patch, a ghost cell outside face f has the
-// double-precision value u_g = (1 - r) u_b + r u_i with u_b fixed (eq. u_i-1jk, r = -1 for a
-// cube patch).  Splitting u_i = ub_i + e_i, the ghost's base is (1 - r) u_b + r ub_i and its
-// correction r e_i, so the face term of N is
-//   (M_g + M_i)(ub_g - ub_i) + (B_g + B_i)(e_g - e_i),
-// the correction form of the face term of eq. bc_modified_fR_op, and its derivative in e_i
-//   (r B_g + B_i)(ub_g - ub_i + e_g - e_i) + (B_g + B_i)(r - 1).
-#include "device_fp32.h"
+// equation N(e) = r of device_fp32.h; the correction form of a patch's ghost faces is in
+// batch_dev.h.
+#include "batch_dev.h"
 
 namespace mgfr {
 namespace {
 
-using dev32::em1f;
-using dev32::make_v;
-using dev32::newton32;
-using dev32::Op32;
-using dev32::op32;
-using dev32::Res32;
-using dev32::V32;
+using namespace bdev;
 
 constexpr int kB = 256;
-constexpr float kR = -1.0f;  // ghost mask ratio of a cube patch
-
-__device__ __forceinline__ long long idx3(int lg, int i, int j, int k)
-{
-    return ((((long long)i << lg) + j) << lg) + k;
-}
-
-// boundary value u_b of face f next to cell (i, j, k), rounded to single precision
-__device__ __forceinline__ float face_ub32(const BGrid& g, int f, int i, int j, int k)
-{
-    int p, q;
-    if (f < 2) { p = j; q = k; }
-    else if (f < 4) { p = i; q = k; }
-    else { p = i; q = j; }
-    return (float)g.ub[((((long long)f << g.lg) + p) << g.lg) + q];
-}
-
-__device__ __forceinline__ bool live(const BTable& t, const BGrid& g) { return t.active == nullptr || t.active[g.unit]; }
-
-// N_i - f_i and dN_i/de_i of cell (i, j, k), base ub and correction e, ghost faces on the
-// outside of a patch.
-__device__ Res32 bcell32(const BGrid& g, const Op32& o, const float* __restrict__ ub, const float* __restrict__ e,
-                         int i, int j, int k, float f)
-{
-    const int m = g.n - 1;
-    const V32 c = make_v(ub[idx3(g.lg, i, j, k)], e[idx3(g.lg, i, j, k)]);
-    float t1 = 0.0f, t2 = 0.0f, su = 0.0f, se = 0.0f, sB = 0.0f, nreg = 0.0f, lgh = 0.0f, dgh = 0.0f;
-    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const int ii = i + di[q], jj = j + dj[q], kk = k + dk[q];
-        const bool out = ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m;
-        if (out && !g.periodic) {
-            const float ubg = (1.0f - kR) * face_ub32(g, q, i, j, k) + kR * c.ub;
-            const float eg = kR * c.e;
-            const float bg = __expf(ubg);
-            const float Mg = bg * em1f(eg), Bg = bg + Mg;
-            const float du = ubg - c.ub, de = eg - c.e;
-            lgh += (Mg + c.M) * du + (Bg + c.B) * de;
-            dgh += (kR * Bg + c.B) * (du + de) + (Bg + c.B) * (kR - 1.0f);
-        } else {
-            const long long qn = idx3(g.lg, ii & m, jj & m, kk & m);
-            const V32 nb = make_v(ub[qn], e[qn]);
-            const float du = nb.ub - c.ub, de = nb.e - c.e;
-            t1 = fmaf(nb.M, du, t1);
-            t2 = fmaf(nb.B, de, t2);
-            su += du;
-            se += de;
-            sB += nb.B;
-            nreg += 1.0f;
-        }
-    }
-    const float S = o.A * __expf(-c.ub * o.inv_np1);
-    const float x = em1f(-c.e * o.inv_np1);
-    Res32 r;
-    r.N = o.C * (fmaf(c.M, su, t1) + fmaf(c.B, se, t2) + lgh) + S * x - f;
-    r.dN = o.C * (c.B * (su + se) - sB - nreg * c.B + dgh) - S * o.inv_np1 * (1.0f + x);
-    return r;
-}
 
 // ---- smoother: one colour per launch, one thread per cell of that colour ------------------
 __global__ void __launch_bounds__(kB) kb32_ngs(BTable t, int colour)
@@ -194,126 +124,14 @@ __global__ void __launch_bounds__(kB) kb32_prolong_add(BTable t, const BGrid* __
 }
 
 // ---- coarsest level: one workgroup per grid (n <= 8) --------------------------------------
-// Everything that depends only on the base stays in LDS for the whole solve: ub, b = exp(ub),
-// the curvature coefficient S, and per ghost face ub_g - ub_i and b_g; per sweep only the
-// correction-dependent parts (M, B) of the updated cells are recomputed.  The arithmetic is
-// that of bcell32, in the same order.
 template <int NT>
 __global__ void __launch_bounds__(NT) kb32_coarsest(const BGrid* __restrict__ grids, const int* __restrict__ active,
                                                    int cap, float rtol)
 {
-    __shared__ float sub[512], sb[512], se[512], sB[512], sM[512], sf[512], sS[512];
-    __shared__ float gdu[6][512], gbb[6][512];
-    __shared__ float ra[NT], rb[NT];
+    __shared__ Coarse32<NT> sm;
     const BGrid g = grids[blockIdx.x];
     if (active && !active[g.unit]) return;
-    const Op32 o = op32(g);
-    const int nc = 1 << (3 * g.lg), m = g.n - 1;
-    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
-    auto ghost = [&](int q, int f) {
-        const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
-        const int ii = i + di[f], jj = j + dj[f], kk = k + dk[f];
-        return !g.periodic && (ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m);
-    };
-    for (int q = threadIdx.x; q < nc; q += NT) {
-        const V32 v = make_v(g.ub32[q], g.e32[q]);
-        sub[q] = v.ub;
-        sb[q] = __expf(v.ub);
-        se[q] = v.e;
-        sB[q] = v.B;
-        sM[q] = v.M;
-        sf[q] = g.f32[q];
-        sS[q] = o.A * __expf(-v.ub * o.inv_np1);
-        const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
-        for (int f = 0; f < 6; ++f) {
-            gdu[f][q] = 0.0f;
-            gbb[f][q] = 0.0f;
-            if (ghost(q, f)) {
-                const float ubg = (1.0f - kR) * face_ub32(g, f, i, j, k) + kR * v.ub;
-                gdu[f][q] = ubg - v.ub;
-                gbb[f][q] = __expf(ubg);
-            }
-        }
-    }
-    __syncthreads();
-    auto cell = [&](int q, float& dN) -> float {
-        const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
-        const float cub = sub[q], ce = se[q], cB = sB[q], cM = sM[q];
-        float t1 = 0.0f, t2 = 0.0f, su = 0.0f, sE = 0.0f, sBn = 0.0f, nreg = 0.0f, lgh = 0.0f, dgh = 0.0f;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            if (ghost(q, f)) {
-                const float eg = kR * ce;
-                const float bg = gbb[f][q];
-                const float Mg = bg * em1f(eg), Bg = bg + Mg;
-                const float du = gdu[f][q], de = eg - ce;
-                lgh += (Mg + cM) * du + (Bg + cB) * de;
-                dgh += (kR * Bg + cB) * (du + de) + (Bg + cB) * (kR - 1.0f);
-            } else {
-                const int qn = (((i + di[f]) & m) << (2 * g.lg)) + (((j + dj[f]) & m) << g.lg) + ((k + dk[f]) & m);
-                const float du = sub[qn] - cub, de = se[qn] - ce;
-                t1 = fmaf(sM[qn], du, t1);
-                t2 = fmaf(sB[qn], de, t2);
-                su += du;
-                sE += de;
-                sBn += sB[qn];
-                nreg += 1.0f;
-            }
-        }
-        const float S = sS[q];
-        const float x = em1f(-ce * o.inv_np1);
-        dN = o.C * (cB * (su + sE) - sBn - nreg * cB + dgh) - S * o.inv_np1 * (1.0f + x);
-        return o.C * (fmaf(cM, su, t1) + fmaf(cB, sE, t2) + lgh) + S * x - sf[q];
-    };
-    // rms of N - f and its single-precision rounding floor (|dN||e| + |f|)
-    auto rms = [&](float& floor) {
-        float s = 0.0f, fl = 0.0f;
-        for (int q = threadIdx.x; q < nc; q += NT) {
-            float dN;
-            const float N = cell(q, dN);
-            s += N * N;
-            const float f1 = 1.1920929e-7f * (fabsf(dN) * fabsf(se[q]) + fabsf(sf[q]));
-            fl += f1 * f1;
-        }
-        ra[threadIdx.x] = s;
-        rb[threadIdx.x] = fl;
-        __syncthreads();
-        for (int w = NT / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) {
-                ra[threadIdx.x] += ra[threadIdx.x + w];
-                rb[threadIdx.x] += rb[threadIdx.x + w];
-            }
-            __syncthreads();
-        }
-        const float tot = ra[0], tf = rb[0];
-        __syncthreads();
-        floor = sqrtf(tf / nc);
-        return sqrtf(tot / nc);
-    };
-    float fl0;
-    const float r0 = rtol > 0.0f ? rms(fl0) : 0.0f;
-    for (int sweep = 0; sweep < cap; ++sweep) {
-        if (rtol > 0.0f) {
-            float fl;
-            const float r = rms(fl);
-            if (r <= rtol * r0 || r <= fl) break;
-        }
-        for (int colour = 0; colour < 2; ++colour) {
-            for (int q = threadIdx.x; q < nc; q += NT) {
-                const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
-                if (((i + j + k) & 1) != colour) continue;
-                Res32 r;
-                r.N = cell(q, r.dN);
-                const float e = se[q] + newton32(r, o.max_step);
-                const float M = sb[q] * em1f(e);
-                se[q] = e;
-                sM[q] = M;
-                sB[q] = sb[q] + M;
-            }
-            __syncthreads();
-        }
-    }
-    for (int q = threadIdx.x; q < nc; q += NT) g.e32[q] = se[q];
+    coarsest32<NT>(g, cap, rtol, sm);
 }
 
 }  // namespace

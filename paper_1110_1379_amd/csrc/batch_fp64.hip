@@ -3,73 +3,16 @@
 // depth.  A block table maps each workgroup to (unit grid, block within that grid); units
 // whose solve has converged are switched off through a per-unit flag and their workgroups
 // return at once.
-//
-// A patch is a cube of active cells whose outside neighbours are ghost cells (Sec. V): for a
-// ghost with mask ratio r = m_ghost/m_i = -1 (all cells of a cube patch are active) the ghost
-// value is u_g = u_b - r u_b + r u_i = 2 u_b - u_i with the boundary value u_b fixed before
-// the relaxation (eq. u_i-1jk), b_g = exp(u_g) (not interpolated), and the face term of
-// eq. bc_modified_fR_op is C (b_g + b_i)(u_g - u_i).  A box is periodic.
-#include "device_fp64.h"
+// The cell operator of a unit grid (cube patch with ghost faces, or periodic box) is in
+// batch_dev.h.
+#include "batch_dev.h"
 
 namespace mgfr {
 namespace {
 
 constexpr int kB = 256;
-constexpr double kR = -1.0;  // ghost mask ratio of a cube patch
 
-using dev::OpVal;
-
-__device__ __forceinline__ long long idx3(int lg, int i, int j, int k)
-{
-    return ((((long long)i << lg) + j) << lg) + k;
-}
-
-__device__ __forceinline__ double face_ub(const BGrid& g, int f, int i, int j, int k)
-{
-    int p, q;
-    if (f < 2) { p = j; q = k; }
-    else if (f < 4) { p = i; q = k; }
-    else { p = i; q = j; }
-    return g.ub[((((long long)f << g.lg) + p) << g.lg) + q];
-}
-
-// L_i - f_i and dL_i/du_i with ghost faces on the outside of a patch.
-__device__ OpVal bcell(const BGrid& g, const double* __restrict__ u, int i, int j, int k, double f)
-{
-    const int n = g.n, m = n - 1;
-    const double ui = u[idx3(g.lg, i, j, k)];
-    const double bi = exp(ui);
-    double su = 0.0, sb = 0.0, sbu = 0.0, lg_ = 0.0, dlg = 0.0;
-    int nreg = 0;
-    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        int ii = i + di[q], jj = j + dj[q], kk = k + dk[q];
-        const bool out = ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m;
-        if (out && !g.periodic) {
-            const double ug = (1.0 - kR) * face_ub(g, q, i, j, k) + kR * ui;
-            const double bg = exp(ug);
-            lg_ += (bg + bi) * (ug - ui);
-            dlg += (kR * bg + bi) * (ug - ui) + (bg + bi) * (kR - 1.0);
-        } else {
-            const double un = u[idx3(g.lg, ii & m, jj & m, kk & m)];
-            const double bn = exp(un), du = un - ui;
-            su += du;
-            sb += bn;
-            sbu = fma(bn, du, sbu);
-            ++nreg;
-        }
-    }
-    const double S = g.A * exp(-ui * g.inv_np1);
-    OpVal r;
-    r.L = g.C * (fma(bi, su, sbu) + lg_) + S - f;
-    r.dL = g.C * (fma(bi, su, -sb) - nreg * bi + dlg) - S * g.inv_np1;
-    return r;
-}
-
-__device__ __forceinline__ double brhs(const BGrid& g, long long q) { return fma(g.fscale, g.src[q] - g.sref, g.fshift); }
-
-__device__ __forceinline__ bool live(const BTable& t, const BGrid& g) { return t.active == nullptr || t.active[g.unit]; }
+using namespace bdev;
 
 // ---- smoother ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kB) kb_ngs(BTable t, int colour)
@@ -163,106 +106,14 @@ __global__ void __launch_bounds__(kB) kb_prolong_add(BTable t, const BGrid* __re
 }
 
 // ---- coarsest level: one workgroup per grid (n <= 8) --------------------------------------
-// b = exp(u) and the curvature term S of every cell stay in LDS and are refreshed when the
-// cell is updated, so a visit evaluates exponentials only for its ghost faces.  The
-// arithmetic is that of bcell, in the same order.
 template <int NT>
 __global__ void __launch_bounds__(NT) kb_coarsest(const BGrid* __restrict__ grids, const int* __restrict__ active,
                                                  int cap, double rtol)
 {
-    __shared__ double su[512], sb[512], sS[512], sf[512];
-    __shared__ double ra[NT], rb[NT];
+    __shared__ Coarse64<NT> sm;
     const BGrid g = grids[blockIdx.x];
     if (active && !active[g.unit]) return;
-    const int nc = 1 << (3 * g.lg), m = g.n - 1;
-    for (int q = threadIdx.x; q < nc; q += NT) {
-        su[q] = g.u[q];
-        sb[q] = exp(su[q]);
-        sS[q] = g.A * exp(-su[q] * g.inv_np1);
-        sf[q] = brhs(g, q);
-    }
-    __syncthreads();
-    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
-    auto cell = [&](int q) -> OpVal {
-        const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
-        const double ui = su[q], bi = sb[q];
-        double s_u = 0.0, s_b = 0.0, sbu = 0.0, lg_ = 0.0, dlg = 0.0;
-        int nreg = 0;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            const int ii = i + di[f], jj = j + dj[f], kk = k + dk[f];
-            const bool out = ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m;
-            if (out && !g.periodic) {
-                const double ug = (1.0 - kR) * face_ub(g, f, i, j, k) + kR * ui;
-                const double bg = exp(ug);
-                lg_ += (bg + bi) * (ug - ui);
-                dlg += (kR * bg + bi) * (ug - ui) + (bg + bi) * (kR - 1.0);
-            } else {
-                const int qn = ((ii & m) << (2 * g.lg)) + ((jj & m) << g.lg) + (kk & m);
-                const double bn = sb[qn], du = su[qn] - ui;
-                s_u += du;
-                s_b += bn;
-                sbu = fma(bn, du, sbu);
-                ++nreg;
-            }
-        }
-        const double S = sS[q];
-        OpVal r;
-        r.L = g.C * (fma(bi, s_u, sbu) + lg_) + S - sf[q];
-        r.dL = g.C * (fma(bi, s_u, -s_b) - nreg * bi + dlg) - S * g.inv_np1;
-        return r;
-    };
-    auto reduce = [&](double a, double b, double& ta, double& tb) {
-        ra[threadIdx.x] = a;
-        rb[threadIdx.x] = b;
-        __syncthreads();
-        for (int w = NT / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) {
-                ra[threadIdx.x] += ra[threadIdx.x + w];
-                rb[threadIdx.x] += rb[threadIdx.x + w];
-            }
-            __syncthreads();
-        }
-        ta = ra[0];
-        tb = rb[0];
-        __syncthreads();
-    };
-    // rms of L - f and its rounding floor (one unit in the last place of |dL||u| + |f| + S)
-    auto rms = [&](double& floor) {
-        double s = 0.0, fl = 0.0;
-        for (int q = threadIdx.x; q < nc; q += NT) {
-            const OpVal r = cell(q);
-            s += r.L * r.L;
-            const double f1 = 2.220446049250313e-16 * (fabs(r.dL) * fabs(su[q]) + fabs(sf[q]) + sS[q]);
-            fl += f1 * f1;
-        }
-        double ts, tf;
-        reduce(s, fl, ts, tf);
-        floor = sqrt(tf / nc);
-        return sqrt(ts / nc);
-    };
-    double fl0;
-    const double r0 = rtol > 0.0 ? rms(fl0) : 0.0;
-    for (int sweep = 0; sweep < cap; ++sweep) {
-        if (rtol > 0.0) {
-            double fl;
-            const double r = rms(fl);
-            if (r <= rtol * r0 || r <= fl) break;
-        }
-        for (int colour = 0; colour < 2; ++colour) {
-            for (int q = threadIdx.x; q < nc; q += NT) {
-                const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
-                if (((i + j + k) & 1) != colour) continue;
-                const OpVal r = cell(q);
-                const double u = su[q] + dev::bounded(-r.L / r.dL, g.max_step);
-                su[q] = u;
-                sb[q] = exp(u);
-                sS[q] = g.A * exp(-u * g.inv_np1);
-            }
-            __syncthreads();
-        }
-    }
-    for (int q = threadIdx.x; q < nc; q += NT) g.u[q] = su[q];
+    coarsest64<NT>(g, cap, rtol, sm);
 }
 
 // ---- per-grid residual norms -------------------------------------------------------------

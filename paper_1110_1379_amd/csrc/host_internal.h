@@ -159,6 +159,30 @@ struct mgfr_ctx {
         spare.clear();
     }
     long long* counter = nullptr;  // device: coarsest-level sweeps of the current solve
+    // batched solves: a second stream (default priority) for the workgroup-per-unit kernel
+    // beside the launches of the large units, and the events that fork and join it
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // mg_fr_solve with MGFR_GRAPH: the captured cycles (graph, instance and what they were
+    // captured for), the stream they were captured on, the device stop state (cycles done,
+    // stopped) and residual history, and what one captured cycle adds to the counters
+    hipGraph_t dgraph = nullptr;
+    hipGraphExec_t dgexec = nullptr;
+    std::vector<char> dkey;
+    hipStream_t dcap = nullptr;
+    int* gstate = nullptr;
+    double* ghist = nullptr;
+    int ghist_n = 0;
+    long long dper_updates = 0, dper_finest = 0;
+    int dper_inner = 0;
+    void drop_graph()
+    {
+        if (dgexec) (void)hipGraphExecDestroy(dgexec);
+        if (dgraph) (void)hipGraphDestroy(dgraph);
+        dgexec = nullptr;
+        dgraph = nullptr;
+        dkey.clear();
+    }
     mgfr_stats stats{};
     // MGFR_PROFILE: event pairs around finest-level smoother launches
     std::vector<hipEvent_t> ev;
@@ -175,8 +199,10 @@ struct mgfr_ctx {
         return code;
     }
 
+    // (the level buffers are in a captured graph's kernel arguments: it goes with them)
     void free_levels()
     {
+        drop_graph();
         for (size_t m = 0; m < lv.size(); ++m) {
             if (m > 0) {
                 (void)hipFree(lv[m].u);
@@ -191,6 +217,7 @@ struct mgfr_ctx {
 
     void free_levels32()
     {
+        drop_graph();
         for (mgfr_host::Level32& L : lv32) {
             (void)hipFree(L.ub);
             (void)hipFree(L.e);
@@ -224,7 +251,7 @@ inline int check_opts(mgfr_ctx* c, const mgfr_opts* o)
         !is_pow2(o->coarsest_n) || o->coarsest_n < 2 || o->coarsest_n > 8 || !(o->max_step >= 0.0) ||
         !(o->coarsest_rtol >= 0.0) || (o->precision != MGFR_FP64 && o->precision != MGFR_MIXED) ||
         o->inner_cycles < 1 || o->planes < 0 || (o->planes > 0 && (!is_pow2(o->planes) || o->planes < 4)) ||
-        !(o->tau_alpha >= 0.0))
+        !(o->tau_alpha >= 0.0) || o->unit_n < 0 || o->unit_n > 1024 || o->tile < 0 || o->tile > 4)
         return c->fail(MGFR_EINVAL, "invalid options (tol=%g pre=%d post=%d coarsest_n=%d precision=%d)",
                        o->tol, o->pre, o->post, o->coarsest_n, o->precision);
     return MGFR_OK;
@@ -243,6 +270,7 @@ inline mgfr::Grid make_grid(const Model& md, int n, double h, double max_step)
     g.fscale = 1.0;
     g.sref = 0.0;
     g.fshift = 0.0;
+    g.halt = nullptr;
     return g;
 }
 
@@ -264,6 +292,24 @@ inline int ensure_scratch(mgfr_ctx* c)
     if (!c->counter && hipMalloc(&c->counter, sizeof(long long)) != hipSuccess) {
         c->counter = nullptr;
         return c->fail(MGFR_ENOMEM, "hipMalloc of the sweep counter failed");
+    }
+    return MGFR_OK;
+}
+
+// The side stream and its fork/join events (created once per context).
+inline int ensure_side(mgfr_ctx* c)
+{
+    if (!c->side && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+        c->side = nullptr;
+        return c->fail(MGFR_EDEVICE, "hipStreamCreate failed");
+    }
+    if (!c->ev_fork && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        c->ev_fork = nullptr;
+        return c->fail(MGFR_EDEVICE, "hipEventCreate failed");
+    }
+    if (!c->ev_join && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        c->ev_join = nullptr;
+        return c->fail(MGFR_EDEVICE, "hipEventCreate failed");
     }
     return MGFR_OK;
 }

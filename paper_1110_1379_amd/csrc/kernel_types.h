@@ -21,6 +21,7 @@ struct Grid {
     int half_power;   // 1 when n_HS = 1: exp(-u/2) is taken as 1/sqrt(exp(u))
     double max_step;  // > 0: bound on |Newton step|
     double fscale, sref, fshift;
+    const int* halt;  // device flag, or null: when it is set the kernels of a level return at once
 };
 
 inline long long cells(const Grid& g) { return 1LL << (3 * g.lg); }

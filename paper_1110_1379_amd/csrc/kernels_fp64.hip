@@ -39,6 +39,7 @@ __device__ __forceinline__ void load_nbrs(const Grid& g, const double* u, int i,
 __global__ void __launch_bounds__(kBlock) k_ngs_colour(Grid g, double* __restrict__ u,
                                                        const double* __restrict__ src, int colour)
 {
+    if (g.halt && *g.halt) return;
     const long long half = 1LL << (3 * g.lg - 1);
     const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= half) return;
@@ -62,6 +63,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(Grid g, const double*
                                                            double* __restrict__ uhat,
                                                            double* __restrict__ fc)
 {
+    if (g.halt && *g.halt) return;
     const int lgc = g.lg - 1, nc = g.n >> 1;
     const long long tc = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (tc >= (1LL << (3 * lgc))) return;
@@ -89,6 +91,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(Grid g, const double*
 __global__ void __launch_bounds__(kBlock) k_fas_rhs(Grid g, const double* __restrict__ uhat,
                                                     double* __restrict__ f)
 {
+    if (g.halt && *g.halt) return;
     const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (q >= (1LL << (3 * g.lg))) return;
     const int i = (int)(q >> (2 * g.lg)), j = (int)((q >> g.lg) & (g.n - 1)), k = (int)(q & (g.n - 1));
@@ -166,6 +169,7 @@ __global__ void __launch_bounds__(kBlock) k_coarsest(Grid g, double* __restrict_
                                                      const double* __restrict__ src, int cap,
                                                      double rtol, long long* __restrict__ sweeps_done)
 {
+    if (g.halt && *g.halt) return;
     __shared__ double su[512];
     __shared__ double sf[512];
     __shared__ double rs[kBlock], rm[kBlock];
@@ -250,6 +254,7 @@ __global__ void __launch_bounds__(kBlock) k_residual_partial(Grid g, const doubl
                                                              const double* __restrict__ src,
                                                              double* __restrict__ partial)
 {
+    if (g.halt && *g.halt) return;
     __shared__ double rs[kBlock], rm[kBlock];
     const long long ncell = 1LL << (3 * g.lg);
     double s = 0.0, mx = 0.0;
@@ -309,8 +314,9 @@ __global__ void __launch_bounds__(kBlock) k_fold(const double* __restrict__ part
 }
 
 __global__ void __launch_bounds__(kBlock) k_add_correction(double* __restrict__ u, const float* __restrict__ e,
-                                                           long long n)
+                                                           long long n, const int* __restrict__ halt)
 {
+    if (halt && *halt) return;
     for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock)
         u[q] += (double)e[q];
 }
@@ -319,6 +325,7 @@ __global__ void __launch_bounds__(kBlock) k_residual_cast(Grid g, const double* 
                                                           const double* __restrict__ src, float* __restrict__ r32,
                                                           float* __restrict__ ub32, double* __restrict__ partial)
 {
+    if (g.halt && *g.halt) return;
     __shared__ double rs[kBlock], rm[kBlock];
     const long long ncell = 1LL << (3 * g.lg);
     double s = 0.0, mx = 0.0;
@@ -344,6 +351,26 @@ __global__ void __launch_bounds__(kBlock) k_fill(double* __restrict__ x, double 
 {
     for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock)
         x[q] = v;
+}
+
+// Stop test of a domain solve captured in a graph: red[0] holds the sum of d^2 over the
+// finest cells after a cycle.  Unless the solve has stopped (state[1] set), count the cycle
+// (state[0]), store rms(d) in hist, and stop when rms is not above tol, non-finite, or the
+// cycle cap is reached.  One thread.
+__global__ void k_domain_stop(const double* __restrict__ red, long long ncell, double tol, int max_cycles,
+                              double* __restrict__ hist, int* __restrict__ state)
+{
+    if (threadIdx.x != 0 || state[1]) return;
+    const double rms = sqrt(red[0] / (double)ncell);
+    const int k = state[0] + 1;
+    state[0] = k;
+    hist[k] = rms;
+    if (!isfinite(rms) || !(rms > tol) || k >= max_cycles) state[1] = 1;
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int v, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = v;
 }
 
 inline unsigned blocks_for(long long work)
@@ -416,9 +443,9 @@ hipError_t sum_and_count_nonfinite(const double* x, long long n, double* partial
     return hipGetLastError();
 }
 
-hipError_t add_correction(double* u, const float* e, long long n, hipStream_t s)
+hipError_t add_correction(double* u, const float* e, long long n, hipStream_t s, const int* halt)
 {
-    hipLaunchKernelGGL(k_add_correction, dim3(reduction_blocks(n)), dim3(kBlock), 0, s, u, e, n);
+    hipLaunchKernelGGL(k_add_correction, dim3(reduction_blocks(n)), dim3(kBlock), 0, s, u, e, n, halt);
     return hipGetLastError();
 }
 
@@ -440,6 +467,20 @@ hipError_t fold_partials(const double* partial, int nb, double* out, hipStream_t
 hipError_t fill(double* x, double v, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill, dim3(reduction_blocks(n)), dim3(kBlock), 0, s, x, v, n);
+    return hipGetLastError();
+}
+
+hipError_t domain_stop(const double* red, long long ncell, double tol, int max_cycles, double* hist, int* state,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_domain_stop, dim3(1), dim3(64), 0, s, red, ncell, tol, max_cycles, hist, state);
+    return hipGetLastError();
+}
+
+hipError_t fill_int(int* p, int v, int n, hipStream_t s)
+{
+    if (n > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, p, v, n);
     return hipGetLastError();
 }
 

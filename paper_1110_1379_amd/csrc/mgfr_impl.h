@@ -99,6 +99,32 @@ struct BTable {
     const int* active;  // per-unit flags, or null (all active)
 };
 
+// Every unit of a batch for the workgroup-per-unit kernels: the descriptors of all levels of
+// all units (unit by unit, finest first), where each unit's start, how many levels it has,
+// and the units solved whole by one workgroup in the order the queue hands them out.
+struct UnitSet {
+    const BGrid* grids;
+    const int* first;
+    const int* nlev;
+    const int* order;
+    int nwhole;
+};
+
+// Per-unit results on the device: residual history (H doubles per unit), cycles done, and
+// status (0 converged, 1 not converged, 2 non-finite).
+struct UnitOut {
+    double* hist;
+    int* ncyc;
+    int* status;
+    int H;
+};
+
+// Solver settings the workgroup-per-unit kernels need.
+struct UnitCfg {
+    double tol, rtol;
+    int pre, post, max_cycles, inner, cap;
+};
+
 // Parent of a patch for the boundary set-up: the parent level's u (side n, periodic for the
 // domain grid), its origin in parent-level cells, and the child's origin in child cells.
 struct PatchParent {
@@ -125,6 +151,23 @@ hipError_t batch_setup(const BTable& t, int nblk, const PatchParent* parents, hi
 hipError_t batch_restrict_faces(const BTable& t, int nblk, const BGrid* fine, hipStream_t s);
 hipError_t batch_fill(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_nonfinite(const BTable& t, int nblk, double* partial, hipStream_t s);
+
+// ---- workgroup-per-unit kernels (unit.hip) ------------------------------------------------
+int unit_block();
+// Every whole unit of us solved completely, nwg persistent workgroups taking units from the
+// device counter *queue (reset here); results into out.
+hipError_t unit_whole(const UnitSet& us, int* queue, const UnitOut& out, const UnitCfg& cfg, bool mixed, int nwg,
+                      hipStream_t s);
+// One workgroup per tails[b] = (index of a large unit's tail level in us.grids, levels from
+// there): the rest of its V-cycle (single-precision correction cycle when mixed).
+hipError_t unit_tail(const UnitSet& us, const int2* tails, int ntail, const int* active, const UnitCfg& cfg,
+                     bool mixed, hipStream_t s);
+// Coarse bases R ub of the tail levels (from each tail level down).
+hipError_t unit_tail_base32(const UnitSet& us, const int2* tails, int ntail, const int* active, hipStream_t s);
+// Device-side stop test of the large units after a cycle (first: before the first cycle).
+hipError_t unit_judge(const double* sums, const int* ids, const double* ncell, int nl, int* active, const UnitOut& out,
+                      double tol, int max_cycles, bool first, int* any, hipStream_t s);
+hipError_t unit_fill_int(int* p, int v, int n, hipStream_t s);
 
 // ---- batched mixed-precision solves (batch_fp32.hip; the double-precision parts in
 // batch_fp64.hip) ------------------------------------------------------------------------------
@@ -191,8 +234,10 @@ hipError_t fill(double* x, double v, long long n, hipStream_t s);
 int fused_sweep_min_n();
 int fused_sweep_planes(int n);
 
-// One red-black sweep from uin into uout (distinct arrays).
-hipError_t ngs_sweep_fused(const Grid& g, const double* uin, double* uout, const double* src, int ti,
+// One red-black sweep from uin into uout (distinct arrays), on 16 x 64 tiles (kTile64x16x64)
+// or 8 x 64 tiles (kTile64x8x64).
+constexpr int kTile64x16x64 = 1, kTile64x8x64 = 2;
+hipError_t ngs_sweep_fused(const Grid& g, const double* uin, double* uout, const double* src, int ti, int tile,
                            hipStream_t s);
 
 // ---- streaming residual (resid_fp64.hip), n >= 64 --------------------------------------
@@ -201,8 +246,13 @@ long long resid_stream_blocks(int n);
 hipError_t resid_stream(const Grid& g, const double* uin, const double* src, ResidStream a, hipStream_t s);
 
 // ---- small-grid helpers of the mixed loop (kernels_fp64.hip) ----------------------------
-// u += e (single-precision correction).
-hipError_t add_correction(double* u, const float* e, long long n, hipStream_t s);
+// u += e (single-precision correction); nothing once *halt is set (halt may be null).
+hipError_t add_correction(double* u, const float* e, long long n, hipStream_t s, const int* halt = nullptr);
+// Stop test of a graph-captured domain solve (red[0] = sum of d^2 after a cycle; state = {cycles
+// done, stopped}), and a fill of up to 64 ints, both single-workgroup kernels.
+hipError_t domain_stop(const double* red, long long ncell, double tol, int max_cycles, double* hist, int* state,
+                       hipStream_t s);
+hipError_t fill_int(int* p, int v, int n, hipStream_t s);
 // r = -d, ub = u in single precision, and block partials of (sum d^2, max |d|) folded into
 // out[0..1].
 hipError_t residual_cast(const Grid& g, const double* u, const double* src, float* r32, float* ub32,
@@ -217,8 +267,12 @@ int tau_finish(const Grid& g, const double* rho, const double* fH, double* tau, 
 
 // ---- single-precision correction multigrid (kernels_fp32.hip) --------------------------
 hipError_t ngs_sweep32(const Grid& g, const float* ub, float* e, const float* f, hipStream_t s);
+// Tiles of the single-precision fused sweep: one tile column pair per thread on 16 x 32,
+// 32 x 32 or 16 x 64 tiles (the last two: 512 threads), or the 8 x 32 tile whose pairs cover
+// the tile and its halo.
+constexpr int kTile16x32 = 1, kTile32x32 = 2, kTile16x64 = 3, kTile32Paired = 4;
 hipError_t ngs_sweep32_fused(const Grid& g, const float* ub, const float* ein, float* eout, const float* f,
-                             int ti, hipStream_t s);
+                             int ti, int tile, hipStream_t s);
 hipError_t resid_restrict32(const Grid& g, const float* ub, const float* e, const float* f, float* ec,
                             float* ehat, float* fc, hipStream_t s);
 hipError_t fas_rhs32(const Grid& gc, const float* ubc, const float* ehat, float* f, hipStream_t s);

@@ -20,8 +20,9 @@ constexpr int kPT = 256;  // threads (fine columns) per workgroup
 template <typename T, int PI, bool DIFF>
 __global__ void __launch_bounds__(kPT) k_prolong_stream(int lgc, T* __restrict__ uf, const T* __restrict__ uc,
                                                         const T* __restrict__ uhat, const float* __restrict__ maskf,
-                                                        int ncolblk)
+                                                        int ncolblk, const int* __restrict__ halt)
 {
+    if (halt && *halt) return;
     const int lg = lgc + 1, n = 1 << lg, mc = (1 << lgc) - 1;
     const int nb = gridDim.x;
     int lid = blockIdx.x;
@@ -72,10 +73,10 @@ hipError_t launch(const Grid& gc, T* uf, const T* uc, const T* uhat, hipStream_t
     if (n >= 8) {
         const unsigned nb = (unsigned)(ncolblk * (n / 8));
         hipLaunchKernelGGL((k_prolong_stream<T, 8, DIFF>), dim3(nb), dim3(kPT), 0, s, gc.lg, uf, uc, uhat, maskf,
-                           ncolblk);
+                           ncolblk, gc.halt);
     } else {
         hipLaunchKernelGGL((k_prolong_stream<T, 4, DIFF>), dim3((unsigned)ncolblk), dim3(kPT), 0, s, gc.lg, uf, uc, uhat,
-                           maskf, ncolblk);
+                           maskf, ncolblk, gc.halt);
     }
     return hipGetLastError();
 }

@@ -21,6 +21,7 @@ template <int TJ, int NT, bool NORM, bool RESTRICT, bool UPDATE, bool CAST>
 __global__ void __launch_bounds__(NT) k_resid_stream(Grid g, const double* __restrict__ uin,
                                                      const double* __restrict__ src, ResidStream a)
 {
+    if (g.halt && *g.halt) return;
     constexpr int LJ = TJ + 2, LK = kTK + 2, NL = LJ * LK;
     constexpr int NS = (NL + NT - 1) / NT;
     __shared__ double lu[2][NL];

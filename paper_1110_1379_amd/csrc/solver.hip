@@ -33,8 +33,54 @@ int planes_for32(const mgfr_opts* o, size_t m, int n)
     return n <= 128 ? 8 : n == 256 ? 32 : 64;
 }
 
+// The storage one domain solve works on: the multigrid levels (double precision, and single
+// precision for the mixed solver) and the reduction buffers (the context's own, allocated on
+// demand).
+struct Hier {
+    Level* lv = nullptr;
+    size_t nlev = 0;
+    Level32* lv32 = nullptr;
+    size_t nlev32 = 0;
+    double* partial = nullptr;   // block partials of the reductions
+    double* red = nullptr;       // device result of a reduction (2 doubles)
+    double* host = nullptr;      // host copy of it
+    long long* counter = nullptr;  // coarsest-level sweeps of the current solve
+};
+
+Hier ctx_hier(mgfr_ctx* c)
+{
+    Hier h;
+    h.lv = c->lv.data();
+    h.nlev = c->lv.size();
+    h.lv32 = c->lv32.data();
+    h.nlev32 = c->lv32.size();
+    h.partial = c->partial;
+    h.red = c->red;
+    h.host = c->host_red;
+    h.counter = c->counter;
+    return h;
+}
+
+// Copies the 2-double reduction result to the host (synchronises the stream).
+int read_red(mgfr_ctx* c, const Hier& h, hipStream_t s, double* out2)
+{
+    MGFR_TRY(hip_check(c, hipMemcpyAsync(h.host, h.red, 2 * sizeof(double), hipMemcpyDeviceToHost, s),
+                       "hipMemcpyAsync"));
+    MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+    out2[0] = h.host[0];
+    out2[1] = h.host[1];
+    return MGFR_OK;
+}
+
+// Tile of the single-precision fused sweep: the option on the finest level, else automatic.
+int tile_for32(const mgfr_opts* o, size_t m)
+{
+    return m == 0 && o->tile > 0 ? o->tile : mgfr::kTile16x32;
+}
+
 struct Cycle {
     mgfr_ctx* c;
+    const Hier& h;
     const mgfr_opts* o;
     hipStream_t s;
     const double* finest_src = nullptr;
@@ -43,7 +89,7 @@ struct Cycle {
     // (cur is updated) or in place.  Finest-level sweeps are timed under MGFR_PROFILE.
     int sweep(size_t m, const double* src, double*& cur)
     {
-        Level& L = c->lv[m];
+        Level& L = h.lv[m];
         const bool fused = L.alt != nullptr && !o_simple;
         const bool timed = m == 0 && (o->flags & MGFR_PROFILE);
         if (timed) {
@@ -58,7 +104,8 @@ struct Cycle {
         }
         if (fused) {
             double* out = cur == L.u ? L.alt : L.u;
-            MGFR_TRY(hip_check(c, mgfr::ngs_sweep_fused(L.g, cur, out, src, planes_for(o, m, L.g.n), s),
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep_fused(L.g, cur, out, src, planes_for(o, m, L.g.n),
+                                                          m == 0 && o->tile > 0 ? o->tile : mgfr::kTile64x16x64, s),
                                "ngs_sweep_fused"));
             cur = out;
         } else {
@@ -91,16 +138,16 @@ struct Cycle {
 
     int vcycle(size_t m)
     {
-        Level& L = c->lv[m];
+        Level& L = h.lv[m];
         const double* src = m == 0 ? finest_src : L.f;
-        if (m + 1 == c->lv.size()) {
+        if (m + 1 == h.nlev) {
             return hip_check(c, mgfr::coarsest_solve(L.g, L.u, src, o->coarsest_sweeps, o->coarsest_rtol,
-                                                     c->counter, s),
+                                                     h.counter, s),
                              "coarsest_solve");
         }
         double* cur = L.u;
         for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m, src, cur));
-        Level& H = c->lv[m + 1];
+        Level& H = h.lv[m + 1];
         if (L.alt && !o_simple) {
             mgfr::ResidStream a{};
             a.ti = mgfr::resid_stream_planes(L.g.n);
@@ -128,12 +175,13 @@ struct Cycle {
 // V-cycle of the single-precision correction multigrid.
 struct Cycle32 {
     mgfr_ctx* c;
+    const Hier& h;
     const mgfr_opts* o;
     hipStream_t s;
 
     int sweep(size_t m, float*& cur)
     {
-        Level32& L = c->lv32[m];
+        Level32& L = h.lv32[m];
         const bool timed = m == 0 && (o->flags & MGFR_PROFILE);
         if (timed) {
             if ((size_t)c->ev_used + 2 > c->ev.size()) {
@@ -147,7 +195,7 @@ struct Cycle32 {
         }
         if (L.ealt) {
             float* out = cur == L.e ? L.ealt : L.e;
-            MGFR_TRY(hip_check(c, mgfr::ngs_sweep32_fused(L.g, L.ub, cur, out, L.f, planes_for32(o, m, L.g.n), s),
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep32_fused(L.g, L.ub, cur, out, L.f, planes_for32(o, m, L.g.n), tile_for32(o, m), s),
                                "ngs_sweep32_fused"));
             cur = out;
         } else {
@@ -157,7 +205,7 @@ struct Cycle32 {
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
             c->ev_used += 2;
             c->stats.sweep_launches += L.ealt ? 1 : 2;
-            c->stats.sweep_bytes += 16.0 * (double)mgfr::cells(L.g);
+            c->stats.sweep_bytes += 12.0 * (double)mgfr::cells(L.g);
         }
         c->stats.cell_updates += mgfr::cells(L.g);
         if (m == 0) c->stats.finest_updates += mgfr::cells(L.g);
@@ -166,13 +214,13 @@ struct Cycle32 {
 
     int vcycle(size_t m)
     {
-        Level32& L = c->lv32[m];
-        if (m + 1 == c->lv32.size())
+        Level32& L = h.lv32[m];
+        if (m + 1 == h.nlev32)
             return hip_check(c, mgfr::coarsest_solve32(L.g, L.ub, L.e, L.f, o->coarsest_sweeps, o->coarsest_rtol, s),
                              "coarsest_solve32");
         float* cur = L.e;
         for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m, cur));
-        Level32& H = c->lv32[m + 1];
+        Level32& H = h.lv32[m + 1];
         MGFR_TRY(hip_check(c, mgfr::resid_restrict32(L.g, L.ub, cur, L.f, H.e, H.ehat, H.f, s), "resid_restrict32"));
         MGFR_TRY(hip_check(c, mgfr::fas_rhs32(H.g, H.ub, H.ehat, H.f, s), "fas_rhs32"));
         MGFR_TRY(vcycle(m + 1));
@@ -187,21 +235,21 @@ struct Cycle32 {
 };
 
 // rms and max of the finest residual L(u) - f (synchronises).
-int finest_norm(mgfr_ctx* c, const mgfr::Grid& g, const double* u, const double* rho, hipStream_t s,
-                double* rms, double* mx)
+int finest_norm(mgfr_ctx* c, const Hier& h, const mgfr::Grid& g, const double* u, const double* rho,
+                hipStream_t s, double* rms, double* mx)
 {
     if (g.n >= mgfr::fused_sweep_min_n()) {
         mgfr::ResidStream a{};
         a.ti = mgfr::resid_stream_planes(g.n);
-        a.partial = c->partial;
+        a.partial = h.partial;
         MGFR_TRY(hip_check(c, mgfr::resid_stream(g, u, rho, a, s), "resid_stream"));
-        MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, (int)mgfr::resid_stream_blocks(g.n), c->red, s),
+        MGFR_TRY(hip_check(c, mgfr::fold_partials(h.partial, (int)mgfr::resid_stream_blocks(g.n), h.red, s),
                            "fold_partials"));
     } else {
-        MGFR_TRY(hip_check(c, mgfr::residual_norm(g, u, rho, c->partial, c->red, s), "residual_norm"));
+        MGFR_TRY(hip_check(c, mgfr::residual_norm(g, u, rho, h.partial, h.red, s), "residual_norm"));
     }
     double r[2];
-    MGFR_TRY(read_reduction(c, s, r));
+    MGFR_TRY(read_red(c, h, s, r));
     *rms = std::sqrt(r[0] / (double)mgfr::cells(g));
     if (mx) *mx = r[1];
     return MGFR_OK;
@@ -235,6 +283,13 @@ void mgfr_destroy(mgfr_ctx* c)
     (void)hipFree(c->red);
     (void)hipFree(c->counter);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    c->drop_graph();
+    if (c->dcap) (void)hipStreamDestroy(c->dcap);
+    (void)hipFree(c->gstate);
+    (void)hipFree(c->ghist);
     if (c->host_red) (void)hipHostFree(c->host_red);
     if (c->pin) (void)hipHostFree(c->pin);
     c->free_spare();
@@ -269,6 +324,8 @@ void mgfr_default_opts(mgfr_opts* o)
     o->coarsest_rtol = 1e-3;
     o->planes = 0;
     o->tau_alpha = 0.0;
+    o->unit_n = 0;
+    o->tile = 0;
 }
 
 int mgfr_constants(const mgfr_params* params, int N, double* out8)
@@ -292,14 +349,14 @@ int mgfr_constants(const mgfr_params* params, int N, double* out8)
 namespace {
 
 // Finest-level grid with the density source; rho_ref = 1 or mean(rho).
-int finest_grid(mgfr_ctx* c, const Model& md, const double* rho, int N, int flags, double max_step,
-                hipStream_t s, mgfr::Grid* g)
+int finest_grid(mgfr_ctx* c, const Hier& h, const Model& md, const double* rho, int N, int flags,
+                double max_step, hipStream_t s, mgfr::Grid* g)
 {
     *g = make_grid(md, N, 1.0 / N, max_step);
     const long long ncell = (long long)N * N * N;
-    MGFR_TRY(hip_check(c, mgfr::sum_and_count_nonfinite(rho, ncell, c->partial, c->red, s), "density check"));
+    MGFR_TRY(hip_check(c, mgfr::sum_and_count_nonfinite(rho, ncell, h.partial, h.red, s), "density check"));
     double r[2];
-    MGFR_TRY(read_reduction(c, s, r));
+    MGFR_TRY(read_red(c, h, s, r));
     if (r[1] != 0.0) return c->fail(MGFR_ENONFINITE, "density has %.0f non-finite cells", r[1]);
     g->fscale = md.D;
     g->sref = (flags & MGFR_SUBTRACT_MEAN) ? r[0] / (double)ncell : 1.0;
@@ -311,14 +368,14 @@ int finest_grid(mgfr_ctx* c, const Model& md, const double* rho, int N, int flag
 // field u, through the coarse level's scratch: R u and R d by the restriction pass, the FAS
 // right-hand side fH = L^H(R u) - R d, then tau = fH - R f_src (synchronises).  tau_out: the
 // tau field (may be null).
-int tau_rms(mgfr_ctx* c, const mgfr::Grid& g0, const double* u, const double* rho, hipStream_t s, double* rms,
-            double* tau_out)
+int tau_rms(mgfr_ctx* c, const Hier& h, const mgfr::Grid& g0, const double* u, const double* rho, hipStream_t s,
+            double* rms, double* tau_out)
 {
-    if (c->lv.size() < 2) {
+    if (h.nlev < 2) {
         *rms = 0.0;
         return MGFR_OK;
     }
-    Level& H = c->lv[1];
+    Level& H = h.lv[1];
     if (g0.n >= mgfr::fused_sweep_min_n()) {
         mgfr::ResidStream a{};
         a.ti = mgfr::resid_stream_planes(g0.n);
@@ -330,23 +387,23 @@ int tau_rms(mgfr_ctx* c, const mgfr::Grid& g0, const double* u, const double* rh
         MGFR_TRY(hip_check(c, mgfr::resid_restrict(g0, u, rho, H.u, H.uhat, H.f, s), "resid_restrict"));
     }
     MGFR_TRY(hip_check(c, mgfr::fas_rhs(H.g, H.uhat, H.f, s), "fas_rhs"));
-    const int nb = mgfr::tau_finish(g0, rho, H.f, tau_out, c->partial, s);
+    const int nb = mgfr::tau_finish(g0, rho, H.f, tau_out, h.partial, s);
     if (nb < 0) return hip_check(c, hipGetLastError(), "tau_finish");
-    MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, nb, c->red, s), "fold_partials"));
+    MGFR_TRY(hip_check(c, mgfr::fold_partials(h.partial, nb, h.red, s), "fold_partials"));
     double r[2];
-    MGFR_TRY(read_reduction(c, s, r));
+    MGFR_TRY(read_red(c, h, s, r));
     *rms = std::sqrt(r[0] / (double)mgfr::cells(H.g));
     return MGFR_OK;
 }
 
 // Stop test of the domain solves: rms(L) <= tol, or <= tau_alpha x rms(tau) when tau_alpha > 0.
-int converged(mgfr_ctx* c, const mgfr_opts* o, const mgfr::Grid& g0, const double* u, const double* rho,
-              hipStream_t s, double rms, bool* done)
+int converged(mgfr_ctx* c, const Hier& h, const mgfr_opts* o, const mgfr::Grid& g0, const double* u,
+              const double* rho, hipStream_t s, double rms, bool* done)
 {
     *done = !(rms > o->tol);
     if (*done || !(o->tau_alpha > 0.0) || !std::isfinite(rms)) return MGFR_OK;
     double t;
-    MGFR_TRY(tau_rms(c, g0, u, rho, s, &t, nullptr));
+    MGFR_TRY(tau_rms(c, h, g0, u, rho, s, &t, nullptr));
     c->stats.tau_rms = t;
     *done = rms <= o->tau_alpha * t;
     return MGFR_OK;
@@ -369,14 +426,15 @@ int mgfr_tau(mgfr_ctx* c, const double* rho, const double* u, int N, const mgfr_
     hipStream_t s = (hipStream_t)stream;
     const int coarsest = c->coarsest >= 2 && c->coarsest <= N / 2 ? c->coarsest : 2;
     MGFR_TRY(ensure_levels(c, N, coarsest));
-    Level& L0 = c->lv[0];
-    MGFR_TRY(finest_grid(c, md, rho, N, flags, 0.0, s, &L0.g));
-    for (size_t m = 1; m < c->lv.size(); ++m) {
+    const Hier h = ctx_hier(c);
+    Level& L0 = h.lv[0];
+    MGFR_TRY(finest_grid(c, h, md, rho, N, flags, 0.0, s, &L0.g));
+    for (size_t m = 1; m < h.nlev; ++m) {
         const int n = N >> m;
-        c->lv[m].g = make_grid(md, n, 1.0 / n, 0.0);
+        h.lv[m].g = make_grid(md, n, 1.0 / n, 0.0);
     }
     double r;
-    MGFR_TRY(tau_rms(c, L0.g, u, rho, s, &r, tau));
+    MGFR_TRY(tau_rms(c, h, L0.g, u, rho, s, &r, tau));
     if (rms) *rms = r;
     return MGFR_OK;
 }
@@ -392,7 +450,7 @@ int mgfr_residual(mgfr_ctx* c, const double* rho, const double* u, int N, const 
     MGFR_TRY(ensure_scratch(c));
     hipStream_t s = (hipStream_t)stream;
     mgfr::Grid g;
-    MGFR_TRY(finest_grid(c, md, rho, N, flags, 0.0, s, &g));
+    MGFR_TRY(finest_grid(c, ctx_hier(c), md, rho, N, flags, 0.0, s, &g));
     return hip_check(c, mgfr::residual_field(g, u, rho, d, s), "residual_field");
 }
 
@@ -413,10 +471,11 @@ int mgfr_smooth(mgfr_ctx* c, const double* rho, double* u, int N, const mgfr_par
     hipStream_t s = (hipStream_t)stream;
     MGFR_TRY(ensure_scratch(c));
     MGFR_TRY(ensure_levels(c, N, std::min(N, o->coarsest_n)));
-    Level& L0 = c->lv[0];
-    MGFR_TRY(finest_grid(c, md, rho, N, o->flags, o->max_step, s, &L0.g));
+    const Hier h = ctx_hier(c);
+    Level& L0 = h.lv[0];
+    MGFR_TRY(finest_grid(c, h, md, rho, N, o->flags, o->max_step, s, &L0.g));
     L0.u = u;
-    Cycle cyc{c, o, s};
+    Cycle cyc{c, h, o, s};
     cyc.finest_src = rho;
     cyc.o_simple = variant == 1;
     c->ev_used = 0;
@@ -427,6 +486,405 @@ int mgfr_smooth(mgfr_ctx* c, const double* rho, double* u, int N, const mgfr_par
                            "hipMemcpyAsync"));
     return cyc.harvest();
 }
+
+int mgfr_smooth32(mgfr_ctx* c, const float* ub, float* e, const float* f, int N, const mgfr_params* params,
+                  const mgfr_opts* o, int nsweeps, int variant, void* stream)
+{
+    if (!c) return MGFR_EINVAL;
+    c->err.clear();
+    c->stats = mgfr_stats{};
+    MGFR_TRY(check_opts(c, o));
+    Model md;
+    if (derive_model(params, &md) != MGFR_OK) return c->fail(MGFR_EINVAL, "invalid model parameters");
+    if (!ub || !e || !f || !is_pow2(N) || N < 2 || N > 1024 || nsweeps < 0 || variant < 0 || variant > 2)
+        return c->fail(MGFR_EINVAL, "invalid arguments");
+    const bool fused = variant == 2 || (variant == 0 && N >= mgfr::fused_sweep_min_n());
+    if (fused && N < mgfr::fused_sweep_min_n())
+        return c->fail(MGFR_EINVAL, "the fused sweep needs N >= %d", mgfr::fused_sweep_min_n());
+    if (fused && o->planes > 0 && (o->planes > N || (o->planes & 3)))
+        return c->fail(MGFR_EINVAL, "planes=%d must be a multiple of 4 and <= N", o->planes);
+    MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+    hipStream_t s = (hipStream_t)stream;
+    MGFR_TRY(ensure_scratch(c));
+    if (fused) MGFR_TRY(ensure_levels32(c, N, std::min(N, o->coarsest_n)));
+    const mgfr::Grid g = make_grid(md, N, 1.0 / N, o->max_step);
+    const bool timed = (o->flags & MGFR_PROFILE) != 0;
+    c->ev_used = 0;
+    float* cur = e;
+    for (int k = 0; k < nsweeps; ++k) {
+        if (timed) {
+            if ((size_t)c->ev_used + 2 > c->ev.size()) {
+                for (int q = 0; q < 64; ++q) {
+                    hipEvent_t ev;
+                    MGFR_TRY(hip_check(c, hipEventCreate(&ev), "hipEventCreate"));
+                    c->ev.push_back(ev);
+                }
+            }
+            MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used], s), "hipEventRecord"));
+        }
+        if (fused) {
+            float* out = cur == e ? c->lv32[0].ealt : e;
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep32_fused(g, ub, cur, out, f, planes_for32(o, 0, N), tile_for32(o, 0), s),
+                               "ngs_sweep32_fused"));
+            cur = out;
+        } else {
+            MGFR_TRY(hip_check(c, mgfr::ngs_sweep32(g, ub, cur, f, s), "ngs_sweep32"));
+        }
+        if (timed) {
+            MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
+            c->ev_used += 2;
+            c->stats.sweep_launches += fused ? 1 : 2;
+            c->stats.sweep_bytes += 12.0 * (double)mgfr::cells(g);
+        }
+        c->stats.cell_updates += mgfr::cells(g);
+        c->stats.finest_updates += mgfr::cells(g);
+    }
+    if (cur != e)
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(e, cur, sizeof(float) * mgfr::cells(g), hipMemcpyDeviceToDevice, s),
+                           "hipMemcpyAsync"));
+    const Hier h = ctx_hier(c);
+    Cycle cyc{c, h, o, s};
+    return cyc.harvest();
+}
+
+}  // extern "C"
+
+namespace {
+
+// FP64 stop test inside a captured graph: the finest residual's block sums, their fold into
+// h.red and the device stop test.
+int norm_and_stop(mgfr_ctx* c, const Hier& h, const mgfr::Grid& g, const double* u, const double* rho,
+                  const mgfr_opts* o, hipStream_t s)
+{
+    if (g.n >= mgfr::fused_sweep_min_n()) {
+        mgfr::ResidStream a{};
+        a.ti = mgfr::resid_stream_planes(g.n);
+        a.partial = h.partial;
+        MGFR_TRY(hip_check(c, mgfr::resid_stream(g, u, rho, a, s), "resid_stream"));
+        MGFR_TRY(hip_check(c, mgfr::fold_partials(h.partial, (int)mgfr::resid_stream_blocks(g.n), h.red, s),
+                           "fold_partials"));
+    } else {
+        MGFR_TRY(hip_check(c, mgfr::residual_norm(g, u, rho, h.partial, h.red, s), "residual_norm"));
+    }
+    return hip_check(c, mgfr::domain_stop(h.red, mgfr::cells(g), o->tol, o->max_cycles, c->ghist, c->gstate, s),
+                     "domain_stop");
+}
+
+// What a captured domain solve depends on besides the data: replayed only while all of it
+// is unchanged.
+struct GraphKey {
+    const void *rho, *u, *lv, *lv32, *partial, *red, *counter, *alt;
+    int N, precision, pre, post, inner, cap, planes, tile, max_cycles, nlev, nlev32;
+    double tol, rtol;
+    mgfr::Grid g0;
+};
+
+// Replays body (two cycles, each ending in the device stop test) from a graph until the
+// stop test has stopped the solve; *k gets the cycles run, *rms the last residual and
+// res_hist[1 .. k] the history.  Every level's kernels return at once after the stop.
+template <class Body>
+int run_graph(mgfr_ctx* c, const Hier& h, const mgfr_opts* o, const double* rho, double* u, int N, hipStream_t s,
+              Body body, double* res_hist, int* k, double* rms)
+{
+    const int H = o->max_cycles + 1;
+    if (c->ghist_n < H) {
+        (void)hipFree(c->ghist);
+        c->ghist = nullptr;
+        c->ghist_n = 0;
+        if (hipMalloc(&c->ghist, sizeof(double) * H) != hipSuccess) return c->fail(MGFR_ENOMEM, "hipMalloc failed");
+        c->ghist_n = H;
+    }
+    if (!c->gstate && hipMalloc(&c->gstate, 2 * sizeof(int)) != hipSuccess) {
+        c->gstate = nullptr;
+        return c->fail(MGFR_ENOMEM, "hipMalloc failed");
+    }
+    int* halt = c->gstate + 1;
+    for (size_t m = 0; m < h.nlev; ++m) h.lv[m].g.halt = halt;
+    for (size_t m = 0; m < h.nlev32; ++m) h.lv32[m].g.halt = halt;
+    GraphKey key;
+    std::memset(&key, 0, sizeof key);
+    key.rho = rho;
+    key.u = u;
+    key.lv = h.lv;
+    key.lv32 = h.lv32;
+    key.partial = h.partial;
+    key.red = h.red;
+    key.counter = h.counter;
+    key.alt = h.lv[0].alt;
+    key.N = N;
+    key.precision = o->precision;
+    key.pre = o->pre;
+    key.post = o->post;
+    key.inner = o->inner_cycles;
+    key.cap = o->coarsest_sweeps;
+    key.planes = o->planes;
+    key.tile = o->tile;
+    key.max_cycles = o->max_cycles;
+    key.nlev = (int)h.nlev;
+    key.nlev32 = (int)h.nlev32;
+    key.tol = o->tol;
+    key.rtol = o->coarsest_rtol;
+    key.g0 = h.lv[0].g;
+    auto restore = [&]() {
+        for (size_t m = 0; m < h.nlev; ++m) h.lv[m].g.halt = nullptr;
+        for (size_t m = 0; m < h.nlev32; ++m) h.lv32[m].g.halt = nullptr;
+    };
+    int st = MGFR_OK;
+    if (!c->dgexec || c->dkey.size() != sizeof key || std::memcmp(c->dkey.data(), &key, sizeof key) != 0) {
+        if (c->dgexec) (void)hipGraphExecDestroy(c->dgexec);
+        if (c->dgraph) (void)hipGraphDestroy(c->dgraph);
+        c->dgexec = nullptr;
+        c->dgraph = nullptr;
+        c->dkey.clear();
+        if (!c->dcap && hipStreamCreateWithFlags(&c->dcap, hipStreamNonBlocking) != hipSuccess) {
+            c->dcap = nullptr;
+            restore();
+            return c->fail(MGFR_EDEVICE, "hipStreamCreate failed");
+        }
+        const mgfr_stats base = c->stats;
+        st = hip_check(c, hipStreamBeginCapture(c->dcap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        if (st == MGFR_OK) {
+            st = body(c->dcap);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->dcap, &g);
+            c->dgraph = g;
+            if (st == MGFR_OK) st = hip_check(c, e, "hipStreamEndCapture");
+            if (st == MGFR_OK)
+                st = hip_check(c, hipGraphInstantiate(&c->dgexec, c->dgraph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        }
+        // what one cycle of the graph adds to the counters (the capture ran two)
+        c->dper_updates = (c->stats.cell_updates - base.cell_updates) / 2;
+        c->dper_finest = (c->stats.finest_updates - base.finest_updates) / 2;
+        c->dper_inner = (c->stats.inner_cycles - base.inner_cycles) / 2;
+        c->stats = base;
+        if (st != MGFR_OK) {
+            restore();
+            return st;
+        }
+        c->dkey.assign((const char*)&key, (const char*)&key + sizeof key);
+    }
+    MGFR_TRY(hip_check(c, mgfr::fill_int(c->gstate, 0, 2, s), "fill_int"));
+    int* hs = (int*)c->host_red;
+    hs[0] = hs[1] = 0;
+    // two cycles per launch; the stop test ends the solve by max_cycles at the latest
+    for (int launch = 0; launch <= o->max_cycles / 2 && !hs[1]; ++launch) {
+        MGFR_TRY(hip_check(c, hipGraphLaunch(c->dgexec, s), "hipGraphLaunch"));
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(hs, c->gstate, 2 * sizeof(int), hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync"));
+        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+    }
+    restore();
+    *k = hs[0];
+    if (*k > 0) {
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(c->host_red, c->ghist + *k, sizeof(double), hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync"));
+        if (res_hist)
+            MGFR_TRY(hip_check(c, hipMemcpyAsync(res_hist + 1, c->ghist + 1, sizeof(double) * *k, hipMemcpyDeviceToHost, s),
+                               "hipMemcpyAsync"));
+        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+        *rms = c->host_red[0];
+    }
+    c->stats.cell_updates += c->dper_updates * *k;
+    c->stats.finest_updates += c->dper_finest * *k;
+    c->stats.inner_cycles += c->dper_inner * *k;
+    return MGFR_OK;
+}
+
+// The domain solve on the storage h, whose levels (and single-precision levels for the
+// mixed solver) are sized for N; level 0's u is the caller's.  Allocates nothing (unless
+// MGFR_GRAPH, whose graph and device stop state are kept in the context).
+int solve_body(mgfr_ctx* c, const Hier& h, const Model& md, const double* rho, int N, const mgfr_opts* o,
+               double* u, double* res_hist, int* n_hist, hipStream_t s,
+               std::chrono::steady_clock::time_point t0, bool graphs)
+{
+    const long long ncell = (long long)N * N * N;
+    Level& L0 = h.lv[0];
+    MGFR_TRY(finest_grid(c, h, md, rho, N, o->flags, o->max_step, s, &L0.g));
+    L0.u = u;
+    for (size_t m = 1; m < h.nlev; ++m) {
+        const int n = N >> m;
+        h.lv[m].g = make_grid(md, n, 1.0 / n, o->max_step);
+    }
+
+    double r[2];
+    if (o->flags & MGFR_WARM_START) {
+        MGFR_TRY(hip_check(c, mgfr::sum_and_count_nonfinite(u, ncell, h.partial, h.red, s), "start check"));
+        MGFR_TRY(read_red(c, h, s, r));
+        if (r[1] != 0.0) return c->fail(MGFR_ENONFINITE, "start field has %.0f non-finite cells", r[1]);
+    } else {
+        MGFR_TRY(hip_check(c, mgfr::fill(u, md.ubar, ncell, s), "fill"));
+    }
+
+    Cycle cyc{c, h, o, s};
+    cyc.finest_src = rho;
+    c->ev_used = 0;
+    MGFR_TRY(hip_check(c, hipMemsetAsync(h.counter, 0, sizeof(long long), s), "hipMemsetAsync"));
+    double rms;
+    int k = 0;
+    bool stop = false;  // the stop test passed
+    // MGFR_GRAPH: the cycles are captured once, with the stop test on the device, and replayed
+    // until it stops them (the rms test only: the truncation-error rule and event timing stay
+    // eager, as does an odd sweep count, whose finest level ends in the second buffer)
+    const bool graph = (o->flags & MGFR_GRAPH) && !(o->flags & MGFR_PROFILE) && !(o->tau_alpha > 0.0) &&
+                       (o->pre + o->post) % 2 == 0 && graphs;
+    if (o->precision == MGFR_FP64) {
+        MGFR_TRY(finest_norm(c, h, L0.g, u, rho, s, &rms, nullptr));
+        if (res_hist) res_hist[0] = rms;
+        MGFR_TRY(converged(c, h, o, L0.g, u, rho, s, rms, &stop));
+        if (graph && std::isfinite(rms) && !stop && k < o->max_cycles) {
+            auto body = [&](hipStream_t st) -> int {
+                const hipStream_t keep = s;
+                s = st;
+                cyc.s = st;
+                int r = MGFR_OK;
+                for (int it = 0; it < 2 && r == MGFR_OK; ++it) {
+                    r = cyc.vcycle(0);
+                    if (r == MGFR_OK) r = norm_and_stop(c, h, L0.g, u, rho, o, st);
+                }
+                s = keep;
+                cyc.s = keep;
+                return r;
+            };
+            MGFR_TRY(run_graph(c, h, o, rho, u, N, s, body, res_hist, &k, &rms));
+            stop = !(rms > o->tol);
+        }
+        while (std::isfinite(rms) && !stop && k < o->max_cycles) {
+            MGFR_TRY(cyc.vcycle(0));
+            MGFR_TRY(finest_norm(c, h, L0.g, u, rho, s, &rms, nullptr));
+            MGFR_TRY(cyc.harvest());
+            ++k;
+            if (res_hist) res_hist[k] = rms;
+            MGFR_TRY(converged(c, h, o, L0.g, u, rho, s, rms, &stop));
+        }
+    } else {
+        // Defect correction: d = L(u) - f in double precision; a single-precision FAS
+        // multigrid solves N(e) = -d for the correction; u += e; repeat.
+        for (size_t m = 0; m < h.nlev32; ++m) h.lv32[m].g = h.lv[m].g;
+        Level32& I0 = h.lv32[0];
+        Cycle32 cyc32{c, h, o, s};
+        const bool stream = N >= mgfr::fused_sweep_min_n();
+        double* ucur = u;
+        // residual of ucur (+ e when `update`), cast to the single-precision right-hand side
+        auto outer_residual = [&](bool update) -> int {
+            if (stream) {
+                mgfr::ResidStream a{};
+                a.ti = mgfr::resid_stream_planes(N);
+                a.partial = h.partial;
+                a.r32 = I0.f;
+                a.ub32 = I0.ub;
+                double* next = ucur;
+                if (update) {
+                    next = ucur == u ? L0.alt : u;
+                    a.e32 = I0.e;
+                    a.uout = next;
+                }
+                MGFR_TRY(hip_check(c, mgfr::resid_stream(L0.g, ucur, rho, a, s), "resid_stream"));
+                MGFR_TRY(hip_check(c, mgfr::fold_partials(h.partial, (int)mgfr::resid_stream_blocks(N), h.red, s),
+                                   "fold_partials"));
+                ucur = next;
+            } else {
+                if (update) MGFR_TRY(hip_check(c, mgfr::add_correction(ucur, I0.e, ncell, s), "add_correction"));
+                MGFR_TRY(hip_check(c, mgfr::residual_cast(L0.g, ucur, rho, I0.f, I0.ub, h.partial, h.red, s),
+                                   "residual_cast"));
+            }
+            double r2[2];
+            MGFR_TRY(read_red(c, h, s, r2));
+            rms = std::sqrt(r2[0] / (double)ncell);
+            return MGFR_OK;
+        };
+        MGFR_TRY(outer_residual(false));
+        if (res_hist) res_hist[0] = rms;
+        MGFR_TRY(converged(c, h, o, L0.g, ucur, rho, s, rms, &stop));
+        if (graph && std::isfinite(rms) && !stop && k < o->max_cycles) {
+            // one outer iteration: coarse bases, e = 0, the inner V-cycles, then u += e with
+            // the double-precision residual; u and the second finest buffer alternate, so
+            // the graph holds two iterations and the solve starts from u
+            auto iteration = [&]() -> int {
+                for (size_t m = 1; m < h.nlev32; ++m)
+                    MGFR_TRY(hip_check(c, mgfr::restrict_mean32(h.lv32[m].g, h.lv32[m - 1].ub, h.lv32[m].ub, s),
+                                       "restrict_mean32"));
+                MGFR_TRY(hip_check(c, mgfr::fill32(I0.e, 0.0f, ncell, s), "fill32"));
+                for (int ic = 0; ic < o->inner_cycles; ++ic) {
+                    MGFR_TRY(cyc32.vcycle(0));
+                    ++c->stats.inner_cycles;
+                }
+                if (stream) {
+                    mgfr::ResidStream a{};
+                    a.ti = mgfr::resid_stream_planes(N);
+                    a.partial = h.partial;
+                    a.r32 = I0.f;
+                    a.ub32 = I0.ub;
+                    double* next = ucur == u ? L0.alt : u;
+                    a.e32 = I0.e;
+                    a.uout = next;
+                    MGFR_TRY(hip_check(c, mgfr::resid_stream(L0.g, ucur, rho, a, s), "resid_stream"));
+                    MGFR_TRY(hip_check(c, mgfr::fold_partials(h.partial, (int)mgfr::resid_stream_blocks(N), h.red, s),
+                                       "fold_partials"));
+                    ucur = next;
+                } else {
+                    MGFR_TRY(hip_check(c, mgfr::add_correction(ucur, I0.e, ncell, s, L0.g.halt), "add_correction"));
+                    MGFR_TRY(hip_check(c, mgfr::residual_cast(L0.g, ucur, rho, I0.f, I0.ub, h.partial, h.red, s),
+                                       "residual_cast"));
+                }
+                return hip_check(c, mgfr::domain_stop(h.red, ncell, o->tol, o->max_cycles, c->ghist, c->gstate, s),
+                                 "domain_stop");
+            };
+            auto body = [&](hipStream_t st) -> int {
+                const hipStream_t keep = s;
+                s = st;
+                cyc.s = st;
+                cyc32.s = st;
+                int r = iteration();
+                if (r == MGFR_OK) r = iteration();
+                s = keep;
+                cyc.s = keep;
+                cyc32.s = keep;
+                return r;
+            };
+            MGFR_TRY(run_graph(c, h, o, rho, u, N, s, body, res_hist, &k, &rms));
+            stop = !(rms > o->tol);
+            if (stream && (k & 1)) ucur = L0.alt;  // an odd count ends in the second buffer
+        }
+        while (std::isfinite(rms) && !stop && k < o->max_cycles) {
+            for (size_t m = 1; m < h.nlev32; ++m)
+                MGFR_TRY(hip_check(c, mgfr::restrict_mean32(h.lv32[m].g, h.lv32[m - 1].ub, h.lv32[m].ub, s),
+                                   "restrict_mean32"));
+            MGFR_TRY(hip_check(c, mgfr::fill32(I0.e, 0.0f, ncell, s), "fill32"));
+            for (int ic = 0; ic < o->inner_cycles; ++ic) {
+                MGFR_TRY(cyc32.vcycle(0));
+                ++c->stats.inner_cycles;
+            }
+            MGFR_TRY(outer_residual(true));
+            MGFR_TRY(cyc.harvest());
+            ++k;
+            if (res_hist) res_hist[k] = rms;
+            MGFR_TRY(converged(c, h, o, L0.g, ucur, rho, s, rms, &stop));
+        }
+        if (ucur != u)
+            MGFR_TRY(hip_check(c, hipMemcpyAsync(u, ucur, sizeof(double) * ncell, hipMemcpyDeviceToDevice, s),
+                               "hipMemcpyAsync"));
+    }
+    if (n_hist) *n_hist = k + 1;
+    {
+        long long coarse_sweeps = 0;
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(&coarse_sweeps, h.counter, sizeof coarse_sweeps, hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync"));
+        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
+        const long long nc = mgfr::cells(h.lv[h.nlev - 1].g);
+        c->stats.cell_updates += coarse_sweeps * nc;
+        if (h.nlev == 1) c->stats.finest_updates += coarse_sweeps * nc;
+        c->stats.cycles = k;
+        c->stats.solve_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!std::isfinite(rms)) return c->fail(MGFR_ENONFINITE, "residual became non-finite after %d cycles", k);
+    if (!stop) return c->fail(MGFR_ENOTCONV, "rms residual %.3e > tol %.3e after %d cycles", rms, o->tol, k);
+    return MGFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params, const mgfr_opts* o,
                 double* u, double* res_hist, int* n_hist, void* stream)
@@ -443,123 +901,14 @@ int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params
     if (!is_pow2(N) || N < o->coarsest_n || N > 1024)
         return c->fail(MGFR_EINVAL, "N=%d must be a power of two in [coarsest_n, 1024]", N);
     MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
-    hipStream_t s = (hipStream_t)stream;
     MGFR_TRY(ensure_scratch(c));
     MGFR_TRY(ensure_levels(c, N, o->coarsest_n));
-    const long long ncell = (long long)N * N * N;
-
-    Level& L0 = c->lv[0];
-    MGFR_TRY(finest_grid(c, md, rho, N, o->flags, o->max_step, s, &L0.g));
-    L0.u = u;
-    for (size_t m = 1; m < c->lv.size(); ++m) {
-        const int n = N >> m;
-        c->lv[m].g = make_grid(md, n, 1.0 / n, o->max_step);
-    }
-
-    double r[2];
-    if (o->flags & MGFR_WARM_START) {
-        MGFR_TRY(hip_check(c, mgfr::sum_and_count_nonfinite(u, ncell, c->partial, c->red, s), "start check"));
-        MGFR_TRY(read_reduction(c, s, r));
-        if (r[1] != 0.0) return c->fail(MGFR_ENONFINITE, "start field has %.0f non-finite cells", r[1]);
-    } else {
-        MGFR_TRY(hip_check(c, mgfr::fill(u, md.ubar, ncell, s), "fill"));
-    }
-
-    Cycle cyc{c, o, s};
-    cyc.finest_src = rho;
-    c->ev_used = 0;
-    MGFR_TRY(hip_check(c, hipMemsetAsync(c->counter, 0, sizeof(long long), s), "hipMemsetAsync"));
-    double rms;
-    int k = 0;
-    bool stop = false;  // the stop test passed
-    if (o->precision == MGFR_FP64) {
-        MGFR_TRY(finest_norm(c, L0.g, u, rho, s, &rms, nullptr));
-        if (res_hist) res_hist[0] = rms;
-        MGFR_TRY(converged(c, o, L0.g, u, rho, s, rms, &stop));
-        while (std::isfinite(rms) && !stop && k < o->max_cycles) {
-            MGFR_TRY(cyc.vcycle(0));
-            MGFR_TRY(finest_norm(c, L0.g, u, rho, s, &rms, nullptr));
-            MGFR_TRY(cyc.harvest());
-            ++k;
-            if (res_hist) res_hist[k] = rms;
-            MGFR_TRY(converged(c, o, L0.g, u, rho, s, rms, &stop));
-        }
-    } else {
-        // Defect correction: d = L(u) - f in double precision; a single-precision FAS
-        // multigrid solves N(e) = -d for the correction; u += e; repeat.
-        MGFR_TRY(ensure_levels32(c, N, o->coarsest_n));
-        for (size_t m = 0; m < c->lv32.size(); ++m) c->lv32[m].g = c->lv[m].g;
-        Level32& I0 = c->lv32[0];
-        Cycle32 cyc32{c, o, s};
-        const bool stream = N >= mgfr::fused_sweep_min_n();
-        double* ucur = u;
-        // residual of ucur (+ e when `update`), cast to the single-precision right-hand side
-        auto outer_residual = [&](bool update) -> int {
-            if (stream) {
-                mgfr::ResidStream a{};
-                a.ti = mgfr::resid_stream_planes(N);
-                a.partial = c->partial;
-                a.r32 = I0.f;
-                a.ub32 = I0.ub;
-                double* next = ucur;
-                if (update) {
-                    next = ucur == u ? L0.alt : u;
-                    a.e32 = I0.e;
-                    a.uout = next;
-                }
-                MGFR_TRY(hip_check(c, mgfr::resid_stream(L0.g, ucur, rho, a, s), "resid_stream"));
-                MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, (int)mgfr::resid_stream_blocks(N), c->red, s),
-                                   "fold_partials"));
-                ucur = next;
-            } else {
-                if (update) MGFR_TRY(hip_check(c, mgfr::add_correction(ucur, I0.e, ncell, s), "add_correction"));
-                MGFR_TRY(hip_check(c, mgfr::residual_cast(L0.g, ucur, rho, I0.f, I0.ub, c->partial, c->red, s),
-                                   "residual_cast"));
-            }
-            double r2[2];
-            MGFR_TRY(read_reduction(c, s, r2));
-            rms = std::sqrt(r2[0] / (double)ncell);
-            return MGFR_OK;
-        };
-        MGFR_TRY(outer_residual(false));
-        if (res_hist) res_hist[0] = rms;
-        MGFR_TRY(converged(c, o, L0.g, ucur, rho, s, rms, &stop));
-        while (std::isfinite(rms) && !stop && k < o->max_cycles) {
-            for (size_t m = 1; m < c->lv32.size(); ++m)
-                MGFR_TRY(hip_check(c, mgfr::restrict_mean32(c->lv32[m].g, c->lv32[m - 1].ub, c->lv32[m].ub, s),
-                                   "restrict_mean32"));
-            MGFR_TRY(hip_check(c, mgfr::fill32(I0.e, 0.0f, ncell, s), "fill32"));
-            for (int ic = 0; ic < o->inner_cycles; ++ic) {
-                MGFR_TRY(cyc32.vcycle(0));
-                ++c->stats.inner_cycles;
-            }
-            MGFR_TRY(outer_residual(true));
-            MGFR_TRY(cyc.harvest());
-            ++k;
-            if (res_hist) res_hist[k] = rms;
-            MGFR_TRY(converged(c, o, L0.g, ucur, rho, s, rms, &stop));
-        }
-        if (ucur != u)
-            MGFR_TRY(hip_check(c, hipMemcpyAsync(u, ucur, sizeof(double) * ncell, hipMemcpyDeviceToDevice, s),
-                               "hipMemcpyAsync"));
-        MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
-    }
-    if (n_hist) *n_hist = k + 1;
-    {
-        long long coarse_sweeps = 0;
-        MGFR_TRY(hip_check(c, hipMemcpy(&coarse_sweeps, c->counter, sizeof coarse_sweeps, hipMemcpyDeviceToHost),
-                           "hipMemcpy"));
-        const long long nc = mgfr::cells(c->lv.back().g);
-        c->stats.cell_updates += coarse_sweeps * nc;
-        if (c->lv.size() == 1) c->stats.finest_updates += coarse_sweeps * nc;
-        c->stats.cycles = k;
-        c->stats.solve_ms =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    }
-    if (!std::isfinite(rms)) return c->fail(MGFR_ENONFINITE, "residual became non-finite after %d cycles", k);
-    if (!stop) return c->fail(MGFR_ENOTCONV, "rms residual %.3e > tol %.3e after %d cycles", rms, o->tol, k);
-    return MGFR_OK;
+    if (o->precision == MGFR_MIXED) MGFR_TRY(ensure_levels32(c, N, o->coarsest_n));
+    Hier h = ctx_hier(c);
+    if (o->precision != MGFR_MIXED) h.nlev32 = 0;
+    return solve_body(c, h, md, rho, N, o, u, res_hist, n_hist, (hipStream_t)stream, t0, true);
 }
+
 
 }  // extern "C"
 
@@ -619,6 +968,16 @@ int mgfr_autotune(mgfr_ctx* c, const double* rho, int N, const mgfr_params* para
         for (int planes = 8; planes <= 128 && planes <= N; planes *= 2) {
             mgfr_opts o = stage1;
             o.planes = planes;
+            MGFR_TRY(consider(o));
+        }
+        // stage 3: its tile (double precision: 16 x 64 or 8 x 64; single precision: 16 x 32,
+        // 32 x 32 or 16 x 64 with one column pair per thread, or 8 x 32 with pairs over the halo)
+        const mgfr_opts stage2 = cur_best;
+        const int ntile = base->precision == MGFR_MIXED ? 4 : 2;
+        for (int tile = 1; tile <= ntile; ++tile) {
+            mgfr_opts o = stage2;
+            o.tile = tile;
+            if (o.planes == 0) o.planes = base->precision == MGFR_MIXED ? planes_for32(&o, 0, N) : planes_for(&o, 0, N);
             MGFR_TRY(consider(o));
         }
     }

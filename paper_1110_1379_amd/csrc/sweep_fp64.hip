@@ -39,6 +39,7 @@ __global__ void __launch_bounds__(NT) k_ngs_fused(Grid g, const double* __restri
                                                   double* __restrict__ uout,
                                                   const double* __restrict__ src, FusedSweep a)
 {
+    if (g.halt && *g.halt) return;
     constexpr int LJ = TJ + 4, LK = kTK + 4, NL = LJ * LK, NP = NL / 2;
     static_assert(NP <= NT, "one column pair per thread");
     // three plane buffers: plane p (red update), plane p-1 (black update), plane p+1 (staged)
@@ -212,13 +213,14 @@ int fused_sweep_planes(int n)
     return ti > n ? n : ti;
 }
 
-hipError_t ngs_sweep_fused(const Grid& g, const double* uin, double* uout, const double* src, int ti,
+hipError_t ngs_sweep_fused(const Grid& g, const double* uin, double* uout, const double* src, int ti, int tile,
                            hipStream_t s)
 {
     if (g.n < kTK || g.n > 1024 || uin == uout || ti < 4 || (ti & 3) || ti > g.n || (g.n % ti) != 0)
         return hipErrorInvalidValue;
     FusedSweep a{};
     a.ti = ti;
+    if (tile == kTile64x8x64) return launch<8, 448>(g, uin, uout, src, a, s);  // 408 column pairs per 12 x 68
     return launch<16, 704>(g, uin, uout, src, a, s);  // 680 column pairs per 20 x 68 tile
 }
 

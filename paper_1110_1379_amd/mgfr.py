@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmgfr.so")
 
 MGFR_OK, MGFR_EINVAL, MGFR_ENONFINITE, MGFR_ENOTCONV, MGFR_EDEVICE, MGFR_ENOMEM = 0, -1, -2, -3, -4, -5
 MGFR_FP64, MGFR_MIXED = 0, 1
-MGFR_SUBTRACT_MEAN, MGFR_WARM_START, MGFR_PROFILE, MGFR_GRAPH = 1, 2, 4, 8
+MGFR_SUBTRACT_MEAN, MGFR_WARM_START, MGFR_PROFILE, MGFR_GRAPH, MGFR_PER_PHASE = 1, 2, 4, 8, 16
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENONFINITE", -3: "ENOTCONV", -4: "EDEVICE", -5: "ENOMEM"}
 
 
@@ -31,7 +31,8 @@ class mgfr_opts(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int), ("coarsest_sweeps", ctypes.c_int),
                 ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
                 ("inner_cycles", ctypes.c_int), ("max_step", ctypes.c_double),
-                ("coarsest_rtol", ctypes.c_double), ("planes", ctypes.c_int), ("tau_alpha", ctypes.c_double)]
+                ("coarsest_rtol", ctypes.c_double), ("planes", ctypes.c_int), ("tau_alpha", ctypes.c_double),
+                ("unit_n", ctypes.c_int), ("tile", ctypes.c_int)]
 
 
 class mgfr_patch(ctypes.Structure):
@@ -89,6 +90,7 @@ def lib():
             "mgfr_residual": ([vp, vp, vp, ctypes.c_int, P, ctypes.c_int, vp, vp], ctypes.c_int),
             "mg_fr_solve": ([vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
             "mgfr_smooth": ([vp, vp, vp, ctypes.c_int, P, O, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
+            "mgfr_smooth32": ([vp, vp, vp, vp, ctypes.c_int, P, O, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
             "mg_fr_solve_patches": ([vp, vp, ctypes.c_int, ctypes.POINTER(mgfr_patch), ctypes.c_int, vp, vp,
                                      ctypes.c_longlong, P, O, dp, ip, vp], ctypes.c_int),
             "mg_fr_solve_batch": ([vp, ctypes.c_int, ip, ctypes.POINTER(vp), P, O, ctypes.POINTER(vp), dp, ip, vp],
@@ -111,7 +113,7 @@ def lib():
 
 def exported_symbols():
     return ("mgfr_create", "mgfr_destroy", "mgfr_last_error", "mgfr_default_opts", "mgfr_constants",
-            "mgfr_residual", "mg_fr_solve", "mgfr_get_stats", "mgfr_smooth", "mg_fr_solve_patches",
+            "mgfr_residual", "mg_fr_solve", "mgfr_get_stats", "mgfr_smooth", "mgfr_smooth32", "mg_fr_solve_patches",
             "mg_fr_solve_batch", "mgfr_autotune", "mg_poisson_solve", "mg_poisson_smooth", "mgfr_tau",
             "mg_fr_solve_masked", "mgfr_tsc_density", "mgfr_tsc_force")
 
@@ -220,6 +222,26 @@ def mgfr_smooth(ctx: Context, rho, u, params: Params, nsweeps: int, variant: int
     if st != MGFR_OK:
         raise MgfrError(st, ctx.last_error())
     return u
+
+
+def mgfr_smooth32(ctx: Context, ub, e, f, params: Params, nsweeps: int, variant: int = 0,
+                  opts: mgfr_opts | None = None, stream=None):
+    """nsweeps red-black Newton-Gauss-Seidel sweeps of the single-precision correction
+    equation N(e) = f about the base ub (float32 device tensors of shape (N, N, N)), in place
+    on e.  variant 0: the mixed solver's finest-level kernel, 1: per-colour kernels, 2: fused
+    red-black kernel (opts.planes planes per workgroup, 0 = automatic)."""
+    import torch
+    for t in (ub, e, f):
+        if t.dtype != torch.float32:
+            raise TypeError("ub, e and f must be float32")
+    N = ub.shape[0]
+    if opts is None:
+        opts = mgfr_default_opts()
+    st = lib().mgfr_smooth32(ctx.handle, _ptr(ub), _ptr(e), _ptr(f), N, ctypes.byref(params.c()),
+                             ctypes.byref(opts), nsweeps, variant, _stream(stream))
+    if st != MGFR_OK:
+        raise MgfrError(st, ctx.last_error())
+    return e
 
 
 def mg_fr_solve(ctx: Context, rho, params: Params, opts: mgfr_opts | None = None, u=None,
@@ -402,7 +424,7 @@ def mg_fr_solve_batch(ctx: Context, rhos, params_list, opts: mgfr_opts | None = 
     return us, hists, st
 
 
-TUNED_FIELDS = ("pre", "post", "inner_cycles", "planes")
+TUNED_FIELDS = ("pre", "post", "inner_cycles", "planes", "tile")
 
 
 def mgfr_autotune(ctx: Context, rho, params: Params, base: mgfr_opts | None = None, u_scratch=None,
@@ -423,7 +445,7 @@ def mgfr_autotune(ctx: Context, rho, params: Params, base: mgfr_opts | None = No
             o = mgfr_opts()
             ctypes.memmove(ctypes.byref(o), ctypes.byref(base), ctypes.sizeof(o))
             for k in TUNED_FIELDS:
-                setattr(o, k, cache[key][k])
+                setattr(o, k, cache[key].get(k, 0))
             return o, cache[key]["ms"]
     if u_scratch is None:
         u_scratch = torch.empty_like(rho)

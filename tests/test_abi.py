@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_1110_1379_amd", "libmgfr.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mgf?r?_[a-z_]+)\s*\(", text)) - {"mgfr_ctx"})
+    return sorted(set(re.findall(r"\b(mgf?r?_[a-z0-9_]+)\s*\(", text)) - {"mgfr_ctx"})
 
 
 @pytest.fixture(scope="module")

@@ -20,27 +20,41 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
+def digest(path):
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
 def test_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
     # the committed figures describe the committed sources
-    for prec in ("mixed", "fp64", "masked", "poisson"):
-        assert bench.measured_traffic(prec, 512) == bench.MEASURED_TRAFFIC[prec]["bytes"]
+    for prec, entry in bench.MEASURED_TRAFFIC.items():
+        assert bench.measured_traffic(prec, 512) == entry["bytes"], prec
         assert bench.measured_traffic(prec, 256) is None
     assert bench.measured_traffic("tsc", 512) is None
     # a changed source voids the figure of every kernel built from it, and only those
     csrc = tmp_path / "paper_1110_1379_amd" / "csrc"
     shutil.copytree(os.path.join(ROOT, "paper_1110_1379_amd", "csrc"), csrc)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("mixed", 512) is not None
-    with open(csrc / "device_fp32.h", "a") as fh:
-        fh.write("\n// edited\n")
-    assert bench.measured_traffic("mixed", 512) is None
-    assert bench.measured_traffic("fp64", 512) is not None
-    with open(csrc / "kernel_types.h", "a") as fh:
-        fh.write("\n// edited\n")
-    assert all(bench.measured_traffic(p, 512) is None for p in ("fp64", "masked", "poisson"))
+    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", {
+        "a": {"bytes": 1.0, "sources": {"kernels_fp64.hip": digest(csrc / "kernels_fp64.hip"),
+                                        "kernel_types.h": digest(csrc / "kernel_types.h")}},
+        "b": {"bytes": 2.0, "sources": {"kernels_fp32.hip": digest(csrc / "kernels_fp32.hip"),
+                                        "kernel_types.h": digest(csrc / "kernel_types.h")}},
+        **bench.MEASURED_TRAFFIC})
+    for edited in sorted({name for e in bench.MEASURED_TRAFFIC.values() for name in e["sources"]}):
+        before = {p: bench.measured_traffic(p, 512) for p in bench.MEASURED_TRAFFIC}
+        with open(csrc / edited, "a") as fh:
+            fh.write("\n// edited\n")
+        for prec, entry in bench.MEASURED_TRAFFIC.items():
+            got = bench.measured_traffic(prec, 512)
+            if edited in entry["sources"]:
+                assert got is None, (edited, prec)
+            else:
+                assert got == before[prec], (edited, prec)
 
 
-@pytest.mark.parametrize("prec,bpc", [("fp64", 24), ("mixed", 16)])
+@pytest.mark.parametrize("prec,bpc", [("fp64", 24), ("mixed", 12)])
 def test_batched_roofline(prec, bpc):
     s = {"sweep_launches": 8, "sweep_ms": 2.0, "sweep_bytes": 4.0e9}
     r = bench._batched_roofline(s, prec)

@@ -45,25 +45,48 @@ def rel_err(u, ref):
     return np.abs(u - ref).max() / np.abs(ref).max()
 
 
-@pytest.mark.parametrize("N0,thr,sizes", [(32, (3.0, 8.0), (8, 4)), (64, (10.0, 40.0, 150.0), (16, 8, 4))])
-def test_patches_match_oracle(mg, ctx, N0, thr, sizes):
-    say(f"[patches] N0={N0}")
-    box, fr0 = 2.0 * N0, 1e-5
-    rho0, patches, rho_packed = inputs.amr_workload(N0, seed=3, thresholds=thr, sizes=sizes)
+# the last case holds 64^3 patches (32 parent cells) on both levels, with 5-level hierarchies
+PATCH_CASES = [(32, (3.0, 8.0), (8, 4)), (64, (10.0, 40.0, 150.0), (16, 8, 4)), (64, (3.0, 10.0), (32, 16, 8, 4))]
+
+# (name, flags, unit_n): the default engine with units of side <= 16 solved whole by one
+# workgroup (larger ones launched per phase on their fine levels and finished by one
+# workgroup each below 16), the same with 8 and with 64 (every unit whole), and the per-phase
+# engine with host stop tests
+ENGINES = [("units16", 0, 0), ("units8", 0, 8), ("units64", 0, 64), ("phases", 16, 0)]
+
+_patch_cache = {}
+
+
+def patch_case(mg, ctx, N0, thr, sizes, tol):
+    """Domain solution (GPU), patches and the oracle's patch solutions at tol, computed once."""
+    key = (N0, thr, sizes, tol)
+    if key not in _patch_cache:
+        box, fr0 = 2.0 * N0, 1e-5
+        rho0, patches, rho_packed = inputs.amr_workload(N0, seed=3, thresholds=thr, sizes=sizes)
+        params = mg.Params(box_mpc_h=box, fr0_abs=fr0)
+        model = O.Model(box_mpc_h=box, fr0_abs=fr0)
+        ud, hist, st = mg.mg_fr_solve(ctx, dev(rho0), params, mg.mgfr_default_opts(tol=1e-12))
+        assert st == mg.MGFR_OK
+        rho_list = [rho_packed[p["offset"]:p["offset"] + p["n"] ** 3].reshape((p["n"],) * 3) for p in patches]
+        us, hs, sts = O.solve_patches(ud.cpu().numpy(), patches, rho_list, model, O.Opts(tol=tol))
+        assert all(st == 0 for st in sts)
+        _patch_cache[key] = (ud, patches, rho_packed, params, us)
+    return _patch_cache[key]
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=[e[0] for e in ENGINES])
+@pytest.mark.parametrize("N0,thr,sizes", PATCH_CASES)
+def test_patches_match_oracle(mg, ctx, N0, thr, sizes, engine):
+    say(f"[patches] N0={N0} sizes={sizes} engine={engine[0]}")
+    ud, patches, rho_packed, params, us = patch_case(mg, ctx, N0, thr, sizes, 1e-10)
     assert len(patches) >= 4 and max(p["level"] for p in patches) >= 2
-    params = mg.Params(box_mpc_h=box, fr0_abs=fr0)
-    model = O.Model(box_mpc_h=box, fr0_abs=fr0)
-    ud, hist, st = mg.mg_fr_solve(ctx, dev(rho0), params, mg.mgfr_default_opts(tol=1e-12))
-    assert st == mg.MGFR_OK
-    u_dom = ud.cpu().numpy()
-    opts = mg.mgfr_default_opts(tol=1e-10)
+    if max(sizes) == 32:
+        assert {p["level"] for p in patches if p["n"] == 64} == {1, 2}
+    opts = mg.mgfr_default_opts(tol=1e-10, flags=engine[1], unit_n=engine[2])
     up, hists, st = mg.mg_fr_solve_patches(ctx, ud, patches, dev(rho_packed), params, opts)
     assert st == mg.MGFR_OK, ctx.last_error()
     up = up.cpu().numpy()
-    rho_list = [rho_packed[p["offset"]:p["offset"] + p["n"] ** 3].reshape((p["n"],) * 3) for p in patches]
-    us, hs, sts = O.solve_patches(u_dom, patches, rho_list, model, O.Opts(tol=1e-10))
     for i, p in enumerate(patches):
-        assert sts[i] == 0
         g = up[p["offset"]:p["offset"] + p["n"] ** 3].reshape((p["n"],) * 3)
         assert rel_err(g, us[i]) <= 1e-10, (i, p)
         assert hists[i][-1] <= 1e-10
@@ -96,48 +119,66 @@ def test_patch_layout_errors(mg, ctx):
     assert st == mg.MGFR_EINVAL
 
 
-def test_batch_of_boxes_matches_oracle(mg, ctx):
-    say("[batch] boxes")
+# up to 128^3, the largest box of the batch workload (6-level hierarchy)
+BOX_SIDES = [16, 32, 16, 32, 8, 64, 128]
+
+
+_box_cache = {}
+
+
+def box_specs():
     rng = np.random.default_rng(5)
     specs = []
-    for b, N in enumerate([16, 32, 16, 32, 8, 64]):
+    for b, N in enumerate(BOX_SIDES):
         fr0 = 10.0 ** rng.uniform(-6, -4)
         sigma = rng.uniform(1.0, 2.0)
         specs.append((N, float(N), fr0, inputs.lognormal(N, sigma, -1.5, seed=b)))
+    return specs
+
+
+def box_refs(specs):
+    """The oracle's solution of every box at 1e-10, computed once."""
+    if "refs" not in _box_cache:
+        refs = []
+        for N, box, fr0, rho in specs:
+            ref, _, st_ref = O.solve(rho, O.Model(box_mpc_h=box, fr0_abs=fr0), O.Opts(tol=1e-10))
+            assert st_ref == 0
+            refs.append(ref)
+        _box_cache["refs"] = refs
+    return _box_cache["refs"]
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=[e[0] for e in ENGINES])
+def test_batch_of_boxes_matches_oracle(mg, ctx, engine):
+    say(f"[batch] boxes engine={engine[0]}")
+    specs = box_specs()
+    refs = box_refs(specs)
     rhos = [dev(s[3]) for s in specs]
     params = [mg.Params(box_mpc_h=s[1], fr0_abs=s[2]) for s in specs]
-    us, hists, st = mg.mg_fr_solve_batch(ctx, rhos, params, mg.mgfr_default_opts(tol=1e-10))
+    opts = mg.mgfr_default_opts(tol=1e-10, flags=engine[1], unit_n=engine[2])
+    us, hists, st = mg.mg_fr_solve_batch(ctx, rhos, params, opts)
     assert st == mg.MGFR_OK, ctx.last_error()
-    for (N, box, fr0, rho), u, h in zip(specs, us, hists):
-        ref, _, st_ref = O.solve(rho, O.Model(box_mpc_h=box, fr0_abs=fr0), O.Opts(tol=1e-10))
-        assert st_ref == 0
+    for ref, u, h in zip(refs, us, hists):
         assert rel_err(u.cpu().numpy(), ref) <= 1e-10
         assert h[-1] <= 1e-10
     # one box alone gives the same field as in the batch (units are independent)
-    u1, h1, st1 = mg.mg_fr_solve_batch(ctx, rhos[1:2], params[1:2], mg.mgfr_default_opts(tol=1e-10))
+    u1, h1, st1 = mg.mg_fr_solve_batch(ctx, rhos[1:2], params[1:2], opts)
     assert st1 == mg.MGFR_OK
     assert np.array_equal(u1[0].cpu().numpy(), us[1].cpu().numpy())
 
 
-@pytest.mark.parametrize("N0,thr,sizes", [(32, (3.0, 8.0), (8, 4)), (64, (10.0, 40.0, 150.0), (16, 8, 4))])
+@pytest.mark.parametrize("engine", ENGINES, ids=[e[0] for e in ENGINES])
+@pytest.mark.parametrize("N0,thr,sizes", PATCH_CASES)
 @pytest.mark.parametrize("inner", [1, 2])
-def test_mixed_patches_match_oracle(mg, ctx, N0, thr, sizes, inner):
-    say(f"[patches mixed] N0={N0} inner={inner}")
-    box, fr0 = 2.0 * N0, 1e-5
-    rho0, patches, rho_packed = inputs.amr_workload(N0, seed=3, thresholds=thr, sizes=sizes)
-    params = mg.Params(box_mpc_h=box, fr0_abs=fr0)
-    model = O.Model(box_mpc_h=box, fr0_abs=fr0)
-    ud, hist, st = mg.mg_fr_solve(ctx, dev(rho0), params, mg.mgfr_default_opts(tol=1e-12))
-    assert st == mg.MGFR_OK
-    u_dom = ud.cpu().numpy()
-    opts = mg.mgfr_default_opts(tol=1e-8, precision=mg.MGFR_MIXED, inner_cycles=inner)
+def test_mixed_patches_match_oracle(mg, ctx, N0, thr, sizes, inner, engine):
+    say(f"[patches mixed] N0={N0} sizes={sizes} inner={inner} engine={engine[0]}")
+    ud, patches, rho_packed, params, us = patch_case(mg, ctx, N0, thr, sizes, 1e-11)
+    opts = mg.mgfr_default_opts(tol=1e-8, precision=mg.MGFR_MIXED, inner_cycles=inner, flags=engine[1],
+                                unit_n=engine[2])
     up, hists, st = mg.mg_fr_solve_patches(ctx, ud, patches, dev(rho_packed), params, opts)
     assert st == mg.MGFR_OK, ctx.last_error()
     up = up.cpu().numpy()
-    rho_list = [rho_packed[p["offset"]:p["offset"] + p["n"] ** 3].reshape((p["n"],) * 3) for p in patches]
-    us, hs, sts = O.solve_patches(u_dom, patches, rho_list, model, O.Opts(tol=1e-11))
     for i, p in enumerate(patches):
-        assert sts[i] == 0
         g = up[p["offset"]:p["offset"] + p["n"] ** 3].reshape((p["n"],) * 3)
         assert rel_err(g, us[i]) <= 1e-6, (i, p, rel_err(g, us[i]))
         h = np.asarray(hists[i])
@@ -145,23 +186,18 @@ def test_mixed_patches_match_oracle(mg, ctx, N0, thr, sizes, inner):
         assert np.all(np.diff(h) < 0), (i, h)
 
 
-def test_mixed_batch_of_boxes_matches_oracle(mg, ctx):
-    say("[batch mixed] boxes")
-    rng = np.random.default_rng(5)
-    specs = []
-    for b, N in enumerate([16, 32, 16, 32, 8, 64]):
-        fr0 = 10.0 ** rng.uniform(-6, -4)
-        sigma = rng.uniform(1.0, 2.0)
-        specs.append((N, float(N), fr0, inputs.lognormal(N, sigma, -1.5, seed=b)))
+@pytest.mark.parametrize("engine", ENGINES, ids=[e[0] for e in ENGINES])
+def test_mixed_batch_of_boxes_matches_oracle(mg, ctx, engine):
+    say(f"[batch mixed] boxes engine={engine[0]}")
+    specs = box_specs()
+    # reference at 1e-10 (some of these boxes have their double-precision floor above 1e-12)
+    refs = box_refs(specs)
     rhos = [dev(s[3]) for s in specs]
     params = [mg.Params(box_mpc_h=s[1], fr0_abs=s[2]) for s in specs]
-    opts = mg.mgfr_default_opts(tol=1e-8, precision=mg.MGFR_MIXED)
+    opts = mg.mgfr_default_opts(tol=1e-8, precision=mg.MGFR_MIXED, flags=engine[1], unit_n=engine[2])
     us, hists, st = mg.mg_fr_solve_batch(ctx, rhos, params, opts)
     assert st == mg.MGFR_OK, ctx.last_error()
-    for (N, box, fr0, rho), u, h in zip(specs, us, hists):
-        # reference at 1e-10 (some of these boxes have their double-precision floor above 1e-12)
-        ref, _, st_ref = O.solve(rho, O.Model(box_mpc_h=box, fr0_abs=fr0), O.Opts(tol=1e-10))
-        assert st_ref == 0
+    for ref, u, h in zip(refs, us, hists):
         assert rel_err(u.cpu().numpy(), ref) <= 1e-6
         assert h[-1] <= 1e-8
     # a single box alone gives the same field as in the batch
@@ -170,13 +206,16 @@ def test_mixed_batch_of_boxes_matches_oracle(mg, ctx):
     assert np.array_equal(u1[0].cpu().numpy(), us[1].cpu().numpy())
 
 
+@pytest.mark.parametrize("engine", [e for e in ENGINES if e[0] in ("units16", "phases")], ids=["units16", "phases"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_graph_replays_match_eager(mg, ctx, precision):
+def test_graph_replays_match_eager(mg, ctx, precision, engine):
     """With MGFR_GRAPH the launches of one cycle are captured once and replayed for every
-    later cycle, with the norms, their host copy and the active-flag upload run eagerly in
-    between.  Every replay must give what the eager launches give: the per-cycle residual
-    histories and the final fields are compared bit for bit."""
-    say(f"[graph] {precision}")
+    later cycle (default engine: with the device stop test inside the graph; per-phase engine:
+    with the norms, their host copy and the active-flag upload run eagerly in between).  Every
+    replay must give what the eager launches give: the per-cycle residual histories and the
+    final fields are compared bit for bit.  MGFR_PROFILE (HIP events around the finest-level
+    sweeps) must not change them either."""
+    say(f"[graph] {precision} engine={engine[0]}")
     prec = mg.MGFR_MIXED if precision == "mixed" else mg.MGFR_FP64
     tol = 1e-8 if precision == "mixed" else 1e-10
     rng = np.random.default_rng(7)
@@ -187,12 +226,12 @@ def test_graph_replays_match_eager(mg, ctx, precision):
     params = [mg.Params(box_mpc_h=s[1], fr0_abs=s[2]) for s in specs]
     out = {}
     for flags in (0, mg.MGFR_GRAPH, mg.MGFR_PROFILE):
-        opts = mg.mgfr_default_opts(tol=tol, precision=prec, flags=flags)
+        opts = mg.mgfr_default_opts(tol=tol, precision=prec, flags=flags | engine[1], unit_n=engine[2])
         us, hists, st = mg.mg_fr_solve_batch(ctx, rhos, params, opts)
         assert st == mg.MGFR_OK, ctx.last_error()
         out[flags] = ([u.cpu().numpy() for u in us], [np.asarray(h) for h in hists])
         if flags == mg.MGFR_PROFILE:
-            check_profile(mg, ctx, opts)
+            check_profile(mg, ctx, opts, [s[0] for s in specs], out[flags][1])
     assert max(len(h) for h in out[0][1]) >= 4          # several replays
     for f in (mg.MGFR_GRAPH, mg.MGFR_PROFILE):
         for a, b in zip(out[0][0], out[f][0]):
@@ -201,33 +240,48 @@ def test_graph_replays_match_eager(mg, ctx, precision):
             assert np.array_equal(a, b)
     # patches (ghost faces, units of several depths) under a graph
     N0 = 32
-    rho0, patches, rho_packed = inputs.amr_workload(N0, seed=3, thresholds=(3.0, 8.0), sizes=(8, 4))
+    rho0, patches, rho_packed = inputs.amr_workload(N0, seed=3, thresholds=(3.0, 8.0), sizes=(16, 8, 4))
     p = mg.Params(box_mpc_h=2.0 * N0, fr0_abs=1e-5)
     ud, _, st = mg.mg_fr_solve(ctx, dev(rho0), p, mg.mgfr_default_opts(tol=1e-12))
     assert st == mg.MGFR_OK
     res = {}
     for flags in (0, mg.MGFR_GRAPH, mg.MGFR_PROFILE):
-        opts = mg.mgfr_default_opts(tol=tol, precision=prec, flags=flags)
+        opts = mg.mgfr_default_opts(tol=tol, precision=prec, flags=flags | engine[1], unit_n=engine[2])
         up, hists, st = mg.mg_fr_solve_patches(ctx, ud, patches, dev(rho_packed), p, opts)
         assert st == mg.MGFR_OK, ctx.last_error()
         res[flags] = (up.cpu().numpy(), [np.asarray(h) for h in hists])
         if flags == mg.MGFR_PROFILE:
-            check_profile(mg, ctx, opts)
+            check_profile(mg, ctx, opts, [q["n"] for q in patches], res[flags][1])
     for f in (mg.MGFR_GRAPH, mg.MGFR_PROFILE):
         assert np.array_equal(res[0][0], res[f][0])
         for a, b in zip(res[0][1], res[f][1]):
             assert np.array_equal(a, b)
 
 
-def check_profile(mg, ctx, opts):
-    """MGFR_PROFILE on a batched solve: both colour launches of every finest-level sweep are
-    timed (every V-cycle of a run whose units have more than one level), and the bytes
-    credited are 24 (FP64) or 16 (single-precision correction) per finest-level cell update of
-    the active units."""
+def check_profile(mg, ctx, opts, sides, hists):
+    """MGFR_PROFILE on a batched solve: both colour launches of the finest-level sweeps are
+    timed, and the bytes credited are 24 (FP64) or 12 (single-precision correction) per
+    finest-level cell update.  Per-phase engine: every unit's finest level, the units active
+    in each cycle.  Default engine: the finest levels of the units launched per phase (side
+    above unit_n), every cycle each of them ran (the sweeps inside the one-workgroup kernels
+    are not timed)."""
     s = mg.mgfr_get_stats(ctx)
     mixed = opts.precision == mg.MGFR_MIXED
-    vcycles = s["inner_cycles"] if mixed else s["cycles"]
-    per = 2 * (opts.pre + opts.post)
-    assert 0 < s["sweep_launches"] <= per * vcycles and s["sweep_launches"] % per == 0, s
-    assert s["sweep_ms"] > 0.0
-    assert s["sweep_bytes"] == (16 if mixed else 24) * s["finest_updates"], s
+    bpc = 12 if mixed else 24
+    per_sweep = 2 * (opts.pre + opts.post)
+    if opts.flags & mg.MGFR_PER_PHASE:
+        vcycles = s["inner_cycles"] if mixed else s["cycles"]
+        assert 0 < s["sweep_launches"] <= per_sweep * vcycles and s["sweep_launches"] % per_sweep == 0, s
+        assert s["sweep_ms"] > 0.0
+        assert s["sweep_bytes"] == bpc * s["finest_updates"], s
+        return
+    W = max(opts.unit_n or 16, opts.coarsest_n)
+    inner = opts.inner_cycles if mixed else 1
+    large = [(n, len(h) - 1) for n, h in zip(sides, hists) if n > W]
+    assert s["sweep_bytes"] == bpc * sum(n ** 3 * k for n, k in large) * (opts.pre + opts.post) * inner, s
+    if large:
+        kmax = max(k for _, k in large)
+        assert s["sweep_launches"] >= per_sweep * inner * kmax and s["sweep_launches"] % (per_sweep * inner) == 0, s
+        assert s["sweep_ms"] > 0.0
+    else:
+        assert s["sweep_launches"] == 0, s

@@ -59,8 +59,8 @@ MUTANTS = {
         "dL += g->C * ((r * bg + bi) * (ug - ui) + (bg + bi) * (r - 1.0));",
         "dL += g->C * ((bg + bi) * (ug - ui) + (bg + bi) * (r - 1.0));"),
     "masked cells relaxed too": (
-        "if (!(g->mask[q] > 0.0)) continue;\n                    ++g_updates;",
-        "if (!(g->mask[q] > -2.0)) continue;\n                    ++g_updates;"),
+        "if (!(g->mask[q] > 0.0)) continue;\n                    double d;",
+        "if (!(g->mask[q] > -2.0)) continue;\n                    double d;"),
     "correction prolongated into masked cells": (
         "if (F->g.mask[q] > 0.0) F->u[q] += corr[q];",
         "F->u[q] += corr[q];"),
