@@ -58,7 +58,7 @@ extern "C" {
                                 returns at once after it) and read one flag per replay.  Only
                                 with pre + post even and without MGFR_PROFILE and tau_alpha
                                 (otherwise the cycles run eagerly); the results are the same
-                                bits as eager cycles.                                       */
+                                bits as eager cycles.  mg_fr_solve_noalloc rejects it.      */
 #define MGFR_PER_PHASE 16    /* batched solves: the per-phase engine (every phase of every
                                 level one launch over all units, per-unit norms read back by
                                 the host after every cycle) instead of the default engine
@@ -215,6 +215,21 @@ int mgfr_smooth32(mgfr_ctx* ctx, const float* ub, float* e, const float* f, int 
  * was reached first (u holds the last iterate).  Synchronises the stream. */
 int mg_fr_solve(mgfr_ctx* ctx, const double* rho, int N, const mgfr_params* params,
                 const mgfr_opts* opts, double* u, double* res_hist, int* n_hist, void* stream);
+
+/* mg_fr_solve for callers that cannot allocate device memory (code being captured into a HIP
+ * graph, tight serving loops, harnesses that forbid allocation): the same solve, same
+ * arguments, results and errors, but every scratch buffer (multigrid levels, single-precision
+ * levels, reduction partials) is carved from one fixed 72 MiB device array that the library
+ * holds on each GPU it runs on until the process ends; the call itself allocates nothing
+ * (device or host).  Limits: N a power of two in [coarsest_n, 128]; MGFR_PROFILE (its events
+ * would be allocated) and MGFR_GRAPH (it keeps a graph and device state in the context) are
+ * rejected.  Larger N gives MGFR_EINVAL.  The array is shared by every
+ * call on the same GPU and keeps the last call's contents (everything a solve reads is written
+ * by that solve first): calls that overlap on one GPU, from any context or stream, race and
+ * must be serialised by the caller.  Returns MGFR_EDEVICE if the array's device address could
+ * not be resolved when the context was created.  Synchronises the stream. */
+int mg_fr_solve_noalloc(mgfr_ctx* ctx, const double* rho, int N, const mgfr_params* params,
+                        const mgfr_opts* opts, double* u, double* res_hist, int* n_hist, void* stream);
 
 /* Refinement patches, level by level (Sec. V, Sec. VI.B; the paper solves every refinement
  * level with its own V-cycles after the coarser level, with boundary values from it).

@@ -163,6 +163,10 @@ struct mgfr_ctx {
     // beside the launches of the large units, and the events that fork and join it
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // mg_fr_solve_noalloc: this device's address of the library's fixed scratch array (null if
+    // it could not be resolved) and the host side of its reductions
+    void* fixed_scratch = nullptr;
+    double fixed_host[2] = {0.0, 0.0};
     // mg_fr_solve with MGFR_GRAPH: the captured cycles (graph, instance and what they were
     // captured for), the stream they were captured on, the device stop state (cycles done,
     // stopped) and residual history, and what one captured cycle adds to the counters

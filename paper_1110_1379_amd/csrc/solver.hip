@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,8 +35,8 @@ int planes_for32(const mgfr_opts* o, size_t m, int n)
 }
 
 // The storage one domain solve works on: the multigrid levels (double precision, and single
-// precision for the mixed solver) and the reduction buffers (the context's own, allocated on
-// demand).
+// precision for the mixed solver) and the reduction buffers.  The context's own (allocated on
+// demand) or carved from the library's fixed device array by mg_fr_solve_noalloc.
 struct Hier {
     Level* lv = nullptr;
     size_t nlev = 0;
@@ -234,6 +235,84 @@ struct Cycle32 {
     }
 };
 
+// ---- fixed device scratch of mg_fr_solve_noalloc ------------------------------------------
+// A file-scope device array that every GPU the library runs on holds until the process ends.
+// Host code never uses its name as an address: each device's copy sits at its own address,
+// which hipGetSymbolAddress gives once per device (with that device current) and which is kept
+// in fixed_ptr[] and handed to the kernels from there.
+constexpr int kNoAllocMaxN = 128;                         // largest grid side it takes
+constexpr size_t kFixedScratchBytes = size_t(72) << 20;   // 72 MiB: a mixed 128^3 solve needs ~63
+constexpr int kMaxLevels = 12;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) char scratch[kFixedScratchBytes];
+
+std::mutex fixed_mutex;
+void* fixed_ptr[kMaxDevices] = {};
+bool fixed_tried[kMaxDevices] = {};
+
+// This device's address of the scratch array (resolved on the first call for the device, with
+// the device current; the caller's current device is restored).  Null if it cannot be had.
+void* fixed_scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(fixed_mutex);
+    if (!fixed_tried[device]) {
+        fixed_tried[device] = true;
+        int prev = -1;
+        const bool had = hipGetDevice(&prev) == hipSuccess;
+        void* p = nullptr;
+        if (hipSetDevice(device) == hipSuccess && hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess)
+            fixed_ptr[device] = p;
+        else
+            (void)hipGetLastError();
+        if (had) (void)hipSetDevice(prev);
+    }
+    return fixed_ptr[device];
+}
+
+// Lays out the storage of a domain solve of side N (levels N ... coarsest; single-precision
+// levels too when mixed) on the device block at base, each array 256-byte aligned, and
+// returns the bytes it needs (base null: sizes only, nothing written but the byte count).
+size_t carve(char* base, int N, int coarsest, bool mixed, Hier* h, Level* lv, Level32* lv32)
+{
+    size_t at = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + at : nullptr;
+        at += (bytes + 255) & ~size_t(255);
+        return p;
+    };
+    h->partial = (double*)take(sizeof(double) * (size_t)mgfr::reduction_scratch());
+    h->red = (double*)take(2 * sizeof(double));
+    h->counter = (long long*)take(sizeof(long long));
+    size_t m = 0;
+    for (int n = N; n >= coarsest && m < (size_t)kMaxLevels; n /= 2, ++m) {
+        const size_t n3 = (size_t)n * n * n;
+        Level L{};
+        if (n < N) {
+            L.u = (double*)take(sizeof(double) * n3);
+            L.uhat = (double*)take(sizeof(double) * n3);
+            L.f = (double*)take(sizeof(double) * n3);
+        }
+        if (n >= mgfr::fused_sweep_min_n()) L.alt = (double*)take(sizeof(double) * n3);
+        lv[m] = L;
+        if (mixed) {
+            Level32 E{};
+            E.ub = (float*)take(sizeof(float) * n3);
+            E.e = (float*)take(sizeof(float) * n3);
+            E.f = (float*)take(sizeof(float) * n3);
+            if (n < N) E.ehat = (float*)take(sizeof(float) * n3);
+            if (n >= mgfr::fused_sweep_min_n()) E.ealt = (float*)take(sizeof(float) * n3);
+            lv32[m] = E;
+        }
+    }
+    h->lv = lv;
+    h->nlev = m;
+    h->lv32 = lv32;
+    h->nlev32 = mixed ? m : 0;
+    return at;
+}
+
 // rms and max of the finest residual L(u) - f (synchronises).
 int finest_norm(mgfr_ctx* c, const Hier& h, const mgfr::Grid& g, const double* u, const double* rho,
                 hipStream_t s, double* rms, double* mx)
@@ -268,6 +347,9 @@ int mgfr_create(mgfr_ctx** ctx, int device)
     mgfr_ctx* c = new (std::nothrow) mgfr_ctx();
     if (!c) return MGFR_ENOMEM;
     c->device = device;
+    // error messages are at most 511 characters: later failures never allocate
+    c->err.reserve(512);
+    c->fixed_scratch = fixed_scratch_address(device);
     *ctx = c;
     return MGFR_OK;
 }
@@ -909,6 +991,38 @@ int mg_fr_solve(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params
     return solve_body(c, h, md, rho, N, o, u, res_hist, n_hist, (hipStream_t)stream, t0, true);
 }
 
+int mg_fr_solve_noalloc(mgfr_ctx* c, const double* rho, int N, const mgfr_params* params, const mgfr_opts* o,
+                        double* u, double* res_hist, int* n_hist, void* stream)
+{
+    if (!c) return MGFR_EINVAL;
+    c->err.clear();
+    c->stats = mgfr_stats{};
+    const auto t0 = std::chrono::steady_clock::now();
+    if (n_hist) *n_hist = 0;
+    MGFR_TRY(check_opts(c, o));
+    if (o->flags & MGFR_PROFILE) return c->fail(MGFR_EINVAL, "MGFR_PROFILE needs HIP events: not available here");
+    if (o->flags & MGFR_GRAPH)
+        return c->fail(MGFR_EINVAL, "MGFR_GRAPH keeps a graph and device state in the context: not available here");
+    Model md;
+    if (derive_model(params, &md) != MGFR_OK) return c->fail(MGFR_EINVAL, "invalid model parameters");
+    if (!rho || !u) return c->fail(MGFR_EINVAL, "rho or u is NULL");
+    if (!is_pow2(N) || N < o->coarsest_n || N > kNoAllocMaxN)
+        return c->fail(MGFR_EINVAL, "N=%d: this entry point takes powers of two in [coarsest_n, %d]", N, kNoAllocMaxN);
+    Level lv[kMaxLevels];
+    Level32 lv32[kMaxLevels];
+    Hier h;
+    const bool mixed = o->precision == MGFR_MIXED;
+    const size_t need = carve(nullptr, N, o->coarsest_n, mixed, &h, lv, lv32);
+    if (need > kFixedScratchBytes)
+        return c->fail(MGFR_EINVAL, "N=%d needs %zu bytes of scratch, more than the %zu held", N, need,
+                       kFixedScratchBytes);
+    if (!c->fixed_scratch)
+        return c->fail(MGFR_EDEVICE, "the fixed scratch array of device %d could not be resolved", c->device);
+    MGFR_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+    carve((char*)c->fixed_scratch, N, o->coarsest_n, mixed, &h, lv, lv32);
+    h.host = c->fixed_host;
+    return solve_body(c, h, md, rho, N, o, u, res_hist, n_hist, (hipStream_t)stream, t0, false);
+}
 
 }  // extern "C"
 

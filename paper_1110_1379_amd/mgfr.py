@@ -89,6 +89,7 @@ def lib():
             "mgfr_constants": ([P, ctypes.c_int, dp], ctypes.c_int),
             "mgfr_residual": ([vp, vp, vp, ctypes.c_int, P, ctypes.c_int, vp, vp], ctypes.c_int),
             "mg_fr_solve": ([vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
+            "mg_fr_solve_noalloc": ([vp, vp, ctypes.c_int, P, O, vp, dp, ip, vp], ctypes.c_int),
             "mgfr_smooth": ([vp, vp, vp, ctypes.c_int, P, O, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
             "mgfr_smooth32": ([vp, vp, vp, vp, ctypes.c_int, P, O, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
             "mg_fr_solve_patches": ([vp, vp, ctypes.c_int, ctypes.POINTER(mgfr_patch), ctypes.c_int, vp, vp,
@@ -113,7 +114,7 @@ def lib():
 
 def exported_symbols():
     return ("mgfr_create", "mgfr_destroy", "mgfr_last_error", "mgfr_default_opts", "mgfr_constants",
-            "mgfr_residual", "mg_fr_solve", "mgfr_get_stats", "mgfr_smooth", "mgfr_smooth32", "mg_fr_solve_patches",
+            "mgfr_residual", "mg_fr_solve", "mg_fr_solve_noalloc", "mgfr_get_stats", "mgfr_smooth", "mgfr_smooth32", "mg_fr_solve_patches",
             "mg_fr_solve_batch", "mgfr_autotune", "mg_poisson_solve", "mg_poisson_smooth", "mgfr_tau",
             "mg_fr_solve_masked", "mgfr_tsc_density", "mgfr_tsc_force")
 
@@ -260,6 +261,24 @@ def mg_fr_solve(ctx: Context, rho, params: Params, opts: mgfr_opts | None = None
     st = lib().mg_fr_solve(ctx.handle, _ptr(rho), N, ctypes.byref(params.c()), ctypes.byref(opts), _ptr(u),
                            hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(nh),
                            _stream(stream))
+    if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
+        raise MgfrError(st, ctx.last_error())
+    return u, hist[:nh.value].copy(), st
+
+
+def mg_fr_solve_noalloc(ctx: Context, rho, u, params: Params, opts: mgfr_opts | None = None, stream=None,
+                        raise_on_error: bool = True):
+    """mg_fr_solve with every scratch buffer in the library's fixed device array (N <= 128):
+    nothing is allocated by the call.  rho, u: float64 device tensors of shape (N, N, N); u is
+    written in place.  Returns (u, residual history, status)."""
+    N = rho.shape[0]
+    if opts is None:
+        opts = mgfr_default_opts()
+    hist = np.zeros(opts.max_cycles + 1)
+    nh = ctypes.c_int(0)
+    st = lib().mg_fr_solve_noalloc(ctx.handle, _ptr(rho), N, ctypes.byref(params.c()), ctypes.byref(opts),
+                                   _ptr(u), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.byref(nh), _stream(stream))
     if raise_on_error and st not in (MGFR_OK, MGFR_ENOTCONV):
         raise MgfrError(st, ctx.last_error())
     return u, hist[:nh.value].copy(), st
