@@ -205,6 +205,39 @@ def time_domain(mgfr, ctx, rho_d, params, prec, tol, steps, warmup, profile=True
     return res, u_d, opts
 
 
+def graph_ab(mgfr, ctx, rho_d, params, opts, steps):
+    """The timed configuration without event timing, with eager cycles (a host read of the
+    residual after every cycle) and with MGFR_GRAPH (two cycles per captured graph, the stop
+    test on the device, one flag read per replay): time per solve of each, and whether the
+    two fields are the same bits.  Outside the timed region of the main metric."""
+    import ctypes
+    import torch
+    out = {}
+    fields = {}
+    for name, flag in (("eager", 0), ("graph", mgfr.MGFR_GRAPH)):
+        o = mgfr.mgfr_opts()
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(opts), ctypes.sizeof(o))
+        o.flags = (o.flags & ~(mgfr.MGFR_PROFILE | mgfr.MGFR_GRAPH)) | flag
+        u_d = torch.empty_like(rho_d)
+        stream = torch.cuda.current_stream()
+
+        def solve():
+            _, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, o, u=u_d, stream=stream)
+            if st != mgfr.MGFR_OK:
+                raise SystemExit(f"{name} solve failed: {mgfr.STATUS_NAMES.get(st, st)} {ctx.last_error()}")
+            return hist
+
+        ms, hist = _timed(solve, steps, 1)
+        out[f"{name}_ms"] = ms
+        out[f"{name}_cycles"] = len(hist) - 1
+        fields[name] = u_d
+    out["bitwise_equal"] = bool(torch.equal(fields["eager"], fields["graph"]))
+    out["faster"] = "graph" if out["graph_ms"] < out["eager_ms"] else "eager"
+    log(f"graph A/B: eager {out['eager_ms']:.2f} ms, graph {out['graph_ms']:.2f} ms, "
+        f"same bits {out['bitwise_equal']}")
+    return out
+
+
 def stop_rule_comparison(mgfr, ctx, rho_d, params, opts, u_ref, steps=3):
     """The solve of the timed configuration stopped by the truncation-error rule of Sec. V.B
     with MLAPM's constants, rms(d) <= max(1e-6, 0.03 rms(tau)), against the field of the timed
@@ -306,6 +339,8 @@ def bench_domain(args):
             "max_abs": d.max().item(), "rms_abs": d.square().mean().sqrt().item(),
             "max_rel": d.max().item() / ref if ref > 0 else None}
         del d
+    # graph-captured cycles against eager ones, per precision, without the event timing
+    out["graph_ab"] = {p: graph_ab(mgfr, ctx, rho_d, params, used[p], args.steps) for p in runs}
     if not args.no_stop_rule:
         out["stop_rule_comparison"] = stop_rule_comparison(mgfr, ctx, rho_d, params, used[headp], fields[headp])
     if not args.no_cpu_baseline:
@@ -607,7 +642,7 @@ def bench_amr(args):
     from paper_1110_1379_amd import inputs, mgfr
     N0, box, fr0 = 256, 256.0, 1e-5
     log("generating the AMR workload")
-    rho0, patches, rho_packed = inputs.amr_workload(N0)
+    rho0, patches, rho_packed = inputs.amr_box(N0)
     cells = int(sum(p["n"] ** 3 for p in patches))
     log(f"{len(patches)} patches, {cells} patch cells")
     ctx = mgfr.Context(0)
@@ -655,7 +690,7 @@ def bench_amr(args):
            "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if headp == "fp64" else "f32+f64",
            "data": "synthetic",
-           "config": {"workload": f"amr: {N0}^3 domain (lognormal sigma 2), {len(patches)} cube patches "
+           "config": {"workload": f"amr: {N0}^3 domain (lognormal sigma 3, P ~ k^-1), {len(patches)} cube patches "
                                   f"8^3-64^3 over {max(p['level'] for p in patches)} levels "
                                   f"(contrast > 50/200/1000), {cells} patch cells, tol {args.tol:g}",
                       "precision": headp, "graph": bool(args.graph), "engine": _engine_name(args),
@@ -671,7 +706,7 @@ def bench_amr(args):
         import oracle
         Ns = 128
         log(f"timing the CPU oracle on the patches of a {Ns}^3 domain of the same recipe")
-        r0, ps, rps = inputs.amr_workload(Ns)
+        r0, ps, rps = inputs.amr_box(Ns)
         m = oracle.Model(box_mpc_h=box * Ns / N0, fr0_abs=fr0)
         u0, _, st0 = oracle.solve(r0, m, oracle.Opts(tol=args.tol))  # the parent solution, untimed
         rl = [rps[p["offset"]:p["offset"] + p["n"] ** 3].reshape((p["n"],) * 3) for p in ps]

@@ -94,8 +94,9 @@ typedef struct mgfr_opts {
                              mg_fr_solve only: the batched and masked solves reject it
                              with MGFR_EINVAL                                      [0]      */
     int unit_n;           /* batched solves (default engine): units, and the levels of larger
-                             units, of side <= unit_n are relaxed by one workgroup each; 0 =
-                             16; values below coarsest_n count as coarsest_n       [0]      */
+                             units, of side <= unit_n are relaxed by one workgroup each (up
+                             to 16 with every level in LDS); 0 = 16; rounded down to a power
+                             of two; values below coarsest_n count as coarsest_n    [0]      */
     int tile;             /* tile of the finest level's fused sweeps (N >= 64).  FP64: 0 =
                              automatic (16 x 64), 1 = 16 x 64, 2 = 8 x 64 (column pairs over
                              the tile and its halo; 3, 4 as 0).  Mixed, the single-precision
@@ -259,7 +260,10 @@ int mg_fr_solve_patches(mgfr_ctx* ctx, const double* u_domain, int N0, const mgf
                         const mgfr_params* params, const mgfr_opts* opts, double* res_hist,
                         int* n_hist, void* stream);
 
-/* Independent periodic boxes solved together: box b has side N[b] (power of two in
+/* Independent periodic boxes solved together (Sec. V.B: the nonlinear multigrid solve of
+ * the discrete equation eq. discrete_fR on a periodic grid, Sec. V.B.1 smoother, Sec. V.B.2
+ * FAS coarse-grid correction, Sec. VI.A.1 code units per box; each box is the domain-grid
+ * problem of mg_fr_solve with its own parameters).  Box b has side N[b] (power of two in
  * [coarsest_n, 1024]), density rho[b] and output u[b] (device arrays of N[b]^3, pointers
  * given in host arrays), and its own model per_box[b] (box size, |f_R0|, ...).  Every box
  * runs the domain-grid FAS V-cycles of mg_fr_solve batched with the others until

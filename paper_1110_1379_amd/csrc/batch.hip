@@ -22,6 +22,8 @@ using namespace mgfr_host;
 
 namespace {
 
+constexpr int kQueues = 12;  // whole-unit launches per batch, at most one per unit side (2 ... 1024)
+
 struct Unit {
     int n = 0, nlev = 0;
     bool periodic = false;
@@ -79,6 +81,7 @@ struct UPlan {
     std::vector<UDepth> depth;
     size_t grids = 0, first = 0, nlev = 0, order = 0;  // all levels of all units; whole units in queue order
     int nwhole = 0, nlarge = 0;
+    std::vector<int3> ranges;          // whole units: (begin, end, side) in queue order, one launch each
     size_t ids = 0, ncell = 0;        // large units: unit index, finest cells
     Launch cells0;                     // finest cells of the large units
     size_t lfirst = 0, lcount = 0;     // their block ranges (for the fold)
@@ -331,6 +334,14 @@ struct Batch {
         up.nlev = meta.add(nlev);
         up.order = meta.add(order);
         up.nwhole = (int)order.size();
+        up.ranges.clear();
+        for (int b = 0; b < up.nwhole;) {
+            const int side = units[order[b]].n;
+            int e = b;
+            while (e < up.nwhole && units[order[e]].n == side) ++e;
+            up.ranges.push_back(make_int3(b, e, side));
+            b = e;
+        }
         up.nlarge = (int)ids.size();
         up.ids = meta.add(ids);
         up.ncell = meta.add(ncell);
@@ -404,7 +415,7 @@ struct Batch {
         MGFR_TRY(alloc(&dout, 2 * nu));
         if (!phases) {
             MGFR_TRY(alloc(&dhist, nu * (size_t)(o->max_cycles + 1)));
-            MGFR_TRY(alloc(&dints, 3 * nu + 2));  // cycles, status per unit; any; queue
+            MGFR_TRY(alloc(&dints, 2 * nu + 1 + kQueues));  // cycles, status per unit; any; queues
         }
         // the staging area must stay unchanged until the copies have run
         return hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -710,7 +721,6 @@ struct Batch {
         u.first = (const int*)(dmeta + up.first);
         u.nlev = (const int*)(dmeta + up.nlev);
         u.order = (const int*)(dmeta + up.order);
-        u.nwhole = up.nwhole;
         return u;
     }
     mgfr::UnitOut uout() const
@@ -731,7 +741,8 @@ struct Batch {
         return f;
     }
     int* dany() const { return dints + 2 * units.size(); }
-    int* dqueue() const { return dints + 2 * units.size() + 1; }
+    // the device counter of whole-unit launch r (one per side, at most kQueues)
+    int* dqueue(size_t r) const { return dints + 2 * units.size() + 1 + r; }
     mgfr::BTable utab(const Launch& L) const
     {
         mgfr::BTable t;
@@ -758,8 +769,8 @@ struct Batch {
                                "batch_resid_restrict"));
             MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs(utab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs"));
         }
-        if (D.ntail > 0)
-            MGFR_TRY(hip_check(c, mgfr::unit_tail(uset(), (const int2*)(dmeta + D.tails), D.ntail, dactive, ucfg(),
+        if (D.ntail > 0)  // every tail level has side W
+            MGFR_TRY(hip_check(c, mgfr::unit_tail(uset(), (const int2*)(dmeta + D.tails), D.ntail, W, dactive, ucfg(),
                                                   mixed, s),
                                "unit_tail"));
         if ((size_t)m + 1 < up.depth.size()) MGFR_TRY(uvcycle(m + 1, mixed));
@@ -825,9 +836,10 @@ struct Batch {
                                                                   (const mgfr::BGrid*)(dmeta + D.coarse_f.other), s),
                                    "batch_restrict_base32"));
             }
-            MGFR_TRY(hip_check(c, mgfr::unit_tail_base32(uset(), (const int2*)(dmeta + up.all_tails), up.nall_tails,
-                                                         dactive, s),
-                               "unit_tail_base32"));
+            if (!mgfr::unit_resident(W))  // the resident tail kernels form these themselves
+                MGFR_TRY(hip_check(c, mgfr::unit_tail_base32(uset(), (const int2*)(dmeta + up.all_tails),
+                                                             up.nall_tails, dactive, s),
+                                   "unit_tail_base32"));
             for (int it = 0; it < o->inner_cycles; ++it) MGFR_TRY(uvcycle(0, true));
             MGFR_TRY(hip_check(c, mgfr::batch_add_correction(utab(up.cells0), up.cells0.nblk, s),
                                "batch_add_correction"));
@@ -880,8 +892,11 @@ struct Batch {
             MGFR_TRY(ensure_side(c));
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev_fork, s), "hipEventRecord"));
             MGFR_TRY(hip_check(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "hipStreamWaitEvent"));
-            const int nwg = std::min(up.nwhole, 1024);
-            MGFR_TRY(hip_check(c, mgfr::unit_whole(uset(), dqueue(), uout(), ucfg(), mixed, nwg, c->side), "unit_whole"));
+            for (size_t r = 0; r < up.ranges.size(); ++r) {
+                const int3 g = up.ranges[r];
+                MGFR_TRY(hip_check(c, mgfr::unit_whole(uset(), g.x, g.y, g.z, dqueue(r), uout(), ucfg(), mixed, c->side),
+                                   "unit_whole"));
+            }
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev_join, c->side), "hipEventRecord"));
         }
         int cycles = 0;
@@ -940,7 +955,10 @@ struct Batch {
 void engine(Batch& b)
 {
     b.phases = (b.o->flags & MGFR_PER_PHASE) != 0;
-    b.W = std::max(b.o->unit_n > 0 ? b.o->unit_n : 16, b.o->coarsest_n);
+    // a power of two, so that every tail level has side W
+    const int w = std::max(b.o->unit_n > 0 ? b.o->unit_n : 16, b.o->coarsest_n);
+    b.W = 1;
+    while (2 * b.W <= w) b.W *= 2;
 }
 
 int check_batch_opts(mgfr_ctx* c, const mgfr_opts* o)

@@ -143,21 +143,23 @@ struct Coarse64 {
     double ra[NT], rb[NT];
 };
 
+// The arrays of a double-precision coarsest solve in LDS: u, b = exp(u), S = A exp(-u/(n+1))
+// and the right-hand side of every cell, and two reduction buffers of NT entries.
+struct C64 {
+    double *su, *sb, *sS;
+    const double* sf;
+    double *ra, *rb;
+};
+
 // Double precision: b = exp(u) and S of every cell stay in LDS and are refreshed when the
 // cell is updated, so a visit evaluates exponentials only for its ghost faces.  The
 // arithmetic is that of bcell, in the same order.  Sweeps until rms <= rtol x initial, or its
-// rounding floor, or cap sweeps (rtol = 0: exactly cap).  Every thread of the workgroup calls it.
+// rounding floor, or cap sweeps (rtol = 0: exactly cap).  Every thread of the workgroup calls
+// it, with (su, sb, sS, sf) filled and visible to all.
 template <int NT>
-__device__ void coarsest64(const BGrid& g, int cap, double rtol, Coarse64<NT>& sm)
+__device__ void coarsest64_core(const BGrid& g, int cap, double rtol, const C64& sm)
 {
     const int nc = 1 << (3 * g.lg), m = g.n - 1;
-    for (int q = threadIdx.x; q < nc; q += NT) {
-        sm.su[q] = g.u[q];
-        sm.sb[q] = exp(sm.su[q]);
-        sm.sS[q] = g.A * exp(-sm.su[q] * g.inv_np1);
-        sm.sf[q] = brhs(g, q);
-    }
-    __syncthreads();
     const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
     auto cell = [&](int q) -> OpVal {
         const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
@@ -238,6 +240,21 @@ __device__ void coarsest64(const BGrid& g, int cap, double rtol, Coarse64<NT>& s
             __syncthreads();
         }
     }
+}
+
+// The coarsest level of a unit held in device memory: loaded into sm, solved, u written back.
+template <int NT>
+__device__ void coarsest64(const BGrid& g, int cap, double rtol, Coarse64<NT>& sm)
+{
+    const int nc = 1 << (3 * g.lg);
+    for (int q = threadIdx.x; q < nc; q += NT) {
+        sm.su[q] = g.u[q];
+        sm.sb[q] = exp(sm.su[q]);
+        sm.sS[q] = g.A * exp(-sm.su[q] * g.inv_np1);
+        sm.sf[q] = brhs(g, q);
+    }
+    __syncthreads();
+    coarsest64_core<NT>(g, cap, rtol, C64{sm.su, sm.sb, sm.sS, sm.sf, sm.ra, sm.rb});
     for (int q = threadIdx.x; q < nc; q += NT) g.u[q] = sm.su[q];
     __syncthreads();
 }
@@ -251,11 +268,22 @@ struct Coarse32 {
     float ra[NT], rb[NT];
 };
 
+// The arrays of a single-precision coarsest solve in LDS: per cell the base ub, b = exp(ub),
+// the correction e and its (B, M), the right-hand side and S; per ghost face (stride 512)
+// ub_g - ub_i and b_g; two reduction buffers of NT entries.
+struct C32 {
+    float *sub, *sb, *se, *sB, *sM, *sS;
+    const float* sf;
+    float *gdu, *gbb;
+    float *ra, *rb;
+};
+
 // Single precision: everything that depends only on the base stays in LDS for the whole
 // solve; per sweep only the correction-dependent parts (M, B) of the updated cells are
-// recomputed.  The arithmetic is that of bcell32, in the same order.
+// recomputed.  The arithmetic is that of bcell32, in the same order.  Every thread of the
+// workgroup calls it, with every array filled and visible to all.
 template <int NT>
-__device__ void coarsest32(const BGrid& g, int cap, float rtol, Coarse32<NT>& sm)
+__device__ void coarsest32_core(const BGrid& g, int cap, float rtol, const C32& sm)
 {
     const Op32 o = op32(g);
     const int nc = 1 << (3 * g.lg), m = g.n - 1;
@@ -265,27 +293,6 @@ __device__ void coarsest32(const BGrid& g, int cap, float rtol, Coarse32<NT>& sm
         const int ii = i + di[f], jj = j + dj[f], kk = k + dk[f];
         return !g.periodic && (ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m);
     };
-    for (int q = threadIdx.x; q < nc; q += NT) {
-        const V32 v = make_v(g.ub32[q], g.e32[q]);
-        sm.sub[q] = v.ub;
-        sm.sb[q] = __expf(v.ub);
-        sm.se[q] = v.e;
-        sm.sB[q] = v.B;
-        sm.sM[q] = v.M;
-        sm.sf[q] = g.f32[q];
-        sm.sS[q] = o.A * __expf(-v.ub * o.inv_np1);
-        const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
-        for (int f = 0; f < 6; ++f) {
-            sm.gdu[f][q] = 0.0f;
-            sm.gbb[f][q] = 0.0f;
-            if (ghost(q, f)) {
-                const float ubg = (1.0f - kR32) * face_ub32(g, f, i, j, k) + kR32 * v.ub;
-                sm.gdu[f][q] = ubg - v.ub;
-                sm.gbb[f][q] = __expf(ubg);
-            }
-        }
-    }
-    __syncthreads();
     auto cell = [&](int q, float& dN) -> float {
         const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
         const float cub = sm.sub[q], ce = sm.se[q], cB = sm.sB[q], cM = sm.sM[q];
@@ -294,9 +301,9 @@ __device__ void coarsest32(const BGrid& g, int cap, float rtol, Coarse32<NT>& sm
         for (int f = 0; f < 6; ++f) {
             if (ghost(q, f)) {
                 const float eg = kR32 * ce;
-                const float bg = sm.gbb[f][q];
+                const float bg = sm.gbb[f * 512 + q];
                 const float Mg = bg * em1f(eg), Bg = bg + Mg;
-                const float du = sm.gdu[f][q], de = eg - ce;
+                const float du = sm.gdu[f * 512 + q], de = eg - ce;
                 lgh += (Mg + cM) * du + (Bg + cB) * de;
                 dgh += (kR32 * Bg + cB) * (du + de) + (Bg + cB) * (kR32 - 1.0f);
             } else {
@@ -363,6 +370,47 @@ __device__ void coarsest32(const BGrid& g, int cap, float rtol, Coarse32<NT>& sm
             __syncthreads();
         }
     }
+}
+
+// The ghost-face terms of the coarsest solve that depend only on the base (cell q of g with
+// base ub): ub_g - ub and b_g per ghost face, zero elsewhere.
+__device__ inline void coarse_ghosts32(const BGrid& g, int q, float ub, float* gdu, float* gbb)
+{
+    const int m = g.n - 1;
+    const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
+    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+    for (int f = 0; f < 6; ++f) {
+        gdu[f * 512 + q] = 0.0f;
+        gbb[f * 512 + q] = 0.0f;
+        const int ii = i + di[f], jj = j + dj[f], kk = k + dk[f];
+        if (!g.periodic && (ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m)) {
+            const float ubg = (1.0f - kR32) * face_ub32(g, f, i, j, k) + kR32 * ub;
+            gdu[f * 512 + q] = ubg - ub;
+            gbb[f * 512 + q] = __expf(ubg);
+        }
+    }
+}
+
+// The coarsest level of a unit held in device memory: loaded into sm, solved, e written back.
+template <int NT>
+__device__ void coarsest32(const BGrid& g, int cap, float rtol, Coarse32<NT>& sm)
+{
+    const Op32 o = op32(g);
+    const int nc = 1 << (3 * g.lg);
+    for (int q = threadIdx.x; q < nc; q += NT) {
+        const V32 v = make_v(g.ub32[q], g.e32[q]);
+        sm.sub[q] = v.ub;
+        sm.sb[q] = __expf(v.ub);
+        sm.se[q] = v.e;
+        sm.sB[q] = v.B;
+        sm.sM[q] = v.M;
+        sm.sf[q] = g.f32[q];
+        sm.sS[q] = o.A * __expf(-v.ub * o.inv_np1);
+        coarse_ghosts32(g, q, v.ub, &sm.gdu[0][0], &sm.gbb[0][0]);
+    }
+    __syncthreads();
+    coarsest32_core<NT>(g, cap, rtol,
+                        C32{sm.sub, sm.sb, sm.se, sm.sB, sm.sM, sm.sS, sm.sf, &sm.gdu[0][0], &sm.gbb[0][0], sm.ra, sm.rb});
     for (int q = threadIdx.x; q < nc; q += NT) g.e32[q] = sm.se[q];
     __syncthreads();
 }

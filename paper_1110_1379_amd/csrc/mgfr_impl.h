@@ -107,7 +107,6 @@ struct UnitSet {
     const int* first;
     const int* nlev;
     const int* order;
-    int nwhole;
 };
 
 // Per-unit results on the device: residual history (H doubles per unit), cycles done, and
@@ -153,16 +152,20 @@ hipError_t batch_fill(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_nonfinite(const BTable& t, int nblk, double* partial, hipStream_t s);
 
 // ---- workgroup-per-unit kernels (unit.hip) ------------------------------------------------
-int unit_block();
-// Every whole unit of us solved completely, nwg persistent workgroups taking units from the
-// device counter *queue (reset here); results into out.
-hipError_t unit_whole(const UnitSet& us, int* queue, const UnitOut& out, const UnitCfg& cfg, bool mixed, int nwg,
-                      hipStream_t s);
-// One workgroup per tails[b] = (index of a large unit's tail level in us.grids, levels from
-// there): the rest of its V-cycle (single-precision correction cycle when mixed).
-hipError_t unit_tail(const UnitSet& us, const int2* tails, int ntail, const int* active, const UnitCfg& cfg,
+// Sides up to which a unit, or the levels below a tail, are solved with every level in LDS.
+constexpr int kUnitResidentMax = 16;
+inline bool unit_resident(int side) { return side <= kUnitResidentMax; }
+// The whole units us.order[begin, end), all of side `side`, solved completely by persistent
+// workgroups taking units from the device counter *queue (reset here); results into out.
+hipError_t unit_whole(const UnitSet& us, int begin, int end, int side, int* queue, const UnitOut& out,
+                      const UnitCfg& cfg, bool mixed, hipStream_t s);
+// One workgroup per tails[b] = (index of a large unit's tail level, of side `side`, in
+// us.grids; levels from there): the rest of its V-cycle (the single-precision correction
+// cycle when mixed, with the coarse bases below the tail level).
+hipError_t unit_tail(const UnitSet& us, const int2* tails, int ntail, int side, const int* active, const UnitCfg& cfg,
                      bool mixed, hipStream_t s);
-// Coarse bases R ub of the tail levels (from each tail level down).
+// Coarse bases R ub of the tail levels (from each tail level down), for tails the resident
+// kernels do not take.
 hipError_t unit_tail_base32(const UnitSet& us, const int2* tails, int ntail, const int* active, hipStream_t s);
 // Device-side stop test of the large units after a cycle (first: before the first cycle).
 hipError_t unit_judge(const double* sums, const int* ids, const double* ncell, int nl, int* active, const UnitOut& out,

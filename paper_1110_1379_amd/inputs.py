@@ -226,6 +226,15 @@ def amr_workload(N0: int = 256, seed: int = 1, sigma: float = 2.0, p: float = -1
     return rho0, patches, rho_packed
 
 
+def amr_box(N0: int = 256, seed: int = 1):
+    """The AMR workload: a 256^3 domain (lognormal sigma = 3, P(k) ~ k^-1) refined over 3
+    levels where the contrast exceeds 50 / 200 / 1000, cube patches of 8^3 to 64^3 cells, each
+    kept while at least 1.5% of its parent cells are flagged: 1706 patches (1204 / 379 / 123
+    per level; 722, 643, 328 and 13 of side 8, 16, 32, 64) holding 17.2 M cells at N0 = 256,
+    seed 1."""
+    return amr_workload(N0, seed=seed, sigma=3.0, p=-1.0, min_fraction=0.015, max_patches=4000)
+
+
 # --- refinement masks of an adaptive level ----------------------------------------------
 
 def oct_mask(rho: np.ndarray, threshold: float, expand: int = 1) -> np.ndarray:

@@ -1,5 +1,5 @@
-"""Wave code of the persistent workgroup-per-unit kernels (CPU: compiles unit.hip for gfx950
-to assembly, no GPU needed).
+"""Wave code of the persistent workgroup-per-unit kernels, device-memory and LDS-resident
+(CPU: compiles unit.hip for gfx950 to assembly, no GPU needed).
 
 Each workgroup of those kernels loops: barrier, lane 0 takes the next unit from a device
 counter into LDS, barrier, every lane reads it, solve, lane-0 stores of the results.  If the
@@ -18,7 +18,8 @@ import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "..", "paper_1110_1379_amd", "csrc", "unit.hip")
-KERNELS = ["ku_whole64", "ku_whole_mixed"]
+KERNELS = ["ku_whole64", "ku_whole_mixed", "kr_whole64ILi16E", "kr_whole_mixedILi16E", "kr_whole64ILi8E",
+           "kr_whole_mixedILi8E", "kr_whole64ILi4E", "kr_whole_mixedILi4E"]
 
 
 @pytest.fixture(scope="module")
