@@ -40,13 +40,19 @@ __device__ __forceinline__ long long idx3(int lg, int i, int j, int k)
     return ((((long long)i << lg) + j) << lg) + k;
 }
 
-__device__ __forceinline__ double face_ub(const BGrid& g, int f, int i, int j, int k)
+// element of the boundary values [6][n][n] (n = 2^lg) next to cell (i, j, k) through face f
+__device__ __forceinline__ int face_index(int lg, int f, int i, int j, int k)
 {
     int p, q;
     if (f < 2) { p = j; q = k; }
     else if (f < 4) { p = i; q = k; }
     else { p = i; q = j; }
-    return g.ub[((((long long)f << g.lg) + p) << g.lg) + q];
+    return (((f << lg) + p) << lg) + q;
+}
+
+__device__ __forceinline__ double face_ub(const BGrid& g, int f, int i, int j, int k)
+{
+    return g.ub[face_index(g.lg, f, i, j, k)];
 }
 
 // boundary value u_b of face f next to cell (i, j, k), rounded to single precision
@@ -156,8 +162,8 @@ struct C64 {
 // arithmetic is that of bcell, in the same order.  Sweeps until rms <= rtol x initial, or its
 // rounding floor, or cap sweeps (rtol = 0: exactly cap).  Every thread of the workgroup calls
 // it, with (su, sb, sS, sf) filled and visible to all.
-template <int NT>
-__device__ void coarsest64_core(const BGrid& g, int cap, double rtol, const C64& sm)
+template <int NT, class FaceFn>
+__device__ void coarsest64_core(const BGrid& g, int cap, double rtol, const C64& sm, FaceFn face)
 {
     const int nc = 1 << (3 * g.lg), m = g.n - 1;
     const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
@@ -171,7 +177,7 @@ __device__ void coarsest64_core(const BGrid& g, int cap, double rtol, const C64&
             const int ii = i + di[f], jj = j + dj[f], kk = k + dk[f];
             const bool out = ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m;
             if (out && !g.periodic) {
-                const double ug = (1.0 - kR) * face_ub(g, f, i, j, k) + kR * ui;
+                const double ug = (1.0 - kR) * face(f, i, j, k) + kR * ui;
                 const double bg = exp(ug);
                 lg_ += (bg + bi) * (ug - ui);
                 dlg += (kR * bg + bi) * (ug - ui) + (bg + bi) * (kR - 1.0);
@@ -254,7 +260,8 @@ __device__ void coarsest64(const BGrid& g, int cap, double rtol, Coarse64<NT>& s
         sm.sf[q] = brhs(g, q);
     }
     __syncthreads();
-    coarsest64_core<NT>(g, cap, rtol, C64{sm.su, sm.sb, sm.sS, sm.sf, sm.ra, sm.rb});
+    coarsest64_core<NT>(g, cap, rtol, C64{sm.su, sm.sb, sm.sS, sm.sf, sm.ra, sm.rb},
+                        [&](int f, int i, int j, int k) { return face_ub(g, f, i, j, k); });
     for (int q = threadIdx.x; q < nc; q += NT) g.u[q] = sm.su[q];
     __syncthreads();
 }
@@ -373,8 +380,10 @@ __device__ void coarsest32_core(const BGrid& g, int cap, float rtol, const C32& 
 }
 
 // The ghost-face terms of the coarsest solve that depend only on the base (cell q of g with
-// base ub): ub_g - ub and b_g per ghost face, zero elsewhere.
-__device__ inline void coarse_ghosts32(const BGrid& g, int q, float ub, float* gdu, float* gbb)
+// base ub): ub_g - ub and b_g per ghost face, zero elsewhere; face(f, i, j, k) gives the
+// boundary value in single precision.
+template <class FaceFn>
+__device__ inline void coarse_ghosts32(const BGrid& g, int q, float ub, float* gdu, float* gbb, FaceFn face)
 {
     const int m = g.n - 1;
     const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
@@ -384,7 +393,7 @@ __device__ inline void coarse_ghosts32(const BGrid& g, int q, float ub, float* g
         gbb[f * 512 + q] = 0.0f;
         const int ii = i + di[f], jj = j + dj[f], kk = k + dk[f];
         if (!g.periodic && (ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m)) {
-            const float ubg = (1.0f - kR32) * face_ub32(g, f, i, j, k) + kR32 * ub;
+            const float ubg = (1.0f - kR32) * face(f, i, j, k) + kR32 * ub;
             gdu[f * 512 + q] = ubg - ub;
             gbb[f * 512 + q] = __expf(ubg);
         }
@@ -406,7 +415,8 @@ __device__ void coarsest32(const BGrid& g, int cap, float rtol, Coarse32<NT>& sm
         sm.sM[q] = v.M;
         sm.sf[q] = g.f32[q];
         sm.sS[q] = o.A * __expf(-v.ub * o.inv_np1);
-        coarse_ghosts32(g, q, v.ub, &sm.gdu[0][0], &sm.gbb[0][0]);
+        coarse_ghosts32(g, q, v.ub, &sm.gdu[0][0], &sm.gbb[0][0],
+                        [&](int f, int i, int j, int k) { return face_ub32(g, f, i, j, k); });
     }
     __syncthreads();
     coarsest32_core<NT>(g, cap, rtol,

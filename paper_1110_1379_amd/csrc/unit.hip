@@ -466,49 +466,52 @@ constexpr int cube(int s) { return s * s * s; }
 // workgroup size of the resident kernels of side W
 constexpr int res_threads(int W) { return W >= 16 ? 512 : 256; }
 
-// element offsets of level d in the LDS array (double precision: top u, b, f; below + uh)
+// element offsets of level d in the LDS array (double precision: top u, b, f; below + uh;
+// every level its boundary values fc [6][s][s])
 struct Off64 {
-    int u, b, f, uh;
+    int u, b, f, uh, fc;
 };
+constexpr int sq6(int s) { return 6 * s * s; }
 template <int W>
 __device__ __forceinline__ Off64 off64(int d)
 {
-    int at = 3 * cube(W);
-    Off64 o{0, cube(W), 2 * cube(W), -1};
+    int at = 3 * cube(W) + sq6(W);
+    Off64 o{0, cube(W), 2 * cube(W), -1, 3 * cube(W)};
     for (int e = 1, s = W / 2; e <= d; ++e, s /= 2) {
-        o = Off64{at, at + cube(s), at + 2 * cube(s), at + 3 * cube(s)};
-        at += 4 * cube(s);
+        o = Off64{at, at + cube(s), at + 2 * cube(s), at + 3 * cube(s), at + 4 * cube(s)};
+        at += 4 * cube(s) + sq6(s);
     }
     return o;
 }
 template <int W>
 constexpr int res64_size()
 {
-    int t = 3 * cube(W);
-    for (int s = W / 2; s >= 2; s /= 2) t += 4 * cube(s);
+    int t = 3 * cube(W) + sq6(W);
+    for (int s = W / 2; s >= 2; s /= 2) t += 4 * cube(s) + sq6(s);
     return t;
 }
 
-// single precision: top ub, e, f, b, S; below + eh
+// single precision: top ub, e, f, b, S; below + eh; every level its boundary values fc
 struct Off32 {
-    int ub, e, f, b, S, eh;
+    int ub, e, f, b, S, eh, fc;
 };
 template <int W>
 __device__ __forceinline__ Off32 off32(int d)
 {
-    int at = 5 * cube(W);
-    Off32 o{0, cube(W), 2 * cube(W), 3 * cube(W), 4 * cube(W), -1};
+    int at = 5 * cube(W) + sq6(W);
+    Off32 o{0, cube(W), 2 * cube(W), 3 * cube(W), 4 * cube(W), -1, 5 * cube(W)};
     for (int e = 1, s = W / 2; e <= d; ++e, s /= 2) {
-        o = Off32{at, at + cube(s), at + 2 * cube(s), at + 3 * cube(s), at + 4 * cube(s), at + 5 * cube(s)};
-        at += 6 * cube(s);
+        o = Off32{at, at + cube(s), at + 2 * cube(s), at + 3 * cube(s), at + 4 * cube(s), at + 5 * cube(s),
+                  at + 6 * cube(s)};
+        at += 6 * cube(s) + sq6(s);
     }
     return o;
 }
 template <int W>
 constexpr int res32_size()
 {
-    int t = 5 * cube(W);
-    for (int s = W / 2; s >= 2; s /= 2) t += 6 * cube(s);
+    int t = 5 * cube(W) + sq6(W);
+    for (int s = W / 2; s >= 2; s /= 2) t += 6 * cube(s) + sq6(s);
     return t;
 }
 
@@ -526,9 +529,9 @@ __device__ double wg_sum_t(double v, double* red)
     return s;
 }
 
-// bcell with b read from the level instead of evaluated
-__device__ __forceinline__ OpVal rcell64(const BGrid& g, const double* u, const double* b, int i, int j, int k,
-                                         double f)
+// bcell with b and the boundary values read from the level instead of evaluated / loaded
+__device__ __forceinline__ OpVal rcell64(const BGrid& g, const double* u, const double* b, const double* fc, int i,
+                                         int j, int k, double f)
 {
     const int m = g.n - 1;
     const int q = (((i << g.lg) + j) << g.lg) + k;
@@ -541,7 +544,7 @@ __device__ __forceinline__ OpVal rcell64(const BGrid& g, const double* u, const 
         const int ii = i + di[x], jj = j + dj[x], kk = k + dk[x];
         const bool out = ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m;
         if (out && !g.periodic) {
-            const double ug = (1.0 - kR) * face_ub(g, x, i, j, k) + kR * ui;
+            const double ug = (1.0 - kR) * fc[face_index(g.lg, x, i, j, k)] + kR * ui;
             const double bg = exp(ug);
             lg_ += (bg + bi) * (ug - ui);
             dlg += (kR * bg + bi) * (ug - ui) + (bg + bi) * (kR - 1.0);
@@ -562,13 +565,13 @@ __device__ __forceinline__ OpVal rcell64(const BGrid& g, const double* u, const 
 }
 
 template <int NT>
-__device__ void rsweep64(const BGrid& g, double* u, double* b, const double* f, int colour)
+__device__ void rsweep64(const BGrid& g, double* u, double* b, const double* f, const double* fc, int colour)
 {
     const int half = 1 << (3 * g.lg - 1);
     for (int t = threadIdx.x; t < half; t += NT) {
         int i, j, k;
         const int q = (int)colour_cell(g, t, colour, i, j, k);
-        const OpVal r = rcell64(g, u, b, i, j, k, f[q]);
+        const OpVal r = rcell64(g, u, b, fc, i, j, k, f[q]);
         const double v = u[q] + dev::bounded(-r.L / r.dL, g.max_step);
         u[q] = v;
         b[q] = exp(v);
@@ -591,7 +594,7 @@ __device__ void rcoarsen64(const BGrid& g, const BGrid& c, double* lds, const Of
                     const int i = 2 * I + x, j = 2 * J + y, k = 2 * K + w;
                     const int q = (int)idx3(g.lg, i, j, k);
                     su += lds[a.u + q];
-                    sd += rcell64(g, lds + a.u, lds + a.b, i, j, k, lds[a.f + q]).L;
+                    sd += rcell64(g, lds + a.u, lds + a.b, lds + a.fc, i, j, k, lds[a.f + q]).L;
                 }
         lds[z.u + qc] = 0.125 * su;
         lds[z.uh + qc] = 0.125 * su;
@@ -602,7 +605,7 @@ __device__ void rcoarsen64(const BGrid& g, const BGrid& c, double* lds, const Of
     for (int q = threadIdx.x; q < ncc; q += NT) {
         int i, j, k;
         cell_of(c, q, i, j, k);
-        lds[z.f + q] = rcell64(c, lds + z.uh, lds + z.b, i, j, k, 0.0).L - lds[z.f + q];
+        lds[z.f + q] = rcell64(c, lds + z.uh, lds + z.b, lds + z.fc, i, j, k, 0.0).L - lds[z.f + q];
     }
     __syncthreads();
 }
@@ -646,7 +649,7 @@ __device__ double rrms64(const BGrid& g, double* lds, const Off64& a, double* re
     for (int q = threadIdx.x; q < nf; q += NT) {
         int i, j, k;
         cell_of(g, q, i, j, k);
-        const double d = rcell64(g, lds + a.u, lds + a.b, i, j, k, lds[a.f + q]).L;
+        const double d = rcell64(g, lds + a.u, lds + a.b, lds + a.fc, i, j, k, lds[a.f + q]).L;
         s += d * d;
     }
     return sqrt(wg_sum_t<NT>(s, red) / (double)nf);
@@ -659,8 +662,8 @@ __device__ void rvcycle64(const BGrid* G, int nl, const UnitCfg& cfg, double* ld
     for (int d = 0; d + 1 < nl; ++d) {
         const Off64 a = off64<W>(d), z = off64<W>(d + 1);
         for (int s = 0; s < cfg.pre; ++s) {
-            rsweep64<NT>(G[d], lds + a.u, lds + a.b, lds + a.f, 0);
-            rsweep64<NT>(G[d], lds + a.u, lds + a.b, lds + a.f, 1);
+            rsweep64<NT>(G[d], lds + a.u, lds + a.b, lds + a.f, lds + a.fc, 0);
+            rsweep64<NT>(G[d], lds + a.u, lds + a.b, lds + a.f, lds + a.fc, 1);
         }
         rcoarsen64<NT>(G[d], G[d + 1], lds, a, z);
     }
@@ -670,23 +673,27 @@ __device__ void rvcycle64(const BGrid* G, int nl, const UnitCfg& cfg, double* ld
         const int nc = 1 << (3 * g.lg);
         for (int q = threadIdx.x; q < nc; q += NT) cS[q] = g.A * exp(-lds[a.u + q] * g.inv_np1);
         __syncthreads();
-        coarsest64_core<NT>(g, cfg.cap, cfg.rtol, C64{lds + a.u, lds + a.b, cS, lds + a.f, ra, rb});
+        const double* fc = lds + a.fc;
+        coarsest64_core<NT>(g, cfg.cap, cfg.rtol, C64{lds + a.u, lds + a.b, cS, lds + a.f, ra, rb},
+                            [&](int f, int i, int j, int k) { return fc[face_index(g.lg, f, i, j, k)]; });
         __syncthreads();
     }
     for (int d = nl - 2; d >= 0; --d) {
         const Off64 a = off64<W>(d), z = off64<W>(d + 1);
         rcorrect64<NT>(G[d], G[d + 1], lds, a, z);
         for (int s = 0; s < cfg.post; ++s) {
-            rsweep64<NT>(G[d], lds + a.u, lds + a.b, lds + a.f, 0);
-            rsweep64<NT>(G[d], lds + a.u, lds + a.b, lds + a.f, 1);
+            rsweep64<NT>(G[d], lds + a.u, lds + a.b, lds + a.f, lds + a.fc, 0);
+            rsweep64<NT>(G[d], lds + a.u, lds + a.b, lds + a.f, lds + a.fc, 1);
         }
     }
 }
 
-// level 0 from device memory: u, b = exp(u), f = the level's right-hand side
+// level 0 from device memory: u, b = exp(u), f = the level's right-hand side; and the
+// boundary values of levels 0 .. nl - 1 (patches)
 template <int W, int NT>
-__device__ void rload64(const BGrid& g, double* lds)
+__device__ void rload64(const BGrid* G, int nl, double* lds)
 {
+    const BGrid& g = G[0];
     const Off64 a = off64<W>(0);
     for (int q = threadIdx.x; q < cube(W); q += NT) {
         const double v = g.u[q];
@@ -694,6 +701,11 @@ __device__ void rload64(const BGrid& g, double* lds)
         lds[a.b + q] = exp(v);
         lds[a.f + q] = brhs(g, q);
     }
+    if (!g.periodic)
+        for (int d = 0; d < nl; ++d) {
+            const int n6 = 6 << (2 * G[d].lg), fc = off64<W>(d).fc;
+            for (int q = threadIdx.x; q < n6; q += NT) lds[fc + q] = G[d].ub[q];
+        }
     __syncthreads();
 }
 
@@ -720,7 +732,7 @@ __global__ void __launch_bounds__(res_threads(W)) kr_whole64(UnitSet us, int beg
         const BGrid* G = us.grids + us.first[u];
         const int nl = us.nlev[u];
         double* hist = out.hist + (long long)u * out.H;
-        rload64<W, NT>(G[0], lds);
+        rload64<W, NT>(G, nl, lds);
         double rms = rrms64<NT>(G[0], lds, off64<W>(0), ra);
         if (threadIdx.x == 0) hist[0] = rms;
         int k = 0;
@@ -746,15 +758,16 @@ __global__ void __launch_bounds__(res_threads(W)) kr_tail64(UnitSet us, const in
     const int2 t = tails[blockIdx.x];
     const BGrid* G = us.grids + t.x;
     if (!active[G[0].unit]) return;
-    rload64<W, NT>(G[0], lds);
+    rload64<W, NT>(G, t.y, lds);
     rvcycle64<W, NT>(G, t.y, cfg, lds, cS, ra, rb);
     rstore64<W, NT>(G[0], lds);
 }
 
 // ---- single precision, resident ---------------------------------------------------------
-// bcell32 with b and S read from the level instead of evaluated
+// bcell32 with b, S and the boundary values read from the level instead of evaluated / loaded
 __device__ __forceinline__ Res32 rcell32(const BGrid& g, const Op32& o, const float* ub, const float* e,
-                                         const float* b, const float* S, int i, int j, int k, float f)
+                                         const float* b, const float* S, const float* fc, int i, int j, int k,
+                                         float f)
 {
     const int m = g.n - 1;
     const int q = (((i << g.lg) + j) << g.lg) + k;
@@ -770,7 +783,7 @@ __device__ __forceinline__ Res32 rcell32(const BGrid& g, const Op32& o, const fl
         const int ii = i + di[x], jj = j + dj[x], kk = k + dk[x];
         const bool out = ii < 0 || ii > m || jj < 0 || jj > m || kk < 0 || kk > m;
         if (out && !g.periodic) {
-            const float ubg = (1.0f - kR32) * face_ub32(g, x, i, j, k) + kR32 * c.ub;
+            const float ubg = (1.0f - kR32) * fc[face_index(g.lg, x, i, j, k)] + kR32 * c.ub;
             const float eg = kR32 * c.e;
             const float bg = __expf(ubg);
             const float Mg = bg * em1f(eg), Bg = bg + Mg;
@@ -806,7 +819,7 @@ __device__ void rsweep32(const BGrid& g, float* lds, const Off32& a, int colour)
     for (int t = threadIdx.x; t < half; t += NT) {
         int i, j, k;
         const int q = (int)colour_cell(g, t, colour, i, j, k);
-        const Res32 r = rcell32(g, o, lds + a.ub, lds + a.e, lds + a.b, lds + a.S, i, j, k, lds[a.f + q]);
+        const Res32 r = rcell32(g, o, lds + a.ub, lds + a.e, lds + a.b, lds + a.S, lds + a.fc, i, j, k, lds[a.f + q]);
         lds[a.e + q] = lds[a.e + q] + newton32(r, o.max_step);
     }
     __syncthreads();
@@ -828,7 +841,8 @@ __device__ void rcoarsen32(const BGrid& g, const BGrid& c, float* lds, const Off
                     const int i = 2 * I + x, j = 2 * J + y, k = 2 * K + w;
                     const int q = (int)idx3(g.lg, i, j, k);
                     se += lds[a.e + q];
-                    sd += rcell32(g, o, lds + a.ub, lds + a.e, lds + a.b, lds + a.S, i, j, k, lds[a.f + q]).N;
+                    sd += rcell32(g, o, lds + a.ub, lds + a.e, lds + a.b, lds + a.S, lds + a.fc, i, j, k,
+                                  lds[a.f + q]).N;
                 }
         lds[z.e + qc] = 0.125f * se;
         lds[z.eh + qc] = 0.125f * se;
@@ -838,7 +852,8 @@ __device__ void rcoarsen32(const BGrid& g, const BGrid& c, float* lds, const Off
     for (int q = threadIdx.x; q < ncc; q += NT) {
         int i, j, k;
         cell_of(c, q, i, j, k);
-        lds[z.f + q] = rcell32(c, oc, lds + z.ub, lds + z.eh, lds + z.b, lds + z.S, i, j, k, 0.0f).N - lds[z.f + q];
+        lds[z.f + q] =
+            rcell32(c, oc, lds + z.ub, lds + z.eh, lds + z.b, lds + z.S, lds + z.fc, i, j, k, 0.0f).N - lds[z.f + q];
     }
     __syncthreads();
 }
@@ -938,7 +953,9 @@ __device__ void rvcycle32(const BGrid* G, int nl, const UnitCfg& cfg, float* lds
             const float M = bq * em1f(lds[a.e + q]);
             co.cM[q] = M;
             co.cB[q] = bq + M;
-            coarse_ghosts32(g, q, lds[a.ub + q], co.gdu, co.gbb);
+            const float* fc = lds + a.fc;
+            coarse_ghosts32(g, q, lds[a.ub + q], co.gdu, co.gbb,
+                            [&](int f, int i, int j, int k) { return fc[face_index(g.lg, f, i, j, k)]; });
         }
         __syncthreads();
         coarsest32_core<NT>(g, cfg.cap, (float)cfg.rtol,
@@ -953,6 +970,17 @@ __device__ void rvcycle32(const BGrid* G, int nl, const UnitCfg& cfg, float* lds
             rsweep32<NT>(G[d], lds, a, 0);
             rsweep32<NT>(G[d], lds, a, 1);
         }
+    }
+}
+
+// boundary values of levels 0 .. nl - 1 (patches), in single precision
+template <int W, int NT>
+__device__ void rfaces32(const BGrid* G, int nl, float* lds)
+{
+    if (G[0].periodic) return;
+    for (int d = 0; d < nl; ++d) {
+        const int n6 = 6 << (2 * G[d].lg), fc = off32<W>(d).fc;
+        for (int q = threadIdx.x; q < n6; q += NT) lds[fc + q] = (float)G[d].ub[q];
     }
 }
 
@@ -1000,6 +1028,7 @@ __global__ void __launch_bounds__(res_threads(W)) kr_whole_mixed(UnitSet us, int
         const BGrid* G = us.grids + us.first[u];
         const int nl = us.nlev[u];
         double* hist = out.hist + (long long)u * out.H;
+        rfaces32<W, NT>(G, nl, lds);
         double rms = rresid_cast<W, NT>(G[0], lds, red);
         if (threadIdx.x == 0) hist[0] = rms;
         int k = 0;
@@ -1034,6 +1063,7 @@ __global__ void __launch_bounds__(res_threads(W)) kr_tail32(UnitSet us, const in
         lds[a.e + q] = g.e32[q];
         lds[a.f + q] = g.f32[q];
     }
+    rfaces32<W, NT>(G, t.y, lds);
     __syncthreads();
     rbase_terms32<NT>(g, lds, a);
     __syncthreads();
