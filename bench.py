@@ -340,7 +340,8 @@ def bench_domain(args):
             "max_rel": d.max().item() / ref if ref > 0 else None}
         del d
     # graph-captured cycles against eager ones, per precision, without the event timing
-    out["graph_ab"] = {p: graph_ab(mgfr, ctx, rho_d, params, used[p], args.steps) for p in runs}
+    if not args.no_graph_ab:
+        out["graph_ab"] = {p: graph_ab(mgfr, ctx, rho_d, params, used[p], args.steps) for p in runs}
     if not args.no_stop_rule:
         out["stop_rule_comparison"] = stop_rule_comparison(mgfr, ctx, rho_d, params, used[headp], fields[headp])
     if not args.no_cpu_baseline:
@@ -829,6 +830,8 @@ def main():
                          "(baseline), or both")
     ap.add_argument("--unit-n", type=int, default=0,
                     help="amr/batch: units and levels of side <= this run in one workgroup (0: the library's 16)")
+    ap.add_argument("--no-graph-ab", action="store_true",
+                    help="domain workloads: skip the graph-captured against eager comparison")
     ap.add_argument("--no-stop-rule", action="store_true",
                     help="domain workloads: skip the truncation-error stop-rule comparison")
     ap.add_argument("--copy-probe", action="store_true",

@@ -99,10 +99,10 @@ typedef struct mgfr_opts {
                              of two; values below coarsest_n count as coarsest_n    [0]      */
     int tile;             /* tile of the finest level's fused sweeps (N >= 64).  FP64: 0 =
                              automatic (16 x 64), 1 = 16 x 64, 2 = 8 x 64 (column pairs over
-                             the tile and its halo; 3, 4 as 0).  Mixed, the single-precision
+                             the tile and its halo; 3 - 5 as 0).  Mixed, the single-precision
                              correction sweep: 0 = automatic (16 x 32), 1 = 16 x 32, 2 = 32 x
-                             32, 3 = 16 x 64 (one tile column pair per thread), 4 = 8 x 32
-                             (column pairs over the tile and its halo)              [0]      */
+                             32, 3 = 16 x 64, 5 = 32 x 64 (one tile column pair per thread),
+                             4 = 8 x 32 (column pairs over the tile and its halo)   [0]      */
 } mgfr_opts;
 
 /* One refinement patch: a cube of n^3 cells at refinement level `level` >= 1 (cell size

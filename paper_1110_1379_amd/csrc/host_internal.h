@@ -115,14 +115,18 @@ struct mgfr_ctx {
         double* uhat = nullptr;       // coarse: R u of the finer level
         double* f = nullptr;          // coarse: FAS right-hand side
         long long active = 0;         // number of active cells
+        const unsigned char* flags = nullptr;  // level 0 with a +1 / -1 mask: its byte flags
     };
     int MN = 0, Mcoarsest = 0;
     std::vector<MLevel> mlv;
     double* mpart = nullptr;  // block partials of the finest-level norm
+    unsigned char* mflags = nullptr;  // byte flags of the finest mask
     void free_masked()
     {
         (void)hipFree(mpart);
         mpart = nullptr;
+        (void)hipFree(mflags);
+        mflags = nullptr;
         for (size_t m = 0; m < mlv.size(); ++m) {
             (void)hipFree(mlv[m].mbuf);
             (void)hipFree(mlv[m].w);
@@ -255,7 +259,7 @@ inline int check_opts(mgfr_ctx* c, const mgfr_opts* o)
         !is_pow2(o->coarsest_n) || o->coarsest_n < 2 || o->coarsest_n > 8 || !(o->max_step >= 0.0) ||
         !(o->coarsest_rtol >= 0.0) || (o->precision != MGFR_FP64 && o->precision != MGFR_MIXED) ||
         o->inner_cycles < 1 || o->planes < 0 || (o->planes > 0 && (!is_pow2(o->planes) || o->planes < 4)) ||
-        !(o->tau_alpha >= 0.0) || o->unit_n < 0 || o->unit_n > 1024 || o->tile < 0 || o->tile > 4)
+        !(o->tau_alpha >= 0.0) || o->unit_n < 0 || o->unit_n > 1024 || o->tile < 0 || o->tile > 5)
         return c->fail(MGFR_EINVAL, "invalid options (tol=%g pre=%d post=%d coarsest_n=%d precision=%d)",
                        o->tol, o->pre, o->post, o->coarsest_n, o->precision);
     return MGFR_OK;

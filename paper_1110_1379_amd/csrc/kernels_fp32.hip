@@ -668,6 +668,7 @@ hipError_t ngs_sweep32_fused(const Grid& g, const float* ub, const float* ein, f
         };
         if (tile == kTile32x32) return launch(k32_fused2<32, 32>, 32, 32);
         if (tile == kTile16x64) return launch(k32_fused2<16, 64>, 16, 64);
+        if (tile == kTile32x64) return launch(k32_fused2<32, 64>, 32, 64);
         return launch(k32_fused2<16, 32>, 16, 32);
     }
     // 216 column pairs per 12 x 36 tile.  With 90 VGPRs a SIMD holds 5 wavefronts, so five

@@ -10,6 +10,11 @@
 // The residual is restricted from active children (masked ones count zero) into active coarse
 // cells, R u from all 8 children; the coarse correction is zero in masked coarse cells and
 // is prolongated into active fine cells only (Sec. V.A.2, V.A.3, V.B.2).
+//
+// On the finest level a mask that only holds +1 and -1 is read as one byte per cell (1:
+// active), which gives the same values as the float mask.  The per-cell kernels renumber
+// their workgroups so that each XCD takes a contiguous range of rows: a cell's neighbours in
+// the rows and planes next to it are then mostly in that XCD's L2.
 #include "device_fp64.h"
 
 namespace mgfr {
@@ -21,9 +26,23 @@ constexpr int kMaxParts = 8192;
 using dev::OpVal;
 using dev::at;
 using dev::bounded;
+using u8 = unsigned char;
+
+// mask value of cell q: the float mask, or a byte flag standing for +1 / -1
+__device__ __forceinline__ double mval(const float* __restrict__ m, long long q) { return m[q]; }
+__device__ __forceinline__ double mval(const u8* __restrict__ m, long long q) { return m[q] ? 1.0 : -1.0; }
+
+// Workgroups are dealt to the 8 XCDs in turn; this numbering gives each XCD a contiguous
+// eighth of the grid.
+__device__ __forceinline__ long long xcd_block()
+{
+    const long long nb = gridDim.x, b = blockIdx.x;
+    return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
 
 // L_i - f and dL_i/du_i at active cell (i,j,k) of value ui, mask mi.
-__device__ __forceinline__ OpVal masked_op(const Grid& g, const float* __restrict__ mask,
+template <class M>
+__device__ __forceinline__ OpVal masked_op(const Grid& g, const M* __restrict__ mask,
                                            const double* __restrict__ w, const double* __restrict__ u,
                                            int i, int j, int k, double ui, double mi, double f)
 {
@@ -35,7 +54,7 @@ __device__ __forceinline__ OpVal masked_op(const Grid& g, const float* __restric
     bool have_wi = false;
 #pragma unroll
     for (int v = 0; v < 6; ++v) {
-        const double mn = mask[qn[v]];
+        const double mn = mval(mask, qn[v]);
         if (mn > 0.0) {
             const double un = u[qn[v]], bn = exp(un), du = un - ui;
             L = fma(bn + bi, du, L);
@@ -131,12 +150,13 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sa, dou
 
 // One colour of a red-black Newton-Gauss-Seidel sweep; one thread per cell of the colour,
 // masked cells untouched.
-__global__ void __launch_bounds__(kB) km_ngs_colour(Grid g, const float* __restrict__ mask,
+template <class M>
+__global__ void __launch_bounds__(kB) km_ngs_colour(Grid g, const M* __restrict__ mask,
                                                     const double* __restrict__ w, double* __restrict__ u,
                                                     const double* __restrict__ src, int colour)
 {
     const long long half = 1LL << (3 * g.lg - 1);
-    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    const long long t = xcd_block() * kB + threadIdx.x;
     if (t >= half) return;
     const int hk = g.n >> 1;
     const int s = (int)(t & (hk - 1));
@@ -144,7 +164,7 @@ __global__ void __launch_bounds__(kB) km_ngs_colour(Grid g, const float* __restr
     const int i = (int)(row >> g.lg), j = (int)(row & (g.n - 1));
     const int k = 2 * s + ((i + j + colour) & 1);
     const long long q = at(g, i, j, k);
-    const double mi = mask[q];
+    const double mi = mval(mask, q);
     if (!(mi > 0.0)) return;
     const double ui = u[q];
     const OpVal r = masked_op(g, mask, w, u, i, j, k, ui, mi, dev::rhs_value(g, src[q]));
@@ -153,7 +173,8 @@ __global__ void __launch_bounds__(kB) km_ngs_colour(Grid g, const float* __restr
 
 // One thread per coarse cell: R u of all 8 children and R d of the active ones into active
 // coarse cells; masked coarse cells take their fixed value and a zero right-hand side.
-__global__ void __launch_bounds__(kB) km_resid_restrict(Grid g, const float* __restrict__ mask,
+template <class M>
+__global__ void __launch_bounds__(kB) km_resid_restrict(Grid g, const M* __restrict__ mask,
                                                         const double* __restrict__ w, const double* __restrict__ u,
                                                         const double* __restrict__ src,
                                                         const float* __restrict__ maskc,
@@ -161,7 +182,7 @@ __global__ void __launch_bounds__(kB) km_resid_restrict(Grid g, const float* __r
                                                         double* __restrict__ uhat, double* __restrict__ fc)
 {
     const int lgc = g.lg - 1, nc = g.n >> 1;
-    const long long tc = (long long)blockIdx.x * kB + threadIdx.x;
+    const long long tc = xcd_block() * kB + threadIdx.x;
     if (tc >= (1LL << (3 * lgc))) return;
     if (!(maskc[tc] > 0.0f)) {
         uc[tc] = wc[tc];
@@ -179,7 +200,7 @@ __global__ void __launch_bounds__(kB) km_resid_restrict(Grid g, const float* __r
             for (int c = 0; c < 2; ++c) {
                 const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
                 const long long q = at(g, i, j, k);
-                const double ui = u[q], mi = mask[q];
+                const double ui = u[q], mi = mval(mask, q);
                 su += ui;
                 if (mi > 0.0) sd += masked_op(g, mask, w, u, i, j, k, ui, mi, dev::rhs_value(g, src[q])).L;
             }
@@ -193,7 +214,7 @@ __global__ void __launch_bounds__(kB) km_fas_rhs(Grid g, const float* __restrict
                                                  const double* __restrict__ w, const double* __restrict__ uhat,
                                                  double* __restrict__ f)
 {
-    const long long q = (long long)blockIdx.x * kB + threadIdx.x;
+    const long long q = xcd_block() * kB + threadIdx.x;
     if (q >= (1LL << (3 * g.lg))) return;
     const double mi = mask[q];
     if (!(mi > 0.0)) return;
@@ -214,7 +235,8 @@ __global__ void __launch_bounds__(kB) km_coarse_diff(long long n, const float* _
 
 // Block partials (sum d^2, max |d|) over the active cells.  A thread takes one 2x2x2 block of
 // cells, the eight cells unrolled so that their loads overlap; one partial pair per workgroup.
-__global__ void __launch_bounds__(kB) km_norm(Grid g, const float* __restrict__ mask,
+template <class M>
+__global__ void __launch_bounds__(kB) km_norm(Grid g, const M* __restrict__ mask,
                                               const double* __restrict__ w, const double* __restrict__ u,
                                               const double* __restrict__ src, double* __restrict__ partial)
 {
@@ -222,7 +244,7 @@ __global__ void __launch_bounds__(kB) km_norm(Grid g, const float* __restrict__ 
     const int lgc = g.lg - 1, nc = g.n >> 1;
     const long long nblk = 1LL << (3 * lgc);
     double s = 0.0, mx = 0.0;
-    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    const long long t = xcd_block() * kB + threadIdx.x;
     if (t < nblk) {
         const int I = (int)(t >> (2 * lgc)), J = (int)((t >> lgc) & (nc - 1)), K = (int)(t & (nc - 1));
 #pragma unroll
@@ -233,7 +255,7 @@ __global__ void __launch_bounds__(kB) km_norm(Grid g, const float* __restrict__ 
                 for (int z = 0; z < 2; ++z) {
                     const int i = 2 * I + x, j = 2 * J + y, k = 2 * K + z;
                     const long long q = at(g, i, j, k);
-                    const double mi = mask[q];
+                    const double mi = mval(mask, q);
                     if (mi > 0.0) {
                         const double d = masked_op(g, mask, w, u, i, j, k, u[q], mi, dev::rhs_value(g, src[q])).L;
                         s += d * d;
@@ -260,6 +282,25 @@ __global__ void __launch_bounds__(kB) km_count(const float* __restrict__ mask, l
         if (m > 0.0f) s += 1.0;
         const double a = fabs((double)m);
         if (!(mx >= a)) mx = a;
+    }
+    block_sum_max(s, mx, sa, sb);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = s;
+        partial[2 * blockIdx.x + 1] = mx;
+    }
+}
+
+// Byte flags of a mask (1 where > 0) and block partials of the number of cells whose mask is
+// neither +1 nor -1 (the flags stand for the mask only when there is none).
+__global__ void __launch_bounds__(kB) km_flags(const float* __restrict__ mask, long long n, u8* __restrict__ flags,
+                                               double* __restrict__ partial)
+{
+    __shared__ double sa[kB], sb[kB];
+    double s = 0.0, mx = 0.0;
+    for (long long q = (long long)blockIdx.x * kB + threadIdx.x; q < n; q += (long long)gridDim.x * kB) {
+        const float m = mask[q];
+        flags[q] = m > 0.0f ? 1 : 0;
+        if (m != 1.0f && m != -1.0f) s += 1.0;
     }
     block_sum_max(s, mx, sa, sb);
     if (threadIdx.x == 0) {
@@ -391,26 +432,61 @@ hipError_t masked_restrict_setup(const Grid& gc, const float* maskf, const doubl
     return hipGetLastError();
 }
 
-hipError_t masked_ngs(const Grid& g, const float* mask, const double* w, double* u, const double* src, hipStream_t s)
+hipError_t masked_flags(const float* mask, long long n, unsigned char* flags, double* partial, int* nparts,
+                        hipStream_t s)
+{
+    const unsigned nb = rblocks(n);
+    hipLaunchKernelGGL(km_flags, dim3(nb), dim3(kB), 0, s, mask, n, flags, partial);
+    *nparts = (int)nb;
+    return hipGetLastError();
+}
+
+template <class M>
+hipError_t ngs_t(const Grid& g, const M* mask, const double* w, double* u, const double* src, hipStream_t s)
 {
     if (g.n < 2) return hipErrorInvalidValue;
     const long long half = cells(g) / 2;
     for (int colour = 0; colour < 2; ++colour) {
-        hipLaunchKernelGGL(km_ngs_colour, dim3(blocks(half)), dim3(kB), 0, s, g, mask, w, u, src, colour);
+        hipLaunchKernelGGL(km_ngs_colour<M>, dim3(blocks(half)), dim3(kB), 0, s, g, mask, w, u, src, colour);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+hipError_t masked_ngs(const Grid& g, const float* mask, const double* w, double* u, const double* src, hipStream_t s)
+{
+    return ngs_t(g, mask, w, u, src, s);
+}
+
+hipError_t masked_ngs(const Grid& g, const unsigned char* flags, const double* w, double* u, const double* src,
+                      hipStream_t s)
+{
+    return ngs_t(g, flags, w, u, src, s);
+}
+
+template <class M>
+hipError_t resid_restrict_t(const Grid& g, const M* mask, const double* w, const double* u, const double* src,
+                            const float* maskc, const double* wc, double* uc, double* uhat, double* fc, hipStream_t s)
+{
+    if (g.n < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(km_resid_restrict<M>, dim3(blocks(cells(g) / 8)), dim3(kB), 0, s, g, mask, w, u, src, maskc,
+                       wc, uc, uhat, fc);
+    return hipGetLastError();
+}
+
 hipError_t masked_resid_restrict(const Grid& g, const float* mask, const double* w, const double* u,
                                  const double* src, const float* maskc, const double* wc, double* uc, double* uhat,
                                  double* fc, hipStream_t s)
 {
-    if (g.n < 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(km_resid_restrict, dim3(blocks(cells(g) / 8)), dim3(kB), 0, s, g, mask, w, u, src, maskc, wc,
-                       uc, uhat, fc);
-    return hipGetLastError();
+    return resid_restrict_t(g, mask, w, u, src, maskc, wc, uc, uhat, fc, s);
+}
+
+hipError_t masked_resid_restrict(const Grid& g, const unsigned char* flags, const double* w, const double* u,
+                                 const double* src, const float* maskc, const double* wc, double* uc, double* uhat,
+                                 double* fc, hipStream_t s)
+{
+    return resid_restrict_t(g, flags, w, u, src, maskc, wc, uc, uhat, fc, s);
 }
 
 hipError_t masked_fas_rhs(const Grid& gc, const float* maskc, const double* wc, const double* uhat, double* f,
@@ -432,14 +508,27 @@ hipError_t masked_prolong(const Grid& gc, const float* maskc, const double* uc, 
 
 long long masked_norm_partials(const Grid& g) { return (long long)blocks(cells(g) / 8); }
 
-hipError_t masked_norm(const Grid& g, const float* mask, const double* w, const double* u, const double* src,
-                       double* partial, int* nparts, hipStream_t s)
+template <class M>
+hipError_t norm_t(const Grid& g, const M* mask, const double* w, const double* u, const double* src, double* partial,
+                  int* nparts, hipStream_t s)
 {
     if (g.n < 2) return hipErrorInvalidValue;
     const unsigned nb = blocks(cells(g) / 8);
-    hipLaunchKernelGGL(km_norm, dim3(nb), dim3(kB), 0, s, g, mask, w, u, src, partial);
+    hipLaunchKernelGGL(km_norm<M>, dim3(nb), dim3(kB), 0, s, g, mask, w, u, src, partial);
     *nparts = (int)nb;
     return hipGetLastError();
+}
+
+hipError_t masked_norm(const Grid& g, const float* mask, const double* w, const double* u, const double* src,
+                       double* partial, int* nparts, hipStream_t s)
+{
+    return norm_t(g, mask, w, u, src, partial, nparts, s);
+}
+
+hipError_t masked_norm(const Grid& g, const unsigned char* flags, const double* w, const double* u,
+                       const double* src, double* partial, int* nparts, hipStream_t s)
+{
+    return norm_t(g, flags, w, u, src, partial, nparts, s);
 }
 
 hipError_t masked_coarsest(const Grid& g, const float* mask, const double* w, double* u, const double* f, int cap,

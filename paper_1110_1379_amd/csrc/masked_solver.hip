@@ -32,7 +32,8 @@ int ensure_masked(mgfr_ctx* c, int N, int coarsest)
     mgfr::Grid gN{};
     gN.n = N;
     gN.lg = ilog2(N);
-    if (hipMalloc(&c->mpart, sizeof(double) * 2 * (size_t)mgfr::masked_norm_partials(gN)) != hipSuccess) {
+    if (hipMalloc(&c->mpart, sizeof(double) * 2 * (size_t)mgfr::masked_norm_partials(gN)) != hipSuccess ||
+        hipMalloc(&c->mflags, (size_t)N * N * N) != hipSuccess) {
         c->free_masked();
         return c->fail(MGFR_ENOMEM, "hipMalloc of the norm partials failed");
     }
@@ -63,13 +64,17 @@ struct MCycle {
             }
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used], s), "hipEventRecord"));
         }
-        MGFR_TRY(hip_check(c, mgfr::masked_ngs(L.g, L.mask, L.w, L.u, src(m), s), "masked_ngs"));
+        if (L.flags)
+            MGFR_TRY(hip_check(c, mgfr::masked_ngs(L.g, L.flags, L.w, L.u, src(m), s), "masked_ngs"));
+        else
+            MGFR_TRY(hip_check(c, mgfr::masked_ngs(L.g, L.mask, L.w, L.u, src(m), s), "masked_ngs"));
         if (timed) {
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
             c->ev_used += 2;
             c->stats.sweep_launches += 2;
-            // every mask read; per active cell u read and written and the density read
-            c->stats.sweep_bytes += 4.0 * (double)mgfr::cells(L.g) + 24.0 * (double)L.active;
+            // every mask read (one byte per cell with flags); per active cell u read and written
+            // and the density read
+            c->stats.sweep_bytes += (L.flags ? 1.0 : 4.0) * (double)mgfr::cells(L.g) + 24.0 * (double)L.active;
         }
         c->stats.cell_updates += L.active;
         if (m == 0) c->stats.finest_updates += L.active;
@@ -85,9 +90,14 @@ struct MCycle {
                              "masked_coarsest");
         mgfr_ctx::MLevel& H = c->mlv[m + 1];
         for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m));
-        MGFR_TRY(hip_check(c, mgfr::masked_resid_restrict(L.g, L.mask, L.w, L.u, src(m), H.mask, H.w, H.u, H.uhat,
-                                                          H.f, s),
-                           "masked_resid_restrict"));
+        if (L.flags)
+            MGFR_TRY(hip_check(c, mgfr::masked_resid_restrict(L.g, L.flags, L.w, L.u, src(m), H.mask, H.w, H.u,
+                                                              H.uhat, H.f, s),
+                               "masked_resid_restrict"));
+        else
+            MGFR_TRY(hip_check(c, mgfr::masked_resid_restrict(L.g, L.mask, L.w, L.u, src(m), H.mask, H.w, H.u,
+                                                              H.uhat, H.f, s),
+                               "masked_resid_restrict"));
         MGFR_TRY(hip_check(c, mgfr::masked_fas_rhs(H.g, H.mask, H.w, H.uhat, H.f, s), "masked_fas_rhs"));
         MGFR_TRY(vcycle(m + 1));
         MGFR_TRY(hip_check(c, mgfr::masked_prolong(H.g, H.mask, H.u, H.uhat, L.mask, L.u, s), "masked_prolong"));
@@ -113,7 +123,10 @@ struct MCycle {
     {
         mgfr_ctx::MLevel& L = c->mlv[0];
         int nparts = 0;
-        MGFR_TRY(hip_check(c, mgfr::masked_norm(L.g, L.mask, L.w, L.u, rho, c->mpart, &nparts, s), "masked_norm"));
+        if (L.flags)
+            MGFR_TRY(hip_check(c, mgfr::masked_norm(L.g, L.flags, L.w, L.u, rho, c->mpart, &nparts, s), "masked_norm"));
+        else
+            MGFR_TRY(hip_check(c, mgfr::masked_norm(L.g, L.mask, L.w, L.u, rho, c->mpart, &nparts, s), "masked_norm"));
         MGFR_TRY(hip_check(c, mgfr::fold_partials(c->mpart, nparts, c->red, s), "fold_partials"));
         double r[2];
         MGFR_TRY(read_reduction(c, s, r));
@@ -179,6 +192,14 @@ int mg_fr_solve_masked(mgfr_ctx* c, const double* rho, const float* mask, int N,
     double mx;
     MGFR_TRY(count_active(c, mask, ncell, s, &L0.active, &mx));
     if (!(mx <= 1.0)) return c->fail(MGFR_EINVAL, "mask values must lie in [-1, 1] (max |mask| = %g)", mx);
+    // a mask of +1 and -1 only is read as byte flags on this level (the same values)
+    {
+        int nparts = 0;
+        MGFR_TRY(hip_check(c, mgfr::masked_flags(mask, ncell, c->mflags, c->partial, &nparts, s), "masked_flags"));
+        MGFR_TRY(hip_check(c, mgfr::fold_partials(c->partial, nparts, c->red, s), "fold_partials"));
+        MGFR_TRY(read_reduction(c, s, r));
+        L0.flags = r[0] == 0.0 ? c->mflags : nullptr;
+    }
     // fixed values: u on entry; coarse masks and fixed values by 8-child means
     MGFR_TRY(hip_check(c, hipMemcpyAsync(L0.w, u, sizeof(double) * ncell, hipMemcpyDeviceToDevice, s),
                        "hipMemcpyAsync"));

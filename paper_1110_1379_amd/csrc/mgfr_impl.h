@@ -46,11 +46,21 @@ hipError_t masked_count(const float* mask, long long n, double* partial, int* np
 // Coarse mask and w of level gc: 8-child means of the finer level's.
 hipError_t masked_restrict_setup(const Grid& gc, const float* maskf, const double* wf, float* maskc, double* wc,
                                  hipStream_t s);
-// One red-black Newton-Gauss-Seidel sweep of the active cells (one launch per colour).
+// Byte flags of a mask (1 where > 0), and block partials (first of each pair) of the number
+// of cells whose mask is neither +1 nor -1; their number in *nparts.
+hipError_t masked_flags(const float* mask, long long n, unsigned char* flags, double* partial, int* nparts,
+                        hipStream_t s);
+// One red-black Newton-Gauss-Seidel sweep of the active cells (one launch per colour).  The
+// byte-flag forms take a +1 / -1 mask as flags (1: active).
 hipError_t masked_ngs(const Grid& g, const float* mask, const double* w, double* u, const double* src, hipStream_t s);
+hipError_t masked_ngs(const Grid& g, const unsigned char* flags, const double* w, double* u, const double* src,
+                      hipStream_t s);
 // Into the level below: uc = uhat = R u and fc = R d at active coarse cells (w, w and 0 at
 // masked ones).
 hipError_t masked_resid_restrict(const Grid& g, const float* mask, const double* w, const double* u,
+                                 const double* src, const float* maskc, const double* wc, double* uc, double* uhat,
+                                 double* fc, hipStream_t s);
+hipError_t masked_resid_restrict(const Grid& g, const unsigned char* flags, const double* w, const double* u,
                                  const double* src, const float* maskc, const double* wc, double* uc, double* uhat,
                                  double* fc, hipStream_t s);
 // f = L^H(uhat) - f at active cells of the coarse level gc.
@@ -65,6 +75,8 @@ hipError_t masked_prolong(const Grid& gc, const float* maskc, const double* uc, 
 long long masked_norm_partials(const Grid& g);
 hipError_t masked_norm(const Grid& g, const float* mask, const double* w, const double* u, const double* src,
                        double* partial, int* nparts, hipStream_t s);
+hipError_t masked_norm(const Grid& g, const unsigned char* flags, const double* w, const double* u,
+                       const double* src, double* partial, int* nparts, hipStream_t s);
 // Coarsest level (n <= 8), one workgroup: sweeps until rms <= rtol x initial, or the rounding
 // floor, or cap;
 // the sweep count is added to *sweeps.
@@ -273,7 +285,7 @@ hipError_t ngs_sweep32(const Grid& g, const float* ub, float* e, const float* f,
 // Tiles of the single-precision fused sweep: one tile column pair per thread on 16 x 32,
 // 32 x 32 or 16 x 64 tiles (the last two: 512 threads), or the 8 x 32 tile whose pairs cover
 // the tile and its halo.
-constexpr int kTile16x32 = 1, kTile32x32 = 2, kTile16x64 = 3, kTile32Paired = 4;
+constexpr int kTile16x32 = 1, kTile32x32 = 2, kTile16x64 = 3, kTile32Paired = 4, kTile32x64 = 5;
 hipError_t ngs_sweep32_fused(const Grid& g, const float* ub, const float* ein, float* eout, const float* f,
                              int ti, int tile, hipStream_t s);
 hipError_t resid_restrict32(const Grid& g, const float* ub, const float* e, const float* f, float* ec,

@@ -1085,9 +1085,10 @@ int mgfr_autotune(mgfr_ctx* c, const double* rho, int N, const mgfr_params* para
             MGFR_TRY(consider(o));
         }
         // stage 3: its tile (double precision: 16 x 64 or 8 x 64; single precision: 16 x 32,
-        // 32 x 32 or 16 x 64 with one column pair per thread, or 8 x 32 with pairs over the halo)
+        // 32 x 32, 16 x 64 or 32 x 64 with one column pair per thread, or 8 x 32 with pairs
+        // over the halo)
         const mgfr_opts stage2 = cur_best;
-        const int ntile = base->precision == MGFR_MIXED ? 4 : 2;
+        const int ntile = base->precision == MGFR_MIXED ? 5 : 2;
         for (int tile = 1; tile <= ntile; ++tile) {
             mgfr_opts o = stage2;
             o.tile = tile;

@@ -450,13 +450,15 @@ def mgfr_autotune(ctx: Context, rho, params: Params, base: mgfr_opts | None = No
                   stream=None, cache_path: str | None = None, key: str | None = None):
     """Times candidate settings (sweeps, planes per workgroup, inner cycles) on this problem and
     returns (best opts, best solve ms).  With cache_path, results are kept in a JSON file under
-    `key` (default: N and precision) and reused without timing."""
+    `key` (default: N, precision and the GPU architecture) and reused without timing."""
     import json
     import torch
     if base is None:
         base = mgfr_default_opts()
     N = rho.shape[0]
-    key = key or f"N={N},precision={base.precision}"
+    if key is None:
+        arch = torch.cuda.get_device_properties(rho.device).gcnArchName.split(":")[0]
+        key = f"N={N},precision={base.precision},arch={arch}"
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
