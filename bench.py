@@ -37,7 +37,27 @@ METRIC = "f(R) MG time-to-residual 1e-8 & cell-updates/s, 512^3, FP64 vs mixed"
 # of the sources those kernels are compiled from (the kernel file, its device header and the
 # by-value kernel types): when any of them differs the figure no longer describes the kernel
 # that runs and `traffic` is reported as null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # per finest launch (one red-black sweep of the correction, 16 x 64 tiles, 32 planes)
+    "mixed": {"bytes": 3.0591e9, "sources": {
+        "kernels_fp32.hip": "b3baae8fa2c777348557489cc62ee26d086124d17ada2392195053d4ff690cd4",
+        "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
+        "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
+    # per finest launch (one red-black sweep, 16 x 64 tiles, 128 planes per workgroup)
+    "fp64": {"bytes": 3.4275e9, "sources": {
+        "sweep_fp64.hip": "52fc69d7da60d3ca2f99db208d943e175ded4ad6bf8ace4cd379e03154f184c8",
+        "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
+        "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
+    # per sweep (both colour launches of the masked per-colour kernel, byte flags)
+    "masked": {"bytes": 11.585e9, "sources": {
+        "masked.hip": "df27c0acbfb0992e4429674a6417061994c747ff653a7d93435f03746fa7a236",
+        "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
+        "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
+    # per pass of two sweeps
+    "poisson": {"bytes": 3.6313e9, "sources": {
+        "poisson_kernels.hip": "8ef270f9a78d0ee210179a3dab0de7499c9764aa3bab3ed9d665d4bd122c4738",
+        "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
+}
 
 
 def measured_traffic(prec, N):
@@ -472,7 +492,8 @@ def bench_masked(args):
                         "traffic": measured_traffic("masked", N),
                         "traffic_unit": "HBM bytes per sweep (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                         "kernel": "masked red-black sweep km_ngs_colour, both colours (finest level)",
-                        "bytes_per_sweep": "4 N^3 (mask) + 24 per active cell (u read and write, density)",
+                        "bytes_per_sweep": "1 N^3 (the mask as byte flags: it holds only +1 and -1) + 24 per "
+                                           "active cell (u read and write, density)",
                         "sweeps": sweeps, "avg_sweep_ms": s["sweep_ms"] / sweeps if sweeps else None}}
     if not args.no_cpu_baseline:
         import oracle
@@ -611,7 +632,7 @@ def _engine_name(args):
     return {"units": "workgroup per unit", "phases": "per phase", "both": "workgroup per unit"}[args.engine]
 
 
-def _batched_roofline(s, prec_name, unit_n=0):
+def _batched_roofline(s, prec_name, unit_n=0, phases=False):
     """Roofline object of the batched smoother from the statistics of a solve run eagerly with
     MGFR_PROFILE: HIP events around the finest-level sweeps of the units launched per phase
     (the two colour launches of kb_ngs / kb32_ngs), algorithmic bytes of the sweeps those
@@ -622,7 +643,8 @@ def _batched_roofline(s, prec_name, unit_n=0):
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
             "kernel": ("kb_ngs" if fp64 else "kb32_ngs") + " (red-black Newton-Gauss-Seidel, one launch per "
-                      f"colour over the finest level of every unit larger than {unit_n or 16}^3)",
+                      "colour over the finest level of every unit" +
+                      ("" if phases else f" larger than {unit_n or 16}^3") + ")",
             "bytes_per_cell": 24 if fp64 else 12, "launches": launches,
             "avg_launch_ms": s["sweep_ms"] / launches if launches else None,
             "timing": "one more solve of the same problem after the timed steps, launched eagerly (no graph) "
@@ -671,12 +693,13 @@ def bench_amr(args):
                  "max_cycles_per_patch": int(max(len(h) for h in hists) - 1),
                  "max_final_residual": float(max(h[-1] for h in hists))}
             log(f"amr {engine} {name}: {ms:.2f} ms, {r['max_cycles_per_patch']} cycles max")
-            if engine == "phases":
+            if engine == "phases" and args.engine == "both":
                 per_phase[name] = r
                 continue
 
-            def solve_profiled(code=code):
-                po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=mgfr.MGFR_PROFILE,
+            def solve_profiled(code=code, eflags=eflags):
+                pflags = mgfr.MGFR_PROFILE | (eflags & mgfr.MGFR_PER_PHASE)
+                po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=pflags,
                                             unit_n=args.unit_n)
                 _, _, st = mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, po, u_packed=torch.empty_like(rp))
                 assert st == mgfr.MGFR_OK, ctx.last_error()
@@ -699,7 +722,7 @@ def bench_amr(args):
     out.update(runs)
     if per_phase:
         out["per_phase_engine"] = per_phase
-    out["roofline"] = _batched_roofline(profiled[headp](), headp, args.unit_n)
+    out["roofline"] = _batched_roofline(profiled[headp](), headp, args.unit_n, args.engine == "phases")
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
         out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])
@@ -753,12 +776,13 @@ def bench_batch(args):
                  "max_cycles_per_box": int(max(len(h) for h in hists) - 1),
                  "max_final_residual": float(max(h[-1] for h in hists))}
             log(f"batch {engine} {name}: {ms:.2f} ms, {r['max_cycles_per_box']} cycles max")
-            if engine == "phases":
+            if engine == "phases" and args.engine == "both":
                 per_phase[name] = r
                 continue
 
-            def solve_profiled(code=code):
-                po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=mgfr.MGFR_PROFILE,
+            def solve_profiled(code=code, eflags=eflags):
+                pflags = mgfr.MGFR_PROFILE | (eflags & mgfr.MGFR_PER_PHASE)
+                po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=pflags,
                                             unit_n=args.unit_n)
                 _, _, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, po, us=[torch.empty_like(r) for r in rhos])
                 assert st == mgfr.MGFR_OK, ctx.last_error()
@@ -779,7 +803,7 @@ def bench_batch(args):
     out.update(runs)
     if per_phase:
         out["per_phase_engine"] = per_phase
-    out["roofline"] = _batched_roofline(profiled[headp](), headp, args.unit_n)
+    out["roofline"] = _batched_roofline(profiled[headp](), headp, args.unit_n, args.engine == "phases")
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
         out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])

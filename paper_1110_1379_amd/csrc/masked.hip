@@ -12,9 +12,7 @@
 // is prolongated into active fine cells only (Sec. V.A.2, V.A.3, V.B.2).
 //
 // On the finest level a mask that only holds +1 and -1 is read as one byte per cell (1:
-// active), which gives the same values as the float mask.  The per-cell kernels renumber
-// their workgroups so that each XCD takes a contiguous range of rows: a cell's neighbours in
-// the rows and planes next to it are then mostly in that XCD's L2.
+// active), which gives the same values as the float mask.
 #include "device_fp64.h"
 
 namespace mgfr {
@@ -31,14 +29,6 @@ using u8 = unsigned char;
 // mask value of cell q: the float mask, or a byte flag standing for +1 / -1
 __device__ __forceinline__ double mval(const float* __restrict__ m, long long q) { return m[q]; }
 __device__ __forceinline__ double mval(const u8* __restrict__ m, long long q) { return m[q] ? 1.0 : -1.0; }
-
-// Workgroups are dealt to the 8 XCDs in turn; this numbering gives each XCD a contiguous
-// eighth of the grid.
-__device__ __forceinline__ long long xcd_block()
-{
-    const long long nb = gridDim.x, b = blockIdx.x;
-    return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
-}
 
 // L_i - f and dL_i/du_i at active cell (i,j,k) of value ui, mask mi.
 template <class M>
@@ -156,7 +146,7 @@ __global__ void __launch_bounds__(kB) km_ngs_colour(Grid g, const M* __restrict_
                                                     const double* __restrict__ src, int colour)
 {
     const long long half = 1LL << (3 * g.lg - 1);
-    const long long t = xcd_block() * kB + threadIdx.x;
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
     if (t >= half) return;
     const int hk = g.n >> 1;
     const int s = (int)(t & (hk - 1));
@@ -182,7 +172,7 @@ __global__ void __launch_bounds__(kB) km_resid_restrict(Grid g, const M* __restr
                                                         double* __restrict__ uhat, double* __restrict__ fc)
 {
     const int lgc = g.lg - 1, nc = g.n >> 1;
-    const long long tc = xcd_block() * kB + threadIdx.x;
+    const long long tc = (long long)blockIdx.x * kB + threadIdx.x;
     if (tc >= (1LL << (3 * lgc))) return;
     if (!(maskc[tc] > 0.0f)) {
         uc[tc] = wc[tc];
@@ -214,7 +204,7 @@ __global__ void __launch_bounds__(kB) km_fas_rhs(Grid g, const float* __restrict
                                                  const double* __restrict__ w, const double* __restrict__ uhat,
                                                  double* __restrict__ f)
 {
-    const long long q = xcd_block() * kB + threadIdx.x;
+    const long long q = (long long)blockIdx.x * kB + threadIdx.x;
     if (q >= (1LL << (3 * g.lg))) return;
     const double mi = mask[q];
     if (!(mi > 0.0)) return;
@@ -244,7 +234,7 @@ __global__ void __launch_bounds__(kB) km_norm(Grid g, const M* __restrict__ mask
     const int lgc = g.lg - 1, nc = g.n >> 1;
     const long long nblk = 1LL << (3 * lgc);
     double s = 0.0, mx = 0.0;
-    const long long t = xcd_block() * kB + threadIdx.x;
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
     if (t < nblk) {
         const int I = (int)(t >> (2 * lgc)), J = (int)((t >> lgc) & (nc - 1)), K = (int)(t & (nc - 1));
 #pragma unroll
