@@ -160,9 +160,17 @@ def field_error_vs_oracle(mgfr, ctx, name, used, tol):
     scale = float(np.abs(ref).max())
     out = {"sample": f"{Ns}^3 box of {box_s:g} Mpc/h (the CPU-baseline sample); oracle at rms 1e-12 "
                      f"({len(hist) - 1} V-cycles); GPU at the timed settings and tolerance {tol:g}"}
+    # the oracle stopped where the timed solves stop: the same tolerance and sweep counts
+    first = next(iter(used.values()))
+    same, hs, st = oracle.solve(rho, oracle.Model(box_mpc_h=box_s, fr0_abs=fr0),
+                                oracle.Opts(tol=tol, pre=first.pre, post=first.post))
+    if st != 0:
+        raise SystemExit(f"oracle same-tolerance solve failed: status {st}")
+    out["same_tolerance"] = {"oracle": f"rms {tol:g}, {first.pre}+{first.post} sweeps ({len(hs) - 1} V-cycles, "
+                                       f"final {hs[-1]:.3e})"}
+    import ctypes
     for pname, opts in used.items():
         o = mgfr.mgfr_opts()
-        import ctypes
         ctypes.memmove(ctypes.byref(o), ctypes.byref(opts), ctypes.sizeof(o))
         o.flags = 0
         if o.planes > Ns:
@@ -170,9 +178,13 @@ def field_error_vs_oracle(mgfr, ctx, name, used, tol):
         u, h, st = mgfr.mg_fr_solve(ctx, rho_d, params, o)
         if st != mgfr.MGFR_OK:
             raise SystemExit(f"sample solve failed: {ctx.last_error()}")
-        d = np.abs(u.cpu().numpy() - ref)
+        un = u.cpu().numpy()
+        d = np.abs(un - ref)
         out[pname] = {"max_abs": float(d.max()), "rms_abs": float(np.sqrt(np.mean(d * d))),
                       "max_rel": float(d.max() / scale), "cycles": len(h) - 1, "final_residual": float(h[-1])}
+        d2 = np.abs(un - same)
+        out["same_tolerance"][pname] = {"max_abs": float(d2.max()), "rms_abs": float(np.sqrt(np.mean(d2 * d2))),
+                                        "max_rel": float(d2.max() / scale)}
     return out
 
 
@@ -223,6 +235,12 @@ def time_domain(mgfr, ctx, rho_d, params, prec, tol, steps, warmup, profile=True
     log(f"prec={prec}: {ms:.2f} ms/solve, {res['cycles']} cycles, smoother "
         f"{achieved and round(achieved)} GB/s over {launches} launches")
     return res, u_d, opts
+
+
+def _k32_name(settings):
+    """The single-precision fused sweep the tile setting selects."""
+    return {0: "k32_fused2<16, 32>", 1: "k32_fused2<16, 32>", 2: "k32_fused2<32, 32>", 3: "k32_fused2<16, 64>",
+            4: "k32_fused<8, 32, 256>", 5: "k32_fused2<32, 64>"}.get(settings.get("tile", 0), "k32_fused2")
 
 
 def graph_ab(mgfr, ctx, rho_d, params, opts, steps):
@@ -332,7 +350,7 @@ def bench_domain(args):
             "bound": "hbm", "achieved": sm["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (sm["achieved_GBs"] / HBM_PEAK_GBS) if sm["achieved_GBs"] else None,
             "traffic": measured_traffic(headp, N),
-            "kernel": ("single-precision correction smoother k32_fused" if headp == "mixed"
+            "kernel": (f"single-precision correction smoother {_k32_name(head['settings'])}" if headp == "mixed"
                        else "double-precision smoother k_ngs_fused") + " (finest level)",
             "bytes_per_cell": sm["bytes_per_cell_sweep"], "launches": sm["launches"],
             "avg_launch_ms": sm["avg_launch_ms"],
