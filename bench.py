@@ -660,9 +660,10 @@ def _batched_roofline(s, prec_name, unit_n=0, phases=False):
     fp64 = prec_name == "fp64"
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
-            "kernel": ("kb_ngs" if fp64 else "kb32_ngs") + " (red-black Newton-Gauss-Seidel, one launch per "
-                      "colour over the finest level of every unit" +
-                      ("" if phases else f" larger than {unit_n or 16}^3") + ")",
+            "kernel": ("kc_ngs<P64> / kb_ngs" if fp64 else "kc_ngs<P32> / kb32_ngs") +
+                      " (red-black Newton-Gauss-Seidel, one launch per colour over the finest level of every unit" +
+                      ("" if phases else f" larger than {unit_n or 16}^3") +
+                      "; column tiles for periodic boxes of side >= 32, one thread per cell for patches)",
             "bytes_per_cell": 24 if fp64 else 12, "launches": launches,
             "avg_launch_ms": s["sweep_ms"] / launches if launches else None,
             "timing": "one more solve of the same problem after the timed steps, launched eagerly (no graph) "
@@ -697,7 +698,7 @@ def bench_amr(args):
         for name, code in _precisions(mgfr, args):
             eflags = (mgfr.MGFR_GRAPH if args.graph else 0) | (mgfr.MGFR_PER_PHASE if engine == "phases" else 0)
             opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=eflags,
-                                          unit_n=args.unit_n)
+                                          unit_n=args.unit_n, tile=args.batch_sweep_tile)
             up = torch.empty_like(rp)
 
             def solve(opts=opts, up=up):
@@ -718,7 +719,7 @@ def bench_amr(args):
             def solve_profiled(code=code, eflags=eflags):
                 pflags = mgfr.MGFR_PROFILE | (eflags & mgfr.MGFR_PER_PHASE)
                 po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=pflags,
-                                            unit_n=args.unit_n)
+                                            unit_n=args.unit_n, tile=args.batch_sweep_tile)
                 _, _, st = mgfr.mg_fr_solve_patches(ctx, ud, patches, rp, params, po, u_packed=torch.empty_like(rp))
                 assert st == mgfr.MGFR_OK, ctx.last_error()
                 return mgfr.mgfr_get_stats(ctx)
@@ -779,7 +780,7 @@ def bench_batch(args):
         for name, code in _precisions(mgfr, args):
             eflags = (mgfr.MGFR_GRAPH if args.graph else 0) | (mgfr.MGFR_PER_PHASE if engine == "phases" else 0)
             opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=eflags,
-                                          unit_n=args.unit_n)
+                                          unit_n=args.unit_n, tile=args.batch_sweep_tile)
             us = [torch.empty_like(r) for r in rhos]
 
             def solve(opts=opts, us=us):
@@ -801,7 +802,7 @@ def bench_batch(args):
             def solve_profiled(code=code, eflags=eflags):
                 pflags = mgfr.MGFR_PROFILE | (eflags & mgfr.MGFR_PER_PHASE)
                 po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=pflags,
-                                            unit_n=args.unit_n)
+                                            unit_n=args.unit_n, tile=args.batch_sweep_tile)
                 _, _, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, po, us=[torch.empty_like(r) for r in rhos])
                 assert st == mgfr.MGFR_OK, ctx.last_error()
                 return mgfr.mgfr_get_stats(ctx)
@@ -870,6 +871,10 @@ def main():
     ap.add_argument("--engine", default="both", choices=["units", "phases", "both"],
                     help="amr/batch: the workgroup-per-unit engine (the line's value), the per-phase engine "
                          "(baseline), or both")
+    ap.add_argument("--batch-sweep", default="auto", choices=["auto", "cell", "column"],
+                    help="amr/batch: sweeps of unit levels of side >= 32 over column tiles for periodic boxes "
+                         "and one thread per cell of the colour for patches (auto, the default), one thread per "
+                         "cell everywhere (cell), or column tiles everywhere (column)")
     ap.add_argument("--unit-n", type=int, default=0,
                     help="amr/batch: units and levels of side <= this run in one workgroup (0: the library's 16)")
     ap.add_argument("--no-graph-ab", action="store_true",
@@ -879,6 +884,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy three times (calibrates HBM counters)")
     args = ap.parse_args()
+    args.batch_sweep_tile = {"auto": 0, "cell": 1, "column": 2}[args.batch_sweep]
     if args.copy_probe:
         import torch
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")

@@ -102,7 +102,13 @@ typedef struct mgfr_opts {
                              the tile and its halo; 3 - 5 as 0).  Mixed, the single-precision
                              correction sweep: 0 = automatic (16 x 32), 1 = 16 x 32, 2 = 32 x
                              32, 3 = 16 x 64, 5 = 32 x 64 (one tile column pair per thread),
-                             4 = 8 x 32 (column pairs over the tile and its halo)   [0]      */
+                             4 = 8 x 32 (column pairs over the tile and its halo).
+                             Batched solves, launched sweeps of unit levels of side >=
+                             32: 0 = periodic boxes walk 16 x 32 column tiles through 16
+                             planes per workgroup, patches one thread per cell of the
+                             colour; 1 = one thread per cell everywhere; 2 = column
+                             tiles for patches too; 3 - 5 as 0 (same results, bit for
+                             bit)                                                 [0]      */
 } mgfr_opts;
 
 /* One refinement patch: a cube of n^3 cells at refinement level `level` >= 1 (cell size

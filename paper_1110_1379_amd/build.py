@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmgfr.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["kernels_fp64.hip", "sweep_fp64.hip", "resid_fp64.hip", "prolong.hip", "kernels_fp32.hip", "batch_fp64.hip",
-           "batch_fp32.hip", "poisson_kernels.hip", "solver.hip", "batch.hip", "poisson.hip", "masked.hip",
+           "batch_fp32.hip", "batch_col.hip", "poisson_kernels.hip", "solver.hip", "batch.hip", "poisson.hip", "masked.hip",
            "masked_solver.hip", "tsc.hip", "unit.hip"]
 ARCH = os.environ.get("MGFR_OFFLOAD_ARCH", "gfx950")
 

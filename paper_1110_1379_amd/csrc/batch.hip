@@ -53,8 +53,15 @@ struct Launch {
     int nblk = 0, ngrid = 0;
 };
 
+// Red-black sweep of one depth: the grids swept by column tiles (side >= 32) and the rest, one
+// thread per cell of the colour.
+struct Sweep {
+    Launch cell, col;
+};
+
 struct Depth {
-    Launch half_f, coarse_f, coarse_c, fine_f, faces_c, crs;
+    Sweep half;
+    Launch coarse_f, coarse_c, fine_f, faces_c, crs;
     bool deep = false, coarsest = false;
 };
 
@@ -71,7 +78,8 @@ struct Plan {
 // workgroup from level m + 1 (tails: (index of that level in the all-levels array, levels
 // from there)).
 struct UDepth {
-    Launch half_f, coarse_f, coarse_c, fine_f;
+    Sweep half;
+    Launch coarse_f, coarse_c, fine_f;
     size_t tails = 0;
     int ntail = 0;
     bool deep = false;
@@ -113,6 +121,32 @@ Launch table(Meta& meta, const std::vector<mgfr::BGrid>& grids, W work, std::vec
 }
 
 long long cells3(const mgfr::BGrid& g) { return 1LL << (3 * g.lg); }
+
+// Sweep tables of the grids f: column tiles for the grids that take them (side >= 32;
+// tile = 0: periodic boxes only, 2: patches too, 1: none), one thread per cell of the colour
+// for the others.
+Sweep sweep_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, int tile)
+{
+    std::vector<mgfr::BGrid> cell, col;
+    std::vector<int2> blk;
+    for (const mgfr::BGrid& g : f) {
+        const bool want = tile == 2 || (tile == 0 && g.periodic);
+        const long long nt = want ? mgfr::batch_col_tiles(g.n) : 0;
+        if (nt == 0) {
+            cell.push_back(g);
+            continue;
+        }
+        for (long long b = 0; b < nt; ++b) blk.push_back(make_int2((int)col.size(), (int)b));
+        col.push_back(g);
+    }
+    Sweep S;
+    S.cell = table(meta, cell, [](const mgfr::BGrid& g) { return cells3(g) / 2; });
+    S.col.grids = meta.add(col);
+    S.col.blk = meta.add(blk);
+    S.col.nblk = (int)blk.size();
+    S.col.ngrid = (int)col.size();
+    return S;
+}
 
 struct Batch {
     mgfr_ctx* c;
@@ -274,7 +308,7 @@ struct Batch {
             D.deep = !f.empty();
             D.coarsest = !crs.empty();
             if (D.deep) {
-                D.half_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 2; });
+                D.half = sweep_tables(meta, f, o->tile);
                 D.fine_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g); });
                 D.coarse_c = table(meta, cgr, [](const mgfr::BGrid& g) { return cells3(g); });
                 // resid_restrict: table over the coarse cells, indexed by the fine grids
@@ -366,7 +400,7 @@ struct Batch {
             if (f.empty()) break;
             UDepth D;
             D.deep = true;
-            D.half_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 2; });
+            D.half = sweep_tables(meta, f, o->tile);
             D.fine_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g); });
             D.coarse_c = table(meta, cg, [](const mgfr::BGrid& g) { return cells3(g); });
             D.coarse_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 8; });
@@ -481,12 +515,30 @@ struct Batch {
         return MGFR_OK;
     }
 
+    // One red-black sweep of a depth's grids (grids are independent: the two tables in turn).
+    int ngs(const Sweep& S, bool mixed)
+    {
+        if (S.cell.nblk > 0) {
+            if (mixed)
+                MGFR_TRY(hip_check(c, mgfr::batch_ngs32(tab(S.cell), S.cell.nblk, s), "batch_ngs32"));
+            else
+                MGFR_TRY(hip_check(c, mgfr::batch_ngs(tab(S.cell), S.cell.nblk, s), "batch_ngs"));
+        }
+        if (S.col.nblk > 0) {
+            if (mixed)
+                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_col(tab(S.col), S.col.nblk, s), "batch_ngs32_col"));
+            else
+                MGFR_TRY(hip_check(c, mgfr::batch_ngs_col(tab(S.col), S.col.nblk, s), "batch_ngs_col"));
+        }
+        return MGFR_OK;
+    }
+
     // read u and rho, write u
     int sweep(int m)
     {
         const Depth& D = plan.depth[m];
         MGFR_TRY(ev_begin(m));
-        MGFR_TRY(hip_check(c, mgfr::batch_ngs(tab(D.half_f), D.half_f.nblk, s), "batch_ngs"));
+        MGFR_TRY(ngs(D.half, false));
         return ev_end(m, 24.0);
     }
 
@@ -519,7 +571,7 @@ struct Batch {
     {
         const Depth& D = plan.depth[m];
         MGFR_TRY(ev_begin(m));
-        MGFR_TRY(hip_check(c, mgfr::batch_ngs32(tab(D.half_f), D.half_f.nblk, s), "batch_ngs32"));
+        MGFR_TRY(ngs(D.half, true));
         return ev_end(m, 12.0);
     }
 
@@ -793,10 +845,7 @@ struct Batch {
         const UDepth& D = up.depth[m];
         const bool timed = m == 0 && (o->flags & MGFR_PROFILE) && !(o->flags & MGFR_GRAPH);
         if (timed) MGFR_TRY(ev_begin(0));
-        if (mixed)
-            MGFR_TRY(hip_check(c, mgfr::batch_ngs32(utab(D.half_f), D.half_f.nblk, s), "batch_ngs32"));
-        else
-            MGFR_TRY(hip_check(c, mgfr::batch_ngs(utab(D.half_f), D.half_f.nblk, s), "batch_ngs"));
+        MGFR_TRY(ngs(D.half, mixed));
         if (timed) {
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
             c->ev_used += 2;

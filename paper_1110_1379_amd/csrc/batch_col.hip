@@ -1,0 +1,324 @@
+// Batched red-black sweeps of units of side >= 32, one colour per launch, column-walking:
+// a workgroup owns a 16 x 32 column tile of one unit and a chunk of 16 planes i, which it
+// walks in order.  Each plane of the tile and its one-cell in-plane halo is staged in LDS
+// once, with everything a neighbour contributes (double precision: u and b = exp(u); single
+// precision: ub, e, B and M), so a cell's exponentials are evaluated once per launch instead
+// of at every visit from each of its six neighbours.  Outside a patch the staged value is the
+// boundary value u_b of the face there (the face term needs only u_b and the cell's own
+// value), so no visit waits on a load.  Loads run kAhead planes ahead of the plane being
+// updated: the raw values of the next planes are in flight while the current one is relaxed.
+//
+// The update of a cell of the colour is that of kb_ngs / kb32_ngs (batch_dev.h: bcell,
+// bcell32), with the same operands in the same order, so the results are the same bits.
+// Each thread updates one cell of the colour per plane, in place: within one colour launch a
+// cell's neighbours are all of the other colour and are not written.
+#include "batch_dev.h"
+
+namespace mgfr {
+namespace {
+
+using namespace bdev;
+
+constexpr int kTJ = 16, kTK = 32, kTI = 16;     // tile and plane chunk
+constexpr int kAhead = 4;                       // planes whose loads are in flight
+constexpr int kNT = kTJ * kTK / 2;              // one cell of the colour per thread per plane
+constexpr int kLK = kTK + 2, kNL = (kTJ + 2) * kLK;
+constexpr int kSlots = (kNL + kNT - 1) / kNT;   // staged entries per thread and plane
+constexpr int kRing = 4;                        // staged planes p - 1 .. p + 2
+
+// Global-memory accesses through the pointers of a grid descriptor.  Read from a table, they
+// would otherwise be accessed as flat addresses, which the LDS wait before every barrier of
+// the walk also waits for: the loads issued for the planes ahead would have to land first.
+template <class T>
+__device__ __forceinline__ T gload(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ void gstore(T* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// ---- the two precisions ------------------------------------------------------------------
+// Raw: what is loaded for a staged entry, from offset off of the cell values or (face) of
+// the boundary values; Lds: what is staged; Rhs: the right-hand side of a cell.  A staged
+// entry outside a patch holds the face's u_b in its first field.  The loads take no branch
+// on the kind of entry (a branch whose result is converted or copied at its join would wait
+// there for every load in flight).
+struct P64 {
+    using Raw = double;
+    using Lds = double2;
+    using Rhs = double;
+    __device__ __forceinline__ static Raw load(const BGrid& g, bool face, long long off)
+    {
+        const double* base = face ? g.ub : g.u;
+        return gload(base + off);
+    }
+    __device__ __forceinline__ static Raw cell(const BGrid& g, unsigned off) { return gload(g.u + off); }
+    __device__ __forceinline__ static Lds make(Raw v, bool) { return make_double2(v, exp(v)); }
+    __device__ __forceinline__ static Rhs rhs(const BGrid& g, unsigned q) { return gload(g.src + q); }
+
+    // bcell's update with the neighbours (i-1, i+1, j-1, j+1, k-1, k+1) and the cell from LDS
+    __device__ __forceinline__ static void update(const BGrid& g, unsigned q, const bool (&out)[6], const Lds (&nb)[6], Lds c, Rhs src)
+    {
+        const double ui = c.x, bi = c.y;
+        double su = 0.0, sb = 0.0, sbu = 0.0, lg_ = 0.0, dlg = 0.0;
+        int nreg = 0;
+#pragma unroll
+        for (int x = 0; x < 6; ++x) {
+            if (out[x]) {
+                const double ug = (1.0 - kR) * nb[x].x + kR * ui;
+                const double bg = exp(ug);
+                lg_ += (bg + bi) * (ug - ui);
+                dlg += (kR * bg + bi) * (ug - ui) + (bg + bi) * (kR - 1.0);
+            } else {
+                const double un = nb[x].x, bn = nb[x].y, du = un - ui;
+                su += du;
+                sb += bn;
+                sbu = fma(bn, du, sbu);
+                ++nreg;
+            }
+        }
+        const double S = g.A * exp(-ui * g.inv_np1);
+        const double L = g.C * (fma(bi, su, sbu) + lg_) + S - fma(g.fscale, src - g.sref, g.fshift);
+        const double dL = g.C * (fma(bi, su, -sb) - nreg * bi + dlg) - S * g.inv_np1;
+        gstore(g.u + q, ui + dev::bounded(-L / dL, g.max_step));
+    }
+};
+
+struct F2 {
+    float x, y;
+};
+
+struct P32 {
+    using Raw = F2;
+    using Lds = V32;
+    using Rhs = float;
+    // a cell: (ub, e); a face: the two halves of the double u_b
+    __device__ __forceinline__ static Raw load(const BGrid& g, bool face, long long off)
+    {
+        const float* px = face ? (const float*)(g.ub + off) : g.ub32 + off;
+        const float* py = face ? px + 1 : g.e32 + off;
+        return F2{gload(px), gload(py)};
+    }
+    __device__ __forceinline__ static Raw cell(const BGrid& g, unsigned off)
+    {
+        return F2{gload(g.ub32 + off), gload(g.e32 + off)};
+    }
+    __device__ __forceinline__ static Lds make(Raw v, bool face)
+    {
+        const unsigned long long bits = ((unsigned long long)__builtin_bit_cast(unsigned, v.y) << 32) |
+                                        __builtin_bit_cast(unsigned, v.x);
+        const float ubf = (float)__builtin_bit_cast(double, bits);
+        return make_v(face ? ubf : v.x, face ? 0.0f : v.y);
+    }
+    __device__ __forceinline__ static Rhs rhs(const BGrid& g, unsigned q) { return gload(g.f32 + q); }
+
+    // bcell32's update with the neighbours and the cell from LDS
+    __device__ __forceinline__ static void update(const BGrid& g, unsigned q, const bool (&out)[6], const Lds (&nb)[6], Lds c, Rhs f)
+    {
+        const Op32 o = op32(g);
+        float t1 = 0.0f, t2 = 0.0f, su = 0.0f, se = 0.0f, sB = 0.0f, nreg = 0.0f, lgh = 0.0f, dgh = 0.0f;
+#pragma unroll
+        for (int x = 0; x < 6; ++x) {
+            if (out[x]) {
+                const float ubg = (1.0f - kR32) * nb[x].ub + kR32 * c.ub;
+                const float eg = kR32 * c.e;
+                const float bg = __expf(ubg);
+                const float Mg = bg * em1f(eg), Bg = bg + Mg;
+                const float du = ubg - c.ub, de = eg - c.e;
+                lgh += (Mg + c.M) * du + (Bg + c.B) * de;
+                dgh += (kR32 * Bg + c.B) * (du + de) + (Bg + c.B) * (kR32 - 1.0f);
+            } else {
+                const V32 n = nb[x];
+                const float du = n.ub - c.ub, de = n.e - c.e;
+                t1 = fmaf(n.M, du, t1);
+                t2 = fmaf(n.B, de, t2);
+                su += du;
+                se += de;
+                sB += n.B;
+                nreg += 1.0f;
+            }
+        }
+        const float S = o.A * __expf(-c.ub * o.inv_np1);
+        const float xx = em1f(-c.e * o.inv_np1);
+        Res32 r;
+        r.N = o.C * (fmaf(c.M, su, t1) + fmaf(c.B, se, t2) + lgh) + S * xx - f;
+        r.dN = o.C * (c.B * (su + se) - sB - nreg * c.B + dgh) - S * o.inv_np1 * (1.0f + xx);
+        gstore(g.e32 + q, c.e + newton32(r, o.max_step));
+    }
+};
+
+// ---- the walk ------------------------------------------------------------------------------
+// Staged entry e = (row jj, column kk) of the tile and its halo: what a plane p holds there.
+//   kind 0: a cell of the unit (periodic: wrapped), at plane offset a = (j << lg) + k; on a
+//           patch's planes -1 and n it is the i-face's u_b at (f << 2 lg) + a, f = 0 / 1;
+//   kind 1: outside a patch in j or k only: the face's u_b at fq + (p << lg);
+//   kind 2: nothing (a corner of the halo, or past the halo).
+// Entries that hold nothing on a plane load cell (p, 0, 0) of the unit, or cell 0, in vain.
+struct Entry {
+    int kind, a, fq;
+};
+
+__device__ __forceinline__ Entry entry(const BGrid& g, int j0, int k0, int e)
+{
+    Entry s{2, 0, 0};
+    if (e >= kNL) return s;
+    const int m = g.n - 1;
+    int j = j0 - 1 + e / kLK, k = k0 - 1 + e % kLK;
+    if (g.periodic) {
+        j &= m;
+        k &= m;
+    }
+    const bool jo = j < 0 || j > m, ko = k < 0 || k > m;
+    if (!jo && !ko) {
+        s.kind = 0;
+        s.a = (j << g.lg) + k;
+    } else if (jo != ko) {
+        // face 2 / 3 (index (i, k)) or 4 / 5 (index (i, j))
+        const int f = jo ? (j < 0 ? 2 : 3) : (k < 0 ? 4 : 5);
+        s.kind = 1;
+        s.fq = (f << (2 * g.lg)) + (jo ? k : j);
+    }
+    return s;
+}
+
+// The walk of one tile, PER: the unit is a periodic box (no faces, indices wrap).
+template <class P, bool PER>
+__device__ __forceinline__ void walk(const BGrid g, int tile, int colour, typename P::Lds (*lv)[kNL])
+{
+    using Raw = typename P::Raw;
+    const int m = g.n - 1, lg = g.lg;
+    int i0, j0, k0;
+    {
+        const int ntk = g.n / kTK, ntj = g.n / kTJ;
+        k0 = (tile % ntk) * kTK;
+        tile /= ntk;
+        j0 = (tile % ntj) * kTJ;
+        i0 = (tile / ntj) * kTI;
+    }
+    const int t = threadIdx.x;
+    Entry en[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) en[s] = entry(g, j0, k0, t + s * kNT);
+
+    // raw values of plane p; a plane outside a patch holds its i-face
+    auto outside = [&](int p) { return !PER && (p < 0 || p > m); };
+    auto fetch = [&](int p, Raw (&r)[kSlots]) __attribute__((always_inline)) {
+        if (PER) {
+            const unsigned pl = (unsigned)(p & m) << (2 * lg);
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s) r[s] = P::cell(g, pl + (unsigned)en[s].a);
+        } else if (!outside(p)) {
+            const long long pl = (long long)p << (2 * lg);
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s) {
+                const bool face = en[s].kind == 1;
+                r[s] = P::load(g, face, face ? en[s].fq + (p << lg) : pl + en[s].a);
+            }
+        } else {
+            const int fb = (p < 0 ? 0 : 1) << (2 * lg);
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s) {
+                const bool face = en[s].kind == 0;
+                r[s] = P::load(g, face, face ? fb + en[s].a : 0);
+            }
+        }
+    };
+    auto put = [&](int p, const Raw (&r)[kSlots]) __attribute__((always_inline)) {
+        typename P::Lds* L = lv[(p - i0 + 1) % kRing];
+        const int fk = outside(p) ? 0 : 1;  // the kind that holds a face on this plane
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s)
+            if (en[s].kind != 2) L[t + s * kNT] = P::make(r[s], !PER && en[s].kind == fk);
+    };
+    // The cell of the colour that this thread relaxes on plane p: row jj of the tile, column
+    // kb or kb + 1 by the parity of p (i0 is even, so that of the step).  Its offset in the
+    // plane and its LDS entry for even and odd steps.
+    const int jj = t / (kTK / 2);
+    const int kb = 2 * (t - jj * (kTK / 2));
+    const int j = j0 + jj;
+    int kc[2];
+    unsigned jk[2];
+    int ec[2];
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        kc[par] = k0 + kb + ((par + j + colour) & 1);
+        jk[par] = ((unsigned)j << lg) + (unsigned)kc[par];
+        ec[par] = (jj + 1) * kLK + (kc[par] - k0) + 1;
+    }
+    auto cell_q = [&](int p, int par) { return ((unsigned)p << (2 * lg)) + jk[par]; };
+
+    Raw ahead[kAhead][kSlots];
+    typename P::Rhs rh[kAhead];
+    {
+        Raw r0[kSlots], r1[kSlots], r2[kSlots];
+        fetch(i0 - 1, r0);
+        fetch(i0, r1);
+        fetch(i0 + 1, r2);
+#pragma unroll
+        for (int d = 0; d < kAhead; ++d) fetch(i0 + 2 + d, ahead[d]);
+#pragma unroll
+        for (int d = 0; d < kAhead; ++d) rh[d] = P::rhs(g, cell_q(i0 + d, d & 1));
+        put(i0 - 1, r0);
+        put(i0, r1);
+        put(i0 + 1, r2);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kTI; ++s) {
+        const int p = i0 + s, d = s % kAhead, par = s & 1;
+        {
+            const typename P::Lds* Lm = lv[(s + 0) % kRing];
+            const typename P::Lds* L0 = lv[(s + 1) % kRing];
+            const typename P::Lds* Lp = lv[(s + 2) % kRing];
+            const int e = ec[par], k = kc[par];
+            const bool out[6] = {!PER && p == 0, !PER && p == m, !PER && j == 0,
+                                 !PER && j == m, !PER && k == 0, !PER && k == m};
+            const typename P::Lds nb[6] = {Lm[e], Lp[e], L0[e - kLK], L0[e + kLK], L0[e - 1], L0[e + 1]};
+            P::update(g, cell_q(p, par), out, nb, L0[e], rh[d]);
+        }
+        if (s + kAhead < kTI) rh[d] = P::rhs(g, cell_q(p + kAhead, par));
+        if (s + 2 <= kTI) put(p + 2, ahead[d]);
+        if (s + 2 + kAhead <= kTI) fetch(p + 2 + kAhead, ahead[d]);
+        __syncthreads();
+    }
+}
+
+template <class P>
+__global__ void __launch_bounds__(kNT) kc_ngs(BTable t, int colour)
+{
+    __shared__ typename P::Lds lv[kRing][kNL];
+    const int2 blk = t.blk[blockIdx.x];
+    const BGrid g = t.grids[blk.x];
+    if (!live(t, g)) return;
+    if (g.periodic)
+        walk<P, true>(g, blk.y, colour, lv);
+    else
+        walk<P, false>(g, blk.y, colour, lv);
+}
+
+}  // namespace
+
+long long batch_col_tiles(int n)
+{
+    if (n < kTK || n % kTK || n % kTI) return 0;
+    return (long long)(n / kTI) * (n / kTJ) * (n / kTK);
+}
+
+hipError_t batch_ngs_col(const BTable& t, int nblk, hipStream_t s)
+{
+    for (int colour = 0; colour < 2; ++colour)
+        hipLaunchKernelGGL(kc_ngs<P64>, dim3(nblk), dim3(kNT), 0, s, t, colour);
+    return hipGetLastError();
+}
+
+hipError_t batch_ngs32_col(const BTable& t, int nblk, hipStream_t s)
+{
+    for (int colour = 0; colour < 2; ++colour)
+        hipLaunchKernelGGL(kc_ngs<P32>, dim3(nblk), dim3(kNT), 0, s, t, colour);
+    return hipGetLastError();
+}
+
+}  // namespace mgfr

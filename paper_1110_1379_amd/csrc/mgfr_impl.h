@@ -147,6 +147,12 @@ struct PatchParent {
 
 int batch_block();
 hipError_t batch_ngs(const BTable& t, int nblk, hipStream_t s);
+// The same sweep over column tiles (batch_col.hip): blk[b] = (grid, tile), tiles of 16 x 32
+// cells by 16 planes; batch_col_tiles(n) is the number of tiles of a grid of side n, 0 where
+// the side does not allow them (n < 32).  Same results, bit for bit, as batch_ngs / batch_ngs32.
+long long batch_col_tiles(int n);
+hipError_t batch_ngs_col(const BTable& t, int nblk, hipStream_t s);
+hipError_t batch_ngs32_col(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_resid_restrict(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
 hipError_t batch_fas_rhs(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_coarse_diff(const BTable& t, int nblk, hipStream_t s);

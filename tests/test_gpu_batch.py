@@ -285,3 +285,43 @@ def check_profile(mg, ctx, opts, sides, hists):
         assert s["sweep_ms"] > 0.0
     else:
         assert s["sweep_launches"] == 0, s
+
+
+@pytest.mark.parametrize("engine", [e for e in ENGINES if e[0] in ("units16", "phases")], ids=["units16", "phases"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_column_sweep_matches_per_cell_sweep(mg, ctx, precision, engine):
+    """The sweeps of unit levels of side >= 32 walk column tiles (periodic boxes by default,
+    tile = 0; patches too with tile = 2); with tile = 1 they run one thread per cell of the
+    colour.  Both evaluate every cell update with the same operands in the same order, so
+    fields and residual histories agree bit for bit: periodic boxes of sides 32 - 128, and
+    patches of side 32 and 64 (ghost faces) walked with tile = 2."""
+    say(f"[column sweep] {precision} engine={engine[0]}")
+    prec = mg.MGFR_MIXED if precision == "mixed" else mg.MGFR_FP64
+    tol = 1e-8 if precision == "mixed" else 1e-10
+    rng = np.random.default_rng(9)
+    specs = []
+    for b, N in enumerate([32, 128, 64, 16]):
+        specs.append((N, float(N), 10.0 ** rng.uniform(-6, -4), inputs.lognormal(N, rng.uniform(1.0, 2.0), -1.5, seed=40 + b)))
+    rhos = [dev(s[3]) for s in specs]
+    params = [mg.Params(box_mpc_h=s[1], fr0_abs=s[2]) for s in specs]
+    out = []
+    for tile in (0, 1):
+        opts = mg.mgfr_default_opts(tol=tol, precision=prec, flags=engine[1], unit_n=engine[2], tile=tile)
+        us, hists, st = mg.mg_fr_solve_batch(ctx, rhos, params, opts)
+        assert st == mg.MGFR_OK, ctx.last_error()
+        out.append(([u.cpu().numpy() for u in us], [np.asarray(h) for h in hists]))
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)
+    ud, patches, rho_packed, p, _ = patch_case(mg, ctx, 64, (3.0, 10.0), (32, 16, 8, 4), 1e-10)
+    assert {q["n"] for q in patches} >= {32, 64}
+    res = []
+    for tile in (2, 1):
+        opts = mg.mgfr_default_opts(tol=tol, precision=prec, flags=engine[1], unit_n=engine[2], tile=tile)
+        up, hists, st = mg.mg_fr_solve_patches(ctx, ud, patches, dev(rho_packed), p, opts)
+        assert st == mg.MGFR_OK, ctx.last_error()
+        res.append((up.cpu().numpy(), [np.asarray(h) for h in hists]))
+    assert np.array_equal(res[0][0], res[1][0])
+    for a, b in zip(res[0][1], res[1][1]):
+        assert np.array_equal(a, b)
