@@ -53,10 +53,11 @@ struct Launch {
     int nblk = 0, ngrid = 0;
 };
 
-// Red-black sweep of one depth: the grids swept by column tiles (side >= 32) and the rest, one
-// thread per cell of the colour.
+// Red-black sweep of one depth: the grids swept one thread per cell of the colour, those swept
+// by column tiles (side >= 32), and the periodic boxes of a mixed solve swept in fused pairs
+// (column tiles, e32b set).
 struct Sweep {
-    Launch cell, col;
+    Launch cell, col, pair;
 };
 
 struct Depth {
@@ -122,29 +123,38 @@ Launch table(Meta& meta, const std::vector<mgfr::BGrid>& grids, W work, std::vec
 
 long long cells3(const mgfr::BGrid& g) { return 1LL << (3 * g.lg); }
 
-// Sweep tables of the grids f: column tiles for the grids that take them (side >= 32;
-// tile = 0: periodic boxes only, 2: patches too, 1: none), one thread per cell of the colour
-// for the others.
+// Sweep tables of the grids f: fused pairs for the grids with a second correction buffer;
+// column tiles for the others that take them (side >= 32; tile = 0: periodic boxes only, 2:
+// patches too, 1: none); one thread per cell of the colour for the rest.
 Sweep sweep_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, int tile)
 {
-    std::vector<mgfr::BGrid> cell, col;
-    std::vector<int2> blk;
+    std::vector<mgfr::BGrid> cell, col, pair;
+    std::vector<int2> bcol, bpair;
     for (const mgfr::BGrid& g : f) {
+        const long long nt = mgfr::batch_col_tiles(g.n);
+        if (g.e32b && nt > 0) {
+            for (long long b = 0; b < nt; ++b) bpair.push_back(make_int2((int)pair.size(), (int)b));
+            pair.push_back(g);
+            continue;
+        }
         const bool want = tile == 2 || (tile == 0 && g.periodic);
-        const long long nt = want ? mgfr::batch_col_tiles(g.n) : 0;
-        if (nt == 0) {
+        if (!want || nt == 0) {
             cell.push_back(g);
             continue;
         }
-        for (long long b = 0; b < nt; ++b) blk.push_back(make_int2((int)col.size(), (int)b));
+        for (long long b = 0; b < nt; ++b) bcol.push_back(make_int2((int)col.size(), (int)b));
         col.push_back(g);
     }
     Sweep S;
     S.cell = table(meta, cell, [](const mgfr::BGrid& g) { return cells3(g) / 2; });
-    S.col.grids = meta.add(col);
-    S.col.blk = meta.add(blk);
-    S.col.nblk = (int)blk.size();
-    S.col.ngrid = (int)col.size();
+    auto tiles = [&](Launch& L, const std::vector<mgfr::BGrid>& gs, const std::vector<int2>& blk) {
+        L.grids = meta.add(gs);
+        L.blk = meta.add(blk);
+        L.nblk = (int)blk.size();
+        L.ngrid = (int)gs.size();
+    };
+    tiles(S.col, col, bcol);
+    tiles(S.pair, pair, bpair);
     return S;
 }
 
@@ -207,6 +217,14 @@ struct Batch {
     }
     const mgfr::BGrid* grids(const Launch& L) const { return (const mgfr::BGrid*)(dmeta + L.grids); }
 
+    // A level of side n of unit U swept in fused pairs: a periodic box of a mixed solve, side
+    // >= 32, swept by launches (not inside a one-workgroup solve), column tiles allowed.
+    bool pair_level(const Unit& U, int n) const
+    {
+        return o->precision == MGFR_MIXED && U.periodic && o->tile != 1 && mgfr::batch_col_tiles(n) > 0 &&
+               (phases || n > W);
+    }
+
     // Allocates each unit's coarse levels (and patch boundary faces), fills the descriptors
     // and uploads the plan.
     int prepare()
@@ -226,8 +244,8 @@ struct Batch {
         double* pool = nullptr;
         MGFR_TRY(alloc(&pool, need));
         size_t at = 0;
-        // mixed precision: single-precision base, correction, right-hand side (every level)
-        // and coarse difference (coarse levels)
+        // mixed precision: single-precision base, correction, right-hand side (every level),
+        // coarse difference (coarse levels) and the second correction buffer of fused pairs
         const bool mixed = o->precision == MGFR_MIXED;
         float* pool32 = nullptr;
         size_t at32 = 0;
@@ -236,7 +254,7 @@ struct Batch {
             for (Unit& U : units)
                 for (int m = 0; m < U.nlev; ++m) {
                     const size_t n = (size_t)(U.n >> m);
-                    need32 += (m > 0 ? 4 : 3) * n * n * n;
+                    need32 += (m > 0 ? 4 : 3) * n * n * n + (pair_level(U, (int)n) ? n * n * n : 0);
                 }
             MGFR_TRY(alloc(&pool32, need32));
         }
@@ -284,6 +302,10 @@ struct Batch {
                     at32 += 3 * n3;
                     if (m > 0) {
                         G.eh32 = pool32 + at32;
+                        at32 += n3;
+                    }
+                    if (pair_level(U, n)) {
+                        G.e32b = pool32 + at32;
                         at32 += n3;
                     }
                 }
@@ -494,13 +516,13 @@ struct Batch {
         }
         return hip_check(c, hipEventRecord(c->ev[c->ev_used], s), "hipEventRecord");
     }
-    int ev_end(int m, double bytes_per_cell)
+    int ev_end(int m, double bytes_per_cell, int count, int launches)
     {
         if (!profiled(m)) return MGFR_OK;
         MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
         c->ev_used += 2;
-        c->stats.sweep_launches += 2;  // one launch per colour
-        c->stats.sweep_bytes += bytes_per_cell * (double)act0;
+        c->stats.sweep_launches += launches;
+        c->stats.sweep_bytes += bytes_per_cell * (double)act0 * count;
         return MGFR_OK;
     }
     // Sums the timed intervals (the stream has been synchronised) and releases the events.
@@ -515,31 +537,51 @@ struct Batch {
         return MGFR_OK;
     }
 
-    // One red-black sweep of a depth's grids (grids are independent: the two tables in turn).
-    int ngs(const Sweep& S, bool mixed)
+    // `count` red-black sweeps of a depth's grids (grids are independent: the tables in turn);
+    // the number of kernel launches in *launches.
+    int ngs(const Sweep& S, bool mixed, int count, int* launches)
     {
-        if (S.cell.nblk > 0) {
-            if (mixed)
-                MGFR_TRY(hip_check(c, mgfr::batch_ngs32(tab(S.cell), S.cell.nblk, s), "batch_ngs32"));
-            else
-                MGFR_TRY(hip_check(c, mgfr::batch_ngs(tab(S.cell), S.cell.nblk, s), "batch_ngs"));
+        int nl = 0;
+        for (int k = 0; k < count; ++k) {
+            if (S.cell.nblk > 0) {
+                if (mixed)
+                    MGFR_TRY(hip_check(c, mgfr::batch_ngs32(tab(S.cell), S.cell.nblk, s), "batch_ngs32"));
+                else
+                    MGFR_TRY(hip_check(c, mgfr::batch_ngs(tab(S.cell), S.cell.nblk, s), "batch_ngs"));
+                nl += 2;
+            }
+            if (S.col.nblk > 0) {
+                if (mixed)
+                    MGFR_TRY(hip_check(c, mgfr::batch_ngs32_col(tab(S.col), S.col.nblk, s), "batch_ngs32_col"));
+                else
+                    MGFR_TRY(hip_check(c, mgfr::batch_ngs_col(tab(S.col), S.col.nblk, s), "batch_ngs_col"));
+                nl += 2;
+            }
         }
-        if (S.col.nblk > 0) {
-            if (mixed)
-                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_col(tab(S.col), S.col.nblk, s), "batch_ngs32_col"));
-            else
-                MGFR_TRY(hip_check(c, mgfr::batch_ngs_col(tab(S.col), S.col.nblk, s), "batch_ngs_col"));
+        if (S.pair.nblk > 0) {
+            // pairs of fused sweeps end where they began (e32); an odd one out runs in place
+            for (int k = 0; k + 2 <= count; k += 2) {
+                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_pair(tab(S.pair), S.pair.nblk, s), "batch_ngs32_pair"));
+                nl += 2;
+            }
+            if (count & 1) {
+                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_col(tab(S.pair), S.pair.nblk, s), "batch_ngs32_col"));
+                nl += 2;
+            }
         }
+        if (launches) *launches = nl;
         return MGFR_OK;
     }
 
     // read u and rho, write u
-    int sweep(int m)
+    int sweep(int m, int count)
     {
+        if (count == 0) return MGFR_OK;
         const Depth& D = plan.depth[m];
+        int nl = 0;
         MGFR_TRY(ev_begin(m));
-        MGFR_TRY(ngs(D.half, false));
-        return ev_end(m, 24.0);
+        MGFR_TRY(ngs(D.half, false, count, &nl));
+        return ev_end(m, 24.0, count, nl);
     }
 
     int vcycle(int m)
@@ -550,7 +592,7 @@ struct Batch {
                                                        o->coarsest_rtol, s),
                                "batch_coarsest"));
         if (!D.deep) return MGFR_OK;
-        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep(m));
+        MGFR_TRY(sweep(m, o->pre));
         MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict(tab(D.coarse_f), D.coarse_f.nblk,
                                                          (const mgfr::BGrid*)(dmeta + D.coarse_f.other), s),
                            "batch_resid_restrict"));
@@ -560,19 +602,21 @@ struct Batch {
         MGFR_TRY(hip_check(c, mgfr::batch_prolong_add(tab(D.fine_f), D.fine_f.nblk,
                                                       (const mgfr::BGrid*)(dmeta + D.fine_f.other), s),
                            "batch_prolong_add"));
-        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep(m));
+        MGFR_TRY(sweep(m, o->post));
         return MGFR_OK;
     }
 
     // ---- mixed precision: single-precision correction V-cycle, double-precision outer loop
     // credited 12 B per cell: e and the right-hand side read, e written (the fixed base ub,
     // also read, is not counted)
-    int sweep32(int m)
+    int sweep32(int m, int count)
     {
+        if (count == 0) return MGFR_OK;
         const Depth& D = plan.depth[m];
+        int nl = 0;
         MGFR_TRY(ev_begin(m));
-        MGFR_TRY(ngs(D.half, true));
-        return ev_end(m, 12.0);
+        MGFR_TRY(ngs(D.half, true, count, &nl));
+        return ev_end(m, 12.0, count, nl);
     }
 
     int vcycle32(int m)
@@ -584,7 +628,7 @@ struct Batch {
                                "batch_coarsest32"));
         if (!D.deep) return MGFR_OK;
         const mgfr::BGrid* coarse = (const mgfr::BGrid*)(dmeta + D.coarse_f.other);
-        for (int k = 0; k < o->pre; ++k) MGFR_TRY(sweep32(m));
+        MGFR_TRY(sweep32(m, o->pre));
         MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict32(tab(D.coarse_f), D.coarse_f.nblk, coarse, s),
                            "batch_resid_restrict32"));
         MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs32(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs32"));
@@ -593,7 +637,7 @@ struct Batch {
         MGFR_TRY(hip_check(c, mgfr::batch_prolong_add32(tab(D.fine_f), D.fine_f.nblk,
                                                         (const mgfr::BGrid*)(dmeta + D.fine_f.other), s),
                            "batch_prolong_add32"));
-        for (int k = 0; k < o->post; ++k) MGFR_TRY(sweep32(m));
+        MGFR_TRY(sweep32(m, o->post));
         return MGFR_OK;
     }
 
@@ -811,7 +855,7 @@ struct Batch {
     {
         const UDepth& D = up.depth[m];
         const mgfr::BGrid* coarse = (const mgfr::BGrid*)(dmeta + D.coarse_f.other);
-        for (int k = 0; k < o->pre; ++k) MGFR_TRY(usweep(m, mixed));
+        MGFR_TRY(usweep(m, mixed, o->pre));
         if (mixed) {
             MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict32(utab(D.coarse_f), D.coarse_f.nblk, coarse, s),
                                "batch_resid_restrict32"));
@@ -836,20 +880,22 @@ struct Batch {
             MGFR_TRY(hip_check(c, mgfr::batch_prolong_add(utab(D.fine_f), D.fine_f.nblk, coarse, s),
                                "batch_prolong_add"));
         }
-        for (int k = 0; k < o->post; ++k) MGFR_TRY(usweep(m, mixed));
+        MGFR_TRY(usweep(m, mixed, o->post));
         return MGFR_OK;
     }
 
-    int usweep(int m, bool mixed)
+    int usweep(int m, bool mixed, int count)
     {
+        if (count == 0) return MGFR_OK;
         const UDepth& D = up.depth[m];
         const bool timed = m == 0 && (o->flags & MGFR_PROFILE) && !(o->flags & MGFR_GRAPH);
         if (timed) MGFR_TRY(ev_begin(0));
-        MGFR_TRY(ngs(D.half, mixed));
+        int nl = 0;
+        MGFR_TRY(ngs(D.half, mixed, count, &nl));
         if (timed) {
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
             c->ev_used += 2;
-            c->stats.sweep_launches += 2;
+            c->stats.sweep_launches += nl;
         }
         return MGFR_OK;
     }

@@ -13,6 +13,7 @@
 // Each thread updates one cell of the colour per plane, in place: within one colour launch a
 // cell's neighbours are all of the other colour and are not written.
 #include "batch_dev.h"
+#include "fused_fp32.h"
 
 namespace mgfr {
 namespace {
@@ -299,6 +300,31 @@ __global__ void __launch_bounds__(kNT) kc_ngs(BTable t, int colour)
         walk<P, false>(g, blk.y, colour, lv);
 }
 
+// ---- both colours in one pass (single precision, periodic boxes) ---------------------------
+// The tile sweep of the domain solve over the same 16 x 32 x 16 tiles, out of place: a tile's
+// halo is read from the old values while neighbouring tiles write theirs, so each sweep reads
+// one buffer of e and writes the other (dir 0: e32 to e32b, dir 1: back).  Consecutive table
+// entries go to the same XCD (workgroups are dealt to the 8 XCDs in turn).
+__global__ void __launch_bounds__(kNT) kf32_ngs(BTable t, int dir)
+{
+    __shared__ V32 lv[3][(kTJ + 4) * (kTK + 4)];
+    const int nb = gridDim.x;
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int2 blk = t.blk[b];
+    const BGrid g = t.grids[blk.x];
+    if (!live(t, g)) return;
+    const int ntk = g.n / kTK, ntj = g.n / kTJ;
+    int tile = blk.y;
+    const int k0 = (tile % ntk) * kTK;
+    tile /= ntk;
+    const int j0 = (tile % ntj) * kTJ;
+    const int i0 = (tile / ntj) * kTI;
+    const float* ein = dir ? g.e32b : g.e32;
+    float* eout = dir ? g.e32 : g.e32b;
+    fused32::sweep_tile<kTJ, kTK>(op32(g), g.n, g.lg, i0, j0, k0, kTI, g.ub32, ein, eout, g.f32, lv);
+}
+
 }  // namespace
 
 long long batch_col_tiles(int n)
@@ -318,6 +344,12 @@ hipError_t batch_ngs32_col(const BTable& t, int nblk, hipStream_t s)
 {
     for (int colour = 0; colour < 2; ++colour)
         hipLaunchKernelGGL(kc_ngs<P32>, dim3(nblk), dim3(kNT), 0, s, t, colour);
+    return hipGetLastError();
+}
+
+hipError_t batch_ngs32_pair(const BTable& t, int nblk, hipStream_t s)
+{
+    for (int dir = 0; dir < 2; ++dir) hipLaunchKernelGGL(kf32_ngs, dim3(nblk), dim3(kNT), 0, s, t, dir);
     return hipGetLastError();
 }
 

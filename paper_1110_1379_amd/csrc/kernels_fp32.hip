@@ -6,6 +6,7 @@
 // The coarse levels of this inner multigrid use the restricted base R ub.  Smoother:
 // red-black Newton-Gauss-Seidel on N (Sec. V.B.1 applied to the correction equation).
 #include "device_fp32.h"
+#include "fused_fp32.h"
 
 #include <type_traits>
 
@@ -69,13 +70,7 @@ __global__ void __launch_bounds__(kBlock) k32_ngs_colour(Grid g, const float* __
 // owns a pair of k-adjacent columns: at every plane step exactly one column of each pair
 // holds the cells to update (red on plane p, black on plane p-1), and the two swap at the
 // next step, so with the step loop unrolled by two every lane updates a cell at every step.
-struct Col32 {
-    V32 v[4];                 // plane q in v[(q - i0 + 3) & 3]: planes p-2 .. p+1 at step p
-    float f[4];               // right-hand side, same slots (planes p-1 .. p+1 used)
-    float rub[2], re[2], rf[2];  // raw loads of planes p+2 and p+3, plane q in [(q - i0) & 1]
-    unsigned col;             // (j,k) offset within a plane
-    int c, fl;                // LDS cell; 1 loaded, 2 red range (tile + ring), 4 tile
-};
+using fused32::Col32;
 
 template <int TJ, int TK, int NT>
 __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict__ ub, const float* __restrict__ ein,
@@ -208,28 +203,14 @@ __global__ void __launch_bounds__(NT) k32_fused(Grid g, const float* __restrict_
 }
 
 // ---- fused red-black sweep, one tile column pair per thread -------------------------------
-// The same plane-streaming scheme, with the work laid out so that lanes hold only cells that
-// need updating.  Thread t owns the pair of k-adjacent tile columns t (TJ x TK tile, TJ TK / 2
-// threads): at every step it updates one red cell on plane p and one black cell on plane p-1,
-// every one of them part of the result.  The ring of red cells around the tile (recomputed
-// from the same old values by every tile that sees them, as before) and the outer halo (only
-// read) are extra columns E of the first threads: thread t < NR holds ring cell t, which it
-// updates on the planes where that cell is red; the next NH threads hold one halo cell each,
-// which they only stage.  Every updated cell's (B, M) are formed again from (ub, e) as the
-// per-colour kernel forms them, so both sweeps give the same bits.
+// The tile sweep itself is in fused_fp32.h (shared with the batched solves).
 template <int TJ, int TK>
 __global__ void __launch_bounds__(TJ * TK / 2) k32_fused2(Grid g, const float* __restrict__ ub,
                                                          const float* __restrict__ ein, float* __restrict__ eout,
                                                          const float* __restrict__ f, FusedSweep32 a)
 {
     if (g.halt && *g.halt) return;
-    constexpr int NT = TJ * TK / 2;
-    constexpr int LJ = TJ + 4, LK = TK + 4, NL = LJ * LK;
-    constexpr int NR = 2 * (TK + 2) + 2 * TJ;        // ring around the tile
-    constexpr int NH = 2 * (TK + 4) + 2 * (TJ + 2);  // outer halo
-    static_assert(NR + NH <= NT, "one extra column per thread");
-    __shared__ V32 lv[3][NL];
-    const Op32 o = op32(g);
+    __shared__ V32 lv[3][(TJ + 4) * (TK + 4)];
     const int nb = gridDim.x;
     int lid = blockIdx.x;
     if ((nb & 7) == 0) lid = (lid & 7) * (nb >> 3) + (lid >> 3);
@@ -237,135 +218,7 @@ __global__ void __launch_bounds__(TJ * TK / 2) k32_fused2(Grid g, const float* _
     lid /= a.ntk;
     const int tj = lid % a.ntj;
     const int ci = lid / a.ntj;
-    const int i0 = ci * a.ti, j0 = tj * TJ, k0 = tk * TK;
-    const int lg = g.lg, m = g.n - 1;
-    const int last = i0 + a.ti + 1;  // last plane read
-    const int t = threadIdx.x;
-
-    // X: the tile column of the pair whose cell on plane i0-1 is red; Y: the other one
-    Col32 X{}, Y{}, E{};
-    {
-        const int jj = t / (TK / 2), kk0 = 2 * (t - jj * (TK / 2));
-        const int gj = (j0 + jj) & m, gk0 = (k0 + kk0) & m;
-        const int sx = (i0 - 1 + gj + gk0) & 1;
-        auto setup = [&](Col32& q, int d) {
-            q.col = (unsigned)((gj << lg) | (gk0 + d));
-            q.c = (jj + 2) * LK + kk0 + 2 + d;
-            q.fl = 7;
-        };
-        setup(X, sx);
-        setup(Y, 1 - sx);
-    }
-    // E: ring cell t or halo cell t - NR, walked around its rectangle (rows first, then the
-    // two side columns)
-    int epar = 0;  // parity of (j + k) of E's column
-    if (t < NR + NH) {
-        const bool ring = t < NR;
-        const int r = ring ? t : t - NR;
-        const int ra = ring ? TJ + 2 : TJ + 4, rb = ring ? TK + 2 : TK + 4, off = ring ? 1 : 0;
-        int ej, ek;
-        if (r < rb) { ej = 0; ek = r; }
-        else if (r < 2 * rb) { ej = ra - 1; ek = r - rb; }
-        else if (r < 2 * rb + ra - 2) { ej = 1 + (r - 2 * rb); ek = 0; }
-        else { ej = 1 + (r - 2 * rb - (ra - 2)); ek = rb - 1; }
-        ej += off;
-        ek += off;
-        const int gj = (j0 - 2 + ej) & m, gk = (k0 - 2 + ek) & m;
-        E.col = (unsigned)((gj << lg) | gk);
-        E.c = ej * LK + ek;
-        E.fl = ring ? 3 : 1;
-        epar = (gj + gk) & 1;
-    }
-    // element offsets fit in 32 bits (n <= 1024)
-    auto offset = [&](int p, const Col32& q) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + q.col; };
-    auto buf = [&](int p) { return (p - i0 + 3) % 3; };
-    auto prologue = [&](Col32& q) {
-        if (!q.fl) return;
-        // planes i0-2, i0-1, i0 in slots 1, 2, 3; plane i0+1 raw in slot 1
-        q.v[1] = make_v(ub[offset(i0 - 2, q)], ein[offset(i0 - 2, q)]);
-        q.v[2] = make_v(ub[offset(i0 - 1, q)], ein[offset(i0 - 1, q)]);
-        q.v[3] = make_v(ub[offset(i0, q)], ein[offset(i0, q)]);
-        q.rub[1] = ub[offset(i0 + 1, q)];
-        q.re[1] = ein[offset(i0 + 1, q)];
-        if (q.fl & 2) {
-            q.f[1] = f[offset(i0 - 2, q)];
-            q.f[2] = f[offset(i0 - 1, q)];
-            q.f[3] = f[offset(i0, q)];
-            q.rf[1] = f[offset(i0 + 1, q)];
-        }
-        lv[buf(i0 - 1)][q.c] = q.v[2];
-    };
-    prologue(X);
-    prologue(Y);
-    prologue(E);
-    __syncthreads();
-
-    // One plane step, R = (p - i0 + 1) mod 4 fixed at compile time so that the register planes
-    // rotate by renaming.  A holds the red cell of plane p and the black cell of plane p-1.
-    auto step = [&](auto Rc, int p, Col32& A, Col32& B) {
-        constexpr int R = decltype(Rc)::value;
-        constexpr int M2 = R, M1 = (R + 1) & 3, P0 = (R + 2) & 3, P1 = (R + 3) & 3;
-        constexpr int N2 = (R + 1) & 1, N3 = R & 1;  // raw slots of planes p+2, p+3
-        auto fetch = [&](Col32& q) {
-            if (!q.fl) return;
-            q.rub[N3] = ub[offset(p + 3, q)];
-            q.re[N3] = ein[offset(p + 3, q)];
-            if (q.fl & 2) q.rf[N3] = f[offset(p + 3, q)];
-        };
-        if (p + 3 <= last) {
-            fetch(A);
-            fetch(B);
-            fetch(E);
-        }
-        V32* LA = lv[buf(p)];
-        auto red = [&](Col32& q) {
-            const int c = q.c;
-            const V32 nbv[6] = {q.v[M1], q.v[P1], LA[c - LK], LA[c + LK], LA[c - 1], LA[c + 1]};
-            const Res32 r = dev32::corr_op(o, q.v[P0], nbv, q.f[P0]);
-            q.v[P0] = make_v(q.v[P0].ub, q.v[P0].e + newton32(r, o.max_step));
-            LA[c] = q.v[P0];
-        };
-        red(A);
-        if ((E.fl & 2) && ((p + epar) & 1) == 0) red(E);
-        if (p - 1 >= i0) {
-            const V32* LB = lv[buf(p - 1)];
-            const int c = A.c;
-            const V32 nbv[6] = {A.v[M2], A.v[P0], LB[c - LK], LB[c + LK], LB[c - 1], LB[c + 1]};
-            const Res32 r = dev32::corr_op(o, A.v[M1], nbv, A.f[M1]);
-            A.v[M1].e = A.v[M1].e + newton32(r, o.max_step);
-            eout[offset(p - 1, A)] = A.v[M1].e;
-            eout[offset(p - 1, B)] = B.v[M1].e;
-        }
-        V32* LC = lv[buf(p + 1)];
-        const bool more2 = p + 2 <= last;
-        auto advance = [&](Col32& q) {
-            if (!q.fl) return;
-            LC[q.c] = q.v[P1];
-            if (more2) {  // plane p+2 takes the slot of plane p-2
-                q.v[M2] = make_v(q.rub[N2], q.re[N2]);
-                q.f[M2] = q.rf[N2];
-            }
-        };
-        advance(A);
-        advance(B);
-        advance(E);
-        __syncthreads();
-    };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    using I3 = std::integral_constant<int, 3>;
-    // a.ti + 2 steps (a.ti a multiple of 4): two, then groups of four so that the register
-    // planes and the column roles are back in place at the end of every iteration.  X holds
-    // the red cells of planes i0-1, i0+1, ...
-    step(I0{}, i0 - 1, X, Y);
-    step(I1{}, i0, Y, X);
-    for (int p = i0 + 1; p <= i0 + a.ti; p += 4) {
-        step(I2{}, p, X, Y);
-        step(I3{}, p + 1, Y, X);
-        step(I0{}, p + 2, X, Y);
-        step(I1{}, p + 3, Y, X);
-    }
+    fused32::sweep_tile<TJ, TK>(op32(g), g.n, g.lg, ci * a.ti, tj * TJ, tk * TK, a.ti, ub, ein, eout, f, lv);
 }
 
 // ---- streaming residual + restriction (n >= 64) ----------------------------------------
