@@ -38,13 +38,14 @@ METRIC = "f(R) MG time-to-residual 1e-8 & cell-updates/s, 512^3, FP64 vs mixed"
 # by-value kernel types): when any of them differs the figure no longer describes the kernel
 # that runs and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    # per finest launch (one red-black sweep of the correction, 16 x 64 tiles, 32 planes)
-    "mixed": {"bytes": 3.0591e9, "sources": {
-        "kernels_fp32.hip": "b3baae8fa2c777348557489cc62ee26d086124d17ada2392195053d4ff690cd4",
+    # per finest launch (one red-black sweep of the correction, 16 x 64 tiles, 64 planes)
+    "mixed": {"bytes": 3.5543e9, "settings": {"planes": 64, "tile": 3}, "sources": {
+        "kernels_fp32.hip": "3e2d5fa7b74c8e9e8695fb1c7fd7f008127e8b020b552ac5893de6581d7cd948",
+        "fused_fp32.h": "3b8a1dfc12b810a10f8d0335158966d434455a2017154154b7ee148726d3b98f",
         "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
         "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
     # per finest launch (one red-black sweep, 16 x 64 tiles, 128 planes per workgroup)
-    "fp64": {"bytes": 3.4275e9, "sources": {
+    "fp64": {"bytes": 3.4275e9, "settings": {"planes": 128, "tile": 1}, "sources": {
         "sweep_fp64.hip": "52fc69d7da60d3ca2f99db208d943e175ded4ad6bf8ace4cd379e03154f184c8",
         "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
         "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
@@ -60,12 +61,25 @@ MEASURED_TRAFFIC = {
 }
 
 
-def measured_traffic(prec, N):
-    """Bytes per finest launch if the counters describe the kernel built from these sources."""
+def _tile_shape(prec, tile):
+    """Tile shape a finest-level sweep setting selects (0 is the automatic choice)."""
+    if prec == "fp64":
+        return "8x64" if tile == 2 else "16x64"
+    return {2: "32x32", 3: "16x64", 4: "8x32", 5: "32x64"}.get(tile, "16x32")
+
+
+def measured_traffic(prec, N, settings=None):
+    """Bytes per finest launch if the counters describe the kernel built from these sources,
+    at the planes and tile of the timed settings (when the figure was taken at given ones)."""
     import hashlib
     entry = MEASURED_TRAFFIC.get(prec)
     if entry is None or N != 512:
         return None
+    want = entry.get("settings")
+    if want is not None and settings is not None:
+        if settings.get("planes") != want["planes"] or \
+                _tile_shape(prec, settings.get("tile", 0)) != _tile_shape(prec, want["tile"]):
+            return None
     csrc = os.path.join(ROOT, "paper_1110_1379_amd", "csrc")
     for name, digest in entry["sources"].items():
         with open(os.path.join(csrc, name), "rb") as fh:
@@ -349,7 +363,7 @@ def bench_domain(args):
         "roofline": {
             "bound": "hbm", "achieved": sm["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (sm["achieved_GBs"] / HBM_PEAK_GBS) if sm["achieved_GBs"] else None,
-            "traffic": measured_traffic(headp, N),
+            "traffic": measured_traffic(headp, N, head["settings"]),
             "kernel": (f"single-precision correction smoother {_k32_name(head['settings'])}" if headp == "mixed"
                        else "double-precision smoother k_ngs_fused") + " (finest level)",
             "bytes_per_cell": sm["bytes_per_cell_sweep"], "launches": sm["launches"],
@@ -365,7 +379,7 @@ def bench_domain(args):
         out["roofline"]["achieved_with_base"] = sm["achieved_GBs"] * 16.0 / 12.0
         out["roofline"]["frac_with_base"] = sm["achieved_GBs"] * 16.0 / 12.0 / HBM_PEAK_GBS
     for p, r in runs.items():
-        r["smoother"]["traffic"] = measured_traffic(p, N)
+        r["smoother"]["traffic"] = measured_traffic(p, N, r["settings"])
         out[p] = r
     if "fp64" in runs and "mixed" in runs:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
