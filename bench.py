@@ -38,14 +38,18 @@ METRIC = "f(R) MG time-to-residual 1e-8 & cell-updates/s, 512^3, FP64 vs mixed"
 # by-value kernel types): when any of them differs the figure no longer describes the kernel
 # that runs and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    # per finest launch (one red-black sweep of the correction, 16 x 64 tiles, 64 planes)
-    "mixed": {"bytes": 3.5543e9, "settings": {"planes": 64, "tile": 3}, "sources": {
-        "kernels_fp32.hip": "3e2d5fa7b74c8e9e8695fb1c7fd7f008127e8b020b552ac5893de6581d7cd948",
-        "fused_fp32.h": "3b8a1dfc12b810a10f8d0335158966d434455a2017154154b7ee148726d3b98f",
-        "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
-        "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
+    # per finest launch (one red-black sweep of the correction, 16 x 64 tiles), at 64 and 32
+    # planes per workgroup
+    "mixed": {"points": [({"planes": 64, "tile": 3}, 3.5597e9), ({"planes": 32, "tile": 3}, 3.0682e9)],
+              "sources": {
+                  "kernels_fp32.hip": "3e2d5fa7b74c8e9e8695fb1c7fd7f008127e8b020b552ac5893de6581d7cd948",
+                  "fused_fp32.h": "15a7b8dd99f9658da4ca4829a5ccfca8cbde9a8d2f80880b54dee5b2ccee4554",
+                  "batch_dev.h": "e5f458582bef25e31797cfb18129042fdc32f6ea8e68172805ca135c071d10fb",
+                  "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
+                  "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
+                  "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
     # per finest launch (one red-black sweep, 16 x 64 tiles, 128 planes per workgroup)
-    "fp64": {"bytes": 3.4275e9, "settings": {"planes": 128, "tile": 1}, "sources": {
+    "fp64": {"points": [({"planes": 128, "tile": 1}, 3.4275e9)], "sources": {
         "sweep_fp64.hip": "52fc69d7da60d3ca2f99db208d943e175ded4ad6bf8ace4cd379e03154f184c8",
         "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
         "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
@@ -69,23 +73,28 @@ def _tile_shape(prec, tile):
 
 
 def measured_traffic(prec, N, settings=None):
-    """Bytes per finest launch if the counters describe the kernel built from these sources,
-    at the planes and tile of the timed settings (when the figure was taken at given ones)."""
+    """Bytes per finest launch if the counters describe the kernel built from these sources;
+    a sweep counted at given planes and tile: at those of the timed settings (without
+    settings, the first point counted)."""
     import hashlib
     entry = MEASURED_TRAFFIC.get(prec)
     if entry is None or N != 512:
         return None
-    want = entry.get("settings")
-    if want is not None and settings is not None:
-        if settings.get("planes") != want["planes"] or \
-                _tile_shape(prec, settings.get("tile", 0)) != _tile_shape(prec, want["tile"]):
-            return None
     csrc = os.path.join(ROOT, "paper_1110_1379_amd", "csrc")
     for name, digest in entry["sources"].items():
         with open(os.path.join(csrc, name), "rb") as fh:
             if hashlib.sha256(fh.read()).hexdigest() != digest:
                 return None
-    return entry["bytes"]
+    if "points" not in entry:
+        return entry["bytes"]
+    if settings is None:
+        return entry["points"][0][1]
+    for want, nbytes in entry["points"]:
+        if settings.get("planes") == want["planes"] and \
+                _tile_shape(prec, settings.get("tile", 0)) == _tile_shape(prec, want["tile"]):
+            return nbytes
+    return None
+
 
 WORKLOADS = {
     # name: (N, box Mpc/h, |f_R0|, generator, oracle sample (N, structures))
@@ -674,10 +683,12 @@ def _batched_roofline(s, prec_name, unit_n=0, phases=False):
     fp64 = prec_name == "fp64"
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
-            "kernel": ("kc_ngs<P64> / kb_ngs" if fp64 else "kc_ngs<P32> / kb32_ngs") +
-                      " (red-black Newton-Gauss-Seidel, one launch per colour over the finest level of every unit" +
-                      ("" if phases else f" larger than {unit_n or 16}^3") +
-                      "; column tiles for periodic boxes of side >= 32, one thread per cell for patches)",
+            "kernel": ("kc_ngs<P64> / kb_ngs (red-black Newton-Gauss-Seidel, one launch per colour: column tiles "
+                       "for periodic boxes, one thread per cell for patches)" if fp64 else
+                       "kf32_ngs / kb32_ngs (red-black Newton-Gauss-Seidel: periodic boxes both colours in one "
+                       "pass over column tiles, two launches per pair of sweeps; patches one launch per colour, "
+                       "one thread per cell)") +
+                      " over the finest level of every unit" + ("" if phases else f" larger than {unit_n or 16}^3"),
             "bytes_per_cell": 24 if fp64 else 12, "launches": launches,
             "avg_launch_ms": s["sweep_ms"] / launches if launches else None,
             "timing": "one more solve of the same problem after the timed steps, launched eagerly (no graph) "
@@ -885,10 +896,11 @@ def main():
     ap.add_argument("--engine", default="both", choices=["units", "phases", "both"],
                     help="amr/batch: the workgroup-per-unit engine (the line's value), the per-phase engine "
                          "(baseline), or both")
-    ap.add_argument("--batch-sweep", default="auto", choices=["auto", "cell", "column"],
-                    help="amr/batch: sweeps of unit levels of side >= 32 over column tiles for periodic boxes "
-                         "and one thread per cell of the colour for patches (auto, the default), one thread per "
-                         "cell everywhere (cell), or column tiles everywhere (column)")
+    ap.add_argument("--batch-sweep", default="auto", choices=["auto", "cell", "column", "pairs"],
+                    help="amr/batch: sweeps of unit levels of side >= 32: automatic (periodic boxes over column "
+                         "tiles, mixed in fused two-colour pairs; patches one thread per cell), one thread per "
+                         "cell of the colour everywhere (cell), column tiles one colour per launch everywhere "
+                         "(column), or as automatic with patches in fused pairs too (pairs)")
     ap.add_argument("--unit-n", type=int, default=0,
                     help="amr/batch: units and levels of side <= this run in one workgroup (0: the library's 16)")
     ap.add_argument("--no-graph-ab", action="store_true",
@@ -898,7 +910,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy three times (calibrates HBM counters)")
     args = ap.parse_args()
-    args.batch_sweep_tile = {"auto": 0, "cell": 1, "column": 2}[args.batch_sweep]
+    args.batch_sweep_tile = {"auto": 0, "cell": 1, "column": 2, "pairs": 3}[args.batch_sweep]
     if args.copy_probe:
         import torch
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")

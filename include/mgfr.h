@@ -104,11 +104,14 @@ typedef struct mgfr_opts {
                              32, 3 = 16 x 64, 5 = 32 x 64 (one tile column pair per thread),
                              4 = 8 x 32 (column pairs over the tile and its halo).
                              Batched solves, launched sweeps of unit levels of side >=
-                             32: 0 = periodic boxes walk 16 x 32 column tiles through 16
-                             planes per workgroup, patches one thread per cell of the
-                             colour; 1 = one thread per cell everywhere; 2 = column
-                             tiles for patches too; 3 - 5 as 0 (same results, bit for
-                             bit)                                                 [0]      */
+                             32: 0 = automatic: periodic boxes walk 16 x 32 column tiles
+                             (16 planes per workgroup), a mixed solve in pairs of fused
+                             two-colour sweeps, double precision one colour per launch;
+                             patches run one thread per cell of the colour; 1 = one
+                             thread per cell everywhere; 2 = column tiles one colour per
+                             launch everywhere; 3 = as 0, and mixed solves sweep patches
+                             in fused pairs too (8 planes per workgroup); 4, 5 as 0 (all
+                             give the same results, bit for bit)                  [0]      */
 } mgfr_opts;
 
 /* One refinement patch: a cube of n^3 cells at refinement level `level` >= 1 (cell size

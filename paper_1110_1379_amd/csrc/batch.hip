@@ -57,7 +57,7 @@ struct Launch {
 // by column tiles (side >= 32), and the periodic boxes of a mixed solve swept in fused pairs
 // (column tiles, e32b set).
 struct Sweep {
-    Launch cell, col, pair;
+    Launch cell, col, pair, pair1;  // pair1: the fused pairs' grids as column tiles (an odd sweep)
 };
 
 struct Depth {
@@ -124,20 +124,21 @@ Launch table(Meta& meta, const std::vector<mgfr::BGrid>& grids, W work, std::vec
 long long cells3(const mgfr::BGrid& g) { return 1LL << (3 * g.lg); }
 
 // Sweep tables of the grids f: fused pairs for the grids with a second correction buffer;
-// column tiles for the others that take them (side >= 32; tile = 0: periodic boxes only, 2:
-// patches too, 1: none); one thread per cell of the colour for the rest.
+// column tiles for the others that take them (side >= 32; tile = 2: all, 1: none, otherwise
+// periodic boxes); one thread per cell of the colour for the rest.
 Sweep sweep_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, int tile)
 {
     std::vector<mgfr::BGrid> cell, col, pair;
-    std::vector<int2> bcol, bpair;
+    std::vector<int2> bcol, bpair, bpair1;
     for (const mgfr::BGrid& g : f) {
-        const long long nt = mgfr::batch_col_tiles(g.n);
-        if (g.e32b && nt > 0) {
-            for (long long b = 0; b < nt; ++b) bpair.push_back(make_int2((int)pair.size(), (int)b));
+        const long long nt = mgfr::batch_col_tiles(g.n), np = mgfr::batch_pair_tiles(g.n, g.periodic);
+        if (g.e32b && nt > 0 && np > 0) {
+            for (long long b = 0; b < np; ++b) bpair.push_back(make_int2((int)pair.size(), (int)b));
+            for (long long b = 0; b < nt; ++b) bpair1.push_back(make_int2((int)pair.size(), (int)b));
             pair.push_back(g);
             continue;
         }
-        const bool want = tile == 2 || (tile == 0 && g.periodic);
+        const bool want = tile == 2 || (tile != 1 && g.periodic);
         if (!want || nt == 0) {
             cell.push_back(g);
             continue;
@@ -155,6 +156,7 @@ Sweep sweep_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, int tile)
     };
     tiles(S.col, col, bcol);
     tiles(S.pair, pair, bpair);
+    tiles(S.pair1, pair, bpair1);
     return S;
 }
 
@@ -217,12 +219,15 @@ struct Batch {
     }
     const mgfr::BGrid* grids(const Launch& L) const { return (const mgfr::BGrid*)(dmeta + L.grids); }
 
-    // A level of side n of unit U swept in fused pairs: a periodic box of a mixed solve, side
-    // >= 32, swept by launches (not inside a one-workgroup solve), column tiles allowed.
+    // A level of side n swept in fused pairs: a level of a mixed solve, side >= 32, swept by
+    // launches (not inside a one-workgroup solve); periodic boxes by default (tile 0, 4, 5),
+    // patches too with tile 3.  (On patches of the sizes of a refinement level the fused pairs
+    // gain nothing over one thread per cell: their launches are few workgroups deep.)
     bool pair_level(const Unit& U, int n) const
     {
-        return o->precision == MGFR_MIXED && U.periodic && o->tile != 1 && mgfr::batch_col_tiles(n) > 0 &&
-               (phases || n > W);
+        const bool want = o->tile == 3 || (o->tile != 1 && o->tile != 2 && U.periodic);
+        return o->precision == MGFR_MIXED && want && mgfr::batch_col_tiles(n) > 0 &&
+               mgfr::batch_pair_tiles(n, U.periodic) > 0 && (phases || n > W);
     }
 
     // Allocates each unit's coarse levels (and patch boundary faces), fills the descriptors
@@ -565,7 +570,7 @@ struct Batch {
                 nl += 2;
             }
             if (count & 1) {
-                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_col(tab(S.pair), S.pair.nblk, s), "batch_ngs32_col"));
+                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_col(tab(S.pair1), S.pair1.nblk, s), "batch_ngs32_col"));
                 nl += 2;
             }
         }

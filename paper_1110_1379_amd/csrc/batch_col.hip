@@ -21,6 +21,7 @@ namespace {
 using namespace bdev;
 
 constexpr int kTJ = 16, kTK = 32, kTI = 16;     // tile and plane chunk
+constexpr int kPatchTI = 8;                     // plane chunk of the fused sweep of a patch
 constexpr int kAhead = 4;                       // planes whose loads are in flight
 constexpr int kNT = kTJ * kTK / 2;              // one cell of the colour per thread per plane
 constexpr int kLK = kTK + 2, kNL = (kTJ + 2) * kLK;
@@ -300,12 +301,13 @@ __global__ void __launch_bounds__(kNT) kc_ngs(BTable t, int colour)
         walk<P, false>(g, blk.y, colour, lv);
 }
 
-// ---- both colours in one pass (single precision, periodic boxes) ---------------------------
-// The tile sweep of the domain solve over the same 16 x 32 x 16 tiles, out of place: a tile's
+// ---- both colours in one pass (single precision) --------------------------------------------
+// The tile sweep of the domain solve over the same 16 x 32 x 16 tiles (on a patch with its
+// boundary values in the halo, fused_fp32.h), out of place: a tile's
 // halo is read from the old values while neighbouring tiles write theirs, so each sweep reads
 // one buffer of e and writes the other (dir 0: e32 to e32b, dir 1: back).  Consecutive table
 // entries go to the same XCD (workgroups are dealt to the 8 XCDs in turn).
-__global__ void __launch_bounds__(kNT) kf32_ngs(BTable t, int dir)
+__global__ void __launch_bounds__(kNT, 4) kf32_ngs(BTable t, int dir)
 {
     __shared__ V32 lv[3][(kTJ + 4) * (kTK + 4)];
     const int nb = gridDim.x;
@@ -319,10 +321,14 @@ __global__ void __launch_bounds__(kNT) kf32_ngs(BTable t, int dir)
     const int k0 = (tile % ntk) * kTK;
     tile /= ntk;
     const int j0 = (tile % ntj) * kTJ;
-    const int i0 = (tile / ntj) * kTI;
+    const int ti = g.periodic ? kTI : kPatchTI;
+    const int i0 = (tile / ntj) * ti;
     const float* ein = dir ? g.e32b : g.e32;
     float* eout = dir ? g.e32 : g.e32b;
-    fused32::sweep_tile<kTJ, kTK>(op32(g), g.n, g.lg, i0, j0, k0, kTI, g.ub32, ein, eout, g.f32, lv);
+    if (g.periodic)
+        fused32::sweep_tile<kTJ, kTK, false>(op32(g), g.n, g.lg, i0, j0, k0, ti, g.ub32, ein, eout, g.f32, lv);
+    else
+        fused32::sweep_tile<kTJ, kTK, true>(op32(g), g.n, g.lg, i0, j0, k0, ti, g.ub32, ein, eout, g.f32, lv, g.ub);
 }
 
 }  // namespace
@@ -331,6 +337,13 @@ long long batch_col_tiles(int n)
 {
     if (n < kTK || n % kTK || n % kTI) return 0;
     return (long long)(n / kTI) * (n / kTJ) * (n / kTK);
+}
+
+long long batch_pair_tiles(int n, int periodic)
+{
+    const int ti = periodic ? kTI : kPatchTI;
+    if (n < kTK || n % kTK || n % ti) return 0;
+    return (long long)(n / ti) * (n / kTJ) * (n / kTK);
 }
 
 hipError_t batch_ngs_col(const BTable& t, int nblk, hipStream_t s)

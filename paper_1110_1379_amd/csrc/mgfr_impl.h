@@ -102,7 +102,7 @@ struct BGrid {
     float* e32;        // correction e
     float* eh32;       // coarse: R e of the finer level, then e - R e
     float* f32;        // finest: r = -d; coarse: the FAS right-hand side
-    float* e32b;       // periodic level swept by pairs of fused sweeps: their second buffer of e, or null
+    float* e32b;       // level swept by pairs of fused sweeps: their second buffer of e, or null
 };
 
 // Workgroup table: blk[b] = (index into grids, block number within that grid).
@@ -154,10 +154,13 @@ hipError_t batch_ngs(const BTable& t, int nblk, hipStream_t s);
 long long batch_col_tiles(int n);
 hipError_t batch_ngs_col(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_ngs32_col(const BTable& t, int nblk, hipStream_t s);
-// Two single-precision sweeps of periodic boxes (side >= 32, e32b set), each with both colours
+// Two single-precision sweeps of unit levels (side >= 32, e32b set), each with both colours
 // in one pass over the same column tiles (the fused tile sweep of the domain solve): e32 into
 // e32b, then back.  Same results, bit for bit, as two batch_ngs32 sweeps.
+// Its table: blk[b] = (grid, tile), tiles of 16 x 32 cells by 16 planes (periodic) or 8 planes
+// (patch); batch_pair_tiles gives their number, 0 where the side does not allow them.
 hipError_t batch_ngs32_pair(const BTable& t, int nblk, hipStream_t s);
+long long batch_pair_tiles(int n, int periodic);
 hipError_t batch_resid_restrict(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
 hipError_t batch_fas_rhs(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_coarse_diff(const BTable& t, int nblk, hipStream_t s);

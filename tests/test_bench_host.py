@@ -29,18 +29,17 @@ def digest(path):
 def test_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
     # the committed figures describe the committed sources
     for prec, entry in bench.MEASURED_TRAFFIC.items():
-        assert bench.measured_traffic(prec, 512) == entry["bytes"], prec
+        first = entry["points"][0][1] if "points" in entry else entry["bytes"]
+        assert bench.measured_traffic(prec, 512) == first, prec
         assert bench.measured_traffic(prec, 256) is None
     assert bench.measured_traffic("tsc", 512) is None
     # a figure taken at given planes and tile holds only for those (tile 0 is the automatic shape)
     for prec, entry in bench.MEASURED_TRAFFIC.items():
-        if "settings" not in entry:
-            continue
-        want = dict(entry["settings"])
-        assert bench.measured_traffic(prec, 512, want) == entry["bytes"], prec
-        assert bench.measured_traffic(prec, 512, dict(want, planes=2 * want["planes"])) is None, prec
-        other = next(t for t in range(6) if bench._tile_shape(prec, t) != bench._tile_shape(prec, want["tile"]))
-        assert bench.measured_traffic(prec, 512, dict(want, tile=other)) is None, prec
+        for want, nbytes in entry.get("points", []):
+            assert bench.measured_traffic(prec, 512, dict(want)) == nbytes, prec
+            assert bench.measured_traffic(prec, 512, dict(want, planes=3 * want["planes"])) is None, prec
+            other = next(t for t in range(6) if bench._tile_shape(prec, t) != bench._tile_shape(prec, want["tile"]))
+            assert bench.measured_traffic(prec, 512, dict(want, tile=other)) is None, prec
     assert bench._tile_shape("fp64", 0) == bench._tile_shape("fp64", 1) == "16x64"
     assert bench._tile_shape("mixed", 0) == bench._tile_shape("mixed", 1) == "16x32"
     # a changed source voids the figure of every kernel built from it, and only those

@@ -293,13 +293,14 @@ def check_profile(mg, ctx, opts, sides, hists):
 @pytest.mark.parametrize("engine", [e for e in ENGINES if e[0] in ("units16", "phases")], ids=["units16", "phases"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_column_sweep_matches_per_cell_sweep(mg, ctx, precision, engine):
-    """The sweeps of unit levels of side >= 32 walk column tiles (periodic boxes by default,
-    tile = 0, in a mixed solve as pairs of fused two-colour sweeps; patches too with tile =
-    2); with tile = 1 they run one thread per cell of the colour.  All evaluate every cell
-    update with the same operands in the same order, so fields and residual histories agree
-    bit for bit: periodic boxes of sides 32 - 128 (also with odd sweep counts, where one sweep
-    of a group runs in place), and patches of side 32 and 64 (ghost faces) walked with tile =
-    2."""
+    """The sweeps of unit levels of side >= 32 walk column tiles: by default (tile = 0) a mixed
+    solve sweeps periodic boxes in pairs of fused two-colour sweeps and a double-precision one
+    walks them one colour per launch; tile = 3 also sweeps patches in fused pairs, and tile = 2
+    walks every level one colour per launch; with tile = 1 they run one thread per cell of the
+    colour.  All evaluate every cell update with the same operands in the same order, so
+    fields and residual histories agree bit for bit: periodic boxes of sides 32 - 128 (also
+    with odd sweep counts, where one sweep of a group runs in place), and patches of side 32
+    and 64 (ghost faces)."""
     say(f"[column sweep] {precision} engine={engine[0]}")
     prec = mg.MGFR_MIXED if precision == "mixed" else mg.MGFR_FP64
     tol = 1e-8 if precision == "mixed" else 1e-10
@@ -324,11 +325,12 @@ def test_column_sweep_matches_per_cell_sweep(mg, ctx, precision, engine):
     ud, patches, rho_packed, p, _ = patch_case(mg, ctx, 64, (3.0, 10.0), (32, 16, 8, 4), 1e-10)
     assert {q["n"] for q in patches} >= {32, 64}
     res = []
-    for tile in (2, 1):
+    for tile in (3, 2, 1):
         opts = mg.mgfr_default_opts(tol=tol, precision=prec, flags=engine[1], unit_n=engine[2], tile=tile)
         up, hists, st = mg.mg_fr_solve_patches(ctx, ud, patches, dev(rho_packed), p, opts)
         assert st == mg.MGFR_OK, ctx.last_error()
         res.append((up.cpu().numpy(), [np.asarray(h) for h in hists]))
-    assert np.array_equal(res[0][0], res[1][0])
-    for a, b in zip(res[0][1], res[1][1]):
-        assert np.array_equal(a, b)
+    for r in res[:2]:
+        assert np.array_equal(r[0], res[2][0])
+        for a, b in zip(r[1], res[2][1]):
+            assert np.array_equal(a, b)
