@@ -1066,7 +1066,7 @@ int mgfr_autotune(mgfr_ctx* c, const double* rho, int N, const mgfr_params* para
     };
     // stage 1: sweeps before / after the coarse step (and inner cycles for mixed)
     const int sweeps[][2] = {{1, 1}, {2, 1}, {1, 2}, {2, 2}, {3, 3}};
-    const int inners[] = {1, 2};
+    const int inners[] = {1, 2, 3};
     for (const auto& pp : sweeps)
         for (int ic : inners) {
             if (ic > 1 && base->precision != MGFR_MIXED) continue;
