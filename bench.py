@@ -43,10 +43,8 @@ MEASURED_TRAFFIC = {
     "mixed": {"points": [({"planes": 64, "tile": 3}, 3.5597e9), ({"planes": 32, "tile": 3}, 3.0682e9)],
               "sources": {
                   "kernels_fp32.hip": "3e2d5fa7b74c8e9e8695fb1c7fd7f008127e8b020b552ac5893de6581d7cd948",
-                  "fused_fp32.h": "15a7b8dd99f9658da4ca4829a5ccfca8cbde9a8d2f80880b54dee5b2ccee4554",
-                  "batch_dev.h": "e5f458582bef25e31797cfb18129042fdc32f6ea8e68172805ca135c071d10fb",
+                  "fused_fp32.h": "fce16a9bef4d9388e9a6989bb8ef11d68ccff8034c97859cecce07499f2cc8e4",
                   "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
-                  "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
                   "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
     # per finest launch (one red-black sweep, 16 x 64 tiles, 128 planes per workgroup)
     "fp64": {"points": [({"planes": 128, "tile": 1}, 3.4275e9)], "sources": {

@@ -20,6 +20,8 @@
 #include "device_fp32.h"
 #include "device_fp64.h"
 
+#include <type_traits>
+
 namespace mgfr {
 namespace bdev {
 
@@ -140,6 +142,15 @@ __device__ inline Res32 bcell32(const BGrid& g, const Op32& o, const float* __re
     return r;
 }
 
+// Orders the LDS accesses of one wavefront before and after it (its lanes run in lockstep and
+// the LDS serves a wavefront's accesses in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---- coarsest level in one workgroup of NT threads (n <= 8) -------------------------------
 // LDS of the double-precision solve: u, b = exp(u), the curvature term S and the right-hand
 // side of every cell, and the reduction buffers.
@@ -161,7 +172,9 @@ struct C64 {
 // cell is updated, so a visit evaluates exponentials only for its ghost faces.  The
 // arithmetic is that of bcell, in the same order.  Sweeps until rms <= rtol x initial, or its
 // rounding floor, or cap sweeps (rtol = 0: exactly cap).  Every thread of the workgroup calls
-// it, with (su, sb, sS, sf) filled and visible to all.
+// it, with (su, sb, sS, sf) filled and visible to all.  A level of at most 64 cells is relaxed
+// by the first wavefront alone (one cell per lane), with the same sums in the same order:
+// its sweeps then cost no workgroup barriers.
 template <int NT, class FaceFn>
 __device__ void coarsest64_core(const BGrid& g, int cap, double rtol, const C64& sm, FaceFn face)
 {
@@ -196,55 +209,78 @@ __device__ void coarsest64_core(const BGrid& g, int cap, double rtol, const C64&
         r.dL = g.C * (fma(bi, s_u, -s_b) - nreg * bi + dlg) - S * g.inv_np1;
         return r;
     };
-    auto reduce = [&](double a, double b, double& ta, double& tb) {
-        sm.ra[threadIdx.x] = a;
-        sm.rb[threadIdx.x] = b;
-        __syncthreads();
-        for (int w = NT / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) {
-                sm.ra[threadIdx.x] += sm.ra[threadIdx.x + w];
-                sm.rb[threadIdx.x] += sm.rb[threadIdx.x + w];
+    // Sums over the workgroup by the tree ra[t] += ra[t + w], w = NT/2 .. 1; in one wavefront
+    // (WAVE) the same tree by lane shuffles (threads 64 .. NT - 1 would only add zeros).
+    auto solve = [&](auto W) {
+        constexpr bool WAVE = decltype(W)::value;
+        auto reduce = [&](double a, double b, double& ta, double& tb) {
+            if constexpr (WAVE) {
+                for (int w = 32; w > 0; w >>= 1) {
+                    a += __shfl_down(a, w);
+                    b += __shfl_down(b, w);
+                }
+                ta = __shfl(a, 0);
+                tb = __shfl(b, 0);
+            } else {
+                sm.ra[threadIdx.x] = a;
+                sm.rb[threadIdx.x] = b;
+                __syncthreads();
+                for (int w = NT / 2; w > 0; w >>= 1) {
+                    if (threadIdx.x < w) {
+                        sm.ra[threadIdx.x] += sm.ra[threadIdx.x + w];
+                        sm.rb[threadIdx.x] += sm.rb[threadIdx.x + w];
+                    }
+                    __syncthreads();
+                }
+                ta = sm.ra[0];
+                tb = sm.rb[0];
+                __syncthreads();
             }
-            __syncthreads();
-        }
-        ta = sm.ra[0];
-        tb = sm.rb[0];
-        __syncthreads();
-    };
-    // rms of L - f and its rounding floor (one unit in the last place of |dL||u| + |f| + S)
-    auto rms = [&](double& floor) {
-        double s = 0.0, fl = 0.0;
-        for (int q = threadIdx.x; q < nc; q += NT) {
-            const OpVal r = cell(q);
-            s += r.L * r.L;
-            const double f1 = 2.220446049250313e-16 * (fabs(r.dL) * fabs(sm.su[q]) + fabs(sm.sf[q]) + sm.sS[q]);
-            fl += f1 * f1;
-        }
-        double ts, tf;
-        reduce(s, fl, ts, tf);
-        floor = sqrt(tf / nc);
-        return sqrt(ts / nc);
-    };
-    double fl0;
-    const double r0 = rtol > 0.0 ? rms(fl0) : 0.0;
-    for (int sweep = 0; sweep < cap; ++sweep) {
-        if (rtol > 0.0) {
-            double fl;
-            const double r = rms(fl);
-            if (r <= rtol * r0 || r <= fl) break;
-        }
-        for (int colour = 0; colour < 2; ++colour) {
+        };
+        // rms of L - f and its rounding floor (one unit in the last place of |dL||u| + |f| + S)
+        auto rms = [&](double& floor) {
+            double s = 0.0, fl = 0.0;
             for (int q = threadIdx.x; q < nc; q += NT) {
-                const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
-                if (((i + j + k) & 1) != colour) continue;
                 const OpVal r = cell(q);
-                const double u = sm.su[q] + dev::bounded(-r.L / r.dL, g.max_step);
-                sm.su[q] = u;
-                sm.sb[q] = exp(u);
-                sm.sS[q] = g.A * exp(-u * g.inv_np1);
+                s += r.L * r.L;
+                const double f1 = 2.220446049250313e-16 * (fabs(r.dL) * fabs(sm.su[q]) + fabs(sm.sf[q]) + sm.sS[q]);
+                fl += f1 * f1;
             }
-            __syncthreads();
+            double ts, tf;
+            reduce(s, fl, ts, tf);
+            floor = sqrt(tf / nc);
+            return sqrt(ts / nc);
+        };
+        double fl0;
+        const double r0 = rtol > 0.0 ? rms(fl0) : 0.0;
+        for (int sweep = 0; sweep < cap; ++sweep) {
+            if (rtol > 0.0) {
+                double fl;
+                const double r = rms(fl);
+                if (r <= rtol * r0 || r <= fl) break;
+            }
+            for (int colour = 0; colour < 2; ++colour) {
+                for (int q = threadIdx.x; q < nc; q += NT) {
+                    const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
+                    if (((i + j + k) & 1) != colour) continue;
+                    const OpVal r = cell(q);
+                    const double u = sm.su[q] + dev::bounded(-r.L / r.dL, g.max_step);
+                    sm.su[q] = u;
+                    sm.sb[q] = exp(u);
+                    sm.sS[q] = g.A * exp(-u * g.inv_np1);
+                }
+                if constexpr (WAVE) wave_sync();
+                else __syncthreads();
+            }
         }
+    };
+    if (NT >= 64 && nc <= 64) {
+        // a level of at most 64 cells is relaxed by the first wavefront alone, without
+        // workgroup barriers; the others wait for it at the one barrier below
+        if (threadIdx.x < 64) solve(std::true_type{});
+        __syncthreads();
+    } else {
+        solve(std::false_type{});
     }
 }
 
@@ -288,7 +324,8 @@ struct C32 {
 // Single precision: everything that depends only on the base stays in LDS for the whole
 // solve; per sweep only the correction-dependent parts (M, B) of the updated cells are
 // recomputed.  The arithmetic is that of bcell32, in the same order.  Every thread of the
-// workgroup calls it, with every array filled and visible to all.
+// workgroup calls it, with every array filled and visible to all; a level of at most 64 cells
+// is relaxed by the first wavefront alone, as in coarsest64_core.
 template <int NT>
 __device__ void coarsest32_core(const BGrid& g, int cap, float rtol, const C32& sm)
 {
@@ -329,53 +366,76 @@ __device__ void coarsest32_core(const BGrid& g, int cap, float rtol, const C32& 
         dN = o.C * (cB * (su + sE) - sBn - nreg * cB + dgh) - S * o.inv_np1 * (1.0f + x);
         return o.C * (fmaf(cM, su, t1) + fmaf(cB, sE, t2) + lgh) + S * x - sm.sf[q];
     };
-    // rms of N - f and its single-precision rounding floor (|dN||e| + |f|)
-    auto rms = [&](float& floor) {
-        float s = 0.0f, fl = 0.0f;
-        for (int q = threadIdx.x; q < nc; q += NT) {
-            float dN;
-            const float N = cell(q, dN);
-            s += N * N;
-            const float f1 = 1.1920929e-7f * (fabsf(dN) * fabsf(sm.se[q]) + fabsf(sm.sf[q]));
-            fl += f1 * f1;
-        }
-        sm.ra[threadIdx.x] = s;
-        sm.rb[threadIdx.x] = fl;
-        __syncthreads();
-        for (int w = NT / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) {
-                sm.ra[threadIdx.x] += sm.ra[threadIdx.x + w];
-                sm.rb[threadIdx.x] += sm.rb[threadIdx.x + w];
-            }
-            __syncthreads();
-        }
-        const float tot = sm.ra[0], tf = sm.rb[0];
-        __syncthreads();
-        floor = sqrtf(tf / nc);
-        return sqrtf(tot / nc);
-    };
-    float fl0;
-    const float r0 = rtol > 0.0f ? rms(fl0) : 0.0f;
-    for (int sweep = 0; sweep < cap; ++sweep) {
-        if (rtol > 0.0f) {
-            float fl;
-            const float r = rms(fl);
-            if (r <= rtol * r0 || r <= fl) break;
-        }
-        for (int colour = 0; colour < 2; ++colour) {
+    // Sums as in coarsest64_core: the LDS tree over the workgroup, or in one wavefront (WAVE)
+    // the same tree by lane shuffles.
+    auto solve = [&](auto W) {
+        constexpr bool WAVE = decltype(W)::value;
+        // rms of N - f and its single-precision rounding floor (|dN||e| + |f|)
+        auto rms = [&](float& floor) {
+            float s = 0.0f, fl = 0.0f;
             for (int q = threadIdx.x; q < nc; q += NT) {
-                const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
-                if (((i + j + k) & 1) != colour) continue;
-                Res32 r;
-                r.N = cell(q, r.dN);
-                const float e = sm.se[q] + newton32(r, o.max_step);
-                const float M = sm.sb[q] * em1f(e);
-                sm.se[q] = e;
-                sm.sM[q] = M;
-                sm.sB[q] = sm.sb[q] + M;
+                float dN;
+                const float N = cell(q, dN);
+                s += N * N;
+                const float f1 = 1.1920929e-7f * (fabsf(dN) * fabsf(sm.se[q]) + fabsf(sm.sf[q]));
+                fl += f1 * f1;
             }
-            __syncthreads();
+            float tot, tf;
+            if constexpr (WAVE) {
+                for (int w = 32; w > 0; w >>= 1) {
+                    s += __shfl_down(s, w);
+                    fl += __shfl_down(fl, w);
+                }
+                tot = __shfl(s, 0);
+                tf = __shfl(fl, 0);
+            } else {
+                sm.ra[threadIdx.x] = s;
+                sm.rb[threadIdx.x] = fl;
+                __syncthreads();
+                for (int w = NT / 2; w > 0; w >>= 1) {
+                    if (threadIdx.x < w) {
+                        sm.ra[threadIdx.x] += sm.ra[threadIdx.x + w];
+                        sm.rb[threadIdx.x] += sm.rb[threadIdx.x + w];
+                    }
+                    __syncthreads();
+                }
+                tot = sm.ra[0];
+                tf = sm.rb[0];
+                __syncthreads();
+            }
+            floor = sqrtf(tf / nc);
+            return sqrtf(tot / nc);
+        };
+        float fl0;
+        const float r0 = rtol > 0.0f ? rms(fl0) : 0.0f;
+        for (int sweep = 0; sweep < cap; ++sweep) {
+            if (rtol > 0.0f) {
+                float fl;
+                const float r = rms(fl);
+                if (r <= rtol * r0 || r <= fl) break;
+            }
+            for (int colour = 0; colour < 2; ++colour) {
+                for (int q = threadIdx.x; q < nc; q += NT) {
+                    const int i = q >> (2 * g.lg), j = (q >> g.lg) & m, k = q & m;
+                    if (((i + j + k) & 1) != colour) continue;
+                    Res32 r;
+                    r.N = cell(q, r.dN);
+                    const float e = sm.se[q] + newton32(r, o.max_step);
+                    const float M = sm.sb[q] * em1f(e);
+                    sm.se[q] = e;
+                    sm.sM[q] = M;
+                    sm.sB[q] = sm.sb[q] + M;
+                }
+                if constexpr (WAVE) wave_sync();
+                else __syncthreads();
+            }
         }
+    };
+    if (NT >= 64 && nc <= 64) {
+        if (threadIdx.x < 64) solve(std::true_type{});
+        __syncthreads();
+    } else {
+        solve(std::false_type{});
     }
 }
 

@@ -20,7 +20,6 @@
 // outside (the patch's edges and corners) are never read.
 #pragma once
 
-#include "batch_dev.h"
 #include "device_fp32.h"
 
 #include <type_traits>
@@ -34,6 +33,10 @@ using dev32::newton32;
 using dev32::Res32;
 using dev32::Op32;
 using dev32::V32;
+
+// Mask ratio m_ghost / m_i of a ghost cell next to a cell of a cube patch (every cell of the
+// patch is active), as in the per-cell kernels.
+constexpr float kGhostR = -1.0f;
 
 // One column of a thread: the values of planes p-2 .. p+1 and the loads in flight.
 struct Col32 {
@@ -53,7 +56,8 @@ struct ColP : Col32 {
 };
 
 // N_i - f_i and dN_i/de_i of a patch cell with the ghost faces of the neighbours flagged out
-// (their ub field holds u_b): the arithmetic of bdev::bcell32, in the same order.
+// (their ub field holds u_b): the arithmetic of the per-cell kernel (bcell32), in the same
+// order.
 __device__ __forceinline__ Res32 corr_op_patch(const Op32& o, const V32& c, const V32 (&nb)[6], const bool (&out)[6],
                                                float f)
 {
@@ -61,13 +65,13 @@ __device__ __forceinline__ Res32 corr_op_patch(const Op32& o, const V32& c, cons
 #pragma unroll
     for (int x = 0; x < 6; ++x) {
         if (out[x]) {
-            const float ubg = (1.0f - bdev::kR32) * nb[x].ub + bdev::kR32 * c.ub;
-            const float eg = bdev::kR32 * c.e;
+            const float ubg = (1.0f - kGhostR) * nb[x].ub + kGhostR * c.ub;
+            const float eg = kGhostR * c.e;
             const float bg = __expf(ubg);
             const float Mg = bg * em1f(eg), Bg = bg + Mg;
             const float du = ubg - c.ub, de = eg - c.e;
             lgh += (Mg + c.M) * du + (Bg + c.B) * de;
-            dgh += (bdev::kR32 * Bg + c.B) * (du + de) + (Bg + c.B) * (bdev::kR32 - 1.0f);
+            dgh += (kGhostR * Bg + c.B) * (du + de) + (Bg + c.B) * (kGhostR - 1.0f);
         } else {
             const float du = nb[x].ub - c.ub, de = nb[x].e - c.e;
             t1 = fmaf(nb[x].M, du, t1);

@@ -136,7 +136,7 @@ MIXED_CASES = [
 ]
 
 
-@pytest.mark.parametrize("inner", [1, 2])
+@pytest.mark.parametrize("inner", [1, 2, 3])
 @pytest.mark.parametrize("name,N,box,fr0,make", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
 def test_mixed_solve_matches_fp64_oracle(mg, ctx, name, N, box, fr0, make, inner):
     """Single-precision correction V-cycles inside the double-precision defect-correction loop

@@ -167,7 +167,7 @@ def test_tophat256_fp64_every_cell_matches_oracle(mg, ctx, tophat256):
 
 def test_tophat256_mixed_every_cell_matches_oracle(mg, ctx, tophat256):
     """Mixed solver (single-precision V-cycles in the double-precision defect correction) at
-    every planes setting with 1 and 2 inner V-cycles, at rms(L) <= 1e-8: max|u - u*| / max|u*|
+    every planes setting with 1, 2 and 3 inner V-cycles, at rms(L) <= 1e-8: max|u - u*| / max|u*|
     <= 1e-6 against the oracle at 1e-12.  The outer iteration count is pinned too: a fault in
     the single-precision sweep would only slow the outer loop down, since the double-precision
     residual corrects whatever the inner cycles return.  With k inner V-cycles the outer loop
@@ -181,8 +181,8 @@ def test_tophat256_mixed_every_cell_matches_oracle(mg, ctx, tophat256):
     _, h64, st = mg.mg_fr_solve(ctx, rho_d, p, mg.mgfr_default_opts(tol=1e-8, max_cycles=100))
     assert st == mg.MGFR_OK
     c64 = len(h64) - 1
-    settings = [(inner, planes, 0) for inner in (1, 2) for planes in (0,) + PLANES]
-    settings += [(2, planes, tile) for tile in (1, 2, 3, 4, 5) for planes in (32, 64)]
+    settings = [(inner, planes, 0) for inner in (1, 2, 3) for planes in (0,) + PLANES]
+    settings += [(inner, planes, tile) for inner in (2, 3) for tile in (1, 2, 3, 4, 5) for planes in (32, 64)]
     for inner, planes, tile in settings:
         say(f"[timed] tophat256 mixed inner={inner} planes={planes} tile={tile}")
         o = mg.mgfr_default_opts(tol=1e-8, precision=mg.MGFR_MIXED, inner_cycles=inner, planes=planes,
@@ -205,9 +205,10 @@ def _sampled_operator_check(mg, ctx, u_d, rho, rho_d, p, m, N, nsample=100000):
     return np.sqrt(np.mean(L ** 2)), np.abs(d - L).max()
 
 
-@pytest.mark.parametrize("precision,inner,planes", [("fp64", 1, 128), ("fp64", 1, 64), ("mixed", 2, 0),
-                                                    ("mixed", 2, 64), ("mixed", 2, 128), ("mixed", 1, 0)])
-def test_halo512_at_benchmark_settings(mg, ctx, precision, inner, planes):
+@pytest.mark.parametrize("precision,inner,planes,tile", [("fp64", 1, 128, 0), ("fp64", 1, 64, 0), ("mixed", 2, 0, 0),
+                                                         ("mixed", 2, 64, 3), ("mixed", 2, 128, 0), ("mixed", 1, 0, 0),
+                                                         ("mixed", 3, 32, 3), ("mixed", 3, 64, 3)])
+def test_halo512_at_benchmark_settings(mg, ctx, precision, inner, planes, tile):
     """The 512^3 halo workload solved at the settings the autotuner picks for the benchmark:
     the oracle's operator at 100 000 sampled cells of the GPU field gives rms <= 3e-8 (the
     solve stops at 1e-8) and the GPU's own residual agrees with it there."""
@@ -221,8 +222,8 @@ def test_halo512_at_benchmark_settings(mg, ctx, precision, inner, planes):
     p, m = both(512.0, 1e-6)
     rho_d = dev(rho)
     prec = mg.MGFR_MIXED if precision == "mixed" else mg.MGFR_FP64
-    say(f"[timed] halo512 {precision} inner={inner} planes={planes}")
-    o = mg.mgfr_default_opts(tol=1e-8, precision=prec, inner_cycles=inner, planes=planes, max_cycles=100)
+    say(f"[timed] halo512 {precision} inner={inner} planes={planes} tile={tile}")
+    o = mg.mgfr_default_opts(tol=1e-8, precision=prec, inner_cycles=inner, planes=planes, tile=tile, max_cycles=100)
     u_d, hist, st = mg.mg_fr_solve(ctx, rho_d, p, o)
     assert st == mg.MGFR_OK, (ctx.last_error(), hist)
     rms, agree = _sampled_operator_check(mg, ctx, u_d, rho, rho_d, p, m, N)
@@ -256,7 +257,7 @@ def test_autotuner_options_converge_and_match_oracle(mg, ctx, precision):
     assert (best.pre, best.post) in {(1, 1), (2, 1), (1, 2), (2, 2), (3, 3)}
     assert best.planes in (0,) + PLANES
     assert best.tile in ((0, 1, 2, 3, 4, 5) if precision == "mixed" else (0, 1, 2))
-    assert best.inner_cycles in ((1, 2) if precision == "mixed" else (1,))
+    assert best.inner_cycles in ((1, 2, 3) if precision == "mixed" else (1,))
     assert best.tol == base.tol and best.precision == prec and best.max_cycles == base.max_cycles
     u_ref, _, st_ref = O.solve(rho, m, O.Opts(tol=1e-12))
     assert st_ref == 0
