@@ -57,7 +57,8 @@ struct Launch {
 // by column tiles (side >= 32), and the periodic boxes of a mixed solve swept in fused pairs
 // (column tiles, e32b set).
 struct Sweep {
-    Launch cell, col, pair, pair1;  // pair1: the fused pairs' grids as column tiles (an odd sweep)
+    Launch cell, col;
+    Launch pair[2], pair1[2];  // [periodic] fused pairs; pair1: their grids as column tiles (an odd sweep)
 };
 
 struct Depth {
@@ -66,10 +67,21 @@ struct Depth {
     bool deep = false, coarsest = false;
 };
 
+// The finest residual of a list of units: column tiles for the grids that take them (side
+// >= 32), one thread per cell for the others; the (sum, max) partials of the tiles first,
+// then those of the cell blocks, and each unit's range of them for the fold.
+struct NormPlan {
+    Launch tile, cell;
+    size_t first = 0, count = 0;
+    int ngrid = 0;
+    long long nparts = 0;
+};
+
 struct Plan {
     std::vector<Depth> depth;
     Launch cells0, setup;
-    size_t first = 0, count = 0;  // per-unit block ranges of cells0 (for the norm fold)
+    size_t first = 0, count = 0;  // per-unit block ranges of cells0 (for the non-finite fold)
+    NormPlan norm;
     int nunit = 0;
     long long nblk_cells0 = 0;
 };
@@ -93,7 +105,7 @@ struct UPlan {
     std::vector<int3> ranges;          // whole units: (begin, end, side) in queue order, one launch each
     size_t ids = 0, ncell = 0;        // large units: unit index, finest cells
     Launch cells0;                     // finest cells of the large units
-    size_t lfirst = 0, lcount = 0;     // their block ranges (for the fold)
+    NormPlan norm;                     // their residual
     size_t all_tails = 0;              // every large unit's tail (for the tail bases)
     int nall_tails = 0;
 };
@@ -123,19 +135,59 @@ Launch table(Meta& meta, const std::vector<mgfr::BGrid>& grids, W work, std::vec
 
 long long cells3(const mgfr::BGrid& g) { return 1LL << (3 * g.lg); }
 
+NormPlan norm_tables(Meta& meta, const std::vector<mgfr::BGrid>& g0)
+{
+    std::vector<mgfr::BGrid> tg, cg;
+    std::vector<int2> tb, cb;
+    std::vector<int> first(g0.size()), count(g0.size());
+    const int B = mgfr::batch_block();
+    for (size_t u = 0; u < g0.size(); ++u) {
+        const long long nt = mgfr::batch_col_tiles(g0[u].n);
+        if (nt > 0) {
+            first[u] = (int)tb.size();
+            count[u] = (int)nt;
+            for (long long b = 0; b < nt; ++b) tb.push_back(make_int2((int)tg.size(), (int)b));
+            tg.push_back(g0[u]);
+        }
+    }
+    for (size_t u = 0; u < g0.size(); ++u) {
+        if (mgfr::batch_col_tiles(g0[u].n) > 0) continue;
+        const long long nb = (cells3(g0[u]) + B - 1) / B;
+        first[u] = (int)(tb.size() + cb.size());
+        count[u] = (int)nb;
+        for (long long b = 0; b < nb; ++b) cb.push_back(make_int2((int)cg.size(), (int)b));
+        cg.push_back(g0[u]);
+    }
+    NormPlan N;
+    N.tile.grids = meta.add(tg);
+    N.tile.blk = meta.add(tb);
+    N.tile.nblk = (int)tb.size();
+    N.tile.ngrid = (int)tg.size();
+    N.cell.grids = meta.add(cg);
+    N.cell.blk = meta.add(cb);
+    N.cell.nblk = (int)cb.size();
+    N.cell.ngrid = (int)cg.size();
+    N.first = meta.add(first);
+    N.count = meta.add(count);
+    N.ngrid = (int)g0.size();
+    N.nparts = (long long)tb.size() + (long long)cb.size();
+    return N;
+}
+
 // Sweep tables of the grids f: fused pairs for the grids with a second correction buffer;
 // column tiles for the others that take them (side >= 32; tile = 2: all, 1: none, otherwise
 // periodic boxes); one thread per cell of the colour for the rest.
 Sweep sweep_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, int tile)
 {
-    std::vector<mgfr::BGrid> cell, col, pair;
-    std::vector<int2> bcol, bpair, bpair1;
+    std::vector<mgfr::BGrid> cell, col, pair[2];
+    std::vector<int2> bcol, bpair[2], bpair1[2];
     for (const mgfr::BGrid& g : f) {
         const long long nt = mgfr::batch_col_tiles(g.n), np = mgfr::batch_pair_tiles(g.n, g.periodic);
         if (g.e32b && nt > 0 && np > 0) {
-            for (long long b = 0; b < np; ++b) bpair.push_back(make_int2((int)pair.size(), (int)b));
-            for (long long b = 0; b < nt; ++b) bpair1.push_back(make_int2((int)pair.size(), (int)b));
-            pair.push_back(g);
+            const int w = g.periodic ? 1 : 0;
+            for (long long b = 0; b < np; ++b) bpair[w].push_back(make_int2((int)pair[w].size(), (int)b));
+            for (long long b = 0; b < nt; ++b) bpair1[w].push_back(make_int2((int)pair[w].size(), (int)b));
+            pair[w].push_back(g);
             continue;
         }
         const bool want = tile == 2 || (tile != 1 && g.periodic);
@@ -155,8 +207,10 @@ Sweep sweep_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, int tile)
         L.ngrid = (int)gs.size();
     };
     tiles(S.col, col, bcol);
-    tiles(S.pair, pair, bpair);
-    tiles(S.pair1, pair, bpair1);
+    for (int w = 0; w < 2; ++w) {
+        tiles(S.pair[w], pair[w], bpair[w]);
+        tiles(S.pair1[w], pair[w], bpair1[w]);
+    }
     return S;
 }
 
@@ -362,6 +416,7 @@ struct Batch {
         plan.cells0 = table(meta, g0, [](const mgfr::BGrid& g) { return cells3(g); }, &first, &count);
         plan.first = meta.add(first);
         plan.count = meta.add(count);
+        plan.norm = norm_tables(meta, g0);
         plan.nunit = (int)units.size();
         plan.nblk_cells0 = plan.cells0.nblk;
         if (!phases) build_units(meta);
@@ -408,10 +463,8 @@ struct Batch {
         up.ncell = meta.add(ncell);
         std::vector<mgfr::BGrid> g0;
         for (int u : ids) g0.push_back(units[u].g[0]);
-        std::vector<int> lf, lc;
-        up.cells0 = table(meta, g0, [](const mgfr::BGrid& g) { return cells3(g); }, &lf, &lc);
-        up.lfirst = meta.add(lf);
-        up.lcount = meta.add(lc);
+        up.cells0 = table(meta, g0, [](const mgfr::BGrid& g) { return cells3(g); });
+        up.norm = norm_tables(meta, g0);
         std::vector<int2> all_tails;
         up.depth.clear();
         for (int m = 0;; ++m) {
@@ -472,7 +525,8 @@ struct Batch {
         MGFR_TRY(alloc(&dactive, nu));
         active.assign(nu, 1);
         MGFR_TRY(upload_active());
-        MGFR_TRY(alloc(&dpartial, 2 * (size_t)std::max<long long>(plan.nblk_cells0, 1)));
+        const long long nparts = std::max({plan.nblk_cells0, plan.norm.nparts, up.norm.nparts, 1LL});
+        MGFR_TRY(alloc(&dpartial, 2 * (size_t)nparts));
         MGFR_TRY(alloc(&dout, 2 * nu));
         if (!phases) {
             MGFR_TRY(alloc(&dhist, nu * (size_t)(o->max_cycles + 1)));
@@ -563,14 +617,16 @@ struct Batch {
                 nl += 2;
             }
         }
-        if (S.pair.nblk > 0) {
+        for (int w = 0; w < 2; ++w) {
+            if (S.pair[w].nblk == 0) continue;
             // pairs of fused sweeps end where they began (e32); an odd one out runs in place
             for (int k = 0; k + 2 <= count; k += 2) {
-                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_pair(tab(S.pair), S.pair.nblk, s), "batch_ngs32_pair"));
+                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_pair(tab(S.pair[w]), S.pair[w].nblk, w == 1, s),
+                                   "batch_ngs32_pair"));
                 nl += 2;
             }
             if (count & 1) {
-                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_col(tab(S.pair1), S.pair1.nblk, s), "batch_ngs32_col"));
+                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_col(tab(S.pair1[w]), S.pair1[w].nblk, s), "batch_ngs32_col"));
                 nl += 2;
             }
         }
@@ -659,15 +715,29 @@ struct Batch {
         return MGFR_OK;
     }
 
+    // Per-unit (sum d^2, max |d|) of the finest double-precision residual of N's units into
+    // dout; cast: also the single-precision r = -d, ub = u and e = 0 of the next inner solve.
+    int resid_norm(const NormPlan& N, bool cast)
+    {
+        if (N.tile.nblk > 0)
+            MGFR_TRY(hip_check(c, mgfr::batch_resid_col(tab(N.tile), N.tile.nblk, dpartial, cast, s), "batch_resid_col"));
+        if (N.cell.nblk > 0) {
+            double* part = dpartial + 2 * (size_t)N.tile.nblk;
+            if (cast)
+                MGFR_TRY(hip_check(c, mgfr::batch_resid_cast(tab(N.cell), N.cell.nblk, part, s), "batch_resid_cast"));
+            else
+                MGFR_TRY(hip_check(c, mgfr::batch_norm_blocks(tab(N.cell), N.cell.nblk, part, s), "batch_norm_blocks"));
+        }
+        return hip_check(c, mgfr::batch_fold(dpartial, (const int*)(dmeta + N.first), (const int*)(dmeta + N.count),
+                                             N.ngrid, dout, s),
+                         "batch_fold");
+    }
+
     // Per-unit rms of the finest double-precision residual (synchronises); also writes the
     // single-precision right-hand side r = -d, base ub = u and e = 0 of the next inner solve.
     int norms_cast(std::vector<double>& rms, std::vector<double>& mx)
     {
-        MGFR_TRY(hip_check(c, mgfr::batch_resid_cast(tab(plan.cells0), plan.cells0.nblk, dpartial, s),
-                           "batch_resid_cast"));
-        MGFR_TRY(hip_check(c, mgfr::batch_fold(dpartial, (const int*)(dmeta + plan.first),
-                                               (const int*)(dmeta + plan.count), plan.nunit, dout, s),
-                           "batch_fold"));
+        MGFR_TRY(resid_norm(plan.norm, true));
         MGFR_TRY(hip_check(c, hipMemcpyAsync(hout, dout, sizeof(double) * 2 * units.size(), hipMemcpyDeviceToHost, s),
                            "hipMemcpyAsync"));
         MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
@@ -695,10 +765,7 @@ struct Batch {
     // Per-unit rms of the finest residual into rms[] (synchronises).
     int norms(std::vector<double>& rms, std::vector<double>& mx)
     {
-        MGFR_TRY(hip_check(c, mgfr::batch_norm(tab(plan.cells0), plan.cells0.nblk, dpartial,
-                                               (const int*)(dmeta + plan.first), (const int*)(dmeta + plan.count),
-                                               plan.nunit, dout, s),
-                           "batch_norm"));
+        MGFR_TRY(resid_norm(plan.norm, false));
         MGFR_TRY(hip_check(c, hipMemcpyAsync(hout, dout, sizeof(double) * 2 * units.size(), hipMemcpyDeviceToHost, s),
                            "hipMemcpyAsync"));
         MGFR_TRY(hip_check(c, hipStreamSynchronize(s), "hipStreamSynchronize"));
@@ -909,16 +976,7 @@ struct Batch {
     // next right-hand side and base), its per-unit sums and the judge.
     int ujudge(bool mixed, bool first)
     {
-        const mgfr::BTable t = utab(up.cells0);
-        const int* lfirst = (const int*)(dmeta + up.lfirst);
-        const int* lcount = (const int*)(dmeta + up.lcount);
-        if (mixed) {
-            MGFR_TRY(hip_check(c, mgfr::batch_resid_cast(t, up.cells0.nblk, dpartial, s), "batch_resid_cast"));
-            MGFR_TRY(hip_check(c, mgfr::batch_fold(dpartial, lfirst, lcount, up.nlarge, dout, s), "batch_fold"));
-        } else {
-            MGFR_TRY(hip_check(c, mgfr::batch_norm(t, up.cells0.nblk, dpartial, lfirst, lcount, up.nlarge, dout, s),
-                               "batch_norm"));
-        }
+        MGFR_TRY(resid_norm(up.norm, mixed));
         return hip_check(c, mgfr::unit_judge(dout, (const int*)(dmeta + up.ids), (const double*)(dmeta + up.ncell),
                                              up.nlarge, dactive, uout(), o->tol, o->max_cycles, first, dany(), s),
                          "unit_judge");

@@ -61,15 +61,17 @@ struct P64 {
     __device__ __forceinline__ static Lds make(Raw v, bool) { return make_double2(v, exp(v)); }
     __device__ __forceinline__ static Rhs rhs(const BGrid& g, unsigned q) { return gload(g.src + q); }
 
-    // bcell's update with the neighbours (i-1, i+1, j-1, j+1, k-1, k+1) and the cell from LDS
-    __device__ __forceinline__ static void update(const BGrid& g, unsigned q, const bool (&out)[6], const Lds (&nb)[6], Lds c, Rhs src)
+    // bcell's L - f and dL with the neighbours (i-1, i+1, j-1, j+1, k-1, k+1) and the cell
+    // from LDS
+    __device__ __forceinline__ static void op(const BGrid& g, const bool (&out)[6], const Lds (&nb)[6], Lds c, Rhs src,
+                                              double& L, double& dL)
     {
         const double ui = c.x, bi = c.y;
         double su = 0.0, sb = 0.0, sbu = 0.0, lg_ = 0.0, dlg = 0.0;
         int nreg = 0;
 #pragma unroll
         for (int x = 0; x < 6; ++x) {
-            if (out[x]) {
+            if (__builtin_expect(out[x], 0)) {
                 const double ug = (1.0 - kR) * nb[x].x + kR * ui;
                 const double bg = exp(ug);
                 lg_ += (bg + bi) * (ug - ui);
@@ -83,9 +85,15 @@ struct P64 {
             }
         }
         const double S = g.A * exp(-ui * g.inv_np1);
-        const double L = g.C * (fma(bi, su, sbu) + lg_) + S - fma(g.fscale, src - g.sref, g.fshift);
-        const double dL = g.C * (fma(bi, su, -sb) - nreg * bi + dlg) - S * g.inv_np1;
-        gstore(g.u + q, ui + dev::bounded(-L / dL, g.max_step));
+        L = g.C * (fma(bi, su, sbu) + lg_) + S - fma(g.fscale, src - g.sref, g.fshift);
+        dL = g.C * (fma(bi, su, -sb) - nreg * bi + dlg) - S * g.inv_np1;
+    }
+    // bcell's update
+    __device__ __forceinline__ static void update(const BGrid& g, unsigned q, const bool (&out)[6], const Lds (&nb)[6], Lds c, Rhs src)
+    {
+        double L, dL;
+        op(g, out, nb, c, src, L, dL);
+        gstore(g.u + q, c.x + dev::bounded(-L / dL, g.max_step));
     }
 };
 
@@ -124,7 +132,7 @@ struct P32 {
         float t1 = 0.0f, t2 = 0.0f, su = 0.0f, se = 0.0f, sB = 0.0f, nreg = 0.0f, lgh = 0.0f, dgh = 0.0f;
 #pragma unroll
         for (int x = 0; x < 6; ++x) {
-            if (out[x]) {
+            if (__builtin_expect(out[x], 0)) {
                 const float ubg = (1.0f - kR32) * nb[x].ub + kR32 * c.ub;
                 const float eg = kR32 * c.e;
                 const float bg = __expf(ubg);
@@ -186,9 +194,26 @@ __device__ __forceinline__ Entry entry(const BGrid& g, int j0, int k0, int e)
     return s;
 }
 
+// What a walk does at each plane (A): A::kCells cells per thread, in its tile column pair
+// (row jj, columns kb and kb + 1), column kb + A::column(parity of the plane, j, c) for cell
+// c; act(g, q, out, nb, centre, rhs) on each.
+//
+// A colour sweep: one cell per thread and plane, the one of the colour.
+template <class P>
+struct ColourSweep {
+    static constexpr int kCells = 1;
+    int colour;
+    __device__ __forceinline__ int column(int par, int j, int) const { return (par + j + colour) & 1; }
+    __device__ __forceinline__ void operator()(const BGrid& g, unsigned q, const bool (&out)[6],
+                                               const typename P::Lds (&nb)[6], typename P::Lds c, typename P::Rhs f)
+    {
+        P::update(g, q, out, nb, c, f);
+    }
+};
+
 // The walk of one tile, PER: the unit is a periodic box (no faces, indices wrap).
-template <class P, bool PER>
-__device__ __forceinline__ void walk(const BGrid g, int tile, int colour, typename P::Lds (*lv)[kNL])
+template <class P, bool PER, class A>
+__device__ __forceinline__ void walk(const BGrid g, int tile, typename P::Lds (*lv)[kNL], A& act)
 {
     using Raw = typename P::Raw;
     const int m = g.n - 1, lg = g.lg;
@@ -235,25 +260,29 @@ __device__ __forceinline__ void walk(const BGrid g, int tile, int colour, typena
         for (int s = 0; s < kSlots; ++s)
             if (en[s].kind != 2) L[t + s * kNT] = P::make(r[s], !PER && en[s].kind == fk);
     };
-    // The cell of the colour that this thread relaxes on plane p: row jj of the tile, column
-    // kb or kb + 1 by the parity of p (i0 is even, so that of the step).  Its offset in the
-    // plane and its LDS entry for even and odd steps.
+    // The cells this thread handles on plane p: row jj of the tile, columns chosen by the
+    // action from kb, kb + 1 by the parity of p (i0 is even, so that of the step).  Their
+    // offsets in the plane and LDS entries for even and odd steps.
+    constexpr int NC = A::kCells;
     const int jj = t / (kTK / 2);
     const int kb = 2 * (t - jj * (kTK / 2));
     const int j = j0 + jj;
-    int kc[2];
-    unsigned jk[2];
-    int ec[2];
+    int kc[2][NC];
+    unsigned jk[2][NC];
+    int ec[2][NC];
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
-        kc[par] = k0 + kb + ((par + j + colour) & 1);
-        jk[par] = ((unsigned)j << lg) + (unsigned)kc[par];
-        ec[par] = (jj + 1) * kLK + (kc[par] - k0) + 1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            kc[par][c] = k0 + kb + act.column(par, j, c);
+            jk[par][c] = ((unsigned)j << lg) + (unsigned)kc[par][c];
+            ec[par][c] = (jj + 1) * kLK + (kc[par][c] - k0) + 1;
+        }
     }
-    auto cell_q = [&](int p, int par) { return ((unsigned)p << (2 * lg)) + jk[par]; };
+    auto cell_q = [&](int p, int par, int c) { return ((unsigned)p << (2 * lg)) + jk[par][c]; };
 
     Raw ahead[kAhead][kSlots];
-    typename P::Rhs rh[kAhead];
+    typename P::Rhs rh[kAhead][NC];
     {
         Raw r0[kSlots], r1[kSlots], r2[kSlots];
         fetch(i0 - 1, r0);
@@ -262,7 +291,9 @@ __device__ __forceinline__ void walk(const BGrid g, int tile, int colour, typena
 #pragma unroll
         for (int d = 0; d < kAhead; ++d) fetch(i0 + 2 + d, ahead[d]);
 #pragma unroll
-        for (int d = 0; d < kAhead; ++d) rh[d] = P::rhs(g, cell_q(i0 + d, d & 1));
+        for (int d = 0; d < kAhead; ++d)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) rh[d][c] = P::rhs(g, cell_q(i0 + d, d & 1, c));
         put(i0 - 1, r0);
         put(i0, r1);
         put(i0 + 1, r2);
@@ -271,17 +302,20 @@ __device__ __forceinline__ void walk(const BGrid g, int tile, int colour, typena
 #pragma unroll
     for (int s = 0; s < kTI; ++s) {
         const int p = i0 + s, d = s % kAhead, par = s & 1;
-        {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
             const typename P::Lds* Lm = lv[(s + 0) % kRing];
             const typename P::Lds* L0 = lv[(s + 1) % kRing];
             const typename P::Lds* Lp = lv[(s + 2) % kRing];
-            const int e = ec[par], k = kc[par];
+            const int e = ec[par][c], k = kc[par][c];
             const bool out[6] = {!PER && p == 0, !PER && p == m, !PER && j == 0,
                                  !PER && j == m, !PER && k == 0, !PER && k == m};
             const typename P::Lds nb[6] = {Lm[e], Lp[e], L0[e - kLK], L0[e + kLK], L0[e - 1], L0[e + 1]};
-            P::update(g, cell_q(p, par), out, nb, L0[e], rh[d]);
+            act(g, cell_q(p, par, c), out, nb, L0[e], rh[d][c]);
         }
-        if (s + kAhead < kTI) rh[d] = P::rhs(g, cell_q(p + kAhead, par));
+        if (s + kAhead < kTI)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) rh[d][c] = P::rhs(g, cell_q(p + kAhead, par, c));
         if (s + 2 <= kTI) put(p + 2, ahead[d]);
         if (s + 2 + kAhead <= kTI) fetch(p + 2 + kAhead, ahead[d]);
         __syncthreads();
@@ -295,10 +329,76 @@ __global__ void __launch_bounds__(kNT) kc_ngs(BTable t, int colour)
     const int2 blk = t.blk[blockIdx.x];
     const BGrid g = t.grids[blk.x];
     if (!live(t, g)) return;
+    ColourSweep<P> act{colour};
     if (g.periodic)
-        walk<P, true>(g, blk.y, colour, lv);
+        walk<P, true>(g, blk.y, lv, act);
     else
-        walk<P, false>(g, blk.y, colour, lv);
+        walk<P, false>(g, blk.y, lv, act);
+}
+
+// ---- double-precision residual over the same tiles ------------------------------------------
+// d = L(u) - f at both cells of the thread's column pair on every plane (bcell's arithmetic,
+// the exponentials of each staged cell formed once); the thread keeps sum d^2 and max |d|,
+// the workgroup folds them into one (sum, max) pair per tile.  CAST (the outer loop of a
+// mixed solve): also r = -d, ub = u in single precision and e = 0, as kb_resid_cast.
+// The running sums are also written to the thread's LDS slots at every cell: kept only in
+// registers, their updates would be sunk to the end of the walk, every d held live until
+// then (over 256 VGPRs).
+template <bool CAST>
+struct Resid64 {
+    static constexpr int kCells = 2;
+    double s = 0.0, mx = 0.0;
+    double *ls, *lm;
+    __device__ __forceinline__ int column(int, int, int c) const { return c; }
+    __device__ __forceinline__ void operator()(const BGrid& g, unsigned q, const bool (&out)[6], const double2 (&nb)[6],
+                                               double2 c, double src)
+    {
+        double d, dL;
+        P64::op(g, out, nb, c, src, d, dL);
+        if (CAST) {
+            gstore(g.f32 + q, (float)(-d));
+            gstore(g.ub32 + q, (float)c.x);
+            gstore(g.e32 + q, 0.0f);
+        }
+        s += d * d;
+        const double a = fabs(d);
+        if (!(mx >= a)) mx = a;
+        *ls = s;
+        *lm = mx;
+    }
+};
+
+template <bool CAST>
+__global__ void __launch_bounds__(kNT) kc_resid(BTable t, double* __restrict__ partial)
+{
+    __shared__ double2 lv[kRing][kNL];
+    __shared__ double ra[kNT], rb[kNT];
+    const int2 blk = t.blk[blockIdx.x];
+    const BGrid g = t.grids[blk.x];
+    Resid64<CAST> act;
+    act.ls = ra + threadIdx.x;
+    act.lm = rb + threadIdx.x;
+    ra[threadIdx.x] = 0.0;
+    rb[threadIdx.x] = 0.0;
+    if (live(t, g)) {
+        if (g.periodic)
+            walk<P64, true>(g, blk.y, lv, act);
+        else
+            walk<P64, false>(g, blk.y, lv, act);
+    }
+    __syncthreads();
+    for (int w = kNT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            ra[threadIdx.x] += ra[threadIdx.x + w];
+            const double o = rb[threadIdx.x + w];
+            if (!(rb[threadIdx.x] >= o)) rb[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = ra[0];
+        partial[2 * blockIdx.x + 1] = rb[0];
+    }
 }
 
 // ---- both colours in one pass (single precision) --------------------------------------------
@@ -307,6 +407,9 @@ __global__ void __launch_bounds__(kNT) kc_ngs(BTable t, int colour)
 // halo is read from the old values while neighbouring tiles write theirs, so each sweep reads
 // one buffer of e and writes the other (dir 0: e32 to e32b, dir 1: back).  Consecutive table
 // entries go to the same XCD (workgroups are dealt to the 8 XCDs in turn).
+// PER: periodic boxes, else patches (kernels of their own: the patch form's registers would
+// push the box form into spills).
+template <bool PER>
 __global__ void __launch_bounds__(kNT, 4) kf32_ngs(BTable t, int dir)
 {
     __shared__ V32 lv[3][(kTJ + 4) * (kTK + 4)];
@@ -321,11 +424,11 @@ __global__ void __launch_bounds__(kNT, 4) kf32_ngs(BTable t, int dir)
     const int k0 = (tile % ntk) * kTK;
     tile /= ntk;
     const int j0 = (tile % ntj) * kTJ;
-    const int ti = g.periodic ? kTI : kPatchTI;
+    const int ti = PER ? kTI : kPatchTI;
     const int i0 = (tile / ntj) * ti;
     const float* ein = dir ? g.e32b : g.e32;
     float* eout = dir ? g.e32 : g.e32b;
-    if (g.periodic)
+    if (PER)
         fused32::sweep_tile<kTJ, kTK, false>(op32(g), g.n, g.lg, i0, j0, k0, ti, g.ub32, ein, eout, g.f32, lv);
     else
         fused32::sweep_tile<kTJ, kTK, true>(op32(g), g.n, g.lg, i0, j0, k0, ti, g.ub32, ein, eout, g.f32, lv, g.ub);
@@ -360,9 +463,23 @@ hipError_t batch_ngs32_col(const BTable& t, int nblk, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t batch_ngs32_pair(const BTable& t, int nblk, hipStream_t s)
+hipError_t batch_ngs32_pair(const BTable& t, int nblk, bool periodic, hipStream_t s)
 {
-    for (int dir = 0; dir < 2; ++dir) hipLaunchKernelGGL(kf32_ngs, dim3(nblk), dim3(kNT), 0, s, t, dir);
+    for (int dir = 0; dir < 2; ++dir) {
+        if (periodic)
+            hipLaunchKernelGGL(kf32_ngs<true>, dim3(nblk), dim3(kNT), 0, s, t, dir);
+        else
+            hipLaunchKernelGGL(kf32_ngs<false>, dim3(nblk), dim3(kNT), 0, s, t, dir);
+    }
+    return hipGetLastError();
+}
+
+hipError_t batch_resid_col(const BTable& t, int nblk, double* partial, bool cast, hipStream_t s)
+{
+    if (cast)
+        hipLaunchKernelGGL(kc_resid<true>, dim3(nblk), dim3(kNT), 0, s, t, partial);
+    else
+        hipLaunchKernelGGL(kc_resid<false>, dim3(nblk), dim3(kNT), 0, s, t, partial);
     return hipGetLastError();
 }
 

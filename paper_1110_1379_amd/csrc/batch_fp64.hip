@@ -394,6 +394,11 @@ hipError_t batch_nonfinite(const BTable& t, int nblk, double* partial, hipStream
     return hipGetLastError();
 }
 
+hipError_t batch_norm_blocks(const BTable& t, int nblk, double* partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_norm, dim3(nblk), dim3(kB), 0, s, t, partial);
+    return hipGetLastError();
+}
 hipError_t batch_resid_cast(const BTable& t, int nblk, double* partial, hipStream_t s)
 {
     hipLaunchKernelGGL(kb_resid_cast, dim3(nblk), dim3(kB), 0, s, t, partial);

@@ -153,13 +153,18 @@ hipError_t batch_ngs(const BTable& t, int nblk, hipStream_t s);
 // the side does not allow them (n < 32).  Same results, bit for bit, as batch_ngs / batch_ngs32.
 long long batch_col_tiles(int n);
 hipError_t batch_ngs_col(const BTable& t, int nblk, hipStream_t s);
+// d = L(u) - f of every cell over the same column tiles, with one (sum d^2, max |d|) pair per
+// tile in partial (as batch_norm's blocks); cast: also r = -d, ub = u and e = 0 in single
+// precision (as batch_resid_cast).  d is the same, bit for bit, as theirs.
+hipError_t batch_resid_col(const BTable& t, int nblk, double* partial, bool cast, hipStream_t s);
 hipError_t batch_ngs32_col(const BTable& t, int nblk, hipStream_t s);
 // Two single-precision sweeps of unit levels (side >= 32, e32b set), each with both colours
 // in one pass over the same column tiles (the fused tile sweep of the domain solve): e32 into
 // e32b, then back.  Same results, bit for bit, as two batch_ngs32 sweeps.
 // Its table: blk[b] = (grid, tile), tiles of 16 x 32 cells by 16 planes (periodic) or 8 planes
-// (patch); batch_pair_tiles gives their number, 0 where the side does not allow them.
-hipError_t batch_ngs32_pair(const BTable& t, int nblk, hipStream_t s);
+// (patch), every grid of the table periodic or every one a patch, as `periodic` says;
+// batch_pair_tiles gives their number, 0 where the side does not allow them.
+hipError_t batch_ngs32_pair(const BTable& t, int nblk, bool periodic, hipStream_t s);
 long long batch_pair_tiles(int n, int periodic);
 hipError_t batch_resid_restrict(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
 hipError_t batch_fas_rhs(const BTable& t, int nblk, hipStream_t s);
@@ -170,6 +175,8 @@ hipError_t batch_coarsest(const BGrid* grids, int ngrid, int n, const int* activ
                           hipStream_t s);
 hipError_t batch_norm(const BTable& t, int nblk, double* partial, const int* first, const int* count, int ngrid,
                       double* out, hipStream_t s);
+// The blocks' (sum d^2, max |d|) of batch_norm only, without the fold.
+hipError_t batch_norm_blocks(const BTable& t, int nblk, double* partial, hipStream_t s);
 hipError_t batch_fold(const double* partial, const int* first, const int* count, int ngrid, double* out,
                       hipStream_t s);
 hipError_t batch_setup(const BTable& t, int nblk, const PatchParent* parents, hipStream_t s);
