@@ -61,8 +61,15 @@ struct Sweep {
     Launch pair[2], pair1[2];  // [periodic] fused pairs; pair1: their grids as column tiles (an odd sweep)
 };
 
+// Residual and restriction of one depth: column tiles over the fine grids that take them,
+// one thread per coarse cell for the rest; each with its coarse grids (other, same order).
+struct RR {
+    Launch tile, cell;
+};
+
 struct Depth {
     Sweep half;
+    RR rr;
     Launch coarse_f, coarse_c, fine_f, faces_c, crs;
     bool deep = false, coarsest = false;
 };
@@ -92,6 +99,7 @@ struct Plan {
 // from there)).
 struct UDepth {
     Sweep half;
+    RR rr;
     Launch coarse_f, coarse_c, fine_f;
     size_t tails = 0;
     int ntail = 0;
@@ -134,6 +142,32 @@ Launch table(Meta& meta, const std::vector<mgfr::BGrid>& grids, W work, std::vec
 }
 
 long long cells3(const mgfr::BGrid& g) { return 1LL << (3 * g.lg); }
+
+RR rr_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, const std::vector<mgfr::BGrid>& cg)
+{
+    std::vector<mgfr::BGrid> tf, tc, cf, cc;
+    std::vector<int2> tb;
+    for (size_t i = 0; i < f.size(); ++i) {
+        const long long nt = mgfr::batch_col_tiles(f[i].n);
+        if (nt > 0) {
+            for (long long b = 0; b < nt; ++b) tb.push_back(make_int2((int)tf.size(), (int)b));
+            tf.push_back(f[i]);
+            tc.push_back(cg[i]);
+        } else {
+            cf.push_back(f[i]);
+            cc.push_back(cg[i]);
+        }
+    }
+    RR R;
+    R.tile.grids = meta.add(tf);
+    R.tile.blk = meta.add(tb);
+    R.tile.nblk = (int)tb.size();
+    R.tile.ngrid = (int)tf.size();
+    R.tile.other = meta.add(tc);
+    R.cell = table(meta, cf, [](const mgfr::BGrid& g) { return cells3(g) / 8; });
+    R.cell.other = meta.add(cc);
+    return R;
+}
 
 NormPlan norm_tables(Meta& meta, const std::vector<mgfr::BGrid>& g0)
 {
@@ -396,6 +430,7 @@ struct Batch {
                 D.coarse_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 8; });
                 D.coarse_f.other = D.coarse_c.grids;  // coarse grids, same order
                 D.fine_f.other = D.coarse_c.grids;
+                D.rr = rr_tables(meta, f, cgr);
                 std::vector<mgfr::BGrid> pf, pc;
                 for (size_t i = 0; i < f.size(); ++i)
                     if (!f[i].periodic) {
@@ -486,6 +521,7 @@ struct Batch {
             D.coarse_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 8; });
             D.coarse_f.other = D.coarse_c.grids;
             D.fine_f.other = D.coarse_c.grids;
+            D.rr = rr_tables(meta, f, cg);
             D.tails = meta.add(tails);
             D.ntail = (int)tails.size();
             all_tails.insert(all_tails.end(), tails.begin(), tails.end());
@@ -634,6 +670,26 @@ struct Batch {
         return MGFR_OK;
     }
 
+    // Residual and restriction of a depth into its coarse level (FP64, or single: the
+    // correction equation)
+    int resid_restrict(const RR& R, bool single)
+    {
+        if (R.tile.nblk > 0)
+            MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict_col(tab(R.tile), R.tile.nblk,
+                                                                 (const mgfr::BGrid*)(dmeta + R.tile.other), single, s),
+                               "batch_resid_restrict_col"));
+        if (R.cell.nblk > 0) {
+            const mgfr::BGrid* coarse = (const mgfr::BGrid*)(dmeta + R.cell.other);
+            if (single)
+                MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict32(tab(R.cell), R.cell.nblk, coarse, s),
+                                   "batch_resid_restrict32"));
+            else
+                MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict(tab(R.cell), R.cell.nblk, coarse, s),
+                                   "batch_resid_restrict"));
+        }
+        return MGFR_OK;
+    }
+
     // read u and rho, write u
     int sweep(int m, int count)
     {
@@ -654,9 +710,7 @@ struct Batch {
                                "batch_coarsest"));
         if (!D.deep) return MGFR_OK;
         MGFR_TRY(sweep(m, o->pre));
-        MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict(tab(D.coarse_f), D.coarse_f.nblk,
-                                                         (const mgfr::BGrid*)(dmeta + D.coarse_f.other), s),
-                           "batch_resid_restrict"));
+        MGFR_TRY(resid_restrict(D.rr, false));
         MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs"));
         MGFR_TRY(vcycle(m + 1));
         MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_coarse_diff"));
@@ -688,10 +742,8 @@ struct Batch {
                                                          o->coarsest_rtol, s),
                                "batch_coarsest32"));
         if (!D.deep) return MGFR_OK;
-        const mgfr::BGrid* coarse = (const mgfr::BGrid*)(dmeta + D.coarse_f.other);
         MGFR_TRY(sweep32(m, o->pre));
-        MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict32(tab(D.coarse_f), D.coarse_f.nblk, coarse, s),
-                           "batch_resid_restrict32"));
+        MGFR_TRY(resid_restrict(D.rr, true));
         MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs32(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs32"));
         MGFR_TRY(vcycle32(m + 1));
         MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff32(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_coarse_diff32"));
@@ -929,12 +981,10 @@ struct Batch {
         const mgfr::BGrid* coarse = (const mgfr::BGrid*)(dmeta + D.coarse_f.other);
         MGFR_TRY(usweep(m, mixed, o->pre));
         if (mixed) {
-            MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict32(utab(D.coarse_f), D.coarse_f.nblk, coarse, s),
-                               "batch_resid_restrict32"));
+            MGFR_TRY(resid_restrict(D.rr, true));
             MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs32(utab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs32"));
         } else {
-            MGFR_TRY(hip_check(c, mgfr::batch_resid_restrict(utab(D.coarse_f), D.coarse_f.nblk, coarse, s),
-                               "batch_resid_restrict"));
+            MGFR_TRY(resid_restrict(D.rr, false));
             MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs(utab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs"));
         }
         if (D.ntail > 0)  // every tail level has side W

@@ -95,6 +95,21 @@ struct P64 {
         op(g, out, nb, c, src, L, dL);
         gstore(g.u + q, c.x + dev::bounded(-L / dL, g.max_step));
     }
+    // the value restricted, the residual, and the coarse cell they set
+    __device__ __forceinline__ static double value(Lds c) { return c.x; }
+    __device__ __forceinline__ static double residual(const BGrid& g, const bool (&out)[6], const Lds (&nb)[6], Lds c,
+                                                      Rhs src)
+    {
+        double L, dL;
+        op(g, out, nb, c, src, L, dL);
+        return L;
+    }
+    __device__ __forceinline__ static void restrict_to(const BGrid& c, unsigned qc, double su, double sd)
+    {
+        gstore(c.u + qc, 0.125 * su);
+        gstore(c.uhat + qc, 0.125 * su);
+        gstore(c.f + qc, 0.125 * sd);
+    }
 };
 
 struct F2 {
@@ -125,8 +140,8 @@ struct P32 {
     }
     __device__ __forceinline__ static Rhs rhs(const BGrid& g, unsigned q) { return gload(g.f32 + q); }
 
-    // bcell32's update with the neighbours and the cell from LDS
-    __device__ __forceinline__ static void update(const BGrid& g, unsigned q, const bool (&out)[6], const Lds (&nb)[6], Lds c, Rhs f)
+    // bcell32's N - f and dN with the neighbours and the cell from LDS
+    __device__ __forceinline__ static Res32 op(const BGrid& g, const bool (&out)[6], const Lds (&nb)[6], Lds c, Rhs f)
     {
         const Op32 o = op32(g);
         float t1 = 0.0f, t2 = 0.0f, su = 0.0f, se = 0.0f, sB = 0.0f, nreg = 0.0f, lgh = 0.0f, dgh = 0.0f;
@@ -156,7 +171,24 @@ struct P32 {
         Res32 r;
         r.N = o.C * (fmaf(c.M, su, t1) + fmaf(c.B, se, t2) + lgh) + S * xx - f;
         r.dN = o.C * (c.B * (su + se) - sB - nreg * c.B + dgh) - S * o.inv_np1 * (1.0f + xx);
-        gstore(g.e32 + q, c.e + newton32(r, o.max_step));
+        return r;
+    }
+    // bcell32's update
+    __device__ __forceinline__ static void update(const BGrid& g, unsigned q, const bool (&out)[6], const Lds (&nb)[6], Lds c, Rhs f)
+    {
+        const Res32 r = op(g, out, nb, c, f);
+        gstore(g.e32 + q, c.e + newton32(r, (float)g.max_step));
+    }
+    __device__ __forceinline__ static float value(Lds c) { return c.e; }
+    __device__ __forceinline__ static float residual(const BGrid& g, const bool (&out)[6], const Lds (&nb)[6], Lds c, Rhs f)
+    {
+        return op(g, out, nb, c, f).N;
+    }
+    __device__ __forceinline__ static void restrict_to(const BGrid& c, unsigned qc, float se, float sd)
+    {
+        gstore(c.e32 + qc, 0.125f * se);
+        gstore(c.eh32 + qc, 0.125f * se);
+        gstore(c.f32 + qc, 0.125f * sd);
     }
 };
 
@@ -196,7 +228,7 @@ __device__ __forceinline__ Entry entry(const BGrid& g, int j0, int k0, int e)
 
 // What a walk does at each plane (A): A::kCells cells per thread, in its tile column pair
 // (row jj, columns kb and kb + 1), column kb + A::column(parity of the plane, j, c) for cell
-// c; act(g, q, out, nb, centre, rhs) on each.
+// c; act(g, q, c, out, nb, centre, rhs) on each, then act.plane_end(p) (every thread).
 //
 // A colour sweep: one cell per thread and plane, the one of the colour.
 template <class P>
@@ -204,11 +236,12 @@ struct ColourSweep {
     static constexpr int kCells = 1;
     int colour;
     __device__ __forceinline__ int column(int par, int j, int) const { return (par + j + colour) & 1; }
-    __device__ __forceinline__ void operator()(const BGrid& g, unsigned q, const bool (&out)[6],
+    __device__ __forceinline__ void operator()(const BGrid& g, unsigned q, int, const bool (&out)[6],
                                                const typename P::Lds (&nb)[6], typename P::Lds c, typename P::Rhs f)
     {
         P::update(g, q, out, nb, c, f);
     }
+    __device__ __forceinline__ void plane_end(int) {}
 };
 
 // The walk of one tile, PER: the unit is a periodic box (no faces, indices wrap).
@@ -311,8 +344,9 @@ __device__ __forceinline__ void walk(const BGrid g, int tile, typename P::Lds (*
             const bool out[6] = {!PER && p == 0, !PER && p == m, !PER && j == 0,
                                  !PER && j == m, !PER && k == 0, !PER && k == m};
             const typename P::Lds nb[6] = {Lm[e], Lp[e], L0[e - kLK], L0[e + kLK], L0[e - 1], L0[e + 1]};
-            act(g, cell_q(p, par, c), out, nb, L0[e], rh[d][c]);
+            act(g, cell_q(p, par, c), c, out, nb, L0[e], rh[d][c]);
         }
+        act.plane_end(p);
         if (s + kAhead < kTI)
 #pragma unroll
             for (int c = 0; c < NC; ++c) rh[d][c] = P::rhs(g, cell_q(p + kAhead, par, c));
@@ -350,8 +384,8 @@ struct Resid64 {
     double s = 0.0, mx = 0.0;
     double *ls, *lm;
     __device__ __forceinline__ int column(int, int, int c) const { return c; }
-    __device__ __forceinline__ void operator()(const BGrid& g, unsigned q, const bool (&out)[6], const double2 (&nb)[6],
-                                               double2 c, double src)
+    __device__ __forceinline__ void operator()(const BGrid& g, unsigned q, int, const bool (&out)[6],
+                                               const double2 (&nb)[6], double2 c, double src)
     {
         double d, dL;
         P64::op(g, out, nb, c, src, d, dL);
@@ -365,6 +399,56 @@ struct Resid64 {
         if (!(mx >= a)) mx = a;
         *ls = s;
         *lm = mx;
+    }
+    __device__ __forceinline__ void plane_end(int) {}
+};
+
+// ---- residual and restriction over the same tiles --------------------------------------------
+// The residual of both cells of the thread's column pair on every plane (P64: L(u) - f; P32:
+// N(e) - r), and with them the sums over each 2 x 2 x 2 block that the coarse level takes:
+// coarse value = mean of the fine values, coarse right-hand side = mean of the residuals
+// (kb_resid_restrict / kb32_resid_restrict, summed in their order: i, then j, then k).  The
+// rows jj and jj + 1 of a block lie on lanes t and t + 16 of one wavefront.
+template <class P>
+struct ResidRestrict {
+    using T = decltype(P::value(typename P::Lds{}));
+    static constexpr int kCells = 2;
+    BGrid c;       // the coarse grid
+    T v[2], r[2];  // this plane's values and residuals
+    T sv = 0, sr = 0;
+    unsigned q0 = 0;
+    __device__ __forceinline__ int column(int, int, int cc) const { return cc; }
+    __device__ __forceinline__ void operator()(const BGrid& g, unsigned q, int cc, const bool (&out)[6],
+                                               const typename P::Lds (&nb)[6], typename P::Lds ctr,
+                                               typename P::Rhs rhs)
+    {
+        v[cc] = P::value(ctr);
+        r[cc] = P::residual(g, out, nb, ctr, rhs);
+        if (cc == 0) q0 = q;
+    }
+    __device__ __forceinline__ void plane_end(int p)
+    {
+        const T pv0 = __shfl_down(v[0], 16), pv1 = __shfl_down(v[1], 16);
+        const T pr0 = __shfl_down(r[0], 16), pr1 = __shfl_down(r[1], 16);
+        if (!(p & 1)) {
+            sv = 0;
+            sr = 0;
+        }
+        sv += v[0];
+        sr += r[0];
+        sv += v[1];
+        sr += r[1];
+        sv += pv0;
+        sr += pr0;
+        sv += pv1;
+        sr += pr1;
+        const int lg = c.lg + 1, m = (1 << lg) - 1;
+        const int j = (int)(q0 >> lg) & m;
+        if ((p & 1) && !(j & 1)) {
+            const int k = (int)(q0 & m) & ~1;
+            const unsigned qc = ((((unsigned)(p >> 1) << c.lg) + (unsigned)(j >> 1)) << c.lg) + (unsigned)(k >> 1);
+            P::restrict_to(c, qc, sv, sr);
+        }
     }
 };
 
@@ -399,6 +483,21 @@ __global__ void __launch_bounds__(kNT) kc_resid(BTable t, double* __restrict__ p
         partial[2 * blockIdx.x] = ra[0];
         partial[2 * blockIdx.x + 1] = rb[0];
     }
+}
+
+template <class P>
+__global__ void __launch_bounds__(kNT) kc_resid_restrict(BTable t, const BGrid* __restrict__ tc)
+{
+    __shared__ typename P::Lds lv[kRing][kNL];
+    const int2 blk = t.blk[blockIdx.x];
+    const BGrid g = t.grids[blk.x];
+    if (!live(t, g)) return;
+    ResidRestrict<P> act;
+    act.c = tc[blk.x];
+    if (g.periodic)
+        walk<P, true>(g, blk.y, lv, act);
+    else
+        walk<P, false>(g, blk.y, lv, act);
 }
 
 // ---- both colours in one pass (single precision) --------------------------------------------
@@ -480,6 +579,15 @@ hipError_t batch_resid_col(const BTable& t, int nblk, double* partial, bool cast
         hipLaunchKernelGGL(kc_resid<true>, dim3(nblk), dim3(kNT), 0, s, t, partial);
     else
         hipLaunchKernelGGL(kc_resid<false>, dim3(nblk), dim3(kNT), 0, s, t, partial);
+    return hipGetLastError();
+}
+
+hipError_t batch_resid_restrict_col(const BTable& t, int nblk, const BGrid* coarse, bool single, hipStream_t s)
+{
+    if (single)
+        hipLaunchKernelGGL(kc_resid_restrict<P32>, dim3(nblk), dim3(kNT), 0, s, t, coarse);
+    else
+        hipLaunchKernelGGL(kc_resid_restrict<P64>, dim3(nblk), dim3(kNT), 0, s, t, coarse);
     return hipGetLastError();
 }
 

@@ -157,6 +157,9 @@ hipError_t batch_ngs_col(const BTable& t, int nblk, hipStream_t s);
 // tile in partial (as batch_norm's blocks); cast: also r = -d, ub = u and e = 0 in single
 // precision (as batch_resid_cast).  d is the same, bit for bit, as theirs.
 hipError_t batch_resid_col(const BTable& t, int nblk, double* partial, bool cast, hipStream_t s);
+// Residual and restriction over the same column tiles (coarse: the coarse grids, same order):
+// as batch_resid_restrict (single: batch_resid_restrict32), the same results bit for bit.
+hipError_t batch_resid_restrict_col(const BTable& t, int nblk, const BGrid* coarse, bool single, hipStream_t s);
 hipError_t batch_ngs32_col(const BTable& t, int nblk, hipStream_t s);
 // Two single-precision sweeps of unit levels (side >= 32, e32b set), each with both colours
 // in one pass over the same column tiles (the fused tile sweep of the domain solve): e32 into
