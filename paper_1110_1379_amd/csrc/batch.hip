@@ -987,11 +987,25 @@ struct Batch {
             MGFR_TRY(resid_restrict(D.rr, false));
             MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs(utab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs"));
         }
-        if (D.ntail > 0)  // every tail level has side W
+        // The tails (every tail level has side W) touch only their own units: while other
+        // units go deeper they run on the tail stream, joined before the prolongation.
+        const bool deeper = (size_t)m + 1 < up.depth.size();
+        const bool fork = D.ntail > 0 && deeper && m < mgfr_ctx::kTailForks;
+        if (D.ntail > 0) {
+            hipStream_t ts = s;
+            if (fork) {
+                MGFR_TRY(ensure_tail(c));
+                MGFR_TRY(hip_check(c, hipEventRecord(c->ev_tf[m], s), "hipEventRecord"));
+                MGFR_TRY(hip_check(c, hipStreamWaitEvent(c->tail, c->ev_tf[m], 0), "hipStreamWaitEvent"));
+                ts = c->tail;
+            }
             MGFR_TRY(hip_check(c, mgfr::unit_tail(uset(), (const int2*)(dmeta + D.tails), D.ntail, W, dactive, ucfg(),
-                                                  mixed, s),
+                                                  mixed, ts),
                                "unit_tail"));
-        if ((size_t)m + 1 < up.depth.size()) MGFR_TRY(uvcycle(m + 1, mixed));
+            if (fork) MGFR_TRY(hip_check(c, hipEventRecord(c->ev_tj[m], c->tail), "hipEventRecord"));
+        }
+        if (deeper) MGFR_TRY(uvcycle(m + 1, mixed));
+        if (fork) MGFR_TRY(hip_check(c, hipStreamWaitEvent(s, c->ev_tj[m], 0), "hipStreamWaitEvent"));
         if (mixed) {
             MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff32(utab(D.coarse_c), D.coarse_c.nblk, s),
                                "batch_coarse_diff32"));

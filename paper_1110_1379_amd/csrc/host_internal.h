@@ -167,6 +167,11 @@ struct mgfr_ctx {
     // beside the launches of the large units, and the events that fork and join it
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // and a third (default priority) for the one-workgroup tails of the large units that end
+    // at a depth while others go deeper: per depth, the events that fork and join it
+    static constexpr int kTailForks = 16;
+    hipStream_t tail = nullptr;
+    hipEvent_t ev_tf[kTailForks] = {}, ev_tj[kTailForks] = {};
     // mg_fr_solve_noalloc: this device's address of the library's fixed scratch array (null if
     // it could not be resolved) and the host side of its reductions
     void* fixed_scratch = nullptr;
@@ -318,6 +323,26 @@ inline int ensure_side(mgfr_ctx* c)
     if (!c->ev_join && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         c->ev_join = nullptr;
         return c->fail(MGFR_EDEVICE, "hipEventCreate failed");
+    }
+    return MGFR_OK;
+}
+
+// The tail stream and its per-depth fork/join events (created once per context).
+inline int ensure_tail(mgfr_ctx* c)
+{
+    if (!c->tail && hipStreamCreateWithFlags(&c->tail, hipStreamNonBlocking) != hipSuccess) {
+        c->tail = nullptr;
+        return c->fail(MGFR_EDEVICE, "hipStreamCreate failed");
+    }
+    for (int d = 0; d < mgfr_ctx::kTailForks; ++d) {
+        if (!c->ev_tf[d] && hipEventCreateWithFlags(&c->ev_tf[d], hipEventDisableTiming) != hipSuccess) {
+            c->ev_tf[d] = nullptr;
+            return c->fail(MGFR_EDEVICE, "hipEventCreate failed");
+        }
+        if (!c->ev_tj[d] && hipEventCreateWithFlags(&c->ev_tj[d], hipEventDisableTiming) != hipSuccess) {
+            c->ev_tj[d] = nullptr;
+            return c->fail(MGFR_EDEVICE, "hipEventCreate failed");
+        }
     }
     return MGFR_OK;
 }

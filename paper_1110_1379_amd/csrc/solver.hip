@@ -368,6 +368,11 @@ void mgfr_destroy(mgfr_ctx* c)
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->side) (void)hipStreamDestroy(c->side);
+    for (int d = 0; d < mgfr_ctx::kTailForks; ++d) {
+        if (c->ev_tf[d]) (void)hipEventDestroy(c->ev_tf[d]);
+        if (c->ev_tj[d]) (void)hipEventDestroy(c->ev_tj[d]);
+    }
+    if (c->tail) (void)hipStreamDestroy(c->tail);
     c->drop_graph();
     if (c->dcap) (void)hipStreamDestroy(c->dcap);
     (void)hipFree(c->gstate);
