@@ -465,6 +465,9 @@ constexpr int cube(int s) { return s * s * s; }
 
 // workgroup size of the resident kernels of side W
 constexpr int res_threads(int W) { return W >= 16 ? 512 : 256; }
+// The tails relax one unit's lower levels per launch (no persistent loop): twice the threads,
+// for more waves to hide the LDS and arithmetic latency of their sweeps.
+constexpr int tail_threads(int W) { return W >= 16 ? 1024 : res_threads(W); }
 
 // element offsets of level d in the LDS array (double precision: top u, b, f; below + uh;
 // every level its boundary values fc [6][s][s])
@@ -579,29 +582,44 @@ __device__ void rsweep64(const BGrid& g, double* u, double* b, const double* f, 
     __syncthreads();
 }
 
-// coarse u = uh = R u, b = exp(u), f = R d; then f = L^H(uh) - f
+
+// coarse u = uh = R u, b = exp(u), f = R d; then f = L^H(uh) - f.  Rounds of NT fine cells
+// (whole slabs of coarse cells: NT is a multiple of 2 n^2, or the level fits one round):
+// every thread evaluates one fine residual into red (NT entries), then each coarse cell of
+// the round sums its eight children in (i, j, k) order.
 template <int NT>
-__device__ void rcoarsen64(const BGrid& g, const BGrid& c, double* lds, const Off64& a, const Off64& z)
+__device__ void rcoarsen64(const BGrid& g, const BGrid& c, double* lds, const Off64& a, const Off64& z, double* red)
 {
     const int ncc = 1 << (3 * c.lg);
-    for (int qc = threadIdx.x; qc < ncc; qc += NT) {
-        int I, J, K;
-        cell_of(c, qc, I, J, K);
-        double su = 0.0, sd = 0.0;
-        for (int x = 0; x < 2; ++x)
-            for (int y = 0; y < 2; ++y)
-                for (int w = 0; w < 2; ++w) {
-                    const int i = 2 * I + x, j = 2 * J + y, k = 2 * K + w;
-                    const int q = (int)idx3(g.lg, i, j, k);
-                    su += lds[a.u + q];
-                    sd += rcell64(g, lds + a.u, lds + a.b, lds + a.fc, i, j, k, lds[a.f + q]).L;
-                }
-        lds[z.u + qc] = 0.125 * su;
-        lds[z.uh + qc] = 0.125 * su;
-        lds[z.b + qc] = exp(0.125 * su);
-        lds[z.f + qc] = 0.125 * sd;
+    const int nf = 1 << (3 * g.lg);
+    for (int r0 = 0; r0 < nf; r0 += NT) {
+        const int q = r0 + (int)threadIdx.x;
+        if (q < nf) {
+            int i, j, k;
+            cell_of(g, q, i, j, k);
+            red[threadIdx.x] = rcell64(g, lds + a.u, lds + a.b, lds + a.fc, i, j, k, lds[a.f + q]).L;
+        }
+        __syncthreads();
+        const int nct = min(NT, nf - r0) / 8;
+        for (int t = threadIdx.x; t < nct; t += NT) {
+            const int qc = r0 / 8 + t;
+            int I, J, K;
+            cell_of(c, qc, I, J, K);
+            double su = 0.0, sd = 0.0;
+            for (int x = 0; x < 2; ++x)
+                for (int y = 0; y < 2; ++y)
+                    for (int w = 0; w < 2; ++w) {
+                        const int qf = (int)idx3(g.lg, 2 * I + x, 2 * J + y, 2 * K + w);
+                        su += lds[a.u + qf];
+                        sd += red[qf - r0];
+                    }
+            lds[z.u + qc] = 0.125 * su;
+            lds[z.uh + qc] = 0.125 * su;
+            lds[z.b + qc] = exp(0.125 * su);
+            lds[z.f + qc] = 0.125 * sd;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int q = threadIdx.x; q < ncc; q += NT) {
         int i, j, k;
         cell_of(c, q, i, j, k);
@@ -659,13 +677,15 @@ __device__ double rrms64(const BGrid& g, double* lds, const Off64& a, double* re
 template <int W, int NT>
 __device__ void rvcycle64(const BGrid* G, int nl, const UnitCfg& cfg, double* lds, double* cS, double* ra, double* rb)
 {
+    // the restriction rounds: whole slabs of coarse cells per NT fine cells on every level
+    static_assert(NT >= 2 * W * W && NT % (2 * W * W) == 0, "NT threads per resident workgroup");
     for (int d = 0; d + 1 < nl; ++d) {
         const Off64 a = off64<W>(d), z = off64<W>(d + 1);
         for (int s = 0; s < cfg.pre; ++s) {
             rsweep64<NT>(G[d], lds + a.u, lds + a.b, lds + a.f, lds + a.fc, 0);
             rsweep64<NT>(G[d], lds + a.u, lds + a.b, lds + a.f, lds + a.fc, 1);
         }
-        rcoarsen64<NT>(G[d], G[d + 1], lds, a, z);
+        rcoarsen64<NT>(G[d], G[d + 1], lds, a, z, ra);
     }
     {
         const BGrid& g = G[nl - 1];
@@ -748,10 +768,10 @@ __global__ void __launch_bounds__(res_threads(W)) kr_whole64(UnitSet us, int beg
 }
 
 template <int W>
-__global__ void __launch_bounds__(res_threads(W)) kr_tail64(UnitSet us, const int2* __restrict__ tails,
-                                                           const int* __restrict__ active, UnitCfg cfg)
+__global__ void __launch_bounds__(tail_threads(W)) kr_tail64(UnitSet us, const int2* __restrict__ tails,
+                                                            const int* __restrict__ active, UnitCfg cfg)
 {
-    constexpr int NT = res_threads(W);
+    constexpr int NT = tail_threads(W);
     __shared__ double lds[res64_size<W>()];
     __shared__ double cS[cube(W < 8 ? W : 8)];
     __shared__ double ra[NT], rb[NT];
@@ -825,30 +845,43 @@ __device__ void rsweep32(const BGrid& g, float* lds, const Off32& a, int colour)
     __syncthreads();
 }
 
-// coarse e = eh = R e, f = R N; then f = N^H(eh) - f
+
+// coarse e = eh = R e, f = R N; then f = N^H(eh) - f (red: NT entries, as in rcoarsen64)
 template <int NT>
-__device__ void rcoarsen32(const BGrid& g, const BGrid& c, float* lds, const Off32& a, const Off32& z)
+__device__ void rcoarsen32(const BGrid& g, const BGrid& c, float* lds, const Off32& a, const Off32& z, float* red)
 {
     const Op32 o = op32(g), oc = op32(c);
     const int ncc = 1 << (3 * c.lg);
-    for (int qc = threadIdx.x; qc < ncc; qc += NT) {
-        int I, J, K;
-        cell_of(c, qc, I, J, K);
-        float se = 0.0f, sd = 0.0f;
-        for (int x = 0; x < 2; ++x)
-            for (int y = 0; y < 2; ++y)
-                for (int w = 0; w < 2; ++w) {
-                    const int i = 2 * I + x, j = 2 * J + y, k = 2 * K + w;
-                    const int q = (int)idx3(g.lg, i, j, k);
-                    se += lds[a.e + q];
-                    sd += rcell32(g, o, lds + a.ub, lds + a.e, lds + a.b, lds + a.S, lds + a.fc, i, j, k,
-                                  lds[a.f + q]).N;
-                }
-        lds[z.e + qc] = 0.125f * se;
-        lds[z.eh + qc] = 0.125f * se;
-        lds[z.f + qc] = 0.125f * sd;
+    const int nf = 1 << (3 * g.lg);
+    // as rcoarsen64: the fine residuals of a round of whole coarse slabs, one per thread
+    for (int r0 = 0; r0 < nf; r0 += NT) {
+        const int q = r0 + (int)threadIdx.x;
+        if (q < nf) {
+            int i, j, k;
+            cell_of(g, q, i, j, k);
+            red[threadIdx.x] =
+                rcell32(g, o, lds + a.ub, lds + a.e, lds + a.b, lds + a.S, lds + a.fc, i, j, k, lds[a.f + q]).N;
+        }
+        __syncthreads();
+        const int nct = min(NT, nf - r0) / 8;
+        for (int t = threadIdx.x; t < nct; t += NT) {
+            const int qc = r0 / 8 + t;
+            int I, J, K;
+            cell_of(c, qc, I, J, K);
+            float se = 0.0f, sd = 0.0f;
+            for (int x = 0; x < 2; ++x)
+                for (int y = 0; y < 2; ++y)
+                    for (int w = 0; w < 2; ++w) {
+                        const int qf = (int)idx3(g.lg, 2 * I + x, 2 * J + y, 2 * K + w);
+                        se += lds[a.e + qf];
+                        sd += red[qf - r0];
+                    }
+            lds[z.e + qc] = 0.125f * se;
+            lds[z.eh + qc] = 0.125f * se;
+            lds[z.f + qc] = 0.125f * sd;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int q = threadIdx.x; q < ncc; q += NT) {
         int i, j, k;
         cell_of(c, q, i, j, k);
@@ -936,13 +969,15 @@ struct R32Co {
 template <int W, int NT>
 __device__ void rvcycle32(const BGrid* G, int nl, const UnitCfg& cfg, float* lds, const R32Co& co)
 {
+    // the restriction rounds: whole slabs of coarse cells per NT fine cells on every level
+    static_assert(NT >= 2 * W * W && NT % (2 * W * W) == 0, "NT threads per resident workgroup");
     for (int d = 0; d + 1 < nl; ++d) {
         const Off32 a = off32<W>(d), z = off32<W>(d + 1);
         for (int s = 0; s < cfg.pre; ++s) {
             rsweep32<NT>(G[d], lds, a, 0);
             rsweep32<NT>(G[d], lds, a, 1);
         }
-        rcoarsen32<NT>(G[d], G[d + 1], lds, a, z);
+        rcoarsen32<NT>(G[d], G[d + 1], lds, a, z, co.ra);
     }
     {
         const BGrid& g = G[nl - 1];
@@ -1006,8 +1041,8 @@ __device__ double rresid_cast(const BGrid& g, float* lds, double* red)
     return sqrt(wg_sum_t<NT>(s, red) / (double)nf);
 }
 
-#define MGFR_R32_LDS(W)                                \
-    constexpr int NT = res_threads(W);                 \
+#define MGFR_R32_LDS(W, NTV)                           \
+    constexpr int NT = NTV;                            \
     __shared__ float lds[res32_size<W>()];             \
     constexpr int NC = cube(W < 8 ? W : 8);            \
     __shared__ float cB[NC], cM[NC], gdu[6 * 512], gbb[6 * 512]; \
@@ -1018,7 +1053,7 @@ template <int W>
 __global__ void __launch_bounds__(res_threads(W)) kr_whole_mixed(UnitSet us, int begin, int end, int* queue,
                                                                 UnitOut out, UnitCfg cfg)
 {
-    MGFR_R32_LDS(W)
+    MGFR_R32_LDS(W, res_threads(W))
     __shared__ double red[NT];
     __shared__ int slot;
     for (;;) {
@@ -1049,10 +1084,10 @@ __global__ void __launch_bounds__(res_threads(W)) kr_whole_mixed(UnitSet us, int
 }
 
 template <int W>
-__global__ void __launch_bounds__(res_threads(W)) kr_tail32(UnitSet us, const int2* __restrict__ tails,
-                                                           const int* __restrict__ active, UnitCfg cfg)
+__global__ void __launch_bounds__(tail_threads(W)) kr_tail32(UnitSet us, const int2* __restrict__ tails,
+                                                            const int* __restrict__ active, UnitCfg cfg)
 {
-    MGFR_R32_LDS(W)
+    MGFR_R32_LDS(W, tail_threads(W))
     const int2 t = tails[blockIdx.x];
     const BGrid* G = us.grids + t.x;
     if (!active[G[0].unit]) return;
@@ -1098,9 +1133,9 @@ hipError_t tail_resident(const UnitSet& us, const int2* tails, int ntail, const 
                          bool mixed, hipStream_t s)
 {
     if (mixed)
-        hipLaunchKernelGGL(kr_tail32<W>, dim3(ntail), dim3(res_threads(W)), 0, s, us, tails, active, cfg);
+        hipLaunchKernelGGL(kr_tail32<W>, dim3(ntail), dim3(tail_threads(W)), 0, s, us, tails, active, cfg);
     else
-        hipLaunchKernelGGL(kr_tail64<W>, dim3(ntail), dim3(res_threads(W)), 0, s, us, tails, active, cfg);
+        hipLaunchKernelGGL(kr_tail64<W>, dim3(ntail), dim3(tail_threads(W)), 0, s, us, tails, active, cfg);
     return hipGetLastError();
 }
 
