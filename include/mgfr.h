@@ -106,12 +106,14 @@ typedef struct mgfr_opts {
                              Batched solves, launched sweeps of unit levels of side >=
                              32: 0 = automatic: periodic boxes walk 16 x 32 column tiles
                              (16 planes per workgroup), a mixed solve in pairs of fused
-                             two-colour sweeps, double precision one colour per launch;
+                             two-colour sweeps, double precision one colour per launch,
+                             at multigrid depths with at least 256 such tiles in the
+                             batch (one thread per cell of the colour at the others);
                              patches run one thread per cell of the colour; 1 = one
                              thread per cell everywhere; 2 = column tiles one colour per
-                             launch everywhere; 3 = as 0, and mixed solves sweep patches
-                             in fused pairs too (8 planes per workgroup); 4, 5 as 0 (all
-                             give the same results, bit for bit)                  [0]      */
+                             launch everywhere; 3 = fused pairs at every depth, for
+                             patches too (8 planes per workgroup) in mixed solves; 4, 5
+                             as 0 (all give the same results, bit for bit)        [0]      */
 } mgfr_opts;
 
 /* One refinement patch: a cube of n^3 cells at refinement level `level` >= 1 (cell size

@@ -22,6 +22,7 @@ using namespace mgfr_host;
 
 namespace {
 
+constexpr int kMinTiles = 256;  // automatic sweep form: column tiles from this many per depth
 constexpr int kQueues = 12;  // whole-unit launches per batch, at most one per unit side (2 ... 1024)
 
 struct Unit {
@@ -215,8 +216,23 @@ Sweep sweep_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, int tile)
 {
     std::vector<mgfr::BGrid> cell, col, pair[2];
     std::vector<int2> bcol, bpair[2], bpair1[2];
+    // Automatic choice: tiles only for a depth that has at least one per compute unit.  A
+    // tile's walk is a chain of barrier-separated plane steps; with fewer tiles than CUs the
+    // one-thread-per-cell launches finish sooner (16 boxes of 32^3: 64 tiles take 22 us per
+    // fused sweep, the two per-cell colour launches 12 us).
+    bool few = false;
+    if (tile != 1 && tile != 2 && tile != 3) {
+        long long total = 0;
+        for (const mgfr::BGrid& g : f)
+            if (g.periodic || g.e32b) total += mgfr::batch_col_tiles(g.n);
+        few = total < kMinTiles;
+    }
     for (const mgfr::BGrid& g : f) {
         const long long nt = mgfr::batch_col_tiles(g.n), np = mgfr::batch_pair_tiles(g.n, g.periodic);
+        if (few) {
+            cell.push_back(g);
+            continue;
+        }
         if (g.e32b && nt > 0 && np > 0) {
             const int w = g.periodic ? 1 : 0;
             for (long long b = 0; b < np; ++b) bpair[w].push_back(make_int2((int)pair[w].size(), (int)b));

@@ -295,12 +295,13 @@ def check_profile(mg, ctx, opts, sides, hists):
 def test_column_sweep_matches_per_cell_sweep(mg, ctx, precision, engine):
     """The sweeps of unit levels of side >= 32 walk column tiles: by default (tile = 0) a mixed
     solve sweeps periodic boxes in pairs of fused two-colour sweeps and a double-precision one
-    walks them one colour per launch; tile = 3 also sweeps patches in fused pairs, and tile = 2
-    walks every level one colour per launch; with tile = 1 they run one thread per cell of the
-    colour.  All evaluate every cell update with the same operands in the same order, so
-    fields and residual histories agree bit for bit: periodic boxes of sides 32 - 128 (also
-    with odd sweep counts, where one sweep of a group runs in place), and patches of side 32
-    and 64 (ghost faces)."""
+    walks them one colour per launch, at depths with at least 256 tiles (per cell below);
+    tile = 3 sweeps boxes and patches in fused pairs at every depth, and tile = 2 walks every
+    level one colour per launch; with tile = 1 they run one thread per cell of the colour.
+    All evaluate every cell update with the same operands in the same order, so fields and
+    residual histories agree bit for bit: periodic boxes of sides 32 - 128 (also with odd
+    sweep counts, where one sweep of a group runs in place), and patches of side 32 and 64
+    (ghost faces)."""
     say(f"[column sweep] {precision} engine={engine[0]}")
     prec = mg.MGFR_MIXED if precision == "mixed" else mg.MGFR_FP64
     tol = 1e-8 if precision == "mixed" else 1e-10
@@ -312,16 +313,17 @@ def test_column_sweep_matches_per_cell_sweep(mg, ctx, precision, engine):
     params = [mg.Params(box_mpc_h=s[1], fr0_abs=s[2]) for s in specs]
     for pre, post in ((2, 2), (1, 3)):
         out = []
-        for tile in (0, 1):
+        for tile in (1, 0, 2, 3):
             opts = mg.mgfr_default_opts(tol=tol, precision=prec, flags=engine[1], unit_n=engine[2], tile=tile,
                                         pre=pre, post=post)
             us, hists, st = mg.mg_fr_solve_batch(ctx, rhos, params, opts)
             assert st == mg.MGFR_OK, ctx.last_error()
             out.append(([u.cpu().numpy() for u in us], [np.asarray(h) for h in hists]))
-        for a, b in zip(out[0][0], out[1][0]):
-            assert np.array_equal(a, b)
-        for a, b in zip(out[0][1], out[1][1]):
-            assert np.array_equal(a, b)
+        for o in out[1:]:
+            for a, b in zip(o[0], out[0][0]):
+                assert np.array_equal(a, b)
+            for a, b in zip(o[1], out[0][1]):
+                assert np.array_equal(a, b)
     ud, patches, rho_packed, p, _ = patch_case(mg, ctx, 64, (3.0, 10.0), (32, 16, 8, 4), 1e-10)
     assert {q["n"] for q in patches} >= {32, 64}
     res = []
