@@ -43,7 +43,7 @@ MEASURED_TRAFFIC = {
     "mixed": {"points": [({"planes": 64, "tile": 3}, 3.5597e9), ({"planes": 32, "tile": 3}, 3.0682e9)],
               "sources": {
                   "kernels_fp32.hip": "3e2d5fa7b74c8e9e8695fb1c7fd7f008127e8b020b552ac5893de6581d7cd948",
-                  "fused_fp32.h": "fce16a9bef4d9388e9a6989bb8ef11d68ccff8034c97859cecce07499f2cc8e4",
+                  "fused_fp32.h": "b9ed53a6627e0abd80a493c36476053bfd8d2a934debc47118343d03e6ed03ca",
                   "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
                   "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
     # per finest launch (one red-black sweep, 16 x 64 tiles, 128 planes per workgroup)

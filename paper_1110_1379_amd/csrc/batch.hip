@@ -60,7 +60,20 @@ struct Launch {
 struct Sweep {
     Launch cell, col;
     Launch pair[2], pair1[2];  // [periodic] fused pairs; pair1: their grids as column tiles (an odd sweep)
+    std::vector<const double*> box_pairs;  // u of the periodic grids swept in fused pairs
 };
+
+// The finest grids whose correction a separate u += e must add: all of them, unless the
+// last post-smoothing sweep adds it (an even number of post sweeps >= 2 of a mixed solve;
+// then all but the boxes that depth 0 sweeps in fused pairs).
+std::vector<mgfr::BGrid> add_rest(const std::vector<mgfr::BGrid>& g0, const Sweep* S0, bool fuse)
+{
+    std::vector<mgfr::BGrid> rest;
+    for (const mgfr::BGrid& g : g0)
+        if (!fuse || !S0 || std::find(S0->box_pairs.begin(), S0->box_pairs.end(), g.u) == S0->box_pairs.end())
+            rest.push_back(g);
+    return rest;
+}
 
 // Residual and restriction of one depth: column tiles over the fine grids that take them,
 // one thread per coarse cell for the rest; each with its coarse grids (other, same order).
@@ -88,6 +101,8 @@ struct NormPlan {
 struct Plan {
     std::vector<Depth> depth;
     Launch cells0, setup;
+    Launch add0;                  // finest grids of the separate u += e (add_rest)
+    bool fuse_add = false;        // the last post sweep of a correction solve adds it for the others
     size_t first = 0, count = 0;  // per-unit block ranges of cells0 (for the non-finite fold)
     NormPlan norm;
     int nunit = 0;
@@ -114,6 +129,7 @@ struct UPlan {
     std::vector<int3> ranges;          // whole units: (begin, end, side) in queue order, one launch each
     size_t ids = 0, ncell = 0;        // large units: unit index, finest cells
     Launch cells0;                     // finest cells of the large units
+    Launch add0;                       // of those, the grids of the separate u += e (add_rest)
     NormPlan norm;                     // their residual
     size_t all_tails = 0;              // every large unit's tail (for the tail bases)
     int nall_tails = 0;
@@ -216,6 +232,7 @@ Sweep sweep_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, int tile)
 {
     std::vector<mgfr::BGrid> cell, col, pair[2];
     std::vector<int2> bcol, bpair[2], bpair1[2];
+    std::vector<const double*> box_u;
     // Automatic choice: tiles only for a depth that has at least one per compute unit.  A
     // tile's walk is a chain of barrier-separated plane steps; with fewer tiles than CUs the
     // one-thread-per-cell launches finish sooner (16 boxes of 32^3: 64 tiles take 22 us per
@@ -238,6 +255,7 @@ Sweep sweep_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, int tile)
             for (long long b = 0; b < np; ++b) bpair[w].push_back(make_int2((int)pair[w].size(), (int)b));
             for (long long b = 0; b < nt; ++b) bpair1[w].push_back(make_int2((int)pair[w].size(), (int)b));
             pair[w].push_back(g);
+            if (g.periodic) box_u.push_back(g.u);
             continue;
         }
         const bool want = tile == 2 || (tile != 1 && g.periodic);
@@ -261,6 +279,7 @@ Sweep sweep_tables(Meta& meta, const std::vector<mgfr::BGrid>& f, int tile)
         tiles(S.pair[w], pair[w], bpair[w]);
         tiles(S.pair1[w], pair[w], bpair1[w]);
     }
+    S.box_pairs = std::move(box_u);
     return S;
 }
 
@@ -465,6 +484,10 @@ struct Batch {
         for (Unit& U : units) g0.push_back(U.g[0]);
         std::vector<int> first, count;
         plan.cells0 = table(meta, g0, [](const mgfr::BGrid& g) { return cells3(g); }, &first, &count);
+        plan.fuse_add = o->precision == MGFR_MIXED && o->post >= 2 && o->post % 2 == 0;
+        plan.add0 = table(meta, add_rest(g0, plan.depth.empty() || !plan.depth[0].deep ? nullptr : &plan.depth[0].half,
+                                         plan.fuse_add),
+                          [](const mgfr::BGrid& g) { return cells3(g); });
         plan.first = meta.add(first);
         plan.count = meta.add(count);
         plan.norm = norm_tables(meta, g0);
@@ -545,6 +568,8 @@ struct Batch {
         }
         up.all_tails = meta.add(all_tails);
         up.nall_tails = (int)all_tails.size();
+        up.add0 = table(meta, add_rest(g0, up.depth.empty() ? nullptr : &up.depth[0].half, plan.fuse_add),
+                        [](const mgfr::BGrid& g) { return cells3(g); });
     }
 
     std::vector<char> meta_image;
@@ -649,8 +674,9 @@ struct Batch {
     }
 
     // `count` red-black sweeps of a depth's grids (grids are independent: the tables in turn);
-    // the number of kernel launches in *launches.
-    int ngs(const Sweep& S, bool mixed, int count, int* launches)
+    // the number of kernel launches in *launches.  add_u (an even count): the last sweep of
+    // the boxes swept in fused pairs also adds their correction, u += e.
+    int ngs(const Sweep& S, bool mixed, int count, int* launches, bool add_u = false)
     {
         int nl = 0;
         for (int k = 0; k < count; ++k) {
@@ -673,7 +699,8 @@ struct Batch {
             if (S.pair[w].nblk == 0) continue;
             // pairs of fused sweeps end where they began (e32); an odd one out runs in place
             for (int k = 0; k + 2 <= count; k += 2) {
-                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_pair(tab(S.pair[w]), S.pair[w].nblk, w == 1, s),
+                const bool add = add_u && w == 1 && k + 2 == count && !(count & 1);
+                MGFR_TRY(hip_check(c, mgfr::batch_ngs32_pair(tab(S.pair[w]), S.pair[w].nblk, w == 1, add, s),
                                    "batch_ngs32_pair"));
                 nl += 2;
             }
@@ -740,17 +767,19 @@ struct Batch {
     // ---- mixed precision: single-precision correction V-cycle, double-precision outer loop
     // credited 12 B per cell: e and the right-hand side read, e written (the fixed base ub,
     // also read, is not counted)
-    int sweep32(int m, int count)
+    int sweep32(int m, int count, bool add_u = false)
     {
         if (count == 0) return MGFR_OK;
         const Depth& D = plan.depth[m];
         int nl = 0;
         MGFR_TRY(ev_begin(m));
-        MGFR_TRY(ngs(D.half, true, count, &nl));
+        MGFR_TRY(ngs(D.half, true, count, &nl, add_u));
         return ev_end(m, 12.0, count, nl);
     }
 
-    int vcycle32(int m)
+    // add_u: the last correction cycle of an outer iteration (its last finest sweep adds u += e
+    // for the boxes swept in fused pairs)
+    int vcycle32(int m, bool add_u = false)
     {
         const Depth& D = plan.depth[m];
         if (D.coarsest)
@@ -766,7 +795,7 @@ struct Batch {
         MGFR_TRY(hip_check(c, mgfr::batch_prolong_add32(tab(D.fine_f), D.fine_f.nblk,
                                                         (const mgfr::BGrid*)(dmeta + D.fine_f.other), s),
                            "batch_prolong_add32"));
-        MGFR_TRY(sweep32(m, o->post));
+        MGFR_TRY(sweep32(m, o->post, add_u && m == 0 && plan.fuse_add));
         return MGFR_OK;
     }
 
@@ -867,8 +896,9 @@ struct Batch {
     {
         if (o->precision != MGFR_MIXED) return vcycle(0);
         MGFR_TRY(restrict_base32());
-        for (int it = 0; it < o->inner_cycles; ++it) MGFR_TRY(vcycle32(0));
-        return hip_check(c, mgfr::batch_add_correction(tab(plan.cells0), plan.cells0.nblk, s), "batch_add_correction");
+        for (int it = 0; it < o->inner_cycles; ++it) MGFR_TRY(vcycle32(0, it + 1 == o->inner_cycles));
+        if (plan.add0.nblk == 0) return MGFR_OK;
+        return hip_check(c, mgfr::batch_add_correction(tab(plan.add0), plan.add0.nblk, s), "batch_add_correction");
     }
 
     // With MGFR_GRAPH, the body is captured once on a private stream and the graph is
@@ -991,7 +1021,7 @@ struct Batch {
     // one V-cycle of the large units from depth m (double precision, or the single-precision
     // correction cycle when mixed): launch-based phases while their level is larger than W,
     // then one workgroup per unit for the rest
-    int uvcycle(int m, bool mixed)
+    int uvcycle(int m, bool mixed, bool add_u = false)
     {
         const UDepth& D = up.depth[m];
         const mgfr::BGrid* coarse = (const mgfr::BGrid*)(dmeta + D.coarse_f.other);
@@ -1032,18 +1062,18 @@ struct Batch {
             MGFR_TRY(hip_check(c, mgfr::batch_prolong_add(utab(D.fine_f), D.fine_f.nblk, coarse, s),
                                "batch_prolong_add"));
         }
-        MGFR_TRY(usweep(m, mixed, o->post));
+        MGFR_TRY(usweep(m, mixed, o->post, mixed && add_u && m == 0 && plan.fuse_add));
         return MGFR_OK;
     }
 
-    int usweep(int m, bool mixed, int count)
+    int usweep(int m, bool mixed, int count, bool add_u = false)
     {
         if (count == 0) return MGFR_OK;
         const UDepth& D = up.depth[m];
         const bool timed = m == 0 && (o->flags & MGFR_PROFILE) && !(o->flags & MGFR_GRAPH);
         if (timed) MGFR_TRY(ev_begin(0));
         int nl = 0;
-        MGFR_TRY(ngs(D.half, mixed, count, &nl));
+        MGFR_TRY(ngs(D.half, mixed, count, &nl, add_u));
         if (timed) {
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
             c->ev_used += 2;
@@ -1078,9 +1108,10 @@ struct Batch {
                 MGFR_TRY(hip_check(c, mgfr::unit_tail_base32(uset(), (const int2*)(dmeta + up.all_tails),
                                                              up.nall_tails, dactive, s),
                                    "unit_tail_base32"));
-            for (int it = 0; it < o->inner_cycles; ++it) MGFR_TRY(uvcycle(0, true));
-            MGFR_TRY(hip_check(c, mgfr::batch_add_correction(utab(up.cells0), up.cells0.nblk, s),
-                               "batch_add_correction"));
+            for (int it = 0; it < o->inner_cycles; ++it) MGFR_TRY(uvcycle(0, true, it + 1 == o->inner_cycles));
+            if (up.add0.nblk > 0)
+                MGFR_TRY(hip_check(c, mgfr::batch_add_correction(utab(up.add0), up.add0.nblk, s),
+                                   "batch_add_correction"));
         } else {
             MGFR_TRY(uvcycle(0, false));
         }

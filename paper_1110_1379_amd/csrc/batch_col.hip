@@ -507,8 +507,9 @@ __global__ void __launch_bounds__(kNT) kc_resid_restrict(BTable t, const BGrid* 
 // one buffer of e and writes the other (dir 0: e32 to e32b, dir 1: back).  Consecutive table
 // entries go to the same XCD (workgroups are dealt to the 8 XCDs in turn).
 // PER: periodic boxes, else patches (kernels of their own: the patch form's registers would
-// push the box form into spills).
-template <bool PER>
+// push the box form into spills).  ADDU (dir 1, boxes only): the last sweep of a correction
+// solve, which adds its e to u instead of writing it back.
+template <bool PER, bool ADDU = false>
 __global__ void __launch_bounds__(kNT, 4) kf32_ngs(BTable t, int dir)
 {
     __shared__ V32 lv[3][(kTJ + 4) * (kTK + 4)];
@@ -528,9 +529,11 @@ __global__ void __launch_bounds__(kNT, 4) kf32_ngs(BTable t, int dir)
     const float* ein = dir ? g.e32b : g.e32;
     float* eout = dir ? g.e32 : g.e32b;
     if (PER)
-        fused32::sweep_tile<kTJ, kTK, false>(op32(g), g.n, g.lg, i0, j0, k0, ti, g.ub32, ein, eout, g.f32, lv);
+        fused32::sweep_tile<kTJ, kTK, false, ADDU>(op32(g), g.n, g.lg, i0, j0, k0, ti, g.ub32, ein, eout, g.f32, lv,
+                                                   nullptr, g.u);
     else
-        fused32::sweep_tile<kTJ, kTK, true>(op32(g), g.n, g.lg, i0, j0, k0, ti, g.ub32, ein, eout, g.f32, lv, g.ub);
+        fused32::sweep_tile<kTJ, kTK, true, ADDU>(op32(g), g.n, g.lg, i0, j0, k0, ti, g.ub32, ein, eout, g.f32, lv,
+                                                  g.ub, g.u);
 }
 
 }  // namespace
@@ -562,13 +565,17 @@ hipError_t batch_ngs32_col(const BTable& t, int nblk, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t batch_ngs32_pair(const BTable& t, int nblk, bool periodic, hipStream_t s)
+hipError_t batch_ngs32_pair(const BTable& t, int nblk, bool periodic, bool add_u, hipStream_t s)
 {
+    if (add_u && !periodic) return hipErrorInvalidValue;  // boxes only (the patch form would spill)
     for (int dir = 0; dir < 2; ++dir) {
-        if (periodic)
+        if (dir == 1 && add_u) {
+            hipLaunchKernelGGL((kf32_ngs<true, true>), dim3(nblk), dim3(kNT), 0, s, t, dir);
+        } else if (periodic) {
             hipLaunchKernelGGL(kf32_ngs<true>, dim3(nblk), dim3(kNT), 0, s, t, dir);
-        else
+        } else {
             hipLaunchKernelGGL(kf32_ngs<false>, dim3(nblk), dim3(kNT), 0, s, t, dir);
+        }
     }
     return hipGetLastError();
 }

@@ -94,11 +94,14 @@ __device__ __forceinline__ Res32 corr_op_patch(const Op32& o, const V32& c, cons
 // (ti a multiple of 4), reading ein and writing eout (never the same array): every thread of
 // the TJ TK / 2 of the workgroup calls it, with lv its workgroup's LDS.  PATCH: the grid is a
 // patch whose boundary values are faces ([6][n][n], batch_dev.h); otherwise it is periodic.
-template <int TJ, int TK, bool PATCH = false>
+// ADDU: the sweep is the last of a correction solve; instead of writing e it adds it to the
+// double-precision field, uadd += e (each cell of the tile once, after its black update).
+template <int TJ, int TK, bool PATCH = false, bool ADDU = false>
 __device__ __forceinline__ void sweep_tile(const Op32& o, int n, int lg, int i0, int j0, int k0, int ti,
                                            const float* __restrict__ ub, const float* __restrict__ ein,
                                            float* __restrict__ eout, const float* __restrict__ f,
-                                           V32 (*lv)[(TJ + 4) * (TK + 4)], const double* __restrict__ faces = nullptr)
+                                           V32 (*lv)[(TJ + 4) * (TK + 4)], const double* __restrict__ faces = nullptr,
+                                           double* __restrict__ uadd = nullptr)
 {
     constexpr int NT = TJ * TK / 2;
     constexpr int LK = TK + 4;
@@ -254,6 +257,14 @@ __device__ __forceinline__ void sweep_tile(const Op32& o, int n, int lg, int i0,
             fetch(B);
             fetch(E);
         }
+        // ADDU: the field of this step's two output cells, loaded before the updates
+        double ua = 0.0, ubv = 0.0;
+        if constexpr (ADDU) {
+            if (p - 1 >= i0) {
+                ua = uadd[offset(p - 1, A)];
+                ubv = uadd[offset(p - 1, B)];
+            }
+        }
         V32* LA = lv[buf(p)];
         const bool pin = !PATCH || (p >= 0 && p <= m);  // a patch's planes -1 and n are not relaxed
         auto red = [&](Col& q) {
@@ -273,8 +284,13 @@ __device__ __forceinline__ void sweep_tile(const Op32& o, int n, int lg, int i0,
             const V32 nbv[6] = {A.v[M2], A.v[P0], LB[c - LK], LB[c + LK], LB[c - 1], LB[c + 1]};
             const Res32 r = op(p - 1, A, A.v[M1], nbv, A.f[M1]);
             A.v[M1].e = A.v[M1].e + newton32(r, o.max_step);
-            eout[offset(p - 1, A)] = A.v[M1].e;
-            eout[offset(p - 1, B)] = B.v[M1].e;
+            if constexpr (ADDU) {
+                uadd[offset(p - 1, A)] = ua + (double)A.v[M1].e;
+                uadd[offset(p - 1, B)] = ubv + (double)B.v[M1].e;
+            } else {
+                eout[offset(p - 1, A)] = A.v[M1].e;
+                eout[offset(p - 1, B)] = B.v[M1].e;
+            }
         }
         V32* LC = lv[buf(p + 1)];
         const bool more2 = p + 2 <= last;

@@ -166,8 +166,12 @@ hipError_t batch_ngs32_col(const BTable& t, int nblk, hipStream_t s);
 // e32b, then back.  Same results, bit for bit, as two batch_ngs32 sweeps.
 // Its table: blk[b] = (grid, tile), tiles of 16 x 32 cells by 16 planes (periodic) or 8 planes
 // (patch), every grid of the table periodic or every one a patch, as `periodic` says;
-// batch_pair_tiles gives their number, 0 where the side does not allow them.
-hipError_t batch_ngs32_pair(const BTable& t, int nblk, bool periodic, hipStream_t s);
+// batch_pair_tiles gives their number, 0 where the side does not allow them.  add_u
+// (periodic tables only, else hipErrorInvalidValue): the second sweep ends a correction solve
+// and adds its e to the grids' u (double precision) instead of writing e32 (as a
+// batch_add_correction of those grids after it would, bit for bit); e32 keeps the first
+// sweep's input.
+hipError_t batch_ngs32_pair(const BTable& t, int nblk, bool periodic, bool add_u, hipStream_t s);
 long long batch_pair_tiles(int n, int periodic);
 hipError_t batch_resid_restrict(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
 hipError_t batch_fas_rhs(const BTable& t, int nblk, hipStream_t s);
