@@ -63,6 +63,39 @@ MEASURED_TRAFFIC = {
 }
 
 
+# HBM bytes per finest-level sweep launch of the batch workload (workgroup-per-unit engine,
+# automatic sweep form), averaged over the launches of one solve (FETCH_SIZE x 2 + WRITE_SIZE,
+# copy-calibrated): mixed, the fused two-colour launches (the last of each outer iteration also
+# adds u += e); FP64, the one-colour launches
+BATCH_TRAFFIC = {
+    "mixed": {"bytes": 0.4714e9, "sources": {
+        "batch_col.hip": "1c3ac948bf60869a2c8ef3224e9c0f6d227552121414c5f25f895ad53f76efdd",
+        "batch.hip": "f2316d52fc5bfbfd4dd03e9a420fd395bda5810b55236e1e35cd4a6da901bba5",
+        "fused_fp32.h": "b9ed53a6627e0abd80a493c36476053bfd8d2a934debc47118343d03e6ed03ca",
+        "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
+        "batch_dev.h": "de43e35ad4c4670dc0ee3196ac06e4ee6a59cd2320f45743b1b175dbf70de6f3"}},
+    "fp64": {"bytes": 0.7707e9, "sources": {
+        "batch_col.hip": "1c3ac948bf60869a2c8ef3224e9c0f6d227552121414c5f25f895ad53f76efdd",
+        "batch.hip": "f2316d52fc5bfbfd4dd03e9a420fd395bda5810b55236e1e35cd4a6da901bba5",
+        "batch_dev.h": "de43e35ad4c4670dc0ee3196ac06e4ee6a59cd2320f45743b1b175dbf70de6f3"}},
+}
+
+
+def batch_traffic(prec):
+    """Measured bytes per finest sweep launch of the batch workload, if the counters describe
+    the kernels and tables built from these sources."""
+    import hashlib
+    entry = BATCH_TRAFFIC.get(prec)
+    if entry is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_1110_1379_amd", "csrc")
+    for name, digest in entry["sources"].items():
+        with open(os.path.join(csrc, name), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
+                return None
+    return entry["bytes"]
+
+
 def _tile_shape(prec, tile):
     """Tile shape a finest-level sweep setting selects (0 is the automatic choice)."""
     if prec == "fp64":
@@ -845,7 +878,20 @@ def bench_batch(args):
     out.update(runs)
     if per_phase:
         out["per_phase_engine"] = per_phase
-    out["roofline"] = _batched_roofline(profiled[headp](), headp, args.unit_n, args.engine == "phases")
+    roof = _batched_roofline(profiled[headp](), headp, args.unit_n, args.engine == "phases")
+    if args.engine != "phases" and args.batch_sweep_tile == 0 and args.unit_n == 0 and not args.graph:
+        t = batch_traffic(headp)
+        if t is not None and roof["achieved"]:
+            algo = roof["achieved"] * 1e9 * roof["avg_launch_ms"] * 1e-3
+            roof["traffic"] = t
+            roof["traffic_over_algorithmic"] = t / algo
+            roof["traffic_note"] = ("HBM bytes per finest sweep launch averaged over one solve's launches "
+                                    "(rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE, copy-calibrated); algorithmic: "
+                                    f"{roof['bytes_per_cell']} B per updated cell" +
+                                    ("; the last fused launch of each outer iteration also reads and writes u "
+                                     "(u += e)" if headp == "mixed" else "; a colour launch writes whole "
+                                     "cache lines of u and reads u and rho whole"))
+    out["roofline"] = roof
     if len(runs) == 2:
         out["speedup_mixed_over_fp64"] = runs["fp64"]["ms_per_step"] / runs["mixed"]["ms_per_step"]
         out["field_error_mixed_vs_fp64"] = _field_error(fields["mixed"], fields["fp64"])

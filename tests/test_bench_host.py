@@ -64,6 +64,23 @@ def test_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
                 assert got == before[prec], (edited, prec)
 
 
+def test_batch_traffic_follows_the_sources(tmp_path, monkeypatch):
+    # the committed batch figures describe the committed sources; an edit to any voids them
+    for prec, entry in bench.BATCH_TRAFFIC.items():
+        assert bench.batch_traffic(prec) == entry["bytes"], prec
+    assert bench.batch_traffic("masked") is None
+    csrc = tmp_path / "paper_1110_1379_amd" / "csrc"
+    shutil.copytree(os.path.join(ROOT, "paper_1110_1379_amd", "csrc"), csrc)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    for edited in sorted({name for e in bench.BATCH_TRAFFIC.values() for name in e["sources"]}):
+        before = {p: bench.batch_traffic(p) for p in bench.BATCH_TRAFFIC}
+        with open(csrc / edited, "a") as fh:
+            fh.write("\n// edited\n")
+        for prec, entry in bench.BATCH_TRAFFIC.items():
+            got = bench.batch_traffic(prec)
+            assert got == (None if edited in entry["sources"] else before[prec]), (edited, prec)
+
+
 @pytest.mark.parametrize("prec,bpc", [("fp64", 24), ("mixed", 12)])
 def test_batched_roofline(prec, bpc):
     s = {"sweep_launches": 8, "sweep_ms": 2.0, "sweep_bytes": 4.0e9}
