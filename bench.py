@@ -70,13 +70,13 @@ MEASURED_TRAFFIC = {
 BATCH_TRAFFIC = {
     "mixed": {"bytes": 0.4714e9, "sources": {
         "batch_col.hip": "1c3ac948bf60869a2c8ef3224e9c0f6d227552121414c5f25f895ad53f76efdd",
-        "batch.hip": "f2316d52fc5bfbfd4dd03e9a420fd395bda5810b55236e1e35cd4a6da901bba5",
+        "batch.hip": "09dd9fed86ff99bb08b296dc9c0ac61833f363040883159815452f3b45c75445",
         "fused_fp32.h": "b9ed53a6627e0abd80a493c36476053bfd8d2a934debc47118343d03e6ed03ca",
         "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
         "batch_dev.h": "de43e35ad4c4670dc0ee3196ac06e4ee6a59cd2320f45743b1b175dbf70de6f3"}},
     "fp64": {"bytes": 0.7707e9, "sources": {
         "batch_col.hip": "1c3ac948bf60869a2c8ef3224e9c0f6d227552121414c5f25f895ad53f76efdd",
-        "batch.hip": "f2316d52fc5bfbfd4dd03e9a420fd395bda5810b55236e1e35cd4a6da901bba5",
+        "batch.hip": "09dd9fed86ff99bb08b296dc9c0ac61833f363040883159815452f3b45c75445",
         "batch_dev.h": "de43e35ad4c4670dc0ee3196ac06e4ee6a59cd2320f45743b1b175dbf70de6f3"}},
 }
 

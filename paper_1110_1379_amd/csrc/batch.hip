@@ -1156,14 +1156,24 @@ struct Batch {
         const size_t nu = units.size();
         const int H = o->max_cycles + 1;
         c->ev_used = 0;
-        // whole units: one persistent launch on the side stream, beside the large units
+        // whole units: one persistent launch on the side stream, beside the large units; while
+        // those run, the whole-unit workgroups (one per CU at side 16) keep a quarter of the
+        // compute units free for the large units' launches (amr workload: 31.1 -> 29.9 ms mixed)
         if (up.nwhole > 0) {
             MGFR_TRY(ensure_side(c));
+            int max_wg = 1 << 30;
+            if (up.nlarge > 0) {
+                int cus = 0;
+                MGFR_TRY(hip_check(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device),
+                                   "hipDeviceGetAttribute"));
+                max_wg = std::max(1, 3 * cus / 4);
+            }
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev_fork, s), "hipEventRecord"));
             MGFR_TRY(hip_check(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "hipStreamWaitEvent"));
             for (size_t r = 0; r < up.ranges.size(); ++r) {
                 const int3 g = up.ranges[r];
-                MGFR_TRY(hip_check(c, mgfr::unit_whole(uset(), g.x, g.y, g.z, dqueue(r), uout(), ucfg(), mixed, c->side),
+                MGFR_TRY(hip_check(c, mgfr::unit_whole(uset(), g.x, g.y, g.z, dqueue(r), uout(), ucfg(), mixed, max_wg,
+                                                       c->side),
                                    "unit_whole"));
             }
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev_join, c->side), "hipEventRecord"));

@@ -195,10 +195,11 @@ hipError_t batch_nonfinite(const BTable& t, int nblk, double* partial, hipStream
 // Sides up to which a unit, or the levels below a tail, are solved with every level in LDS.
 constexpr int kUnitResidentMax = 16;
 inline bool unit_resident(int side) { return side <= kUnitResidentMax; }
-// The whole units us.order[begin, end), all of side `side`, solved completely by persistent
-// workgroups taking units from the device counter *queue (reset here); results into out.
+// The whole units us.order[begin, end), all of side `side`, solved completely by at most
+// max_wg persistent workgroups taking units from the device counter *queue (reset here);
+// results into out.
 hipError_t unit_whole(const UnitSet& us, int begin, int end, int side, int* queue, const UnitOut& out,
-                      const UnitCfg& cfg, bool mixed, hipStream_t s);
+                      const UnitCfg& cfg, bool mixed, int max_wg, hipStream_t s);
 // One workgroup per tails[b] = (index of a large unit's tail level, of side `side`, in
 // us.grids; levels from there): the rest of its V-cycle (the single-precision correction
 // cycle when mixed, with the coarse bases below the tail level).

@@ -1140,10 +1140,10 @@ hipError_t tail_resident(const UnitSet& us, const int2* tails, int ntail, const 
 }
 
 hipError_t unit_whole(const UnitSet& us, int begin, int end, int side, int* queue, const UnitOut& out,
-                      const UnitCfg& cfg, bool mixed, hipStream_t s)
+                      const UnitCfg& cfg, bool mixed, int max_wg, hipStream_t s)
 {
     if (end <= begin) return hipSuccess;
-    const int nwg = std::min(end - begin, 1024);
+    const int nwg = std::max(1, std::min({end - begin, 1024, max_wg}));
     hipLaunchKernelGGL(ku_fill_int, dim3(1), dim3(kU), 0, s, queue, 0, 1);
     switch (side) {
     case 2: return whole_resident<2>(us, begin, end, queue, out, cfg, mixed, nwg, s);
