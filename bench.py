@@ -64,29 +64,30 @@ MEASURED_TRAFFIC = {
 
 
 # HBM bytes per finest-level sweep launch of the batch workload (workgroup-per-unit engine,
-# automatic sweep form), averaged over the launches of one solve (FETCH_SIZE x 2 + WRITE_SIZE,
-# copy-calibrated): mixed, the fused two-colour launches (the last of each outer iteration also
-# adds u += e); FP64, the one-colour launches
+# automatic sweep form), averaged over the launches of one solve at the (pre, post, inner)
+# settings counted (FETCH_SIZE x 2 + WRITE_SIZE, copy-calibrated): mixed, the fused two-colour
+# launches (the last of each outer iteration also adds u += e); FP64, the one-colour launches
 BATCH_TRAFFIC = {
-    "mixed": {"bytes": 0.4714e9, "sources": {
+    "mixed": {"bytes": 0.4292e9, "settings": (2, 2, 3), "sources": {
         "batch_col.hip": "1c3ac948bf60869a2c8ef3224e9c0f6d227552121414c5f25f895ad53f76efdd",
         "batch.hip": "09dd9fed86ff99bb08b296dc9c0ac61833f363040883159815452f3b45c75445",
         "fused_fp32.h": "b9ed53a6627e0abd80a493c36476053bfd8d2a934debc47118343d03e6ed03ca",
         "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
         "batch_dev.h": "de43e35ad4c4670dc0ee3196ac06e4ee6a59cd2320f45743b1b175dbf70de6f3"}},
-    "fp64": {"bytes": 0.7707e9, "sources": {
+    "fp64": {"bytes": 0.9508e9, "settings": (1, 1, 1), "sources": {
         "batch_col.hip": "1c3ac948bf60869a2c8ef3224e9c0f6d227552121414c5f25f895ad53f76efdd",
         "batch.hip": "09dd9fed86ff99bb08b296dc9c0ac61833f363040883159815452f3b45c75445",
         "batch_dev.h": "de43e35ad4c4670dc0ee3196ac06e4ee6a59cd2320f45743b1b175dbf70de6f3"}},
 }
 
 
-def batch_traffic(prec):
+def batch_traffic(prec, settings=None):
     """Measured bytes per finest sweep launch of the batch workload, if the counters describe
-    the kernels and tables built from these sources."""
+    the kernels and tables built from these sources, at these (pre, post, inner) settings
+    (without settings: at those counted)."""
     import hashlib
     entry = BATCH_TRAFFIC.get(prec)
-    if entry is None:
+    if entry is None or (settings is not None and tuple(settings) != tuple(entry["settings"])):
         return None
     csrc = os.path.join(ROOT, "paper_1110_1379_amd", "csrc")
     for name, digest in entry["sources"].items():
@@ -263,16 +264,22 @@ def time_domain(mgfr, ctx, rho_d, params, prec, tol, steps, warmup, profile=True
         _, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, opts, u=u_d, stream=stream)
         log(f"warmup {w} prec={prec}: status {st}, {len(hist) - 1} cycles, final {hist[-1]:.3e}")
     stats, hists = [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        _, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, opts, u=u_d, stream=stream)
-        if st != mgfr.MGFR_OK:
-            raise SystemExit(f"solve failed: {mgfr.STATUS_NAMES.get(st, st)} {ctx.last_error()}")
-        stats.append(mgfr.mgfr_get_stats(ctx))
-        hists.append(hist)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    import gc
+    gc.collect()  # held off while timing (as in _timed)
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, hist, st = mgfr.mg_fr_solve(ctx, rho_d, params, opts, u=u_d, stream=stream)
+            if st != mgfr.MGFR_OK:
+                raise SystemExit(f"solve failed: {mgfr.STATUS_NAMES.get(st, st)} {ctx.last_error()}")
+            stats.append(mgfr.mgfr_get_stats(ctx))
+            hists.append(hist)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+    finally:
+        gc.enable()
     updates = sum(s["cell_updates"] for s in stats) / steps
     finest = sum(s["finest_updates"] for s in stats) / steps
     sweep_ms = sum(s["sweep_ms"] for s in stats)
@@ -680,15 +687,24 @@ def bench_tsc(args):
 
 
 def _timed(fn, steps, warmup):
+    """Mean milliseconds of `steps` calls after `warmup` untimed ones.  Python's cyclic garbage
+    collector is run before and held off during the timed calls: a full collection of this
+    process's objects takes about 40 ms, which would otherwise land in one step at random."""
+    import gc
     import torch
     for _ in range(warmup):
         fn()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        out = fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1000.0 / steps, out
+    gc.collect()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1000.0 / steps, out
+    finally:
+        gc.enable()
 
 
 def _precisions(mgfr, args):
@@ -821,6 +837,28 @@ def bench_amr(args):
     return out
 
 
+# Sweeps before / after the coarse step and single-precision cycles per outer iteration that
+# the batch workload tries per precision (the first is the library's default)
+BATCH_CANDIDATES = {"mixed": [(2, 2, 1), (2, 2, 2), (2, 2, 3)], "fp64": [(2, 2, 1), (1, 1, 1), (2, 1, 1)]}
+
+
+def _pick_batch_settings(name, run, args):
+    """The fastest of the precision's candidates (pre, post, inner): each solved once to warm
+    up, then timed as the faster of two solves.  With --no-autotune the default."""
+    cands = BATCH_CANDIDATES[name]
+    if args.batch_settings:
+        return tuple(int(x) for x in args.batch_settings.split(",")), None
+    if args.no_autotune:
+        return cands[0], None
+    trials = {}
+    for cand in cands:
+        trials["pre=%d,post=%d,inner=%d" % cand] = min(_timed(lambda: run(cand), 1, 1 if k == 0 else 0)[0]
+                                                      for k in range(2))
+    pick = min(cands, key=lambda c: trials["pre=%d,post=%d,inner=%d" % c])
+    log(f"batch {name}: candidates {trials}, picked pre/post/inner {pick}")
+    return pick, trials
+
+
 def bench_batch(args):
     """64 boxes of 64^3 plus 16 of 128^3 with their own |f_R0| and sigma, solved together,
     FP64 and mixed."""
@@ -831,13 +869,25 @@ def bench_batch(args):
     rhos = [torch.from_numpy(b[5]).to("cuda:0") for b in boxes]
     params = [mgfr.Params(box_mpc_h=b[1], fr0_abs=b[2]) for b in boxes]
     ctx = mgfr.Context(0)
-    runs, fields, profiled, per_phase = {}, {}, {}, {}
+    runs, fields, profiled, per_phase, picked = {}, {}, {}, {}, {}
     for engine in _engines(args):
         for name, code in _precisions(mgfr, args):
             eflags = (mgfr.MGFR_GRAPH if args.graph else 0) | (mgfr.MGFR_PER_PHASE if engine == "phases" else 0)
-            opts = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=eflags,
-                                          unit_n=args.unit_n, tile=args.batch_sweep_tile)
+
+            def make_opts(cand, flags, code=code):
+                return mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=flags,
+                                              unit_n=args.unit_n, tile=args.batch_sweep_tile, pre=cand[0],
+                                              post=cand[1], inner_cycles=cand[2])
             us = [torch.empty_like(r) for r in rhos]
+            if name not in picked:  # chosen with the first engine, kept for the second
+
+                def trial(cand, eflags=eflags, us=us):
+                    _, _, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, make_opts(cand, eflags), us=us)
+                    if st != mgfr.MGFR_OK:
+                        raise SystemExit(f"batch solve failed: {ctx.last_error()}")
+                picked[name] = _pick_batch_settings(name, trial, args)
+            cand, trials = picked[name]
+            opts = make_opts(cand, eflags)
 
             def solve(opts=opts, us=us):
                 _, hists, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, opts, us=us)
@@ -850,15 +900,18 @@ def bench_batch(args):
                  "cell_updates_per_s": s["cell_updates"] / (ms * 1e-3),
                  "max_cycles_per_box": int(max(len(h) for h in hists) - 1),
                  "max_final_residual": float(max(h[-1] for h in hists))}
+            r["settings"] = {"pre": cand[0], "post": cand[1], "inner_cycles": cand[2] if code else 1,
+                             "autotuned": trials is not None}
+            if trials is not None:
+                r["settings"]["candidates_ms"] = trials
             log(f"batch {engine} {name}: {ms:.2f} ms, {r['max_cycles_per_box']} cycles max")
             if engine == "phases" and args.engine == "both":
                 per_phase[name] = r
                 continue
 
-            def solve_profiled(code=code, eflags=eflags):
+            def solve_profiled(cand=cand, eflags=eflags):
                 pflags = mgfr.MGFR_PROFILE | (eflags & mgfr.MGFR_PER_PHASE)
-                po = mgfr.mgfr_default_opts(tol=args.tol, max_cycles=100, precision=code, flags=pflags,
-                                            unit_n=args.unit_n, tile=args.batch_sweep_tile)
+                po = make_opts(cand, pflags)
                 _, _, st = mgfr.mg_fr_solve_batch(ctx, rhos, params, po, us=[torch.empty_like(r) for r in rhos])
                 assert st == mgfr.MGFR_OK, ctx.last_error()
                 return mgfr.mgfr_get_stats(ctx)
@@ -874,13 +927,16 @@ def bench_batch(args):
            "data": "synthetic",
            "config": {"workload": "batch: 64 x 64^3 (B=64) + 16 x 128^3 (B=128), |f_R0| log-uniform "
                                   f"[1e-6,1e-4], lognormal sigma U[1,3], tol {args.tol:g}",
-                      "precision": headp, "graph": bool(args.graph), "engine": _engine_name(args)}}
+                      "precision": headp, "graph": bool(args.graph), "engine": _engine_name(args),
+                      "pre_post_inner": [runs[headp]["settings"]["pre"], runs[headp]["settings"]["post"],
+                                         runs[headp]["settings"]["inner_cycles"]]}}
     out.update(runs)
     if per_phase:
         out["per_phase_engine"] = per_phase
     roof = _batched_roofline(profiled[headp](), headp, args.unit_n, args.engine == "phases")
     if args.engine != "phases" and args.batch_sweep_tile == 0 and args.unit_n == 0 and not args.graph:
-        t = batch_traffic(headp)
+        st = runs[headp]["settings"]
+        t = batch_traffic(headp, (st["pre"], st["post"], st["inner_cycles"]))
         if t is not None and roof["achieved"]:
             algo = roof["achieved"] * 1e9 * roof["avg_launch_ms"] * 1e-3
             roof["traffic"] = t
@@ -929,7 +985,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="domain workloads: time the default options instead of autotuned ones")
+                    help="domain workloads and batch: time the default options instead of tuned ones")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of autotuned settings: reused when it holds this problem, else "
                          "written after tuning (so that profiled runs time the same settings)")
@@ -945,6 +1001,8 @@ def main():
                          "tiles, mixed in fused two-colour pairs; patches one thread per cell), one thread per "
                          "cell of the colour everywhere (cell), column tiles one colour per launch everywhere "
                          "(column), or as automatic with patches in fused pairs too (pairs)")
+    ap.add_argument("--batch-settings", default=None,
+                    help="batch: pre,post,inner to time (both precisions) instead of picking among the candidates")
     ap.add_argument("--unit-n", type=int, default=0,
                     help="amr/batch: units and levels of side <= this run in one workgroup (0: the library's 16)")
     ap.add_argument("--no-graph-ab", action="store_true",

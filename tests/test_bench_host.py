@@ -68,6 +68,9 @@ def test_batch_traffic_follows_the_sources(tmp_path, monkeypatch):
     # the committed batch figures describe the committed sources; an edit to any voids them
     for prec, entry in bench.BATCH_TRAFFIC.items():
         assert bench.batch_traffic(prec) == entry["bytes"], prec
+        assert bench.batch_traffic(prec, entry["settings"]) == entry["bytes"], prec
+        other = tuple(entry["settings"][:2]) + (entry["settings"][2] + 1,)
+        assert bench.batch_traffic(prec, other) is None, prec
     assert bench.batch_traffic("masked") is None
     csrc = tmp_path / "paper_1110_1379_amd" / "csrc"
     shutil.copytree(os.path.join(ROOT, "paper_1110_1379_amd", "csrc"), csrc)

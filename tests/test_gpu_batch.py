@@ -4,6 +4,7 @@ comparison is of the patch solves (boundary set-up, BC-modified operator, V-cycl
 Bar: double precision max|u - u*|/max|u*| <= 1e-10 per unit, both converged to
 rms(L) <= 1e-10; mixed precision (single-precision correction V-cycles in the
 double-precision defect-correction loop) <= 1e-6 at rms(L) <= 1e-8."""
+import os
 import sys
 
 import numpy as np
@@ -204,6 +205,38 @@ def test_mixed_batch_of_boxes_matches_oracle(mg, ctx, engine):
     u1, h1, st1 = mg.mg_fr_solve_batch(ctx, rhos[1:2], params[1:2], opts)
     assert st1 == mg.MGFR_OK
     assert np.array_equal(u1[0].cpu().numpy(), us[1].cpu().numpy())
+
+
+# the settings the batch bench tries (and may time): (precision, pre, post, inner cycles)
+TIMED_BATCH = [(prec, *cand) for prec, cands in (("fp64", [(2, 2, 1), (1, 1, 1), (2, 1, 1)]),
+                                                  ("mixed", [(2, 2, 1), (2, 2, 2), (2, 2, 3)])) for cand in cands]
+
+
+def test_timed_batch_settings_are_the_bench_candidates():
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    assert sorted(TIMED_BATCH) == sorted((p, *c) for p, cs in bench.BATCH_CANDIDATES.items() for c in cs)
+
+
+@pytest.mark.parametrize("precision,pre,post,inner", TIMED_BATCH, ids=["-".join(map(str, t)) for t in TIMED_BATCH])
+def test_batch_at_the_timed_settings_matches_oracle(mg, ctx, precision, pre, post, inner):
+    """Every setting the batch bench may time, in its engine (workgroup per unit), against the
+    oracle's fields at 1e-10: double precision to <= 1e-10 at rms 1e-10, mixed to <= 1e-6 at
+    rms 1e-8."""
+    say(f"[batch timed settings] {precision} pre={pre} post={post} inner={inner}")
+    specs = box_specs()
+    refs = box_refs(specs)
+    rhos = [dev(s[3]) for s in specs]
+    params = [mg.Params(box_mpc_h=s[1], fr0_abs=s[2]) for s in specs]
+    fp64 = precision == "fp64"
+    tol = 1e-10 if fp64 else 1e-8
+    opts = mg.mgfr_default_opts(tol=tol, precision=mg.MGFR_FP64 if fp64 else mg.MGFR_MIXED, pre=pre, post=post,
+                                inner_cycles=inner)
+    us, hists, st = mg.mg_fr_solve_batch(ctx, rhos, params, opts)
+    assert st == mg.MGFR_OK, ctx.last_error()
+    for ref, u, h in zip(refs, us, hists):
+        assert rel_err(u.cpu().numpy(), ref) <= (1e-10 if fp64 else 1e-6)
+        assert h[-1] <= tol
 
 
 @pytest.mark.parametrize("engine", [e for e in ENGINES if e[0] in ("units16", "phases")], ids=["units16", "phases"])
