@@ -70,13 +70,13 @@ MEASURED_TRAFFIC = {
 BATCH_TRAFFIC = {
     "mixed": {"bytes": 0.4292e9, "settings": (2, 2, 3), "sources": {
         "batch_col.hip": "1c3ac948bf60869a2c8ef3224e9c0f6d227552121414c5f25f895ad53f76efdd",
-        "batch.hip": "09dd9fed86ff99bb08b296dc9c0ac61833f363040883159815452f3b45c75445",
+        "batch.hip": "d4f88b9b651180a5616915b3f59d1d0ad76b9174d50ddcf080ec8f068b5792b9",
         "fused_fp32.h": "b9ed53a6627e0abd80a493c36476053bfd8d2a934debc47118343d03e6ed03ca",
         "device_fp32.h": "d5b6a8e51761f987af9084e51f4c3970ee35457c72c0a474d5c42afb25ff1921",
         "batch_dev.h": "de43e35ad4c4670dc0ee3196ac06e4ee6a59cd2320f45743b1b175dbf70de6f3"}},
     "fp64": {"bytes": 0.9508e9, "settings": (1, 1, 1), "sources": {
         "batch_col.hip": "1c3ac948bf60869a2c8ef3224e9c0f6d227552121414c5f25f895ad53f76efdd",
-        "batch.hip": "09dd9fed86ff99bb08b296dc9c0ac61833f363040883159815452f3b45c75445",
+        "batch.hip": "d4f88b9b651180a5616915b3f59d1d0ad76b9174d50ddcf080ec8f068b5792b9",
         "batch_dev.h": "de43e35ad4c4670dc0ee3196ac06e4ee6a59cd2320f45743b1b175dbf70de6f3"}},
 }
 

@@ -84,7 +84,7 @@ struct RR {
 struct Depth {
     Sweep half;
     RR rr;
-    Launch coarse_f, coarse_c, fine_f, faces_c, crs;
+    Launch coarse_f, coarse_c, faces_c, crs;
     bool deep = false, coarsest = false;
 };
 
@@ -116,7 +116,7 @@ struct Plan {
 struct UDepth {
     Sweep half;
     RR rr;
-    Launch coarse_f, coarse_c, fine_f;
+    Launch coarse_f, coarse_c;
     size_t tails = 0;
     int ntail = 0;
     bool deep = false;
@@ -459,12 +459,10 @@ struct Batch {
             D.coarsest = !crs.empty();
             if (D.deep) {
                 D.half = sweep_tables(meta, f, o->tile);
-                D.fine_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g); });
                 D.coarse_c = table(meta, cgr, [](const mgfr::BGrid& g) { return cells3(g); });
                 // resid_restrict: table over the coarse cells, indexed by the fine grids
                 D.coarse_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 8; });
                 D.coarse_f.other = D.coarse_c.grids;  // coarse grids, same order
-                D.fine_f.other = D.coarse_c.grids;
                 D.rr = rr_tables(meta, f, cgr);
                 std::vector<mgfr::BGrid> pf, pc;
                 for (size_t i = 0; i < f.size(); ++i)
@@ -555,11 +553,9 @@ struct Batch {
             UDepth D;
             D.deep = true;
             D.half = sweep_tables(meta, f, o->tile);
-            D.fine_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g); });
             D.coarse_c = table(meta, cg, [](const mgfr::BGrid& g) { return cells3(g); });
             D.coarse_f = table(meta, f, [](const mgfr::BGrid& g) { return cells3(g) / 8; });
             D.coarse_f.other = D.coarse_c.grids;
-            D.fine_f.other = D.coarse_c.grids;
             D.rr = rr_tables(meta, f, cg);
             D.tails = meta.add(tails);
             D.ntail = (int)tails.size();
@@ -757,9 +753,9 @@ struct Batch {
         MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs"));
         MGFR_TRY(vcycle(m + 1));
         MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_coarse_diff"));
-        MGFR_TRY(hip_check(c, mgfr::batch_prolong_add(tab(D.fine_f), D.fine_f.nblk,
-                                                      (const mgfr::BGrid*)(dmeta + D.fine_f.other), s),
-                           "batch_prolong_add"));
+        MGFR_TRY(hip_check(c, mgfr::batch_prolong_add8(tab(D.coarse_f), D.coarse_f.nblk,
+                                                       (const mgfr::BGrid*)(dmeta + D.coarse_f.other), s),
+                           "batch_prolong_add8"));
         MGFR_TRY(sweep(m, o->post));
         return MGFR_OK;
     }
@@ -792,9 +788,9 @@ struct Batch {
         MGFR_TRY(hip_check(c, mgfr::batch_fas_rhs32(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_fas_rhs32"));
         MGFR_TRY(vcycle32(m + 1));
         MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff32(tab(D.coarse_c), D.coarse_c.nblk, s), "batch_coarse_diff32"));
-        MGFR_TRY(hip_check(c, mgfr::batch_prolong_add32(tab(D.fine_f), D.fine_f.nblk,
-                                                        (const mgfr::BGrid*)(dmeta + D.fine_f.other), s),
-                           "batch_prolong_add32"));
+        MGFR_TRY(hip_check(c, mgfr::batch_prolong_add8_32(tab(D.coarse_f), D.coarse_f.nblk,
+                                                          (const mgfr::BGrid*)(dmeta + D.coarse_f.other), s),
+                           "batch_prolong_add8_32"));
         MGFR_TRY(sweep32(m, o->post, add_u && m == 0 && plan.fuse_add));
         return MGFR_OK;
     }
@@ -1055,12 +1051,12 @@ struct Batch {
         if (mixed) {
             MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff32(utab(D.coarse_c), D.coarse_c.nblk, s),
                                "batch_coarse_diff32"));
-            MGFR_TRY(hip_check(c, mgfr::batch_prolong_add32(utab(D.fine_f), D.fine_f.nblk, coarse, s),
-                               "batch_prolong_add32"));
+            MGFR_TRY(hip_check(c, mgfr::batch_prolong_add8_32(utab(D.coarse_f), D.coarse_f.nblk, coarse, s),
+                               "batch_prolong_add8_32"));
         } else {
             MGFR_TRY(hip_check(c, mgfr::batch_coarse_diff(utab(D.coarse_c), D.coarse_c.nblk, s), "batch_coarse_diff"));
-            MGFR_TRY(hip_check(c, mgfr::batch_prolong_add(utab(D.fine_f), D.fine_f.nblk, coarse, s),
-                               "batch_prolong_add"));
+            MGFR_TRY(hip_check(c, mgfr::batch_prolong_add8(utab(D.coarse_f), D.coarse_f.nblk, coarse, s),
+                               "batch_prolong_add8"));
         }
         MGFR_TRY(usweep(m, mixed, o->post, mixed && add_u && m == 0 && plan.fuse_add));
         return MGFR_OK;

@@ -97,30 +97,44 @@ __global__ void __launch_bounds__(kB) kb32_coarse_diff(BTable t)
     c.eh32[q] = c.e32[q] - c.eh32[q];
 }
 
-// e += P(coarse difference) on fine grids; outside a patch a coarse cell contributes zero
-// (Sec. V.A.3)
-__global__ void __launch_bounds__(kB) kb32_prolong_add(BTable t, const BGrid* __restrict__ tc)
+// e += P(coarse difference) on fine grids, as kb_prolong_add8 (outside a patch a coarse cell
+// contributes zero, Sec. V.A.3): one thread per coarse cell and its eight fine cells.
+__global__ void __launch_bounds__(kB) kb32_prolong_add8(BTable t, const BGrid* __restrict__ tc)
 {
     const int2 b = t.blk[blockIdx.x];
     const BGrid g = t.grids[b.x];
     if (!live(t, g)) return;
     const BGrid c = tc[b.x];
-    const long long q = (long long)b.y * kB + threadIdx.x;
-    if (q >= (1LL << (3 * g.lg))) return;
-    const int i = (int)(q >> (2 * g.lg)), j = (int)((q >> g.lg) & (g.n - 1)), k = (int)(q & (g.n - 1));
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+    const long long qc = (long long)b.y * kB + threadIdx.x;
+    if (qc >= (1LL << (3 * c.lg))) return;
     const int mc = c.n - 1;
+    const int I = (int)(qc >> (2 * c.lg)), J = (int)((qc >> c.lg) & mc), K = (int)(qc & mc);
     auto E = [&](int a, int bb, int z) -> float {
         if (c.periodic) return c.eh32[idx3(c.lg, a & mc, bb & mc, z & mc)];
         if (a < 0 || a > mc || bb < 0 || bb > mc || z < 0 || z > mc) return 0.0f;
         return c.eh32[idx3(c.lg, a, bb, z)];
     };
-    const float p = (27.0f / 64.0f) * E(I, J, K) +
-                    (9.0f / 64.0f) * (E(I + si, J, K) + E(I, J + sj, K) + E(I, J, K + sk)) +
-                    (3.0f / 64.0f) * (E(I + si, J + sj, K) + E(I + si, J, K + sk) + E(I, J + sj, K + sk)) +
-                    (1.0f / 64.0f) * E(I + si, J + sj, K + sk);
-    g.e32[q] += p;
+    float v[3][3][3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+#pragma unroll
+            for (int z = 0; z < 3; ++z) v[x][y][z] = E(I + x - 1, J + y - 1, K + z - 1);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int z = 0; z < 2; ++z) {
+                const int si = x ? 2 : 0, sj = y ? 2 : 0, sk = z ? 2 : 0;  // index of I + s
+                const float p = (27.0f / 64.0f) * v[1][1][1] +
+                                (9.0f / 64.0f) * (v[si][1][1] + v[1][sj][1] + v[1][1][sk]) +
+                                (3.0f / 64.0f) * (v[si][sj][1] + v[si][1][sk] + v[1][sj][sk]) +
+                                (1.0f / 64.0f) * v[si][sj][sk];
+                const long long q = idx3(g.lg, 2 * I + x, 2 * J + y, 2 * K + z);
+                g.e32[q] += p;
+            }
 }
 
 // ---- coarsest level: one workgroup per grid (n <= 8) --------------------------------------
@@ -161,9 +175,9 @@ hipError_t batch_coarse_diff32(const BTable& t, int nblk, hipStream_t s)
     hipLaunchKernelGGL(kb32_coarse_diff, dim3(nblk), dim3(kB), 0, s, t);
     return hipGetLastError();
 }
-hipError_t batch_prolong_add32(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s)
+hipError_t batch_prolong_add8_32(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb32_prolong_add, dim3(nblk), dim3(kB), 0, s, t, coarse);
+    hipLaunchKernelGGL(kb32_prolong_add8, dim3(nblk), dim3(kB), 0, s, t, coarse);
     return hipGetLastError();
 }
 hipError_t batch_coarsest32(const BGrid* grids, int ngrid, int n, const int* active, int cap, double rtol,

@@ -79,30 +79,48 @@ __global__ void __launch_bounds__(kB) kb_coarse_diff(BTable t)
     c.uhat[q] = c.u[q] - c.uhat[q];
 }
 
-// u += P(e) on fine grids (table over fine cells; tc = coarse grids holding e in uhat).
-// Outside a patch a coarse cell is not a multigrid cell and contributes zero (Sec. V.A.3).
-__global__ void __launch_bounds__(kB) kb_prolong_add(BTable t, const BGrid* __restrict__ tc)
+// u += P(e) on fine grids, trilinear (27/9/3/1 over the eight nearest coarse centres; tc =
+// coarse grids holding e in uhat).  Outside a patch a coarse cell is not a multigrid cell and
+// contributes zero (Sec. V.A.3).  A table of coarse cells (blocks of the fine grids' cells /
+// 8): one thread per coarse cell adds the correction to its eight fine cells, from the
+// 3 x 3 x 3 coarse values around it loaded once (a fine cell's interpolation reads 8 of
+// them); consecutive threads write consecutive pairs of fine cells along k.
+__global__ void __launch_bounds__(kB) kb_prolong_add8(BTable t, const BGrid* __restrict__ tc)
 {
     const int2 e = t.blk[blockIdx.x];
     const BGrid g = t.grids[e.x];
     if (!live(t, g)) return;
     const BGrid c = tc[e.x];
-    const long long q = (long long)e.y * kB + threadIdx.x;
-    if (q >= (1LL << (3 * g.lg))) return;
-    const int i = (int)(q >> (2 * g.lg)), j = (int)((q >> g.lg) & (g.n - 1)), k = (int)(q & (g.n - 1));
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+    const long long qc = (long long)e.y * kB + threadIdx.x;
+    if (qc >= (1LL << (3 * c.lg))) return;
     const int mc = c.n - 1;
+    const int I = (int)(qc >> (2 * c.lg)), J = (int)((qc >> c.lg) & mc), K = (int)(qc & mc);
     auto E = [&](int a, int b, int z) -> double {
         if (c.periodic) return c.uhat[idx3(c.lg, a & mc, b & mc, z & mc)];
         if (a < 0 || a > mc || b < 0 || b > mc || z < 0 || z > mc) return 0.0;
         return c.uhat[idx3(c.lg, a, b, z)];
     };
-    const double p = (27.0 / 64.0) * E(I, J, K) +
-                     (9.0 / 64.0) * (E(I + si, J, K) + E(I, J + sj, K) + E(I, J, K + sk)) +
-                     (3.0 / 64.0) * (E(I + si, J + sj, K) + E(I + si, J, K + sk) + E(I, J + sj, K + sk)) +
-                     (1.0 / 64.0) * E(I + si, J + sj, K + sk);
-    g.u[q] += p;
+    double v[3][3][3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+#pragma unroll
+            for (int z = 0; z < 3; ++z) v[x][y][z] = E(I + x - 1, J + y - 1, K + z - 1);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int z = 0; z < 2; ++z) {
+                const int si = x ? 2 : 0, sj = y ? 2 : 0, sk = z ? 2 : 0;  // index of I + s
+                const double p = (27.0 / 64.0) * v[1][1][1] +
+                                 (9.0 / 64.0) * (v[si][1][1] + v[1][sj][1] + v[1][1][sk]) +
+                                 (3.0 / 64.0) * (v[si][sj][1] + v[si][1][sk] + v[1][sj][sk]) +
+                                 (1.0 / 64.0) * v[si][sj][sk];
+                const long long q = idx3(g.lg, 2 * I + x, 2 * J + y, 2 * K + z);
+                g.u[q] += p;
+            }
 }
 
 // ---- coarsest level: one workgroup per grid (n <= 8) --------------------------------------
@@ -345,9 +363,9 @@ hipError_t batch_coarse_diff(const BTable& t, int nblk, hipStream_t s)
     hipLaunchKernelGGL(kb_coarse_diff, dim3(nblk), dim3(kB), 0, s, t);
     return hipGetLastError();
 }
-hipError_t batch_prolong_add(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s)
+hipError_t batch_prolong_add8(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_prolong_add, dim3(nblk), dim3(kB), 0, s, t, coarse);
+    hipLaunchKernelGGL(kb_prolong_add8, dim3(nblk), dim3(kB), 0, s, t, coarse);
     return hipGetLastError();
 }
 hipError_t batch_coarsest(const BGrid* grids, int ngrid, int n, const int* active, int cap, double rtol,

@@ -176,7 +176,12 @@ long long batch_pair_tiles(int n, int periodic);
 hipError_t batch_resid_restrict(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
 hipError_t batch_fas_rhs(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_coarse_diff(const BTable& t, int nblk, hipStream_t s);
-hipError_t batch_prolong_add(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
+// Fine u += P(coarse uhat) (trilinear 27/9/3/1; outside a patch a coarse cell contributes
+// zero), over a table of coarse cells (blocks of the fine grids' cells / 8, the coarse grids
+// in the same order): one thread per coarse cell and its eight fine cells.
+// batch_prolong_add8_32: the same in single precision, e32 += P(coarse eh32).
+hipError_t batch_prolong_add8(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
+hipError_t batch_prolong_add8_32(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
 // n: side of every grid in the list (the coarsest side, <= 8)
 hipError_t batch_coarsest(const BGrid* grids, int ngrid, int n, const int* active, int cap, double rtol,
                           hipStream_t s);
@@ -226,7 +231,6 @@ hipError_t batch_ngs32(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_resid_restrict32(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
 hipError_t batch_fas_rhs32(const BTable& t, int nblk, hipStream_t s);
 hipError_t batch_coarse_diff32(const BTable& t, int nblk, hipStream_t s);
-hipError_t batch_prolong_add32(const BTable& t, int nblk, const BGrid* coarse, hipStream_t s);
 hipError_t batch_coarsest32(const BGrid* grids, int ngrid, int n, const int* active, int cap, double rtol,
                             hipStream_t s);
 
