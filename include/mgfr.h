@@ -351,6 +351,10 @@ int mg_poisson_smooth(mgfr_ctx* ctx, const double* rho, const double* u, int N, 
  *          active cells hold the solution and the others are bit-for-bit unchanged.
  * N        power of two in [coarsest_n, 1024].  opts->precision must be MGFR_FP64 and
  *          opts->tau_alpha 0.  res_hist, n_hist: as mg_fr_solve (rms over active cells).
+ *          A finest level of N >= 64 whose mask holds only +1 and -1 is swept both colours in
+ *          one pass (opts->planes planes per workgroup, 0: automatic), out of place between
+ *          u and a context buffer; opts->tile = 1 keeps one launch per colour (the same
+ *          results, bit for bit).
  * Returns MGFR_EINVAL for a mask outside [-1, 1], MGFR_ENONFINITE for non-finite rho or u,
  * MGFR_ENOTCONV if tol was not reached (u still written).  Synchronises. */
 int mg_fr_solve_masked(mgfr_ctx* ctx, const double* rho, const float* mask, int N, const mgfr_params* params,

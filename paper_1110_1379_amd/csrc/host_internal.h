@@ -121,12 +121,15 @@ struct mgfr_ctx {
     std::vector<MLevel> mlv;
     double* mpart = nullptr;  // block partials of the finest-level norm
     unsigned char* mflags = nullptr;  // byte flags of the finest mask
+    double* malt = nullptr;           // N >= 64: second buffer of the finest level's fused sweeps
     void free_masked()
     {
         (void)hipFree(mpart);
         mpart = nullptr;
         (void)hipFree(mflags);
         mflags = nullptr;
+        (void)hipFree(malt);
+        malt = nullptr;
         for (size_t m = 0; m < mlv.size(); ++m) {
             (void)hipFree(mlv[m].mbuf);
             (void)hipFree(mlv[m].w);

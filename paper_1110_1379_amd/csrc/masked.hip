@@ -15,6 +15,8 @@
 // active), which gives the same values as the float mask.
 #include "device_fp64.h"
 
+#include <type_traits>
+
 namespace mgfr {
 namespace {
 
@@ -29,6 +31,22 @@ using u8 = unsigned char;
 // mask value of cell q: the float mask, or a byte flag standing for +1 / -1
 __device__ __forceinline__ double mval(const float* __restrict__ m, long long q) { return m[q]; }
 __device__ __forceinline__ double mval(const u8* __restrict__ m, long long q) { return m[q] ? 1.0 : -1.0; }
+
+// The term of a masked neighbour (mask mn <= 0, fixed value wn) in L_i and dL_i/du_i of an
+// active cell of mask mi, value ui, b_i = bi and fixed value wi: the boundary value
+// u_b = (mi wn - mn wi) / (mi - mn), the ghost u_g = (1 - r) u_b + r ui with r = mn / mi, and
+// b_g = exp(u_g) (eq. phi_b, eq. u_i-1jk, eq. bc_modified_fR_op, eq. bc_modified_fR_dop).
+__device__ __forceinline__ void masked_face(double mi, double mn, double wn, double wi, double ui, double bi,
+                                            double& L, double& dL)
+{
+    const double r = mn / mi;
+    const double ubv = (mi * wn - mn * wi) / (mi - mn);
+    const double ug = (1.0 - r) * ubv + r * ui;
+    const double bg = exp(ug), du = ug - ui;
+    L = fma(bg + bi, du, L);
+    // chain rule: du_g/du_i = r, db_g/du_i = r b_g
+    dL += (r * bg + bi) * du + (bg + bi) * (r - 1.0);
+}
 
 // L_i - f and dL_i/du_i at active cell (i,j,k) of value ui, mask mi.
 template <class M>
@@ -54,13 +72,7 @@ __device__ __forceinline__ OpVal masked_op(const Grid& g, const M* __restrict__ 
                 wi = w[at(g, i, j, k)];
                 have_wi = true;
             }
-            const double r = mn / mi;
-            const double ubv = (mi * w[qn[v]] - mn * wi) / (mi - mn);
-            const double ug = (1.0 - r) * ubv + r * ui;
-            const double bg = exp(ug), du = ug - ui;
-            L = fma(bg + bi, du, L);
-            // chain rule: du_g/du_i = r, db_g/du_i = r b_g
-            dL += (r * bg + bi) * du + (bg + bi) * (r - 1.0);
+            masked_face(mi, mn, w[qn[v]], wi, ui, bi, L, dL);
         }
     }
     const double S = dev::curvature(g, ui, bi);
@@ -159,6 +171,191 @@ __global__ void __launch_bounds__(kB) km_ngs_colour(Grid g, const M* __restrict_
     const double ui = u[q];
     const OpVal r = masked_op(g, mask, w, u, i, j, k, ui, mi, dev::rhs_value(g, src[q]));
     u[q] = ui + bounded(-r.L / r.dL, g.max_step);
+}
+
+// ---- fused red-black sweep of a level read as byte flags (n >= 64) ------------------------
+// The domain's fused sweep (red cells of plane p, then black cells of plane p-1, in one pass
+// over HBM; tiles of TJ x 64 columns and a chunk of planes per workgroup, u and b = exp(u)
+// of each plane staged once in LDS, out of place from uin to uout) with the mask scheme of
+// km_ngs_colour: a staged masked cell carries b = -1 (b of an active cell is positive), is
+// never updated and is copied to uout unchanged; its value, which a masked cell keeps for
+// the whole solve, is the w its active neighbours need.  Every update sees the operands of
+// the two-colour sweep in the same order (masked_op with mask +1 / -1).  The fixed values w
+// are loaded with u, three planes ahead (a load at the update would stall the wavefront).
+constexpr int kMK = 64;  // tile width along k
+
+struct ColM {
+    double u[4], b[4], f[4], w[4];
+    double ru[2], rf[2], rw[2];
+    int rm[2];     // raw flags of planes p+2, p+3
+    unsigned col;  // (j,k) offset within a plane
+    int c, fl;     // LDS cell; 1 loaded, 2 red range (tile + ring), 4 tile
+};
+
+// L_i - f and dL_i/du_i of an active cell (mask +1, fixed value wi) with staged neighbours:
+// b_nb > 0 active, else masked (mask -1, value = its fixed value w).
+__device__ __forceinline__ OpVal masked_op_staged(const Grid& g, double ui, double bi, const double (&un)[6],
+                                                  const double (&bn)[6], double f, double wi)
+{
+    double L = 0.0, dL = 0.0;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) {
+        if (bn[v] > 0.0) {
+            const double du = un[v] - ui;
+            L = fma(bn[v] + bi, du, L);
+            dL += bi * du - bn[v] - bi;
+        } else {
+            masked_face(1.0, -1.0, un[v], wi, ui, bi, L, dL);
+        }
+    }
+    const double S = dev::curvature(g, ui, bi);
+    OpVal o;
+    o.L = fma(g.C, L, S) - f;
+    o.dL = fma(g.C, dL, -S * g.inv_np1);
+    return o;
+}
+
+template <int TJ, int NT>
+__global__ void __launch_bounds__(NT) km_ngs_fused(Grid g, const u8* __restrict__ flags, const double* __restrict__ w,
+                                                   const double* __restrict__ uin, double* __restrict__ uout,
+                                                   const double* __restrict__ src, FusedSweep a)
+{
+    constexpr int LJ = TJ + 4, LK = kMK + 4, NL = LJ * LK, NP = NL / 2;
+    static_assert(NP <= NT, "one column pair per thread");
+    __shared__ double lu[3][NL];
+    __shared__ double lb[3][NL];
+    const int nb = gridDim.x;
+    int lid = blockIdx.x;
+    if ((nb & 7) == 0) lid = (lid & 7) * (nb >> 3) + (lid >> 3);
+    const int tk = lid % a.ntk;
+    lid /= a.ntk;
+    const int tj = lid % a.ntj;
+    const int ci = lid / a.ntj;
+    const int i0 = ci * a.ti, j0 = tj * TJ, k0 = tk * kMK;
+    const int lg = g.lg, m = g.n - 1;
+    const int last = i0 + a.ti + 1;  // last plane read
+
+    // X: the column of the thread's pair whose cell on plane i0-1 is red; Y the other
+    ColM X{}, Y{};
+    const int pc = threadIdx.x;
+    if (pc < NP) {
+        const int jj = pc / (LK / 2), kk0 = 2 * (pc - jj * (LK / 2));
+        const int gj = (j0 - 2 + jj) & m, gk0 = (k0 - 2 + kk0) & m;
+        const int sx = (i0 - 1 + gj + gk0) & 1;
+        auto setup = [&](ColM& q, int d) {
+            const int kk = kk0 + d;
+            q.col = (unsigned)((gj << lg) | (gk0 + d));
+            q.c = jj * LK + kk;
+            q.fl = 1;
+            if (jj >= 1 && jj <= LJ - 2 && kk >= 1 && kk <= LK - 2) q.fl |= 2;
+            if (jj >= 2 && jj <= LJ - 3 && kk >= 2 && kk <= LK - 3) q.fl |= 4;
+        };
+        setup(X, sx);
+        setup(Y, 1 - sx);
+    }
+    auto offset = [&](int p, const ColM& q) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + q.col; };
+    auto buf = [&](int p) { return (p - i0 + 3) % 3; };
+    auto bval = [](double u, int active) { return active ? exp(u) : -1.0; };
+    auto prologue = [&](ColM& q) {
+        if (!q.fl) return;
+        for (int t = 1; t < 4; ++t) {
+            q.u[t] = uin[offset(i0 - 3 + t, q)];
+            q.b[t] = bval(q.u[t], flags[offset(i0 - 3 + t, q)]);
+            q.f[t] = dev::rhs_value(g, src[offset(i0 - 3 + t, q)]);
+            q.w[t] = w[offset(i0 - 3 + t, q)];
+        }
+        q.ru[1] = uin[offset(i0 + 1, q)];
+        q.rm[1] = flags[offset(i0 + 1, q)];
+        q.rf[1] = src[offset(i0 + 1, q)];
+        q.rw[1] = w[offset(i0 + 1, q)];
+        lu[buf(i0 - 1)][q.c] = q.u[2];
+        lb[buf(i0 - 1)][q.c] = q.b[2];
+    };
+    prologue(X);
+    prologue(Y);
+    __syncthreads();
+
+    const double ms = g.max_step;
+    auto step = [&](auto Rc, int p, ColM& A, ColM& B) {
+        constexpr int R = decltype(Rc)::value;
+        constexpr int M2 = R, M1 = (R + 1) & 3, P0 = (R + 2) & 3, P1 = (R + 3) & 3;
+        constexpr int N2 = (R + 1) & 1, N3 = R & 1;
+        if (p + 3 <= last) {
+            if (A.fl) {
+                A.ru[N3] = uin[offset(p + 3, A)];
+                A.rm[N3] = flags[offset(p + 3, A)];
+                A.rf[N3] = src[offset(p + 3, A)];
+                A.rw[N3] = w[offset(p + 3, A)];
+            }
+            if (B.fl) {
+                B.ru[N3] = uin[offset(p + 3, B)];
+                B.rm[N3] = flags[offset(p + 3, B)];
+                B.rf[N3] = src[offset(p + 3, B)];
+                B.rw[N3] = w[offset(p + 3, B)];
+            }
+        }
+        // red cell of plane p (tile + ring), if active
+        double* LA = lu[buf(p)];
+        double* BA = lb[buf(p)];
+        if ((A.fl & 2) && A.b[P0] > 0.0) {
+            const int c = A.c;
+            const double un[6] = {A.u[M1], A.u[P1], LA[c - LK], LA[c + LK], LA[c - 1], LA[c + 1]};
+            const double bn[6] = {A.b[M1], A.b[P1], BA[c - LK], BA[c + LK], BA[c - 1], BA[c + 1]};
+            const OpVal r = masked_op_staged(g, A.u[P0], A.b[P0], un, bn, A.f[P0], A.w[P0]);
+            const double v = A.u[P0] + bounded(-r.L / r.dL, ms);
+            const double bv = exp(v);
+            A.u[P0] = v;
+            A.b[P0] = bv;
+            LA[c] = v;
+            BA[c] = bv;
+        }
+        // black cell of plane p-1 (tile), if active; plane p-1 is then final in both columns
+        if (p - 1 >= i0) {
+            if (A.fl & 4) {
+                if (A.b[M1] > 0.0) {
+                    const double* LB = lu[buf(p - 1)];
+                    const double* BB = lb[buf(p - 1)];
+                    const int c = A.c;
+                    const double un[6] = {A.u[M2], A.u[P0], LB[c - LK], LB[c + LK], LB[c - 1], LB[c + 1]};
+                    const double bn[6] = {A.b[M2], A.b[P0], BB[c - LK], BB[c + LK], BB[c - 1], BB[c + 1]};
+                    const OpVal r = masked_op_staged(g, A.u[M1], A.b[M1], un, bn, A.f[M1], A.w[M1]);
+                    A.u[M1] = A.u[M1] + bounded(-r.L / r.dL, ms);
+                }
+                uout[offset(p - 1, A)] = A.u[M1];
+            }
+            if (B.fl & 4) uout[offset(p - 1, B)] = B.u[M1];
+        }
+        double* LC = lu[buf(p + 1)];
+        double* BC = lb[buf(p + 1)];
+        const bool more2 = p + 2 <= last;
+        auto advance = [&](ColM& q) {
+            if (q.fl) {
+                LC[q.c] = q.u[P1];
+                BC[q.c] = q.b[P1];
+                if (more2) {
+                    q.u[M2] = q.ru[N2];
+                    q.b[M2] = bval(q.ru[N2], q.rm[N2]);
+                    q.f[M2] = dev::rhs_value(g, q.rf[N2]);
+                    q.w[M2] = q.rw[N2];
+                }
+            }
+        };
+        advance(A);
+        advance(B);
+        __syncthreads();
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    step(I0{}, i0 - 1, X, Y);
+    step(I1{}, i0, Y, X);
+    for (int p = i0 + 1; p <= i0 + a.ti; p += 4) {
+        step(I2{}, p, X, Y);
+        step(I3{}, p + 1, Y, X);
+        step(I0{}, p + 2, X, Y);
+        step(I1{}, p + 3, Y, X);
+    }
 }
 
 // One thread per coarse cell: R u of all 8 children and R d of the active ones into active
@@ -453,6 +650,21 @@ hipError_t masked_ngs(const Grid& g, const unsigned char* flags, const double* w
                       hipStream_t s)
 {
     return ngs_t(g, flags, w, u, src, s);
+}
+
+hipError_t masked_ngs_fused(const Grid& g, const unsigned char* flags, const double* w, const double* uin,
+                            double* uout, const double* src, int ti, hipStream_t s)
+{
+    if (g.n < kMK || g.n > 1024 || uin == uout || ti < 4 || (ti & 3) || ti > g.n || (g.n % ti) != 0)
+        return hipErrorInvalidValue;
+    constexpr int TJ = 16, NT = 704;  // 680 column pairs per 20 x 68 tile
+    FusedSweep a{};
+    a.ti = ti;
+    a.ntj = g.n / TJ;
+    a.ntk = g.n / kMK;
+    const unsigned nb = (unsigned)((g.n / ti) * a.ntj * a.ntk);
+    hipLaunchKernelGGL((km_ngs_fused<TJ, NT>), dim3(nb), dim3(NT), 0, s, g, flags, w, uin, uout, src, a);
+    return hipGetLastError();
 }
 
 template <class M>

@@ -33,9 +33,10 @@ int ensure_masked(mgfr_ctx* c, int N, int coarsest)
     gN.n = N;
     gN.lg = ilog2(N);
     if (hipMalloc(&c->mpart, sizeof(double) * 2 * (size_t)mgfr::masked_norm_partials(gN)) != hipSuccess ||
-        hipMalloc(&c->mflags, (size_t)N * N * N) != hipSuccess) {
+        hipMalloc(&c->mflags, (size_t)N * N * N) != hipSuccess ||
+        (N >= mgfr::fused_sweep_min_n() && hipMalloc(&c->malt, sizeof(double) * N * N * N) != hipSuccess)) {
         c->free_masked();
-        return c->fail(MGFR_ENOMEM, "hipMalloc of the norm partials failed");
+        return c->fail(MGFR_ENOMEM, "hipMalloc of the norm partials, flags or sweep buffer failed");
     }
     c->MN = N;
     c->Mcoarsest = coarsest;
@@ -47,6 +48,7 @@ struct MCycle {
     const mgfr_opts* o;
     hipStream_t s;
     const double* rho;
+    double* user_u;  // the caller's finest u (the finest level's u alternates with c->malt)
 
     const double* src(size_t m) const { return m == 0 ? rho : c->mlv[m].f; }
 
@@ -64,14 +66,24 @@ struct MCycle {
             }
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used], s), "hipEventRecord"));
         }
-        if (L.flags)
+        // a finest level of byte flags (n >= 64): both colours in one pass, out of place
+        // between the caller's u and the context's second buffer (opts->tile = 1: per colour)
+        const bool fused = m == 0 && L.flags && c->malt && o->tile != 1;
+        if (fused) {
+            double* out = L.u == c->malt ? user_u : c->malt;
+            const int ti = o->planes > 0 && o->planes <= L.g.n ? o->planes : mgfr::fused_sweep_planes(L.g.n);
+            MGFR_TRY(hip_check(c, mgfr::masked_ngs_fused(L.g, L.flags, L.w, L.u, out, src(m), ti, s),
+                               "masked_ngs_fused"));
+            L.u = out;
+        } else if (L.flags) {
             MGFR_TRY(hip_check(c, mgfr::masked_ngs(L.g, L.flags, L.w, L.u, src(m), s), "masked_ngs"));
-        else
+        } else {
             MGFR_TRY(hip_check(c, mgfr::masked_ngs(L.g, L.mask, L.w, L.u, src(m), s), "masked_ngs"));
+        }
         if (timed) {
             MGFR_TRY(hip_check(c, hipEventRecord(c->ev[c->ev_used + 1], s), "hipEventRecord"));
             c->ev_used += 2;
-            c->stats.sweep_launches += 2;
+            c->stats.sweep_launches += fused ? 1 : 2;
             // every mask read (one byte per cell with flags); per active cell u read and written
             // and the density read
             c->stats.sweep_bytes += (L.flags ? 1.0 : 4.0) * (double)mgfr::cells(L.g) + 24.0 * (double)L.active;
@@ -212,7 +224,7 @@ int mg_fr_solve_masked(mgfr_ctx* c, const double* rho, const float* mask, int N,
         MGFR_TRY(count_active(c, H.mask, mgfr::cells(H.g), s, &H.active, &mx));
     }
 
-    MCycle cyc{c, o, s, rho};
+    MCycle cyc{c, o, s, rho, u};
     c->ev_used = 0;
     MGFR_TRY(hip_check(c, hipMemsetAsync(c->counter, 0, sizeof(long long), s), "hipMemsetAsync"));
     double rms;
@@ -227,6 +239,10 @@ int mg_fr_solve_masked(mgfr_ctx* c, const double* rho, const float* mask, int N,
         if (res_hist) res_hist[k] = rms;
     }
     if (n_hist) *n_hist = k + 1;
+    if (L0.u != u)  // an odd number of fused sweeps left the field in the second buffer
+        MGFR_TRY(hip_check(c, hipMemcpyAsync(u, L0.u, sizeof(double) * ncell, hipMemcpyDeviceToDevice, s),
+                           "hipMemcpyAsync"));
+    L0.u = u;
     long long coarse_sweeps = 0;
     MGFR_TRY(hip_check(c, hipMemcpy(&coarse_sweeps, c->counter, sizeof coarse_sweeps, hipMemcpyDeviceToHost),
                        "hipMemcpy"));

@@ -55,6 +55,12 @@ hipError_t masked_flags(const float* mask, long long n, unsigned char* flags, do
 hipError_t masked_ngs(const Grid& g, const float* mask, const double* w, double* u, const double* src, hipStream_t s);
 hipError_t masked_ngs(const Grid& g, const unsigned char* flags, const double* w, double* u, const double* src,
                       hipStream_t s);
+// One red-black sweep of a level read as byte flags in one pass (n >= 64, the domain's fused
+// tiling with the mask scheme), out of place: uin to uout (never the same array; masked
+// cells copied unchanged), ti planes per workgroup (a multiple of 4 dividing n).  The same
+// values, bit for bit, as masked_ngs on the flags.
+hipError_t masked_ngs_fused(const Grid& g, const unsigned char* flags, const double* w, const double* uin,
+                            double* uout, const double* src, int ti, hipStream_t s);
 // Into the level below: uc = uhat = R u and fc = R d at active coarse cells (w, w and 0 at
 // masked ones).
 hipError_t masked_resid_restrict(const Grid& g, const float* mask, const double* w, const double* u,
