@@ -53,7 +53,7 @@ MEASURED_TRAFFIC = {
         "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},
     # per sweep (one launch of the fused masked sweep, byte flags)
     "masked": {"bytes": 4.995e9, "sources": {
-        "masked.hip": "bf349d89fc454f84c20eb2ea9df3fa72e8418aad91c4701afbb572c4f833105f",
+        "masked.hip": "6d044054bb4f6a7c5c48cc0c85298a8667acd115f241463a6694d6092d87489c",
         "masked_solver.hip": "966744ac3561f1ca7912ab5e2f3f4cb699879477b5a7f0d61b1cdd7d0d0be3ad",
         "device_fp64.h": "45739fd671f614d6a70c9201b41df3c5734bf39dd756f08db278f61fa5027ac7",
         "kernel_types.h": "21ac1843e9d4b3e18646111fcbd3ff3b7e20b75086410058eb389d6397f79ef6"}},

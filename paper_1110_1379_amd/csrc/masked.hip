@@ -458,6 +458,101 @@ __global__ void __launch_bounds__(kB) km_norm(Grid g, const M* __restrict__ mask
     }
 }
 
+// The same partials for a level read as byte flags (n >= 64), streamed: a workgroup owns a
+// tile of TJ x 64 columns and a chunk of ti planes; per plane it stages u and b = exp(u) of
+// the tile and a one-cell ring in LDS (b = -1 at masked cells, as in km_ngs_fused), keeps the
+// i-neighbours in registers and loads the next planes while it evaluates this one, so each
+// value and exponential is fetched and formed once.  Sums in a fixed order (a thread's cells
+// plane by plane, then a tree over the workgroup); one partial pair per workgroup.
+template <int TJ, int NT>
+__global__ void __launch_bounds__(NT) km_norm_fused(Grid g, const u8* __restrict__ flags, const double* __restrict__ w,
+                                                    const double* __restrict__ u, const double* __restrict__ src,
+                                                    double* __restrict__ partial, int ti)
+{
+    constexpr int LJ = TJ + 2, LK = kMK + 2, NL = LJ * LK;
+    static_assert(NL <= NT, "one column per thread");
+    __shared__ double lu[NL], lb[NL];
+    __shared__ double ra[NT], rb[NT];
+    const int ntk = g.n / kMK, ntj = g.n / TJ;
+    int lid = blockIdx.x;
+    const int tk = lid % ntk;
+    lid /= ntk;
+    const int tj = lid % ntj;
+    const int i0 = (lid / ntj) * ti, j0 = tj * TJ, k0 = tk * kMK;
+    const int lg = g.lg, m = g.n - 1;
+    const int t = threadIdx.x;
+    const bool on = t < NL;
+    const int jj = on ? t / LK : 0, kk = on ? t - jj * LK : 0;
+    const bool in = on && jj >= 1 && jj <= TJ && kk >= 1 && kk <= kMK;
+    const unsigned col = (unsigned)((((j0 - 1 + jj) & m) << lg) | ((k0 - 1 + kk) & m));
+    auto off = [&](int p) -> unsigned { return ((unsigned)(p & m) << (2 * lg)) + col; };
+    auto bval = [](double v, int a) { return a ? exp(v) : -1.0; };
+    double um = 0.0, uc = 0.0, up = 0.0, bm = 0.0, bc = 0.0, bp = 0.0, fc = 0.0, wc = 0.0;
+    double ru = 0.0, rf = 0.0, rw = 0.0;
+    int rm = 0;
+    if (on) {
+        um = u[off(i0 - 1)];
+        bm = bval(um, flags[off(i0 - 1)]);
+        uc = u[off(i0)];
+        bc = bval(uc, flags[off(i0)]);
+        up = u[off(i0 + 1)];
+        bp = bval(up, flags[off(i0 + 1)]);
+        if (in) {
+            fc = src[off(i0)];
+            wc = w[off(i0)];
+        }
+    }
+    double s = 0.0, mx = 0.0;
+    for (int p = i0; p < i0 + ti; ++p) {
+        // the loads of the next steps: u and flag of plane p+2, rho and w of plane p+1
+        if (on && p + 2 <= i0 + ti) {
+            ru = u[off(p + 2)];
+            rm = flags[off(p + 2)];
+        }
+        if (in && p + 1 < i0 + ti) {
+            rf = src[off(p + 1)];
+            rw = w[off(p + 1)];
+        }
+        if (on) {
+            lu[t] = uc;
+            lb[t] = bc;
+        }
+        __syncthreads();
+        if (in && bc > 0.0) {
+            const double un[6] = {um, up, lu[t - LK], lu[t + LK], lu[t - 1], lu[t + 1]};
+            const double bn[6] = {bm, bp, lb[t - LK], lb[t + LK], lb[t - 1], lb[t + 1]};
+            const double d = masked_op_staged(g, uc, bc, un, bn, dev::rhs_value(g, fc), wc).L;
+            s += d * d;
+            const double a = fabs(d);
+            if (!(mx >= a)) mx = a;
+        }
+        __syncthreads();
+        um = uc;
+        bm = bc;
+        uc = up;
+        bc = bp;
+        up = ru;
+        bp = bval(ru, rm);
+        fc = rf;
+        wc = rw;
+    }
+    ra[t] = s;
+    rb[t] = mx;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if (t < h && t + h < NT) {
+            ra[t] += ra[t + h];
+            const double o = rb[t + h];
+            if (!(rb[t] >= o)) rb[t] = o;
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        partial[2 * blockIdx.x] = ra[0];
+        partial[2 * blockIdx.x + 1] = rb[0];
+    }
+}
+
 // Block partials (number of active cells, max |mask|; NaN propagates).
 __global__ void __launch_bounds__(kB) km_count(const float* __restrict__ mask, long long n,
                                                double* __restrict__ partial)
@@ -730,7 +825,15 @@ hipError_t masked_norm(const Grid& g, const float* mask, const double* w, const 
 hipError_t masked_norm(const Grid& g, const unsigned char* flags, const double* w, const double* u,
                        const double* src, double* partial, int* nparts, hipStream_t s)
 {
-    return norm_t(g, flags, w, u, src, partial, nparts, s);
+    if (g.n < kMK) return norm_t(g, flags, w, u, src, partial, nparts, s);
+    // streamed: 8 x 64 column tiles, chunks of 64 planes (at most n)
+    constexpr int TJ = 8, NT = 704;
+    const int ti = g.n < 64 ? g.n : 64;
+    const unsigned nb = (unsigned)((g.n / ti) * (g.n / TJ) * (g.n / kMK));
+    if ((long long)nb > masked_norm_partials(g)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((km_norm_fused<TJ, NT>), dim3(nb), dim3(NT), 0, s, g, flags, w, u, src, partial, ti);
+    *nparts = (int)nb;
+    return hipGetLastError();
 }
 
 hipError_t masked_coarsest(const Grid& g, const float* mask, const double* w, double* u, const double* f, int cap,
